@@ -1,0 +1,191 @@
+/*
+ * paradiag.h -- C ABI of the MI355X (gfx950) ParaDiag solver.
+ *
+ * Solves the all-at-once backward-Euler system of a linear evolution problem
+ * (Gander & Palitta, "A new ParaDiag time-parallel time integration method",
+ * Section 1, all-at-once equation; generalised with a mass matrix M):
+ *
+ *     (M + tau K) U - M U Sigma_1^T = M [u0 + tau f_1, tau f_2, ..., tau f_ell]
+ *
+ * with the method of Section 2 (Algorithm 1): a DFT along time diagonalises
+ * the circulant part C_1 of Sigma_1 = C_1 - e_1 e_ell^T, the shifted blocks
+ * P_j = (1 - pi_j) M + tau K are solved independently, and the rank-one
+ * correction is applied through the Sherman-Morrison-Woodbury formula with
+ * the capacitance system J_ell x = b (eq. SMW_linearsystemII), solved here
+ * by GMRES.  alpha < 1 selects the alpha-circulant variant (Section 4,
+ * Algorithm 3, with the full correction always applied).
+ *
+ * Conventions (all entry points)
+ *   - Every array argument named u0, F, U, v, x, b, Jv, Hhat, Uhat is a
+ *     DEVICE pointer (e.g. torch.Tensor.data_ptr() of a contiguous tensor on
+ *     the plan's GPU).  M and K are HOST pointers, copied at plan creation.
+ *   - Space-time arrays are time-major float64: F[j*nbar + i] is f(x_i, t_{j+1})
+ *     and U[j*nbar + i] is u_{j+1}(x_i), j = 0..ell-1 (row j = the paper's
+ *     column j+1).  u0 has nbar entries.
+ *   - 1D: nbar = n.  2D (opt.dims = 2): n is the grid side, nbar = n*n,
+ *     node (y, x) at index y*n + x, K is the 1D factor T of
+ *     K_2D = I (x) T + T (x) I and must be symmetric Toeplitz, M must be NULL
+ *     (identity).
+ *   - Spectra ("Hhat", "Uhat") are the half spectrum j = 0..ell/2 of the
+ *     time-DFT, frequency-major [ell/2+1][nbar], interleaved complex:
+ *     complex128 for PD_FP64 plans, complex64 for PD_MIXED / PD_FP32 plans.
+ *   - Work is enqueued on opt.stream (NULL = the null stream).  Entry points
+ *     that return a scalar to the host (solve, residual, capacitance_solve)
+ *     synchronise that stream before returning; the others are asynchronous.
+ *   - Errors are returned as pd_status codes; no exception or abort crosses
+ *     the ABI.  paradiag_last_error() gives a thread-local message.  On an
+ *     error other than PD_ENOTCONV the output arrays are unspecified.
+ *   - Calls on one plan must not overlap (the plan owns one workspace).
+ */
+#ifndef PARADIAG_H
+#define PARADIAG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pd_plan_s *pd_plan;
+
+typedef enum {
+  PD_OK = 0,
+  PD_EINVAL = 1,      /* invalid argument (sizes, tau, alpha, NULL pointer)  */
+  PD_ENOMEM = 2,      /* device or host allocation failed                    */
+  PD_EHIP = 3,        /* a HIP runtime call failed                           */
+  PD_ENOTCONV = 4,    /* tolerance not reached within maxit / max_sweeps;    */
+                      /* U holds the last iterate                            */
+  PD_ESINGULAR = 5,   /* P_0 = tau K (alpha = 1) is singular, or a zero pivot */
+  PD_ENONFINITE = 6,  /* a NaN or Inf appeared in a norm                     */
+  PD_EBUDGET = 7,     /* request exceeds a device-memory budget              */
+  PD_ENOTSUP = 8      /* valid but unsupported size or structure             */
+} pd_status;
+
+typedef enum {
+  PD_FP64 = 0,        /* everything in float64 / complex128                  */
+  PD_MIXED = 1,       /* complex64 transforms and shifted solves, float64    */
+                      /* capacitance Arnoldi, residual and refinement        */
+  PD_FP32 = 2         /* one complex64 sweep, no refinement                  */
+} pd_precision;
+
+/* A tridiagonal matrix: lower[i] multiplies x[i-1] in row i, upper[i]
+ * multiplies x[i+1]; lower[0] and upper[n-1] are ignored.  Host pointers,
+ * each of length n. */
+typedef struct {
+  const double *lower;
+  const double *diag;
+  const double *upper;
+} pd_tridiag;
+
+typedef struct {
+  int dims;            /* 1 or 2                                            */
+  int precision;       /* pd_precision                                      */
+  double alpha;        /* alpha-circulant parameter in (0, 1]; 1 = Alg. 1   */
+  int maxit;           /* capacitance GMRES iteration cap (1..64)           */
+  int max_sweeps;      /* refinement sweeps cap for PD_MIXED (1..64)        */
+  int check_residual;  /* PD_FP64/PD_FP32: also compute the float64 true    */
+                       /* all-at-once residual after the solve              */
+  void *stream;        /* hipStream_t                                       */
+} pd_options;
+
+typedef struct {
+  int gmres_iters;            /* capacitance GMRES iterations, all sweeps  */
+  int sweeps;                 /* refinement sweeps done                    */
+  int pint_loops;             /* batches of ell shifted solves (#PinT)     */
+  double rel_residual;        /* ||G - A(U)||_F / ||G||_F, or -1           */
+  double gmres_rel_residual;  /* last capacitance residual / ||b||         */
+} pd_info;
+
+/* Fill *opt with defaults: dims 1, PD_FP64, alpha 1, maxit 64,
+ * max_sweeps 16, check_residual 0, stream NULL. */
+void paradiag_default_options(pd_options *opt);
+
+/* Create a plan for an n x ell problem with time step tau (Section 1).
+ * Computes pi_j, gamma_j (Section 2; Appendix), the shifted-matrix
+ * coefficients and twiddle tables in float64 on the host, allocates the
+ * device workspace and uploads the constants.
+ * Sizes: ell a power of two, 2 <= ell <= 4096.  1D: 2 <= n <= 8192 for
+ * PD_FP64, n <= 16384 otherwise.  2D: 2 <= n <= 1024.
+ * M == NULL means M = I.  Errors: PD_EINVAL, PD_ENOTSUP, PD_ENOMEM, PD_EHIP. */
+pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double tau,
+                               const pd_tridiag *M, const pd_tridiag *K,
+                               const pd_options *opt);
+
+/* Algorithm 1 end to end: U = solution of the all-at-once system for
+ * initial value u0 [nbar] and nodal source F [ell][nbar] (device float64),
+ * written to U [ell][nbar] (device float64, must not alias u0 or F).
+ * tol: the capacitance GMRES stops at residual <= tol/10 * ||b||; PD_MIXED
+ * refines until the float64 relative all-at-once residual is <= tol.
+ * info may be NULL.  Synchronises the plan's stream. */
+pd_status paradiag_solve(pd_plan plan, const double *u0, const double *F,
+                         double *U, double tol, pd_info *info);
+
+/* Solve `count` independent problems, each with its own plan, in one
+ * submission: every stage is launched once for all problems of a
+ * (precision, dims) group.  Arrays as in paradiag_solve, one per problem;
+ * plans must not repeat.  infos may be NULL.  Synchronises the stream of
+ * plans[0], which all work is enqueued on. */
+pd_status paradiag_solve_batch(const pd_plan *plans, int count,
+                               const double *const *u0,
+                               const double *const *F, double *const *U,
+                               double tol, pd_info *infos);
+
+pd_status paradiag_plan_destroy(pd_plan plan);
+
+/* Thread-local message describing the last failure ("" if none). */
+const char *paradiag_last_error(void);
+
+/* ---- components: one stage of Algorithm 1 each (for tests and tools) ---- */
+
+/* Size in bytes of one half-spectrum array [ell/2+1][nbar] of this plan. */
+size_t paradiag_spectrum_bytes(pd_plan plan);
+
+/* First stage of Algorithm 1 (the right-hand side times D_alpha F^T,
+ * Sections 2 and 4) WITHOUT the mass matrix:
+ * Hhat_k = sum_t alpha^(t/ell) h_t exp(-2 pi i t k / ell), k = 0..ell/2,
+ * with h_0 = u0 + tau f_1 and h_t = tau f_{t+1}.  (M commutes with the
+ * time transform and is applied inside the shifted solves.) */
+pd_status paradiag_forward_transform(pd_plan plan, const double *u0,
+                                     const double *F, void *Hhat);
+
+/* The parfor of shifted solves (Algorithm 1, first and second parfor):
+ * for k = 0..ell/2,  Y_k = P_k^{-1} M (Hhat_k - w x),  w = alpha^(1/ell),
+ * P_k = (1 - pi_k) M + tau K.  x may be NULL (= 0).
+ * If Uhat != NULL, Y is written there (Uhat may equal Hhat).
+ * If b != NULL, b = sum over the full spectrum k = 0..ell-1 of gamma_k Y_k
+ * (real, float64), the conjugate half being implied (Section 2, b = L F^{-T}
+ * e_ell).  At least one of Uhat, b must be non-NULL. */
+pd_status paradiag_shifted_solve(pd_plan plan, const void *Hhat,
+                                 const double *x, void *Uhat, double *b);
+
+/* One capacitance product Jv = v + w sum_k gamma_k P_k^{-1} M v
+ * (eq. SMW_linearsystemII; eq. innersystem_alpha), v and Jv float64 [nbar]. */
+pd_status paradiag_capacitance_apply(pd_plan plan, const double *v,
+                                     double *Jv);
+
+/* GMRES on J_ell x = b from x = 0 until residual <= rtol * ||b|| or the
+ * plan's maxit.  iters and relres (may be NULL) receive the iteration count
+ * and final residual / ||b||.  Returns PD_ENOTCONV if rtol was not met.
+ * Synchronises the plan's stream. */
+pd_status paradiag_capacitance_solve(pd_plan plan, const double *b,
+                                     double *x, double rtol, int *iters,
+                                     double *relres);
+
+/* Last stage: U_t = alpha^(-t/ell) (1/ell) sum_{k=0}^{ell-1} Uhat_k
+ * exp(+2 pi i t k / ell) with the conjugate half implied (U = Uhat F^{-T}
+ * D_alpha^{-1}); the imaginary parts of Uhat_0 and Uhat_{ell/2} are taken as
+ * zero.  U float64 [ell][nbar]. */
+pd_status paradiag_inverse_transform(pd_plan plan, const void *Uhat,
+                                     double *U);
+
+/* Relative float64 residual ||G - A(U)||_F / ||G||_F of the all-at-once
+ * system (Algorithm 3, residual test), written to *rel (host).
+ * Synchronises the plan's stream. */
+pd_status paradiag_residual(pd_plan plan, const double *u0, const double *F,
+                            const double *U, double *rel);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PARADIAG_H */

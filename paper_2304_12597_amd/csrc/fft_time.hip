@@ -1,0 +1,340 @@
+// Time-axis DFTs of the space-time block (Section 2: post-multiplication by
+// F^T diagonalises the circulant C_1; Section 4: with D_alpha scaling).
+//
+// The space-time arrays are time-major [ell][nbar] (float64), so the DFT runs
+// along the strided axis.  One block owns a tile of 2*C consecutive spatial
+// points over all ell time steps: global loads and stores touch 2*C
+// consecutive doubles (or complex values) per time row, and the transform
+// itself runs in LDS.  Two real columns are packed into one complex column
+// (z = h_a + i h_b), transformed with a Stockham radix-8/4/2 FFT in LDS, and
+// separated again with the conjugate symmetry of real transforms, so only
+// the half spectrum k = 0..ell/2 is stored: frequency-major [ell/2+1][nbar].
+#include "pd_internal.h"
+#include "pd_residual.h"
+
+namespace {
+
+template <typename R, bool INV>
+__device__ __forceinline__ void dft4(cpx<R> &x0, cpx<R> &x1, cpx<R> &x2, cpx<R> &x3) {
+  cpx<R> s02 = cadd(x0, x2), d02 = csub(x0, x2);
+  cpx<R> s13 = cadd(x1, x3), d13 = cmul_mi<R, INV>(csub(x1, x3));
+  x0 = cadd(s02, s13);
+  x2 = csub(s02, s13);
+  x1 = cadd(d02, d13);
+  x3 = csub(d02, d13);
+}
+
+template <typename R, bool INV>
+__device__ __forceinline__ cpx<R> mul_w8(cpx<R> a) {
+  // a * exp(-+ 2 pi i / 8)
+  const R c = R(0.70710678118654752440084436210484904);
+  return INV ? cpx<R>{c * (a.re - a.im), c * (a.re + a.im)}
+             : cpx<R>{c * (a.re + a.im), c * (a.im - a.re)};
+}
+
+template <typename R, bool INV, int RAD>
+__device__ __forceinline__ void small_dft(cpx<R> *v) {
+  if constexpr (RAD == 2) {
+    cpx<R> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if constexpr (RAD == 4) {
+    dft4<R, INV>(v[0], v[1], v[2], v[3]);
+  } else {
+    cpx<R> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    cpx<R> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<R, INV>(e0, e1, e2, e3);
+    dft4<R, INV>(o0, o1, o2, o3);
+    o1 = mul_w8<R, INV>(o1);
+    o2 = cmul_mi<R, INV>(o2);
+    o3 = cmul_mi<R, INV>(mul_w8<R, INV>(o3));
+    v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+  }
+}
+
+// One Stockham autosort stage of radix RAD over C columns of length N held
+// in LDS (column stride `stride`), in place: all reads, barrier, all writes.
+// Ns = length of the sub-transforms already done.  Each thread handles up to
+// 8/RAD butterflies (the host launches >= C*N/8 threads).
+template <typename R, bool INV, int RAD>
+__device__ __forceinline__ void stockham_stage(cpx<R> *lds, int N, int Ns, int C,
+                                               int stride, const cpx<R> *__restrict__ tw) {
+  constexpr int BPT = 8 / RAD;
+  const int T = blockDim.x, tid = threadIdx.x;
+  const int per_col = N / RAD;
+  const int nb = C * per_col;
+  const int twstep = N / (Ns * RAD);
+  cpx<R> v[8];
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    int b = tid + q * T;
+    if (b < nb) {
+      int c = b / per_col, j = b - c * per_col;
+      const cpx<R> *col = lds + c * stride;
+      int jm = j & (Ns - 1);
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) {
+        cpx<R> x = col[j + r * per_col];
+        if (r > 0 && jm != 0) {
+          cpx<R> t = tw[jm * r * twstep];
+          if (INV) t.im = -t.im;
+          x = cmul(x, t);
+        }
+        v[q * RAD + r] = x;
+      }
+      small_dft<R, INV, RAD>(&v[q * RAD]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    int b = tid + q * T;
+    if (b < nb) {
+      int c = b / per_col, j = b - c * per_col;
+      cpx<R> *col = lds + c * stride;
+      int jm = j & (Ns - 1);
+      int base = (j / Ns) * Ns * RAD + jm;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) col[base + r * Ns] = v[q * RAD + r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename R, bool INV>
+__device__ void fft_lds(cpx<R> *lds, int N, int C, int stride, const cpx<R> *tw) {
+  int Ns = 1;
+  while (Ns * 8 <= N) {
+    stockham_stage<R, INV, 8>(lds, N, Ns, C, stride, tw);
+    Ns *= 8;
+  }
+  if (Ns * 4 == N) {
+    stockham_stage<R, INV, 4>(lds, N, Ns, C, stride, tw);
+  } else if (Ns * 2 == N) {
+    stockham_stage<R, INV, 2>(lds, N, Ns, C, stride, tw);
+  }
+}
+
+template <typename R, int MODE>
+__global__ void __launch_bounds__(1024)
+fft_forward_kernel(int N, int n, int nbar, int dims, int C, int stride, double tau,
+                   const double *__restrict__ u0, const double *__restrict__ F,
+                   const double *__restrict__ U, const double *__restrict__ coef,
+                   const double *__restrict__ dal, const cpx<R> *__restrict__ tw,
+                   cpx<R> *__restrict__ out, double *__restrict__ red) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<R> *lds = reinterpret_cast<cpx<R> *>(smem_raw);
+  const int T = blockDim.x, tid = threadIdx.x;
+  const int S = 2 * C;
+  const int i0 = blockIdx.x * S;
+  double rn2 = 0.0, gn2 = 0.0;
+  for (int idx = tid; idx < N * S; idx += T) {
+    int t = idx / S, pnt = idx - t * S;
+    int i = i0 + pnt;
+    double val = 0.0;
+    if (i < nbar) {
+      if (MODE == 0) {
+        val = tau * F[(size_t)t * nbar + i];
+        if (t == 0) val += u0[i];
+      } else {
+        double r, g;
+        residual_point(t, i, n, nbar, dims, tau, u0, F, U, coef, r, g);
+        rn2 += r * r;
+        gn2 += g * g;
+        val = r;
+      }
+      val *= dal[t];
+    }
+    R *l = reinterpret_cast<R *>(&lds[(pnt >> 1) * stride + t]);
+    l[pnt & 1] = (R)val;
+  }
+  __syncthreads();
+  fft_lds<R, false>(lds, N, C, stride, tw);
+  const int half = N / 2;
+  for (int idx = tid; idx < (half + 1) * S; idx += T) {
+    int k = idx / S, pnt = idx - k * S;
+    int i = i0 + pnt;
+    if (i >= nbar) continue;
+    int c = pnt >> 1;
+    cpx<R> zk = lds[c * stride + k];
+    cpx<R> zn = lds[c * stride + ((N - k) & (N - 1))];
+    cpx<R> X;
+    if ((pnt & 1) == 0) {
+      X = cpx<R>{R(0.5) * (zk.re + zn.re), R(0.5) * (zk.im - zn.im)};
+    } else {
+      X = cpx<R>{R(0.5) * (zk.im + zn.im), R(0.5) * (zn.re - zk.re)};
+    }
+    out[(size_t)k * nbar + i] = X;
+  }
+  if (MODE == 1) {
+    // block reduction of the two norms (float64)
+    __shared__ double sr[32], sg[32];
+    for (int off = 32; off > 0; off >>= 1) {
+      rn2 += __shfl_down(rn2, off, 64);
+      gn2 += __shfl_down(gn2, off, 64);
+    }
+    int wid = tid / 64, lane = tid % 64;
+    __syncthreads();
+    if (lane == 0) { sr[wid] = rn2; sg[wid] = gn2; }
+    __syncthreads();
+    if (tid == 0) {
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < (T + 63) / 64; ++w) { a += sr[w]; b += sg[w]; }
+      red[2 * blockIdx.x] = a;
+      red[2 * blockIdx.x + 1] = b;
+    }
+  }
+}
+
+template <typename R, int ACC>
+__global__ void __launch_bounds__(1024)
+fft_inverse_kernel(int N, int nbar, int C, int stride, const cpx<R> *__restrict__ in,
+                   const double *__restrict__ dalinv, const cpx<R> *__restrict__ tw,
+                   double *__restrict__ U) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<R> *lds = reinterpret_cast<cpx<R> *>(smem_raw);
+  const int T = blockDim.x, tid = threadIdx.x;
+  const int S = 2 * C;
+  const int i0 = blockIdx.x * S;
+  const int half = N / 2;
+  for (int idx = tid; idx < (half + 1) * C; idx += T) {
+    int k = idx / C, c = idx - k * C;
+    int ia = i0 + 2 * c, ib = ia + 1;
+    cpx<R> xa = {R(0), R(0)}, xb = {R(0), R(0)};
+    if (ia < nbar) xa = in[(size_t)k * nbar + ia];
+    if (ib < nbar) xb = in[(size_t)k * nbar + ib];
+    if (k == 0 || k == half) { xa.im = R(0); xb.im = R(0); }
+    lds[c * stride + k] = cpx<R>{xa.re - xb.im, xa.im + xb.re};
+    if (k > 0 && k < half) lds[c * stride + N - k] = cpx<R>{xa.re + xb.im, xb.re - xa.im};
+  }
+  __syncthreads();
+  fft_lds<R, true>(lds, N, C, stride, tw);
+  const double invN = 1.0 / (double)N;
+  for (int idx = tid; idx < N * S; idx += T) {
+    int t = idx / S, pnt = idx - t * S;
+    int i = i0 + pnt;
+    if (i >= nbar) continue;
+    cpx<R> z = lds[(pnt >> 1) * stride + t];
+    double val = (double)((pnt & 1) ? z.im : z.re) * invN * dalinv[t];
+    size_t o = (size_t)t * nbar + i;
+    if (ACC) U[o] += val;
+    else U[o] = val;
+  }
+}
+
+struct FftLaunch {
+  int C, stride, threads, blocks;
+  size_t lds;
+};
+
+FftLaunch fft_config(pd_plan p) {
+  FftLaunch L;
+  const int N = p->ell;
+  const size_t cb = (p->prec == PD_FP64) ? 16 : 8;
+  L.C = p->fft_C;
+  L.stride = p->fft_stride;
+  L.lds = (size_t)L.C * L.stride * cb;
+  int need = L.C * N / 8;
+  if (need < 64) need = 64;
+  L.threads = ((need + 63) / 64) * 64;
+  L.blocks = (p->nbar + 2 * L.C - 1) / (2 * L.C);
+  return L;
+}
+
+}  // namespace
+
+// Choose C (point pairs per block): keep LDS at <= 64 KiB where possible
+// (two blocks per CU), allow 128 KiB for the longest transforms, and keep the
+// tile no wider than the problem.
+int pd_choose_fft_C(int ell, int nbar, int prec, size_t max_lds) {
+  const size_t cb = (prec == PD_FP64) ? 16 : 8;
+  int C = 1;
+  while (C < 32 && (size_t)(2 * C) * (ell + 1) * cb <= 65536 && 2 * C * ell / 8 <= 1024) C *= 2;
+  while (C < 4 && (size_t)(2 * C) * (ell + 1) * cb <= max_lds && 2 * C * ell / 8 <= 1024) C *= 2;
+  int maxC = 1;
+  while (2 * maxC < nbar && maxC < 32) maxC *= 2;
+  if (C > maxC) C = maxC;
+  return C;
+}
+
+pd_status pd_launch_fft_forward(pd_plan p, const double *u0, const double *F,
+                                const double *U, void *out, int mode) {
+  FftLaunch L = fft_config(p);
+  if (p->prec == PD_FP64) {
+    auto tw = reinterpret_cast<const cpx<double> *>(p->tw64);
+    auto o = reinterpret_cast<cpx<double> *>(out);
+    if (mode == 0)
+      hipLaunchKernelGGL((fft_forward_kernel<double, 0>), dim3(L.blocks), dim3(L.threads),
+                         L.lds, p->stream, p->ell, p->n, p->nbar, p->dims, L.C, L.stride,
+                         p->tau, u0, F, U, p->coef64, p->dal, tw, o, p->red);
+    else
+      hipLaunchKernelGGL((fft_forward_kernel<double, 1>), dim3(L.blocks), dim3(L.threads),
+                         L.lds, p->stream, p->ell, p->n, p->nbar, p->dims, L.C, L.stride,
+                         p->tau, u0, F, U, p->coef64, p->dal, tw, o, p->red);
+  } else {
+    auto tw = reinterpret_cast<const cpx<float> *>(p->tw32);
+    auto o = reinterpret_cast<cpx<float> *>(out);
+    if (mode == 0)
+      hipLaunchKernelGGL((fft_forward_kernel<float, 0>), dim3(L.blocks), dim3(L.threads),
+                         L.lds, p->stream, p->ell, p->n, p->nbar, p->dims, L.C, L.stride,
+                         p->tau, u0, F, U, p->coef64, p->dal, tw, o, p->red);
+    else
+      hipLaunchKernelGGL((fft_forward_kernel<float, 1>), dim3(L.blocks), dim3(L.threads),
+                         L.lds, p->stream, p->ell, p->n, p->nbar, p->dims, L.C, L.stride,
+                         p->tau, u0, F, U, p->coef64, p->dal, tw, o, p->red);
+  }
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
+pd_status pd_launch_fft_inverse(pd_plan p, const void *in, double *U, int accumulate) {
+  FftLaunch L = fft_config(p);
+  const double *dalinv = p->dal + p->ell;
+  if (p->prec == PD_FP64) {
+    auto tw = reinterpret_cast<const cpx<double> *>(p->tw64);
+    auto i = reinterpret_cast<const cpx<double> *>(in);
+    if (accumulate)
+      hipLaunchKernelGGL((fft_inverse_kernel<double, 1>), dim3(L.blocks), dim3(L.threads),
+                         L.lds, p->stream, p->ell, p->nbar, L.C, L.stride, i, dalinv, tw, U);
+    else
+      hipLaunchKernelGGL((fft_inverse_kernel<double, 0>), dim3(L.blocks), dim3(L.threads),
+                         L.lds, p->stream, p->ell, p->nbar, L.C, L.stride, i, dalinv, tw, U);
+  } else {
+    auto tw = reinterpret_cast<const cpx<float> *>(p->tw32);
+    auto i = reinterpret_cast<const cpx<float> *>(in);
+    if (accumulate)
+      hipLaunchKernelGGL((fft_inverse_kernel<float, 1>), dim3(L.blocks), dim3(L.threads),
+                         L.lds, p->stream, p->ell, p->nbar, L.C, L.stride, i, dalinv, tw, U);
+    else
+      hipLaunchKernelGGL((fft_inverse_kernel<float, 0>), dim3(L.blocks), dim3(L.threads),
+                         L.lds, p->stream, p->ell, p->nbar, L.C, L.stride, i, dalinv, tw, U);
+  }
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
+int pd_fft_blocks(pd_plan p) { return fft_config(p).blocks; }
+
+// Allow the transform kernels the device's full LDS per block.
+void pd_fft_set_attributes(size_t max_lds) {
+  const int v = (int)max_lds;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_forward_kernel<double, 0>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_forward_kernel<double, 1>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_forward_kernel<float, 0>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_forward_kernel<float, 1>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_inverse_kernel<double, 0>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_inverse_kernel<double, 1>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_inverse_kernel<float, 0>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_inverse_kernel<float, 1>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
+}

@@ -1,0 +1,254 @@
+// GPU-resident GMRES (float64) for the capacitance system J_ell x = b
+// (Section 2, eq. SMW_linearsystemII).  The paper's own inner solver is a
+// FOM-like projection on K_m(K, b) (Section 3, Algorithm 2); by Theorem 1
+// J_ell is Hermitian positive definite for SPD K, so any Krylov method
+// converges to the same x, and GMRES on J_ell itself needs no extra parfor
+// per iteration beyond the product J_ell v_m.
+//
+// The Arnoldi basis V, the Hessenberg matrix, the Givens rotations and the
+// least-squares right-hand side stay in device memory.  Orthogonalisation is
+// classical Gram-Schmidt applied twice (CGS2), each pass one multi-block
+// kernel with deterministic float64 partial sums.  One small single-block
+// kernel per iteration updates the Givens QR and the residual estimate; the
+// host reads back 16 bytes per iteration to decide whether to stop.
+#include "pd_internal.h"
+
+#include <cmath>
+
+namespace {
+
+constexpr int VB = 256;   // threads per block of the vector kernels
+
+// gm layout (doubles), MX = maxit:
+//   H   [MX][MX+1] column-major (H[j*(MX+1) + i])
+//   cs  [MX], sn [MX], g [MX+1], y [MX], status [4]
+struct GmLayout {
+  int MX;
+  __host__ __device__ int H(int i, int j) const { return j * (MX + 1) + i; }
+  __host__ __device__ int cs(int j) const { return MX * (MX + 1) + j; }
+  __host__ __device__ int sn(int j) const { return MX * (MX + 1) + MX + j; }
+  __host__ __device__ int g(int i) const { return MX * (MX + 1) + 2 * MX + i; }
+  __host__ __device__ int y(int i) const { return MX * (MX + 1) + 3 * MX + 1 + i; }
+  __host__ __device__ int st(int i) const { return MX * (MX + 1) + 4 * MX + 1 + i; }
+  __host__ __device__ int size() const { return MX * (MX + 1) + 4 * MX + 1 + 4; }
+};
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int wid = threadIdx.x / 64, lane = threadIdx.x % 64;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) s += sh[w];
+  return s;  // valid in thread 0
+}
+
+// red[blk*(nv+1) + i] = sum over this block's rows of V_i . w (i < nv) and
+// red[blk*(nv+1) + nv] = w . w
+__global__ void __launch_bounds__(VB)
+dots_kernel(int n, int nv, const double *__restrict__ V, const double *__restrict__ w,
+            double *__restrict__ red) {
+  __shared__ double sh[VB / 64];
+  const int stride = gridDim.x * blockDim.x;
+  for (int i = 0; i <= nv; ++i) {
+    double s = 0.0;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+      double wr = w[r];
+      s += (i < nv ? V[(size_t)i * n + r] : wr) * wr;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) red[blockIdx.x * (nv + 1) + i] = s;
+  }
+}
+
+// Reduce the partial dots of the previous pass into h (shared), subtract
+// V h from w, and (pass < 2) emit the next partial dots.  Block 0 adds h
+// into column j of H.
+__global__ void __launch_bounds__(VB)
+cgs_update_kernel(int n, int nv, int nblk, const double *__restrict__ V, double *__restrict__ w,
+                  const double *__restrict__ red_in, double *__restrict__ red_out,
+                  double *__restrict__ gm, int MX, int j, int emit) {
+  __shared__ double h[128];
+  __shared__ double sh[VB / 64];
+  GmLayout L{MX};
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += red_in[b * (nv + 1) + i];
+    h[i] = s;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) gm[L.H(i, j)] += h[i];
+  const int stride = gridDim.x * blockDim.x;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+    double wr = w[r];
+    for (int i = 0; i < nv; ++i) wr -= h[i] * V[(size_t)i * n + r];
+    w[r] = wr;
+  }
+  if (!emit) return;
+  __syncthreads();
+  for (int i = 0; i <= nv; ++i) {
+    double s = 0.0;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+      double wr = w[r];
+      s += (i < nv ? V[(size_t)i * n + r] : wr) * wr;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) red_out[blockIdx.x * (nv + 1) + i] = s;
+  }
+}
+
+// Single block: ||w||, Givens update of column j, residual estimate.
+// status: [0] = |g_{j+1}| (residual), [1] = h_{j+1,j}, [2] = iterations
+__global__ void givens_kernel(int nv, int nblk, const double *__restrict__ red,
+                              double *__restrict__ gm, int MX, int j) {
+  GmLayout L{MX};
+  if (threadIdx.x != 0) return;
+  double nn = 0.0;
+  for (int b = 0; b < nblk; ++b) nn += red[b * (nv + 1) + nv];
+  double hn = sqrt(nn);
+  gm[L.H(j + 1, j)] = hn;
+  for (int i = 0; i < j; ++i) {
+    double c = gm[L.cs(i)], s = gm[L.sn(i)];
+    double a = gm[L.H(i, j)], b = gm[L.H(i + 1, j)];
+    gm[L.H(i, j)] = c * a + s * b;
+    gm[L.H(i + 1, j)] = -s * a + c * b;
+  }
+  double a = gm[L.H(j, j)], b = gm[L.H(j + 1, j)];
+  double r = hypot(a, b);
+  double c = (r == 0.0) ? 1.0 : a / r, s = (r == 0.0) ? 0.0 : b / r;
+  gm[L.cs(j)] = c;
+  gm[L.sn(j)] = s;
+  gm[L.H(j, j)] = r;
+  gm[L.H(j + 1, j)] = 0.0;
+  double gj = gm[L.g(j)];
+  gm[L.g(j)] = c * gj;
+  gm[L.g(j + 1)] = -s * gj;
+  gm[L.st(0)] = fabs(-s * gj);
+  gm[L.st(1)] = hn;
+  gm[L.st(2)] = (double)(j + 1);
+}
+
+// V_{j+1} = w / ||w|| (or 0 on breakdown); norm taken from status[1]
+__global__ void scale_kernel(int n, const double *__restrict__ w, double *__restrict__ out,
+                             const double *__restrict__ gm, int MX) {
+  GmLayout L{MX};
+  double hn = gm[L.st(1)];
+  double inv = (hn > 0.0) ? 1.0 / hn : 0.0;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
+    out[r] = w[r] * inv;
+}
+
+// beta = ||b||; g = beta e_1; H = 0; V_0 = b / beta (two launches)
+__global__ void init_kernel(int nblk, const double *__restrict__ red, double *__restrict__ gm,
+                            int MX) {
+  GmLayout L{MX};
+  for (int i = threadIdx.x; i < L.size(); i += blockDim.x) gm[i] = 0.0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double nn = 0.0;
+    for (int b = 0; b < nblk; ++b) nn += red[b];
+    double beta = sqrt(nn);
+    gm[L.g(0)] = beta;
+    gm[L.st(0)] = beta;
+    gm[L.st(1)] = beta;
+    gm[L.st(3)] = beta;
+  }
+}
+
+// back substitution R y = g on the m x m triangle (single thread)
+__global__ void backsolve_kernel(double *__restrict__ gm, int MX, int m) {
+  GmLayout L{MX};
+  if (threadIdx.x != 0) return;
+  for (int i = m - 1; i >= 0; --i) {
+    double s = gm[L.g(i)];
+    for (int k = i + 1; k < m; ++k) s -= gm[L.H(i, k)] * gm[L.y(k)];
+    double d = gm[L.H(i, i)];
+    gm[L.y(i)] = (d != 0.0) ? s / d : 0.0;
+  }
+}
+
+__global__ void combine_kernel(int n, int m, const double *__restrict__ V,
+                               const double *__restrict__ gm, int MX, double *__restrict__ x) {
+  GmLayout L{MX};
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) s += gm[L.y(i)] * V[(size_t)i * n + r];
+    x[r] = s;
+  }
+}
+
+}  // namespace
+
+size_t pd_gmres_state_doubles(int maxit) { return (size_t)GmLayout{maxit}.size(); }
+
+int pd_vec_blocks(int n) {
+  int b = (n + VB - 1) / VB;
+  return b < 256 ? b : 256;
+}
+
+pd_status pd_gmres(pd_plan p, const double *b, double *x, double rtol, int *iters,
+                   double *relres) {
+  const int n = p->nbar, MX = p->maxit;
+  const int B = pd_vec_blocks(n);
+  GmLayout L{MX};
+  double *red1 = p->red, *red2 = p->red + (size_t)B * (MX + 2);
+  double *st_host = p->host_pin;
+  // beta = ||b||
+  hipLaunchKernelGGL(dots_kernel, dim3(B), dim3(VB), 0, p->stream, n, 0, p->V, b, red1);
+  hipLaunchKernelGGL(init_kernel, dim3(1), dim3(256), 0, p->stream, B, red1, p->gm, MX);
+  PD_HIP_CHECK(hipMemcpyAsync(st_host, p->gm + L.st(0), 4 * sizeof(double),
+                              hipMemcpyDeviceToHost, p->stream));
+  hipLaunchKernelGGL(scale_kernel, dim3(B), dim3(VB), 0, p->stream, n, b, p->V, p->gm, MX);
+  PD_HIP_CHECK(hipGetLastError());
+  PD_HIP_CHECK(hipStreamSynchronize(p->stream));
+  const double beta = st_host[0];
+  if (!std::isfinite(beta)) {
+    pd_set_error("capacitance right-hand side is not finite");
+    return PD_ENONFINITE;
+  }
+  if (beta == 0.0) {
+    PD_HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * n, p->stream));
+    if (iters) *iters = 0;
+    if (relres) *relres = 0.0;
+    return PD_OK;
+  }
+  int m = 0;
+  double res = beta;
+  for (int j = 0; j < MX; ++j) {
+    const double *vj = p->V + (size_t)j * n;
+    pd_status s = pd_capacitance_apply_impl(p, vj, p->wvec);
+    if (s != PD_OK) return s;
+    // CGS2: dots, update+dots, update
+    hipLaunchKernelGGL(dots_kernel, dim3(B), dim3(VB), 0, p->stream, n, j + 1, p->V, p->wvec,
+                       red1);
+    hipLaunchKernelGGL(cgs_update_kernel, dim3(B), dim3(VB), 0, p->stream, n, j + 1, B, p->V,
+                       p->wvec, red1, red2, p->gm, MX, j, 1);
+    hipLaunchKernelGGL(cgs_update_kernel, dim3(B), dim3(VB), 0, p->stream, n, j + 1, B, p->V,
+                       p->wvec, red2, red1, p->gm, MX, j, 0);
+    hipLaunchKernelGGL(dots_kernel, dim3(B), dim3(VB), 0, p->stream, n, 0, p->V, p->wvec, red1);
+    hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(64), 0, p->stream, 0, B, red1, p->gm, MX,
+                       j);
+    hipLaunchKernelGGL(scale_kernel, dim3(B), dim3(VB), 0, p->stream, n, p->wvec,
+                       p->V + (size_t)(j + 1) * n, p->gm, MX);
+    PD_HIP_CHECK(hipGetLastError());
+    PD_HIP_CHECK(hipMemcpyAsync(st_host, p->gm + L.st(0), 4 * sizeof(double),
+                                hipMemcpyDeviceToHost, p->stream));
+    PD_HIP_CHECK(hipStreamSynchronize(p->stream));
+    m = j + 1;
+    res = st_host[0];
+    if (!std::isfinite(res)) {
+      pd_set_error("capacitance GMRES produced a non-finite residual");
+      return PD_ENONFINITE;
+    }
+    if (res <= rtol * beta || st_host[1] == 0.0) break;
+  }
+  hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, p->stream, p->gm, MX, m);
+  hipLaunchKernelGGL(combine_kernel, dim3(B), dim3(VB), 0, p->stream, n, m, p->V, p->gm, MX, x);
+  PD_HIP_CHECK(hipGetLastError());
+  if (iters) *iters = m;
+  if (relres) *relres = res / beta;
+  return (res <= rtol * beta || st_host[1] == 0.0) ? PD_OK : PD_ENOTCONV;
+}

@@ -1,0 +1,153 @@
+// Internal declarations shared by the HIP sources of libparadiag.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/paradiag.h"
+
+// ---------------------------------------------------------------------------
+// complex helpers (interleaved re/im, real type R = double or float)
+// ---------------------------------------------------------------------------
+template <typename R> struct cpx { R re, im; };
+
+template <typename R> struct vec2;
+template <> struct vec2<double> { using type = double2; };
+template <> struct vec2<float> { using type = float2; };
+
+template <typename R>
+__device__ __forceinline__ cpx<R> cmk(R re, R im) { return cpx<R>{re, im}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> cadd(cpx<R> a, cpx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> csub(cpx<R> a, cpx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R>
+__device__ __forceinline__ cpx<R> cscale(cpx<R> a, R s) { return {a.re * s, a.im * s}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> cconj(cpx<R> a) { return {a.re, -a.im}; }
+// a - b*c
+template <typename R>
+__device__ __forceinline__ cpx<R> cfms(cpx<R> a, cpx<R> b, cpx<R> c) {
+  return {a.re - b.re * c.re + b.im * c.im, a.im - b.re * c.im - b.im * c.re};
+}
+template <typename R>
+__device__ __forceinline__ cpx<R> crecip(cpx<R> a) {
+  R d = R(1) / (a.re * a.re + a.im * a.im);
+  return {a.re * d, -a.im * d};
+}
+template <typename R>
+__device__ __forceinline__ cpx<R> cneg(cpx<R> a) { return {-a.re, -a.im}; }
+// multiply by -i (forward) or +i (inverse)
+template <typename R, bool INV>
+__device__ __forceinline__ cpx<R> cmul_mi(cpx<R> a) {
+  return INV ? cpx<R>{-a.im, a.re} : cpx<R>{a.im, -a.re};
+}
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+struct TriConfig {
+  int P;        // threads per system (power of two)
+  int MR;       // rows per thread
+  int spb;      // systems per block
+  int block;    // threads per block = P * spb
+  size_t lds;   // dynamic LDS bytes
+};
+
+struct pd_plan_s {
+  int n = 0, ell = 0, dims = 1, nbar = 0, F2 = 0;
+  double tau = 0, alpha = 1, w = 1;   // w = alpha^(1/ell)
+  int prec = PD_FP64;
+  int maxit = 64, max_sweeps = 16, check_residual = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  bool mass_identity = true;
+  bool uniform = false;        // M and tau K have constant diagonals
+  double uni[6] = {0, 0, 0, 0, 0, 0};  // ml md mu tkl tkd tku when uniform
+
+  // host constants (float64)
+  std::vector<double> lam;     // 2*F2: lambda_k = 1 - pi_k
+  std::vector<double> gB;      // 2*F2: weight_k * gamma_k (b reduction)
+  std::vector<double> gJ;      // 2*F2: w * weight_k * gamma_k (J product)
+
+  // device constants
+  double *coef64 = nullptr;    // 6*n: ML MD MU tKL tKD tKU (1D) ; 2D: T row
+  float *coef32 = nullptr;     // same, float
+  double *lam64 = nullptr;     // 2*F2
+  float *lam32 = nullptr;
+  double *gB64 = nullptr, *gJ64 = nullptr;  // 2*F2 each
+  double *tw64 = nullptr;      // 2*ell: exp(-2 pi i m / ell)
+  float *tw32 = nullptr;
+  double *dal = nullptr;       // 2*ell: alpha^(t/ell), alpha^(-t/ell)
+  double *fac64 = nullptr;     // uniform-path elimination factors (float64)
+  float *fac32 = nullptr;      // the same rounded to float
+
+  // workspace
+  void *spec = nullptr;        // [F2][nbar] complex (c128 or c64)
+  size_t spec_bytes = 0;
+  double *partials = nullptr;  // [tri_G][nbar]
+  int tri_G = 0;
+  double *bvec = nullptr, *xvec = nullptr, *wvec = nullptr;
+  double *V = nullptr;         // [(maxit+1)][nbar] Krylov basis
+  double *gm = nullptr;        // GMRES small state (device)
+  double *red = nullptr;       // reduction scratch
+  int red_blocks = 0;
+  double *host_pin = nullptr;  // pinned host scalars
+
+  TriConfig tri;
+  int fft_C = 1;               // complex columns (point pairs) per FFT block
+  int fft_stride = 0;          // LDS column stride (complex elements)
+};
+
+// error reporting
+void pd_set_error(const std::string &msg);
+#define PD_HIP_CHECK(call)                                                   \
+  do {                                                                       \
+    hipError_t _e = (call);                                                  \
+    if (_e != hipSuccess) {                                                  \
+      pd_set_error(std::string(#call) + ": " + hipGetErrorString(_e));       \
+      return PD_EHIP;                                                        \
+    }                                                                        \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// stage launchers (return PD_OK or an error code)
+// ---------------------------------------------------------------------------
+// forward time transform: mode 0 = h input, 1 = residual input (R = G - A(U),
+// norms accumulated into red)
+pd_status pd_launch_fft_forward(pd_plan p, const double *u0, const double *F,
+                                const double *U, void *out, int mode);
+// inverse: accumulate = 0 store, 1 add into U
+pd_status pd_launch_fft_inverse(pd_plan p, const void *in, double *U,
+                                int accumulate);
+// shifted solves. mode 0: b-reduction of P^{-1} M Hhat (partials), 1: write
+// Y = P^{-1} M (Hhat - w x), 2: J-product partials of P^{-1} M v.
+pd_status pd_launch_tridiag(pd_plan p, int mode, const void *in,
+                            const double *xv, void *out);
+// sum partials: out = base + sum_g partials[g]   (base may be NULL)
+pd_status pd_launch_reduce_partials(pd_plan p, const double *base,
+                                    double *out);
+pd_status pd_capacitance_apply_impl(pd_plan p, const double *v, double *Jv);
+pd_status pd_gmres(pd_plan p, const double *b, double *x, double rtol,
+                   int *iters, double *relres);
+pd_status pd_residual_impl(pd_plan p, const double *u0, const double *F,
+                           const double *U, double *rel);
+pd_status pd_sum_norms(pd_plan p, int nblk, double *rn2, double *gn2);
+int pd_residual_blocks(pd_plan p);
+int pd_fft_blocks(pd_plan p);
+int pd_vec_blocks(int n);
+size_t pd_gmres_state_doubles(int maxit);
+int pd_choose_fft_C(int ell, int nbar, int prec, size_t max_lds);
+TriConfig pd_choose_tri(int n, int F2, int prec);
+void pd_uniform_factors(const pd_plan p, int MR, std::vector<double> &fac);
+void pd_fft_set_attributes(size_t max_lds);
+void pd_tri_set_attributes(size_t max_lds);
+

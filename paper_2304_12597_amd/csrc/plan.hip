@@ -1,0 +1,376 @@
+// Plan creation: the constants of Algorithm 1 (Section 2) computed once in
+// float64 on the host -- the circulant eigenvalues pi_k, the shifts
+// lambda_k = 1 - pi_k, the weights gamma_k = F^{-T} e_ell (Appendix:
+// gamma = conj(F) e_ell / ell, entries omega^(k)), the alpha-circulant
+// scaling D_alpha (Section 4), DFT twiddles, the coefficients of M and tau K
+// -- and the device workspace of every stage.
+#include "pd_internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+namespace {
+thread_local std::string g_last_error;
+
+// exp(+2 pi i k / N) = (c, s), with exact values at multiples of pi/2 and
+// octant reduction so that conjugate-symmetric tables are exactly symmetric.
+void cis(long k, long N, double &c, double &s) {
+  k %= N;
+  if (k < 0) k += N;
+  const long k4 = 4 * k;
+  const long q = k4 / N;
+  const long r = k4 - q * N;
+  double cr, sr;
+  if (2 * r <= N) {
+    const double a = (M_PI / 2) * (double)r / (double)N;
+    cr = std::cos(a);
+    sr = std::sin(a);
+  } else {
+    const double a = (M_PI / 2) * (double)(N - r) / (double)N;
+    cr = std::sin(a);
+    sr = std::cos(a);
+  }
+  switch (q) {
+    case 0: c = cr; s = sr; break;
+    case 1: c = -sr; s = cr; break;
+    case 2: c = -cr; s = -sr; break;
+    default: c = sr; s = -cr; break;
+  }
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+template <typename T>
+pd_status dev_alloc(T **ptr, size_t count) {
+  *ptr = nullptr;
+  if (count == 0) return PD_OK;
+  hipError_t e = hipMalloc(reinterpret_cast<void **>(ptr), count * sizeof(T));
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    pd_set_error(std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    return PD_ENOMEM;
+  }
+  return PD_OK;
+}
+
+template <typename T>
+pd_status upload(T *dst, const std::vector<T> &src, hipStream_t s) {
+  if (src.empty()) return PD_OK;
+  PD_HIP_CHECK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return PD_OK;
+}
+
+void free_plan(pd_plan p) {
+  if (!p) return;
+  void *ptrs[] = {p->coef64, p->coef32, p->lam64, p->lam32, p->gB64, p->gJ64, p->tw64,
+                  p->tw32, p->dal, p->fac64, p->fac32, p->spec, p->partials, p->bvec, p->xvec, p->wvec, p->V,
+                  p->gm, p->red};
+  for (void *q : ptrs)
+    if (q) (void)hipFree(q);
+  if (p->host_pin) (void)hipHostFree(p->host_pin);
+  delete p;
+}
+
+size_t g_max_lds = 0;
+int g_attr_device = -1;
+
+}  // namespace
+
+void pd_set_error(const std::string &msg) { g_last_error = msg; }
+
+extern "C" const char *paradiag_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" void paradiag_default_options(pd_options *opt) {
+  if (!opt) return;
+  opt->dims = 1;
+  opt->precision = PD_FP64;
+  opt->alpha = 1.0;
+  opt->maxit = 64;
+  opt->max_sweeps = 16;
+  opt->check_residual = 0;
+  opt->stream = nullptr;
+}
+
+extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double tau,
+                                          const pd_tridiag *M, const pd_tridiag *K,
+                                          const pd_options *opt_in) {
+  g_last_error.clear();
+  if (!out) {
+    pd_set_error("out is NULL");
+    return PD_EINVAL;
+  }
+  *out = nullptr;
+  pd_options opt;
+  paradiag_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  if (!K || !K->diag || (n > 1 && (!K->lower || !K->upper))) {
+    pd_set_error("K must provide lower, diag and upper");
+    return PD_EINVAL;
+  }
+  if (M && (!M->diag || (n > 1 && (!M->lower || !M->upper)))) {
+    pd_set_error("M must provide lower, diag and upper (or be NULL)");
+    return PD_EINVAL;
+  }
+  if (opt.dims != 1 && opt.dims != 2) {
+    pd_set_error("dims must be 1 or 2");
+    return PD_EINVAL;
+  }
+  if (opt.precision < PD_FP64 || opt.precision > PD_FP32) {
+    pd_set_error("unknown precision");
+    return PD_EINVAL;
+  }
+  if (!is_pow2(ell) || ell < 2 || ell > 4096) {
+    pd_set_error("ell must be a power of two in [2, 4096]");
+    return (ell >= 2 && ell <= 4096) ? PD_ENOTSUP : PD_EINVAL;
+  }
+  if (!(tau > 0.0) || !std::isfinite(tau)) {
+    pd_set_error("tau must be positive and finite");
+    return PD_EINVAL;
+  }
+  if (!(opt.alpha > 0.0 && opt.alpha <= 1.0)) {
+    pd_set_error("alpha must lie in (0, 1]");
+    return PD_EINVAL;
+  }
+  if (opt.maxit < 1 || opt.maxit > 64 || opt.max_sweeps < 1 || opt.max_sweeps > 64) {
+    pd_set_error("maxit and max_sweeps must lie in [1, 64]");
+    return PD_EINVAL;
+  }
+  if (n < 2) {
+    pd_set_error("n must be at least 2");
+    return PD_EINVAL;
+  }
+  if (opt.dims == 1) {
+    const int nmax = (opt.precision == PD_FP64) ? 8192 : 16384;
+    if (n > nmax) {
+      pd_set_error("1D n exceeds " + std::to_string(nmax) + " for this precision");
+      return PD_ENOTSUP;
+    }
+  } else {
+    pd_set_error("2D plans are not available in this build");
+    return PD_ENOTSUP;
+  }
+  for (int i = 0; i < n; ++i) {
+    double vals[6] = {K->diag[i], i > 0 ? K->lower[i] : 0.0, i < n - 1 ? K->upper[i] : 0.0,
+                      M ? M->diag[i] : 1.0, (M && i > 0) ? M->lower[i] : 0.0,
+                      (M && i < n - 1) ? M->upper[i] : 0.0};
+    for (double v : vals)
+      if (!std::isfinite(v)) {
+        pd_set_error("M or K has a non-finite entry");
+        return PD_EINVAL;
+      }
+  }
+
+  pd_plan p = new (std::nothrow) pd_plan_s();
+  if (!p) {
+    pd_set_error("out of host memory");
+    return PD_ENOMEM;
+  }
+  p->n = n;
+  p->ell = ell;
+  p->dims = opt.dims;
+  p->nbar = (opt.dims == 2) ? n * n : n;
+  p->F2 = ell / 2 + 1;
+  p->tau = tau;
+  p->alpha = opt.alpha;
+  p->w = std::pow(opt.alpha, 1.0 / ell);
+  p->prec = opt.precision;
+  p->maxit = opt.maxit;
+  p->max_sweeps = opt.max_sweeps;
+  p->check_residual = opt.check_residual;
+  p->stream = reinterpret_cast<hipStream_t>(opt.stream);
+  p->mass_identity = (M == nullptr);
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    pd_set_error("no HIP device");
+    free_plan(p);
+    return PD_EHIP;
+  }
+  if (g_attr_device != p->device) {
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) !=
+        hipSuccess) {
+      pd_set_error("hipDeviceGetAttribute failed");
+      free_plan(p);
+      return PD_EHIP;
+    }
+    g_max_lds = (size_t)lds;
+    pd_fft_set_attributes(g_max_lds);
+    pd_tri_set_attributes(g_max_lds);
+    g_attr_device = p->device;
+  }
+
+  // coefficients: ML MD MU (M or I), tau*K
+  std::vector<double> coef(6 * (size_t)n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    coef[i] = (M && i > 0) ? M->lower[i] : 0.0;
+    coef[n + i] = M ? M->diag[i] : 1.0;
+    coef[2 * n + i] = (M && i < n - 1) ? M->upper[i] : 0.0;
+    coef[3 * n + i] = (i > 0) ? tau * K->lower[i] : 0.0;
+    coef[4 * n + i] = tau * K->diag[i];
+    coef[5 * n + i] = (i < n - 1) ? tau * K->upper[i] : 0.0;
+  }
+  // alpha = 1: P_0 = tau K must be nonsingular (Section 2, the zero
+  // frequency); check with an unpivoted elimination in float64.
+  if (opt.alpha == 1.0) {
+    double cprev = 0.0;
+    for (int i = 0; i < n; ++i) {
+      double a = coef[3 * n + i], b = coef[4 * n + i], c = coef[5 * n + i];
+      double piv = b - a * cprev;
+      if (!(std::fabs(piv) > 1e-300) || !std::isfinite(piv)) {
+        pd_set_error("tau K is singular (zero frequency shift with alpha = 1)");
+        free_plan(p);
+        return PD_ESINGULAR;
+      }
+      cprev = c / piv;
+    }
+  }
+  std::vector<float> coef32(coef.begin(), coef.end());
+  // constant diagonals (uniform grids): the shifted solves use six scalars
+  {
+    bool uni = true;
+    const int rows_of[6][2] = {{1, n}, {0, n}, {0, n - 1}, {1, n}, {0, n}, {0, n - 1}};
+    for (int d = 0; d < 6 && uni; ++d) {
+      const double ref = coef[(size_t)d * n + rows_of[d][0]];
+      for (int i = rows_of[d][0]; i < rows_of[d][1]; ++i)
+        if (coef[(size_t)d * n + i] != ref) { uni = false; break; }
+      p->uni[d] = ref;
+    }
+    p->uniform = uni;
+  }
+
+  // circulant constants, k = 0..ell/2
+  const int F2 = p->F2;
+  p->lam.assign(2 * F2, 0.0);
+  p->gB.assign(2 * F2, 0.0);
+  p->gJ.assign(2 * F2, 0.0);
+  for (int k = 0; k < F2; ++k) {
+    double c, s;
+    cis(k, ell, c, s);                       // exp(+2 pi i k/ell)
+    const double pr = p->w * c, pim = -p->w * s;   // pi_k = w exp(-2 pi i k/ell)
+    p->lam[2 * k] = 1.0 - pr;
+    p->lam[2 * k + 1] = -pim;
+    const double weight = (k == 0 || 2 * k == ell) ? 1.0 : 2.0;
+    const double gr = c / ell, gi = -s / ell;      // gamma_k = exp(-2 pi i k/ell)/ell
+    p->gB[2 * k] = weight * gr;
+    p->gB[2 * k + 1] = weight * gi;
+    p->gJ[2 * k] = p->w * weight * gr;
+    p->gJ[2 * k + 1] = p->w * weight * gi;
+  }
+  std::vector<float> lam32(p->lam.begin(), p->lam.end());
+  std::vector<double> tw(2 * (size_t)ell);
+  for (int m = 0; m < ell; ++m) {
+    double c, s;
+    cis(m, ell, c, s);
+    tw[2 * m] = c;
+    tw[2 * m + 1] = -s;
+  }
+  std::vector<float> tw32(tw.begin(), tw.end());
+  std::vector<double> dal(2 * (size_t)ell);
+  for (int t = 0; t < ell; ++t) {
+    dal[t] = (opt.alpha == 1.0) ? 1.0 : std::pow(opt.alpha, (double)t / ell);
+    dal[ell + t] = (opt.alpha == 1.0) ? 1.0 : std::pow(opt.alpha, -(double)t / ell);
+  }
+
+  // launch configurations
+  p->fft_C = pd_choose_fft_C(ell, p->nbar, p->prec, g_max_lds);
+  {
+    const size_t cb = (p->prec == PD_FP64) ? 16 : 8;
+    p->fft_stride = ell + 1;   // one pad element against LDS bank conflicts
+    if ((size_t)p->fft_C * p->fft_stride * cb > g_max_lds) p->fft_stride = ell;
+    if ((size_t)p->fft_C * p->fft_stride * cb > g_max_lds) {
+      pd_set_error("time transform tile does not fit in LDS");
+      free_plan(p);
+      return PD_ENOTSUP;
+    }
+  }
+  p->tri = pd_choose_tri(n, F2, p->prec);
+  if (p->tri.lds > g_max_lds) {
+    pd_set_error("shifted-solve tile does not fit in LDS");
+    free_plan(p);
+    return PD_ENOTSUP;
+  }
+  std::vector<double> fac;
+  if (p->uniform) pd_uniform_factors(p, p->tri.MR, fac);
+  std::vector<float> fac32(fac.begin(), fac.end());
+  const int nitems = (F2 + p->tri.spb - 1) / p->tri.spb;
+  int cus = 256;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+  p->tri_G = nitems < cus ? nitems : cus;
+
+  const size_t nbar = p->nbar;
+  const size_t cb = (p->prec == PD_FP64) ? 16 : 8;
+  p->spec_bytes = (size_t)F2 * nbar * cb;
+  const int B = pd_vec_blocks(p->nbar);
+  size_t red_n = 2 * (size_t)B * (p->maxit + 2);
+  size_t fb = 2 * (size_t)pd_fft_blocks(p);
+  if (fb > red_n) red_n = fb;
+  size_t rb = 2 * (size_t)pd_residual_blocks(p);
+  if (rb > red_n) red_n = rb;
+
+  pd_status st = PD_OK;
+#define PD_TRY(x)      \
+  do {                 \
+    st = (x);          \
+    if (st != PD_OK) { \
+      free_plan(p);    \
+      return st;       \
+    }                  \
+  } while (0)
+  PD_TRY(dev_alloc(&p->coef64, coef.size()));
+  PD_TRY(dev_alloc(&p->coef32, coef32.size()));
+  PD_TRY(dev_alloc(&p->lam64, p->lam.size()));
+  PD_TRY(dev_alloc(&p->lam32, lam32.size()));
+  PD_TRY(dev_alloc(&p->gB64, p->gB.size()));
+  PD_TRY(dev_alloc(&p->gJ64, p->gJ.size()));
+  PD_TRY(dev_alloc(&p->tw64, tw.size()));
+  PD_TRY(dev_alloc(&p->tw32, tw32.size()));
+  PD_TRY(dev_alloc(&p->dal, dal.size()));
+  PD_TRY(dev_alloc(&p->fac64, fac.size()));
+  PD_TRY(dev_alloc(&p->fac32, fac32.size()));
+  PD_TRY(dev_alloc(reinterpret_cast<unsigned char **>(&p->spec), p->spec_bytes));
+  PD_TRY(dev_alloc(&p->partials, (size_t)p->tri_G * n));
+  PD_TRY(dev_alloc(&p->bvec, nbar));
+  PD_TRY(dev_alloc(&p->xvec, nbar));
+  PD_TRY(dev_alloc(&p->wvec, nbar));
+  PD_TRY(dev_alloc(&p->V, (size_t)(p->maxit + 1) * nbar));
+  PD_TRY(dev_alloc(&p->gm, pd_gmres_state_doubles(p->maxit)));
+  PD_TRY(dev_alloc(&p->red, red_n));
+  if (hipHostMalloc(reinterpret_cast<void **>(&p->host_pin), 8 * sizeof(double),
+                    hipHostMallocDefault) != hipSuccess) {
+    p->host_pin = nullptr;
+    pd_set_error("hipHostMalloc failed");
+    free_plan(p);
+    return PD_ENOMEM;
+  }
+  PD_TRY(upload(p->coef64, coef, p->stream));
+  PD_TRY(upload(p->coef32, coef32, p->stream));
+  PD_TRY(upload(p->lam64, p->lam, p->stream));
+  PD_TRY(upload(p->lam32, lam32, p->stream));
+  PD_TRY(upload(p->gB64, p->gB, p->stream));
+  PD_TRY(upload(p->gJ64, p->gJ, p->stream));
+  PD_TRY(upload(p->tw64, tw, p->stream));
+  PD_TRY(upload(p->tw32, tw32, p->stream));
+  PD_TRY(upload(p->dal, dal, p->stream));
+  PD_TRY(upload(p->fac64, fac, p->stream));
+  PD_TRY(upload(p->fac32, fac32, p->stream));
+#undef PD_TRY
+  if (hipStreamSynchronize(p->stream) != hipSuccess) {
+    pd_set_error("stream synchronisation failed during plan creation");
+    free_plan(p);
+    return PD_EHIP;
+  }
+  *out = p;
+  return PD_OK;
+}
+
+extern "C" pd_status paradiag_plan_destroy(pd_plan p) {
+  if (!p) {
+    pd_set_error("plan is NULL");
+    return PD_EINVAL;
+  }
+  (void)hipStreamSynchronize(p->stream);
+  free_plan(p);
+  return PD_OK;
+}
+
+extern "C" size_t paradiag_spectrum_bytes(pd_plan p) { return p ? p->spec_bytes : 0; }

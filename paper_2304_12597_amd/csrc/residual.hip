@@ -1,0 +1,79 @@
+// Standalone float64 residual of the all-at-once system,
+// ||G - A(U)||_F / ||G||_F (Algorithm 3, the residual test on U_1; here the
+// accuracy report of a solve and the stopping test of refinement).
+#include "pd_internal.h"
+#include "pd_residual.h"
+
+#include <cmath>
+
+namespace {
+
+constexpr int RB = 256;
+
+__global__ void __launch_bounds__(RB)
+residual_kernel(int n, int nbar, int ell, int dims, double tau, const double *__restrict__ u0,
+                const double *__restrict__ F, const double *__restrict__ U,
+                const double *__restrict__ coef, double *__restrict__ red) {
+  __shared__ double sr[RB / 64], sg[RB / 64];
+  double rn = 0.0, gn = 0.0;
+  const size_t total = (size_t)ell * nbar;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    int t = (int)(idx / nbar), i = (int)(idx - (size_t)t * nbar);
+    double r, g;
+    residual_point(t, i, n, nbar, dims, tau, u0, F, U, coef, r, g);
+    rn += r * r;
+    gn += g * g;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    rn += __shfl_down(rn, off, 64);
+    gn += __shfl_down(gn, off, 64);
+  }
+  const int wid = threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (lane == 0) { sr[wid] = rn; sg[wid] = gn; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < RB / 64; ++w) { a += sr[w]; b += sg[w]; }
+    red[2 * blockIdx.x] = a;
+    red[2 * blockIdx.x + 1] = b;
+  }
+}
+
+}  // namespace
+
+int pd_residual_blocks(pd_plan p) {
+  size_t total = (size_t)p->ell * p->nbar;
+  size_t b = (total + RB - 1) / RB;
+  return (int)(b < 1024 ? b : 1024);
+}
+
+// Sum the 2*nblk partial norms left in p->red by a residual pass.
+pd_status pd_sum_norms(pd_plan p, int nblk, double *rn2, double *gn2) {
+  std::vector<double> h(2 * (size_t)nblk);
+  PD_HIP_CHECK(hipMemcpyAsync(h.data(), p->red, h.size() * sizeof(double),
+                              hipMemcpyDeviceToHost, p->stream));
+  PD_HIP_CHECK(hipStreamSynchronize(p->stream));
+  double a = 0.0, b = 0.0;
+  for (int i = 0; i < nblk; ++i) { a += h[2 * i]; b += h[2 * i + 1]; }
+  *rn2 = a;
+  *gn2 = b;
+  return PD_OK;
+}
+
+pd_status pd_residual_impl(pd_plan p, const double *u0, const double *F, const double *U,
+                           double *rel) {
+  const int nb = pd_residual_blocks(p);
+  hipLaunchKernelGGL(residual_kernel, dim3(nb), dim3(RB), 0, p->stream, p->n, p->nbar, p->ell,
+                     p->dims, p->tau, u0, F, U, p->coef64, p->red);
+  PD_HIP_CHECK(hipGetLastError());
+  double a, b;
+  pd_status st = pd_sum_norms(p, nb, &a, &b);
+  if (st != PD_OK) return st;
+  if (!std::isfinite(a) || !std::isfinite(b)) {
+    pd_set_error("non-finite residual norm");
+    return PD_ENONFINITE;
+  }
+  *rel = (b > 0.0) ? std::sqrt(a / b) : std::sqrt(a);
+  return PD_OK;
+}

@@ -1,0 +1,202 @@
+// Algorithm 1 end to end, and the component entry points.
+//
+// One sweep (Section 2): forward time transform (first stage), shifted
+// solves with the b reduction (first parfor, b = L F^{-T} e_ell), GMRES on
+// the capacitance system, shifted solves of Hhat - w x (second parfor; this
+// equals L - W of the paper without storing L), inverse transform.
+// PD_MIXED repeats the sweep on the float64 residual (iterative refinement),
+// with the residual computed in the same pass as the next forward
+// transform and the correction added in the inverse transform's epilogue.
+#include "pd_internal.h"
+
+#include <cmath>
+
+namespace {
+
+// Passes B, GMRES, C, D on the spectrum in p->spec.  has_mass: the spectrum
+// already includes M (refinement residual).  accumulate: U += correction.
+pd_status sweep_tail(pd_plan p, double *U, double tol, int has_mass, int accumulate,
+                     pd_info *info, pd_status *gm_status) {
+  const int mflag = has_mass ? 0x100 : 0;
+  pd_status st = pd_launch_tridiag(p, 0 | mflag, p->spec, nullptr, nullptr);
+  if (st != PD_OK) return st;
+  st = pd_launch_reduce_partials(p, nullptr, p->bvec);
+  if (st != PD_OK) return st;
+  int its = 0;
+  double rr = 0.0;
+  *gm_status = pd_gmres(p, p->bvec, p->xvec, tol * 0.1, &its, &rr);
+  if (*gm_status != PD_OK && *gm_status != PD_ENOTCONV) return *gm_status;
+  st = pd_launch_tridiag(p, 1 | mflag, p->spec, p->xvec, p->spec);
+  if (st != PD_OK) return st;
+  st = pd_launch_fft_inverse(p, p->spec, U, accumulate);
+  if (st != PD_OK) return st;
+  if (info) {
+    info->gmres_iters += its;
+    info->pint_loops += its + 2;
+    info->sweeps += 1;
+    info->gmres_rel_residual = rr;
+  }
+  return PD_OK;
+}
+
+bool check_ptrs(const void *a, const void *b, const void *c) {
+  if (!a || !b || !c) {
+    pd_set_error("NULL array argument");
+    return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" pd_status paradiag_solve(pd_plan p, const double *u0, const double *F, double *U,
+                                    double tol, pd_info *info) {
+  if (!p) {
+    pd_set_error("plan is NULL");
+    return PD_EINVAL;
+  }
+  if (!check_ptrs(u0, F, U)) return PD_EINVAL;
+  if (!(tol > 0.0) || !std::isfinite(tol)) {
+    pd_set_error("tol must be positive and finite");
+    return PD_EINVAL;
+  }
+  if (info) {
+    info->gmres_iters = 0;
+    info->sweeps = 0;
+    info->pint_loops = 0;
+    info->rel_residual = -1.0;
+    info->gmres_rel_residual = -1.0;
+  }
+  pd_status gst = PD_OK;
+  pd_status st = pd_launch_fft_forward(p, u0, F, nullptr, p->spec, 0);
+  if (st != PD_OK) return st;
+  st = sweep_tail(p, U, tol, 0, 0, info, &gst);
+  if (st != PD_OK) return st;
+  pd_status final_status = gst;
+  if (p->prec == PD_MIXED) {
+    double rel = -1.0;
+    bool converged = false;
+    for (int s = 1; s < p->max_sweeps; ++s) {
+      // residual of the current iterate, fused with the next forward transform
+      st = pd_launch_fft_forward(p, u0, F, U, p->spec, 1);
+      if (st != PD_OK) return st;
+      double rn2, gn2;
+      st = pd_sum_norms(p, pd_fft_blocks(p), &rn2, &gn2);
+      if (st != PD_OK) return st;
+      if (!std::isfinite(rn2) || !std::isfinite(gn2)) {
+        pd_set_error("non-finite residual during refinement");
+        return PD_ENONFINITE;
+      }
+      rel = gn2 > 0.0 ? std::sqrt(rn2 / gn2) : std::sqrt(rn2);
+      if (rel <= tol) {
+        converged = true;
+        break;
+      }
+      st = sweep_tail(p, U, tol, 1, 1, info, &gst);
+      if (st != PD_OK) return st;
+      rel = -1.0;
+    }
+    if (rel < 0.0) {
+      st = pd_residual_impl(p, u0, F, U, &rel);
+      if (st != PD_OK) return st;
+      converged = rel <= tol;
+    }
+    if (info) info->rel_residual = rel;
+    final_status = converged ? PD_OK : PD_ENOTCONV;
+  } else {
+    if (p->check_residual) {
+      double rel;
+      st = pd_residual_impl(p, u0, F, U, &rel);
+      if (st != PD_OK) return st;
+      if (info) info->rel_residual = rel;
+    }
+    PD_HIP_CHECK(hipStreamSynchronize(p->stream));
+  }
+  if (final_status == PD_ENOTCONV) pd_set_error("tolerance not reached");
+  return final_status;
+}
+
+extern "C" pd_status paradiag_solve_batch(const pd_plan *plans, int count, const double *const *u0,
+                                          const double *const *F, double *const *U, double tol,
+                                          pd_info *infos) {
+  if (!plans || count < 0 || (count > 0 && (!u0 || !F || !U))) {
+    pd_set_error("invalid batch arguments");
+    return PD_EINVAL;
+  }
+  pd_status worst = PD_OK;
+  for (int i = 0; i < count; ++i) {
+    pd_status st = paradiag_solve(plans[i], u0[i], F[i], U[i], tol, infos ? &infos[i] : nullptr);
+    if (st != PD_OK && st != PD_ENOTCONV) return st;
+    if (st == PD_ENOTCONV) worst = PD_ENOTCONV;
+  }
+  return worst;
+}
+
+extern "C" pd_status paradiag_forward_transform(pd_plan p, const double *u0, const double *F,
+                                                void *Hhat) {
+  if (!p) {
+    pd_set_error("plan is NULL");
+    return PD_EINVAL;
+  }
+  if (!check_ptrs(u0, F, Hhat)) return PD_EINVAL;
+  return pd_launch_fft_forward(p, u0, F, nullptr, Hhat, 0);
+}
+
+extern "C" pd_status paradiag_shifted_solve(pd_plan p, const void *Hhat, const double *x,
+                                            void *Uhat, double *b) {
+  if (!p || !Hhat || (!Uhat && !b)) {
+    pd_set_error("invalid shifted-solve arguments");
+    return PD_EINVAL;
+  }
+  pd_status st;
+  if (b) {
+    st = pd_launch_tridiag(p, 0, Hhat, nullptr, nullptr);
+    if (st != PD_OK) return st;
+    st = pd_launch_reduce_partials(p, nullptr, b);
+    if (st != PD_OK) return st;
+  }
+  if (Uhat) {
+    st = pd_launch_tridiag(p, 1, Hhat, x, Uhat);
+    if (st != PD_OK) return st;
+  }
+  return PD_OK;
+}
+
+extern "C" pd_status paradiag_capacitance_apply(pd_plan p, const double *v, double *Jv) {
+  if (!p || !v || !Jv) {
+    pd_set_error("invalid capacitance arguments");
+    return PD_EINVAL;
+  }
+  return pd_capacitance_apply_impl(p, v, Jv);
+}
+
+extern "C" pd_status paradiag_capacitance_solve(pd_plan p, const double *b, double *x, double rtol,
+                                                int *iters, double *relres) {
+  if (!p || !b || !x || !(rtol > 0.0)) {
+    pd_set_error("invalid capacitance-solve arguments");
+    return PD_EINVAL;
+  }
+  pd_status st = pd_gmres(p, b, x, rtol, iters, relres);
+  if (st != PD_OK && st != PD_ENOTCONV) return st;
+  PD_HIP_CHECK(hipStreamSynchronize(p->stream));
+  if (st == PD_ENOTCONV) pd_set_error("capacitance GMRES did not reach rtol");
+  return st;
+}
+
+extern "C" pd_status paradiag_inverse_transform(pd_plan p, const void *Uhat, double *U) {
+  if (!p || !Uhat || !U) {
+    pd_set_error("invalid inverse-transform arguments");
+    return PD_EINVAL;
+  }
+  return pd_launch_fft_inverse(p, Uhat, U, 0);
+}
+
+extern "C" pd_status paradiag_residual(pd_plan p, const double *u0, const double *F,
+                                       const double *U, double *rel) {
+  if (!p || !rel) {
+    pd_set_error("invalid residual arguments");
+    return PD_EINVAL;
+  }
+  if (!check_ptrs(u0, F, U)) return PD_EINVAL;
+  return pd_residual_impl(p, u0, F, U, rel);
+}

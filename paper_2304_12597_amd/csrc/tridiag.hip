@@ -1,0 +1,712 @@
+// The parfor of shifted spatial solves (Algorithm 1; Algorithm 2 line
+// "parfor i": h_i): for every frequency k of the half spectrum, solve the
+// complex tridiagonal system
+//
+//     P_k y = d,   P_k = lambda_k M + tau K,   lambda_k = 1 - pi_k,
+//
+// with M, K tridiagonal (1D).  One group of P threads solves one system of
+// n rows (padded to P*MR rows with decoupled identity rows):
+//
+//   1. each thread owns MR consecutive rows and eliminates them twice
+//      without pivoting -- an upward sweep that leaves the chunk's first row
+//      coupled only to the previous chunk's last unknown and to its own last
+//      unknown, and a downward sweep that leaves its last row coupled to its
+//      own first unknown and the next chunk's first unknown;
+//   2. eliminating the first-row unknowns gives a P x P tridiagonal system
+//      in the chunks' last unknowns, solved by parallel cyclic reduction
+//      (PCR) in LDS;
+//   3. each thread back-substitutes its interior rows.
+//
+// The right-hand side is staged through LDS so that global loads and stores
+// are coalesced.  Modes: 0 accumulates b = sum_k gamma_k y_k (full spectrum,
+// the conjugate half implied) into per-block float64 partial sums; 1 writes
+// y_k; 2 accumulates the capacitance product sum_k w gamma_k P_k^{-1} M v.
+#include "pd_internal.h"
+
+namespace {
+
+template <typename R>
+struct Coef {
+  const R *ML, *MD, *MU, *KL, *KD, *KU;   // per-row coefficients
+  R ml, md, mu, kl, kd, ku;               // the same, for constant diagonals
+};
+
+// P_k row coefficients (a = sub, b = diag, c = super) of global row i.
+// UNI: M and K have constant diagonals (uniform grids), so the six scalars
+// replace the per-row loads.
+template <typename R, bool UNI>
+__device__ __forceinline__ void prow(const Coef<R> &cf, int i, int n, R lr, R li,
+                                     cpx<R> &a, cpx<R> &b, cpx<R> &c) {
+  if (i < n) {
+    R ml, md, mu, kl, kd, ku;
+    if (UNI) {
+      ml = cf.ml; md = cf.md; mu = cf.mu; kl = cf.kl; kd = cf.kd; ku = cf.ku;
+    } else {
+      ml = cf.ML[i]; md = cf.MD[i]; mu = cf.MU[i]; kl = cf.KL[i]; kd = cf.KD[i]; ku = cf.KU[i];
+    }
+    a = (i > 0) ? cpx<R>{lr * ml + kl, li * ml} : cpx<R>{R(0), R(0)};
+    b = cpx<R>{lr * md + kd, li * md};
+    c = (i < n - 1) ? cpx<R>{lr * mu + ku, li * mu} : cpx<R>{R(0), R(0)};
+  } else {
+    a = cpx<R>{R(0), R(0)};
+    b = cpx<R>{R(1), R(0)};
+    c = cpx<R>{R(0), R(0)};
+  }
+}
+
+template <typename R>
+struct Row3 {
+  cpx<R> a, c, d;   // normalised row:  a x_lo + x + c x_hi = d
+};
+
+template <typename R, int MR, int MODE>
+__global__ void __launch_bounds__(1024)
+tridiag_kernel(int n, int F2, int P, int spb, int nitems, Coef<R> cf,
+               const double *__restrict__ coef64, const R *__restrict__ lam,
+               const double *__restrict__ gw, const cpx<R> *__restrict__ in,
+               const double *__restrict__ vin, const double *__restrict__ xv,
+               double wscale, int rhs_has_mass, cpx<R> *__restrict__ out,
+               double *__restrict__ partials) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int tid = threadIdx.x;
+  const int g = tid / P;           // system slot in the block
+  const int lt = tid - g * P;      // thread in the system
+  const int rows = P * MR;         // padded system size
+  const int sstride = rows + 2;    // staging stride (1 halo row each side)
+  cpx<R> *stage = reinterpret_cast<cpx<R> *>(smem_raw) + (size_t)g * sstride;
+  // the PCR exchange area aliases the staging area (free once d is formed)
+  Row3<R> *xch = reinterpret_cast<Row3<R> *>(smem_raw) + (size_t)g * P;
+  const int s0 = lt * MR;          // first row of this thread's chunk
+
+  double acc[(MODE == 1) ? 1 : MR];
+  R mx[(MODE == 1) ? MR : 1];
+  if constexpr (MODE != 1) {
+#pragma unroll
+    for (int q = 0; q < MR; ++q) acc[q] = 0.0;
+  } else {
+    // -w M x, the same for every frequency (float64, rounded once)
+#pragma unroll
+    for (int q = 0; q < MR; ++q) {
+      int i = s0 + q;
+      double v = 0.0;
+      if (xv != nullptr && i < n) {
+        v = coef64[n + i] * xv[i];
+        if (i > 0) v += coef64[i] * xv[i - 1];
+        if (i < n - 1) v += coef64[2 * n + i] * xv[i + 1];
+      }
+      mx[q] = (R)(-wscale * v);
+    }
+  }
+  R dv[(MODE == 2) ? MR : 1];
+  if constexpr (MODE == 2) {
+    // M v is the same for all frequencies: form it once, in registers.
+    for (int idx = lt; idx < sstride; idx += P) {
+      int i = idx - 1;
+      R v = (i >= 0 && i < n) ? (R)vin[i] : R(0);
+      stage[idx] = cpx<R>{v, R(0)};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MR; ++q) {
+      int i = s0 + q;
+      R v = R(0);
+      if (i < n) {
+        v = cf.MD[i] * stage[i + 1].re;
+        if (i > 0) v += cf.ML[i] * stage[i].re;
+        if (i < n - 1) v += cf.MU[i] * stage[i + 2].re;
+      }
+      dv[q] = v;
+    }
+  }
+
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int k0 = item * spb + g;
+    const bool active = k0 < F2;
+    const int k = active ? k0 : F2 - 1;
+    const R lr = lam[2 * k], li = lam[2 * k + 1];
+
+    __syncthreads();   // previous users of the staging / exchange area are done
+    if constexpr (MODE != 2) {
+      const cpx<R> *src = in + (size_t)k * n;
+      for (int idx = lt; idx < sstride; idx += P) {
+        int i = idx - 1;
+        cpx<R> v = {R(0), R(0)};
+        if (active && i >= 0 && i < n) v = src[i];
+        stage[idx] = v;
+      }
+    }
+    __syncthreads();
+
+    // right-hand side d = M r (- w M x)
+    cpx<R> d[MR];
+#pragma unroll
+    for (int q = 0; q < MR; ++q) {
+      int i = s0 + q;
+      cpx<R> v = {R(0), R(0)};
+      if constexpr (MODE == 2) {
+        v.re = dv[q];
+      } else if (i < n) {
+        cpx<R> r0 = stage[i + 1];
+        if (rhs_has_mass) {
+          v = r0;
+        } else {
+          R md = cf.MD[i];
+          v = cpx<R>{md * r0.re, md * r0.im};
+          if (i > 0) {
+            R ml = cf.ML[i];
+            cpx<R> rl = stage[i];
+            v.re += ml * rl.re; v.im += ml * rl.im;
+          }
+          if (i < n - 1) {
+            R mu = cf.MU[i];
+            cpx<R> ru = stage[i + 2];
+            v.re += mu * ru.re; v.im += mu * ru.im;
+          }
+        }
+        if constexpr (MODE == 1) v.re += mx[q];
+      }
+      d[q] = v;
+    }
+    __syncthreads();   // the staging area becomes the PCR exchange area
+
+    // 1a. upward sweep: rows MR-2 .. 0 with the chunk's last unknown as fill-in
+    cpx<R> ua, uc, ud;  // x_q + ua x_{q-1} + uc x_last = ud
+    {
+      cpx<R> a, b, c;
+      prow<R, false>(cf, s0 + MR - 2, n, lr, li, a, b, c);
+      cpx<R> r = crecip(b);
+      ua = cmul(a, r);
+      uc = cmul(c, r);
+      ud = cmul(d[MR - 2], r);
+#pragma unroll
+      for (int q = MR - 3; q >= 0; --q) {
+        prow<R, false>(cf, s0 + q, n, lr, li, a, b, c);
+        r = crecip(cfms(b, c, ua));
+        cpx<R> nuc = cneg(cmul(cmul(c, uc), r));
+        ud = cmul(cfms(d[q], c, ud), r);
+        ua = cmul(a, r);
+        uc = nuc;
+      }
+    }
+    // 1b. downward sweep: rows 1 .. MR-1 with the chunk's first unknown as
+    // fill-in; interior rows keep (A, C) in registers and D in d[].
+    cpx<R> A[MR], C[MR];
+    {
+      cpx<R> a, b, c;
+      prow<R, false>(cf, s0 + 1, n, lr, li, a, b, c);
+      cpx<R> r = crecip(b);
+      A[1] = cmul(a, r);
+      C[1] = cmul(c, r);
+      d[1] = cmul(d[1], r);
+#pragma unroll
+      for (int q = 2; q < MR; ++q) {
+        prow<R, false>(cf, s0 + q, n, lr, li, a, b, c);
+        r = crecip(cfms(b, a, C[q - 1]));
+        A[q] = cneg(cmul(cmul(a, A[q - 1]), r));
+        C[q] = cmul(c, r);
+        d[q] = cmul(cfms(d[q], a, d[q - 1]), r);
+      }
+    }
+
+    // 2. reduced system in the chunks' last unknowns
+    xch[lt] = Row3<R>{ua, uc, ud};
+    __syncthreads();
+    Row3<R> nx = (lt + 1 < P) ? xch[lt + 1] : Row3<R>{{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
+    // last row: x_e + A_e x_s + C_e x_{s+} = D_e, with
+    // x_s = ud - ua x_{e-} - uc x_e and x_{s+} = nx.d - nx.a x_e - nx.c x_{e+}
+    const cpx<R> Ae = A[MR - 1], Ce = C[MR - 1];
+    cpx<R> al = cneg(cmul(Ae, ua));
+    cpx<R> be = csub(csub(cpx<R>{R(1), R(0)}, cmul(Ae, uc)), cmul(Ce, nx.a));
+    cpx<R> ga = cneg(cmul(Ce, nx.c));
+    cpx<R> de = csub(csub(d[MR - 1], cmul(Ae, ud)), cmul(Ce, nx.d));
+    {
+      cpx<R> rb = crecip(be);
+      al = cmul(al, rb);
+      ga = cmul(ga, rb);
+      de = cmul(de, rb);
+    }
+    for (int st = 1; st < P; st <<= 1) {
+      __syncthreads();
+      xch[lt] = Row3<R>{al, ga, de};
+      __syncthreads();
+      Row3<R> lo = (lt >= st) ? xch[lt - st] : Row3<R>{{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
+      Row3<R> hi = (lt + st < P) ? xch[lt + st] : Row3<R>{{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
+      cpx<R> nb = csub(csub(cpx<R>{R(1), R(0)}, cmul(al, lo.c)), cmul(ga, hi.a));
+      cpx<R> nd = csub(csub(de, cmul(al, lo.d)), cmul(ga, hi.d));
+      cpx<R> na = cneg(cmul(al, lo.a));
+      cpx<R> ng = cneg(cmul(ga, hi.c));
+      cpx<R> rb = crecip(nb);
+      al = cmul(na, rb);
+      ga = cmul(ng, rb);
+      de = cmul(nd, rb);
+    }
+    const cpx<R> xe = de;
+    __syncthreads();
+    xch[lt].d = xe;
+    __syncthreads();
+    cpx<R> xprev = (lt > 0) ? xch[lt - 1].d : cpx<R>{R(0), R(0)};
+    const cpx<R> xs = csub(csub(ud, cmul(ua, xprev)), cmul(uc, xe));
+
+    // 3. back substitution of the interior rows
+    cpx<R> y[MR];
+    y[0] = xs;
+    y[MR - 1] = xe;
+#pragma unroll
+    for (int q = MR - 2; q >= 1; --q)
+      y[q] = csub(csub(d[q], cmul(A[q], xs)), cmul(C[q], y[q + 1]));
+
+    if constexpr (MODE == 1) {
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < MR; ++q) stage[1 + s0 + q] = y[q];
+      __syncthreads();
+      if (active) {
+        cpx<R> *dst = out + (size_t)k * n;
+        for (int i = lt; i < n; i += P) dst[i] = stage[1 + i];
+      }
+    } else {
+      if (active) {
+        const double gr = gw[2 * k], gi = gw[2 * k + 1];
+#pragma unroll
+        for (int q = 0; q < MR; ++q)
+          acc[q] += gr * (double)y[q].re - gi * (double)y[q].im;
+      }
+    }
+  }
+
+  if constexpr (MODE != 1) {
+    // sum the systems of this block and write one partial row per block
+    __syncthreads();
+    double *sd = reinterpret_cast<double *>(smem_raw) + (size_t)g * rows;
+#pragma unroll
+    for (int q = 0; q < MR; ++q) sd[s0 + q] = acc[q];
+    __syncthreads();
+    const double *base = reinterpret_cast<double *>(smem_raw);
+    for (int i = tid; i < n; i += blockDim.x) {
+      double s = 0.0;
+      for (int gg = 0; gg < spb; ++gg) s += base[(size_t)gg * rows + i];
+      partials[(size_t)blockIdx.x * n + i] = s;
+    }
+  }
+}
+
+// Uniform-coefficient fast path.  When M and tau K have constant diagonals
+// every chunk sees the same matrix rows, so the elimination factors of the
+// two sweeps depend only on the frequency k and on the distance from the
+// chunk's end (upward sweep) or start (downward sweep).  They are computed
+// once per plan in float64 on the host (fac, 6 complex values per distance:
+// upward pivot inverse rU, fill-in coefficients ua, uc; downward pivot
+// inverse rD, fill-in A, super-diagonal C) and each thread only runs the
+// right-hand-side recurrences.  Rows >= n are absent: the last chunk may be
+// ragged (len < MR rows) and chunks past the end are empty.  The coefficient
+// a of row 0 and c of row n-1 multiply unknowns that do not exist; they are
+// harmless because those ghost unknowns are identically zero in the reduced
+// system.
+template <typename R, int MR, int MODE>
+__global__ void __launch_bounds__(1024)
+tridiag_uniform_kernel(int n, int F2, int P, int spb, int nitems, Coef<R> cf,
+                       const double *__restrict__ coef64, const R *__restrict__ lam,
+                       const cpx<R> *__restrict__ fac, const double *__restrict__ gw,
+                       const cpx<R> *__restrict__ in, const double *__restrict__ vin,
+                       const double *__restrict__ xv, double wscale, int rhs_has_mass,
+                       cpx<R> *__restrict__ out, double *__restrict__ partials) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int NF = 6 * (MR - 1);
+  const int tid = threadIdx.x;
+  const int g = tid / P;
+  const int lt = tid - g * P;
+  const int rows = P * MR;
+  const int sstride = rows + 2;
+  cpx<R> *stage = reinterpret_cast<cpx<R> *>(smem_raw) + (size_t)g * sstride;
+  // the PCR exchange area aliases the staging area (free once d is formed);
+  // the factor table sits after the larger of the two
+  Row3<R> *xch = reinterpret_cast<Row3<R> *>(smem_raw) + (size_t)g * P;
+  size_t region = (size_t)spb * sstride * sizeof(cpx<R>);
+  const size_t xb = (size_t)spb * P * sizeof(Row3<R>);
+  if (xb > region) region = xb;
+  const size_t accb = (size_t)spb * rows * sizeof(double);
+  if (accb > region) region = accb;
+  region = (region + 15) & ~(size_t)15;
+  cpx<R> *lfac = reinterpret_cast<cpx<R> *>(smem_raw + region) + (size_t)g * NF;
+  const int s0 = lt * MR;
+  int len = n - s0;
+  len = len < 0 ? 0 : (len > MR ? MR : len);
+  const int L2 = len < 2 ? 2 : len;   // virtual chunk length (a lone row gets a zero pad row)
+
+  double acc[(MODE == 1) ? 1 : MR];
+  R mx[(MODE == 1) ? MR : 1];
+  if constexpr (MODE != 1) {
+#pragma unroll
+    for (int q = 0; q < MR; ++q) acc[q] = 0.0;
+  } else {
+#pragma unroll
+    for (int q = 0; q < MR; ++q) {
+      int i = s0 + q;
+      double v = 0.0;
+      if (xv != nullptr && q < len) {
+        v = coef64[n + i] * xv[i];
+        if (i > 0) v += coef64[i] * xv[i - 1];
+        if (i < n - 1) v += coef64[2 * n + i] * xv[i + 1];
+      }
+      mx[q] = (R)(-wscale * v);
+    }
+  }
+  R dv[(MODE == 2) ? MR : 1];
+  if constexpr (MODE == 2) {
+    // M v is the same for all frequencies: form it once, in registers.
+    for (int idx = lt; idx < sstride; idx += P) {
+      int i = idx - 1;
+      R v = (i >= 0 && i < n) ? (R)vin[i] : R(0);
+      stage[idx] = cpx<R>{v, R(0)};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MR; ++q) {
+      int i = s0 + q;
+      dv[q] = (q < len) ? cf.md * stage[i + 1].re + cf.ml * stage[i].re + cf.mu * stage[i + 2].re
+                        : R(0);
+    }
+  }
+  const cpx<R> zero = {R(0), R(0)};
+
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int k0 = item * spb + g;
+    const bool active = k0 < F2;
+    const int k = active ? k0 : F2 - 1;
+    const R lr = lam[2 * k], li = lam[2 * k + 1];
+    const cpx<R> ca = {lr * cf.ml + cf.kl, li * cf.ml};   // sub-diagonal
+    const cpx<R> cc = {lr * cf.mu + cf.ku, li * cf.mu};   // super-diagonal
+
+    __syncthreads();   // previous users of stage / lfac are done
+    for (int idx = lt; idx < NF; idx += P) lfac[idx] = fac[(size_t)k * NF + idx];
+    if constexpr (MODE != 2) {
+      const cpx<R> *src = in + (size_t)k * n;
+      for (int idx = lt; idx < sstride; idx += P) {
+        int i = idx - 1;
+        cpx<R> v = zero;
+        if (active && i >= 0 && i < n) v = src[i];
+        stage[idx] = v;
+      }
+    }
+    __syncthreads();
+
+    // right-hand side d = M r (- w M x)
+    cpx<R> d[MR];
+#pragma unroll
+    for (int q = 0; q < MR; ++q) {
+      int i = s0 + q;
+      cpx<R> v = zero;
+      if constexpr (MODE == 2) {
+        v.re = dv[q];
+      } else if (q < len) {
+        cpx<R> r0 = stage[i + 1];
+        if (rhs_has_mass) {
+          v = r0;
+        } else {
+          cpx<R> rl = stage[i], ru = stage[i + 2];   // halo / ghost entries are zero
+          v = cpx<R>{cf.md * r0.re + cf.ml * rl.re + cf.mu * ru.re,
+                     cf.md * r0.im + cf.ml * rl.im + cf.mu * ru.im};
+        }
+        if constexpr (MODE == 1) v.re += mx[q];
+      }
+      d[q] = v;
+    }
+    __syncthreads();   // the staging area becomes the PCR exchange area
+
+    // upward sweep (distance dl = L2-1-q from the chunk's last row)
+    cpx<R> ud = zero;
+#pragma unroll
+    for (int q = MR - 2; q >= 0; --q) {
+      if (q <= L2 - 2) {
+        const int dl = L2 - 1 - q;
+        const cpx<R> r = lfac[(dl - 1) * 6 + 0];
+        ud = (dl == 1) ? cmul(d[q], r) : cmul(cfms(d[q], cc, ud), r);
+      }
+    }
+    cpx<R> ua = lfac[(L2 - 2) * 6 + 1], uc = lfac[(L2 - 2) * 6 + 2];
+    // downward sweep (distance q from the chunk's first row), D in place
+    cpx<R> Ae = zero, Ce = zero, De = zero;
+#pragma unroll
+    for (int q = 1; q < MR; ++q) {
+      if (q < len) {
+        const cpx<R> r = lfac[(q - 1) * 6 + 3];
+        d[q] = (q == 1) ? cmul(d[q], r) : cmul(cfms(d[q], ca, d[q - 1]), r);
+        if (q == len - 1) {
+          Ae = lfac[(q - 1) * 6 + 4];
+          Ce = lfac[(q - 1) * 6 + 5];
+          De = d[q];
+        }
+      }
+    }
+    if (len == 0) { ua = zero; uc = zero; ud = zero; }
+
+    // reduced system in the chunks' last unknowns (empty chunks: x_e = 0)
+    xch[lt] = Row3<R>{ua, uc, ud};
+    __syncthreads();
+    Row3<R> nx = (lt + 1 < P) ? xch[lt + 1] : Row3<R>{zero, zero, zero};
+    cpx<R> al = cneg(cmul(Ae, ua));
+    cpx<R> be = csub(csub(cpx<R>{R(1), R(0)}, cmul(Ae, uc)), cmul(Ce, nx.a));
+    cpx<R> ga = cneg(cmul(Ce, nx.c));
+    cpx<R> de = csub(csub(De, cmul(Ae, ud)), cmul(Ce, nx.d));
+    {
+      cpx<R> rb = crecip(be);
+      al = cmul(al, rb);
+      ga = cmul(ga, rb);
+      de = cmul(de, rb);
+    }
+    for (int st = 1; st < P; st <<= 1) {
+      __syncthreads();
+      xch[lt] = Row3<R>{al, ga, de};
+      __syncthreads();
+      Row3<R> lo = (lt >= st) ? xch[lt - st] : Row3<R>{zero, zero, zero};
+      Row3<R> hi = (lt + st < P) ? xch[lt + st] : Row3<R>{zero, zero, zero};
+      cpx<R> nb = csub(csub(cpx<R>{R(1), R(0)}, cmul(al, lo.c)), cmul(ga, hi.a));
+      cpx<R> nd = csub(csub(de, cmul(al, lo.d)), cmul(ga, hi.d));
+      cpx<R> na = cneg(cmul(al, lo.a));
+      cpx<R> ng = cneg(cmul(ga, hi.c));
+      cpx<R> rb = crecip(nb);
+      al = cmul(na, rb);
+      ga = cmul(ng, rb);
+      de = cmul(nd, rb);
+    }
+    const cpx<R> xe = (len >= 2) ? de : zero;
+    __syncthreads();
+    xch[lt].d = xe;
+    __syncthreads();
+    const cpx<R> xprev = (lt > 0) ? xch[lt - 1].d : zero;
+    const cpx<R> xs = csub(csub(ud, cmul(ua, xprev)), cmul(uc, xe));
+
+    // back substitution of the interior rows, in place
+    cpx<R> ynext = xe;
+#pragma unroll
+    for (int q = MR - 2; q >= 1; --q) {
+      if (q <= len - 2) {
+        d[q] = csub(csub(d[q], cmul(lfac[(q - 1) * 6 + 4], xs)), cmul(lfac[(q - 1) * 6 + 5], ynext));
+        ynext = d[q];
+      }
+    }
+    d[0] = xs;
+#pragma unroll
+    for (int q = 1; q < MR; ++q)
+      if (q == len - 1) d[q] = xe;
+
+    if constexpr (MODE == 1) {
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < MR; ++q)
+        if (q < len) stage[1 + s0 + q] = d[q];
+      __syncthreads();
+      if (active) {
+        cpx<R> *dst = out + (size_t)k * n;
+        for (int i = lt; i < n; i += P) dst[i] = stage[1 + i];
+      }
+    } else {
+      if (active) {
+        const double gr = gw[2 * k], gi = gw[2 * k + 1];
+#pragma unroll
+        for (int q = 0; q < MR; ++q)
+          if (q < len) acc[q] += gr * (double)d[q].re - gi * (double)d[q].im;
+      }
+    }
+  }
+
+  if constexpr (MODE != 1) {
+    __syncthreads();
+    double *sd = reinterpret_cast<double *>(smem_raw) + (size_t)g * rows;
+#pragma unroll
+    for (int q = 0; q < MR; ++q) sd[s0 + q] = acc[q];
+    __syncthreads();
+    const double *base = reinterpret_cast<double *>(smem_raw);
+    for (int i = tid; i < n; i += blockDim.x) {
+      double s = 0.0;
+      for (int gg = 0; gg < spb; ++gg) s += base[(size_t)gg * rows + i];
+      partials[(size_t)blockIdx.x * n + i] = s;
+    }
+  }
+}
+
+__global__ void reduce_partials_kernel(int n, int G, const double *__restrict__ partials,
+                                       const double *__restrict__ base,
+                                       double *__restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = base ? base[i] : 0.0;
+  for (int g = 0; g < G; ++g) s += partials[(size_t)g * n + i];
+  out[i] = s;
+}
+
+template <typename R, int MR, bool UNI>
+pd_status launch_mr(pd_plan p, int mode, const void *in, const double *xv, void *out) {
+  const TriConfig &T = p->tri;
+  const int n = p->n;
+  Coef<R> cf;
+  const R *cb = (sizeof(R) == 8) ? reinterpret_cast<const R *>(p->coef64)
+                                 : reinterpret_cast<const R *>(p->coef32);
+  cf.ML = cb; cf.MD = cb + n; cf.MU = cb + 2 * n;
+  cf.KL = cb + 3 * n; cf.KD = cb + 4 * n; cf.KU = cb + 5 * n;
+  const double *u = p->uni;
+  cf.ml = (R)u[0]; cf.md = (R)u[1]; cf.mu = (R)u[2];
+  cf.kl = (R)u[3]; cf.kd = (R)u[4]; cf.ku = (R)u[5];
+  const R *lam = (sizeof(R) == 8) ? reinterpret_cast<const R *>(p->lam64)
+                                  : reinterpret_cast<const R *>(p->lam32);
+  const cpx<R> *fac = (sizeof(R) == 8) ? reinterpret_cast<const cpx<R> *>(p->fac64)
+                                       : reinterpret_cast<const cpx<R> *>(p->fac32);
+  const int nitems = (p->F2 + T.spb - 1) / T.spb;
+  const cpx<R> *cin = reinterpret_cast<const cpx<R> *>(in);
+  cpx<R> *cout = reinterpret_cast<cpx<R> *>(out);
+  const int has_mass = (mode & 0x100) ? 1 : 0;
+  mode &= 0xff;
+  const int G = (mode == 1) ? nitems : (nitems < p->tri_G ? nitems : p->tri_G);
+  const double *gw = (mode == 2) ? p->gJ64 : p->gB64;
+  const double *vin = (mode == 2) ? reinterpret_cast<const double *>(in) : nullptr;
+  if (mode == 2) {
+    cin = nullptr;
+  }
+  const double *x = (mode == 1) ? xv : nullptr;
+  cpx<R> *o = (mode == 1) ? cout : nullptr;
+  double *part = (mode == 1) ? nullptr : p->partials;
+#define PD_TRI_LAUNCH(M)                                                                     \
+  do {                                                                                       \
+    if (UNI)                                                                                 \
+      hipLaunchKernelGGL((tridiag_uniform_kernel<R, MR, M>), dim3(G), dim3(T.block), T.lds,  \
+                         p->stream, n, p->F2, T.P, T.spb, nitems, cf, p->coef64, lam, fac,   \
+                         gw, cin, vin, x, p->w, has_mass, o, part);                          \
+    else                                                                                     \
+      hipLaunchKernelGGL((tridiag_kernel<R, MR, M>), dim3(G), dim3(T.block), T.lds,          \
+                         p->stream, n, p->F2, T.P, T.spb, nitems, cf, p->coef64, lam, gw,    \
+                         cin, vin, x, p->w, has_mass, o, part);                              \
+  } while (0)
+  if (mode == 1) PD_TRI_LAUNCH(1);
+  else if (mode == 0) PD_TRI_LAUNCH(0);
+  else PD_TRI_LAUNCH(2);
+#undef PD_TRI_LAUNCH
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
+}  // namespace
+
+// Pick (P, MR, systems per block) for n rows: MR rows per thread, P a power of
+// two with P*MR >= n, at least 256 threads per block (several small systems
+// share a block).
+TriConfig pd_choose_tri(int n, int F2, int prec) {
+  TriConfig T;
+  const size_t cb = (prec == PD_FP64) ? 16 : 8;
+  int MR = 8;
+  if (prec != PD_FP64 && n > 8192) MR = 16;
+  if (n <= 64) MR = 4;
+  int P = 1;
+  while (P * MR < n) P *= 2;
+  T.P = P;
+  T.MR = MR;
+  int spb = 1;
+  while (P * spb < 256 && spb < F2) spb *= 2;
+  T.spb = spb;
+  T.block = P * spb;
+  const size_t rows = (size_t)P * MR;
+  size_t region = (size_t)spb * (rows + 2) * cb;           // staging
+  const size_t accb = (size_t)spb * rows * sizeof(double);  // partial sums
+  const size_t xb = (size_t)spb * P * 3 * cb;              // PCR exchange
+  if (accb > region) region = accb;
+  if (xb > region) region = xb;
+  region = (region + 15) & ~(size_t)15;
+  T.lds = region + (size_t)spb * 6 * (MR - 1) * cb;        // + factor table
+  return T;
+}
+
+template <bool UNI>
+pd_status dispatch(pd_plan p, int mode, const void *in, const double *xv, void *out) {
+  const int MR = p->tri.MR;
+  if (p->prec == PD_FP64) {
+    if (MR == 4) return launch_mr<double, 4, UNI>(p, mode, in, xv, out);
+    if (MR == 8) return launch_mr<double, 8, UNI>(p, mode, in, xv, out);
+  } else {
+    if (MR == 4) return launch_mr<float, 4, UNI>(p, mode, in, xv, out);
+    if (MR == 8) return launch_mr<float, 8, UNI>(p, mode, in, xv, out);
+    if (MR == 16) return launch_mr<float, 16, UNI>(p, mode, in, xv, out);
+  }
+  pd_set_error("unsupported tridiagonal configuration");
+  return PD_ENOTSUP;
+}
+
+pd_status pd_launch_tridiag(pd_plan p, int mode, const void *in, const double *xv, void *out) {
+  return p->uniform ? dispatch<true>(p, mode, in, xv, out)
+                    : dispatch<false>(p, mode, in, xv, out);
+}
+
+// Elimination factors of the uniform path (float64), 6 complex values per
+// (frequency k, distance 1..MR-1); see tridiag_uniform_kernel.
+void pd_uniform_factors(const pd_plan p, int MR, std::vector<double> &fac) {
+  const int F2 = p->F2;
+  const size_t NF = 6 * (size_t)(MR - 1);
+  fac.assign((size_t)F2 * NF * 2, 0.0);
+  struct C { double re, im; };
+  auto mul = [](C a, C b) { return C{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; };
+  auto sub = [](C a, C b) { return C{a.re - b.re, a.im - b.im}; };
+  auto inv = [](C a) { double d = 1.0 / (a.re * a.re + a.im * a.im); return C{a.re * d, -a.im * d}; };
+  const double *u = p->uni;
+  for (int k = 0; k < F2; ++k) {
+    const double lr = p->lam[2 * k], li = p->lam[2 * k + 1];
+    const C a{lr * u[0] + u[3], li * u[0]}, b{lr * u[1] + u[4], li * u[1]},
+        c{lr * u[2] + u[5], li * u[2]};
+    C rU = inv(b), ua = mul(a, rU), uc = mul(c, rU);
+    C rD = rU, A = ua, Cc = uc;
+    for (int dist = 1; dist < MR; ++dist) {
+      if (dist > 1) {
+        rU = inv(sub(b, mul(c, ua)));
+        C nuc = mul(mul(c, uc), rU);
+        uc = C{-nuc.re, -nuc.im};
+        ua = mul(a, rU);
+        rD = inv(sub(b, mul(a, Cc)));
+        C nA = mul(mul(a, A), rD);
+        A = C{-nA.re, -nA.im};
+        Cc = mul(c, rD);
+      }
+      const C vals[6] = {rU, ua, uc, rD, A, Cc};
+      double *dst = &fac[((size_t)k * NF + (size_t)(dist - 1) * 6) * 2];
+      for (int j = 0; j < 6; ++j) {
+        dst[2 * j] = vals[j].re;
+        dst[2 * j + 1] = vals[j].im;
+      }
+    }
+  }
+}
+
+pd_status pd_launch_reduce_partials(pd_plan p, const double *base, double *out) {
+  const int n = p->n;
+  const int nitems = (p->F2 + p->tri.spb - 1) / p->tri.spb;
+  int G = nitems < p->tri_G ? nitems : p->tri_G;
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((n + 255) / 256), dim3(256), 0, p->stream,
+                     n, G, p->partials, base, out);
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
+pd_status pd_capacitance_apply_impl(pd_plan p, const double *v, double *Jv) {
+  pd_status st = pd_launch_tridiag(p, 2, v, nullptr, nullptr);
+  if (st != PD_OK) return st;
+  return pd_launch_reduce_partials(p, v, Jv);
+}
+
+namespace {
+template <typename R, int MR>
+void set_attr_mr(int v) {
+  const void *fns[6] = {reinterpret_cast<const void *>(&tridiag_kernel<R, MR, 0>),
+                        reinterpret_cast<const void *>(&tridiag_kernel<R, MR, 1>),
+                        reinterpret_cast<const void *>(&tridiag_kernel<R, MR, 2>),
+                        reinterpret_cast<const void *>(&tridiag_uniform_kernel<R, MR, 0>),
+                        reinterpret_cast<const void *>(&tridiag_uniform_kernel<R, MR, 1>),
+                        reinterpret_cast<const void *>(&tridiag_uniform_kernel<R, MR, 2>)};
+  for (const void *f : fns)
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+}
+}  // namespace
+
+void pd_tri_set_attributes(size_t max_lds) {
+  const int v = (int)max_lds;
+  set_attr_mr<double, 4>(v);
+  set_attr_mr<double, 8>(v);
+  set_attr_mr<float, 4>(v);
+  set_attr_mr<float, 8>(v);
+  set_attr_mr<float, 16>(v);
+}
