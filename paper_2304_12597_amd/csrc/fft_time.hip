@@ -139,6 +139,8 @@ fft_forward_kernel(int N, int n, int nbar, int dims, int C, int stride, double t
       if (MODE == 0) {
         val = tau * F[(size_t)t * nbar + i];
         if (t == 0) val += u0[i];
+      } else if (MODE == 2) {
+        val = F[(size_t)t * nbar + i];   // plain real input
       } else {
         double r, g;
         residual_point(t, i, n, nbar, dims, tau, u0, F, U, coef, r, g);
@@ -225,6 +227,91 @@ fft_inverse_kernel(int N, int nbar, int C, int stride, const cpx<R> *__restrict_
   }
 }
 
+// Orthonormal DST-I along x of every grid row (t, y) of a 2D space-time
+// array [ell][n*n] (x fastest): S[m] = sqrt(2/(n+1)) sum_x v[x] sin((x+1)(m+1)
+// pi/(n+1)).  It diagonalises the 1D factor T of K = I (x) T + T (x) I
+// (Section 6.1) and is its own inverse.  Two rows share one complex FFT of
+// length N = 2(n+1) of their odd extensions: with z = ext(a) + i ext(b),
+// Z[k] = 2 S_b[k] - 2i S_a[k].
+// MODE 0: v = h (tau f + u0 at t = 0); 1: v = float64 residual R (norms to
+// red); 2: v = in.  ACC: out += S instead of out = S.
+template <int MODE, int ACC>
+__global__ void __launch_bounds__(1024)
+dst_x_kernel(int n, int ell, int C, int stride, double tau, const double *__restrict__ u0,
+             const double *__restrict__ F, const double *__restrict__ U,
+             const double *__restrict__ in, const double *__restrict__ coef,
+             const cpx<double> *__restrict__ tw, double *__restrict__ out,
+             double *__restrict__ red) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<double> *lds = reinterpret_cast<cpx<double> *>(smem_raw);
+  const int T = blockDim.x, tid = threadIdx.x;
+  const int N = 2 * (n + 1);
+  const int nbar = n * n;
+  const int rows = ell * n;
+  const int r0 = blockIdx.x * 2 * C;
+  double rn2 = 0.0, gn2 = 0.0;
+  for (int c = tid; c < C; c += T) {
+    lds[c * stride] = cpx<double>{0.0, 0.0};
+    lds[c * stride + n + 1] = cpx<double>{0.0, 0.0};
+  }
+  for (int idx = tid; idx < 2 * C * n; idx += T) {
+    const int lr = idx / n, x = idx - lr * n;
+    const int row = r0 + lr;
+    double v = 0.0;
+    if (row < rows) {
+      const int t = row / n, y = row - t * n;
+      const int i = y * n + x;
+      if (MODE == 0) {
+        v = tau * F[(size_t)t * nbar + i];
+        if (t == 0) v += u0[i];
+      } else if (MODE == 1) {
+        double r, g;
+        residual_point(t, i, n, nbar, 2, tau, u0, F, U, coef, r, g);
+        rn2 += r * r;
+        gn2 += g * g;
+        v = r;
+      } else {
+        v = in[(size_t)t * nbar + i];
+      }
+    }
+    double *p1 = reinterpret_cast<double *>(&lds[(lr >> 1) * stride + x + 1]);
+    double *p2 = reinterpret_cast<double *>(&lds[(lr >> 1) * stride + N - 1 - x]);
+    p1[lr & 1] = v;
+    p2[lr & 1] = -v;
+  }
+  __syncthreads();
+  fft_lds<double, false>(lds, N, C, stride, tw);
+  const double scale = 0.5 * sqrt(2.0 / (double)(n + 1));
+  for (int idx = tid; idx < 2 * C * n; idx += T) {
+    const int lr = idx / n, m = idx - lr * n;
+    const int row = r0 + lr;
+    if (row >= rows) continue;
+    const int t = row / n, y = row - t * n;
+    const cpx<double> z = lds[(lr >> 1) * stride + m + 1];
+    const double s = ((lr & 1) ? z.re : -z.im) * scale;
+    const size_t o = (size_t)t * nbar + (size_t)y * n + m;
+    if (ACC) out[o] += s;
+    else out[o] = s;
+  }
+  if (MODE == 1) {
+    __shared__ double sr[32], sg[32];
+    for (int off = 32; off > 0; off >>= 1) {
+      rn2 += __shfl_down(rn2, off, 64);
+      gn2 += __shfl_down(gn2, off, 64);
+    }
+    int wid = tid / 64, lane = tid % 64;
+    __syncthreads();
+    if (lane == 0) { sr[wid] = rn2; sg[wid] = gn2; }
+    __syncthreads();
+    if (tid == 0) {
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < (T + 63) / 64; ++w) { a += sr[w]; b += sg[w]; }
+      red[2 * blockIdx.x] = a;
+      red[2 * blockIdx.x + 1] = b;
+    }
+  }
+}
+
 struct FftLaunch {
   int C, stride, threads, blocks;
   size_t lds;
@@ -270,6 +357,10 @@ pd_status pd_launch_fft_forward(pd_plan p, const double *u0, const double *F,
       hipLaunchKernelGGL((fft_forward_kernel<double, 0>), dim3(L.blocks), dim3(L.threads),
                          L.lds, p->stream, p->ell, p->n, p->nbar, p->dims, L.C, L.stride,
                          p->tau, u0, F, U, p->coef64, p->dal, tw, o, p->red);
+    else if (mode == 2)
+      hipLaunchKernelGGL((fft_forward_kernel<double, 2>), dim3(L.blocks), dim3(L.threads),
+                         L.lds, p->stream, p->ell, p->n, p->nbar, p->dims, L.C, L.stride,
+                         p->tau, u0, F, U, p->coef64, p->dal, tw, o, p->red);
     else
       hipLaunchKernelGGL((fft_forward_kernel<double, 1>), dim3(L.blocks), dim3(L.threads),
                          L.lds, p->stream, p->ell, p->n, p->nbar, p->dims, L.C, L.stride,
@@ -281,11 +372,61 @@ pd_status pd_launch_fft_forward(pd_plan p, const double *u0, const double *F,
       hipLaunchKernelGGL((fft_forward_kernel<float, 0>), dim3(L.blocks), dim3(L.threads),
                          L.lds, p->stream, p->ell, p->n, p->nbar, p->dims, L.C, L.stride,
                          p->tau, u0, F, U, p->coef64, p->dal, tw, o, p->red);
+    else if (mode == 2)
+      hipLaunchKernelGGL((fft_forward_kernel<float, 2>), dim3(L.blocks), dim3(L.threads),
+                         L.lds, p->stream, p->ell, p->n, p->nbar, p->dims, L.C, L.stride,
+                         p->tau, u0, F, U, p->coef64, p->dal, tw, o, p->red);
     else
       hipLaunchKernelGGL((fft_forward_kernel<float, 1>), dim3(L.blocks), dim3(L.threads),
                          L.lds, p->stream, p->ell, p->n, p->nbar, p->dims, L.C, L.stride,
                          p->tau, u0, F, U, p->coef64, p->dal, tw, o, p->red);
   }
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
+namespace {
+struct DstLaunch {
+  int C, stride, threads, blocks;
+  size_t lds;
+};
+DstLaunch dst_config(pd_plan p) {
+  DstLaunch L;
+  const int N = 2 * (p->n + 1);
+  L.C = p->dst_C;
+  L.stride = N + 1;
+  L.lds = (size_t)L.C * L.stride * 16;
+  int need = L.C * N / 8;
+  if (need < 64) need = 64;
+  L.threads = ((need + 63) / 64) * 64;
+  const int rows = p->ell * p->n;
+  L.blocks = (rows + 2 * L.C - 1) / (2 * L.C);
+  return L;
+}
+}  // namespace
+
+int pd_choose_dst_C(int n) {
+  const int N = 2 * (n + 1);
+  int C = 1;
+  while (C < 16 && (size_t)(2 * C) * (N + 1) * 16 <= 65536 && 2 * C * N / 8 <= 1024) C *= 2;
+  return C;
+}
+
+int pd_dst_blocks(pd_plan p) { return dst_config(p).blocks; }
+
+pd_status pd_launch_dst_x(pd_plan p, int mode, const double *u0, const double *F,
+                          const double *U, const double *in, double *out, int accumulate) {
+  DstLaunch L = dst_config(p);
+  auto tw = reinterpret_cast<const cpx<double> *>(p->twd);
+#define PD_DST(M, A)                                                                        \
+  hipLaunchKernelGGL((dst_x_kernel<M, A>), dim3(L.blocks), dim3(L.threads), L.lds, p->stream, \
+                     p->n, p->ell, L.C, L.stride, p->tau, u0, F, U, in, p->coef64, tw, out,   \
+                     p->red)
+  if (mode == 0) PD_DST(0, 0);
+  else if (mode == 1) PD_DST(1, 0);
+  else if (accumulate) PD_DST(2, 1);
+  else PD_DST(2, 0);
+#undef PD_DST
   PD_HIP_CHECK(hipGetLastError());
   return PD_OK;
 }
@@ -328,6 +469,18 @@ void pd_fft_set_attributes(size_t max_lds) {
   (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_forward_kernel<float, 0>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, v);
   (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_forward_kernel<float, 1>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_forward_kernel<double, 2>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_forward_kernel<float, 2>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&dst_x_kernel<0, 0>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&dst_x_kernel<1, 0>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&dst_x_kernel<2, 0>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&dst_x_kernel<2, 1>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, v);
   (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_inverse_kernel<double, 0>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, v);

@@ -62,6 +62,11 @@ struct TriConfig {
   size_t lds;   // dynamic LDS bytes
 };
 
+struct Line2DConfig {
+  int MR = 8, P = 1, S = 1, block = 1, mgroups = 1, nkc = 1, kchunk = 1;
+  size_t lds = 0;
+};
+
 struct pd_plan_s {
   int n = 0, ell = 0, dims = 1, nbar = 0, F2 = 0;
   double tau = 0, alpha = 1, w = 1;   // w = alpha^(1/ell)
@@ -103,8 +108,12 @@ struct pd_plan_s {
   double *host_pin = nullptr;  // pinned host scalars
 
   TriConfig tri;
+  Line2DConfig l2d;
   int fft_C = 1;               // complex columns (point pairs) per FFT block
   int fft_stride = 0;          // LDS column stride (complex elements)
+  int dst_C = 1;               // 2D: row pairs per DST-I block
+  double *twd = nullptr;       // 2D: exp(-2 pi i m / (2(n+1))) twiddles
+  double *wreal = nullptr;     // 2D: [ell][nbar] float64 work array (DST-x domain)
 };
 
 // error reporting
@@ -132,6 +141,21 @@ pd_status pd_launch_fft_inverse(pd_plan p, const void *in, double *U,
 // Y = P^{-1} M (Hhat - w x), 2: J-product partials of P^{-1} M v.
 pd_status pd_launch_tridiag(pd_plan p, int mode, const void *in,
                             const double *xv, void *out);
+// 2D: orthonormal DST-I along x of every row. mode 0: h from (u0, F);
+// 1: float64 residual of (u0, F, U) with norms in red; 2: in.
+pd_status pd_launch_dst_x(pd_plan p, int mode, const double *u0, const double *F,
+                          const double *U, const double *in, double *out, int accumulate);
+int pd_choose_dst_C(int n);
+Line2DConfig pd_choose_line2d(int n, int F2, int prec, int cus);
+void pd_line2d_factors(const pd_plan p, std::vector<double> &fac);
+pd_status pd_launch_line2d(pd_plan p, int mode, const void *in, const double *xv, void *out);
+void pd_line2d_set_attributes(size_t max_lds);
+// whole-pipeline helpers (1D or 2D)
+pd_status pd_forward(pd_plan p, const double *u0, const double *F, const double *U, void *spec,
+                     int residual);
+pd_status pd_inverse(pd_plan p, const void *spec, double *U, int accumulate);
+int pd_forward_norm_blocks(pd_plan p);
+int pd_dst_blocks(pd_plan p);
 // sum partials: out = base + sum_g partials[g]   (base may be NULL)
 pd_status pd_launch_reduce_partials(pd_plan p, const double *base,
                                     double *out);

@@ -64,7 +64,7 @@ pd_status upload(T *dst, const std::vector<T> &src, hipStream_t s) {
 void free_plan(pd_plan p) {
   if (!p) return;
   void *ptrs[] = {p->coef64, p->coef32, p->lam64, p->lam32, p->gB64, p->gJ64, p->tw64,
-                  p->tw32, p->dal, p->fac64, p->fac32, p->spec, p->partials, p->bvec, p->xvec, p->wvec, p->V,
+                  p->tw32, p->dal, p->fac64, p->fac32, p->twd, p->wreal, p->spec, p->partials, p->bvec, p->xvec, p->wvec, p->V,
                   p->gm, p->red};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
@@ -147,8 +147,22 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
       return PD_ENOTSUP;
     }
   } else {
-    pd_set_error("2D plans are not available in this build");
-    return PD_ENOTSUP;
+    // separable 2D path: DST-I along x via a radix-2 FFT of length 2(n+1)
+    if (M) {
+      pd_set_error("2D plans take M = I (pass NULL)");
+      return PD_EINVAL;
+    }
+    if (n > 1023 || !is_pow2(n + 1)) {
+      pd_set_error("2D plans need n + 1 a power of two, n <= 1023");
+      return PD_ENOTSUP;
+    }
+    const double d0 = K->diag[0], o0 = K->upper[0];
+    for (int i = 0; i < n; ++i) {
+      if (K->diag[i] != d0 || (i < n - 1 && (K->upper[i] != o0 || K->lower[i + 1] != o0))) {
+        pd_set_error("2D plans need a symmetric Toeplitz 1D factor T");
+        return PD_ENOTSUP;
+      }
+    }
   }
   for (int i = 0; i < n; ++i) {
     double vals[6] = {K->diag[i], i > 0 ? K->lower[i] : 0.0, i < n - 1 ? K->upper[i] : 0.0,
@@ -196,6 +210,7 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
     g_max_lds = (size_t)lds;
     pd_fft_set_attributes(g_max_lds);
     pd_tri_set_attributes(g_max_lds);
+    pd_line2d_set_attributes(g_max_lds);
     g_attr_device = p->device;
   }
 
@@ -289,13 +304,36 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
     free_plan(p);
     return PD_ENOTSUP;
   }
-  std::vector<double> fac;
-  if (p->uniform) pd_uniform_factors(p, p->tri.MR, fac);
-  std::vector<float> fac32(fac.begin(), fac.end());
-  const int nitems = (F2 + p->tri.spb - 1) / p->tri.spb;
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+  std::vector<double> fac;
+  std::vector<double> twd;
+  if (p->dims == 2) {
+    p->l2d = pd_choose_line2d(n, F2, p->prec, cus);
+    if (p->l2d.lds > g_max_lds) {
+      pd_set_error("2D line tile does not fit in LDS");
+      free_plan(p);
+      return PD_ENOTSUP;
+    }
+    pd_line2d_factors(p, fac);
+    p->dst_C = pd_choose_dst_C(n);
+    const int N = 2 * (n + 1);
+    twd.resize(2 * (size_t)N);
+    for (int m = 0; m < N; ++m) {
+      double c, s;
+      cis(m, N, c, s);
+      twd[2 * m] = c;
+      twd[2 * m + 1] = -s;
+    }
+  } else if (p->uniform) {
+    pd_uniform_factors(p, p->tri.MR, fac);
+  }
+  std::vector<float> fac32(fac.begin(), fac.end());
+  const int nitems = (F2 + p->tri.spb - 1) / p->tri.spb;
   p->tri_G = nitems < cus ? nitems : cus;
+  size_t partial_rows = (size_t)p->tri_G * n;
+  if (p->dims == 2 && (size_t)p->l2d.nkc * p->nbar > partial_rows)
+    partial_rows = (size_t)p->l2d.nkc * p->nbar;
 
   const size_t nbar = p->nbar;
   const size_t cb = (p->prec == PD_FP64) ? 16 : 8;
@@ -306,6 +344,10 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   if (fb > red_n) red_n = fb;
   size_t rb = 2 * (size_t)pd_residual_blocks(p);
   if (rb > red_n) red_n = rb;
+  if (p->dims == 2) {
+    size_t db = 2 * (size_t)pd_dst_blocks(p);
+    if (db > red_n) red_n = db;
+  }
 
   pd_status st = PD_OK;
 #define PD_TRY(x)      \
@@ -327,8 +369,10 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   PD_TRY(dev_alloc(&p->dal, dal.size()));
   PD_TRY(dev_alloc(&p->fac64, fac.size()));
   PD_TRY(dev_alloc(&p->fac32, fac32.size()));
+  PD_TRY(dev_alloc(&p->twd, twd.size()));
+  if (p->dims == 2) PD_TRY(dev_alloc(&p->wreal, (size_t)ell * nbar));
   PD_TRY(dev_alloc(reinterpret_cast<unsigned char **>(&p->spec), p->spec_bytes));
-  PD_TRY(dev_alloc(&p->partials, (size_t)p->tri_G * n));
+  PD_TRY(dev_alloc(&p->partials, partial_rows));
   PD_TRY(dev_alloc(&p->bvec, nbar));
   PD_TRY(dev_alloc(&p->xvec, nbar));
   PD_TRY(dev_alloc(&p->wvec, nbar));
@@ -353,6 +397,7 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   PD_TRY(upload(p->dal, dal, p->stream));
   PD_TRY(upload(p->fac64, fac, p->stream));
   PD_TRY(upload(p->fac32, fac32, p->stream));
+  PD_TRY(upload(p->twd, twd, p->stream));
 #undef PD_TRY
   if (hipStreamSynchronize(p->stream) != hipSuccess) {
     pd_set_error("stream synchronisation failed during plan creation");

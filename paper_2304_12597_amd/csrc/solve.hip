@@ -11,6 +11,29 @@
 
 #include <cmath>
 
+// Forward stage for 1D or 2D plans.  residual = 0: transform h from (u0, F);
+// residual = 1: transform the float64 residual of (u0, F, U), with the
+// partial norms left in p->red.  2D plans first apply the orthonormal DST-I
+// along x (into p->wreal), so their spectra live in the DST-x domain.
+pd_status pd_forward(pd_plan p, const double *u0, const double *F, const double *U, void *spec,
+                     int residual) {
+  if (p->dims == 1) return pd_launch_fft_forward(p, u0, F, U, spec, residual ? 1 : 0);
+  pd_status st = pd_launch_dst_x(p, residual ? 1 : 0, u0, F, U, nullptr, p->wreal, 0);
+  if (st != PD_OK) return st;
+  return pd_launch_fft_forward(p, nullptr, p->wreal, nullptr, spec, 2);
+}
+
+int pd_forward_norm_blocks(pd_plan p) {
+  return p->dims == 1 ? pd_fft_blocks(p) : pd_dst_blocks(p);
+}
+
+pd_status pd_inverse(pd_plan p, const void *spec, double *U, int accumulate) {
+  if (p->dims == 1) return pd_launch_fft_inverse(p, spec, U, accumulate);
+  pd_status st = pd_launch_fft_inverse(p, spec, p->wreal, 0);
+  if (st != PD_OK) return st;
+  return pd_launch_dst_x(p, 2, nullptr, nullptr, nullptr, p->wreal, U, accumulate);
+}
+
 namespace {
 
 // Passes B, GMRES, C, D on the spectrum in p->spec.  has_mass: the spectrum
@@ -28,7 +51,7 @@ pd_status sweep_tail(pd_plan p, double *U, double tol, int has_mass, int accumul
   if (*gm_status != PD_OK && *gm_status != PD_ENOTCONV) return *gm_status;
   st = pd_launch_tridiag(p, 1 | mflag, p->spec, p->xvec, p->spec);
   if (st != PD_OK) return st;
-  st = pd_launch_fft_inverse(p, p->spec, U, accumulate);
+  st = pd_inverse(p, p->spec, U, accumulate);
   if (st != PD_OK) return st;
   if (info) {
     info->gmres_iters += its;
@@ -68,7 +91,7 @@ extern "C" pd_status paradiag_solve(pd_plan p, const double *u0, const double *F
     info->gmres_rel_residual = -1.0;
   }
   pd_status gst = PD_OK;
-  pd_status st = pd_launch_fft_forward(p, u0, F, nullptr, p->spec, 0);
+  pd_status st = pd_forward(p, u0, F, nullptr, p->spec, 0);
   if (st != PD_OK) return st;
   st = sweep_tail(p, U, tol, 0, 0, info, &gst);
   if (st != PD_OK) return st;
@@ -78,10 +101,10 @@ extern "C" pd_status paradiag_solve(pd_plan p, const double *u0, const double *F
     bool converged = false;
     for (int s = 1; s < p->max_sweeps; ++s) {
       // residual of the current iterate, fused with the next forward transform
-      st = pd_launch_fft_forward(p, u0, F, U, p->spec, 1);
+      st = pd_forward(p, u0, F, U, p->spec, 1);
       if (st != PD_OK) return st;
       double rn2, gn2;
-      st = pd_sum_norms(p, pd_fft_blocks(p), &rn2, &gn2);
+      st = pd_sum_norms(p, pd_forward_norm_blocks(p), &rn2, &gn2);
       if (st != PD_OK) return st;
       if (!std::isfinite(rn2) || !std::isfinite(gn2)) {
         pd_set_error("non-finite residual during refinement");
@@ -139,7 +162,7 @@ extern "C" pd_status paradiag_forward_transform(pd_plan p, const double *u0, con
     return PD_EINVAL;
   }
   if (!check_ptrs(u0, F, Hhat)) return PD_EINVAL;
-  return pd_launch_fft_forward(p, u0, F, nullptr, Hhat, 0);
+  return pd_forward(p, u0, F, nullptr, Hhat, 0);
 }
 
 extern "C" pd_status paradiag_shifted_solve(pd_plan p, const void *Hhat, const double *x,
@@ -188,7 +211,7 @@ extern "C" pd_status paradiag_inverse_transform(pd_plan p, const void *Uhat, dou
     pd_set_error("invalid inverse-transform arguments");
     return PD_EINVAL;
   }
-  return pd_launch_fft_inverse(p, Uhat, U, 0);
+  return pd_inverse(p, Uhat, U, 0);
 }
 
 extern "C" pd_status paradiag_residual(pd_plan p, const double *u0, const double *F,

@@ -630,6 +630,7 @@ pd_status dispatch(pd_plan p, int mode, const void *in, const double *xv, void *
 }
 
 pd_status pd_launch_tridiag(pd_plan p, int mode, const void *in, const double *xv, void *out) {
+  if (p->dims == 2) return pd_launch_line2d(p, mode, in, xv, out);
   return p->uniform ? dispatch<true>(p, mode, in, xv, out)
                     : dispatch<false>(p, mode, in, xv, out);
 }
@@ -673,9 +674,10 @@ void pd_uniform_factors(const pd_plan p, int MR, std::vector<double> &fac) {
 }
 
 pd_status pd_launch_reduce_partials(pd_plan p, const double *base, double *out) {
-  const int n = p->n;
+  const int n = p->nbar;
   const int nitems = (p->F2 + p->tri.spb - 1) / p->tri.spb;
   int G = nitems < p->tri_G ? nitems : p->tri_G;
+  if (p->dims == 2) G = p->l2d.nkc;
   hipLaunchKernelGGL(reduce_partials_kernel, dim3((n + 255) / 256), dim3(256), 0, p->stream,
                      n, G, p->partials, base, out);
   PD_HIP_CHECK(hipGetLastError());
