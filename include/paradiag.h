@@ -184,6 +184,59 @@ pd_status paradiag_inverse_transform(pd_plan plan, const void *Uhat,
 pd_status paradiag_residual(pd_plan plan, const double *u0, const double *F,
                             const double *U, double *rel);
 
+/* ---- serving: continuous batching of independent solves ---------------- */
+
+typedef struct pd_server_s *pd_server;
+
+/* One request: the problem (as for paradiag_plan_create) and its device
+ * arrays (as for paradiag_solve).  M may be NULL.  The arrays must stay
+ * alive and untouched until the request completes. */
+typedef struct {
+  int n, ell;
+  double tau;
+  const pd_tridiag *M;
+  const pd_tridiag *K;
+  pd_options opt;              /* opt.stream is ignored (the server owns streams) */
+  const double *u0;
+  const double *F;
+  double *U;
+  double tol;
+} pd_request;
+
+/* Create a server with `workers` host threads, each owning one HIP stream on
+ * the current device, that admits requests while the device memory it
+ * accounts for (plan workspace of running and cached plans plus the requests'
+ * u0, F and U) stays within budget_bytes.  Plans are cached by problem
+ * (n, ell, tau, M, K, options) and keep their constants and Krylov workspace
+ * on the device between requests; idle cached plans are evicted when the
+ * budget needs room.  Work of different workers runs concurrently on the GPU.
+ * Errors: PD_EINVAL, PD_ENOMEM, PD_EHIP. */
+pd_status pd_server_create(pd_server *out, int workers, size_t budget_bytes);
+
+/* Queue a request; returns at once with a ticket (>= 0).  PD_EBUDGET if the
+ * request alone can never fit the budget.  The server copies *req (but not
+ * the arrays). */
+pd_status pd_server_submit(pd_server s, const pd_request *req, long *ticket);
+
+/* Wait for ticket to finish (timeout_ms < 0: forever; 0: poll).  Returns
+ * PD_OK with *done = 1 and the request's status/info when finished, *done = 0
+ * on timeout.  info and status may be NULL. */
+pd_status pd_server_wait(pd_server s, long ticket, int timeout_ms, int *done,
+                         pd_status *status, pd_info *info);
+
+/* Statistics: requests completed, peak accounted bytes, plan-cache hits and
+ * misses, current accounted bytes.  Any pointer may be NULL. */
+pd_status pd_server_stats(pd_server s, long *completed, size_t *peak_bytes,
+                          long *cache_hits, long *cache_misses,
+                          size_t *current_bytes);
+
+/* Finish all queued work, free every plan and stream. */
+pd_status pd_server_destroy(pd_server s);
+
+/* Device bytes a plan for this problem would allocate (workspace and
+ * constants), without creating it. */
+size_t paradiag_plan_bytes(int n, int ell, const pd_options *opt);
+
 #ifdef __cplusplus
 }
 #endif

@@ -196,3 +196,79 @@ def paradiag_residual(plan, u0, F, U) -> float:
     rel = ctypes.c_double(0.0)
     _check(_residual(plan, _ptr(u0), _ptr(F), _ptr(U), ctypes.byref(rel)), "paradiag_residual")
     return rel.value
+
+
+# ---- serving ---------------------------------------------------------------
+
+class pd_request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("ell", ctypes.c_int), ("tau", ctypes.c_double),
+                ("M", ctypes.POINTER(pd_tridiag)), ("K", ctypes.POINTER(pd_tridiag)),
+                ("opt", pd_options), ("u0", _vp), ("F", _vp), ("U", _vp),
+                ("tol", ctypes.c_double)]
+
+
+_server_create = _sig("pd_server_create", ctypes.c_int,
+                      [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_size_t])
+_server_submit = _sig("pd_server_submit", ctypes.c_int,
+                      [_vp, ctypes.POINTER(pd_request), ctypes.POINTER(ctypes.c_long)])
+_server_wait = _sig("pd_server_wait", ctypes.c_int,
+                    [_vp, ctypes.c_long, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(pd_info)])
+_server_stats = _sig("pd_server_stats", ctypes.c_int,
+                     [_vp, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_size_t),
+                      ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long),
+                      ctypes.POINTER(ctypes.c_size_t)])
+_server_destroy = _sig("pd_server_destroy", ctypes.c_int, [_vp])
+_plan_bytes = _sig("paradiag_plan_bytes", ctypes.c_size_t,
+                   [ctypes.c_int, ctypes.c_int, ctypes.POINTER(pd_options)])
+
+
+def paradiag_plan_bytes(n, ell, options=None, **kw):
+    opt = options if options is not None else paradiag_default_options()
+    for k, v in kw.items():
+        setattr(opt, k, v)
+    return int(_plan_bytes(int(n), int(ell), ctypes.byref(opt)))
+
+
+def pd_server_create(workers, budget_bytes):
+    s = _vp()
+    _check(_server_create(ctypes.byref(s), int(workers), int(budget_bytes)), "pd_server_create")
+    return s
+
+
+def pd_server_submit(server, n, ell, tau, M, K, u0, F, U, tol, options=None, **kw):
+    """Queue one solve; returns the ticket.  The tensors must stay alive until
+    pd_server_wait reports the ticket done."""
+    opt = options if options is not None else paradiag_default_options()
+    for k, v in kw.items():
+        setattr(opt, k, v)
+    keep = []
+    req = pd_request(int(n), int(ell), float(tau), _tridiag(M, keep) or
+                     ctypes.POINTER(pd_tridiag)(), _tridiag(K, keep), opt, _ptr(u0), _ptr(F),
+                     _ptr(U), float(tol))
+    t = ctypes.c_long(-1)
+    _check(_server_submit(server, ctypes.byref(req), ctypes.byref(t)), "pd_server_submit")
+    return t.value
+
+
+def pd_server_wait(server, ticket, timeout_ms=-1):
+    """Returns (done, status, info)."""
+    done = ctypes.c_int(0)
+    st = ctypes.c_int(0)
+    info = pd_info()
+    _check(_server_wait(server, int(ticket), int(timeout_ms), ctypes.byref(done),
+                        ctypes.byref(st), ctypes.byref(info)), "pd_server_wait")
+    return bool(done.value), st.value, info
+
+
+def pd_server_stats(server):
+    c = ctypes.c_long(0); pk = ctypes.c_size_t(0); h = ctypes.c_long(0)
+    m = ctypes.c_long(0); cur = ctypes.c_size_t(0)
+    _check(_server_stats(server, ctypes.byref(c), ctypes.byref(pk), ctypes.byref(h),
+                         ctypes.byref(m), ctypes.byref(cur)), "pd_server_stats")
+    return {"completed": c.value, "peak_bytes": pk.value, "cache_hits": h.value,
+            "cache_misses": m.value, "current_bytes": cur.value}
+
+
+def pd_server_destroy(server):
+    return _check(_server_destroy(server), "pd_server_destroy")

@@ -119,17 +119,21 @@ __device__ void fft_lds(cpx<R> *lds, int N, int C, int stride, const cpx<R> *tw)
 }
 
 template <typename R, int MODE>
-__global__ void __launch_bounds__(1024)
-fft_forward_kernel(int N, int n, int nbar, int dims, int C, int stride, double tau,
-                   const double *__restrict__ u0, const double *__restrict__ F,
-                   const double *__restrict__ U, const double *__restrict__ coef,
-                   const double *__restrict__ dal, const cpx<R> *__restrict__ tw,
-                   cpx<R> *__restrict__ out, double *__restrict__ red) {
+__device__ __forceinline__ void fft_forward_body(int tile, int N, int n, int nbar, int dims, int C,
+                                                 int stride, double tau,
+                                                 const double *__restrict__ u0,
+                                                 const double *__restrict__ F,
+                                                 const double *__restrict__ U,
+                                                 const double *__restrict__ coef,
+                                                 const double *__restrict__ dal,
+                                                 const cpx<R> *__restrict__ tw,
+                                                 cpx<R> *__restrict__ out,
+                                                 double *__restrict__ red) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<R> *lds = reinterpret_cast<cpx<R> *>(smem_raw);
   const int T = blockDim.x, tid = threadIdx.x;
   const int S = 2 * C;
-  const int i0 = blockIdx.x * S;
+  const int i0 = tile * S;
   double rn2 = 0.0, gn2 = 0.0;
   for (int idx = tid; idx < N * S; idx += T) {
     int t = idx / S, pnt = idx - t * S;
@@ -185,22 +189,34 @@ fft_forward_kernel(int N, int n, int nbar, int dims, int C, int stride, double t
     if (tid == 0) {
       double a = 0.0, b = 0.0;
       for (int w = 0; w < (T + 63) / 64; ++w) { a += sr[w]; b += sg[w]; }
-      red[2 * blockIdx.x] = a;
-      red[2 * blockIdx.x + 1] = b;
+      red[2 * tile] = a;
+      red[2 * tile + 1] = b;
     }
   }
 }
 
-template <typename R, int ACC>
+template <typename R, int MODE>
 __global__ void __launch_bounds__(1024)
-fft_inverse_kernel(int N, int nbar, int C, int stride, const cpx<R> *__restrict__ in,
-                   const double *__restrict__ dalinv, const cpx<R> *__restrict__ tw,
-                   double *__restrict__ U) {
+fft_forward_kernel(int N, int n, int nbar, int dims, int C, int stride, double tau,
+                   const double *__restrict__ u0, const double *__restrict__ F,
+                   const double *__restrict__ U, const double *__restrict__ coef,
+                   const double *__restrict__ dal, const cpx<R> *__restrict__ tw,
+                   cpx<R> *__restrict__ out, double *__restrict__ red) {
+  fft_forward_body<R, MODE>(blockIdx.x, N, n, nbar, dims, C, stride, tau, u0, F, U, coef, dal,
+                            tw, out, red);
+}
+
+template <typename R, int ACC>
+__device__ __forceinline__ void fft_inverse_body(int tile, int N, int nbar, int C, int stride,
+                                                 const cpx<R> *__restrict__ in,
+                                                 const double *__restrict__ dalinv,
+                                                 const cpx<R> *__restrict__ tw,
+                                                 double *__restrict__ U) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<R> *lds = reinterpret_cast<cpx<R> *>(smem_raw);
   const int T = blockDim.x, tid = threadIdx.x;
   const int S = 2 * C;
-  const int i0 = blockIdx.x * S;
+  const int i0 = tile * S;
   const int half = N / 2;
   for (int idx = tid; idx < (half + 1) * C; idx += T) {
     int k = idx / C, c = idx - k * C;
@@ -225,6 +241,14 @@ fft_inverse_kernel(int N, int nbar, int C, int stride, const cpx<R> *__restrict_
     if (ACC) U[o] += val;
     else U[o] = val;
   }
+}
+
+template <typename R, int ACC>
+__global__ void __launch_bounds__(1024)
+fft_inverse_kernel(int N, int nbar, int C, int stride, const cpx<R> *__restrict__ in,
+                   const double *__restrict__ dalinv, const cpx<R> *__restrict__ tw,
+                   double *__restrict__ U) {
+  fft_inverse_body<R, ACC>(blockIdx.x, N, nbar, C, stride, in, dalinv, tw, U);
 }
 
 // Orthonormal DST-I along x of every grid row (t, y) of a 2D space-time
@@ -490,4 +514,61 @@ void pd_fft_set_attributes(size_t max_lds) {
                             hipFuncAttributeMaxDynamicSharedMemorySize, v);
   (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_inverse_kernel<float, 1>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, v);
+}
+
+namespace {
+template <typename R, int MODE>
+__global__ void __launch_bounds__(1024)
+fft_forward_batch_kernel(const FftJob *__restrict__ jobs, const int2 *__restrict__ map) {
+  const int2 m = map[blockIdx.x];
+  const FftJob &j = jobs[m.x];
+  fft_forward_body<R, MODE>(m.y, j.N, j.n, j.nbar, j.dims, j.C, j.stride, j.tau, j.u0, j.F, j.U,
+                            j.coef, j.dal, reinterpret_cast<const cpx<R> *>(j.tw),
+                            reinterpret_cast<cpx<R> *>(j.spec), j.red);
+}
+template <typename R>
+__global__ void __launch_bounds__(1024)
+fft_inverse_batch_kernel(const FftJob *__restrict__ jobs, const int2 *__restrict__ map) {
+  const int2 m = map[blockIdx.x];
+  const FftJob &j = jobs[m.x];
+  fft_inverse_body<R, 0>(m.y, j.N, j.nbar, j.C, j.stride,
+                         reinterpret_cast<const cpx<R> *>(j.spec), j.dal + j.N,
+                         reinterpret_cast<const cpx<R> *>(j.tw), j.out);
+}
+}  // namespace
+
+pd_status pd_launch_fft_forward_batch(int prec, const FftJob *jobs, const int2 *map, int nblocks,
+                                      int threads, size_t lds, hipStream_t s) {
+  if (nblocks == 0) return PD_OK;
+  if (prec == PD_FP64)
+    hipLaunchKernelGGL((fft_forward_batch_kernel<double, 0>), dim3(nblocks), dim3(threads), lds,
+                       s, jobs, map);
+  else
+    hipLaunchKernelGGL((fft_forward_batch_kernel<float, 0>), dim3(nblocks), dim3(threads), lds,
+                       s, jobs, map);
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
+pd_status pd_launch_fft_inverse_batch(int prec, const FftJob *jobs, const int2 *map, int nblocks,
+                                      int threads, size_t lds, hipStream_t s) {
+  if (nblocks == 0) return PD_OK;
+  if (prec == PD_FP64)
+    hipLaunchKernelGGL((fft_inverse_batch_kernel<double>), dim3(nblocks), dim3(threads), lds, s,
+                       jobs, map);
+  else
+    hipLaunchKernelGGL((fft_inverse_batch_kernel<float>), dim3(nblocks), dim3(threads), lds, s,
+                       jobs, map);
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
+void pd_fft_batch_set_attributes(size_t max_lds) {
+  const int v = (int)max_lds;
+  const void *fns[] = {reinterpret_cast<const void *>(&fft_forward_batch_kernel<double, 0>),
+                       reinterpret_cast<const void *>(&fft_forward_batch_kernel<float, 0>),
+                       reinterpret_cast<const void *>(&fft_inverse_batch_kernel<double>),
+                       reinterpret_cast<const void *>(&fft_inverse_batch_kernel<float>)};
+  for (const void *fn : fns)
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, v);
 }

@@ -252,3 +252,225 @@ pd_status pd_gmres(pd_plan p, const double *b, double *x, double rtol, int *iter
   if (relres) *relres = res / beta;
   return (res <= rtol * beta || st_host[1] == 0.0) ? PD_OK : PD_ENOTCONV;
 }
+
+// ---------------------------------------------------------------------------
+// Batched GMRES: the same steps for many independent problems in lockstep
+// (iteration j is shared); problems whose flag in `active` is 0 are skipped.
+// ---------------------------------------------------------------------------
+namespace {
+
+// which = 0: dots of w with V_0..V_{nv-1} and w.w into red1;
+// which = 1: ||b||^2 into red1 (nv = 0)
+__global__ void __launch_bounds__(VB)
+batch_dots_kernel(const VecJob *__restrict__ jobs, const int2 *__restrict__ vmap, int nv,
+                  int which, const int *__restrict__ active) {
+  __shared__ double sh[VB / 64];
+  const int2 m = vmap[blockIdx.x];
+  if (active && !active[m.x]) return;
+  const VecJob &J = jobs[m.x];
+  const double *w = which ? J.b : J.w;
+  const int n = J.n;
+  const int stride = J.B * blockDim.x;
+  for (int i = 0; i <= nv; ++i) {
+    double s = 0.0;
+    for (int r = m.y * blockDim.x + threadIdx.x; r < n; r += stride) {
+      const double wr = w[r];
+      s += (i < nv ? J.V[(size_t)i * n + r] : wr) * wr;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) J.red1[m.y * (nv + 1) + i] = s;
+  }
+}
+
+// pass 1: h from red1, w -= V h, dots into red2;  pass 2: h from red2, w -= V h
+__global__ void __launch_bounds__(VB)
+batch_update_kernel(const VecJob *__restrict__ jobs, const int2 *__restrict__ vmap, int nv, int j,
+                    int MX, int pass, const int *__restrict__ active) {
+  __shared__ double h[128];
+  __shared__ double sh[VB / 64];
+  const int2 m = vmap[blockIdx.x];
+  if (active && !active[m.x]) return;
+  const VecJob &J = jobs[m.x];
+  GmLayout L{MX};
+  const double *red_in = (pass == 1) ? J.red1 : J.red2;
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < J.B; ++b) s += red_in[b * (nv + 1) + i];
+    h[i] = s;
+  }
+  __syncthreads();
+  if (m.y == 0)
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) J.gm[L.H(i, j)] += h[i];
+  const int n = J.n;
+  const int stride = J.B * blockDim.x;
+  for (int r = m.y * blockDim.x + threadIdx.x; r < n; r += stride) {
+    double wr = J.w[r];
+    for (int i = 0; i < nv; ++i) wr -= h[i] * J.V[(size_t)i * n + r];
+    J.w[r] = wr;
+  }
+  if (pass != 1) return;
+  __syncthreads();
+  for (int i = 0; i <= nv; ++i) {
+    double s = 0.0;
+    for (int r = m.y * blockDim.x + threadIdx.x; r < n; r += stride) {
+      const double wr = J.w[r];
+      s += (i < nv ? J.V[(size_t)i * n + r] : wr) * wr;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) J.red2[m.y * (nv + 1) + i] = s;
+  }
+}
+
+// one block per problem: ||w|| from red1 (nv = 0 layout), Givens update;
+// status[4*p + 0..3] = residual, h_{j+1,j}, iterations, beta
+__global__ void batch_givens_kernel(const VecJob *__restrict__ jobs, int j, int MX,
+                                    double *__restrict__ status, const int *__restrict__ active) {
+  const int p = blockIdx.x;
+  if (threadIdx.x != 0 || (active && !active[p])) return;
+  const VecJob &J = jobs[p];
+  double *gm = J.gm;
+  GmLayout L{MX};
+  double nn = 0.0;
+  for (int b = 0; b < J.B; ++b) nn += J.red1[b];
+  const double hn = sqrt(nn);
+  gm[L.H(j + 1, j)] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double c = gm[L.cs(i)], s = gm[L.sn(i)];
+    const double a = gm[L.H(i, j)], b = gm[L.H(i + 1, j)];
+    gm[L.H(i, j)] = c * a + s * b;
+    gm[L.H(i + 1, j)] = -s * a + c * b;
+  }
+  const double a = gm[L.H(j, j)], b = gm[L.H(j + 1, j)];
+  const double r = hypot(a, b);
+  const double c = (r == 0.0) ? 1.0 : a / r, s = (r == 0.0) ? 0.0 : b / r;
+  gm[L.cs(j)] = c;
+  gm[L.sn(j)] = s;
+  gm[L.H(j, j)] = r;
+  gm[L.H(j + 1, j)] = 0.0;
+  const double gj = gm[L.g(j)];
+  gm[L.g(j)] = c * gj;
+  gm[L.g(j + 1)] = -s * gj;
+  gm[L.st(0)] = fabs(-s * gj);
+  gm[L.st(1)] = hn;
+  gm[L.st(2)] = (double)(j + 1);
+  status[4 * p + 0] = fabs(-s * gj);
+  status[4 * p + 1] = hn;
+  status[4 * p + 2] = (double)(j + 1);
+  status[4 * p + 3] = gm[L.st(3)];
+}
+
+// one block per problem: reset the small state, beta = ||b|| from red1
+__global__ void batch_init_kernel(const VecJob *__restrict__ jobs, int MX,
+                                  double *__restrict__ status) {
+  const VecJob &J = jobs[blockIdx.x];
+  GmLayout L{MX};
+  for (int i = threadIdx.x; i < L.size(); i += blockDim.x) J.gm[i] = 0.0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double nn = 0.0;
+    for (int b = 0; b < J.B; ++b) nn += J.red1[b];
+    const double beta = sqrt(nn);
+    J.gm[L.g(0)] = beta;
+    J.gm[L.st(0)] = beta;
+    J.gm[L.st(1)] = beta;
+    J.gm[L.st(3)] = beta;
+    status[4 * blockIdx.x + 0] = beta;
+    status[4 * blockIdx.x + 1] = beta;
+    status[4 * blockIdx.x + 2] = 0.0;
+    status[4 * blockIdx.x + 3] = beta;
+  }
+}
+
+// V_{j+1} = w / h_{j+1,j} (from_b: V_0 = b / beta)
+__global__ void batch_scale_kernel(const VecJob *__restrict__ jobs, const int2 *__restrict__ vmap,
+                                   int j, int MX, int from_b, const int *__restrict__ active) {
+  const int2 m = vmap[blockIdx.x];
+  if (active && !active[m.x]) return;
+  const VecJob &J = jobs[m.x];
+  GmLayout L{MX};
+  const double hn = J.gm[L.st(1)];
+  const double inv = (hn > 0.0) ? 1.0 / hn : 0.0;
+  const double *src = from_b ? J.b : J.w;
+  double *dst = J.V + (size_t)(from_b ? 0 : j + 1) * J.n;
+  for (int r = m.y * blockDim.x + threadIdx.x; r < J.n; r += J.B * blockDim.x)
+    dst[r] = src[r] * inv;
+}
+
+// per problem: back substitution (block 0 of the problem does it first in a
+// separate launch), then x = V y
+__global__ void batch_backsolve_kernel(const VecJob *__restrict__ jobs, int MX,
+                                       const int *__restrict__ mlist) {
+  const VecJob &J = jobs[blockIdx.x];
+  if (threadIdx.x != 0) return;
+  GmLayout L{MX};
+  const int m = mlist[blockIdx.x];
+  double *gm = J.gm;
+  for (int i = m - 1; i >= 0; --i) {
+    double s = gm[L.g(i)];
+    for (int k = i + 1; k < m; ++k) s -= gm[L.H(i, k)] * gm[L.y(k)];
+    const double d = gm[L.H(i, i)];
+    gm[L.y(i)] = (d != 0.0) ? s / d : 0.0;
+  }
+}
+
+__global__ void batch_combine_kernel(const VecJob *__restrict__ jobs, const int2 *__restrict__ vmap,
+                                     int MX, const int *__restrict__ mlist) {
+  const int2 mp = vmap[blockIdx.x];
+  const VecJob &J = jobs[mp.x];
+  GmLayout L{MX};
+  const int m = mlist[mp.x];
+  for (int r = mp.y * blockDim.x + threadIdx.x; r < J.n; r += J.B * blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) s += J.gm[L.y(i)] * J.V[(size_t)i * J.n + r];
+    J.x[r] = s;
+  }
+}
+
+}  // namespace
+
+pd_status pd_gmres_batch_dots(const VecJob *jobs, const int2 *vmap, int nvb, int nv, int which,
+                              const int *active, hipStream_t s) {
+  hipLaunchKernelGGL(batch_dots_kernel, dim3(nvb), dim3(VB), 0, s, jobs, vmap, nv, which, active);
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
+pd_status pd_gmres_batch_update(const VecJob *jobs, const int2 *vmap, int nvb, int nv, int j,
+                                int MX, int pass, const int *active, hipStream_t s) {
+  hipLaunchKernelGGL(batch_update_kernel, dim3(nvb), dim3(VB), 0, s, jobs, vmap, nv, j, MX, pass,
+                     active);
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
+pd_status pd_gmres_batch_givens(const VecJob *jobs, int count, int j, int MX, double *status,
+                                const int *active, hipStream_t s) {
+  hipLaunchKernelGGL(batch_givens_kernel, dim3(count), dim3(64), 0, s, jobs, j, MX, status,
+                     active);
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
+pd_status pd_gmres_batch_init(const VecJob *jobs, int count, int MX, double *status,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(batch_init_kernel, dim3(count), dim3(256), 0, s, jobs, MX, status);
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
+pd_status pd_gmres_batch_scale(const VecJob *jobs, const int2 *vmap, int nvb, int j, int MX,
+                               int from_b, const int *active, hipStream_t s) {
+  hipLaunchKernelGGL(batch_scale_kernel, dim3(nvb), dim3(VB), 0, s, jobs, vmap, j, MX, from_b,
+                     active);
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
+pd_status pd_gmres_batch_finish(const VecJob *jobs, const int2 *vmap, int nvb, int count, int MX,
+                                const int *m_per_problem, hipStream_t s) {
+  hipLaunchKernelGGL(batch_backsolve_kernel, dim3(count), dim3(64), 0, s, jobs, MX, m_per_problem);
+  hipLaunchKernelGGL(batch_combine_kernel, dim3(nvb), dim3(VB), 0, s, jobs, vmap, MX,
+                     m_per_problem);
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}

@@ -52,6 +52,39 @@ __device__ __forceinline__ cpx<R> cmul_mi(cpx<R> a) {
 }
 
 // ---------------------------------------------------------------------------
+// batched launches: one entry per problem, a block map (problem, local block)
+// ---------------------------------------------------------------------------
+struct FftJob {
+  int N, n, nbar, dims, C, stride;
+  double tau;
+  const double *u0, *F, *U, *coef, *dal;
+  const void *tw;
+  void *spec;
+  double *out;
+  double *red;
+};
+
+struct TriJob {
+  int n, F2, P, spb, nitems, nblk, has_mass;
+  double ml, md, mu, kl, kd, ku;   // constant diagonals of M and tau K
+  const double *coef64;
+  const void *lam, *fac;
+  const double *gw;
+  const void *in;
+  const double *vin, *xv;
+  double wscale;
+  void *out;
+  double *partials;
+};
+
+struct VecJob {     // one problem's vectors for the batched GMRES kernels
+  int n, B;         // vector length, vector-kernel blocks
+  int G;            // partial rows of the shifted-solve reductions
+  double *V, *w, *x, *red1, *red2, *gm, *partials, *bout;
+  const double *b;
+};
+
+// ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
 struct TriConfig {
@@ -98,6 +131,7 @@ struct pd_plan_s {
   // workspace
   void *spec = nullptr;        // [F2][nbar] complex (c128 or c64)
   size_t spec_bytes = 0;
+  size_t bytes = 0;            // device bytes this plan allocated
   double *partials = nullptr;  // [tri_G][nbar]
   int tri_G = 0;
   double *bvec = nullptr, *xvec = nullptr, *wvec = nullptr;
@@ -175,3 +209,35 @@ void pd_uniform_factors(const pd_plan p, int MR, std::vector<double> &fac);
 void pd_fft_set_attributes(size_t max_lds);
 void pd_tri_set_attributes(size_t max_lds);
 
+
+// batched stage launchers (all problems of one precision; blocks map to
+// (problem, local block) pairs in `map`, int2 per block)
+pd_status pd_launch_fft_forward_batch(int prec, const FftJob *jobs, const int2 *map, int nblocks,
+                                      int threads, size_t lds, hipStream_t s);
+pd_status pd_launch_fft_inverse_batch(int prec, const FftJob *jobs, const int2 *map, int nblocks,
+                                      int threads, size_t lds, hipStream_t s);
+pd_status pd_launch_tridiag_batch(int prec, int MR, int mode, const TriJob *jobs, const int2 *map,
+                                  int nblocks, size_t lds, const int *active, int jv,
+                                  hipStream_t s);
+pd_status pd_launch_reduce_batch(const VecJob *jobs, const int2 *map, int nblocks, int base_j,
+                                 const int *active, hipStream_t s);
+void pd_fft_batch_set_attributes(size_t max_lds);
+void pd_tri_batch_set_attributes(size_t max_lds);
+// batched GMRES vector kernels (gmres.hip); vmap: blocks of every problem's
+// vectors, one int2 (problem, block) each; pmap: one block per problem
+pd_status pd_gmres_batch_dots(const VecJob *jobs, const int2 *vmap, int nvb, int nv, int which,
+                              const int *active, hipStream_t s);
+pd_status pd_gmres_batch_update(const VecJob *jobs, const int2 *vmap, int nvb, int nv, int j,
+                                int MX, int pass, const int *active, hipStream_t s);
+pd_status pd_gmres_batch_givens(const VecJob *jobs, int count, int j, int MX, double *status,
+                                const int *active, hipStream_t s);
+pd_status pd_gmres_batch_init(const VecJob *jobs, int count, int MX, double *status,
+                              hipStream_t s);
+pd_status pd_gmres_batch_scale(const VecJob *jobs, const int2 *vmap, int nvb, int j, int MX,
+                               int from_b, const int *active, hipStream_t s);
+pd_status pd_gmres_batch_finish(const VecJob *jobs, const int2 *vmap, int nvb, int count, int MX,
+                                const int *m_per_problem, hipStream_t s);
+bool pd_batchable(const pd_plan *plans, int count);
+pd_status pd_solve_batch_impl(const pd_plan *plans, int count, const double *const *u0,
+                              const double *const *F, double *const *U, double tol,
+                              pd_info *infos);

@@ -8,6 +8,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 namespace {
@@ -74,6 +75,78 @@ void free_plan(pd_plan p) {
 
 size_t g_max_lds = 0;
 int g_attr_device = -1;
+std::mutex g_attr_mu;
+
+// Launch configurations and device allocation sizes (in elements of their
+// type) of a plan; shared by plan creation and paradiag_plan_bytes.
+struct Layout {
+  size_t coef = 0, lam = 0, tw = 0, dal = 0, fac = 0, twd = 0, wreal = 0;
+  size_t spec_bytes = 0, partials = 0, vec = 0, V = 0, gm = 0, red = 0;
+  size_t total_bytes() const {
+    return coef * 12 + lam * 12 + 2 * lam * 8 + tw * 12 + dal * 8 + fac * 12 + twd * 8 +
+           wreal * 8 + spec_bytes + partials * 8 + 3 * vec * 8 + V * 8 + gm * 8 + red * 8;
+  }
+};
+
+// Fills p->fft_C, fft_stride, tri, tri_G, l2d, dst_C; returns PD_OK or
+// PD_ENOTSUP when a tile does not fit in LDS.
+pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
+  const int n = p->n, ell = p->ell, F2 = p->F2;
+  const size_t cb = (p->prec == PD_FP64) ? 16 : 8;
+  p->fft_C = pd_choose_fft_C(ell, p->nbar, p->prec, max_lds);
+  p->fft_stride = ell + 1;   // one pad element against LDS bank conflicts
+  if ((size_t)p->fft_C * p->fft_stride * cb > max_lds) p->fft_stride = ell;
+  if ((size_t)p->fft_C * p->fft_stride * cb > max_lds) {
+    pd_set_error("time transform tile does not fit in LDS");
+    return PD_ENOTSUP;
+  }
+  p->tri = pd_choose_tri(n, F2, p->prec);
+  if (p->dims == 1 && p->tri.lds > max_lds) {
+    pd_set_error("shifted-solve tile does not fit in LDS");
+    return PD_ENOTSUP;
+  }
+  const int nitems = (F2 + p->tri.spb - 1) / p->tri.spb;
+  p->tri_G = nitems < cus ? nitems : cus;
+  L.partials = (size_t)p->tri_G * n;
+  if (p->dims == 2) {
+    p->l2d = pd_choose_line2d(n, F2, p->prec, cus);
+    if (p->l2d.lds > max_lds) {
+      pd_set_error("2D line tile does not fit in LDS");
+      return PD_ENOTSUP;
+    }
+    p->dst_C = pd_choose_dst_C(n);
+    if ((size_t)2 * p->dst_C * (2 * (n + 1) + 1) * 16 > max_lds) {
+      pd_set_error("DST tile does not fit in LDS");
+      return PD_ENOTSUP;
+    }
+    L.fac = (size_t)F2 * n * 6 * (p->l2d.MR - 1) * 2;
+    L.twd = 4 * (size_t)(n + 1);
+    L.wreal = (size_t)ell * p->nbar;
+    if ((size_t)p->l2d.nkc * p->nbar > L.partials) L.partials = (size_t)p->l2d.nkc * p->nbar;
+  } else if (p->uniform) {
+    L.fac = (size_t)F2 * 6 * (p->tri.MR - 1) * 2;
+  }
+  L.coef = 6 * (size_t)n;
+  L.lam = 2 * (size_t)F2;
+  L.tw = 2 * (size_t)ell;
+  L.dal = 2 * (size_t)ell;
+  L.spec_bytes = (size_t)F2 * p->nbar * cb;
+  L.vec = p->nbar;
+  L.V = (size_t)(p->maxit + 1) * p->nbar;
+  L.gm = pd_gmres_state_doubles(p->maxit);
+  const int B = pd_vec_blocks(p->nbar);
+  size_t red_n = 2 * (size_t)B * (p->maxit + 2);
+  size_t fb = 2 * (size_t)pd_fft_blocks(p);
+  if (fb > red_n) red_n = fb;
+  size_t rb = 2 * (size_t)pd_residual_blocks(p);
+  if (rb > red_n) red_n = rb;
+  if (p->dims == 2) {
+    size_t db = 2 * (size_t)pd_dst_blocks(p);
+    if (db > red_n) red_n = db;
+  }
+  L.red = red_n;
+  return PD_OK;
+}
 
 }  // namespace
 
@@ -199,6 +272,7 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
     free_plan(p);
     return PD_EHIP;
   }
+  std::unique_lock<std::mutex> attr_lock(g_attr_mu);
   if (g_attr_device != p->device) {
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) !=
@@ -211,8 +285,12 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
     pd_fft_set_attributes(g_max_lds);
     pd_tri_set_attributes(g_max_lds);
     pd_line2d_set_attributes(g_max_lds);
+    pd_fft_batch_set_attributes(g_max_lds);
+    pd_tri_batch_set_attributes(g_max_lds);
     g_attr_device = p->device;
   }
+  const size_t max_lds = g_max_lds;
+  attr_lock.unlock();
 
   // coefficients: ML MD MU (M or I), tau*K
   std::vector<double> coef(6 * (size_t)n, 0.0);
@@ -286,37 +364,21 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
     dal[ell + t] = (opt.alpha == 1.0) ? 1.0 : std::pow(opt.alpha, -(double)t / ell);
   }
 
-  // launch configurations
-  p->fft_C = pd_choose_fft_C(ell, p->nbar, p->prec, g_max_lds);
-  {
-    const size_t cb = (p->prec == PD_FP64) ? 16 : 8;
-    p->fft_stride = ell + 1;   // one pad element against LDS bank conflicts
-    if ((size_t)p->fft_C * p->fft_stride * cb > g_max_lds) p->fft_stride = ell;
-    if ((size_t)p->fft_C * p->fft_stride * cb > g_max_lds) {
-      pd_set_error("time transform tile does not fit in LDS");
-      free_plan(p);
-      return PD_ENOTSUP;
-    }
-  }
-  p->tri = pd_choose_tri(n, F2, p->prec);
-  if (p->tri.lds > g_max_lds) {
-    pd_set_error("shifted-solve tile does not fit in LDS");
-    free_plan(p);
-    return PD_ENOTSUP;
-  }
+  // launch configurations and sizes
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+  Layout L;
+  {
+    pd_status lst = compute_layout(p, cus, max_lds, L);
+    if (lst != PD_OK) {
+      free_plan(p);
+      return lst;
+    }
+  }
   std::vector<double> fac;
   std::vector<double> twd;
   if (p->dims == 2) {
-    p->l2d = pd_choose_line2d(n, F2, p->prec, cus);
-    if (p->l2d.lds > g_max_lds) {
-      pd_set_error("2D line tile does not fit in LDS");
-      free_plan(p);
-      return PD_ENOTSUP;
-    }
     pd_line2d_factors(p, fac);
-    p->dst_C = pd_choose_dst_C(n);
     const int N = 2 * (n + 1);
     twd.resize(2 * (size_t)N);
     for (int m = 0; m < N; ++m) {
@@ -329,26 +391,9 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
     pd_uniform_factors(p, p->tri.MR, fac);
   }
   std::vector<float> fac32(fac.begin(), fac.end());
-  const int nitems = (F2 + p->tri.spb - 1) / p->tri.spb;
-  p->tri_G = nitems < cus ? nitems : cus;
-  size_t partial_rows = (size_t)p->tri_G * n;
-  if (p->dims == 2 && (size_t)p->l2d.nkc * p->nbar > partial_rows)
-    partial_rows = (size_t)p->l2d.nkc * p->nbar;
-
   const size_t nbar = p->nbar;
-  const size_t cb = (p->prec == PD_FP64) ? 16 : 8;
-  p->spec_bytes = (size_t)F2 * nbar * cb;
-  const int B = pd_vec_blocks(p->nbar);
-  size_t red_n = 2 * (size_t)B * (p->maxit + 2);
-  size_t fb = 2 * (size_t)pd_fft_blocks(p);
-  if (fb > red_n) red_n = fb;
-  size_t rb = 2 * (size_t)pd_residual_blocks(p);
-  if (rb > red_n) red_n = rb;
-  if (p->dims == 2) {
-    size_t db = 2 * (size_t)pd_dst_blocks(p);
-    if (db > red_n) red_n = db;
-  }
-
+  p->spec_bytes = L.spec_bytes;
+  p->bytes = L.total_bytes();
   pd_status st = PD_OK;
 #define PD_TRY(x)      \
   do {                 \
@@ -372,13 +417,13 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   PD_TRY(dev_alloc(&p->twd, twd.size()));
   if (p->dims == 2) PD_TRY(dev_alloc(&p->wreal, (size_t)ell * nbar));
   PD_TRY(dev_alloc(reinterpret_cast<unsigned char **>(&p->spec), p->spec_bytes));
-  PD_TRY(dev_alloc(&p->partials, partial_rows));
+  PD_TRY(dev_alloc(&p->partials, L.partials));
   PD_TRY(dev_alloc(&p->bvec, nbar));
   PD_TRY(dev_alloc(&p->xvec, nbar));
   PD_TRY(dev_alloc(&p->wvec, nbar));
   PD_TRY(dev_alloc(&p->V, (size_t)(p->maxit + 1) * nbar));
   PD_TRY(dev_alloc(&p->gm, pd_gmres_state_doubles(p->maxit)));
-  PD_TRY(dev_alloc(&p->red, red_n));
+  PD_TRY(dev_alloc(&p->red, L.red));
   if (hipHostMalloc(reinterpret_cast<void **>(&p->host_pin), 8 * sizeof(double),
                     hipHostMallocDefault) != hipSuccess) {
     p->host_pin = nullptr;
@@ -419,3 +464,28 @@ extern "C" pd_status paradiag_plan_destroy(pd_plan p) {
 }
 
 extern "C" size_t paradiag_spectrum_bytes(pd_plan p) { return p ? p->spec_bytes : 0; }
+
+extern "C" size_t paradiag_plan_bytes(int n, int ell, const pd_options *opt_in) {
+  pd_options opt;
+  paradiag_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  if (n < 2 || ell < 2 || !is_pow2(ell) || ell > 4096 || opt.maxit < 1 || opt.maxit > 64 ||
+      (opt.dims != 1 && opt.dims != 2))
+    return 0;
+  pd_plan_s tmp;
+  tmp.n = n;
+  tmp.ell = ell;
+  tmp.dims = opt.dims;
+  tmp.nbar = (opt.dims == 2) ? n * n : n;
+  tmp.F2 = ell / 2 + 1;
+  tmp.prec = opt.precision;
+  tmp.maxit = opt.maxit;
+  tmp.uniform = true;
+  int dev = 0, cus = 256, lds = 65536;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  Layout L;
+  if (compute_layout(&tmp, cus, (size_t)lds, L) != PD_OK) return 0;
+  return L.total_bytes();
+}

@@ -146,6 +146,18 @@ extern "C" pd_status paradiag_solve_batch(const pd_plan *plans, int count, const
     pd_set_error("invalid batch arguments");
     return PD_EINVAL;
   }
+  if (count == 0) return PD_OK;
+  for (int i = 0; i < count; ++i)
+    if (!plans[i] || !u0[i] || !F[i] || !U[i]) {
+      pd_set_error("invalid batch arguments");
+      return PD_EINVAL;
+    }
+  if (!(tol > 0.0) || !std::isfinite(tol)) {
+    pd_set_error("tol must be positive and finite");
+    return PD_EINVAL;
+  }
+  if (pd_batchable(plans, count)) return pd_solve_batch_impl(plans, count, u0, F, U, tol, infos);
+  // other groups (2D, mixed precision, non-uniform grids): one after another
   pd_status worst = PD_OK;
   for (int i = 0; i < count; ++i) {
     pd_status st = paradiag_solve(plans[i], u0[i], F[i], U[i], tol, infos ? &infos[i] : nullptr);

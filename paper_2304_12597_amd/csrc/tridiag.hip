@@ -21,7 +21,7 @@
 // are coalesced.  Modes: 0 accumulates b = sum_k gamma_k y_k (full spectrum,
 // the conjugate half implied) into per-block float64 partial sums; 1 writes
 // y_k; 2 accumulates the capacitance product sum_k w gamma_k P_k^{-1} M v.
-#include "pd_internal.h"
+#include "pd_partition.h"
 
 namespace {
 
@@ -54,10 +54,6 @@ __device__ __forceinline__ void prow(const Coef<R> &cf, int i, int n, R lr, R li
   }
 }
 
-template <typename R>
-struct Row3 {
-  cpx<R> a, c, d;   // normalised row:  a x_lo + x + c x_hi = d
-};
 
 template <typename R, int MR, int MODE>
 __global__ void __launch_bounds__(1024)
@@ -303,13 +299,13 @@ tridiag_kernel(int n, int F2, int P, int spb, int nitems, Coef<R> cf,
 // harmless because those ghost unknowns are identically zero in the reduced
 // system.
 template <typename R, int MR, int MODE>
-__global__ void __launch_bounds__(1024)
-tridiag_uniform_kernel(int n, int F2, int P, int spb, int nitems, Coef<R> cf,
-                       const double *__restrict__ coef64, const R *__restrict__ lam,
-                       const cpx<R> *__restrict__ fac, const double *__restrict__ gw,
-                       const cpx<R> *__restrict__ in, const double *__restrict__ vin,
-                       const double *__restrict__ xv, double wscale, int rhs_has_mass,
-                       cpx<R> *__restrict__ out, double *__restrict__ partials) {
+__device__ __forceinline__ void tridiag_uniform_body(
+    int blk, int nblk, int n, int F2, int P, int spb, int nitems, const Coef<R> &cf,
+    const double *__restrict__ coef64, const R *__restrict__ lam,
+    const cpx<R> *__restrict__ fac, const double *__restrict__ gw,
+    const cpx<R> *__restrict__ in, const double *__restrict__ vin,
+    const double *__restrict__ xv, double wscale, int rhs_has_mass, cpx<R> *__restrict__ out,
+    double *__restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int NF = 6 * (MR - 1);
   const int tid = threadIdx.x;
@@ -331,7 +327,6 @@ tridiag_uniform_kernel(int n, int F2, int P, int spb, int nitems, Coef<R> cf,
   const int s0 = lt * MR;
   int len = n - s0;
   len = len < 0 ? 0 : (len > MR ? MR : len);
-  const int L2 = len < 2 ? 2 : len;   // virtual chunk length (a lone row gets a zero pad row)
 
   double acc[(MODE == 1) ? 1 : MR];
   R mx[(MODE == 1) ? MR : 1];
@@ -339,6 +334,7 @@ tridiag_uniform_kernel(int n, int F2, int P, int spb, int nitems, Coef<R> cf,
 #pragma unroll
     for (int q = 0; q < MR; ++q) acc[q] = 0.0;
   } else {
+    // -w M x, the same for every frequency (float64, rounded once)
 #pragma unroll
     for (int q = 0; q < MR; ++q) {
       int i = s0 + q;
@@ -369,7 +365,7 @@ tridiag_uniform_kernel(int n, int F2, int P, int spb, int nitems, Coef<R> cf,
   }
   const cpx<R> zero = {R(0), R(0)};
 
-  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+  for (int item = blk; item < nitems; item += nblk) {
     const int k0 = item * spb + g;
     const bool active = k0 < F2;
     const int k = active ? k0 : F2 - 1;
@@ -411,84 +407,7 @@ tridiag_uniform_kernel(int n, int F2, int P, int spb, int nitems, Coef<R> cf,
       }
       d[q] = v;
     }
-    __syncthreads();   // the staging area becomes the PCR exchange area
-
-    // upward sweep (distance dl = L2-1-q from the chunk's last row)
-    cpx<R> ud = zero;
-#pragma unroll
-    for (int q = MR - 2; q >= 0; --q) {
-      if (q <= L2 - 2) {
-        const int dl = L2 - 1 - q;
-        const cpx<R> r = lfac[(dl - 1) * 6 + 0];
-        ud = (dl == 1) ? cmul(d[q], r) : cmul(cfms(d[q], cc, ud), r);
-      }
-    }
-    cpx<R> ua = lfac[(L2 - 2) * 6 + 1], uc = lfac[(L2 - 2) * 6 + 2];
-    // downward sweep (distance q from the chunk's first row), D in place
-    cpx<R> Ae = zero, Ce = zero, De = zero;
-#pragma unroll
-    for (int q = 1; q < MR; ++q) {
-      if (q < len) {
-        const cpx<R> r = lfac[(q - 1) * 6 + 3];
-        d[q] = (q == 1) ? cmul(d[q], r) : cmul(cfms(d[q], ca, d[q - 1]), r);
-        if (q == len - 1) {
-          Ae = lfac[(q - 1) * 6 + 4];
-          Ce = lfac[(q - 1) * 6 + 5];
-          De = d[q];
-        }
-      }
-    }
-    if (len == 0) { ua = zero; uc = zero; ud = zero; }
-
-    // reduced system in the chunks' last unknowns (empty chunks: x_e = 0)
-    xch[lt] = Row3<R>{ua, uc, ud};
-    __syncthreads();
-    Row3<R> nx = (lt + 1 < P) ? xch[lt + 1] : Row3<R>{zero, zero, zero};
-    cpx<R> al = cneg(cmul(Ae, ua));
-    cpx<R> be = csub(csub(cpx<R>{R(1), R(0)}, cmul(Ae, uc)), cmul(Ce, nx.a));
-    cpx<R> ga = cneg(cmul(Ce, nx.c));
-    cpx<R> de = csub(csub(De, cmul(Ae, ud)), cmul(Ce, nx.d));
-    {
-      cpx<R> rb = crecip(be);
-      al = cmul(al, rb);
-      ga = cmul(ga, rb);
-      de = cmul(de, rb);
-    }
-    for (int st = 1; st < P; st <<= 1) {
-      __syncthreads();
-      xch[lt] = Row3<R>{al, ga, de};
-      __syncthreads();
-      Row3<R> lo = (lt >= st) ? xch[lt - st] : Row3<R>{zero, zero, zero};
-      Row3<R> hi = (lt + st < P) ? xch[lt + st] : Row3<R>{zero, zero, zero};
-      cpx<R> nb = csub(csub(cpx<R>{R(1), R(0)}, cmul(al, lo.c)), cmul(ga, hi.a));
-      cpx<R> nd = csub(csub(de, cmul(al, lo.d)), cmul(ga, hi.d));
-      cpx<R> na = cneg(cmul(al, lo.a));
-      cpx<R> ng = cneg(cmul(ga, hi.c));
-      cpx<R> rb = crecip(nb);
-      al = cmul(na, rb);
-      ga = cmul(ng, rb);
-      de = cmul(nd, rb);
-    }
-    const cpx<R> xe = (len >= 2) ? de : zero;
-    __syncthreads();
-    xch[lt].d = xe;
-    __syncthreads();
-    const cpx<R> xprev = (lt > 0) ? xch[lt - 1].d : zero;
-    const cpx<R> xs = csub(csub(ud, cmul(ua, xprev)), cmul(uc, xe));
-
-    // back substitution of the interior rows, in place
-    cpx<R> ynext = xe;
-#pragma unroll
-    for (int q = MR - 2; q >= 1; --q) {
-      if (q <= len - 2) {
-        d[q] = csub(csub(d[q], cmul(lfac[(q - 1) * 6 + 4], xs)), cmul(lfac[(q - 1) * 6 + 5], ynext));
-        ynext = d[q];
-      }
-    }
-    d[0] = xs;
-#pragma unroll
-    for (int q = 1; q < MR; ++q)
-      if (q == len - 1) d[q] = xe;
+    partition_solve<R, MR>(d, len, lt, P, lfac, xch, ca, cc);
 
     if constexpr (MODE == 1) {
       __syncthreads();
@@ -520,9 +439,25 @@ tridiag_uniform_kernel(int n, int F2, int P, int spb, int nitems, Coef<R> cf,
     for (int i = tid; i < n; i += blockDim.x) {
       double s = 0.0;
       for (int gg = 0; gg < spb; ++gg) s += base[(size_t)gg * rows + i];
-      partials[(size_t)blockIdx.x * n + i] = s;
+      partials[(size_t)blk * n + i] = s;
     }
   }
+}
+
+// Uniform-coefficient fast path (constant diagonals: uniform grids).  The
+// elimination factors are precomputed per plan (pd_partition.h); rows >= n
+// are absent, so the last chunk may be ragged and chunks past the end empty.
+template <typename R, int MR, int MODE>
+__global__ void __launch_bounds__(1024)
+tridiag_uniform_kernel(int n, int F2, int P, int spb, int nitems, Coef<R> cf,
+                       const double *__restrict__ coef64, const R *__restrict__ lam,
+                       const cpx<R> *__restrict__ fac, const double *__restrict__ gw,
+                       const cpx<R> *__restrict__ in, const double *__restrict__ vin,
+                       const double *__restrict__ xv, double wscale, int rhs_has_mass,
+                       cpx<R> *__restrict__ out, double *__restrict__ partials) {
+  tridiag_uniform_body<R, MR, MODE>(blockIdx.x, gridDim.x, n, F2, P, spb, nitems, cf, coef64,
+                                    lam, fac, gw, in, vin, xv, wscale, rhs_has_mass, out,
+                                    partials);
 }
 
 __global__ void reduce_partials_kernel(int n, int G, const double *__restrict__ partials,
@@ -636,40 +571,16 @@ pd_status pd_launch_tridiag(pd_plan p, int mode, const void *in, const double *x
 }
 
 // Elimination factors of the uniform path (float64), 6 complex values per
-// (frequency k, distance 1..MR-1); see tridiag_uniform_kernel.
+// (frequency k, distance 1..MR-1); see pd_partition.h.
 void pd_uniform_factors(const pd_plan p, int MR, std::vector<double> &fac) {
   const int F2 = p->F2;
   const size_t NF = 6 * (size_t)(MR - 1);
   fac.assign((size_t)F2 * NF * 2, 0.0);
-  struct C { double re, im; };
-  auto mul = [](C a, C b) { return C{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; };
-  auto sub = [](C a, C b) { return C{a.re - b.re, a.im - b.im}; };
-  auto inv = [](C a) { double d = 1.0 / (a.re * a.re + a.im * a.im); return C{a.re * d, -a.im * d}; };
   const double *u = p->uni;
   for (int k = 0; k < F2; ++k) {
     const double lr = p->lam[2 * k], li = p->lam[2 * k + 1];
-    const C a{lr * u[0] + u[3], li * u[0]}, b{lr * u[1] + u[4], li * u[1]},
-        c{lr * u[2] + u[5], li * u[2]};
-    C rU = inv(b), ua = mul(a, rU), uc = mul(c, rU);
-    C rD = rU, A = ua, Cc = uc;
-    for (int dist = 1; dist < MR; ++dist) {
-      if (dist > 1) {
-        rU = inv(sub(b, mul(c, ua)));
-        C nuc = mul(mul(c, uc), rU);
-        uc = C{-nuc.re, -nuc.im};
-        ua = mul(a, rU);
-        rD = inv(sub(b, mul(a, Cc)));
-        C nA = mul(mul(a, A), rD);
-        A = C{-nA.re, -nA.im};
-        Cc = mul(c, rD);
-      }
-      const C vals[6] = {rU, ua, uc, rD, A, Cc};
-      double *dst = &fac[((size_t)k * NF + (size_t)(dist - 1) * 6) * 2];
-      for (int j = 0; j < 6; ++j) {
-        dst[2 * j] = vals[j].re;
-        dst[2 * j + 1] = vals[j].im;
-      }
-    }
+    pd_partition_factors(lr * u[0] + u[3], li * u[0], lr * u[1] + u[4], li * u[1],
+                         lr * u[2] + u[5], li * u[2], MR, &fac[(size_t)k * NF * 2]);
   }
 }
 
@@ -711,4 +622,101 @@ void pd_tri_set_attributes(size_t max_lds) {
   set_attr_mr<float, 4>(v);
   set_attr_mr<float, 8>(v);
   set_attr_mr<float, 16>(v);
+}
+
+namespace {
+template <typename R, int MR, int MODE>
+__global__ void __launch_bounds__(1024)
+tridiag_batch_kernel(const TriJob *__restrict__ jobs, const int2 *__restrict__ map,
+                     const int *__restrict__ active, int jv) {
+  const int2 m = map[blockIdx.x];
+  if (active && !active[m.x]) return;   // whole block leaves together
+  const TriJob &j = jobs[m.x];
+  Coef<R> cf;
+  cf.ML = cf.MD = cf.MU = cf.KL = cf.KD = cf.KU = nullptr;
+  cf.ml = (R)j.ml; cf.md = (R)j.md; cf.mu = (R)j.mu;
+  cf.kl = (R)j.kl; cf.kd = (R)j.kd; cf.ku = (R)j.ku;
+  tridiag_uniform_body<R, MR, MODE>(m.y, j.nblk, j.n, j.F2, j.P, j.spb, j.nitems, cf, j.coef64,
+                                    reinterpret_cast<const R *>(j.lam),
+                                    reinterpret_cast<const cpx<R> *>(j.fac), j.gw,
+                                    reinterpret_cast<const cpx<R> *>(j.in),
+                                    j.vin ? j.vin + (size_t)jv * j.n : nullptr, j.xv,
+                                    j.wscale, j.has_mass, reinterpret_cast<cpx<R> *>(j.out),
+                                    j.partials);
+}
+
+// base_j < 0: b = sum of the pass-B partials (into j.bout);
+// base_j >= 0: w = V_{base_j} + sum of the J-product partials.
+__global__ void reduce_batch_kernel(const VecJob *__restrict__ jobs, const int2 *__restrict__ map,
+                                    int base_j, const int *__restrict__ active) {
+  const int2 m = map[blockIdx.x];
+  if (active && !active[m.x]) return;
+  const VecJob &j = jobs[m.x];
+  const int i = m.y * blockDim.x + threadIdx.x;
+  if (i >= j.n) return;
+  double s = (base_j >= 0) ? j.V[(size_t)base_j * j.n + i] : 0.0;
+  for (int g = 0; g < j.G; ++g) s += j.partials[(size_t)g * j.n + i];
+  if (base_j >= 0) j.w[i] = s;
+  else j.bout[i] = s;
+}
+}  // namespace
+
+pd_status pd_launch_tridiag_batch(int prec, int MR, int mode, const TriJob *jobs, const int2 *map,
+                                  int nblocks, size_t lds, const int *active, int jv,
+                                  hipStream_t s) {
+  if (nblocks == 0) return PD_OK;
+#define PD_TB(R, MRV, M)                                                                   \
+  hipLaunchKernelGGL((tridiag_batch_kernel<R, MRV, M>), dim3(nblocks), dim3(1024), lds, s, \
+                     jobs, map, active, jv)
+#define PD_TB_MODES(R, MRV)          \
+  do {                               \
+    if (mode == 0) PD_TB(R, MRV, 0); \
+    else if (mode == 1) PD_TB(R, MRV, 1); \
+    else PD_TB(R, MRV, 2);           \
+  } while (0)
+  if (prec == PD_FP64) {
+    if (MR == 4) PD_TB_MODES(double, 4);
+    else if (MR == 8) PD_TB_MODES(double, 8);
+    else { pd_set_error("batched solve: unsupported MR"); return PD_ENOTSUP; }
+  } else {
+    if (MR == 4) PD_TB_MODES(float, 4);
+    else if (MR == 8) PD_TB_MODES(float, 8);
+    else if (MR == 16) PD_TB_MODES(float, 16);
+    else { pd_set_error("batched solve: unsupported MR"); return PD_ENOTSUP; }
+  }
+#undef PD_TB_MODES
+#undef PD_TB
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
+pd_status pd_launch_reduce_batch(const VecJob *jobs, const int2 *map, int nblocks, int base_j,
+                                 const int *active, hipStream_t s) {
+  if (nblocks == 0) return PD_OK;
+  hipLaunchKernelGGL(reduce_batch_kernel, dim3(nblocks), dim3(256), 0, s, jobs, map, base_j,
+                     active);
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
+void pd_tri_batch_set_attributes(size_t max_lds) {
+  const int v = (int)max_lds;
+  const void *fns[] = {
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 4, 0>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 4, 1>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 4, 2>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 8, 0>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 8, 1>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 8, 2>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 4, 0>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 4, 1>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 4, 2>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 8, 0>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 8, 1>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 8, 2>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 16, 0>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 16, 1>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 16, 2>)};
+  for (const void *fn : fns)
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, v);
 }

@@ -1,0 +1,126 @@
+"""Serving (continuous batching) and batched solves: every result is the same
+alone and in the mix, the device-memory budget is respected, and results
+match the oracle."""
+import numpy as np
+import pytest
+
+from oracle import allatonce, modal
+from paper_2304_12597_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def T(a):
+    return torch.tensor(np.ascontiguousarray(a), device=dev())
+
+
+def mixed_problems(seed=0):
+    rng = np.random.default_rng(seed)
+    probs = []
+    for i in range(10):
+        if i % 3 == 2:
+            n = int(rng.choice([15, 31, 63]))
+            probs.append(wl.heat_2d(n, int(rng.choice([8, 16, 32])), 0.1,
+                                    float(np.exp(rng.uniform(np.log(1e-3), 0))), rng))
+        else:
+            kind = "fem1" if i % 2 else "fd1"
+            n = int(rng.integers(255, 2048))
+            probs.append(wl.heat_1d(kind, n, int(rng.choice([32, 64, 128])), 1.0,
+                                    float(np.exp(rng.uniform(np.log(1e-3), 0))), rng, True))
+    return probs
+
+
+def solve_alone(lib, p, prec=0, tol=1e-10):
+    plan = lib.paradiag_plan_create(p.n, p.ell, p.tau, p.M, p.K, dims=p.dims, precision=prec,
+                                    stream=torch.cuda.current_stream().cuda_stream)
+    try:
+        U = torch.empty((p.ell, p.nbar), dtype=torch.float64, device=dev())
+        lib.paradiag_solve(plan, T(p.u0), T(p.F), U, tol)
+        torch.cuda.synchronize()
+        return U.cpu().numpy()
+    finally:
+        lib.paradiag_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_server_results_same_alone_and_in_mix(lib, prec):
+    probs = mixed_problems(prec)
+    alone = [solve_alone(lib, p, prec) for p in probs]
+    srv = lib.pd_server_create(4, 8 << 30)
+    try:
+        bufs = []
+        for p in probs:
+            bufs.append((T(p.u0), T(p.F), torch.empty((p.ell, p.nbar), dtype=torch.float64,
+                                                       device=dev())))
+        torch.cuda.synchronize()
+        tickets = []
+        for p, (u0, F, U) in zip(probs, bufs):
+            tickets.append(lib.pd_server_submit(srv, p.n, p.ell, p.tau, p.M, p.K, u0, F, U,
+                                                1e-10, dims=p.dims, precision=prec))
+        for t in tickets:
+            done, st, info = lib.pd_server_wait(srv, t, -1)
+            assert done and st == 0, (st, info.as_dict())
+        stats = lib.pd_server_stats(srv)
+        assert stats["completed"] == len(probs)
+        assert stats["peak_bytes"] <= 8 << 30
+    finally:
+        lib.pd_server_destroy(srv)
+    for p, (u0, F, U), Ua in zip(probs, bufs, alone):
+        Ug = U.cpu().numpy()
+        assert np.array_equal(Ug, Ua)          # identical alone and in the mix
+        err = allatonce.rel_err(Ug, modal.modal_solution(p))
+        assert err < (1e-8 if p.kind != "fd2" else 1e-9), (p.kind, p.n, p.ell, err)
+
+
+def test_server_budget_and_cache(lib):
+    p = wl.heat_1d("fd1", 511, 64, 1.0, 0.1, np.random.default_rng(1), True)
+    need = lib.paradiag_plan_bytes(p.n, p.ell) + (2 * p.ell * p.nbar + p.nbar) * 8
+    budget = int(need * 1.5)            # room for one request at a time
+    srv = lib.pd_server_create(3, budget)
+    try:
+        u0, F = T(p.u0), T(p.F)
+        outs = [torch.empty((p.ell, p.nbar), dtype=torch.float64, device=dev())
+                for _ in range(5)]
+        torch.cuda.synchronize()
+        ts = [lib.pd_server_submit(srv, p.n, p.ell, p.tau, p.M, p.K, u0, F, U, 1e-10)
+              for U in outs]
+        for t in ts:
+            done, st, _ = lib.pd_server_wait(srv, t, -1)
+            assert done and st == 0
+        stats = lib.pd_server_stats(srv)
+        assert stats["peak_bytes"] <= budget
+        assert stats["cache_misses"] == 1 and stats["cache_hits"] == 4
+        big = wl.heat_1d("fd1", 4095, 1024, 1.0, 0.1, np.random.default_rng(2), False)
+        with pytest.raises(lib.PDError) as ei:
+            lib.pd_server_submit(srv, big.n, big.ell, big.tau, None, big.K, u0, F, outs[0],
+                                 1e-10)
+        assert ei.value.status == lib.PD_EBUDGET
+    finally:
+        lib.pd_server_destroy(srv)
+    ref = outs[0].cpu().numpy()
+    for U in outs[1:]:
+        assert np.array_equal(U.cpu().numpy(), ref)
+
+
+def test_solve_batch_matches_individual(lib):
+    probs = [p for p in mixed_problems(5) if p.dims == 1][:5]
+    alone = [solve_alone(lib, p) for p in probs]
+    s = torch.cuda.current_stream().cuda_stream
+    plans = [lib.paradiag_plan_create(p.n, p.ell, p.tau, p.M, p.K, stream=s) for p in probs]
+    try:
+        u0s = [T(p.u0) for p in probs]
+        Fs = [T(p.F) for p in probs]
+        Us = [torch.empty((p.ell, p.nbar), dtype=torch.float64, device=dev()) for p in probs]
+        infos = lib.paradiag_solve_batch(plans, u0s, Fs, Us, 1e-10)
+        torch.cuda.synchronize()
+    finally:
+        for pl in plans:
+            lib.paradiag_plan_destroy(pl)
+    for U, Ua, info in zip(Us, alone, infos):
+        assert np.array_equal(U.cpu().numpy(), Ua)
+        assert info.gmres_iters >= 1
