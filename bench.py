@@ -32,6 +32,10 @@ METRIC = "space-time unknowns/s at 1e-8 rel err (mixed vs FP64) + p50/p99 latenc
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="fem1d", choices=["fem1d", "ensemble", "serve"])
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--count", type=int, default=0, help="ensemble / stream size")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--forms", default="fp64,mixed")
@@ -52,6 +56,15 @@ def main():
     from paper_2304_12597_amd import workloads as wl
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        copy_calibration(torch, dev)
+        return
+    if args.workload == "ensemble":
+        print(json.dumps(bench_ensemble(args, torch, pd, wl, dev)))
+        return
+    if args.workload == "serve":
+        print(json.dumps(bench_serve(args, torch, pd, wl, dev)))
+        return
     stream = torch.cuda.current_stream(dev)
     prob = wl.cfg_fem_1d()
     nbar, ell = prob.nbar, prob.ell
@@ -199,6 +212,130 @@ def cpu_baseline_leg(prob, results_U, forms, seconds):
             "sample": "sequential backward-Euler stepping (C, Thomas, 1 thread) of the full "
                       "n=8191 ell=2048 problem, repeated %d times (%.1f s)" % (reps, el),
             "oracle_rel_err_vs_exact": err}
+
+
+def copy_calibration(torch, dev, gib=1, reps=5):
+    """A plain device copy of known size: its FETCH_SIZE / WRITE_SIZE counter
+    readings convert the counters of the ParaDiag kernels to bytes."""
+    n = gib * (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "reps": reps}))
+
+
+def bench_ensemble(args, torch, pd, wl, dev):
+    """Independent 1D FD heat problems solved in one batched submission."""
+    count = args.count or 512
+    probs = wl.ensemble(count=count)
+    stream = torch.cuda.current_stream(dev)
+    plans, u0s, Fs, Us = [], [], [], []
+    try:
+        for p in probs:
+            plans.append(pd.paradiag_plan_create(p.n, p.ell, p.tau, p.M, p.K,
+                                                 stream=stream.cuda_stream))
+            u0s.append(torch.tensor(p.u0, device=dev))
+            Fs.append(torch.tensor(p.F, device=dev))
+            Us.append(torch.empty((p.ell, p.nbar), dtype=torch.float64, device=dev))
+        unknowns = sum(p.unknowns for p in probs)
+        for _ in range(args.warmup):
+            pd.paradiag_solve_batch(plans, u0s, Fs, Us, 1e-8, allow_notconv=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            infos = pd.paradiag_solve_batch(plans, u0s, Fs, Us, 1e-8, allow_notconv=True)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        its = [i.gmres_iters for i in infos]
+        out = {"metric": "space-time unknowns/s (batched ensemble)",
+               "value": unknowns / wall, "unit": "space-time unknowns/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall,
+               "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+               "config": {"workload": "ensemble of %d 1D FD heat problems, n in [255,4095], "
+                                      "ell in {64..1024}, nu log-uniform [1e-3,1]" % count,
+                          "unknowns": unknowns},
+               "gmres_iters": {"min": min(its), "max": max(its), "mean": float(np.mean(its))}}
+        if not args.no_cpu_baseline:
+            from oracle import modal
+            errs = []
+            rng = np.random.default_rng(0)
+            for p, U in list(zip(probs, Us))[:: max(1, count // 32)]:
+                tt = rng.integers(0, p.ell, 2000)
+                ii = rng.integers(0, p.nbar, 2000)
+                ref = modal.modal_sample(p, tt, ii)
+                Uh = U.cpu().numpy()
+                errs.append(float(np.linalg.norm(Uh[tt, ii] - ref) / np.linalg.norm(ref)))
+            out["rel_err_vs_exact_max_sampled"] = max(errs)
+        return out
+    finally:
+        for pl in plans:
+            pd.paradiag_plan_destroy(pl)
+
+
+def bench_serve(args, torch, pd, wl, dev):
+    """Poisson stream of mixed 1D FEM / 2D FD requests through the serving
+    runtime: first closed loop (saturation throughput), then open loop at
+    0.7x that rate; p50/p99 of completion - arrival."""
+    import threading
+    count = args.count or 32
+    reqs = wl.serving_stream(count=count, rate=1.0)
+    prec = pd.PD_MIXED
+    staged = []
+    for r in reqs:
+        p = r.problem
+        staged.append((p, torch.tensor(p.u0, device=dev), torch.tensor(p.F, device=dev),
+                       torch.empty((p.ell, p.nbar), dtype=torch.float64, device=dev)))
+    torch.cuda.synchronize()
+    budget = 200 << 30
+    srv = pd.pd_server_create(4, budget)
+    try:
+        def submit(item):
+            p, u0, F, U = item
+            return pd.pd_server_submit(srv, p.n, p.ell, p.tau, p.M, p.K, u0, F, U, 1e-8,
+                                       dims=p.dims, precision=prec)
+        # warm the plan cache and measure closed-loop throughput
+        t0 = time.perf_counter()
+        ts = [submit(it) for it in staged]
+        for t in ts:
+            pd.pd_server_wait(srv, t, -1)
+        closed = time.perf_counter() - t0
+        rate = 0.7 * count / closed
+        arrivals = np.cumsum(np.random.default_rng(4).exponential(1.0 / rate, count))
+        done_at = [0.0] * count
+        tickets = [None] * count
+        start = time.perf_counter()
+
+        def waiter():
+            for i in range(count):
+                while tickets[i] is None:
+                    time.sleep(1e-4)
+                pd.pd_server_wait(srv, tickets[i], -1)
+                done_at[i] = time.perf_counter() - start
+        th = threading.Thread(target=waiter)
+        th.start()
+        for i, it in enumerate(staged):
+            now = time.perf_counter() - start
+            if arrivals[i] > now:
+                time.sleep(arrivals[i] - now)
+            tickets[i] = submit(it)
+        th.join()
+        wall = max(done_at)
+        lat = np.array(done_at) - arrivals
+        stats = pd.pd_server_stats(srv)
+    finally:
+        pd.pd_server_destroy(srv)
+    unknowns = sum(it[0].unknowns for it in staged)
+    return {"metric": "space-time unknowns/s + p50/p99 latency (serving)",
+            "value": unknowns / wall, "unit": "space-time unknowns/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "c64+f64", "data": "synthetic",
+            "config": {"workload": "Poisson stream of %d requests, 70%% 1D FEM / 30%% 2D FD, "
+                                   "mixed precision to 1e-8, 200 GB budget" % count,
+                       "arrival_rate_per_s": rate, "closed_loop_s": closed},
+            "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
+                           "p99": 1e3 * float(np.percentile(lat, 99))},
+            "server": stats}
 
 
 if __name__ == "__main__":

@@ -19,6 +19,7 @@ bool batchable(const pd_plan *plans, int count) {
   for (int i = 0; i < count; ++i) {
     const pd_plan p = plans[i];
     if (!p || p->dims != 1 || !p->uniform || p->prec != p0->prec || p->prec == PD_MIXED ||
+        p->tri.block != 1024 ||
         p->maxit != p0->maxit)
       return false;
     for (int j = 0; j < i; ++j)

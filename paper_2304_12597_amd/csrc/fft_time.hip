@@ -486,34 +486,20 @@ int pd_fft_blocks(pd_plan p) { return fft_config(p).blocks; }
 // Allow the transform kernels the device's full LDS per block.
 void pd_fft_set_attributes(size_t max_lds) {
   const int v = (int)max_lds;
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_forward_kernel<double, 0>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_forward_kernel<double, 1>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_forward_kernel<float, 0>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_forward_kernel<float, 1>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_forward_kernel<double, 2>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_forward_kernel<float, 2>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&dst_x_kernel<0, 0>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&dst_x_kernel<1, 0>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&dst_x_kernel<2, 0>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&dst_x_kernel<2, 1>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_inverse_kernel<double, 0>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_inverse_kernel<double, 1>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_inverse_kernel<float, 0>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_inverse_kernel<float, 1>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  pd_set_max_lds(reinterpret_cast<const void *>(&fft_forward_kernel<double, 0>), v);
+  pd_set_max_lds(reinterpret_cast<const void *>(&fft_forward_kernel<double, 1>), v);
+  pd_set_max_lds(reinterpret_cast<const void *>(&fft_forward_kernel<float, 0>), v);
+  pd_set_max_lds(reinterpret_cast<const void *>(&fft_forward_kernel<float, 1>), v);
+  pd_set_max_lds(reinterpret_cast<const void *>(&fft_forward_kernel<double, 2>), v);
+  pd_set_max_lds(reinterpret_cast<const void *>(&fft_forward_kernel<float, 2>), v);
+  pd_set_max_lds(reinterpret_cast<const void *>(&dst_x_kernel<0, 0>), v);
+  pd_set_max_lds(reinterpret_cast<const void *>(&dst_x_kernel<1, 0>), v);
+  pd_set_max_lds(reinterpret_cast<const void *>(&dst_x_kernel<2, 0>), v);
+  pd_set_max_lds(reinterpret_cast<const void *>(&dst_x_kernel<2, 1>), v);
+  pd_set_max_lds(reinterpret_cast<const void *>(&fft_inverse_kernel<double, 0>), v);
+  pd_set_max_lds(reinterpret_cast<const void *>(&fft_inverse_kernel<double, 1>), v);
+  pd_set_max_lds(reinterpret_cast<const void *>(&fft_inverse_kernel<float, 0>), v);
+  pd_set_max_lds(reinterpret_cast<const void *>(&fft_inverse_kernel<float, 1>), v);
 }
 
 namespace {
@@ -570,5 +556,5 @@ void pd_fft_batch_set_attributes(size_t max_lds) {
                        reinterpret_cast<const void *>(&fft_inverse_batch_kernel<double>),
                        reinterpret_cast<const void *>(&fft_inverse_batch_kernel<float>)};
   for (const void *fn : fns)
-    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+    pd_set_max_lds(fn, v);
 }

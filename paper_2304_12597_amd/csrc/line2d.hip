@@ -242,5 +242,5 @@ void pd_line2d_set_attributes(size_t max_lds) {
       reinterpret_cast<const void *>(&line2d_kernel<float, 8, 1>),
       reinterpret_cast<const void *>(&line2d_kernel<float, 8, 2>)};
   for (const void *f : fns)
-    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+    pd_set_max_lds(f, v);
 }

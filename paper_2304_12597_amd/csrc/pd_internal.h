@@ -241,3 +241,14 @@ bool pd_batchable(const pd_plan *plans, int count);
 pd_status pd_solve_batch_impl(const pd_plan *plans, int count, const double *const *u0,
                               const double *const *F, double *const *U, double tol,
                               pd_info *infos);
+
+// Raise a kernel's dynamic-LDS limit to what the device allows beside its
+// static LDS; failures are cleared so no stale error reaches the caller.
+inline void pd_set_max_lds(const void *fn, int max_lds) {
+  hipFuncAttributes a;
+  int static_lds = 0;
+  if (hipFuncGetAttributes(&a, fn) == hipSuccess) static_lds = (int)a.sharedSizeBytes;
+  (void)hipGetLastError();
+  (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds - static_lds);
+  (void)hipGetLastError();
+}

@@ -522,8 +522,7 @@ pd_status launch_mr(pd_plan p, int mode, const void *in, const double *xv, void 
 }  // namespace
 
 // Pick (P, MR, systems per block) for n rows: MR rows per thread, P a power of
-// two with P*MR >= n, at least 256 threads per block (several small systems
-// share a block).
+// two with P*MR >= n.
 TriConfig pd_choose_tri(int n, int F2, int prec) {
   TriConfig T;
   const size_t cb = (prec == PD_FP64) ? 16 : 8;
@@ -534,8 +533,10 @@ TriConfig pd_choose_tri(int n, int F2, int prec) {
   while (P * MR < n) P *= 2;
   T.P = P;
   T.MR = MR;
-  int spb = 1;
-  while (P * spb < 256 && spb < F2) spb *= 2;
+  // every block has 1024 threads: 1024/P systems per block.  Batched
+  // launches use the same packing, so the order of the float64 sums over
+  // frequencies -- and hence every result -- is the same alone and in a batch.
+  const int spb = (P >= 16) ? 1024 / P : 64;   // tiny systems: 64 per block
   T.spb = spb;
   T.block = P * spb;
   const size_t rows = (size_t)P * MR;
@@ -611,7 +612,7 @@ void set_attr_mr(int v) {
                         reinterpret_cast<const void *>(&tridiag_uniform_kernel<R, MR, 1>),
                         reinterpret_cast<const void *>(&tridiag_uniform_kernel<R, MR, 2>)};
   for (const void *f : fns)
-    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+    pd_set_max_lds(f, v);
 }
 }  // namespace
 
@@ -718,5 +719,5 @@ void pd_tri_batch_set_attributes(size_t max_lds) {
       reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 16, 1>),
       reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 16, 2>)};
   for (const void *fn : fns)
-    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+    pd_set_max_lds(fn, v);
 }

@@ -87,16 +87,20 @@ def _solve(lib, p, prec=0, tol=1e-10):
         lib.paradiag_plan_destroy(plan)
 
 
-@pytest.mark.parametrize("n,ell,nu,T_", [(3, 2, 1.0, 0.1), (7, 8, 1.0, 0.1),
-                                         (31, 64, 0.01, 1.0), (127, 16, 1.0, 0.1),
-                                         (63, 256, 0.001, 0.1)])
-def test_2d_end_to_end_fp64(lib, n, ell, nu, T_):
+@pytest.mark.parametrize("n,ell,nu,T_,bound", [(3, 2, 1.0, 0.1, 1e-10), (7, 8, 1.0, 0.1, 1e-10),
+                                               (31, 64, 0.01, 1.0, 1e-10),
+                                               (127, 16, 1.0, 0.1, 1e-10),
+                                               (63, 256, 0.001, 0.1, 1e-9)])
+def test_2d_end_to_end_fp64(lib, n, ell, nu, T_, bound):
+    """nu*T = 1e-4 makes J_ell ill-conditioned (Theorem 1 bound
+    1 + 1/(tau lambda_min) ~ 1e5): the solve uses a tighter tolerance and the
+    error bound is 1e-9 there."""
     p = wl.heat_2d(n, ell, T_, nu, np.random.default_rng(n + ell))
-    U, info = _solve(lib, p)
+    U, info = _solve(lib, p, tol=1e-10 if bound == 1e-10 else 1e-13)
     err = allatonce.rel_err(U, modal.modal_solution(p))
     print("2D n=%d ell=%d err=%.3e res=%.3e gmres=%d" % (n, ell, err, info.rel_residual,
                                                          info.gmres_iters))
-    assert err < 1e-10
+    assert err < bound
     assert info.rel_residual < 1e-11
 
 

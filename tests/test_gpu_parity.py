@@ -81,7 +81,7 @@ def test_inverse_transform(lib, prec, n, ell):
     rng = np.random.default_rng(n)
     X = rng.standard_normal((ell, n))
     F2 = ell // 2 + 1
-    spec = np.fft.fft(X, axis=0)[:F2].astype(cdt)
+    spec = np.ascontiguousarray(np.fft.fft(X, axis=0)[:F2]).astype(cdt)
     plan = plan_for(lib, p, precision=code)
     try:
         Sbuf = torch.tensor(spec.view(np.float64 if prec == "fp64" else np.float32).reshape(-1),
@@ -123,7 +123,7 @@ def test_shifted_solves_and_b(lib, prec, kind, n, ell, alpha):
     w = alpha ** (1.0 / ell)
     plan = plan_for(lib, p, precision=code, alpha=alpha)
     try:
-        Hbuf = torch.tensor(Hhat[:F2].astype(cdt).view(
+        Hbuf = torch.tensor(np.ascontiguousarray(Hhat[:F2]).astype(cdt).view(
             np.float64 if prec == "fp64" else np.float32).reshape(-1), device=dev())
         Y = torch.empty_like(Hbuf)
         b = torch.empty(n, dtype=torch.float64, device=dev())
@@ -138,7 +138,10 @@ def test_shifted_solves_and_b(lib, prec, kind, n, ell, alpha):
     Yref = (out["L"] - w * out["W"])[:F2]
     tolY = 1e-10 if prec == "fp64" else 2e-3
     assert rel(Yg, Yref) < tolY, rel(Yg, Yref)
-    assert rel(bg, out["b"].real) < (1e-10 if prec == "fp64" else 2e-3)
+    # b sums ell solutions of systems with condition number ~ (n+1)^2; two
+    # correct eliminations differ by ~ cond * eps there
+    assert rel(bg, out["b"].real) < (max(1e-10, 1e-16 * (n + 1) ** 2) if prec == "fp64"
+                                     else 2e-3)
 
 
 @pytest.mark.parametrize("kind,n,ell", SOLVE_CASES[:6])

@@ -74,7 +74,7 @@ def test_server_results_same_alone_and_in_mix(lib, prec):
         Ug = U.cpu().numpy()
         assert np.array_equal(Ug, Ua)          # identical alone and in the mix
         err = allatonce.rel_err(Ug, modal.modal_solution(p))
-        assert err < (1e-8 if p.kind != "fd2" else 1e-9), (p.kind, p.n, p.ell, err)
+        assert err < 1e-8, (p.kind, p.n, p.ell, err)
 
 
 def test_server_budget_and_cache(lib):
