@@ -135,27 +135,46 @@ __device__ __forceinline__ void fft_forward_body(int tile, int N, int n, int nba
   const int S = 2 * C;
   const int i0 = tile * S;
   double rn2 = 0.0, gn2 = 0.0;
-  for (int idx = tid; idx < N * S; idx += T) {
-    int t = idx / S, pnt = idx - t * S;
-    int i = i0 + pnt;
-    double val = 0.0;
-    if (i < nbar) {
-      if (MODE == 0) {
-        val = tau * F[(size_t)t * nbar + i];
-        if (t == 0) val += u0[i];
-      } else if (MODE == 2) {
-        val = F[(size_t)t * nbar + i];   // plain real input
-      } else {
-        double r, g;
-        residual_point(t, i, n, nbar, dims, tau, u0, F, U, coef, r, g);
-        rn2 += r * r;
-        gn2 += g * g;
-        val = r;
+  // Issue UNR independent loads per thread before storing to LDS, so their
+  // HBM latencies overlap instead of adding up.
+  constexpr int UNR = 8;
+  const int total = N * S;
+  for (int base = tid; base < total; base += UNR * T) {
+    double vals[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = base + u * T;
+      double val = 0.0;
+      if (idx < total) {
+        const int t = idx / S, pnt = idx - t * S;
+        const int i = i0 + pnt;
+        if (i < nbar) {
+          if (MODE == 0) {
+            val = tau * F[(size_t)t * nbar + i];
+            if (t == 0) val += u0[i];
+          } else if (MODE == 2) {
+            val = F[(size_t)t * nbar + i];   // plain real input
+          } else {
+            double r, g;
+            residual_point(t, i, n, nbar, dims, tau, u0, F, U, coef, r, g);
+            rn2 += r * r;
+            gn2 += g * g;
+            val = r;
+          }
+          val *= dal[t];
+        }
       }
-      val *= dal[t];
+      vals[u] = val;
     }
-    R *l = reinterpret_cast<R *>(&lds[(pnt >> 1) * stride + t]);
-    l[pnt & 1] = (R)val;
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = base + u * T;
+      if (idx < total) {
+        const int t = idx / S, pnt = idx - t * S;
+        R *l = reinterpret_cast<R *>(&lds[(pnt >> 1) * stride + t]);
+        l[pnt & 1] = (R)vals[u];
+      }
+    }
   }
   __syncthreads();
   fft_lds<R, false>(lds, N, C, stride, tw);
@@ -195,6 +214,16 @@ __device__ __forceinline__ void fft_forward_body(int tile, int N, int n, int nba
   }
 }
 
+// Blocks are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Neighbouring tiles read the two halves of the same 128-byte lines, so map
+// consecutive blocks of one XCD to consecutive tiles.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  constexpr int X = 8;
+  const int per = nb / X;            // tiles in the evenly divisible part
+  if (b >= per * X) return b;        // remainder keeps its position
+  return (b % X) * per + b / X;
+}
+
 template <typename R, int MODE>
 __global__ void __launch_bounds__(1024)
 fft_forward_kernel(int N, int n, int nbar, int dims, int C, int stride, double tau,
@@ -202,8 +231,8 @@ fft_forward_kernel(int N, int n, int nbar, int dims, int C, int stride, double t
                    const double *__restrict__ U, const double *__restrict__ coef,
                    const double *__restrict__ dal, const cpx<R> *__restrict__ tw,
                    cpx<R> *__restrict__ out, double *__restrict__ red) {
-  fft_forward_body<R, MODE>(blockIdx.x, N, n, nbar, dims, C, stride, tau, u0, F, U, coef, dal,
-                            tw, out, red);
+  fft_forward_body<R, MODE>(xcd_tile(blockIdx.x, gridDim.x), N, n, nbar, dims, C, stride, tau,
+                            u0, F, U, coef, dal, tw, out, red);
 }
 
 template <typename R, int ACC>
@@ -218,15 +247,33 @@ __device__ __forceinline__ void fft_inverse_body(int tile, int N, int nbar, int 
   const int S = 2 * C;
   const int i0 = tile * S;
   const int half = N / 2;
-  for (int idx = tid; idx < (half + 1) * C; idx += T) {
-    int k = idx / C, c = idx - k * C;
-    int ia = i0 + 2 * c, ib = ia + 1;
-    cpx<R> xa = {R(0), R(0)}, xb = {R(0), R(0)};
-    if (ia < nbar) xa = in[(size_t)k * nbar + ia];
-    if (ib < nbar) xb = in[(size_t)k * nbar + ib];
-    if (k == 0 || k == half) { xa.im = R(0); xb.im = R(0); }
-    lds[c * stride + k] = cpx<R>{xa.re - xb.im, xa.im + xb.re};
-    if (k > 0 && k < half) lds[c * stride + N - k] = cpx<R>{xa.re + xb.im, xb.re - xa.im};
+  constexpr int UNR = 4;
+  const int total = (half + 1) * C;
+  for (int base = tid; base < total; base += UNR * T) {
+    cpx<R> xa[UNR], xb[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = base + u * T;
+      xa[u] = cpx<R>{R(0), R(0)};
+      xb[u] = cpx<R>{R(0), R(0)};
+      if (idx < total) {
+        const int k = idx / C, c = idx - k * C;
+        const int ia = i0 + 2 * c, ib = ia + 1;
+        if (ia < nbar) xa[u] = in[(size_t)k * nbar + ia];
+        if (ib < nbar) xb[u] = in[(size_t)k * nbar + ib];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = base + u * T;
+      if (idx < total) {
+        const int k = idx / C, c = idx - k * C;
+        cpx<R> a = xa[u], b = xb[u];
+        if (k == 0 || k == half) { a.im = R(0); b.im = R(0); }
+        lds[c * stride + k] = cpx<R>{a.re - b.im, a.im + b.re};
+        if (k > 0 && k < half) lds[c * stride + N - k] = cpx<R>{a.re + b.im, b.re - a.im};
+      }
+    }
   }
   __syncthreads();
   fft_lds<R, true>(lds, N, C, stride, tw);
@@ -248,7 +295,8 @@ __global__ void __launch_bounds__(1024)
 fft_inverse_kernel(int N, int nbar, int C, int stride, const cpx<R> *__restrict__ in,
                    const double *__restrict__ dalinv, const cpx<R> *__restrict__ tw,
                    double *__restrict__ U) {
-  fft_inverse_body<R, ACC>(blockIdx.x, N, nbar, C, stride, in, dalinv, tw, U);
+  fft_inverse_body<R, ACC>(xcd_tile(blockIdx.x, gridDim.x), N, nbar, C, stride, in, dalinv, tw,
+                           U);
 }
 
 // Orthonormal DST-I along x of every grid row (t, y) of a 2D space-time
@@ -278,30 +326,47 @@ dst_x_kernel(int n, int ell, int C, int stride, double tau, const double *__rest
     lds[c * stride] = cpx<double>{0.0, 0.0};
     lds[c * stride + n + 1] = cpx<double>{0.0, 0.0};
   }
-  for (int idx = tid; idx < 2 * C * n; idx += T) {
-    const int lr = idx / n, x = idx - lr * n;
-    const int row = r0 + lr;
-    double v = 0.0;
-    if (row < rows) {
-      const int t = row / n, y = row - t * n;
-      const int i = y * n + x;
-      if (MODE == 0) {
-        v = tau * F[(size_t)t * nbar + i];
-        if (t == 0) v += u0[i];
-      } else if (MODE == 1) {
-        double r, g;
-        residual_point(t, i, n, nbar, 2, tau, u0, F, U, coef, r, g);
-        rn2 += r * r;
-        gn2 += g * g;
-        v = r;
-      } else {
-        v = in[(size_t)t * nbar + i];
+  constexpr int UNR = 8;
+  const int total = 2 * C * n;
+  for (int base = tid; base < total; base += UNR * T) {
+    double vals[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = base + u * T;
+      double v = 0.0;
+      if (idx < total) {
+        const int lr = idx / n, x = idx - lr * n;
+        const int row = r0 + lr;
+        if (row < rows) {
+          const int t = row / n, y = row - t * n;
+          const int i = y * n + x;
+          if (MODE == 0) {
+            v = tau * F[(size_t)t * nbar + i];
+            if (t == 0) v += u0[i];
+          } else if (MODE == 1) {
+            double r, g;
+            residual_point(t, i, n, nbar, 2, tau, u0, F, U, coef, r, g);
+            rn2 += r * r;
+            gn2 += g * g;
+            v = r;
+          } else {
+            v = in[(size_t)t * nbar + i];
+          }
+        }
+      }
+      vals[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = base + u * T;
+      if (idx < total) {
+        const int lr = idx / n, x = idx - lr * n;
+        double *p1 = reinterpret_cast<double *>(&lds[(lr >> 1) * stride + x + 1]);
+        double *p2 = reinterpret_cast<double *>(&lds[(lr >> 1) * stride + N - 1 - x]);
+        p1[lr & 1] = vals[u];
+        p2[lr & 1] = -vals[u];
       }
     }
-    double *p1 = reinterpret_cast<double *>(&lds[(lr >> 1) * stride + x + 1]);
-    double *p2 = reinterpret_cast<double *>(&lds[(lr >> 1) * stride + N - 1 - x]);
-    p1[lr & 1] = v;
-    p2[lr & 1] = -v;
   }
   __syncthreads();
   fft_lds<double, false>(lds, N, C, stride, tw);

@@ -103,7 +103,7 @@ cgs_update_kernel(int n, int nv, int nblk, const double *__restrict__ V, double 
 // Single block: ||w||, Givens update of column j, residual estimate.
 // status: [0] = |g_{j+1}| (residual), [1] = h_{j+1,j}, [2] = iterations
 __global__ void givens_kernel(int nv, int nblk, const double *__restrict__ red,
-                              double *__restrict__ gm, int MX, int j) {
+                              double *__restrict__ gm, int MX, int j, double *__restrict__ host) {
   GmLayout L{MX};
   if (threadIdx.x != 0) return;
   double nn = 0.0;
@@ -129,6 +129,10 @@ __global__ void givens_kernel(int nv, int nblk, const double *__restrict__ red,
   gm[L.st(0)] = fabs(-s * gj);
   gm[L.st(1)] = hn;
   gm[L.st(2)] = (double)(j + 1);
+  host[0] = fabs(-s * gj);
+  host[1] = hn;
+  host[2] = (double)(j + 1);
+  host[3] = gm[L.st(3)];
 }
 
 // V_{j+1} = w / ||w|| (or 0 on breakdown); norm taken from status[1]
@@ -143,7 +147,7 @@ __global__ void scale_kernel(int n, const double *__restrict__ w, double *__rest
 
 // beta = ||b||; g = beta e_1; H = 0; V_0 = b / beta (two launches)
 __global__ void init_kernel(int nblk, const double *__restrict__ red, double *__restrict__ gm,
-                            int MX) {
+                            int MX, double *__restrict__ host) {
   GmLayout L{MX};
   for (int i = threadIdx.x; i < L.size(); i += blockDim.x) gm[i] = 0.0;
   __syncthreads();
@@ -155,6 +159,10 @@ __global__ void init_kernel(int nblk, const double *__restrict__ red, double *__
     gm[L.st(0)] = beta;
     gm[L.st(1)] = beta;
     gm[L.st(3)] = beta;
+    host[0] = beta;
+    host[1] = beta;
+    host[2] = 0.0;
+    host[3] = beta;
   }
 }
 
@@ -198,13 +206,12 @@ pd_status pd_gmres(pd_plan p, const double *b, double *x, double rtol, int *iter
   double *st_host = p->host_pin;
   // beta = ||b||
   hipLaunchKernelGGL(dots_kernel, dim3(B), dim3(VB), 0, p->stream, n, 0, p->V, b, red1);
-  hipLaunchKernelGGL(init_kernel, dim3(1), dim3(256), 0, p->stream, B, red1, p->gm, MX);
-  PD_HIP_CHECK(hipMemcpyAsync(st_host, p->gm + L.st(0), 4 * sizeof(double),
-                              hipMemcpyDeviceToHost, p->stream));
+  hipLaunchKernelGGL(init_kernel, dim3(1), dim3(256), 0, p->stream, B, red1, p->gm, MX,
+                     p->host_dev);
   hipLaunchKernelGGL(scale_kernel, dim3(B), dim3(VB), 0, p->stream, n, b, p->V, p->gm, MX);
   PD_HIP_CHECK(hipGetLastError());
   PD_HIP_CHECK(hipStreamSynchronize(p->stream));
-  const double beta = st_host[0];
+  const double beta = ((volatile double *)st_host)[0];
   if (!std::isfinite(beta)) {
     pd_set_error("capacitance right-hand side is not finite");
     return PD_ENONFINITE;
@@ -230,27 +237,25 @@ pd_status pd_gmres(pd_plan p, const double *b, double *x, double rtol, int *iter
                        p->wvec, red2, red1, p->gm, MX, j, 0);
     hipLaunchKernelGGL(dots_kernel, dim3(B), dim3(VB), 0, p->stream, n, 0, p->V, p->wvec, red1);
     hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(64), 0, p->stream, 0, B, red1, p->gm, MX,
-                       j);
+                       j, p->host_dev);
     hipLaunchKernelGGL(scale_kernel, dim3(B), dim3(VB), 0, p->stream, n, p->wvec,
                        p->V + (size_t)(j + 1) * n, p->gm, MX);
     PD_HIP_CHECK(hipGetLastError());
-    PD_HIP_CHECK(hipMemcpyAsync(st_host, p->gm + L.st(0), 4 * sizeof(double),
-                                hipMemcpyDeviceToHost, p->stream));
     PD_HIP_CHECK(hipStreamSynchronize(p->stream));
     m = j + 1;
-    res = st_host[0];
+    res = ((volatile double *)st_host)[0];
     if (!std::isfinite(res)) {
       pd_set_error("capacitance GMRES produced a non-finite residual");
       return PD_ENONFINITE;
     }
-    if (res <= rtol * beta || st_host[1] == 0.0) break;
+    if (res <= rtol * beta || ((volatile double *)st_host)[1] == 0.0) break;
   }
   hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, p->stream, p->gm, MX, m);
   hipLaunchKernelGGL(combine_kernel, dim3(B), dim3(VB), 0, p->stream, n, m, p->V, p->gm, MX, x);
   PD_HIP_CHECK(hipGetLastError());
   if (iters) *iters = m;
   if (relres) *relres = res / beta;
-  return (res <= rtol * beta || st_host[1] == 0.0) ? PD_OK : PD_ENOTCONV;
+  return (res <= rtol * beta || ((volatile double *)st_host)[1] == 0.0) ? PD_OK : PD_ENOTCONV;
 }
 
 // ---------------------------------------------------------------------------

@@ -84,6 +84,21 @@ struct VecJob {     // one problem's vectors for the batched GMRES kernels
   const double *b;
 };
 
+// Direct global -> LDS load of 16 bytes per lane (gfx950 global_load_lds):
+// lane j of the wave writes lds_base + 16 j; lds_base must be wave-uniform.
+// Completion is tracked by the vector-memory counter (wait with
+// __builtin_amdgcn_s_waitcnt before a barrier).
+__device__ __forceinline__ void pd_lds_dma16(const void *gptr, void *lds_base) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_global_load_lds(gptr, lds_base, 16, 0, 0);
+#endif
+}
+__device__ __forceinline__ void pd_wait_all() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_s_waitcnt(0);
+#endif
+}
+
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
@@ -133,6 +148,8 @@ struct pd_plan_s {
   size_t spec_bytes = 0;
   size_t bytes = 0;            // device bytes this plan allocated
   double *partials = nullptr;  // [tri_G][nbar]
+  double *rstage = nullptr;    // [ceil(G/16)][nbar] reduction slices
+  double *host_dev = nullptr;  // device view of host_pin (kernel-written status)
   int tri_G = 0;
   double *bvec = nullptr, *xvec = nullptr, *wvec = nullptr;
   double *V = nullptr;         // [(maxit+1)][nbar] Krylov basis
@@ -204,7 +221,7 @@ int pd_fft_blocks(pd_plan p);
 int pd_vec_blocks(int n);
 size_t pd_gmres_state_doubles(int maxit);
 int pd_choose_fft_C(int ell, int nbar, int prec, size_t max_lds);
-TriConfig pd_choose_tri(int n, int F2, int prec);
+TriConfig pd_choose_tri(int n, int F2, int prec, size_t max_lds);
 void pd_uniform_factors(const pd_plan p, int MR, std::vector<double> &fac);
 void pd_fft_set_attributes(size_t max_lds);
 void pd_tri_set_attributes(size_t max_lds);

@@ -6,6 +6,7 @@
 // -- and the device workspace of every stage.
 #include "pd_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -65,7 +66,7 @@ pd_status upload(T *dst, const std::vector<T> &src, hipStream_t s) {
 void free_plan(pd_plan p) {
   if (!p) return;
   void *ptrs[] = {p->coef64, p->coef32, p->lam64, p->lam32, p->gB64, p->gJ64, p->tw64,
-                  p->tw32, p->dal, p->fac64, p->fac32, p->twd, p->wreal, p->spec, p->partials, p->bvec, p->xvec, p->wvec, p->V,
+                  p->tw32, p->dal, p->fac64, p->fac32, p->twd, p->wreal, p->spec, p->partials, p->rstage, p->bvec, p->xvec, p->wvec, p->V,
                   p->gm, p->red};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
@@ -81,10 +82,11 @@ std::mutex g_attr_mu;
 // type) of a plan; shared by plan creation and paradiag_plan_bytes.
 struct Layout {
   size_t coef = 0, lam = 0, tw = 0, dal = 0, fac = 0, twd = 0, wreal = 0;
-  size_t spec_bytes = 0, partials = 0, vec = 0, V = 0, gm = 0, red = 0;
+  size_t spec_bytes = 0, partials = 0, rstage = 0, vec = 0, V = 0, gm = 0, red = 0;
   size_t total_bytes() const {
     return coef * 12 + lam * 12 + 2 * lam * 8 + tw * 12 + dal * 8 + fac * 12 + twd * 8 +
-           wreal * 8 + spec_bytes + partials * 8 + 3 * vec * 8 + V * 8 + gm * 8 + red * 8;
+           wreal * 8 + spec_bytes + partials * 8 + rstage * 8 + 3 * vec * 8 + V * 8 + gm * 8 +
+           red * 8;
   }
 };
 
@@ -100,7 +102,7 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
     pd_set_error("time transform tile does not fit in LDS");
     return PD_ENOTSUP;
   }
-  p->tri = pd_choose_tri(n, F2, p->prec);
+  p->tri = pd_choose_tri(n, F2, p->prec, max_lds);
   if (p->dims == 1 && p->tri.lds > max_lds) {
     pd_set_error("shifted-solve tile does not fit in LDS");
     return PD_ENOTSUP;
@@ -108,6 +110,7 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
   const int nitems = (F2 + p->tri.spb - 1) / p->tri.spb;
   p->tri_G = nitems < cus ? nitems : cus;
   L.partials = (size_t)p->tri_G * n;
+  L.rstage = (size_t)((p->tri_G + 15) / 16) * n;
   if (p->dims == 2) {
     p->l2d = pd_choose_line2d(n, F2, p->prec, cus);
     if (p->l2d.lds > max_lds) {
@@ -123,6 +126,7 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
     L.twd = 4 * (size_t)(n + 1);
     L.wreal = (size_t)ell * p->nbar;
     if ((size_t)p->l2d.nkc * p->nbar > L.partials) L.partials = (size_t)p->l2d.nkc * p->nbar;
+    L.rstage = std::max(L.rstage, (size_t)((p->l2d.nkc + 15) / 16) * p->nbar);
   } else if (p->uniform) {
     L.fac = (size_t)F2 * 6 * (p->tri.MR - 1) * 2;
   }
@@ -418,16 +422,22 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   if (p->dims == 2) PD_TRY(dev_alloc(&p->wreal, (size_t)ell * nbar));
   PD_TRY(dev_alloc(reinterpret_cast<unsigned char **>(&p->spec), p->spec_bytes));
   PD_TRY(dev_alloc(&p->partials, L.partials));
+  PD_TRY(dev_alloc(&p->rstage, L.rstage));
   PD_TRY(dev_alloc(&p->bvec, nbar));
   PD_TRY(dev_alloc(&p->xvec, nbar));
   PD_TRY(dev_alloc(&p->wvec, nbar));
   PD_TRY(dev_alloc(&p->V, (size_t)(p->maxit + 1) * nbar));
   PD_TRY(dev_alloc(&p->gm, pd_gmres_state_doubles(p->maxit)));
   PD_TRY(dev_alloc(&p->red, L.red));
+  // small status block written by kernels straight into pinned host memory
   if (hipHostMalloc(reinterpret_cast<void **>(&p->host_pin), 8 * sizeof(double),
-                    hipHostMallocDefault) != hipSuccess) {
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer(reinterpret_cast<void **>(&p->host_dev), p->host_pin, 0) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    if (p->host_pin) (void)hipHostFree(p->host_pin);
     p->host_pin = nullptr;
-    pd_set_error("hipHostMalloc failed");
+    pd_set_error("pinned host allocation failed");
     free_plan(p);
     return PD_ENOMEM;
   }

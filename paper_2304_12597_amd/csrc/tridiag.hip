@@ -23,6 +23,8 @@
 // y_k; 2 accumulates the capacitance product sum_k w gamma_k P_k^{-1} M v.
 #include "pd_partition.h"
 
+#include <algorithm>
+
 namespace {
 
 template <typename R>
@@ -373,15 +375,35 @@ __device__ __forceinline__ void tridiag_uniform_body(
     const cpx<R> ca = {lr * cf.ml + cf.kl, li * cf.ml};   // sub-diagonal
     const cpx<R> cc = {lr * cf.mu + cf.ku, li * cf.mu};   // super-diagonal
 
+    // gather this system's right-hand side: all loads first, then the LDS
+    // stores, so the HBM latencies overlap
     __syncthreads();   // previous users of stage / lfac are done
     for (int idx = lt; idx < NF; idx += P) lfac[idx] = fac[(size_t)k * NF + idx];
     if constexpr (MODE != 2) {
       const cpx<R> *src = in + (size_t)k * n;
-      for (int idx = lt; idx < sstride; idx += P) {
-        int i = idx - 1;
-        cpx<R> v = zero;
-        if (active && i >= 0 && i < n) v = src[i];
-        stage[idx] = v;
+      if (sizeof(cpx<R>) == 16 && P >= 64) {
+        // complex128, whole waves per system: DMA the right-hand side
+        // straight into LDS (global_load_lds, 16 bytes per lane, lane j of a
+        // wave lands at base + 16 j); every load is in flight at once and no
+        // registers are used.  Rows >= n read a valid element and are zeroed
+        // below.
+        const int wb = lt & ~63, lane = lt & 63;
+#pragma unroll
+        for (int q = 0; q < MR; ++q) {
+          const int i0 = q * P + wb;
+          int i = i0 + lane;
+          i = i < n ? i : n - 1;
+          pd_lds_dma16(src + i, stage + 1 + i0);
+        }
+        pd_wait_all();
+        __syncthreads();
+        if (lt == 0) stage[0] = zero;
+        for (int i = n + lt; i < sstride - 1; i += P) stage[1 + i] = zero;
+      } else {
+        for (int idx = lt; idx < sstride; idx += P) {
+          const int i = idx - 1;
+          stage[idx] = (active && i >= 0 && i < n) ? src[i] : zero;
+        }
       }
     }
     __syncthreads();
@@ -460,14 +482,30 @@ tridiag_uniform_kernel(int n, int F2, int P, int spb, int nitems, Coef<R> cf,
                                     partials);
 }
 
+// Sum of G partial rows in two deterministic stages: blockIdx.y picks a slice
+// of RS rows (summed in order into stage[slice][i]), then a second kernel
+// adds the slices in order.  Enough blocks are in flight to hide latency.
+constexpr int RS = 16;
+__global__ void reduce_slices_kernel(int n, int G, const double *__restrict__ partials,
+                                     double *__restrict__ stage) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int g0 = blockIdx.y * RS;
+  const int g1 = g0 + RS < G ? g0 + RS : G;
+  double s = 0.0;
+#pragma unroll 4
+  for (int g = g0; g < g1; ++g) s += partials[(size_t)g * n + i];
+  stage[(size_t)blockIdx.y * n + i] = s;
+}
+
 __global__ void reduce_partials_kernel(int n, int G, const double *__restrict__ partials,
                                        const double *__restrict__ base,
                                        double *__restrict__ out) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double s = base ? base[i] : 0.0;
+  double s = 0.0;
   for (int g = 0; g < G; ++g) s += partials[(size_t)g * n + i];
-  out[i] = s;
+  out[i] = (base ? base[i] : 0.0) + s;
 }
 
 template <typename R, int MR, bool UNI>
@@ -523,7 +561,7 @@ pd_status launch_mr(pd_plan p, int mode, const void *in, const double *xv, void 
 
 // Pick (P, MR, systems per block) for n rows: MR rows per thread, P a power of
 // two with P*MR >= n.
-TriConfig pd_choose_tri(int n, int F2, int prec) {
+TriConfig pd_choose_tri(int n, int F2, int prec, size_t max_lds) {
   TriConfig T;
   const size_t cb = (prec == PD_FP64) ? 16 : 8;
   int MR = 8;
@@ -536,17 +574,19 @@ TriConfig pd_choose_tri(int n, int F2, int prec) {
   // every block has 1024 threads: 1024/P systems per block.  Batched
   // launches use the same packing, so the order of the float64 sums over
   // frequencies -- and hence every result -- is the same alone and in a batch.
-  const int spb = (P >= 16) ? 1024 / P : 64;   // tiny systems: 64 per block
+  int spb = (P >= 16) ? 1024 / P : 64;   // tiny systems: 64 per block
+  auto lds_for = [&](int s) {
+    const size_t rows = (size_t)P * MR;
+    size_t region = (size_t)s * (rows + 2) * cb;
+    region = std::max(region, (size_t)s * rows * sizeof(double));
+    region = std::max(region, (size_t)s * P * 3 * cb);
+    region = (region + 15) & ~(size_t)15;
+    return region + (size_t)s * 6 * (MR - 1) * cb;
+  };
+  while (spb > 1 && lds_for(spb) > max_lds) spb /= 2;
   T.spb = spb;
   T.block = P * spb;
-  const size_t rows = (size_t)P * MR;
-  size_t region = (size_t)spb * (rows + 2) * cb;           // staging
-  const size_t accb = (size_t)spb * rows * sizeof(double);  // partial sums
-  const size_t xb = (size_t)spb * P * 3 * cb;              // PCR exchange
-  if (accb > region) region = accb;
-  if (xb > region) region = xb;
-  region = (region + 15) & ~(size_t)15;
-  T.lds = region + (size_t)spb * 6 * (MR - 1) * cb;        // + factor table
+  T.lds = lds_for(spb);   // staging / partial sums / PCR exchange + factor table
   return T;
 }
 
@@ -590,8 +630,16 @@ pd_status pd_launch_reduce_partials(pd_plan p, const double *base, double *out) 
   const int nitems = (p->F2 + p->tri.spb - 1) / p->tri.spb;
   int G = nitems < p->tri_G ? nitems : p->tri_G;
   if (p->dims == 2) G = p->l2d.nkc;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3((n + 255) / 256), dim3(256), 0, p->stream,
-                     n, G, p->partials, base, out);
+  if (G > RS) {
+    const int slices = (G + RS - 1) / RS;
+    hipLaunchKernelGGL(reduce_slices_kernel, dim3((n + 255) / 256, slices), dim3(256), 0,
+                       p->stream, n, G, p->partials, p->rstage);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((n + 255) / 256), dim3(256), 0, p->stream,
+                       n, slices, p->rstage, base, out);
+  } else {
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((n + 255) / 256), dim3(256), 0, p->stream,
+                       n, G, p->partials, base, out);
+  }
   PD_HIP_CHECK(hipGetLastError());
   return PD_OK;
 }
@@ -655,10 +703,20 @@ __global__ void reduce_batch_kernel(const VecJob *__restrict__ jobs, const int2 
   const VecJob &j = jobs[m.x];
   const int i = m.y * blockDim.x + threadIdx.x;
   if (i >= j.n) return;
-  double s = (base_j >= 0) ? j.V[(size_t)base_j * j.n + i] : 0.0;
-  for (int g = 0; g < j.G; ++g) s += j.partials[(size_t)g * j.n + i];
-  if (base_j >= 0) j.w[i] = s;
-  else j.bout[i] = s;
+  // the same summation order as the single-problem two-stage reduction
+  double s = 0.0;
+  if (j.G > RS) {
+    for (int g0 = 0; g0 < j.G; g0 += RS) {
+      const int g1 = g0 + RS < j.G ? g0 + RS : j.G;
+      double t = 0.0;
+      for (int g = g0; g < g1; ++g) t += j.partials[(size_t)g * j.n + i];
+      s += t;
+    }
+  } else {
+    for (int g = 0; g < j.G; ++g) s += j.partials[(size_t)g * j.n + i];
+  }
+  if (base_j >= 0) j.w[i] = j.V[(size_t)base_j * j.n + i] + s;
+  else j.bout[i] = 0.0 + s;
 }
 }  // namespace
 

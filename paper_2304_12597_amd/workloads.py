@@ -128,10 +128,10 @@ def _source_1d(x: np.ndarray, ell: int, tau: float, a: np.ndarray,
                b: np.ndarray) -> np.ndarray:
     """f(x, t_j) = sum_{k=1..16} a_k sin(k pi x) cos(b_k t_j), j = 1..ell."""
     t = tau * np.arange(1, ell + 1, dtype=np.float64)
-    F = np.zeros((ell, x.size), dtype=np.float64)
-    for k in range(1, a.size + 1):
-        F += np.outer(a[k - 1] * np.cos(b[k - 1] * t), np.sin(k * np.pi * x))
-    return F
+    k = np.arange(1, a.size + 1, dtype=np.float64)
+    amp = a[None, :] * np.cos(np.outer(t, b))        # [ell, K]
+    modes = np.sin(np.outer(k, np.pi * x))            # [K, n]
+    return amp @ modes
 
 
 def heat_1d(kind: str, n: int, ell: int, T: float, nu: float,
