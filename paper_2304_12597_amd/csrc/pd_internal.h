@@ -45,6 +45,13 @@ __device__ __forceinline__ cpx<R> crecip(cpx<R> a) {
 }
 template <typename R>
 __device__ __forceinline__ cpx<R> cneg(cpx<R> a) { return {-a.re, -a.im}; }
+// c ? a : b, one component at a time (a select of whole structs can end up as
+// a select of stack addresses)
+__device__ __forceinline__ double pd_sel(bool c, double a, double b) { return c ? a : b; }
+template <typename R>
+__device__ __forceinline__ cpx<R> pd_sel(bool c, cpx<R> a, cpx<R> b) {
+  return cpx<R>{c ? a.re : b.re, c ? a.im : b.im};
+}
 // multiply by -i (forward) or +i (inverse)
 template <typename R, bool INV>
 __device__ __forceinline__ cpx<R> cmul_mi(cpx<R> a) {

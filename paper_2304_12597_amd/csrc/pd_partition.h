@@ -63,7 +63,11 @@ __device__ __forceinline__ void partition_solve(cpx<R> (&d)[MR], int len, int lt
   __syncthreads();   // staging area -> exchange area
   xch[lt] = Row3<R>{ua, uc, ud};
   __syncthreads();
-  const Row3<R> nx = (lt + 1 < P) ? xch[lt + 1] : Row3<R>{zero, zero, zero};
+  Row3<R> nx = xch[lt + 1 < P ? lt + 1 : lt];
+  const bool hasnx = lt + 1 < P;
+  nx.a = pd_sel(hasnx, nx.a, zero);
+  nx.c = pd_sel(hasnx, nx.c, zero);
+  nx.d = pd_sel(hasnx, nx.d, zero);
   cpx<R> al = cneg(cmul(Ae, ua));
   cpx<R> be = csub(csub(cpx<R>{R(1), R(0)}, cmul(Ae, uc)), cmul(Ce, nx.a));
   cpx<R> ga = cneg(cmul(Ce, nx.c));
@@ -78,8 +82,11 @@ __device__ __forceinline__ void partition_solve(cpx<R> (&d)[MR], int len, int lt
     __syncthreads();
     xch[lt] = Row3<R>{al, ga, de};
     __syncthreads();
-    const Row3<R> lo = (lt >= st) ? xch[lt - st] : Row3<R>{zero, zero, zero};
-    const Row3<R> hi = (lt + st < P) ? xch[lt + st] : Row3<R>{zero, zero, zero};
+    Row3<R> lo = xch[lt >= st ? lt - st : lt];
+    Row3<R> hi = xch[lt + st < P ? lt + st : lt];
+    const bool haslo = lt >= st, hashi = lt + st < P;
+    lo.a = pd_sel(haslo, lo.a, zero); lo.c = pd_sel(haslo, lo.c, zero); lo.d = pd_sel(haslo, lo.d, zero);
+    hi.a = pd_sel(hashi, hi.a, zero); hi.c = pd_sel(hashi, hi.c, zero); hi.d = pd_sel(hashi, hi.d, zero);
     const cpx<R> nb = csub(csub(cpx<R>{R(1), R(0)}, cmul(al, lo.c)), cmul(ga, hi.a));
     const cpx<R> nd = csub(csub(de, cmul(al, lo.d)), cmul(ga, hi.d));
     const cpx<R> na = cneg(cmul(al, lo.a));
@@ -89,11 +96,11 @@ __device__ __forceinline__ void partition_solve(cpx<R> (&d)[MR], int len, int lt
     ga = cmul(ng, rb);
     de = cmul(nd, rb);
   }
-  const cpx<R> xe = (len >= 2) ? de : zero;
+  const cpx<R> xe = pd_sel(len >= 2, de, zero);
   __syncthreads();
   xch[lt].d = xe;
   __syncthreads();
-  const cpx<R> xprev = (lt > 0) ? xch[lt - 1].d : zero;
+  const cpx<R> xprev = pd_sel(lt > 0, xch[lt > 0 ? lt - 1 : 0].d, zero);
   const cpx<R> xs = csub(csub(ud, cmul(ua, xprev)), cmul(uc, xe));
   cpx<R> ynext = xe;
 #pragma unroll

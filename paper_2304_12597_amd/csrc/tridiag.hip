@@ -27,6 +27,55 @@
 
 namespace {
 
+// dst[idx] = cvt(src[idx - 1]) for idx = lt, lt + P, ... < count, zero where
+// idx - 1 lies outside [0, n) or when !on.  Each thread issues U loads (at
+// clamped, always valid addresses) before its first store, so their
+// latencies overlap instead of adding up.
+template <int U, typename T, typename S, typename Cvt>
+__device__ __forceinline__ void stage_halo(T *dst, const S *__restrict__ src, int count, int n,
+                                           int lt, int P, bool on, T zero, Cvt cvt) {
+  for (int b = lt; b < count; b += U * P) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = b + u * P - 1;
+      const int ic = i < 0 ? 0 : (i < n ? i : n - 1);
+      const T t = cvt(src[ic]);
+      v[u] = pd_sel(on && i >= 0 && i < n, t, zero);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (b + u * P < count) dst[b + u * P] = v[u];
+  }
+}
+
+// mx[q] = -w (M x)_{s0+q} in float64, rounded once to R (zero past row n-1).
+// x is staged with a zero halo through sx (count >= n + 2 doubles of this
+// thread group's LDS); M's rows come from coef64 = [ML | MD | MU | ...].
+// Contains a block barrier.
+template <typename R, int MR, bool UNI>
+__device__ __forceinline__ void minus_w_mx(R (&mx)[MR], double *sx, int count,
+                                           const double *__restrict__ coef64,
+                                           const double *__restrict__ xv, double w, int n,
+                                           int s0, int lt, int P) {
+  stage_halo<8>(sx, xv != nullptr ? xv : coef64, count, n, lt, P, xv != nullptr, 0.0,
+                [](double v) { return v; });
+  __syncthreads();
+  const double ml0 = coef64[n - 1 > 0 ? n - 1 : 0], md0 = coef64[n], mu0 = coef64[2 * n];
+#pragma unroll
+  for (int q = 0; q < MR; ++q) {
+    const int i = s0 + q;
+    const int ic = i < n ? i : n - 1;
+    const double md = UNI ? md0 : coef64[n + ic];
+    const double ml = UNI ? ml0 : coef64[ic];
+    const double mu = UNI ? mu0 : coef64[2 * n + ic];
+    double v = md * sx[ic + 1];
+    v += ((ic > 0) ? ml : 0.0) * sx[ic];
+    v += ((ic < n - 1) ? mu : 0.0) * sx[ic + 2];
+    mx[q] = (i < n) ? (R)(-w * v) : R(0);
+  }
+}
+
 template <typename R>
 struct Coef {
   const R *ML, *MD, *MU, *KL, *KD, *KU;   // per-row coefficients
@@ -46,9 +95,9 @@ __device__ __forceinline__ void prow(const Coef<R> &cf, int i, int n, R lr, R li
     } else {
       ml = cf.ML[i]; md = cf.MD[i]; mu = cf.MU[i]; kl = cf.KL[i]; kd = cf.KD[i]; ku = cf.KU[i];
     }
-    a = (i > 0) ? cpx<R>{lr * ml + kl, li * ml} : cpx<R>{R(0), R(0)};
+    a = pd_sel(i > 0, cpx<R>{lr * ml + kl, li * ml}, cpx<R>{R(0), R(0)});
     b = cpx<R>{lr * md + kd, li * md};
-    c = (i < n - 1) ? cpx<R>{lr * mu + ku, li * mu} : cpx<R>{R(0), R(0)};
+    c = pd_sel(i < n - 1, cpx<R>{lr * mu + ku, li * mu}, cpx<R>{R(0), R(0)});
   } else {
     a = cpx<R>{R(0), R(0)};
     b = cpx<R>{R(1), R(0)};
@@ -82,27 +131,15 @@ tridiag_kernel(int n, int F2, int P, int spb, int nitems, Coef<R> cf,
 #pragma unroll
     for (int q = 0; q < MR; ++q) acc[q] = 0.0;
   } else {
-    // -w M x, the same for every frequency (float64, rounded once)
-#pragma unroll
-    for (int q = 0; q < MR; ++q) {
-      int i = s0 + q;
-      double v = 0.0;
-      if (xv != nullptr && i < n) {
-        v = coef64[n + i] * xv[i];
-        if (i > 0) v += coef64[i] * xv[i - 1];
-        if (i < n - 1) v += coef64[2 * n + i] * xv[i + 1];
-      }
-      mx[q] = (R)(-wscale * v);
-    }
+    // -w M x, the same for every frequency
+    minus_w_mx<R, MR, false>(mx, reinterpret_cast<double *>(stage), sstride, coef64, xv, wscale,
+                             n, s0, lt, P);
   }
   R dv[(MODE == 2) ? MR : 1];
   if constexpr (MODE == 2) {
     // M v is the same for all frequencies: form it once, in registers.
-    for (int idx = lt; idx < sstride; idx += P) {
-      int i = idx - 1;
-      R v = (i >= 0 && i < n) ? (R)vin[i] : R(0);
-      stage[idx] = cpx<R>{v, R(0)};
-    }
+    stage_halo<8>(stage, vin, sstride, n, lt, P, true, cpx<R>{R(0), R(0)},
+                  [](double v) { return cpx<R>{(R)v, R(0)}; });
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < MR; ++q) {
@@ -124,15 +161,9 @@ tridiag_kernel(int n, int F2, int P, int spb, int nitems, Coef<R> cf,
     const R lr = lam[2 * k], li = lam[2 * k + 1];
 
     __syncthreads();   // previous users of the staging / exchange area are done
-    if constexpr (MODE != 2) {
-      const cpx<R> *src = in + (size_t)k * n;
-      for (int idx = lt; idx < sstride; idx += P) {
-        int i = idx - 1;
-        cpx<R> v = {R(0), R(0)};
-        if (active && i >= 0 && i < n) v = src[i];
-        stage[idx] = v;
-      }
-    }
+    if constexpr (MODE != 2)
+      stage_halo<8>(stage, in + (size_t)k * n, sstride, n, lt, P, active, cpx<R>{R(0), R(0)},
+                    [](cpx<R> v) { return v; });
     __syncthreads();
 
     // right-hand side d = M r (- w M x)
@@ -242,7 +273,7 @@ tridiag_kernel(int n, int F2, int P, int spb, int nitems, Coef<R> cf,
     __syncthreads();
     xch[lt].d = xe;
     __syncthreads();
-    cpx<R> xprev = (lt > 0) ? xch[lt - 1].d : cpx<R>{R(0), R(0)};
+    cpx<R> xprev = pd_sel(lt > 0, xch[lt > 0 ? lt - 1 : 0].d, cpx<R>{R(0), R(0)});
     const cpx<R> xs = csub(csub(ud, cmul(ua, xprev)), cmul(uc, xe));
 
     // 3. back substitution of the interior rows
@@ -260,6 +291,7 @@ tridiag_kernel(int n, int F2, int P, int spb, int nitems, Coef<R> cf,
       __syncthreads();
       if (active) {
         cpx<R> *dst = out + (size_t)k * n;
+#pragma unroll 4
         for (int i = lt; i < n; i += P) dst[i] = stage[1 + i];
       }
     } else {
@@ -326,6 +358,7 @@ __device__ __forceinline__ void tridiag_uniform_body(
   if (accb > region) region = accb;
   region = (region + 15) & ~(size_t)15;
   cpx<R> *lfac = reinterpret_cast<cpx<R> *>(smem_raw + region) + (size_t)g * NF;
+  (void)xb;
   const int s0 = lt * MR;
   int len = n - s0;
   len = len < 0 ? 0 : (len > MR ? MR : len);
@@ -336,27 +369,15 @@ __device__ __forceinline__ void tridiag_uniform_body(
 #pragma unroll
     for (int q = 0; q < MR; ++q) acc[q] = 0.0;
   } else {
-    // -w M x, the same for every frequency (float64, rounded once)
-#pragma unroll
-    for (int q = 0; q < MR; ++q) {
-      int i = s0 + q;
-      double v = 0.0;
-      if (xv != nullptr && q < len) {
-        v = coef64[n + i] * xv[i];
-        if (i > 0) v += coef64[i] * xv[i - 1];
-        if (i < n - 1) v += coef64[2 * n + i] * xv[i + 1];
-      }
-      mx[q] = (R)(-wscale * v);
-    }
+    // -w M x, the same for every frequency
+    minus_w_mx<R, MR, true>(mx, reinterpret_cast<double *>(stage), sstride, coef64, xv, wscale,
+                            n, s0, lt, P);
   }
   R dv[(MODE == 2) ? MR : 1];
   if constexpr (MODE == 2) {
     // M v is the same for all frequencies: form it once, in registers.
-    for (int idx = lt; idx < sstride; idx += P) {
-      int i = idx - 1;
-      R v = (i >= 0 && i < n) ? (R)vin[i] : R(0);
-      stage[idx] = cpx<R>{v, R(0)};
-    }
+    stage_halo<8>(stage, vin, sstride, n, lt, P, true, cpx<R>{R(0), R(0)},
+                  [](double v) { return cpx<R>{(R)v, R(0)}; });
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < MR; ++q) {
@@ -400,10 +421,7 @@ __device__ __forceinline__ void tridiag_uniform_body(
         if (lt == 0) stage[0] = zero;
         for (int i = n + lt; i < sstride - 1; i += P) stage[1 + i] = zero;
       } else {
-        for (int idx = lt; idx < sstride; idx += P) {
-          const int i = idx - 1;
-          stage[idx] = (active && i >= 0 && i < n) ? src[i] : zero;
-        }
+        stage_halo<8>(stage, src, sstride, n, lt, P, active, zero, [](cpx<R> v) { return v; });
       }
     }
     __syncthreads();
@@ -439,6 +457,7 @@ __device__ __forceinline__ void tridiag_uniform_body(
       __syncthreads();
       if (active) {
         cpx<R> *dst = out + (size_t)k * n;
+#pragma unroll 4
         for (int i = lt; i < n; i += P) dst[i] = stage[1 + i];
       }
     } else {
@@ -469,8 +488,8 @@ __device__ __forceinline__ void tridiag_uniform_body(
 // Uniform-coefficient fast path (constant diagonals: uniform grids).  The
 // elimination factors are precomputed per plan (pd_partition.h); rows >= n
 // are absent, so the last chunk may be ragged and chunks past the end empty.
-template <typename R, int MR, int MODE>
-__global__ void __launch_bounds__(1024)
+template <typename R, int MR, int MODE, int MAXT>
+__global__ void __launch_bounds__(MAXT)
 tridiag_uniform_kernel(int n, int F2, int P, int spb, int nitems, Coef<R> cf,
                        const double *__restrict__ coef64, const R *__restrict__ lam,
                        const cpx<R> *__restrict__ fac, const double *__restrict__ gw,
@@ -540,8 +559,12 @@ pd_status launch_mr(pd_plan p, int mode, const void *in, const double *xv, void 
   double *part = (mode == 1) ? nullptr : p->partials;
 #define PD_TRI_LAUNCH(M)                                                                     \
   do {                                                                                       \
-    if (UNI)                                                                                 \
-      hipLaunchKernelGGL((tridiag_uniform_kernel<R, MR, M>), dim3(G), dim3(T.block), T.lds,  \
+    if (UNI && T.block <= 512)                                                               \
+      hipLaunchKernelGGL((tridiag_uniform_kernel<R, MR, M, 512>), dim3(G), dim3(T.block),    \
+                         T.lds, p->stream, n, p->F2, T.P, T.spb, nitems, cf, p->coef64,       \
+                         lam, fac, gw, cin, vin, x, p->w, has_mass, o, part);                \
+    else if (UNI)                                                                            \
+      hipLaunchKernelGGL((tridiag_uniform_kernel<R, MR, M, 1024>), dim3(G), dim3(T.block), T.lds,\
                          p->stream, n, p->F2, T.P, T.spb, nitems, cf, p->coef64, lam, fac,   \
                          gw, cin, vin, x, p->w, has_mass, o, part);                          \
     else                                                                                     \
@@ -565,7 +588,10 @@ TriConfig pd_choose_tri(int n, int F2, int prec, size_t max_lds) {
   TriConfig T;
   const size_t cb = (prec == PD_FP64) ? 16 : 8;
   int MR = 8;
-  if (prec != PD_FP64 && n > 8192) MR = 16;
+  if (n > 8192) MR = 16;
+  // complex128 above 4096 rows: 16 rows per thread, 512-thread blocks (a
+  // 256-register budget, no spills) and an un-aliased PCR exchange area
+  if (prec == PD_FP64 && n > 4096) MR = 16;
   if (n <= 64) MR = 4;
   int P = 1;
   while (P * MR < n) P *= 2;
@@ -575,6 +601,7 @@ TriConfig pd_choose_tri(int n, int F2, int prec, size_t max_lds) {
   // launches use the same packing, so the order of the float64 sums over
   // frequencies -- and hence every result -- is the same alone and in a batch.
   int spb = (P >= 16) ? 1024 / P : 64;   // tiny systems: 64 per block
+  if (prec == PD_FP64 && MR == 16) spb = 1;
   auto lds_for = [&](int s) {
     const size_t rows = (size_t)P * MR;
     size_t region = (size_t)s * (rows + 2) * cb;
@@ -596,6 +623,7 @@ pd_status dispatch(pd_plan p, int mode, const void *in, const double *xv, void *
   if (p->prec == PD_FP64) {
     if (MR == 4) return launch_mr<double, 4, UNI>(p, mode, in, xv, out);
     if (MR == 8) return launch_mr<double, 8, UNI>(p, mode, in, xv, out);
+    if (MR == 16) return launch_mr<double, 16, UNI>(p, mode, in, xv, out);
   } else {
     if (MR == 4) return launch_mr<float, 4, UNI>(p, mode, in, xv, out);
     if (MR == 8) return launch_mr<float, 8, UNI>(p, mode, in, xv, out);
@@ -653,12 +681,15 @@ pd_status pd_capacitance_apply_impl(pd_plan p, const double *v, double *Jv) {
 namespace {
 template <typename R, int MR>
 void set_attr_mr(int v) {
-  const void *fns[6] = {reinterpret_cast<const void *>(&tridiag_kernel<R, MR, 0>),
+  const void *fns[9] = {reinterpret_cast<const void *>(&tridiag_kernel<R, MR, 0>),
                         reinterpret_cast<const void *>(&tridiag_kernel<R, MR, 1>),
                         reinterpret_cast<const void *>(&tridiag_kernel<R, MR, 2>),
-                        reinterpret_cast<const void *>(&tridiag_uniform_kernel<R, MR, 0>),
-                        reinterpret_cast<const void *>(&tridiag_uniform_kernel<R, MR, 1>),
-                        reinterpret_cast<const void *>(&tridiag_uniform_kernel<R, MR, 2>)};
+                        reinterpret_cast<const void *>(&tridiag_uniform_kernel<R, MR, 0, 1024>),
+                        reinterpret_cast<const void *>(&tridiag_uniform_kernel<R, MR, 1, 1024>),
+                        reinterpret_cast<const void *>(&tridiag_uniform_kernel<R, MR, 2, 1024>),
+                        reinterpret_cast<const void *>(&tridiag_uniform_kernel<R, MR, 0, 512>),
+                        reinterpret_cast<const void *>(&tridiag_uniform_kernel<R, MR, 1, 512>),
+                        reinterpret_cast<const void *>(&tridiag_uniform_kernel<R, MR, 2, 512>)};
   for (const void *f : fns)
     pd_set_max_lds(f, v);
 }
@@ -668,6 +699,7 @@ void pd_tri_set_attributes(size_t max_lds) {
   const int v = (int)max_lds;
   set_attr_mr<double, 4>(v);
   set_attr_mr<double, 8>(v);
+  set_attr_mr<double, 16>(v);
   set_attr_mr<float, 4>(v);
   set_attr_mr<float, 8>(v);
   set_attr_mr<float, 16>(v);
