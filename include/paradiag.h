@@ -114,7 +114,7 @@ pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double tau,
 /* Algorithm 1 end to end: U = solution of the all-at-once system for
  * initial value u0 [nbar] and nodal source F [ell][nbar] (device float64),
  * written to U [ell][nbar] (device float64, must not alias u0 or F).
- * tol: the capacitance GMRES stops at residual <= tol/10 * ||b||; PD_MIXED
+ * tol: the capacitance GMRES stops at residual <= tol/100 * ||b||; PD_MIXED
  * refines until the float64 relative all-at-once residual is <= tol.
  * info may be NULL.  Synchronises the plan's stream. */
 pd_status paradiag_solve(pd_plan plan, const double *u0, const double *F,
@@ -152,9 +152,10 @@ pd_status paradiag_forward_transform(pd_plan plan, const double *u0,
  * for k = 0..ell/2,  Y_k = P_k^{-1} M (Hhat_k - w x),  w = alpha^(1/ell),
  * P_k = (1 - pi_k) M + tau K.  x may be NULL (= 0).
  * If Uhat != NULL, Y is written there (Uhat may equal Hhat).
- * If b != NULL, b = sum over the full spectrum k = 0..ell-1 of gamma_k Y_k
- * (real, float64), the conjugate half being implied (Section 2, b = L F^{-T}
- * e_ell).  At least one of Uhat, b must be non-NULL. */
+ * If b != NULL, b = sum over the full spectrum k = 0..ell-1 of
+ * gamma_k P_k^{-1} M Hhat_k (real, float64; x does not enter b), the
+ * conjugate half being implied (Section 2, b = L F^{-T} e_ell).  At least one
+ * of Uhat, b must be non-NULL. */
 pd_status paradiag_shifted_solve(pd_plan plan, const void *Hhat,
                                  const double *x, void *Uhat, double *b);
 

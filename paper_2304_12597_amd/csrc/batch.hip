@@ -19,7 +19,7 @@ bool batchable(const pd_plan *plans, int count) {
   for (int i = 0; i < count; ++i) {
     const pd_plan p = plans[i];
     if (!p || p->dims != 1 || !p->uniform || p->prec != p0->prec || p->prec == PD_MIXED ||
-        p->tri.block != 1024 ||
+        p->tri.block != pd_tri_block_threads(p->prec) ||
         p->maxit != p0->maxit)
       return false;
     for (int j = 0; j < i; ++j)
@@ -71,8 +71,9 @@ pd_status pd_solve_batch_impl(const pd_plan *plans, int count, const double *con
 
     TriJob &t = tj[i];
     const int P = p->tri.P;
-    if (P > 1024) return PD_ENOTSUP;
-    t.n = p->n; t.F2 = p->F2; t.P = P; t.spb = 1024 / P;
+    const int BT = pd_tri_block_threads(prec);
+    if (P > BT) return PD_ENOTSUP;
+    t.n = p->n; t.F2 = p->F2; t.P = P; t.spb = BT / P;
     t.nitems = (p->F2 + t.spb - 1) / t.spb;
     t.nblk = std::min(t.nitems, p->tri_G);
     t.has_mass = 0;
@@ -188,7 +189,7 @@ pd_status pd_solve_batch_impl(const pd_plan *plans, int count, const double *con
     act[i] = beta[i] > 0.0;
     nact += act[i];
   }
-  const double rtol = tol * 0.1;
+  const double rtol = tol * PD_GMRES_TOL_FACTOR;
   for (int j = 0; j < MX && nact > 0; ++j) {
     PD_HIP_CHECK(hipMemcpyAsync(d_act, act.data(), count * sizeof(int), hipMemcpyHostToDevice, s));
     PD_B(pd_launch_tridiag_batch(prec, MR, 2, d_tjJ, d_t0, n0, tri_lds, d_act, j, s));

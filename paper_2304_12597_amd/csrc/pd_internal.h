@@ -58,6 +58,11 @@ __device__ __forceinline__ cpx<R> cmul_mi(cpx<R> a) {
   return INV ? cpx<R>{-a.im, a.re} : cpx<R>{a.im, -a.re};
 }
 
+// The capacitance GMRES stops at residual <= PD_GMRES_TOL_FACTOR * tol * ||b||:
+// the error in x reaches U through the shifted solves of the last pass, which
+// amplify it on ill-conditioned problems (small diffusion, long horizons).
+constexpr double PD_GMRES_TOL_FACTOR = 1e-2;
+
 // ---------------------------------------------------------------------------
 // batched launches: one entry per problem, a block map (problem, local block)
 // ---------------------------------------------------------------------------
@@ -228,6 +233,9 @@ int pd_fft_blocks(pd_plan p);
 int pd_vec_blocks(int n);
 size_t pd_gmres_state_doubles(int maxit);
 int pd_choose_fft_C(int ell, int nbar, int prec, size_t max_lds);
+// Threads per shifted-solve block: 512 for complex128 (a 256-register budget
+// per thread keeps the partition solve out of scratch), 1024 otherwise.
+inline int pd_tri_block_threads(int prec) { return prec == PD_FP64 ? 512 : 1024; }
 TriConfig pd_choose_tri(int n, int F2, int prec, size_t max_lds);
 void pd_uniform_factors(const pd_plan p, int MR, std::vector<double> &fac);
 void pd_fft_set_attributes(size_t max_lds);

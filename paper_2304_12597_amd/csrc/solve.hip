@@ -47,7 +47,7 @@ pd_status sweep_tail(pd_plan p, double *U, double tol, int has_mass, int accumul
   if (st != PD_OK) return st;
   int its = 0;
   double rr = 0.0;
-  *gm_status = pd_gmres(p, p->bvec, p->xvec, tol * 0.1, &its, &rr);
+  *gm_status = pd_gmres(p, p->bvec, p->xvec, tol * PD_GMRES_TOL_FACTOR, &its, &rr);
   if (*gm_status != PD_OK && *gm_status != PD_ENOTCONV) return *gm_status;
   st = pd_launch_tridiag(p, 1 | mflag, p->spec, p->xvec, p->spec);
   if (st != PD_OK) return st;

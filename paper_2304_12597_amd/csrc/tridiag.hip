@@ -589,19 +589,19 @@ TriConfig pd_choose_tri(int n, int F2, int prec, size_t max_lds) {
   const size_t cb = (prec == PD_FP64) ? 16 : 8;
   int MR = 8;
   if (n > 8192) MR = 16;
-  // complex128 above 4096 rows: 16 rows per thread, 512-thread blocks (a
-  // 256-register budget, no spills) and an un-aliased PCR exchange area
+  // complex128 above 4096 rows: 16 rows per thread, one system per block
   if (prec == PD_FP64 && n > 4096) MR = 16;
   if (n <= 64) MR = 4;
   int P = 1;
   while (P * MR < n) P *= 2;
   T.P = P;
   T.MR = MR;
-  // every block has 1024 threads: 1024/P systems per block.  Batched
-  // launches use the same packing, so the order of the float64 sums over
-  // frequencies -- and hence every result -- is the same alone and in a batch.
-  int spb = (P >= 16) ? 1024 / P : 64;   // tiny systems: 64 per block
-  if (prec == PD_FP64 && MR == 16) spb = 1;
+  // every block has BT threads: BT/P systems per block.  Batched launches use
+  // the same packing, so the order of the float64 sums over frequencies --
+  // and hence every result -- is the same alone and in a batch.
+  const int BT = pd_tri_block_threads(prec);
+  int spb = (P >= 16) ? BT / P : 64;   // tiny systems: 64 per block
+  if (spb < 1) spb = 1;
   auto lds_for = [&](int s) {
     const size_t rows = (size_t)P * MR;
     size_t region = (size_t)s * (rows + 2) * cb;
@@ -706,8 +706,8 @@ void pd_tri_set_attributes(size_t max_lds) {
 }
 
 namespace {
-template <typename R, int MR, int MODE>
-__global__ void __launch_bounds__(1024)
+template <typename R, int MR, int MODE, int MAXT>
+__global__ void __launch_bounds__(MAXT)
 tridiag_batch_kernel(const TriJob *__restrict__ jobs, const int2 *__restrict__ map,
                      const int *__restrict__ active, int jv) {
   const int2 m = map[blockIdx.x];
@@ -756,9 +756,10 @@ pd_status pd_launch_tridiag_batch(int prec, int MR, int mode, const TriJob *jobs
                                   int nblocks, size_t lds, const int *active, int jv,
                                   hipStream_t s) {
   if (nblocks == 0) return PD_OK;
-#define PD_TB(R, MRV, M)                                                                   \
-  hipLaunchKernelGGL((tridiag_batch_kernel<R, MRV, M>), dim3(nblocks), dim3(1024), lds, s, \
-                     jobs, map, active, jv)
+#define PD_TB(R, MRV, M)                                                                  \
+  hipLaunchKernelGGL((tridiag_batch_kernel<R, MRV, M, (sizeof(R) == 8 ? 512 : 1024)>),      \
+                     dim3(nblocks), dim3(sizeof(R) == 8 ? 512 : 1024), lds, s, jobs, map,  \
+                     active, jv)
 #define PD_TB_MODES(R, MRV)          \
   do {                               \
     if (mode == 0) PD_TB(R, MRV, 0); \
@@ -793,21 +794,21 @@ pd_status pd_launch_reduce_batch(const VecJob *jobs, const int2 *map, int nblock
 void pd_tri_batch_set_attributes(size_t max_lds) {
   const int v = (int)max_lds;
   const void *fns[] = {
-      reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 4, 0>),
-      reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 4, 1>),
-      reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 4, 2>),
-      reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 8, 0>),
-      reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 8, 1>),
-      reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 8, 2>),
-      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 4, 0>),
-      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 4, 1>),
-      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 4, 2>),
-      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 8, 0>),
-      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 8, 1>),
-      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 8, 2>),
-      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 16, 0>),
-      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 16, 1>),
-      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 16, 2>)};
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 4, 0, 512>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 4, 1, 512>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 4, 2, 512>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 8, 0, 512>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 8, 1, 512>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 8, 2, 512>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 4, 0, 1024>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 4, 1, 1024>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 4, 2, 1024>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 8, 0, 1024>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 8, 1, 1024>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 8, 2, 1024>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 16, 0, 1024>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 16, 1, 1024>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 16, 2, 1024>)};
   for (const void *fn : fns)
     pd_set_max_lds(fn, v);
 }
