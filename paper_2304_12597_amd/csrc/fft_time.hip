@@ -77,7 +77,7 @@ __device__ __forceinline__ void stockham_stage(cpx<R> *lds, int N, int Ns, int C
       int jm = j & (Ns - 1);
 #pragma unroll
       for (int r = 0; r < RAD; ++r) {
-        cpx<R> x = col[j + r * per_col];
+        cpx<R> x = col[pd_fpad(j + r * per_col)];
         if (r > 0 && jm != 0) {
           cpx<R> t = tw[jm * r * twstep];
           if (INV) t.im = -t.im;
@@ -98,7 +98,7 @@ __device__ __forceinline__ void stockham_stage(cpx<R> *lds, int N, int Ns, int C
       int jm = j & (Ns - 1);
       int base = (j / Ns) * Ns * RAD + jm;
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) col[base + r * Ns] = v[q * RAD + r];
+      for (int r = 0; r < RAD; ++r) col[pd_fpad(base + r * Ns)] = v[q * RAD + r];
     }
   }
   __syncthreads();
@@ -171,7 +171,7 @@ __device__ __forceinline__ void fft_forward_body(int tile, int N, int n, int nba
       const int idx = base + u * T;
       if (idx < total) {
         const int t = idx / S, pnt = idx - t * S;
-        R *l = reinterpret_cast<R *>(&lds[(pnt >> 1) * stride + t]);
+        R *l = reinterpret_cast<R *>(&lds[(pnt >> 1) * stride + pd_fpad(t)]);
         l[pnt & 1] = (R)vals[u];
       }
     }
@@ -184,8 +184,8 @@ __device__ __forceinline__ void fft_forward_body(int tile, int N, int n, int nba
     int i = i0 + pnt;
     if (i >= nbar) continue;
     int c = pnt >> 1;
-    cpx<R> zk = lds[c * stride + k];
-    cpx<R> zn = lds[c * stride + ((N - k) & (N - 1))];
+    cpx<R> zk = lds[c * stride + pd_fpad(k)];
+    cpx<R> zn = lds[c * stride + pd_fpad((N - k) & (N - 1))];
     cpx<R> X;
     if ((pnt & 1) == 0) {
       X = cpx<R>{R(0.5) * (zk.re + zn.re), R(0.5) * (zk.im - zn.im)};
@@ -270,8 +270,8 @@ __device__ __forceinline__ void fft_inverse_body(int tile, int N, int nbar, int 
         const int k = idx / C, c = idx - k * C;
         cpx<R> a = xa[u], b = xb[u];
         if (k == 0 || k == half) { a.im = R(0); b.im = R(0); }
-        lds[c * stride + k] = cpx<R>{a.re - b.im, a.im + b.re};
-        if (k > 0 && k < half) lds[c * stride + N - k] = cpx<R>{a.re + b.im, b.re - a.im};
+        lds[c * stride + pd_fpad(k)] = cpx<R>{a.re - b.im, a.im + b.re};
+        if (k > 0 && k < half) lds[c * stride + pd_fpad(N - k)] = cpx<R>{a.re + b.im, b.re - a.im};
       }
     }
   }
@@ -282,7 +282,7 @@ __device__ __forceinline__ void fft_inverse_body(int tile, int N, int nbar, int 
     int t = idx / S, pnt = idx - t * S;
     int i = i0 + pnt;
     if (i >= nbar) continue;
-    cpx<R> z = lds[(pnt >> 1) * stride + t];
+    cpx<R> z = lds[(pnt >> 1) * stride + pd_fpad(t)];
     double val = (double)((pnt & 1) ? z.im : z.re) * invN * dalinv[t];
     size_t o = (size_t)t * nbar + i;
     if (ACC) U[o] += val;
@@ -324,7 +324,7 @@ dst_x_kernel(int n, int ell, int C, int stride, double tau, const double *__rest
   double rn2 = 0.0, gn2 = 0.0;
   for (int c = tid; c < C; c += T) {
     lds[c * stride] = cpx<double>{0.0, 0.0};
-    lds[c * stride + n + 1] = cpx<double>{0.0, 0.0};
+    lds[c * stride + pd_fpad(n + 1)] = cpx<double>{0.0, 0.0};
   }
   constexpr int UNR = 8;
   const int total = 2 * C * n;
@@ -361,8 +361,8 @@ dst_x_kernel(int n, int ell, int C, int stride, double tau, const double *__rest
       const int idx = base + u * T;
       if (idx < total) {
         const int lr = idx / n, x = idx - lr * n;
-        double *p1 = reinterpret_cast<double *>(&lds[(lr >> 1) * stride + x + 1]);
-        double *p2 = reinterpret_cast<double *>(&lds[(lr >> 1) * stride + N - 1 - x]);
+        double *p1 = reinterpret_cast<double *>(&lds[(lr >> 1) * stride + pd_fpad(x + 1)]);
+        double *p2 = reinterpret_cast<double *>(&lds[(lr >> 1) * stride + pd_fpad(N - 1 - x)]);
         p1[lr & 1] = vals[u];
         p2[lr & 1] = -vals[u];
       }
@@ -376,7 +376,7 @@ dst_x_kernel(int n, int ell, int C, int stride, double tau, const double *__rest
     const int row = r0 + lr;
     if (row >= rows) continue;
     const int t = row / n, y = row - t * n;
-    const cpx<double> z = lds[(lr >> 1) * stride + m + 1];
+    const cpx<double> z = lds[(lr >> 1) * stride + pd_fpad(m + 1)];
     const double s = ((lr & 1) ? z.re : -z.im) * scale;
     const size_t o = (size_t)t * nbar + (size_t)y * n + m;
     if (ACC) out[o] += s;
@@ -423,13 +423,14 @@ FftLaunch fft_config(pd_plan p) {
 }  // namespace
 
 // Choose C (point pairs per block): keep LDS at <= 64 KiB where possible
-// (two blocks per CU), allow 128 KiB for the longest transforms, and keep the
-// tile no wider than the problem.
+// (two blocks per CU), else two point pairs per block, and keep the tile no
+// wider than the problem.
 int pd_choose_fft_C(int ell, int nbar, int prec, size_t max_lds) {
   const size_t cb = (prec == PD_FP64) ? 16 : 8;
+  const size_t col = (size_t)pd_fft_col_stride(ell) * cb;
   int C = 1;
-  while (C < 32 && (size_t)(2 * C) * (ell + 1) * cb <= 65536 && 2 * C * ell / 8 <= 1024) C *= 2;
-  while (C < 4 && (size_t)(2 * C) * (ell + 1) * cb <= max_lds && 2 * C * ell / 8 <= 1024) C *= 2;
+  while (C < 32 && 2 * C * col <= 65536 && 2 * C * ell / 8 <= 1024) C *= 2;
+  while (C < 2 && 2 * C * col <= max_lds && 2 * C * ell / 8 <= 1024) C *= 2;
   int maxC = 1;
   while (2 * maxC < nbar && maxC < 32) maxC *= 2;
   if (C > maxC) C = maxC;
@@ -483,7 +484,7 @@ DstLaunch dst_config(pd_plan p) {
   DstLaunch L;
   const int N = 2 * (p->n + 1);
   L.C = p->dst_C;
-  L.stride = N + 1;
+  L.stride = pd_fft_col_stride(N);
   L.lds = (size_t)L.C * L.stride * 16;
   int need = L.C * N / 8;
   if (need < 64) need = 64;
@@ -497,7 +498,8 @@ DstLaunch dst_config(pd_plan p) {
 int pd_choose_dst_C(int n) {
   const int N = 2 * (n + 1);
   int C = 1;
-  while (C < 16 && (size_t)(2 * C) * (N + 1) * 16 <= 65536 && 2 * C * N / 8 <= 1024) C *= 2;
+  const size_t col = (size_t)pd_fft_col_stride(N) * 16;
+  while (C < 16 && 2 * C * col <= 65536 && 2 * C * N / 8 <= 1024) C *= 2;
   return C;
 }
 

@@ -63,6 +63,16 @@ __device__ __forceinline__ cpx<R> cmul_mi(cpx<R> a) {
 // amplify it on ill-conditioned problems (small diffusion, long horizons).
 constexpr double PD_GMRES_TOL_FACTOR = 1e-2;
 
+// LDS column layout of the time and DST transforms: entry i of a column sits
+// at pd_fpad(i) = i + i/8, which spreads the power-of-two strides of the
+// Stockham stages over all LDS banks; columns are pd_fft_col_stride(N)
+// entries apart (odd, so that columns start on different banks).
+__host__ __device__ __forceinline__ int pd_fpad(int i) { return i + (i >> 3); }
+__host__ __device__ __forceinline__ int pd_fft_col_stride(int N) {
+  const int s = pd_fpad(N - 1) + 1;
+  return s | 1;
+}
+
 // ---------------------------------------------------------------------------
 // batched launches: one entry per problem, a block map (problem, local block)
 // ---------------------------------------------------------------------------
