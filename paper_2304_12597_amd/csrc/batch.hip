@@ -67,7 +67,7 @@ pd_status pd_solve_batch_impl(const pd_plan *plans, int count, const double *con
     int need = f.C * f.N / 8;
     need = ((std::max(need, 64) + 63) / 64) * 64;
     fft_threads = std::max(fft_threads, need);
-    fft_lds = std::max(fft_lds, (size_t)f.C * f.stride * cb);
+    fft_lds = std::max(fft_lds, ((size_t)f.C * f.stride + pd_tw_entries(f.N)) * cb);
 
     TriJob &t = tj[i];
     const int P = p->tri.P;

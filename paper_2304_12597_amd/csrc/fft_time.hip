@@ -55,18 +55,46 @@ __device__ __forceinline__ void small_dft(cpx<R> *v) {
   }
 }
 
+// Copies the twiddle tables of a length-N transform (pd_tw_lo / pd_tw_entries)
+// from the global table tw[m] = w^m into LDS; the caller synchronises.
+template <typename R>
+__device__ __forceinline__ void tw_to_lds(cpx<R> *lo, const cpx<R> *__restrict__ tw, int N) {
+  const int LO = pd_tw_lo(N), E = pd_tw_entries(N);
+  for (int m = threadIdx.x; m < E; m += blockDim.x) lo[m] = (m < LO) ? tw[m] : tw[(m - LO) * 64];
+}
+
+// x[r] *= w^r, r = 1..RAD-1, with the powers formed from w by products
+template <typename R, int RAD>
+__device__ __forceinline__ void twiddle_powers(cpx<R> *x, cpx<R> w1) {
+  x[1] = cmul(x[1], w1);
+  if constexpr (RAD >= 4) {
+    const cpx<R> w2 = cmul(w1, w1), w3 = cmul(w2, w1);
+    x[2] = cmul(x[2], w2);
+    x[3] = cmul(x[3], w3);
+    if constexpr (RAD == 8) {
+      const cpx<R> w4 = cmul(w2, w2), w5 = cmul(w4, w1), w6 = cmul(w3, w3), w7 = cmul(w6, w1);
+      x[4] = cmul(x[4], w4);
+      x[5] = cmul(x[5], w5);
+      x[6] = cmul(x[6], w6);
+      x[7] = cmul(x[7], w7);
+    }
+  }
+}
+
 // One Stockham autosort stage of radix RAD over C columns of length N held
-// in LDS (column stride `stride`), in place: all reads, barrier, all writes.
-// Ns = length of the sub-transforms already done.  Each thread handles up to
-// 8/RAD butterflies (the host launches >= C*N/8 threads).
+// in LDS (entry i of column c at c * stride + pd_fpad(i)), in place: all
+// reads, barrier, all writes.  Ns = length of the sub-transforms already
+// done; the twiddles come from the LDS tables (lo, then hi).  Each thread
+// handles up to 8/RAD butterflies (the host launches >= C*N/8 threads).
 template <typename R, bool INV, int RAD>
-__device__ __forceinline__ void stockham_stage(cpx<R> *lds, int N, int Ns, int C,
-                                               int stride, const cpx<R> *__restrict__ tw) {
+__device__ __forceinline__ void stockham_stage(cpx<R> *lds, int N, int Ns, int C, int stride,
+                                               const cpx<R> *lo) {
   constexpr int BPT = 8 / RAD;
   const int T = blockDim.x, tid = threadIdx.x;
   const int per_col = N / RAD;
   const int nb = C * per_col;
   const int twstep = N / (Ns * RAD);
+  const cpx<R> *hi = lo + pd_tw_lo(N);
   cpx<R> v[8];
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
@@ -76,14 +104,12 @@ __device__ __forceinline__ void stockham_stage(cpx<R> *lds, int N, int Ns, int C
       const cpx<R> *col = lds + c * stride;
       int jm = j & (Ns - 1);
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) {
-        cpx<R> x = col[pd_fpad(j + r * per_col)];
-        if (r > 0 && jm != 0) {
-          cpx<R> t = tw[jm * r * twstep];
-          if (INV) t.im = -t.im;
-          x = cmul(x, t);
-        }
-        v[q * RAD + r] = x;
+      for (int r = 0; r < RAD; ++r) v[q * RAD + r] = col[pd_fpad(j + r * per_col)];
+      if (Ns > 1) {
+        const int m = jm * twstep;
+        cpx<R> w = cmul(hi[m >> 6], lo[m & 63]);
+        if (INV) w.im = -w.im;
+        twiddle_powers<R, RAD>(&v[q * RAD], w);
       }
       small_dft<R, INV, RAD>(&v[q * RAD]);
     }
@@ -105,16 +131,16 @@ __device__ __forceinline__ void stockham_stage(cpx<R> *lds, int N, int Ns, int C
 }
 
 template <typename R, bool INV>
-__device__ void fft_lds(cpx<R> *lds, int N, int C, int stride, const cpx<R> *tw) {
+__device__ __forceinline__ void fft_lds(cpx<R> *lds, int N, int C, int stride, const cpx<R> *twl) {
   int Ns = 1;
   while (Ns * 8 <= N) {
-    stockham_stage<R, INV, 8>(lds, N, Ns, C, stride, tw);
+    stockham_stage<R, INV, 8>(lds, N, Ns, C, stride, twl);
     Ns *= 8;
   }
   if (Ns * 4 == N) {
-    stockham_stage<R, INV, 4>(lds, N, Ns, C, stride, tw);
+    stockham_stage<R, INV, 4>(lds, N, Ns, C, stride, twl);
   } else if (Ns * 2 == N) {
-    stockham_stage<R, INV, 2>(lds, N, Ns, C, stride, tw);
+    stockham_stage<R, INV, 2>(lds, N, Ns, C, stride, twl);
   }
 }
 
@@ -131,6 +157,8 @@ __device__ __forceinline__ void fft_forward_body(int tile, int N, int n, int nba
                                                  double *__restrict__ red) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<R> *lds = reinterpret_cast<cpx<R> *>(smem_raw);
+  cpx<R> *twl = lds + C * stride;
+  tw_to_lds(twl, tw, N);
   const int T = blockDim.x, tid = threadIdx.x;
   const int S = 2 * C;
   const int i0 = tile * S;
@@ -177,7 +205,7 @@ __device__ __forceinline__ void fft_forward_body(int tile, int N, int n, int nba
     }
   }
   __syncthreads();
-  fft_lds<R, false>(lds, N, C, stride, tw);
+  fft_lds<R, false>(lds, N, C, stride, twl);
   const int half = N / 2;
   for (int idx = tid; idx < (half + 1) * S; idx += T) {
     int k = idx / S, pnt = idx - k * S;
@@ -243,6 +271,8 @@ __device__ __forceinline__ void fft_inverse_body(int tile, int N, int nbar, int 
                                                  double *__restrict__ U) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<R> *lds = reinterpret_cast<cpx<R> *>(smem_raw);
+  cpx<R> *twl = lds + C * stride;
+  tw_to_lds(twl, tw, N);
   const int T = blockDim.x, tid = threadIdx.x;
   const int S = 2 * C;
   const int i0 = tile * S;
@@ -276,7 +306,7 @@ __device__ __forceinline__ void fft_inverse_body(int tile, int N, int nbar, int 
     }
   }
   __syncthreads();
-  fft_lds<R, true>(lds, N, C, stride, tw);
+  fft_lds<R, true>(lds, N, C, stride, twl);
   const double invN = 1.0 / (double)N;
   for (int idx = tid; idx < N * S; idx += T) {
     int t = idx / S, pnt = idx - t * S;
@@ -321,6 +351,8 @@ dst_x_kernel(int n, int ell, int C, int stride, double tau, const double *__rest
   const int nbar = n * n;
   const int rows = ell * n;
   const int r0 = blockIdx.x * 2 * C;
+  cpx<double> *twl = lds + C * stride;
+  tw_to_lds(twl, tw, N);
   double rn2 = 0.0, gn2 = 0.0;
   for (int c = tid; c < C; c += T) {
     lds[c * stride] = cpx<double>{0.0, 0.0};
@@ -369,7 +401,7 @@ dst_x_kernel(int n, int ell, int C, int stride, double tau, const double *__rest
     }
   }
   __syncthreads();
-  fft_lds<double, false>(lds, N, C, stride, tw);
+  fft_lds<double, false>(lds, N, C, stride, twl);
   const double scale = 0.5 * sqrt(2.0 / (double)(n + 1));
   for (int idx = tid; idx < 2 * C * n; idx += T) {
     const int lr = idx / n, m = idx - lr * n;
@@ -412,7 +444,7 @@ FftLaunch fft_config(pd_plan p) {
   const size_t cb = (p->prec == PD_FP64) ? 16 : 8;
   L.C = p->fft_C;
   L.stride = p->fft_stride;
-  L.lds = (size_t)L.C * L.stride * cb;
+  L.lds = ((size_t)L.C * L.stride + pd_tw_entries(N)) * cb;
   int need = L.C * N / 8;
   if (need < 64) need = 64;
   L.threads = ((need + 63) / 64) * 64;
@@ -423,14 +455,14 @@ FftLaunch fft_config(pd_plan p) {
 }  // namespace
 
 // Choose C (point pairs per block): keep LDS at <= 64 KiB where possible
-// (two blocks per CU), else two point pairs per block, and keep the tile no
-// wider than the problem.
+// (two blocks per CU), else up to two point pairs per block; at most 512
+// threads (C*N/8), and the tile no wider than the problem.
 int pd_choose_fft_C(int ell, int nbar, int prec, size_t max_lds) {
   const size_t cb = (prec == PD_FP64) ? 16 : 8;
-  const size_t col = (size_t)pd_fft_col_stride(ell) * cb;
+  const size_t col = (size_t)pd_fft_col_stride(ell) * cb, twb = pd_tw_entries(ell) * cb;
   int C = 1;
-  while (C < 32 && 2 * C * col <= 65536 && 2 * C * ell / 8 <= 1024) C *= 2;
-  while (C < 2 && 2 * C * col <= max_lds && 2 * C * ell / 8 <= 1024) C *= 2;
+  while (C < 32 && 2 * C * col + twb <= 65536 && 2 * C * ell / 8 <= 512) C *= 2;
+  while (C < 2 && 2 * C * col + twb <= max_lds && 2 * C * ell / 8 <= 512) C *= 2;
   int maxC = 1;
   while (2 * maxC < nbar && maxC < 32) maxC *= 2;
   if (C > maxC) C = maxC;
@@ -440,37 +472,24 @@ int pd_choose_fft_C(int ell, int nbar, int prec, size_t max_lds) {
 pd_status pd_launch_fft_forward(pd_plan p, const double *u0, const double *F,
                                 const double *U, void *out, int mode) {
   FftLaunch L = fft_config(p);
+#define PD_FWD(R, M, TW, O)                                                                 \
+  hipLaunchKernelGGL((fft_forward_kernel<R, M>), dim3(L.blocks), dim3(L.threads), L.lds,    \
+                     p->stream, p->ell, p->n, p->nbar, p->dims, L.C, L.stride, p->tau, u0, \
+                     F, U, p->coef64, p->dal, TW, O, p->red)
   if (p->prec == PD_FP64) {
     auto tw = reinterpret_cast<const cpx<double> *>(p->tw64);
     auto o = reinterpret_cast<cpx<double> *>(out);
-    if (mode == 0)
-      hipLaunchKernelGGL((fft_forward_kernel<double, 0>), dim3(L.blocks), dim3(L.threads),
-                         L.lds, p->stream, p->ell, p->n, p->nbar, p->dims, L.C, L.stride,
-                         p->tau, u0, F, U, p->coef64, p->dal, tw, o, p->red);
-    else if (mode == 2)
-      hipLaunchKernelGGL((fft_forward_kernel<double, 2>), dim3(L.blocks), dim3(L.threads),
-                         L.lds, p->stream, p->ell, p->n, p->nbar, p->dims, L.C, L.stride,
-                         p->tau, u0, F, U, p->coef64, p->dal, tw, o, p->red);
-    else
-      hipLaunchKernelGGL((fft_forward_kernel<double, 1>), dim3(L.blocks), dim3(L.threads),
-                         L.lds, p->stream, p->ell, p->n, p->nbar, p->dims, L.C, L.stride,
-                         p->tau, u0, F, U, p->coef64, p->dal, tw, o, p->red);
+    if (mode == 0) PD_FWD(double, 0, tw, o);
+    else if (mode == 2) PD_FWD(double, 2, tw, o);
+    else PD_FWD(double, 1, tw, o);
   } else {
     auto tw = reinterpret_cast<const cpx<float> *>(p->tw32);
     auto o = reinterpret_cast<cpx<float> *>(out);
-    if (mode == 0)
-      hipLaunchKernelGGL((fft_forward_kernel<float, 0>), dim3(L.blocks), dim3(L.threads),
-                         L.lds, p->stream, p->ell, p->n, p->nbar, p->dims, L.C, L.stride,
-                         p->tau, u0, F, U, p->coef64, p->dal, tw, o, p->red);
-    else if (mode == 2)
-      hipLaunchKernelGGL((fft_forward_kernel<float, 2>), dim3(L.blocks), dim3(L.threads),
-                         L.lds, p->stream, p->ell, p->n, p->nbar, p->dims, L.C, L.stride,
-                         p->tau, u0, F, U, p->coef64, p->dal, tw, o, p->red);
-    else
-      hipLaunchKernelGGL((fft_forward_kernel<float, 1>), dim3(L.blocks), dim3(L.threads),
-                         L.lds, p->stream, p->ell, p->n, p->nbar, p->dims, L.C, L.stride,
-                         p->tau, u0, F, U, p->coef64, p->dal, tw, o, p->red);
+    if (mode == 0) PD_FWD(float, 0, tw, o);
+    else if (mode == 2) PD_FWD(float, 2, tw, o);
+    else PD_FWD(float, 1, tw, o);
   }
+#undef PD_FWD
   PD_HIP_CHECK(hipGetLastError());
   return PD_OK;
 }
@@ -485,7 +504,7 @@ DstLaunch dst_config(pd_plan p) {
   const int N = 2 * (p->n + 1);
   L.C = p->dst_C;
   L.stride = pd_fft_col_stride(N);
-  L.lds = (size_t)L.C * L.stride * 16;
+  L.lds = ((size_t)L.C * L.stride + pd_tw_entries(N)) * 16;
   int need = L.C * N / 8;
   if (need < 64) need = 64;
   L.threads = ((need + 63) / 64) * 64;
@@ -498,8 +517,8 @@ DstLaunch dst_config(pd_plan p) {
 int pd_choose_dst_C(int n) {
   const int N = 2 * (n + 1);
   int C = 1;
-  const size_t col = (size_t)pd_fft_col_stride(N) * 16;
-  while (C < 16 && 2 * C * col <= 65536 && 2 * C * N / 8 <= 1024) C *= 2;
+  const size_t col = (size_t)pd_fft_col_stride(N) * 16, twb = pd_tw_entries(N) * 16;
+  while (C < 16 && 2 * C * col + twb <= 65536 && 2 * C * N / 8 <= 1024) C *= 2;
   return C;
 }
 
@@ -525,25 +544,21 @@ pd_status pd_launch_dst_x(pd_plan p, int mode, const double *u0, const double *F
 pd_status pd_launch_fft_inverse(pd_plan p, const void *in, double *U, int accumulate) {
   FftLaunch L = fft_config(p);
   const double *dalinv = p->dal + p->ell;
+#define PD_INV(R, A, TW, I)                                                                 \
+  hipLaunchKernelGGL((fft_inverse_kernel<R, A>), dim3(L.blocks), dim3(L.threads), L.lds,    \
+                     p->stream, p->ell, p->nbar, L.C, L.stride, I, dalinv, TW, U)
   if (p->prec == PD_FP64) {
     auto tw = reinterpret_cast<const cpx<double> *>(p->tw64);
     auto i = reinterpret_cast<const cpx<double> *>(in);
-    if (accumulate)
-      hipLaunchKernelGGL((fft_inverse_kernel<double, 1>), dim3(L.blocks), dim3(L.threads),
-                         L.lds, p->stream, p->ell, p->nbar, L.C, L.stride, i, dalinv, tw, U);
-    else
-      hipLaunchKernelGGL((fft_inverse_kernel<double, 0>), dim3(L.blocks), dim3(L.threads),
-                         L.lds, p->stream, p->ell, p->nbar, L.C, L.stride, i, dalinv, tw, U);
+    if (accumulate) PD_INV(double, 1, tw, i);
+    else PD_INV(double, 0, tw, i);
   } else {
     auto tw = reinterpret_cast<const cpx<float> *>(p->tw32);
     auto i = reinterpret_cast<const cpx<float> *>(in);
-    if (accumulate)
-      hipLaunchKernelGGL((fft_inverse_kernel<float, 1>), dim3(L.blocks), dim3(L.threads),
-                         L.lds, p->stream, p->ell, p->nbar, L.C, L.stride, i, dalinv, tw, U);
-    else
-      hipLaunchKernelGGL((fft_inverse_kernel<float, 0>), dim3(L.blocks), dim3(L.threads),
-                         L.lds, p->stream, p->ell, p->nbar, L.C, L.stride, i, dalinv, tw, U);
+    if (accumulate) PD_INV(float, 1, tw, i);
+    else PD_INV(float, 0, tw, i);
   }
+#undef PD_INV
   PD_HIP_CHECK(hipGetLastError());
   return PD_OK;
 }

@@ -72,6 +72,12 @@ __host__ __device__ __forceinline__ int pd_fft_col_stride(int N) {
   const int s = pd_fpad(N - 1) + 1;
   return s | 1;
 }
+// Twiddles of a length-N transform in LDS: lo[m] = w^m for m < min(N, 64) and
+// hi[h] = w^(64 h) for h < max(N / 64, 1); w^m = hi[m / 64] lo[m % 64].
+__host__ __device__ __forceinline__ int pd_tw_lo(int N) { return N < 64 ? N : 64; }
+__host__ __device__ __forceinline__ int pd_tw_entries(int N) {
+  return pd_tw_lo(N) + (N < 64 ? 1 : N / 64);
+}
 
 // ---------------------------------------------------------------------------
 // batched launches: one entry per problem, a block map (problem, local block)

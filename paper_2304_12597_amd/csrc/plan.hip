@@ -97,7 +97,7 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
   const size_t cb = (p->prec == PD_FP64) ? 16 : 8;
   p->fft_C = pd_choose_fft_C(ell, p->nbar, p->prec, max_lds);
   p->fft_stride = pd_fft_col_stride(ell);
-  if ((size_t)p->fft_C * p->fft_stride * cb > max_lds) {
+  if (((size_t)p->fft_C * p->fft_stride + pd_tw_entries(ell)) * cb > max_lds) {
     pd_set_error("time transform tile does not fit in LDS");
     return PD_ENOTSUP;
   }
@@ -117,7 +117,8 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
       return PD_ENOTSUP;
     }
     p->dst_C = pd_choose_dst_C(n);
-    if ((size_t)p->dst_C * pd_fft_col_stride(2 * (n + 1)) * 16 > max_lds) {
+    if (((size_t)p->dst_C * pd_fft_col_stride(2 * (n + 1)) + pd_tw_entries(2 * (n + 1))) * 16 >
+        max_lds) {
       pd_set_error("DST tile does not fit in LDS");
       return PD_ENOTSUP;
     }
