@@ -13,6 +13,10 @@ ARCH = os.environ.get("PD_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC",
          # packed FP32 instructions are disabled for every HIP source
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # multiply-adds are fused per source expression only, so a device
+         # function rounds the same way in every kernel it is inlined into
+         # (single-problem and batched launches agree bit for bit)
+         "-ffp-contract=on",
          "-Wno-unused-result"]
 
 

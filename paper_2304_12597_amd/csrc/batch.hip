@@ -85,13 +85,8 @@ pd_status pd_solve_batch_impl(const pd_plan *plans, int count, const double *con
     t.gw = p->gB64; t.in = p->spec; t.vin = nullptr; t.xv = p->xvec; t.wscale = p->w;
     t.out = p->spec; t.partials = p->partials;
     for (int b = 0; b < t.nblk; ++b) tri0map.push_back(make_int2(i, b));
-    for (int b = 0; b < t.nitems; ++b) tri1map.push_back(make_int2(i, b));
-    const size_t rows = (size_t)P * MR;
-    size_t region = (size_t)t.spb * (rows + 2) * cb;
-    region = std::max(region, (size_t)t.spb * rows * sizeof(double));
-    region = std::max(region, (size_t)t.spb * P * 3 * cb);
-    region = (region + 15) & ~(size_t)15;
-    tri_lds = std::max(tri_lds, region + (size_t)t.spb * 6 * (MR - 1) * cb);
+    for (int b = 0; b < t.nblk; ++b) tri1map.push_back(make_int2(i, b));
+    tri_lds = std::max(tri_lds, p->tri.lds);   // batchable: the same packing as p->tri
 
     VecJob &v = vj[i];
     v.n = p->nbar; v.B = pd_vec_blocks(p->nbar); v.G = t.nblk;

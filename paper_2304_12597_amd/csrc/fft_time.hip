@@ -207,20 +207,37 @@ __device__ __forceinline__ void fft_forward_body(int tile, int N, int n, int nba
   __syncthreads();
   fft_lds<R, false>(lds, N, C, stride, twl);
   const int half = N / 2;
-  for (int idx = tid; idx < (half + 1) * S; idx += T) {
-    int k = idx / S, pnt = idx - k * S;
-    int i = i0 + pnt;
-    if (i >= nbar) continue;
-    int c = pnt >> 1;
-    cpx<R> zk = lds[c * stride + pd_fpad(k)];
-    cpx<R> zn = lds[c * stride + pd_fpad((N - k) & (N - 1))];
-    cpx<R> X;
-    if ((pnt & 1) == 0) {
-      X = cpx<R>{R(0.5) * (zk.re + zn.re), R(0.5) * (zk.im - zn.im)};
-    } else {
-      X = cpx<R>{R(0.5) * (zk.im + zn.im), R(0.5) * (zn.re - zk.re)};
+  // split the packed pairs: UNR outputs per thread per round, all LDS reads
+  // before the stores (k < N/2 here, the Nyquist row k = N/2 below)
+  const int nout = half * S;
+  for (int base = tid; base < nout; base += UNR * T) {
+    cpx<R> X[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = base + u * T;
+      const int ic = idx < nout ? idx : 0;
+      const int k = ic / S, pnt = ic - k * S, c = pnt >> 1;
+      const cpx<R> zk = lds[c * stride + pd_fpad(k)];
+      const cpx<R> zn = lds[c * stride + pd_fpad((N - k) & (N - 1))];
+      const R xr = (pnt & 1) ? zk.im + zn.im : zk.re + zn.re;
+      const R xi = (pnt & 1) ? zn.re - zk.re : zk.im - zn.im;
+      X[u] = cpx<R>{R(0.5) * xr, R(0.5) * xi};
     }
-    out[(size_t)k * nbar + i] = X;
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = base + u * T;
+      if (idx < nout) {
+        const int k = idx / S, pnt = idx - k * S;
+        if (i0 + pnt < nbar) out[(size_t)k * nbar + i0 + pnt] = X[u];
+      }
+    }
+  }
+  for (int pnt = tid; pnt < S; pnt += T) {
+    if (i0 + pnt >= nbar) continue;
+    const cpx<R> z = lds[(pnt >> 1) * stride + pd_fpad(half)];
+    const R xr = (pnt & 1) ? z.im + z.im : z.re + z.re;
+    const R xi = (pnt & 1) ? z.re - z.re : z.im - z.im;
+    out[(size_t)half * nbar + i0 + pnt] = cpx<R>{R(0.5) * xr, R(0.5) * xi};
   }
   if (MODE == 1) {
     // block reduction of the two norms (float64)
@@ -308,15 +325,31 @@ __device__ __forceinline__ void fft_inverse_body(int tile, int N, int nbar, int 
   __syncthreads();
   fft_lds<R, true>(lds, N, C, stride, twl);
   const double invN = 1.0 / (double)N;
-  for (int idx = tid; idx < N * S; idx += T) {
-    int t = idx / S, pnt = idx - t * S;
-    int i = i0 + pnt;
-    if (i >= nbar) continue;
-    cpx<R> z = lds[(pnt >> 1) * stride + pd_fpad(t)];
-    double val = (double)((pnt & 1) ? z.im : z.re) * invN * dalinv[t];
-    size_t o = (size_t)t * nbar + i;
-    if (ACC) U[o] += val;
-    else U[o] = val;
+  // UNR2 outputs per thread per round: the LDS reads and the dalinv (and,
+  // accumulating, U) loads are all issued before the stores
+  constexpr int UNR2 = 8;
+  const int nout = N * S;
+  for (int base = tid; base < nout; base += UNR2 * T) {
+    double val[UNR2];
+#pragma unroll
+    for (int u = 0; u < UNR2; ++u) {
+      const int idx = base + u * T;
+      const int ic = idx < nout ? idx : 0;
+      const int t = ic / S, pnt = ic - t * S;
+      int i = i0 + pnt;
+      i = i < nbar ? i : nbar - 1;
+      const cpx<R> z = lds[(pnt >> 1) * stride + pd_fpad(t)];
+      val[u] = (double)((pnt & 1) ? z.im : z.re) * invN * dalinv[t];
+      if (ACC) val[u] += U[(size_t)t * nbar + i];
+    }
+#pragma unroll
+    for (int u = 0; u < UNR2; ++u) {
+      const int idx = base + u * T;
+      if (idx < nout) {
+        const int t = idx / S, pnt = idx - t * S;
+        if (i0 + pnt < nbar) U[(size_t)t * nbar + i0 + pnt] = val[u];
+      }
+    }
   }
 }
 
@@ -403,16 +436,35 @@ dst_x_kernel(int n, int ell, int C, int stride, double tau, const double *__rest
   __syncthreads();
   fft_lds<double, false>(lds, N, C, stride, twl);
   const double scale = 0.5 * sqrt(2.0 / (double)(n + 1));
-  for (int idx = tid; idx < 2 * C * n; idx += T) {
-    const int lr = idx / n, m = idx - lr * n;
-    const int row = r0 + lr;
-    if (row >= rows) continue;
-    const int t = row / n, y = row - t * n;
-    const cpx<double> z = lds[(lr >> 1) * stride + pd_fpad(m + 1)];
-    const double s = ((lr & 1) ? z.re : -z.im) * scale;
-    const size_t o = (size_t)t * nbar + (size_t)y * n + m;
-    if (ACC) out[o] += s;
-    else out[o] = s;
+  // UNR outputs per thread per round, all reads before the stores
+  for (int base = tid; base < total; base += UNR * T) {
+    double s[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = base + u * T;
+      const int ic = idx < total ? idx : 0;
+      const int lr = ic / n, m = ic - lr * n;
+      const cpx<double> z = lds[(lr >> 1) * stride + pd_fpad(m + 1)];
+      s[u] = ((lr & 1) ? z.re : -z.im) * scale;
+      if (ACC) {
+        int row = r0 + lr;
+        row = row < rows ? row : rows - 1;
+        const int t = row / n, y = row - t * n;
+        s[u] += out[(size_t)t * nbar + (size_t)y * n + m];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = base + u * T;
+      if (idx < total) {
+        const int lr = idx / n, m = idx - lr * n;
+        const int row = r0 + lr;
+        if (row < rows) {
+          const int t = row / n, y = row - t * n;
+          out[(size_t)t * nbar + (size_t)y * n + m] = s[u];
+        }
+      }
+    }
   }
   if (MODE == 1) {
     __shared__ double sr[32], sg[32];

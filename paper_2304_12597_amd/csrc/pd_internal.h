@@ -136,6 +136,7 @@ struct TriConfig {
   int spb;      // systems per block
   int block;    // threads per block = P * spb
   size_t lds;   // dynamic LDS bytes
+  int pipe;     // complex128, P >= 64: the pipelined uniform body
 };
 
 struct Line2DConfig {

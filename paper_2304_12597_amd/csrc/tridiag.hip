@@ -485,6 +485,191 @@ __device__ __forceinline__ void tridiag_uniform_body(
   }
 }
 
+// Pipelined complex128 body for systems of whole waves (P >= 64).  LDS holds
+// the NEXT item's right-hand side and elimination factors, brought in by
+// global_load_lds while the current item is solved from registers, so the
+// HBM loads overlap the elimination.  The right-hand side is staged
+// transposed -- row lt*MR + q of group g at g*P*MR + q*P + lt -- so that every
+// LDS read of a thread's chunk is conflict-free; DMA instruction q of a wave
+// reads rows lt*MR + q of its 64 lanes (a 256-byte stride that the L2 merges
+// into whole lines).  The per-item scalars (lambda_k, gamma_k) are read with
+// scalar loads, which do not wait for the vector-memory counter.  Mode 1
+// stores each thread's rows straight from registers.
+//
+// LDS: [spb*P*MR cpx stage][spb*P Row3 exchange][2*spb*NFP cpx factors]
+template <int MR>
+constexpr int pipe_nfp() { return (6 * (MR - 1) + 63) / 64 * 64; }
+
+template <int MR, int MODE>
+__device__ __forceinline__ void tridiag_pipe_body(
+    int blk, int nblk, int n, int F2, int P, int spb, int nitems, const Coef<double> &cf,
+    const double *__restrict__ coef64, const double *__restrict__ lam,
+    const cpx<double> *__restrict__ fac, const double *__restrict__ gw,
+    const cpx<double> *__restrict__ in, const double *__restrict__ vin,
+    const double *__restrict__ xv, double wscale, int rhs_has_mass,
+    cpx<double> *__restrict__ out, double *__restrict__ partials) {
+  using R = double;
+  using Cx = cpx<double>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int NF = 6 * (MR - 1);
+  constexpr int NFP = pipe_nfp<MR>();
+  const int tid = threadIdx.x;
+  const int g = tid / P;
+  const int lt = tid - g * P;
+  const int wib = lt >> 6;   // wave within the group
+  const int rows = P * MR;
+  Cx *stage_all = reinterpret_cast<Cx *>(smem_raw);
+  Cx *stage = stage_all + (size_t)g * rows;
+  Row3<R> *xch_all = reinterpret_cast<Row3<R> *>(stage_all + (size_t)spb * rows);
+  Row3<R> *xch = xch_all + (size_t)g * P;
+  Cx *facb = reinterpret_cast<Cx *>(xch_all + (size_t)spb * P);
+  const int s0 = lt * MR;
+  int len = n - s0;
+  len = len < 0 ? 0 : (len > MR ? MR : len);
+  const Cx zero = {0.0, 0.0};
+
+  double acc[(MODE == 1) ? 1 : MR];
+  R mx[(MODE == 1) ? MR : 1];
+  R dv[(MODE == 2) ? MR : 1];
+  if constexpr (MODE != 1) {
+#pragma unroll
+    for (int q = 0; q < MR; ++q) acc[q] = 0.0;
+  }
+  if constexpr (MODE == 1) {
+    // -w M x, the same for every frequency
+    minus_w_mx<R, MR, true>(mx, reinterpret_cast<double *>(stage), rows + 2, coef64, xv,
+                            wscale, n, s0, lt, P);
+  }
+  if constexpr (MODE == 2) {
+    // M v is the same for all frequencies: form it once, in registers
+    double *sv = reinterpret_cast<double *>(stage);
+    stage_halo<8>(sv, vin, rows + 2, n, lt, P, true, 0.0, [](double v) { return v; });
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MR; ++q) {
+      const int i = s0 + q < n ? s0 + q : n - 1;
+      dv[q] = (q < len) ? cf.md * sv[i + 1] + cf.ml * sv[i] + cf.mu * sv[i + 2] : R(0);
+    }
+  }
+  __syncthreads();   // the staging area is free for the DMA
+
+  // DMA of item `item`'s right-hand side and factors into factor buffer b
+  auto issue = [&](int item, int b) {
+    const int k0 = item * spb + g;
+    const int k = k0 < F2 ? k0 : F2 - 1;
+    if constexpr (MODE != 2) {
+      const Cx *src = in + (size_t)k * n;
+#pragma unroll
+      for (int q = 0; q < MR; ++q) {
+        const int r = s0 + q < n ? s0 + q : n - 1;
+        pd_lds_dma16(src + r, stage + q * P + wib * 64);
+      }
+    }
+    const Cx *fsrc = fac + (size_t)k * NF;
+    Cx *fdst = facb + ((size_t)b * spb + g) * NFP;
+    for (int c0 = wib * 64; c0 < NFP; c0 += P) {
+      const int idx = c0 + (lt & 63);
+      pd_lds_dma16(fsrc + (idx < NF ? idx : NF - 1), fdst + c0);
+    }
+  };
+
+  int buf = 0;
+  if (blk < nitems) issue(blk, 0);
+  for (int item = blk; item < nitems; item += nblk, buf ^= 1) {
+    const int k0 = __builtin_amdgcn_readfirstlane(item * spb + g);
+    const bool active = k0 < F2;
+    const int k = active ? k0 : F2 - 1;
+    const R lr = lam[2 * k], li = lam[2 * k + 1];
+    double gr = 0.0, gi = 0.0;
+    if constexpr (MODE != 1) {
+      gr = gw[2 * k];
+      gi = gw[2 * k + 1];
+    }
+    const Cx ca = {lr * cf.ml + cf.kl, li * cf.ml};   // sub-diagonal
+    const Cx cc = {lr * cf.mu + cf.ku, li * cf.mu};   // super-diagonal
+    pd_wait_all();
+    __syncthreads();   // this item's right-hand side and factors have landed
+
+    Cx d[MR];
+    if constexpr (MODE == 2) {
+#pragma unroll
+      for (int q = 0; q < MR; ++q) d[q] = Cx{dv[q], R(0)};
+    } else {
+#pragma unroll
+      for (int q = 0; q < MR; ++q) d[q] = pd_sel(q < len, stage[q * P + lt], zero);
+      const Cx left = pd_sel(lt > 0, stage[(MR - 1) * P + (lt > 0 ? lt - 1 : 0)], zero);
+      const Cx right =
+          pd_sel(s0 + MR < n && lt + 1 < P, stage[lt + 1 < P ? lt + 1 : lt], zero);
+      // right-hand side d = M r (- w M x), formed in place; ghost rows are zero
+      Cx rl = left;
+#pragma unroll
+      for (int q = 0; q < MR; ++q) {
+        const Cx r0 = d[q];
+        Cx v = r0;
+        if (!rhs_has_mass) {
+          const Cx ru = (q == MR - 1) ? right : d[q < MR - 1 ? q + 1 : q];
+          v = Cx{cf.md * r0.re + cf.ml * rl.re + cf.mu * ru.re,
+                 cf.md * r0.im + cf.ml * rl.im + cf.mu * ru.im};
+        }
+        if constexpr (MODE == 1) v.re += mx[q];
+        rl = r0;
+        d[q] = v;
+      }
+    }
+    Cx *lfac = facb + ((size_t)buf * spb + g) * NFP;
+    __syncthreads();   // every thread has read the staging area
+    if (item + nblk < nitems) issue(item + nblk, buf ^ 1);
+
+    // waves of whole chunks take a copy without the ragged-chunk guards (at
+    // 16 rows per thread the second copy would not fit in registers)
+    if (MR <= 8 && __all(len == MR))
+      partition_solve<R, MR>(d, MR, lt, P, lfac, xch, ca, cc);
+    else
+      partition_solve<R, MR>(d, len, lt, P, lfac, xch, ca, cc);
+
+    if constexpr (MODE == 1) {
+      if (active) {
+        Cx *dst = out + (size_t)k * n + s0;
+#pragma unroll
+        for (int q = 0; q < MR; ++q)
+          if (q < len) dst[q] = d[q];
+      }
+    } else {
+      // rows past n collect values that are never read
+      if (active) {
+#pragma unroll
+        for (int q = 0; q < MR; ++q) acc[q] += gr * d[q].re - gi * d[q].im;
+      }
+    }
+  }
+
+  if constexpr (MODE != 1) {
+    __syncthreads();
+    double *sd = reinterpret_cast<double *>(smem_raw) + (size_t)g * rows;
+#pragma unroll
+    for (int q = 0; q < MR; ++q) sd[s0 + q] = acc[q];
+    __syncthreads();
+    const double *base = reinterpret_cast<double *>(smem_raw);
+    for (int i = tid; i < n; i += blockDim.x) {
+      double s = 0.0;
+      for (int gg = 0; gg < spb; ++gg) s += base[(size_t)gg * rows + i];
+      partials[(size_t)blk * n + i] = s;
+    }
+  }
+}
+
+template <int MR, int MODE>
+__global__ void __launch_bounds__(512)
+tridiag_pipe_kernel(int n, int F2, int P, int spb, int nitems, Coef<double> cf,
+                    const double *__restrict__ coef64, const double *__restrict__ lam,
+                    const cpx<double> *__restrict__ fac, const double *__restrict__ gw,
+                    const cpx<double> *__restrict__ in, const double *__restrict__ vin,
+                    const double *__restrict__ xv, double wscale, int rhs_has_mass,
+                    cpx<double> *__restrict__ out, double *__restrict__ partials) {
+  tridiag_pipe_body<MR, MODE>(blockIdx.x, gridDim.x, n, F2, P, spb, nitems, cf, coef64, lam, fac,
+                              gw, in, vin, xv, wscale, rhs_has_mass, out, partials);
+}
+
 // Uniform-coefficient fast path (constant diagonals: uniform grids).  The
 // elimination factors are precomputed per plan (pd_partition.h); rows >= n
 // are absent, so the last chunk may be ragged and chunks past the end empty.
@@ -527,6 +712,18 @@ __global__ void reduce_partials_kernel(int n, int G, const double *__restrict__ 
   out[i] = (base ? base[i] : 0.0) + s;
 }
 
+template <typename R, int MR, int M>
+void launch_pipe(pd_plan p, int G, int nitems, const Coef<R> &cf, const R *lam,
+                 const cpx<R> *fac, const double *gw, const cpx<R> *cin, const double *vin,
+                 const double *x, int has_mass, cpx<R> *o, double *part) {
+  if constexpr (sizeof(R) == 8) {
+    const TriConfig &T = p->tri;
+    hipLaunchKernelGGL((tridiag_pipe_kernel<MR, M>), dim3(G), dim3(T.block), T.lds, p->stream,
+                       p->n, p->F2, T.P, T.spb, nitems, cf, p->coef64, lam, fac, gw, cin, vin, x,
+                       p->w, has_mass, o, part);
+  }
+}
+
 template <typename R, int MR, bool UNI>
 pd_status launch_mr(pd_plan p, int mode, const void *in, const double *xv, void *out) {
   const TriConfig &T = p->tri;
@@ -557,9 +754,12 @@ pd_status launch_mr(pd_plan p, int mode, const void *in, const double *xv, void 
   const double *x = (mode == 1) ? xv : nullptr;
   cpx<R> *o = (mode == 1) ? cout : nullptr;
   double *part = (mode == 1) ? nullptr : p->partials;
+  const int Gp = nitems < p->tri_G ? nitems : p->tri_G;   // pipelined body: every mode
 #define PD_TRI_LAUNCH(M)                                                                     \
   do {                                                                                       \
-    if (UNI && T.block <= 512)                                                               \
+    if (UNI && T.pipe)                                                                       \
+      launch_pipe<R, MR, M>(p, Gp, nitems, cf, lam, fac, gw, cin, vin, x, has_mass, o, part);  \
+    else if (UNI && T.block <= 512)                                                          \
       hipLaunchKernelGGL((tridiag_uniform_kernel<R, MR, M, 512>), dim3(G), dim3(T.block),    \
                          T.lds, p->stream, n, p->F2, T.P, T.spb, nitems, cf, p->coef64,       \
                          lam, fac, gw, cin, vin, x, p->w, has_mass, o, part);                \
@@ -602,18 +802,26 @@ TriConfig pd_choose_tri(int n, int F2, int prec, size_t max_lds) {
   const int BT = pd_tri_block_threads(prec);
   int spb = (P >= 16) ? BT / P : 64;   // tiny systems: 64 per block
   if (spb < 1) spb = 1;
+  // complex128 systems of whole waves use the pipelined body: staging for one
+  // item, a separate PCR exchange area and two factor buffers
+  T.pipe = (prec == PD_FP64 && P >= 64) ? 1 : 0;
   auto lds_for = [&](int s) {
     const size_t rows = (size_t)P * MR;
     size_t region = (size_t)s * (rows + 2) * cb;
     region = std::max(region, (size_t)s * rows * sizeof(double));
     region = std::max(region, (size_t)s * P * 3 * cb);
     region = (region + 15) & ~(size_t)15;
-    return region + (size_t)s * 6 * (MR - 1) * cb;
+    size_t need = region + (size_t)s * 6 * (MR - 1) * cb;
+    if (T.pipe) {
+      const size_t nfp = (size_t)(6 * (MR - 1) + 63) / 64 * 64;
+      need = std::max(need, (size_t)s * (rows * cb + (size_t)P * 3 * cb + 2 * nfp * cb));
+    }
+    return need;
   };
   while (spb > 1 && lds_for(spb) > max_lds) spb /= 2;
   T.spb = spb;
   T.block = P * spb;
-  T.lds = lds_for(spb);   // staging / partial sums / PCR exchange + factor table
+  T.lds = lds_for(spb);   // staging / partial sums / PCR exchange + factor tables
   return T;
 }
 
@@ -692,6 +900,11 @@ void set_attr_mr(int v) {
                         reinterpret_cast<const void *>(&tridiag_uniform_kernel<R, MR, 2, 512>)};
   for (const void *f : fns)
     pd_set_max_lds(f, v);
+  if constexpr (sizeof(R) == 8) {
+    pd_set_max_lds(reinterpret_cast<const void *>(&tridiag_pipe_kernel<MR, 0>), v);
+    pd_set_max_lds(reinterpret_cast<const void *>(&tridiag_pipe_kernel<MR, 1>), v);
+    pd_set_max_lds(reinterpret_cast<const void *>(&tridiag_pipe_kernel<MR, 2>), v);
+  }
 }
 }  // namespace
 
@@ -717,6 +930,18 @@ tridiag_batch_kernel(const TriJob *__restrict__ jobs, const int2 *__restrict__ m
   cf.ML = cf.MD = cf.MU = cf.KL = cf.KD = cf.KU = nullptr;
   cf.ml = (R)j.ml; cf.md = (R)j.md; cf.mu = (R)j.mu;
   cf.kl = (R)j.kl; cf.kd = (R)j.kd; cf.ku = (R)j.ku;
+  if constexpr (sizeof(R) == 8) {
+    if (j.P >= 64) {   // the single-problem path's pipelined body (TriConfig::pipe)
+      tridiag_pipe_body<MR, MODE>(m.y, j.nblk, j.n, j.F2, j.P, j.spb, j.nitems, cf, j.coef64,
+                                  reinterpret_cast<const double *>(j.lam),
+                                  reinterpret_cast<const cpx<double> *>(j.fac), j.gw,
+                                  reinterpret_cast<const cpx<double> *>(j.in),
+                                  j.vin ? j.vin + (size_t)jv * j.n : nullptr, j.xv, j.wscale,
+                                  j.has_mass, reinterpret_cast<cpx<double> *>(j.out),
+                                  j.partials);
+      return;
+    }
+  }
   tridiag_uniform_body<R, MR, MODE>(m.y, j.nblk, j.n, j.F2, j.P, j.spb, j.nitems, cf, j.coef64,
                                     reinterpret_cast<const R *>(j.lam),
                                     reinterpret_cast<const cpx<R> *>(j.fac), j.gw,
