@@ -20,6 +20,20 @@ FLAGS = ["-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC",
          "-Wno-unused-result"]
 
 
+def source_hash() -> str:
+    """sha256 over the native sources and this build script: a recorded
+    hardware-counter reading is valid only for the kernels it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
+                   if f.endswith((".hip", ".h")))
+    for path in files + [os.path.abspath(__file__)]:
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
