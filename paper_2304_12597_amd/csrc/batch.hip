@@ -74,7 +74,7 @@ pd_status pd_solve_batch_impl(const pd_plan *plans, int count, const double *con
     const int BT = pd_tri_block_threads(prec);
     if (P > BT) return PD_ENOTSUP;
     t.n = p->n; t.F2 = p->F2; t.P = P; t.spb = BT / P;
-    t.nitems = (p->F2 + t.spb - 1) / t.spb;
+    t.nitems = pd_tri_nitems(p->tri, p->F2);
     t.nblk = std::min(t.nitems, p->tri_G);
     t.has_mass = 0;
     t.ml = p->uni[0]; t.md = p->uni[1]; t.mu = p->uni[2];

@@ -250,6 +250,13 @@ int pd_fft_blocks(pd_plan p);
 int pd_vec_blocks(int n);
 size_t pd_gmres_state_doubles(int maxit);
 int pd_choose_fft_C(int ell, int nbar, int prec, size_t max_lds);
+// Work items of a shifted-solve launch: the pipelined body pairs the two real
+// shifts k = 0 and k = ell/2 into one item (slot 0), so F2 - 1 slots.
+inline int pd_tri_nitems(const TriConfig &T, int F2) {
+  const int slots = T.pipe ? F2 - 1 : F2;
+  return (slots + T.spb - 1) / T.spb;
+}
+
 // Threads per shifted-solve block: 512 for complex128 (a 256-register budget
 // per thread keeps the partition solve out of scratch), 1024 otherwise.
 inline int pd_tri_block_threads(int prec) { return prec == PD_FP64 ? 512 : 1024; }

@@ -29,7 +29,33 @@ struct Row3 {
   cpx<R> a, c, d;   // normalised row:  a x_lo + x + c x_hi = d
 };
 
-template <typename R, int MR>
+// Arithmetic of one complex system ...
+template <typename R>
+struct CplxOps {
+  static __device__ __forceinline__ cpx<R> mul(cpx<R> a, cpx<R> b) { return cmul(a, b); }
+  static __device__ __forceinline__ cpx<R> fms(cpx<R> a, cpx<R> b, cpx<R> c) {
+    return cfms(a, b, c);
+  }
+  static __device__ __forceinline__ cpx<R> recip(cpx<R> a) { return crecip(a); }
+  static __device__ __forceinline__ cpx<R> one() { return cpx<R>{R(1), R(0)}; }
+};
+// ... or of two independent real systems held in the real and imaginary
+// parts (the real shifts k = 0 and k = ell/2 share one work item)
+template <typename R>
+struct DualOps {
+  static __device__ __forceinline__ cpx<R> mul(cpx<R> a, cpx<R> b) {
+    return cpx<R>{a.re * b.re, a.im * b.im};
+  }
+  static __device__ __forceinline__ cpx<R> fms(cpx<R> a, cpx<R> b, cpx<R> c) {
+    return cpx<R>{a.re - b.re * c.re, a.im - b.im * c.im};
+  }
+  static __device__ __forceinline__ cpx<R> recip(cpx<R> a) {
+    return cpx<R>{R(1) / a.re, R(1) / a.im};
+  }
+  static __device__ __forceinline__ cpx<R> one() { return cpx<R>{R(1), R(1)}; }
+};
+
+template <typename R, int MR, typename A = CplxOps<R>>
 __device__ __forceinline__ void partition_solve(cpx<R> (&d)[MR], int len, int lt, int P,
                                                 const cpx<R> *lfac, Row3<R> *xch,
                                                 cpx<R> ca, cpx<R> cc) {
@@ -41,7 +67,7 @@ __device__ __forceinline__ void partition_solve(cpx<R> (&d)[MR], int len, int lt
     if (q <= L2 - 2) {
       const int dl = L2 - 1 - q;
       const cpx<R> r = lfac[(dl - 1) * 6 + 0];
-      ud = (dl == 1) ? cmul(d[q], r) : cmul(cfms(d[q], cc, ud), r);
+      ud = (dl == 1) ? A::mul(d[q], r) : A::mul(A::fms(d[q], cc, ud), r);
     }
   }
   cpx<R> ua = lfac[(L2 - 2) * 6 + 1], uc = lfac[(L2 - 2) * 6 + 2];
@@ -50,7 +76,7 @@ __device__ __forceinline__ void partition_solve(cpx<R> (&d)[MR], int len, int lt
   for (int q = 1; q < MR; ++q) {
     if (q < len) {
       const cpx<R> r = lfac[(q - 1) * 6 + 3];
-      d[q] = (q == 1) ? cmul(d[q], r) : cmul(cfms(d[q], ca, d[q - 1]), r);
+      d[q] = (q == 1) ? A::mul(d[q], r) : A::mul(A::fms(d[q], ca, d[q - 1]), r);
       if (q == len - 1) {
         Ae = lfac[(q - 1) * 6 + 4];
         Ce = lfac[(q - 1) * 6 + 5];
@@ -68,15 +94,15 @@ __device__ __forceinline__ void partition_solve(cpx<R> (&d)[MR], int len, int lt
   nx.a = pd_sel(hasnx, nx.a, zero);
   nx.c = pd_sel(hasnx, nx.c, zero);
   nx.d = pd_sel(hasnx, nx.d, zero);
-  cpx<R> al = cneg(cmul(Ae, ua));
-  cpx<R> be = csub(csub(cpx<R>{R(1), R(0)}, cmul(Ae, uc)), cmul(Ce, nx.a));
-  cpx<R> ga = cneg(cmul(Ce, nx.c));
-  cpx<R> de = csub(csub(De, cmul(Ae, ud)), cmul(Ce, nx.d));
+  cpx<R> al = cneg(A::mul(Ae, ua));
+  cpx<R> be = csub(csub(A::one(), A::mul(Ae, uc)), A::mul(Ce, nx.a));
+  cpx<R> ga = cneg(A::mul(Ce, nx.c));
+  cpx<R> de = csub(csub(De, A::mul(Ae, ud)), A::mul(Ce, nx.d));
   {
-    const cpx<R> rb = crecip(be);
-    al = cmul(al, rb);
-    ga = cmul(ga, rb);
-    de = cmul(de, rb);
+    const cpx<R> rb = A::recip(be);
+    al = A::mul(al, rb);
+    ga = A::mul(ga, rb);
+    de = A::mul(de, rb);
   }
   for (int st = 1; st < P; st <<= 1) {
     __syncthreads();
@@ -87,26 +113,26 @@ __device__ __forceinline__ void partition_solve(cpx<R> (&d)[MR], int len, int lt
     const bool haslo = lt >= st, hashi = lt + st < P;
     lo.a = pd_sel(haslo, lo.a, zero); lo.c = pd_sel(haslo, lo.c, zero); lo.d = pd_sel(haslo, lo.d, zero);
     hi.a = pd_sel(hashi, hi.a, zero); hi.c = pd_sel(hashi, hi.c, zero); hi.d = pd_sel(hashi, hi.d, zero);
-    const cpx<R> nb = csub(csub(cpx<R>{R(1), R(0)}, cmul(al, lo.c)), cmul(ga, hi.a));
-    const cpx<R> nd = csub(csub(de, cmul(al, lo.d)), cmul(ga, hi.d));
-    const cpx<R> na = cneg(cmul(al, lo.a));
-    const cpx<R> ng = cneg(cmul(ga, hi.c));
-    const cpx<R> rb = crecip(nb);
-    al = cmul(na, rb);
-    ga = cmul(ng, rb);
-    de = cmul(nd, rb);
+    const cpx<R> nb = csub(csub(A::one(), A::mul(al, lo.c)), A::mul(ga, hi.a));
+    const cpx<R> nd = csub(csub(de, A::mul(al, lo.d)), A::mul(ga, hi.d));
+    const cpx<R> na = cneg(A::mul(al, lo.a));
+    const cpx<R> ng = cneg(A::mul(ga, hi.c));
+    const cpx<R> rb = A::recip(nb);
+    al = A::mul(na, rb);
+    ga = A::mul(ng, rb);
+    de = A::mul(nd, rb);
   }
   const cpx<R> xe = pd_sel(len >= 2, de, zero);
   __syncthreads();
   xch[lt].d = xe;
   __syncthreads();
   const cpx<R> xprev = pd_sel(lt > 0, xch[lt > 0 ? lt - 1 : 0].d, zero);
-  const cpx<R> xs = csub(csub(ud, cmul(ua, xprev)), cmul(uc, xe));
+  const cpx<R> xs = csub(csub(ud, A::mul(ua, xprev)), A::mul(uc, xe));
   cpx<R> ynext = xe;
 #pragma unroll
   for (int q = MR - 2; q >= 1; --q) {
     if (q <= len - 2) {
-      d[q] = csub(csub(d[q], cmul(lfac[(q - 1) * 6 + 4], xs)), cmul(lfac[(q - 1) * 6 + 5], ynext));
+      d[q] = csub(csub(d[q], A::mul(lfac[(q - 1) * 6 + 4], xs)), A::mul(lfac[(q - 1) * 6 + 5], ynext));
       ynext = d[q];
     }
   }

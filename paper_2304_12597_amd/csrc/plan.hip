@@ -106,7 +106,8 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
     pd_set_error("shifted-solve tile does not fit in LDS");
     return PD_ENOTSUP;
   }
-  const int nitems = (F2 + p->tri.spb - 1) / p->tri.spb;
+  if (!(p->dims == 1 && p->uniform)) p->tri.pipe = 0;
+  const int nitems = pd_tri_nitems(p->tri, F2);
   p->tri_G = nitems < cus ? nitems : cus;
   L.partials = (size_t)p->tri_G * n;
   L.rstage = (size_t)((p->tri_G + 15) / 16) * n;
@@ -128,7 +129,7 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
     if ((size_t)p->l2d.nkc * p->nbar > L.partials) L.partials = (size_t)p->l2d.nkc * p->nbar;
     L.rstage = std::max(L.rstage, (size_t)((p->l2d.nkc + 15) / 16) * p->nbar);
   } else if (p->uniform) {
-    L.fac = (size_t)F2 * 6 * (p->tri.MR - 1) * 2;
+    L.fac = (size_t)(F2 + 1) * 6 * (p->tri.MR - 1) * 2;   // + the paired real shifts
   }
   L.coef = 6 * (size_t)n;
   L.lam = 2 * (size_t)F2;

@@ -24,6 +24,7 @@
 #include "pd_partition.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace {
 
@@ -496,6 +497,13 @@ __device__ __forceinline__ void tridiag_uniform_body(
 // scalar loads, which do not wait for the vector-memory counter.  Mode 1
 // stores each thread's rows straight from registers.
 //
+// Work item slot 0 pairs the two real shifts k = 0 and k = ell/2 (real
+// matrices, real right-hand sides): system k = 0 runs in the real parts and
+// k = ell/2 in the imaginary parts with componentwise arithmetic (DualOps,
+// factor row F2), so F2 - 1 items cover the half spectrum; slot s >= 1 is
+// k = s.  Slot 0 reads its right-hand side directly instead of through the
+// staging area.
+//
 // LDS: [spb*P*MR cpx stage][spb*P Row3 exchange][2*spb*NFP cpx factors]
 template <int MR>
 constexpr int pipe_nfp() { return (6 * (MR - 1) + 63) / 64 * 64; }
@@ -513,6 +521,9 @@ __device__ __forceinline__ void tridiag_pipe_body(
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int NF = 6 * (MR - 1);
   constexpr int NFP = pipe_nfp<MR>();
+  // 16 rows per thread (one system per block): the paired item runs in block
+  // 0's prologue, so the item loop holds a single copy of the partition solve
+  constexpr bool PAIR_FIRST = (MR == 16);
   const int tid = threadIdx.x;
   const int g = tid / P;
   const int lt = tid - g * P;
@@ -527,6 +538,7 @@ __device__ __forceinline__ void tridiag_pipe_body(
   int len = n - s0;
   len = len < 0 ? 0 : (len > MR ? MR : len);
   const Cx zero = {0.0, 0.0};
+  const int nslots = F2 - 1;
 
   double acc[(MODE == 1) ? 1 : MR];
   R mx[(MODE == 1) ? MR : 1];
@@ -553,19 +565,21 @@ __device__ __forceinline__ void tridiag_pipe_body(
   }
   __syncthreads();   // the staging area is free for the DMA
 
-  // DMA of item `item`'s right-hand side and factors into factor buffer b
-  auto issue = [&](int item, int b) {
-    const int k0 = item * spb + g;
-    const int k = k0 < F2 ? k0 : F2 - 1;
+  // DMA of a slot's right-hand side (not for slot 0, read directly) and of
+  // its factors into factor buffer b
+  auto issue = [&](int slot_in, int b) {
+    const int sl = slot_in < nslots ? slot_in : nslots - 1;
     if constexpr (MODE != 2) {
-      const Cx *src = in + (size_t)k * n;
+      if (sl != 0) {
+        const Cx *src = in + (size_t)sl * n;
 #pragma unroll
-      for (int q = 0; q < MR; ++q) {
-        const int r = s0 + q < n ? s0 + q : n - 1;
-        pd_lds_dma16(src + r, stage + q * P + wib * 64);
+        for (int q = 0; q < MR; ++q) {
+          const int r = s0 + q < n ? s0 + q : n - 1;
+          pd_lds_dma16(src + r, stage + q * P + wib * 64);
+        }
       }
     }
-    const Cx *fsrc = fac + (size_t)k * NF;
+    const Cx *fsrc = fac + (size_t)(sl == 0 ? F2 : sl) * NF;
     Cx *fdst = facb + ((size_t)b * spb + g) * NFP;
     for (int c0 = wib * 64; c0 < NFP; c0 += P) {
       const int idx = c0 + (lt & 63);
@@ -573,33 +587,53 @@ __device__ __forceinline__ void tridiag_pipe_body(
     }
   };
 
-  int buf = 0;
-  if (blk < nitems) issue(blk, 0);
-  for (int item = blk; item < nitems; item += nblk, buf ^= 1) {
-    const int k0 = __builtin_amdgcn_readfirstlane(item * spb + g);
-    const bool active = k0 < F2;
-    const int k = active ? k0 : F2 - 1;
-    const R lr = lam[2 * k], li = lam[2 * k + 1];
-    double gr = 0.0, gi = 0.0;
+  // One work item: right-hand side, solve, output.  OPS = CplxOps (slot k)
+  // or DualOps (slot 0: k = 0 in the real parts, k = ell/2 in the imaginary
+  // parts).  The caller has made the item's data visible in LDS; `sync`
+  // runs between the last read of the staging area and the solve.
+  auto work = [&](auto ops, int slot, const Cx *lfac, auto sync) {
+    using OPS = decltype(ops);
+    constexpr bool DUAL = std::is_same<OPS, DualOps<R>>::value;
+    const bool active = slot < nslots;
+    const int k = active ? slot : nslots - 1;
+    const int kB = DUAL ? F2 - 1 : k;
+    const R lr = lam[2 * k], li = lam[2 * k + 1], lrB = lam[2 * kB];
+    double gr = 0.0, gi = 0.0, grB = 0.0;
     if constexpr (MODE != 1) {
       gr = gw[2 * k];
       gi = gw[2 * k + 1];
+      grB = gw[2 * kB];
     }
-    const Cx ca = {lr * cf.ml + cf.kl, li * cf.ml};   // sub-diagonal
-    const Cx cc = {lr * cf.mu + cf.ku, li * cf.mu};   // super-diagonal
-    pd_wait_all();
-    __syncthreads();   // this item's right-hand side and factors have landed
-
+    // sub- and super-diagonals: complex, or (k = 0, k = ell/2) componentwise
+    const Cx ca = DUAL ? Cx{lr * cf.ml + cf.kl, lrB * cf.ml + cf.kl}
+                       : Cx{lr * cf.ml + cf.kl, li * cf.ml};
+    const Cx cc = DUAL ? Cx{lr * cf.mu + cf.ku, lrB * cf.mu + cf.ku}
+                       : Cx{lr * cf.mu + cf.ku, li * cf.mu};
     Cx d[MR];
     if constexpr (MODE == 2) {
 #pragma unroll
-      for (int q = 0; q < MR; ++q) d[q] = Cx{dv[q], R(0)};
+      for (int q = 0; q < MR; ++q) d[q] = Cx{dv[q], DUAL ? dv[q] : R(0)};
     } else {
+      Cx left, right;
+      if constexpr (DUAL) {
+        // real parts of rows k = 0 and k = ell/2, read directly
+        const Cx *ra = in, *rb = in + (size_t)(F2 - 1) * n;
 #pragma unroll
-      for (int q = 0; q < MR; ++q) d[q] = pd_sel(q < len, stage[q * P + lt], zero);
-      const Cx left = pd_sel(lt > 0, stage[(MR - 1) * P + (lt > 0 ? lt - 1 : 0)], zero);
-      const Cx right =
-          pd_sel(s0 + MR < n && lt + 1 < P, stage[lt + 1 < P ? lt + 1 : lt], zero);
+        for (int q = 0; q < MR; ++q) {
+          const int r = s0 + q < n ? s0 + q : n - 1;
+          d[q] = pd_sel(q < len, Cx{ra[r].re, rb[r].re}, zero);
+        }
+        // neighbour rows, clamped to [0, n) (threads past the end have s0 > n)
+        const int rl = (lt > 0 && s0 - 1 < n) ? s0 - 1 : 0;
+        const int rr = s0 + MR < n ? s0 + MR : n - 1;
+        left = pd_sel(lt > 0, Cx{ra[rl].re, rb[rl].re}, zero);
+        right = pd_sel(s0 + MR < n, Cx{ra[rr].re, rb[rr].re}, zero);
+      } else {
+#pragma unroll
+        for (int q = 0; q < MR; ++q) d[q] = pd_sel(q < len, stage[q * P + lt], zero);
+        left = pd_sel(lt > 0, stage[(MR - 1) * P + (lt > 0 ? lt - 1 : 0)], zero);
+        right = pd_sel(s0 + MR < n && lt + 1 < P, stage[lt + 1 < P ? lt + 1 : lt], zero);
+      }
       // right-hand side d = M r (- w M x), formed in place; ghost rows are zero
       Cx rl = left;
 #pragma unroll
@@ -611,36 +645,75 @@ __device__ __forceinline__ void tridiag_pipe_body(
           v = Cx{cf.md * r0.re + cf.ml * rl.re + cf.mu * ru.re,
                  cf.md * r0.im + cf.ml * rl.im + cf.mu * ru.im};
         }
-        if constexpr (MODE == 1) v.re += mx[q];
+        if constexpr (MODE == 1) {
+          v.re += mx[q];
+          if (DUAL) v.im += mx[q];
+        }
         rl = r0;
         d[q] = v;
       }
     }
-    Cx *lfac = facb + ((size_t)buf * spb + g) * NFP;
-    __syncthreads();   // every thread has read the staging area
-    if (item + nblk < nitems) issue(item + nblk, buf ^ 1);
-
+    sync();
     // waves of whole chunks take a copy without the ragged-chunk guards (at
     // 16 rows per thread the second copy would not fit in registers)
-    if (MR <= 8 && __all(len == MR))
-      partition_solve<R, MR>(d, MR, lt, P, lfac, xch, ca, cc);
+    if (!DUAL && MR <= 8 && __all(len == MR))
+      partition_solve<R, MR, OPS>(d, MR, lt, P, lfac, xch, ca, cc);
     else
-      partition_solve<R, MR>(d, len, lt, P, lfac, xch, ca, cc);
+      partition_solve<R, MR, OPS>(d, len, lt, P, lfac, xch, ca, cc);
 
     if constexpr (MODE == 1) {
       if (active) {
-        Cx *dst = out + (size_t)k * n + s0;
+        if constexpr (DUAL) {
+          Cx *da = out + s0, *db = out + (size_t)(F2 - 1) * n + s0;
 #pragma unroll
-        for (int q = 0; q < MR; ++q)
-          if (q < len) dst[q] = d[q];
+          for (int q = 0; q < MR; ++q)
+            if (q < len) {
+              da[q] = Cx{d[q].re, R(0)};
+              db[q] = Cx{d[q].im, R(0)};
+            }
+        } else {
+          Cx *dst = out + (size_t)k * n + s0;
+#pragma unroll
+          for (int q = 0; q < MR; ++q)
+            if (q < len) dst[q] = d[q];
+        }
       }
     } else {
       // rows past n collect values that are never read
       if (active) {
 #pragma unroll
-        for (int q = 0; q < MR; ++q) acc[q] += gr * d[q].re - gi * d[q].im;
+        for (int q = 0; q < MR; ++q)
+          acc[q] += DUAL ? gr * d[q].re + grB * d[q].im : gr * d[q].re - gi * d[q].im;
       }
     }
+  };
+
+  int item = blk, buf = 0;
+  if (PAIR_FIRST && blk == 0) {
+    // slot 0 first: its factors into buffer 1 while the next item's data
+    // (buffer 0) streams in behind it
+    issue(0, 1);
+    if (nblk < nitems) issue(nblk, 0);
+    pd_wait_all();
+    __syncthreads();
+    work(DualOps<R>{}, 0, facb + ((size_t)1 * spb + g) * NFP, [] {});
+    item = nblk;
+  } else if (blk < nitems) {
+    issue(item * spb + g, 0);
+  }
+  for (; item < nitems; item += nblk, buf ^= 1) {
+    const int slot = __builtin_amdgcn_readfirstlane(item * spb + g);
+    pd_wait_all();
+    __syncthreads();   // this item's right-hand side and factors have landed
+    const Cx *lfac = facb + ((size_t)buf * spb + g) * NFP;
+    auto sync = [&] {
+      __syncthreads();   // every thread has read the staging area
+      if (item + nblk < nitems) issue((item + nblk) * spb + g, buf ^ 1);
+    };
+    if (!PAIR_FIRST && slot == 0)
+      work(DualOps<R>{}, slot, lfac, sync);
+    else
+      work(CplxOps<R>{}, slot, lfac, sync);
   }
 
   if constexpr (MODE != 1) {
@@ -718,6 +791,7 @@ void launch_pipe(pd_plan p, int G, int nitems, const Coef<R> &cf, const R *lam,
                  const double *x, int has_mass, cpx<R> *o, double *part) {
   if constexpr (sizeof(R) == 8) {
     const TriConfig &T = p->tri;
+    if (MR == 16 && T.spb != 1) return;   // excluded by the caller's check
     hipLaunchKernelGGL((tridiag_pipe_kernel<MR, M>), dim3(G), dim3(T.block), T.lds, p->stream,
                        p->n, p->F2, T.P, T.spb, nitems, cf, p->coef64, lam, fac, gw, cin, vin, x,
                        p->w, has_mass, o, part);
@@ -740,7 +814,7 @@ pd_status launch_mr(pd_plan p, int mode, const void *in, const double *xv, void 
                                   : reinterpret_cast<const R *>(p->lam32);
   const cpx<R> *fac = (sizeof(R) == 8) ? reinterpret_cast<const cpx<R> *>(p->fac64)
                                        : reinterpret_cast<const cpx<R> *>(p->fac32);
-  const int nitems = (p->F2 + T.spb - 1) / T.spb;
+  const int nitems = pd_tri_nitems(T, p->F2);
   const cpx<R> *cin = reinterpret_cast<const cpx<R> *>(in);
   cpx<R> *cout = reinterpret_cast<cpx<R> *>(out);
   const int has_mass = (mode & 0x100) ? 1 : 0;
@@ -755,6 +829,12 @@ pd_status launch_mr(pd_plan p, int mode, const void *in, const double *xv, void 
   cpx<R> *o = (mode == 1) ? cout : nullptr;
   double *part = (mode == 1) ? nullptr : p->partials;
   const int Gp = nitems < p->tri_G ? nitems : p->tri_G;   // pipelined body: every mode
+  if (UNI && T.pipe && MR == 16 && T.spb != 1) {
+    // the 16-row body pairs the real shifts in block 0's prologue: one
+    // system per block
+    pd_set_error("shifted solve: unsupported packing");
+    return PD_ENOTSUP;
+  }
 #define PD_TRI_LAUNCH(M)                                                                     \
   do {                                                                                       \
     if (UNI && T.pipe)                                                                       \
@@ -848,22 +928,29 @@ pd_status pd_launch_tridiag(pd_plan p, int mode, const void *in, const double *x
 }
 
 // Elimination factors of the uniform path (float64), 6 complex values per
-// (frequency k, distance 1..MR-1); see pd_partition.h.
+// (frequency k, distance 1..MR-1); see pd_partition.h.  Row F2 holds the
+// paired real shifts k = 0 (real parts) and k = ell/2 (imaginary parts).
 void pd_uniform_factors(const pd_plan p, int MR, std::vector<double> &fac) {
   const int F2 = p->F2;
   const size_t NF = 6 * (size_t)(MR - 1);
-  fac.assign((size_t)F2 * NF * 2, 0.0);
+  fac.assign((size_t)(F2 + 1) * NF * 2, 0.0);
   const double *u = p->uni;
   for (int k = 0; k < F2; ++k) {
     const double lr = p->lam[2 * k], li = p->lam[2 * k + 1];
     pd_partition_factors(lr * u[0] + u[3], li * u[0], lr * u[1] + u[4], li * u[1],
                          lr * u[2] + u[5], li * u[2], MR, &fac[(size_t)k * NF * 2]);
   }
+  double *dual = &fac[(size_t)F2 * NF * 2];
+  const double *f0 = &fac[0], *fl = &fac[(size_t)(F2 - 1) * NF * 2];
+  for (size_t j = 0; j < NF; ++j) {
+    dual[2 * j] = f0[2 * j];
+    dual[2 * j + 1] = fl[2 * j];
+  }
 }
 
 pd_status pd_launch_reduce_partials(pd_plan p, const double *base, double *out) {
   const int n = p->nbar;
-  const int nitems = (p->F2 + p->tri.spb - 1) / p->tri.spb;
+  const int nitems = pd_tri_nitems(p->tri, p->F2);
   int G = nitems < p->tri_G ? nitems : p->tri_G;
   if (p->dims == 2) G = p->l2d.nkc;
   if (G > RS) {
