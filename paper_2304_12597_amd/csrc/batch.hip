@@ -185,16 +185,24 @@ pd_status pd_solve_batch_impl(const pd_plan *plans, int count, const double *con
     nact += act[i];
   }
   const double rtol = tol * PD_GMRES_TOL_FACTOR;
+  // 1D problems of at most pd_gmres_fused_max_n() unknowns take the fused
+  // Arnoldi step, as they do when solved alone
+  bool fused = true;
+  for (int i = 0; i < count; ++i) fused = fused && plans[i]->nbar <= pd_gmres_fused_max_n();
   for (int j = 0; j < MX && nact > 0; ++j) {
     PD_HIP_CHECK(hipMemcpyAsync(d_act, act.data(), count * sizeof(int), hipMemcpyHostToDevice, s));
     PD_B(pd_launch_tridiag_batch(prec, MR, 2, d_tjJ, d_t0, n0, tri_lds, d_act, j, s));
     PD_B(pd_launch_reduce_batch(d_vj, d_rm, nr, j, d_act, s));
-    PD_B(pd_gmres_batch_dots(d_vj, d_vm, nv, j + 1, 0, d_act, s));
-    PD_B(pd_gmres_batch_update(d_vj, d_vm, nv, j + 1, j, MX, 1, d_act, s));
-    PD_B(pd_gmres_batch_update(d_vj, d_vm, nv, j + 1, j, MX, 2, d_act, s));
-    PD_B(pd_gmres_batch_dots(d_vj, d_vm, nv, 0, 0, d_act, s));
-    PD_B(pd_gmres_batch_givens(d_vj, count, j, MX, d_st, d_act, s));
-    PD_B(pd_gmres_batch_scale(d_vj, d_vm, nv, j, MX, 0, d_act, s));
+    if (fused) {
+      PD_B(pd_gmres_batch_arnoldi(d_vj, count, j, MX, rtol, d_st, d_act, s));
+    } else {
+      PD_B(pd_gmres_batch_dots(d_vj, d_vm, nv, j + 1, 0, d_act, s));
+      PD_B(pd_gmres_batch_update(d_vj, d_vm, nv, j + 1, j, MX, 1, d_act, s));
+      PD_B(pd_gmres_batch_update(d_vj, d_vm, nv, j + 1, j, MX, 2, d_act, s));
+      PD_B(pd_gmres_batch_dots(d_vj, d_vm, nv, 0, 0, d_act, s));
+      PD_B(pd_gmres_batch_givens(d_vj, count, j, MX, d_st, d_act, s));
+      PD_B(pd_gmres_batch_scale(d_vj, d_vm, nv, j, MX, 0, d_act, s));
+    }
     PD_HIP_CHECK(hipMemcpyAsync(hst.data(), d_st, hst.size() * sizeof(double),
                                 hipMemcpyDeviceToHost, s));
     PD_HIP_CHECK(hipStreamSynchronize(s));

@@ -21,7 +21,8 @@ constexpr int VB = 256;   // threads per block of the vector kernels
 
 // gm layout (doubles), MX = maxit:
 //   H   [MX][MX+1] column-major (H[j*(MX+1) + i])
-//   cs  [MX], sn [MX], g [MX+1], y [MX], status [4]
+//   cs  [MX], sn [MX], g [MX+1], y [MX],
+//   status [6]: residual estimate, h_{j+1,j}, iterations, beta, converged flag
 struct GmLayout {
   int MX;
   __host__ __device__ int H(int i, int j) const { return j * (MX + 1) + i; }
@@ -30,8 +31,9 @@ struct GmLayout {
   __host__ __device__ int g(int i) const { return MX * (MX + 1) + 2 * MX + i; }
   __host__ __device__ int y(int i) const { return MX * (MX + 1) + 3 * MX + 1 + i; }
   __host__ __device__ int st(int i) const { return MX * (MX + 1) + 4 * MX + 1 + i; }
-  __host__ __device__ int size() const { return MX * (MX + 1) + 4 * MX + 1 + 4; }
+  __host__ __device__ int size() const { return MX * (MX + 1) + 4 * MX + 1 + 6; }
 };
+constexpr int GM_DONE = 4;   // status slot of the converged flag
 
 __device__ __forceinline__ double block_sum(double v, double *sh) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -159,10 +161,13 @@ __global__ void init_kernel(int nblk, const double *__restrict__ red, double *__
     gm[L.st(0)] = beta;
     gm[L.st(1)] = beta;
     gm[L.st(3)] = beta;
+    const double done = (beta == 0.0 || !isfinite(beta)) ? 1.0 : 0.0;
+    gm[L.st(GM_DONE)] = done;
     host[0] = beta;
     host[1] = beta;
     host[2] = 0.0;
     host[3] = beta;
+    host[4] = done;
   }
 }
 
@@ -188,6 +193,135 @@ __global__ void combine_kernel(int n, int m, const double *__restrict__ V,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fused Arnoldi step for vectors of up to 16 * 1024 entries: one block does
+// the whole iteration after w = J v_j (two classical Gram-Schmidt passes
+// against V_0..V_j, ||w||, the Givens update of column j, the residual
+// estimate and V_{j+1} = w / ||w||), with w in registers: row r = tid +
+// k*ARN_T of thread tid, RPT rows per thread.  The reduction order depends
+// on n only (RPT is fixed by n), so a problem gives the same iterates alone
+// and in a batch.  Nothing happens once the converged flag is set; the step
+// sets it when the residual estimate reaches rtol * beta, on breakdown
+// (h_{j+1,j} = 0) or on a non-finite residual.  st_out[0..3] = residual,
+// h_{j+1,j}, iterations, beta; st_out[4] (if with_flag) = converged.
+// ---------------------------------------------------------------------------
+constexpr int ARN_T = 1024;
+constexpr int ARN_MAXN = 16 * ARN_T;
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;   // valid in lane 0
+}
+
+template <int RPT>
+__device__ __forceinline__ void arnoldi_step_body(int n, double *__restrict__ V,
+                                                  const double *__restrict__ w,
+                                                  double *__restrict__ gm, int MX, int j,
+                                                  double rtol, double *__restrict__ st_out,
+                                                  bool with_flag) {
+  constexpr int NW = ARN_T / 64;
+  __shared__ double part[NW][65];
+  __shared__ double h[64];
+  __shared__ double hsh;
+  GmLayout L{MX};
+  if (gm[L.st(GM_DONE)] != 0.0) return;   // the whole block leaves together
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nv = j + 1;
+  double wr[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int r = tid + k * ARN_T;
+    wr[k] = r < n ? w[r] : 0.0;
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int i = 0; i < nv; ++i) {
+      const double *vi = V + (size_t)i * n;
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int r = tid + k * ARN_T;
+        if (r < n) s += vi[r] * wr[k];
+      }
+      s = wave_sum(s);
+      if (lane == 0) part[wv][i] = s;
+    }
+    __syncthreads();
+    if (tid < nv) {
+      double s = 0.0;
+      for (int q = 0; q < NW; ++q) s += part[q][tid];
+      h[tid] = s;
+      gm[L.H(tid, j)] += s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int r = tid + k * ARN_T;
+      if (r < n) {
+        double t = wr[k];
+        for (int i = 0; i < nv; ++i) t -= h[i] * V[(size_t)i * n + r];
+        wr[k] = t;
+      }
+    }
+    __syncthreads();   // part is written again
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) s += wr[k] * wr[k];
+  s = wave_sum(s);
+  if (lane == 0) part[wv][0] = s;
+  __syncthreads();
+  if (tid == 0) {
+    double nn = 0.0;
+    for (int q = 0; q < NW; ++q) nn += part[q][0];
+    const double hn = sqrt(nn);
+    gm[L.H(j + 1, j)] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double c = gm[L.cs(i)], sn = gm[L.sn(i)];
+      const double a = gm[L.H(i, j)], b = gm[L.H(i + 1, j)];
+      gm[L.H(i, j)] = c * a + sn * b;
+      gm[L.H(i + 1, j)] = -sn * a + c * b;
+    }
+    const double a = gm[L.H(j, j)], b = gm[L.H(j + 1, j)];
+    const double rr = hypot(a, b);
+    const double c = (rr == 0.0) ? 1.0 : a / rr, sn = (rr == 0.0) ? 0.0 : b / rr;
+    gm[L.cs(j)] = c;
+    gm[L.sn(j)] = sn;
+    gm[L.H(j, j)] = rr;
+    gm[L.H(j + 1, j)] = 0.0;
+    const double gj = gm[L.g(j)];
+    gm[L.g(j)] = c * gj;
+    gm[L.g(j + 1)] = -sn * gj;
+    const double res = fabs(-sn * gj), beta = gm[L.st(3)];
+    const double done = (res <= rtol * beta || hn == 0.0 || !isfinite(res)) ? 1.0 : 0.0;
+    gm[L.st(0)] = res;
+    gm[L.st(1)] = hn;
+    gm[L.st(2)] = (double)(j + 1);
+    gm[L.st(GM_DONE)] = done;
+    st_out[0] = res;
+    st_out[1] = hn;
+    st_out[2] = (double)(j + 1);
+    st_out[3] = beta;
+    if (with_flag) st_out[4] = done;
+    hsh = hn;
+  }
+  __syncthreads();
+  const double inv = (hsh > 0.0) ? 1.0 / hsh : 0.0;
+  double *vn = V + (size_t)(j + 1) * n;
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int r = tid + k * ARN_T;
+    if (r < n) vn[r] = wr[k] * inv;
+  }
+}
+
+template <int RPT>
+__global__ void __launch_bounds__(ARN_T)
+arnoldi_step_kernel(int n, double *__restrict__ V, const double *__restrict__ w,
+                    double *__restrict__ gm, int MX, int j, double rtol,
+                    double *__restrict__ host) {
+  arnoldi_step_body<RPT>(n, V, w, gm, MX, j, rtol, host, true);
+}
+
 }  // namespace
 
 size_t pd_gmres_state_doubles(int maxit) { return (size_t)GmLayout{maxit}.size(); }
@@ -197,8 +331,96 @@ int pd_vec_blocks(int n) {
   return b < 256 ? b : 256;
 }
 
+namespace {
+
+void launch_arnoldi(pd_plan p, int j, double rtol) {
+  const int n = p->nbar;
+  GmLayout L{p->maxit};
+  (void)L;
+  if (n <= 4 * ARN_T)
+    hipLaunchKernelGGL((arnoldi_step_kernel<4>), dim3(1), dim3(ARN_T), 0, p->stream, n, p->V,
+                       p->wvec, p->gm, p->maxit, j, rtol, p->host_dev);
+  else if (n <= 8 * ARN_T)
+    hipLaunchKernelGGL((arnoldi_step_kernel<8>), dim3(1), dim3(ARN_T), 0, p->stream, n, p->V,
+                       p->wvec, p->gm, p->maxit, j, rtol, p->host_dev);
+  else
+    hipLaunchKernelGGL((arnoldi_step_kernel<16>), dim3(1), dim3(ARN_T), 0, p->stream, n, p->V,
+                       p->wvec, p->gm, p->maxit, j, rtol, p->host_dev);
+}
+
+// 1D plans: fused Arnoldi steps enqueued in chunks (2, 4, then 8 iterations)
+// with one stream synchronisation per chunk; once the device-side converged
+// flag is set, the remaining launches of a chunk return at once (the
+// capacitance product's kernels read the flag through p->gm_skip).
+pd_status gmres_fused(pd_plan p, const double *b, double *x, double rtol, int *iters,
+                      double *relres) {
+  const int n = p->nbar, MX = p->maxit;
+  const int B = pd_vec_blocks(n);
+  GmLayout L{MX};
+  double *red1 = p->red;
+  volatile double *st = p->host_pin;
+  hipLaunchKernelGGL(dots_kernel, dim3(B), dim3(VB), 0, p->stream, n, 0, p->V, b, red1);
+  hipLaunchKernelGGL(init_kernel, dim3(1), dim3(256), 0, p->stream, B, red1, p->gm, MX,
+                     p->host_dev);
+  hipLaunchKernelGGL(scale_kernel, dim3(B), dim3(VB), 0, p->stream, n, b, p->V, p->gm, MX);
+  PD_HIP_CHECK(hipGetLastError());
+  p->gm_skip = p->gm + L.st(GM_DONE);
+  int j = 0, chunk = 2;
+  pd_status s = PD_OK;
+  bool done = false;
+  while (j < MX && !done) {
+    const int c = (chunk < MX - j) ? chunk : MX - j;
+    for (int t = 0; t < c && s == PD_OK; ++t, ++j) {
+      s = pd_capacitance_apply_impl(p, p->V + (size_t)j * n, p->wvec);
+      if (s == PD_OK) {
+        launch_arnoldi(p, j, rtol);
+        if (hipGetLastError() != hipSuccess) s = PD_EHIP;
+      }
+    }
+    if (s != PD_OK) break;
+    if (hipStreamSynchronize(p->stream) != hipSuccess) {
+      s = PD_EHIP;
+      break;
+    }
+    done = st[4] != 0.0;
+    chunk = chunk < 8 ? 2 * chunk : 8;
+  }
+  p->gm_skip = nullptr;
+  if (s == PD_EHIP) {
+    pd_set_error("capacitance GMRES: HIP error");
+    return s;
+  }
+  if (s != PD_OK) return s;
+  const double beta = st[3];
+  if (!std::isfinite(beta)) {
+    pd_set_error("capacitance right-hand side is not finite");
+    return PD_ENONFINITE;
+  }
+  const int m = (int)st[2];
+  const double res = st[0];
+  if (!std::isfinite(res)) {
+    pd_set_error("capacitance GMRES produced a non-finite residual");
+    return PD_ENONFINITE;
+  }
+  if (beta == 0.0) {
+    PD_HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * n, p->stream));
+    if (iters) *iters = 0;
+    if (relres) *relres = 0.0;
+    return PD_OK;
+  }
+  hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, p->stream, p->gm, MX, m);
+  hipLaunchKernelGGL(combine_kernel, dim3(B), dim3(VB), 0, p->stream, n, m, p->V, p->gm, MX, x);
+  PD_HIP_CHECK(hipGetLastError());
+  if (iters) *iters = m;
+  if (relres) *relres = res / beta;
+  return (res <= rtol * beta || st[1] == 0.0) ? PD_OK : PD_ENOTCONV;
+}
+
+}  // namespace
+
 pd_status pd_gmres(pd_plan p, const double *b, double *x, double rtol, int *iters,
                    double *relres) {
+  if (p->dims == 1 && p->nbar <= ARN_MAXN) return gmres_fused(p, b, x, rtol, iters, relres);
   const int n = p->nbar, MX = p->maxit;
   const int B = pd_vec_blocks(n);
   GmLayout L{MX};
@@ -379,6 +601,7 @@ __global__ void batch_init_kernel(const VecJob *__restrict__ jobs, int MX,
     J.gm[L.st(0)] = beta;
     J.gm[L.st(1)] = beta;
     J.gm[L.st(3)] = beta;
+    J.gm[L.st(GM_DONE)] = (beta == 0.0 || !isfinite(beta)) ? 1.0 : 0.0;
     status[4 * blockIdx.x + 0] = beta;
     status[4 * blockIdx.x + 1] = beta;
     status[4 * blockIdx.x + 2] = 0.0;
@@ -399,6 +622,23 @@ __global__ void batch_scale_kernel(const VecJob *__restrict__ jobs, const int2 *
   double *dst = J.V + (size_t)(from_b ? 0 : j + 1) * J.n;
   for (int r = m.y * blockDim.x + threadIdx.x; r < J.n; r += J.B * blockDim.x)
     dst[r] = src[r] * inv;
+}
+
+// one block per problem: the fused Arnoldi step (same body as the single
+// problem's, rows per thread fixed by the problem's n)
+__global__ void __launch_bounds__(ARN_T)
+batch_arnoldi_kernel(const VecJob *__restrict__ jobs, int j, int MX, double rtol,
+                     double *__restrict__ status, const int *__restrict__ active) {
+  const int p = blockIdx.x;
+  if (active && !active[p]) return;
+  const VecJob &J = jobs[p];
+  double *st = status + 4 * p;
+  if (J.n <= 4 * ARN_T)
+    arnoldi_step_body<4>(J.n, J.V, J.w, J.gm, MX, j, rtol, st, false);
+  else if (J.n <= 8 * ARN_T)
+    arnoldi_step_body<8>(J.n, J.V, J.w, J.gm, MX, j, rtol, st, false);
+  else
+    arnoldi_step_body<16>(J.n, J.V, J.w, J.gm, MX, j, rtol, st, false);
 }
 
 // per problem: back substitution (block 0 of the problem does it first in a
@@ -447,6 +687,16 @@ pd_status pd_gmres_batch_update(const VecJob *jobs, const int2 *vmap, int nvb, i
   PD_HIP_CHECK(hipGetLastError());
   return PD_OK;
 }
+
+pd_status pd_gmres_batch_arnoldi(const VecJob *jobs, int count, int j, int MX, double rtol,
+                                 double *status, const int *active, hipStream_t s) {
+  hipLaunchKernelGGL(batch_arnoldi_kernel, dim3(count), dim3(ARN_T), 0, s, jobs, j, MX, rtol,
+                     status, active);
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
+int pd_gmres_fused_max_n() { return ARN_MAXN; }
 
 pd_status pd_gmres_batch_givens(const VecJob *jobs, int count, int j, int MX, double *status,
                                 const int *active, hipStream_t s) {

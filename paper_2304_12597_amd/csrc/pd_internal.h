@@ -179,6 +179,7 @@ struct pd_plan_s {
   double *partials = nullptr;  // [tri_G][nbar]
   double *rstage = nullptr;    // [ceil(G/16)][nbar] reduction slices
   double *host_dev = nullptr;  // device view of host_pin (kernel-written status)
+  const double *gm_skip = nullptr;   // set during GMRES: converged flag for the J kernels
   int tri_G = 0;
   double *bvec = nullptr, *xvec = nullptr, *wvec = nullptr;
   double *V = nullptr;         // [(maxit+1)][nbar] Krylov basis
@@ -285,6 +286,11 @@ pd_status pd_gmres_batch_dots(const VecJob *jobs, const int2 *vmap, int nvb, int
                               const int *active, hipStream_t s);
 pd_status pd_gmres_batch_update(const VecJob *jobs, const int2 *vmap, int nvb, int nv, int j,
                                 int MX, int pass, const int *active, hipStream_t s);
+// one fused Arnoldi step per problem (vectors of at most pd_gmres_fused_max_n()
+// entries): the single-problem path uses the same step
+pd_status pd_gmres_batch_arnoldi(const VecJob *jobs, int count, int j, int MX, double rtol,
+                                 double *status, const int *active, hipStream_t s);
+int pd_gmres_fused_max_n();
 pd_status pd_gmres_batch_givens(const VecJob *jobs, int count, int j, int MX, double *status,
                                 const int *active, hipStream_t s);
 pd_status pd_gmres_batch_init(const VecJob *jobs, int count, int MX, double *status,

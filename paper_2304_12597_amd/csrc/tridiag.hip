@@ -731,6 +731,7 @@ __device__ __forceinline__ void tridiag_pipe_body(
   }
 }
 
+// skip: if non-null and nonzero (a converged GMRES), the launch does nothing
 template <int MR, int MODE>
 __global__ void __launch_bounds__(512)
 tridiag_pipe_kernel(int n, int F2, int P, int spb, int nitems, Coef<double> cf,
@@ -738,7 +739,9 @@ tridiag_pipe_kernel(int n, int F2, int P, int spb, int nitems, Coef<double> cf,
                     const cpx<double> *__restrict__ fac, const double *__restrict__ gw,
                     const cpx<double> *__restrict__ in, const double *__restrict__ vin,
                     const double *__restrict__ xv, double wscale, int rhs_has_mass,
-                    cpx<double> *__restrict__ out, double *__restrict__ partials) {
+                    cpx<double> *__restrict__ out, double *__restrict__ partials,
+                    const double *__restrict__ skip) {
+  if (skip && *skip != 0.0) return;
   tridiag_pipe_body<MR, MODE>(blockIdx.x, gridDim.x, n, F2, P, spb, nitems, cf, coef64, lam, fac,
                               gw, in, vin, xv, wscale, rhs_has_mass, out, partials);
 }
@@ -764,9 +767,9 @@ tridiag_uniform_kernel(int n, int F2, int P, int spb, int nitems, Coef<R> cf,
 // adds the slices in order.  Enough blocks are in flight to hide latency.
 constexpr int RS = 16;
 __global__ void reduce_slices_kernel(int n, int G, const double *__restrict__ partials,
-                                     double *__restrict__ stage) {
+                                     double *__restrict__ stage, const double *__restrict__ skip) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n || (skip && *skip != 0.0)) return;
   const int g0 = blockIdx.y * RS;
   const int g1 = g0 + RS < G ? g0 + RS : G;
   double s = 0.0;
@@ -777,9 +780,9 @@ __global__ void reduce_slices_kernel(int n, int G, const double *__restrict__ pa
 
 __global__ void reduce_partials_kernel(int n, int G, const double *__restrict__ partials,
                                        const double *__restrict__ base,
-                                       double *__restrict__ out) {
+                                       double *__restrict__ out, const double *__restrict__ skip) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n || (skip && *skip != 0.0)) return;
   double s = 0.0;
   for (int g = 0; g < G; ++g) s += partials[(size_t)g * n + i];
   out[i] = (base ? base[i] : 0.0) + s;
@@ -794,7 +797,7 @@ void launch_pipe(pd_plan p, int G, int nitems, const Coef<R> &cf, const R *lam,
     if (MR == 16 && T.spb != 1) return;   // excluded by the caller's check
     hipLaunchKernelGGL((tridiag_pipe_kernel<MR, M>), dim3(G), dim3(T.block), T.lds, p->stream,
                        p->n, p->F2, T.P, T.spb, nitems, cf, p->coef64, lam, fac, gw, cin, vin, x,
-                       p->w, has_mass, o, part);
+                       p->w, has_mass, o, part, p->gm_skip);
   }
 }
 
@@ -956,12 +959,12 @@ pd_status pd_launch_reduce_partials(pd_plan p, const double *base, double *out) 
   if (G > RS) {
     const int slices = (G + RS - 1) / RS;
     hipLaunchKernelGGL(reduce_slices_kernel, dim3((n + 255) / 256, slices), dim3(256), 0,
-                       p->stream, n, G, p->partials, p->rstage);
+                       p->stream, n, G, p->partials, p->rstage, p->gm_skip);
     hipLaunchKernelGGL(reduce_partials_kernel, dim3((n + 255) / 256), dim3(256), 0, p->stream,
-                       n, slices, p->rstage, base, out);
+                       n, slices, p->rstage, base, out, p->gm_skip);
   } else {
     hipLaunchKernelGGL(reduce_partials_kernel, dim3((n + 255) / 256), dim3(256), 0, p->stream,
-                       n, G, p->partials, base, out);
+                       n, G, p->partials, base, out, p->gm_skip);
   }
   PD_HIP_CHECK(hipGetLastError());
   return PD_OK;
