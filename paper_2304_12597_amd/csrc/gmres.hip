@@ -171,10 +171,12 @@ __global__ void init_kernel(int nblk, const double *__restrict__ red, double *__
   }
 }
 
-// back substitution R y = g on the m x m triangle (single thread)
+// back substitution R y = g on the m x m triangle (single thread); m < 0:
+// the iteration count recorded in the status
 __global__ void backsolve_kernel(double *__restrict__ gm, int MX, int m) {
   GmLayout L{MX};
   if (threadIdx.x != 0) return;
+  if (m < 0) m = (int)gm[L.st(2)];
   for (int i = m - 1; i >= 0; --i) {
     double s = gm[L.g(i)];
     for (int k = i + 1; k < m; ++k) s -= gm[L.H(i, k)] * gm[L.y(k)];
@@ -186,6 +188,7 @@ __global__ void backsolve_kernel(double *__restrict__ gm, int MX, int m) {
 __global__ void combine_kernel(int n, int m, const double *__restrict__ V,
                                const double *__restrict__ gm, int MX, double *__restrict__ x) {
   GmLayout L{MX};
+  if (m < 0) m = (int)gm[L.st(2)];
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
     double s = 0.0;
     for (int i = 0; i < m; ++i) s += gm[L.y(i)] * V[(size_t)i * n + r];
@@ -348,6 +351,24 @@ void launch_arnoldi(pd_plan p, int j, double rtol) {
                        p->wvec, p->gm, p->maxit, j, rtol, p->host_dev);
 }
 
+// Enqueues (no synchronisation) J v_j and the fused Arnoldi step for
+// iterations j0 .. j0 + count - 1, the capacitance kernels reading the
+// converged flag.
+pd_status enqueue_iters(pd_plan p, int j0, int count, double rtol) {
+  GmLayout L{p->maxit};
+  const int n = p->nbar;
+  p->gm_skip = p->gm + L.st(GM_DONE);
+  pd_status s = PD_OK;
+  for (int j = j0; j < j0 + count && j < p->maxit && s == PD_OK; ++j) {
+    s = pd_capacitance_apply_impl(p, p->V + (size_t)j * n, p->wvec);
+    if (s == PD_OK) launch_arnoldi(p, j, rtol);
+  }
+  p->gm_skip = nullptr;
+  if (s != PD_OK) return s;
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
 // 1D plans: fused Arnoldi steps enqueued in chunks (2, 4, then 8 iterations)
 // with one stream synchronisation per chunk; once the device-side converged
 // flag is set, the remaining launches of a chunk return at once (the
@@ -417,6 +438,66 @@ pd_status gmres_fused(pd_plan p, const double *b, double *x, double rtol, int *i
 }
 
 }  // namespace
+
+bool pd_gmres_fused_ok(pd_plan p) { return p->dims == 1 && p->nbar <= ARN_MAXN; }
+
+// Speculative form: init, `count` iterations and x = V y with the iteration
+// count taken from the device status, all enqueued without synchronising.
+pd_status pd_gmres_enqueue(pd_plan p, const double *b, double *x, double rtol, int count) {
+  const int n = p->nbar, MX = p->maxit;
+  const int B = pd_vec_blocks(n);
+  hipLaunchKernelGGL(dots_kernel, dim3(B), dim3(VB), 0, p->stream, n, 0, p->V, b, p->red);
+  hipLaunchKernelGGL(init_kernel, dim3(1), dim3(256), 0, p->stream, B, p->red, p->gm, MX,
+                     p->host_dev);
+  hipLaunchKernelGGL(scale_kernel, dim3(B), dim3(VB), 0, p->stream, n, b, p->V, p->gm, MX);
+  PD_HIP_CHECK(hipGetLastError());
+  pd_status s = enqueue_iters(p, 0, count, rtol);
+  if (s != PD_OK) return s;
+  hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, p->stream, p->gm, MX, -1);
+  hipLaunchKernelGGL(combine_kernel, dim3(B), dim3(VB), 0, p->stream, n, -1, p->V, p->gm, MX, x);
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
+// After a synchronisation: the status of the speculative GMRES.
+void pd_gmres_read(pd_plan p, int *m, double *res, double *beta, bool *done) {
+  volatile double *st = p->host_pin;
+  *res = st[0];
+  *beta = st[3];
+  *m = (int)st[2];
+  *done = st[4] != 0.0;
+}
+
+// Continues a speculative GMRES that had not converged (iterations from m on,
+// one synchronisation per chunk), then x = V y.  Returns the final status.
+pd_status pd_gmres_continue(pd_plan p, double *x, double rtol, int *iters, double *relres) {
+  const int n = p->nbar, MX = p->maxit;
+  const int B = pd_vec_blocks(n);
+  volatile double *st = p->host_pin;
+  int j = (int)st[2], chunk = 2;
+  bool done = st[4] != 0.0;
+  while (j < MX && !done) {
+    const int c = (chunk < MX - j) ? chunk : MX - j;
+    pd_status s = enqueue_iters(p, j, c, rtol);
+    if (s != PD_OK) return s;
+    j += c;
+    PD_HIP_CHECK(hipStreamSynchronize(p->stream));
+    done = st[4] != 0.0;
+    chunk = chunk < 8 ? 2 * chunk : 8;
+  }
+  const int m = (int)st[2];
+  const double res = st[0], beta = st[3];
+  if (!std::isfinite(res)) {
+    pd_set_error("capacitance GMRES produced a non-finite residual");
+    return PD_ENONFINITE;
+  }
+  hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, p->stream, p->gm, MX, m);
+  hipLaunchKernelGGL(combine_kernel, dim3(B), dim3(VB), 0, p->stream, n, m, p->V, p->gm, MX, x);
+  PD_HIP_CHECK(hipGetLastError());
+  if (iters) *iters = m;
+  if (relres) *relres = beta > 0.0 ? res / beta : 0.0;
+  return (res <= rtol * beta || st[1] == 0.0) ? PD_OK : PD_ENOTCONV;
+}
 
 pd_status pd_gmres(pd_plan p, const double *b, double *x, double rtol, int *iters,
                    double *relres) {

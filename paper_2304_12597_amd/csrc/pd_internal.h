@@ -180,6 +180,7 @@ struct pd_plan_s {
   double *rstage = nullptr;    // [ceil(G/16)][nbar] reduction slices
   double *host_dev = nullptr;  // device view of host_pin (kernel-written status)
   const double *gm_skip = nullptr;   // set during GMRES: converged flag for the J kernels
+  int gm_pred = 2;             // GMRES iterations enqueued ahead (the last solve's count)
   int tri_G = 0;
   double *bvec = nullptr, *xvec = nullptr, *wvec = nullptr;
   double *V = nullptr;         // [(maxit+1)][nbar] Krylov basis
@@ -291,6 +292,11 @@ pd_status pd_gmres_batch_update(const VecJob *jobs, const int2 *vmap, int nvb, i
 pd_status pd_gmres_batch_arnoldi(const VecJob *jobs, int count, int j, int MX, double rtol,
                                  double *status, const int *active, hipStream_t s);
 int pd_gmres_fused_max_n();
+// speculative capacitance GMRES of the single-problem 1D path
+bool pd_gmres_fused_ok(pd_plan p);
+pd_status pd_gmres_enqueue(pd_plan p, const double *b, double *x, double rtol, int count);
+void pd_gmres_read(pd_plan p, int *m, double *res, double *beta, bool *done);
+pd_status pd_gmres_continue(pd_plan p, double *x, double rtol, int *iters, double *relres);
 pd_status pd_gmres_batch_givens(const VecJob *jobs, int count, int j, int MX, double *status,
                                 const int *active, hipStream_t s);
 pd_status pd_gmres_batch_init(const VecJob *jobs, int count, int MX, double *status,

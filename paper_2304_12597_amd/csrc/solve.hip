@@ -62,6 +62,73 @@ pd_status sweep_tail(pd_plan p, double *U, double tol, int has_mass, int accumul
   return PD_OK;
 }
 
+// One sweep with the whole tail enqueued ahead: the capacitance GMRES runs
+// as many iterations as the plan's last solve needed (later ones return at
+// once after convergence), then x = V y, pass C and pass D, all before the
+// single synchronisation.  If GMRES had not converged by then, it continues
+// from its state, and pass A (whose spectrum pass C overwrote) and passes C,
+// D are redone.
+pd_status solve_speculative(pd_plan p, const double *u0, const double *F, double *U, double tol,
+                            pd_info *info) {
+  const double rtol = tol * PD_GMRES_TOL_FACTOR;
+  pd_status st = pd_launch_tridiag(p, 0, p->spec, nullptr, nullptr);
+  if (st != PD_OK) return st;
+  st = pd_launch_reduce_partials(p, nullptr, p->bvec);
+  if (st != PD_OK) return st;
+  const int pred = p->gm_pred < 1 ? 1 : (p->gm_pred > p->maxit ? p->maxit : p->gm_pred);
+  st = pd_gmres_enqueue(p, p->bvec, p->xvec, rtol, pred);
+  if (st != PD_OK) return st;
+  st = pd_launch_tridiag(p, 1, p->spec, p->xvec, p->spec);
+  if (st != PD_OK) return st;
+  st = pd_inverse(p, p->spec, U, 0);
+  if (st != PD_OK) return st;
+  PD_HIP_CHECK(hipStreamSynchronize(p->stream));
+  int m;
+  double res, beta;
+  bool done;
+  pd_gmres_read(p, &m, &res, &beta, &done);
+  if (!std::isfinite(beta)) {
+    pd_set_error("capacitance right-hand side is not finite");
+    return PD_ENONFINITE;
+  }
+  if (!std::isfinite(res)) {
+    pd_set_error("capacitance GMRES produced a non-finite residual");
+    return PD_ENONFINITE;
+  }
+  pd_status gst = PD_OK;
+  if (!done && m < p->maxit) {
+    int its = m;
+    double rr = 0.0;
+    gst = pd_gmres_continue(p, p->xvec, rtol, &its, &rr);
+    if (gst != PD_OK && gst != PD_ENOTCONV) return gst;
+    st = pd_forward(p, u0, F, nullptr, p->spec, 0);
+    if (st != PD_OK) return st;
+    st = pd_launch_tridiag(p, 1, p->spec, p->xvec, p->spec);
+    if (st != PD_OK) return st;
+    st = pd_inverse(p, p->spec, U, 0);
+    if (st != PD_OK) return st;
+    PD_HIP_CHECK(hipStreamSynchronize(p->stream));
+    pd_gmres_read(p, &m, &res, &beta, &done);
+  } else if (!done) {
+    gst = PD_ENOTCONV;
+  }
+  if (m > 0) p->gm_pred = m;
+  if (info) {
+    info->gmres_iters = m;
+    info->pint_loops = m + 2;
+    info->sweeps = 1;
+    info->gmres_rel_residual = beta > 0.0 ? res / beta : 0.0;
+  }
+  if (p->check_residual) {
+    double rel;
+    st = pd_residual_impl(p, u0, F, U, &rel);
+    if (st != PD_OK) return st;
+    if (info) info->rel_residual = rel;
+  }
+  if (gst == PD_ENOTCONV) pd_set_error("tolerance not reached");
+  return gst;
+}
+
 bool check_ptrs(const void *a, const void *b, const void *c) {
   if (!a || !b || !c) {
     pd_set_error("NULL array argument");
@@ -93,6 +160,7 @@ extern "C" pd_status paradiag_solve(pd_plan p, const double *u0, const double *F
   pd_status gst = PD_OK;
   pd_status st = pd_forward(p, u0, F, nullptr, p->spec, 0);
   if (st != PD_OK) return st;
+  if (p->prec != PD_MIXED && pd_gmres_fused_ok(p)) return solve_speculative(p, u0, F, U, tol, info);
   st = sweep_tail(p, U, tol, 0, 0, info, &gst);
   if (st != PD_OK) return st;
   pd_status final_status = gst;
