@@ -1,15 +1,25 @@
 // Batched solves: many independent problems, every stage launched once for
 // all of them.  Each launch maps its blocks to (problem, local block) pairs,
 // so problems of different sizes share the GPU in the same kernel; the
-// capacitance GMRES runs in lockstep with a per-problem convergence flag.
-// The per-problem arithmetic is the single-problem kernels' own (the same
-// device bodies, the same reduction order), so a problem's result does not
-// depend on the rest of the batch.
+// capacitance GMRES runs in lockstep, each problem stopping on its own
+// device-side convergence flag.  The per-problem arithmetic is the
+// single-problem kernels' own (the same device bodies, the same reduction
+// order), so a problem's result does not depend on the rest of the batch.
+//
+// The whole solve -- transforms, parfors, K GMRES iterations, x = V y --
+// is one launch sequence with no host round trip; once every plan of a
+// batch has been solved before (K = the largest iteration count they
+// needed), the sequence is captured as a HIP graph, cached per (plans,
+// arrays, tol, K) and replayed.  If some problem has not converged after K
+// iterations, an uncaptured loop continues it and the tail is redone.
 #include "pd_internal.h"
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <list>
+#include <memory>
+#include <mutex>
 #include <vector>
 
 namespace {
@@ -20,7 +30,7 @@ bool batchable(const pd_plan *plans, int count) {
     const pd_plan p = plans[i];
     if (!p || p->dims != 1 || !p->uniform || p->prec != p0->prec || p->prec == PD_MIXED ||
         p->tri.block != pd_tri_block_threads(p->prec) ||
-        p->maxit != p0->maxit)
+        p->maxit != p0->maxit || !pd_gmres_fused_ok(p))
       return false;
     for (int j = 0; j < i; ++j)
       if (plans[j] == p) return false;
@@ -28,214 +38,344 @@ bool batchable(const pd_plan *plans, int count) {
   return true;
 }
 
-struct DevBuf {
-  void *ptr = nullptr;
-  ~DevBuf() {
-    if (ptr) (void)hipFree(ptr);
+// Device tables of one batch shape, its pinned status copy and (once the
+// iteration count is known) its captured graph.
+struct BatchRun {
+  std::vector<const void *> key;   // plans, u0, F, U
+  double tol = 0.0;
+  int K = 0, count = 0, MR = 0, prec = 0, MX = 0;
+  hipStream_t s = nullptr;
+  void *dev = nullptr;
+  double *pin = nullptr;           // statuses [4 * count]: residual, h, iterations, beta
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;       // capture stream (the plan stream may be the legacy one)
+  const FftJob *fj = nullptr;
+  const TriJob *tj = nullptr, *tjJ = nullptr;
+  const VecJob *vj = nullptr;
+  const int2 *fm = nullptr, *t0 = nullptr, *t1 = nullptr, *vm = nullptr, *rm = nullptr;
+  int *act = nullptr;
+  double *st = nullptr;
+  int nf = 0, n0 = 0, n1 = 0, nv = 0, nr = 0, fft_threads = 64;
+  size_t fft_lds = 0, tri_lds = 0;
+  ~BatchRun() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (dev) (void)hipFree(dev);
+    if (pin) (void)hipHostFree(pin);
   }
 };
 
-}  // namespace
+std::mutex g_runs_mu;
+std::list<std::unique_ptr<BatchRun>> g_runs;   // most recent first
+constexpr size_t kMaxRuns = 4;
 
-pd_status pd_solve_batch_impl(const pd_plan *plans, int count, const double *const *u0,
-                              const double *const *F, double *const *U, double tol,
-                              pd_info *infos) {
+pd_status build_run(BatchRun &r, const pd_plan *plans, int count, const double *const *u0,
+                    const double *const *F, double *const *U) {
   const pd_plan p0 = plans[0];
-  const hipStream_t s = p0->stream;
   const int prec = p0->prec;
   const int MX = p0->maxit;
   const size_t cb = (prec == PD_FP64) ? 16 : 8;
+  r.count = count;
+  r.prec = prec;
+  r.MX = MX;
+  r.s = p0->stream;
+  {
+    std::vector<FftJob> fj(count);
+    std::vector<TriJob> tj(count);
+    std::vector<VecJob> vj(count);
+    std::vector<int2> fftmap, tri0map, tri1map, vmap, redmap;
+    int fft_threads = 64, MR = -1;
+    size_t fft_lds = 0, tri_lds = 0;
+    for (int i = 0; i < count; ++i) {
+      const pd_plan p = plans[i];
+      if (MR < 0) MR = p->tri.MR;
+      if (p->tri.MR != MR) return PD_ENOTSUP;
+      FftJob &f = fj[i];
+      f.N = p->ell; f.n = p->n; f.nbar = p->nbar; f.dims = 1;
+      f.C = p->fft_C; f.stride = p->fft_stride; f.tau = p->tau;
+      f.u0 = u0[i]; f.F = F[i]; f.U = nullptr; f.coef = p->coef64; f.dal = p->dal;
+      f.tw = (prec == PD_FP64) ? (const void *)p->tw64 : (const void *)p->tw32;
+      f.spec = p->spec; f.out = U[i]; f.red = p->red;
+      const int tiles = (p->nbar + 2 * f.C - 1) / (2 * f.C);
+      for (int b = 0; b < tiles; ++b) fftmap.push_back(make_int2(i, b));
+      int need = f.C * f.N / 8;
+      need = ((std::max(need, 64) + 63) / 64) * 64;
+      fft_threads = std::max(fft_threads, need);
+      fft_lds = std::max(fft_lds, ((size_t)f.C * f.stride + pd_tw_entries(f.N)) * cb);
 
-  std::vector<FftJob> fj(count);
-  std::vector<TriJob> tj(count);
-  std::vector<VecJob> vj(count);
-  std::vector<int2> fftmap, tri0map, tri1map, vmap, redmap;
-  int fft_threads = 64, MR = -1;
-  size_t fft_lds = 0, tri_lds = 0;
-  for (int i = 0; i < count; ++i) {
-    const pd_plan p = plans[i];
-    if (MR < 0) MR = p->tri.MR;
-    if (p->tri.MR != MR) return PD_ENOTSUP;
-    FftJob &f = fj[i];
-    f.N = p->ell; f.n = p->n; f.nbar = p->nbar; f.dims = 1;
-    f.C = p->fft_C; f.stride = p->fft_stride; f.tau = p->tau;
-    f.u0 = u0[i]; f.F = F[i]; f.U = nullptr; f.coef = p->coef64; f.dal = p->dal;
-    f.tw = (prec == PD_FP64) ? (const void *)p->tw64 : (const void *)p->tw32;
-    f.spec = p->spec; f.out = U[i]; f.red = p->red;
-    const int tiles = (p->nbar + 2 * f.C - 1) / (2 * f.C);
-    for (int b = 0; b < tiles; ++b) fftmap.push_back(make_int2(i, b));
-    int need = f.C * f.N / 8;
-    need = ((std::max(need, 64) + 63) / 64) * 64;
-    fft_threads = std::max(fft_threads, need);
-    fft_lds = std::max(fft_lds, ((size_t)f.C * f.stride + pd_tw_entries(f.N)) * cb);
+      TriJob &t = tj[i];
+      const int P = p->tri.P;
+      const int BT = pd_tri_block_threads(prec);
+      if (P > BT) return PD_ENOTSUP;
+      t.n = p->n; t.F2 = p->F2; t.P = P; t.spb = BT / P;
+      t.nitems = pd_tri_nitems(p->tri, p->F2);
+      t.nblk = std::min(t.nitems, p->tri_G);
+      t.has_mass = 0;
+      t.ml = p->uni[0]; t.md = p->uni[1]; t.mu = p->uni[2];
+      t.kl = p->uni[3]; t.kd = p->uni[4]; t.ku = p->uni[5];
+      t.coef64 = p->coef64;
+      t.lam = (prec == PD_FP64) ? (const void *)p->lam64 : (const void *)p->lam32;
+      t.fac = (prec == PD_FP64) ? (const void *)p->fac64 : (const void *)p->fac32;
+      t.gw = p->gB64; t.in = p->spec; t.vin = nullptr; t.xv = p->xvec; t.wscale = p->w;
+      t.out = p->spec; t.partials = p->partials; t.skip = nullptr;
+      for (int b = 0; b < t.nblk; ++b) tri0map.push_back(make_int2(i, b));
+      for (int b = 0; b < t.nblk; ++b) tri1map.push_back(make_int2(i, b));
+      tri_lds = std::max(tri_lds, p->tri.lds);   // batchable: the same packing as p->tri
 
-    TriJob &t = tj[i];
-    const int P = p->tri.P;
-    const int BT = pd_tri_block_threads(prec);
-    if (P > BT) return PD_ENOTSUP;
-    t.n = p->n; t.F2 = p->F2; t.P = P; t.spb = BT / P;
-    t.nitems = pd_tri_nitems(p->tri, p->F2);
-    t.nblk = std::min(t.nitems, p->tri_G);
-    t.has_mass = 0;
-    t.ml = p->uni[0]; t.md = p->uni[1]; t.mu = p->uni[2];
-    t.kl = p->uni[3]; t.kd = p->uni[4]; t.ku = p->uni[5];
-    t.coef64 = p->coef64;
-    t.lam = (prec == PD_FP64) ? (const void *)p->lam64 : (const void *)p->lam32;
-    t.fac = (prec == PD_FP64) ? (const void *)p->fac64 : (const void *)p->fac32;
-    t.gw = p->gB64; t.in = p->spec; t.vin = nullptr; t.xv = p->xvec; t.wscale = p->w;
-    t.out = p->spec; t.partials = p->partials;
-    for (int b = 0; b < t.nblk; ++b) tri0map.push_back(make_int2(i, b));
-    for (int b = 0; b < t.nblk; ++b) tri1map.push_back(make_int2(i, b));
-    tri_lds = std::max(tri_lds, p->tri.lds);   // batchable: the same packing as p->tri
-
-    VecJob &v = vj[i];
-    v.n = p->nbar; v.B = pd_vec_blocks(p->nbar); v.G = t.nblk;
-    v.V = p->V; v.w = p->wvec; v.x = p->xvec; v.red1 = p->red;
-    v.red2 = p->red + (size_t)v.B * (MX + 2); v.gm = p->gm; v.partials = p->partials;
-    v.bout = p->bvec; v.b = p->bvec;
-    for (int b = 0; b < v.B; ++b) vmap.push_back(make_int2(i, b));
-    for (int b = 0; b < (p->nbar + 255) / 256; ++b) redmap.push_back(make_int2(i, b));
-  }
-  // J-product jobs: same systems, mode 2, weights gamma_J, v = V_j
-  std::vector<TriJob> tjJ = tj;
-  for (int i = 0; i < count; ++i) {
-    tjJ[i].gw = plans[i]->gJ64;
-    tjJ[i].vin = plans[i]->V;
-    tjJ[i].in = nullptr;
-  }
-
-  // one device buffer for the job tables, maps, flags and status
-  auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  size_t off = 0;
-  const size_t o_fj = off; off = align(off + fj.size() * sizeof(FftJob));
-  const size_t o_tj = off; off = align(off + tj.size() * sizeof(TriJob));
-  const size_t o_tjJ = off; off = align(off + tjJ.size() * sizeof(TriJob));
-  const size_t o_vj = off; off = align(off + vj.size() * sizeof(VecJob));
-  const size_t o_fm = off; off = align(off + fftmap.size() * sizeof(int2));
-  const size_t o_t0 = off; off = align(off + tri0map.size() * sizeof(int2));
-  const size_t o_t1 = off; off = align(off + tri1map.size() * sizeof(int2));
-  const size_t o_vm = off; off = align(off + vmap.size() * sizeof(int2));
-  const size_t o_rm = off; off = align(off + redmap.size() * sizeof(int2));
-  const size_t o_act = off; off = align(off + count * sizeof(int));
-  const size_t o_m = off; off = align(off + count * sizeof(int));
-  const size_t o_st = off; off = align(off + 4 * (size_t)count * sizeof(double));
-  DevBuf buf;
-  if (hipMalloc(&buf.ptr, off) != hipSuccess) {
-    buf.ptr = nullptr;
-    pd_set_error("batched solve: device allocation failed");
-    return PD_ENOMEM;
-  }
-  char *base = reinterpret_cast<char *>(buf.ptr);
-  std::vector<char> host(off);
-  auto put = [&](size_t o, const void *src, size_t bytes) { std::memcpy(host.data() + o, src, bytes); };
-  put(o_fj, fj.data(), fj.size() * sizeof(FftJob));
-  put(o_tj, tj.data(), tj.size() * sizeof(TriJob));
-  put(o_tjJ, tjJ.data(), tjJ.size() * sizeof(TriJob));
-  put(o_vj, vj.data(), vj.size() * sizeof(VecJob));
-  put(o_fm, fftmap.data(), fftmap.size() * sizeof(int2));
-  put(o_t0, tri0map.data(), tri0map.size() * sizeof(int2));
-  put(o_t1, tri1map.data(), tri1map.size() * sizeof(int2));
-  put(o_vm, vmap.data(), vmap.size() * sizeof(int2));
-  put(o_rm, redmap.data(), redmap.size() * sizeof(int2));
-  PD_HIP_CHECK(hipMemcpyAsync(buf.ptr, host.data(), o_act, hipMemcpyHostToDevice, s));
-  const FftJob *d_fj = reinterpret_cast<const FftJob *>(base + o_fj);
-  const TriJob *d_tj = reinterpret_cast<const TriJob *>(base + o_tj);
-  const TriJob *d_tjJ = reinterpret_cast<const TriJob *>(base + o_tjJ);
-  const VecJob *d_vj = reinterpret_cast<const VecJob *>(base + o_vj);
-  const int2 *d_fm = reinterpret_cast<const int2 *>(base + o_fm);
-  const int2 *d_t0 = reinterpret_cast<const int2 *>(base + o_t0);
-  const int2 *d_t1 = reinterpret_cast<const int2 *>(base + o_t1);
-  const int2 *d_vm = reinterpret_cast<const int2 *>(base + o_vm);
-  const int2 *d_rm = reinterpret_cast<const int2 *>(base + o_rm);
-  int *d_act = reinterpret_cast<int *>(base + o_act);
-  int *d_m = reinterpret_cast<int *>(base + o_m);
-  double *d_st = reinterpret_cast<double *>(base + o_st);
-  const int nf = (int)fftmap.size(), n0 = (int)tri0map.size(), n1 = (int)tri1map.size();
-  const int nv = (int)vmap.size(), nr = (int)redmap.size();
-
-  pd_status st;
-#define PD_B(x)                    \
-  do {                             \
-    st = (x);                      \
-    if (st != PD_OK) return st;    \
-  } while (0)
-  // first stage and first parfor with the b reduction
-  PD_B(pd_launch_fft_forward_batch(prec, d_fj, d_fm, nf, fft_threads, fft_lds, s));
-  PD_B(pd_launch_tridiag_batch(prec, MR, 0, d_tj, d_t0, n0, tri_lds, nullptr, 0, s));
-  PD_B(pd_launch_reduce_batch(d_vj, d_rm, nr, -1, nullptr, s));
-  // capacitance GMRES in lockstep
-  PD_B(pd_gmres_batch_dots(d_vj, d_vm, nv, 0, 1, nullptr, s));
-  PD_B(pd_gmres_batch_init(d_vj, count, MX, d_st, s));
-  PD_B(pd_gmres_batch_scale(d_vj, d_vm, nv, 0, MX, 1, nullptr, s));
-  std::vector<double> hst(4 * (size_t)count);
-  PD_HIP_CHECK(hipMemcpyAsync(hst.data(), d_st, hst.size() * sizeof(double),
-                              hipMemcpyDeviceToHost, s));
-  PD_HIP_CHECK(hipStreamSynchronize(s));
-  std::vector<int> act(count), m(count, 0);
-  std::vector<double> beta(count), res(count);
-  int nact = 0;
-  for (int i = 0; i < count; ++i) {
-    beta[i] = hst[4 * i];
-    if (!std::isfinite(beta[i])) {
-      pd_set_error("batched solve: non-finite capacitance right-hand side");
-      return PD_ENONFINITE;
+      VecJob &v = vj[i];
+      v.n = p->nbar; v.B = pd_vec_blocks(p->nbar); v.G = t.nblk;
+      v.V = p->V; v.w = p->wvec; v.x = p->xvec; v.red1 = p->red;
+      v.red2 = p->red + (size_t)v.B * (MX + 2); v.gm = p->gm; v.partials = p->partials;
+      v.bout = p->bvec; v.b = p->bvec; v.done = p->gm + pd_gmres_done_index(MX);
+      for (int b = 0; b < v.B; ++b) vmap.push_back(make_int2(i, b));
+      for (int b = 0; b < (p->nbar + 255) / 256; ++b) redmap.push_back(make_int2(i, b));
     }
-    res[i] = beta[i];
-    act[i] = beta[i] > 0.0;
+    // J-product jobs: same systems, mode 2, weights gamma_J, v = V_j
+    std::vector<TriJob> tjJ = tj;
+    for (int i = 0; i < count; ++i) {
+      tjJ[i].gw = plans[i]->gJ64;
+      tjJ[i].vin = plans[i]->V;
+      tjJ[i].in = nullptr;
+      tjJ[i].skip = plans[i]->gm + pd_gmres_done_index(MX);
+    }
+
+    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t off = 0;
+    const size_t o_fj = off; off = align(off + fj.size() * sizeof(FftJob));
+    const size_t o_tj = off; off = align(off + tj.size() * sizeof(TriJob));
+    const size_t o_tjJ = off; off = align(off + tjJ.size() * sizeof(TriJob));
+    const size_t o_vj = off; off = align(off + vj.size() * sizeof(VecJob));
+    const size_t o_fm = off; off = align(off + fftmap.size() * sizeof(int2));
+    const size_t o_t0 = off; off = align(off + tri0map.size() * sizeof(int2));
+    const size_t o_t1 = off; off = align(off + tri1map.size() * sizeof(int2));
+    const size_t o_vm = off; off = align(off + vmap.size() * sizeof(int2));
+    const size_t o_rm = off; off = align(off + redmap.size() * sizeof(int2));
+    const size_t o_act = off; off = align(off + count * sizeof(int));
+    const size_t o_st = off; off = align(off + 4 * (size_t)count * sizeof(double));
+    if (hipMalloc(&r.dev, off) != hipSuccess) {
+      r.dev = nullptr;
+      pd_set_error("batched solve: device allocation failed");
+      return PD_ENOMEM;
+    }
+    if (hipHostMalloc(reinterpret_cast<void **>(&r.pin), 4 * (size_t)count * sizeof(double),
+                      hipHostMallocDefault) != hipSuccess) {
+      r.pin = nullptr;
+      pd_set_error("batched solve: pinned allocation failed");
+      return PD_ENOMEM;
+    }
+    std::vector<char> host(o_act);
+    auto put = [&](size_t o, const void *src, size_t bytes) {
+      std::memcpy(host.data() + o, src, bytes);
+    };
+    put(o_fj, fj.data(), fj.size() * sizeof(FftJob));
+    put(o_tj, tj.data(), tj.size() * sizeof(TriJob));
+    put(o_tjJ, tjJ.data(), tjJ.size() * sizeof(TriJob));
+    put(o_vj, vj.data(), vj.size() * sizeof(VecJob));
+    put(o_fm, fftmap.data(), fftmap.size() * sizeof(int2));
+    put(o_t0, tri0map.data(), tri0map.size() * sizeof(int2));
+    put(o_t1, tri1map.data(), tri1map.size() * sizeof(int2));
+    put(o_vm, vmap.data(), vmap.size() * sizeof(int2));
+    put(o_rm, redmap.data(), redmap.size() * sizeof(int2));
+    PD_HIP_CHECK(hipMemcpy(r.dev, host.data(), o_act, hipMemcpyHostToDevice));
+    char *base = reinterpret_cast<char *>(r.dev);
+    r.fj = reinterpret_cast<const FftJob *>(base + o_fj);
+    r.tj = reinterpret_cast<const TriJob *>(base + o_tj);
+    r.tjJ = reinterpret_cast<const TriJob *>(base + o_tjJ);
+    r.vj = reinterpret_cast<const VecJob *>(base + o_vj);
+    r.fm = reinterpret_cast<const int2 *>(base + o_fm);
+    r.t0 = reinterpret_cast<const int2 *>(base + o_t0);
+    r.t1 = reinterpret_cast<const int2 *>(base + o_t1);
+    r.vm = reinterpret_cast<const int2 *>(base + o_vm);
+    r.rm = reinterpret_cast<const int2 *>(base + o_rm);
+    r.act = reinterpret_cast<int *>(base + o_act);
+    r.st = reinterpret_cast<double *>(base + o_st);
+    r.nf = (int)fftmap.size();
+    r.n0 = (int)tri0map.size();
+    r.n1 = (int)tri1map.size();
+    r.nv = (int)vmap.size();
+    r.nr = (int)redmap.size();
+    r.fft_threads = fft_threads;
+    r.fft_lds = fft_lds;
+    r.tri_lds = tri_lds;
+    r.MR = MR;
+  }
+  return PD_OK;
+}
+
+#define PD_B(x)                 \
+  do {                          \
+    pd_status st_ = (x);        \
+    if (st_ != PD_OK) return st_; \
+  } while (0)
+
+// The launch sequence of one batched solve with K GMRES iterations (no
+// synchronisation, no host data: capturable).
+pd_status enqueue_solve(const BatchRun &r, int K, double rtol, hipStream_t s) {
+  PD_B(pd_launch_fft_forward_batch(r.prec, r.fj, r.fm, r.nf, r.fft_threads, r.fft_lds, s));
+  PD_B(pd_launch_tridiag_batch(r.prec, r.MR, 0, r.tj, r.t0, r.n0, r.tri_lds, nullptr, 0, s));
+  PD_B(pd_launch_reduce_batch(r.vj, r.rm, r.nr, -1, nullptr, s));
+  PD_B(pd_gmres_batch_dots(r.vj, r.vm, r.nv, 0, 1, nullptr, s));
+  PD_B(pd_gmres_batch_init(r.vj, r.count, r.MX, r.st, s));
+  PD_B(pd_gmres_batch_scale(r.vj, r.vm, r.nv, 0, r.MX, 1, nullptr, s));
+  for (int j = 0; j < K; ++j) {
+    PD_B(pd_launch_tridiag_batch(r.prec, r.MR, 2, r.tjJ, r.t0, r.n0, r.tri_lds, nullptr, j, s));
+    PD_B(pd_launch_reduce_batch(r.vj, r.rm, r.nr, j, nullptr, s));
+    PD_B(pd_gmres_batch_arnoldi(r.vj, r.count, j, r.MX, rtol, r.st, nullptr, s));
+  }
+  PD_B(pd_gmres_batch_finish(r.vj, r.vm, r.nv, r.count, r.MX, nullptr, s));
+  PD_B(pd_launch_tridiag_batch(r.prec, r.MR, 1, r.tj, r.t1, r.n1, r.tri_lds, nullptr, 0, s));
+  PD_B(pd_launch_fft_inverse_batch(r.prec, r.fj, r.fm, r.nf, r.fft_threads, r.fft_lds, s));
+  PD_HIP_CHECK(hipMemcpyAsync(r.pin, r.st, 4 * (size_t)r.count * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+  return PD_OK;
+}
+
+bool converged(const double *st, double rtol) {
+  const double res = st[0], hn = st[1], beta = st[3];
+  return beta == 0.0 || res <= rtol * beta || hn == 0.0;
+}
+
+// Problems still iterating after K steps (all at iteration K) continue
+// with host-checked steps; then pass A is redone for every problem (pass C
+// overwrote the spectra) and the tail is run again.
+pd_status finish_unconverged(const BatchRun &r, int K, double rtol) {
+  const hipStream_t s = r.s;
+  std::vector<int> act(r.count);
+  int nact = 0;
+  for (int i = 0; i < r.count; ++i) {
+    act[i] = !converged(r.pin + 4 * i, rtol) && (int)r.pin[4 * i + 2] < r.MX;
     nact += act[i];
   }
-  const double rtol = tol * PD_GMRES_TOL_FACTOR;
-  // 1D problems of at most pd_gmres_fused_max_n() unknowns take the fused
-  // Arnoldi step, as they do when solved alone
-  bool fused = true;
-  for (int i = 0; i < count; ++i) fused = fused && plans[i]->nbar <= pd_gmres_fused_max_n();
-  for (int j = 0; j < MX && nact > 0; ++j) {
-    PD_HIP_CHECK(hipMemcpyAsync(d_act, act.data(), count * sizeof(int), hipMemcpyHostToDevice, s));
-    PD_B(pd_launch_tridiag_batch(prec, MR, 2, d_tjJ, d_t0, n0, tri_lds, d_act, j, s));
-    PD_B(pd_launch_reduce_batch(d_vj, d_rm, nr, j, d_act, s));
-    if (fused) {
-      PD_B(pd_gmres_batch_arnoldi(d_vj, count, j, MX, rtol, d_st, d_act, s));
-    } else {
-      PD_B(pd_gmres_batch_dots(d_vj, d_vm, nv, j + 1, 0, d_act, s));
-      PD_B(pd_gmres_batch_update(d_vj, d_vm, nv, j + 1, j, MX, 1, d_act, s));
-      PD_B(pd_gmres_batch_update(d_vj, d_vm, nv, j + 1, j, MX, 2, d_act, s));
-      PD_B(pd_gmres_batch_dots(d_vj, d_vm, nv, 0, 0, d_act, s));
-      PD_B(pd_gmres_batch_givens(d_vj, count, j, MX, d_st, d_act, s));
-      PD_B(pd_gmres_batch_scale(d_vj, d_vm, nv, j, MX, 0, d_act, s));
-    }
-    PD_HIP_CHECK(hipMemcpyAsync(hst.data(), d_st, hst.size() * sizeof(double),
+  if (nact == 0) return PD_OK;
+  for (int j = K; j < r.MX && nact > 0; ++j) {
+    PD_HIP_CHECK(hipMemcpyAsync(r.act, act.data(), r.count * sizeof(int), hipMemcpyHostToDevice, s));
+    PD_B(pd_launch_tridiag_batch(r.prec, r.MR, 2, r.tjJ, r.t0, r.n0, r.tri_lds, r.act, j, s));
+    PD_B(pd_launch_reduce_batch(r.vj, r.rm, r.nr, j, r.act, s));
+    PD_B(pd_gmres_batch_arnoldi(r.vj, r.count, j, r.MX, rtol, r.st, r.act, s));
+    PD_HIP_CHECK(hipMemcpyAsync(r.pin, r.st, 4 * (size_t)r.count * sizeof(double),
                                 hipMemcpyDeviceToHost, s));
     PD_HIP_CHECK(hipStreamSynchronize(s));
-    for (int i = 0; i < count; ++i) {
+    for (int i = 0; i < r.count; ++i) {
       if (!act[i]) continue;
-      m[i] = j + 1;
-      res[i] = hst[4 * i];
-      if (!std::isfinite(res[i])) {
-        pd_set_error("batched solve: non-finite GMRES residual");
-        return PD_ENONFINITE;
-      }
-      if (res[i] <= rtol * beta[i] || hst[4 * i + 1] == 0.0) {
+      const double *st = r.pin + 4 * i;
+      if (!std::isfinite(st[0]) || converged(st, rtol)) {
         act[i] = 0;
         --nact;
       }
     }
   }
-  PD_HIP_CHECK(hipMemcpyAsync(d_m, m.data(), count * sizeof(int), hipMemcpyHostToDevice, s));
-  PD_B(pd_gmres_batch_finish(d_vj, d_vm, nv, count, MX, d_m, s));
-  // second parfor and last stage
-  PD_B(pd_launch_tridiag_batch(prec, MR, 1, d_tj, d_t1, n1, tri_lds, nullptr, 0, s));
-  PD_B(pd_launch_fft_inverse_batch(prec, d_fj, d_fm, nf, fft_threads, fft_lds, s));
-#undef PD_B
+  PD_B(pd_launch_fft_forward_batch(r.prec, r.fj, r.fm, r.nf, r.fft_threads, r.fft_lds, s));
+  PD_B(pd_gmres_batch_finish(r.vj, r.vm, r.nv, r.count, r.MX, nullptr, s));
+  PD_B(pd_launch_tridiag_batch(r.prec, r.MR, 1, r.tj, r.t1, r.n1, r.tri_lds, nullptr, 0, s));
+  PD_B(pd_launch_fft_inverse_batch(r.prec, r.fj, r.fm, r.nf, r.fft_threads, r.fft_lds, s));
   PD_HIP_CHECK(hipStreamSynchronize(s));
+  return PD_OK;
+}
+
+}  // namespace
+
+void pd_batch_forget(pd_plan p) {
+  std::lock_guard<std::mutex> lk(g_runs_mu);
+  g_runs.remove_if([p](const std::unique_ptr<BatchRun> &r) {
+    for (int i = 0; i < r->count; ++i)
+      if (r->key[i] == p) return true;
+    return false;
+  });
+}
+
+pd_status pd_solve_batch_impl(const pd_plan *plans, int count, const double *const *u0,
+                              const double *const *F, double *const *U, double tol,
+                              pd_info *infos) {
+  const pd_plan p0 = plans[0];
+  const int MX = p0->maxit;
+  const double rtol = tol * PD_GMRES_TOL_FACTOR;
+  bool learned = true;
+  int K = 1;
+  for (int i = 0; i < count; ++i) {
+    learned = learned && plans[i]->gm_seen;
+    K = std::max(K, plans[i]->gm_pred);
+  }
+  K = std::min(K, MX);
+  std::vector<const void *> key;
+  key.reserve(4 * (size_t)count);
+  for (int i = 0; i < count; ++i) key.push_back(plans[i]);
+  for (int i = 0; i < count; ++i) key.push_back(u0[i]);
+  for (int i = 0; i < count; ++i) key.push_back(F[i]);
+  for (int i = 0; i < count; ++i) key.push_back(U[i]);
+
+  std::lock_guard<std::mutex> lk(g_runs_mu);
+  BatchRun *run = nullptr;
+  for (auto it = g_runs.begin(); it != g_runs.end(); ++it)
+    if ((*it)->key == key && (*it)->tol == tol && (*it)->K == K && (*it)->s == p0->stream) {
+      g_runs.splice(g_runs.begin(), g_runs, it);   // most recent first
+      run = g_runs.front().get();
+      break;
+    }
+  if (!run) {
+    auto fresh = std::make_unique<BatchRun>();
+    fresh->key = key;
+    fresh->tol = tol;
+    fresh->K = K;
+    pd_status bs = build_run(*fresh, plans, count, u0, F, U);
+    if (bs != PD_OK) return bs;
+    g_runs.push_front(std::move(fresh));
+    if (g_runs.size() > kMaxRuns) g_runs.pop_back();
+    run = g_runs.front().get();
+  }
+  const hipStream_t s = run->s;
+  if (learned && !run->exec) {
+    // capture once; replays are a single launch
+    hipGraph_t graph = nullptr;
+    if (!run->cap) PD_HIP_CHECK(hipStreamCreateWithFlags(&run->cap, hipStreamNonBlocking));
+    PD_HIP_CHECK(hipStreamBeginCapture(run->cap, hipStreamCaptureModeThreadLocal));
+    const pd_status es = enqueue_solve(*run, K, rtol, run->cap);
+    const hipError_t ce = hipStreamEndCapture(run->cap, &graph);
+    if (es != PD_OK || ce != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      if (es != PD_OK) return es;
+      pd_set_error("batched solve: graph capture failed");
+      return PD_EHIP;
+    }
+    const hipError_t ie = hipGraphInstantiate(&run->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      run->exec = nullptr;
+      pd_set_error("batched solve: graph instantiation failed");
+      return PD_EHIP;
+    }
+  }
+  if (run->exec) {
+    PD_HIP_CHECK(hipGraphLaunch(run->exec, s));
+  } else {
+    PD_B(enqueue_solve(*run, K, rtol, s));
+  }
+  PD_HIP_CHECK(hipStreamSynchronize(s));
+  for (int i = 0; i < count; ++i) {
+    if (!std::isfinite(run->pin[4 * i + 3])) {
+      pd_set_error("batched solve: non-finite capacitance right-hand side");
+      return PD_ENONFINITE;
+    }
+    if (!std::isfinite(run->pin[4 * i])) {
+      pd_set_error("batched solve: non-finite GMRES residual");
+      return PD_ENONFINITE;
+    }
+  }
+  PD_B(finish_unconverged(*run, K, rtol));
+
   pd_status worst = PD_OK;
   for (int i = 0; i < count; ++i) {
-    const bool conv = beta[i] == 0.0 || res[i] <= rtol * beta[i];
+    const double *st = run->pin + 4 * i;
+    const int m = (int)st[2];
+    const double res = st[0], beta = st[3];
+    const bool conv = converged(st, rtol);
     if (!conv) worst = PD_ENOTCONV;
+    plans[i]->gm_seen = 1;
+    if (m > 0) plans[i]->gm_pred = m;
     if (infos) {
-      infos[i].gmres_iters = m[i];
+      infos[i].gmres_iters = m;
       infos[i].sweeps = 1;
-      infos[i].pint_loops = m[i] + 2;
-      infos[i].gmres_rel_residual = beta[i] > 0.0 ? res[i] / beta[i] : 0.0;
+      infos[i].pint_loops = m + 2;
+      infos[i].gmres_rel_residual = beta > 0.0 ? res / beta : 0.0;
       infos[i].rel_residual = -1.0;
       if (plans[i]->check_residual) {
         double rel;
@@ -248,5 +388,6 @@ pd_status pd_solve_batch_impl(const pd_plan *plans, int count, const double *con
   if (worst == PD_ENOTCONV) pd_set_error("tolerance not reached for some problems");
   return worst;
 }
+#undef PD_B
 
 bool pd_batchable(const pd_plan *plans, int count) { return count > 0 && batchable(plans, count); }

@@ -440,6 +440,7 @@ pd_status gmres_fused(pd_plan p, const double *b, double *x, double rtol, int *i
 }  // namespace
 
 bool pd_gmres_fused_ok(pd_plan p) { return p->dims == 1 && p->nbar <= ARN_MAXN; }
+size_t pd_gmres_done_index(int maxit) { return (size_t)GmLayout{maxit}.st(GM_DONE); }
 
 // Speculative form: init, `count` iterations and x = V y with the iteration
 // count taken from the device status, all enqueued without synchronising.
@@ -729,7 +730,7 @@ __global__ void batch_backsolve_kernel(const VecJob *__restrict__ jobs, int MX,
   const VecJob &J = jobs[blockIdx.x];
   if (threadIdx.x != 0) return;
   GmLayout L{MX};
-  const int m = mlist[blockIdx.x];
+  const int m = mlist ? mlist[blockIdx.x] : (int)J.gm[L.st(2)];
   double *gm = J.gm;
   for (int i = m - 1; i >= 0; --i) {
     double s = gm[L.g(i)];
@@ -744,7 +745,7 @@ __global__ void batch_combine_kernel(const VecJob *__restrict__ jobs, const int2
   const int2 mp = vmap[blockIdx.x];
   const VecJob &J = jobs[mp.x];
   GmLayout L{MX};
-  const int m = mlist[mp.x];
+  const int m = mlist ? mlist[mp.x] : (int)J.gm[L.st(2)];
   for (int r = mp.y * blockDim.x + threadIdx.x; r < J.n; r += J.B * blockDim.x) {
     double s = 0.0;
     for (int i = 0; i < m; ++i) s += J.gm[L.y(i)] * J.V[(size_t)i * J.n + r];

@@ -103,6 +103,7 @@ struct TriJob {
   double wscale;
   void *out;
   double *partials;
+  const double *skip;   // nonzero: the problem's GMRES has converged (J jobs)
 };
 
 struct VecJob {     // one problem's vectors for the batched GMRES kernels
@@ -110,6 +111,7 @@ struct VecJob {     // one problem's vectors for the batched GMRES kernels
   int G;            // partial rows of the shifted-solve reductions
   double *V, *w, *x, *red1, *red2, *gm, *partials, *bout;
   const double *b;
+  const double *done;   // the problem's GMRES converged flag
 };
 
 // Direct global -> LDS load of 16 bytes per lane (gfx950 global_load_lds):
@@ -181,6 +183,7 @@ struct pd_plan_s {
   double *host_dev = nullptr;  // device view of host_pin (kernel-written status)
   const double *gm_skip = nullptr;   // set during GMRES: converged flag for the J kernels
   int gm_pred = 2;             // GMRES iterations enqueued ahead (the last solve's count)
+  int gm_seen = 0;             // a solve has run (gm_pred is learned)
   int tri_G = 0;
   double *bvec = nullptr, *xvec = nullptr, *wvec = nullptr;
   double *V = nullptr;         // [(maxit+1)][nbar] Krylov basis
@@ -294,6 +297,9 @@ pd_status pd_gmres_batch_arnoldi(const VecJob *jobs, int count, int j, int MX, d
 int pd_gmres_fused_max_n();
 // speculative capacitance GMRES of the single-problem 1D path
 bool pd_gmres_fused_ok(pd_plan p);
+size_t pd_gmres_done_index(int maxit);   // offset of the converged flag in the state
+// drop cached batch runs (tables, captured graphs) that use this plan
+void pd_batch_forget(pd_plan p);
 pd_status pd_gmres_enqueue(pd_plan p, const double *b, double *x, double rtol, int count);
 void pd_gmres_read(pd_plan p, int *m, double *res, double *beta, bool *done);
 pd_status pd_gmres_continue(pd_plan p, double *x, double rtol, int *iters, double *relres);

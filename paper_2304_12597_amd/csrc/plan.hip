@@ -470,6 +470,7 @@ extern "C" pd_status paradiag_plan_destroy(pd_plan p) {
     return PD_EINVAL;
   }
   (void)hipStreamSynchronize(p->stream);
+  pd_batch_forget(p);
   free_plan(p);
   return PD_OK;
 }

@@ -113,6 +113,7 @@ pd_status solve_speculative(pd_plan p, const double *u0, const double *F, double
     gst = PD_ENOTCONV;
   }
   if (m > 0) p->gm_pred = m;
+  p->gm_seen = 1;
   if (info) {
     info->gmres_iters = m;
     info->pint_loops = m + 2;

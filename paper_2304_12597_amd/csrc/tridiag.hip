@@ -1016,6 +1016,7 @@ tridiag_batch_kernel(const TriJob *__restrict__ jobs, const int2 *__restrict__ m
   const int2 m = map[blockIdx.x];
   if (active && !active[m.x]) return;   // whole block leaves together
   const TriJob &j = jobs[m.x];
+  if (j.skip && *j.skip != 0.0) return;
   Coef<R> cf;
   cf.ML = cf.MD = cf.MU = cf.KL = cf.KD = cf.KU = nullptr;
   cf.ml = (R)j.ml; cf.md = (R)j.md; cf.mu = (R)j.mu;
@@ -1048,6 +1049,7 @@ __global__ void reduce_batch_kernel(const VecJob *__restrict__ jobs, const int2 
   const int2 m = map[blockIdx.x];
   if (active && !active[m.x]) return;
   const VecJob &j = jobs[m.x];
+  if (base_j >= 0 && *j.done != 0.0) return;   // converged: no more J products
   const int i = m.y * blockDim.x + threadIdx.x;
   if (i >= j.n) return;
   // the same summation order as the single-problem two-stage reduction

@@ -124,3 +124,39 @@ def test_solve_batch_matches_individual(lib):
     for U, Ua, info in zip(Us, alone, infos):
         assert np.array_equal(U.cpu().numpy(), Ua)
         assert info.gmres_iters >= 1
+
+
+def test_solve_batch_graph_replays(lib):
+    """The first batched call runs eagerly and records each plan's GMRES
+    iteration count; the second captures the whole solve as a HIP graph and
+    later calls replay it.  Every replay (with eager torch work and
+    synchronisations in between, the outputs cleared first) equals the eager
+    result bit for bit and the problems solved alone."""
+    probs = [p for p in mixed_problems(7) if p.dims == 1][:6]
+    alone = [solve_alone(lib, p) for p in probs]
+    s = torch.cuda.current_stream().cuda_stream
+    plans = [lib.paradiag_plan_create(p.n, p.ell, p.tau, p.M, p.K, stream=s) for p in probs]
+    try:
+        u0s = [T(p.u0) for p in probs]
+        Fs = [T(p.F) for p in probs]
+        Us = [torch.empty((p.ell, p.nbar), dtype=torch.float64, device=dev()) for p in probs]
+        results = []
+        for call in range(5):
+            for U in Us:
+                U.zero_()
+            scratch = torch.ones(1 << 16, dtype=torch.float64, device=dev()).cumsum(0)
+            torch.cuda.synchronize()
+            infos = lib.paradiag_solve_batch(plans, u0s, Fs, Us, 1e-10)
+            torch.cuda.synchronize()
+            assert float(scratch[-1]) == float(1 << 16)
+            results.append([U.cpu().numpy() for U in Us])
+            for info in infos:
+                assert info.gmres_iters >= 1
+    finally:
+        for pl in plans:
+            lib.paradiag_plan_destroy(pl)
+    for call in range(1, 5):
+        for Ua, Ub in zip(results[0], results[call]):
+            assert np.array_equal(Ua, Ub), call
+    for Ua, Ub in zip(results[0], alone):
+        assert np.array_equal(Ua, Ub)
