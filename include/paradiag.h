@@ -86,6 +86,10 @@ typedef struct {
   int check_residual;  /* PD_FP64/PD_FP32: also compute the float64 true    */
                        /* all-at-once residual after the solve              */
   void *stream;        /* hipStream_t                                       */
+  int autotune;        /* 1D: time the candidate time-transform tile widths */
+                       /* and shifted-solve rows per thread at plan creation */
+                       /* and keep the fastest (cached per n, ell,          */
+                       /* precision); 0 = built-in choice                   */
 } pd_options;
 
 typedef struct {
@@ -97,7 +101,7 @@ typedef struct {
 } pd_info;
 
 /* Fill *opt with defaults: dims 1, PD_FP64, alpha 1, maxit 64,
- * max_sweeps 16, check_residual 0, stream NULL. */
+ * max_sweeps 16, check_residual 0, stream NULL, autotune 0. */
 void paradiag_default_options(pd_options *opt);
 
 /* Create a plan for an n x ell problem with time step tau (Section 1).
@@ -131,6 +135,11 @@ pd_status paradiag_solve_batch(const pd_plan *plans, int count,
                                double tol, pd_info *infos);
 
 pd_status paradiag_plan_destroy(pd_plan plan);
+
+/* The launch configuration a plan uses: point pairs per time-transform
+ * tile (*fft_C) and rows per thread of the shifted solves (*rows_per_thread;
+ * 1D).  Either pointer may be NULL.  Errors: PD_EINVAL. */
+pd_status paradiag_plan_config(pd_plan plan, int *fft_C, int *rows_per_thread);
 
 /* Thread-local message describing the last failure ("" if none). */
 const char *paradiag_last_error(void);

@@ -36,7 +36,7 @@ class pd_options(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int), ("precision", ctypes.c_int),
                 ("alpha", ctypes.c_double), ("maxit", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int), ("check_residual", ctypes.c_int),
-                ("stream", _vp)]
+                ("stream", _vp), ("autotune", ctypes.c_int)]
 
 
 class pd_info(ctypes.Structure):
@@ -67,6 +67,8 @@ _solve_batch = _sig("paradiag_solve_batch", ctypes.c_int,
                      ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_double,
                      ctypes.POINTER(pd_info)])
 _plan_destroy = _sig("paradiag_plan_destroy", ctypes.c_int, [_vp])
+_plan_config = _sig("paradiag_plan_config", ctypes.c_int,
+                    [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)])
 _last_error = _sig("paradiag_last_error", ctypes.c_char_p, [])
 _spectrum_bytes = _sig("paradiag_spectrum_bytes", ctypes.c_size_t, [_vp])
 _forward = _sig("paradiag_forward_transform", ctypes.c_int, [_vp, _vp, _vp, _vp])
@@ -128,7 +130,7 @@ def paradiag_last_error() -> str:
 def paradiag_plan_create(n, ell, tau, M, K, options=None, **kw):
     """M, K: (lower, diag, upper) arrays or None for M = I.  Keyword
     arguments override fields of pd_options (dims, precision, alpha, maxit,
-    max_sweeps, check_residual, stream)."""
+    max_sweeps, check_residual, stream, autotune)."""
     opt = options if options is not None else paradiag_default_options()
     for k, v in kw.items():
         if k == "stream" and v is not None and not isinstance(v, int):
@@ -140,6 +142,14 @@ def paradiag_plan_create(n, ell, tau, M, K, options=None, **kw):
                       _tridiag(K, keep), ctypes.byref(opt))
     _check(st, "paradiag_plan_create")
     return plan
+
+
+def paradiag_plan_config(plan):
+    """(point pairs per time-transform tile, rows per thread of the shifted
+    solves) of a plan."""
+    c, mr = ctypes.c_int(), ctypes.c_int()
+    _check(_plan_config(plan, ctypes.byref(c), ctypes.byref(mr)), "paradiag_plan_config")
+    return c.value, mr.value
 
 
 def paradiag_plan_destroy(plan):

@@ -184,6 +184,7 @@ struct pd_plan_s {
   const double *gm_skip = nullptr;   // set during GMRES: converged flag for the J kernels
   int gm_pred = 2;             // GMRES iterations enqueued ahead (the last solve's count)
   int gm_seen = 0;             // a solve has run (gm_pred is learned)
+  int autotune = 0;            // buffers sized for every tuning candidate
   int tri_G = 0;
   double *bvec = nullptr, *xvec = nullptr, *wvec = nullptr;
   double *V = nullptr;         // [(maxit+1)][nbar] Krylov basis
@@ -266,6 +267,7 @@ inline int pd_tri_nitems(const TriConfig &T, int F2) {
 // per thread keeps the partition solve out of scratch), 1024 otherwise.
 inline int pd_tri_block_threads(int prec) { return prec == PD_FP64 ? 512 : 1024; }
 TriConfig pd_choose_tri(int n, int F2, int prec, size_t max_lds);
+TriConfig pd_choose_tri_mr(int n, int F2, int prec, size_t max_lds, int MR);
 void pd_uniform_factors(const pd_plan p, int MR, std::vector<double> &fac);
 void pd_fft_set_attributes(size_t max_lds);
 void pd_tri_set_attributes(size_t max_lds);

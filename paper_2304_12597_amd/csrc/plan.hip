@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 
@@ -110,7 +111,7 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
   const int nitems = pd_tri_nitems(p->tri, F2);
   p->tri_G = nitems < cus ? nitems : cus;
   L.partials = (size_t)p->tri_G * n;
-  L.rstage = (size_t)((p->tri_G + 15) / 16) * n;
+  L.rstage = (size_t)(((p->autotune ? cus : p->tri_G) + 15) / 16) * n;
   if (p->dims == 2) {
     p->l2d = pd_choose_line2d(n, F2, p->prec, cus);
     if (p->l2d.lds > max_lds) {
@@ -129,8 +130,10 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
     if ((size_t)p->l2d.nkc * p->nbar > L.partials) L.partials = (size_t)p->l2d.nkc * p->nbar;
     L.rstage = std::max(L.rstage, (size_t)((p->l2d.nkc + 15) / 16) * p->nbar);
   } else if (p->uniform) {
-    L.fac = (size_t)(F2 + 1) * 6 * (p->tri.MR - 1) * 2;   // + the paired real shifts
+    // + the paired real shifts; autotuning may pick up to 16 rows per thread
+    L.fac = (size_t)(F2 + 1) * 6 * ((p->autotune ? 16 : p->tri.MR) - 1) * 2;
   }
+  if (p->autotune) L.partials = std::max(L.partials, (size_t)cus * n);
   L.coef = 6 * (size_t)n;
   L.lam = 2 * (size_t)F2;
   L.tw = 2 * (size_t)ell;
@@ -142,6 +145,7 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
   const int B = pd_vec_blocks(p->nbar);
   size_t red_n = 2 * (size_t)B * (p->maxit + 2);
   size_t fb = 2 * (size_t)pd_fft_blocks(p);
+  if (p->autotune) fb = 2 * (size_t)((p->nbar + 1) / 2);   // any tile width down to C = 1
   if (fb > red_n) red_n = fb;
   size_t rb = 2 * (size_t)pd_residual_blocks(p);
   if (rb > red_n) red_n = rb;
@@ -157,6 +161,147 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
 
 void pd_set_error(const std::string &msg) { g_last_error = msg; }
 
+// ---------------------------------------------------------------------------
+// Autotuning (1D): the tile width C of the time transforms and the rows per
+// thread MR of the shifted solves are timed on the plan's own buffers with
+// zero inputs (run time does not depend on the values), the fastest kept,
+// and the choice remembered per (n, ell, precision, constant diagonals or
+// not) for later plans.  Buffers that depend on C or MR were sized for every candidate.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct TuneKey {
+  int n, ell, prec, uniform;
+  bool operator<(const TuneKey &o) const {
+    if (n != o.n) return n < o.n;
+    if (ell != o.ell) return ell < o.ell;
+    if (prec != o.prec) return prec < o.prec;
+    return uniform < o.uniform;
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tuned;   // -> (C, MR)
+
+bool fft_C_ok(pd_plan p, int C, size_t max_lds) {
+  const size_t cb = (p->prec == PD_FP64) ? 16 : 8;
+  int maxC = 1;
+  while (2 * maxC < p->nbar && maxC < 32) maxC *= 2;
+  return C <= maxC && (size_t)C * p->ell / 8 <= 1024 &&
+         ((size_t)C * p->fft_stride + pd_tw_entries(p->ell)) * cb <= max_lds;
+}
+
+// Shifted-solve configuration with MR rows per thread, factors uploaded;
+// false if MR is not valid for this plan.
+bool set_tri(pd_plan p, int MR, int cus, size_t max_lds) {
+  TriConfig T = pd_choose_tri_mr(p->n, p->F2, p->prec, max_lds, MR);
+  if (!(p->dims == 1 && p->uniform)) T.pipe = 0;
+  if (T.lds > max_lds || T.block > (T.pipe ? 512 : 1024) || (T.pipe && MR == 16 && T.spb != 1))
+    return false;
+  p->tri = T;
+  const int nitems = pd_tri_nitems(T, p->F2);
+  p->tri_G = nitems < cus ? nitems : cus;
+  if (p->uniform) {
+    std::vector<double> fac;
+    pd_uniform_factors(p, MR, fac);
+    std::vector<float> fac32(fac.begin(), fac.end());
+    if (hipMemcpy(p->fac64, fac.data(), fac.size() * sizeof(double), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(p->fac32, fac32.data(), fac32.size() * sizeof(float), hipMemcpyHostToDevice) !=
+            hipSuccess)
+      return false;
+  }
+  return true;
+}
+
+template <typename Fn>
+float time_launches(pd_plan p, Fn fn) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return -1.f;
+  }
+  fn();   // warm-up
+  (void)hipEventRecord(e0, p->stream);
+  for (int r = 0; r < 3; ++r) fn();
+  (void)hipEventRecord(e1, p->stream);
+  float ms = -1.f;
+  if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+    ms = -1.f;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms;
+}
+
+pd_status autotune(pd_plan p, int cus, size_t max_lds) {
+  const TuneKey key{p->n, p->ell, p->prec, p->uniform ? 1 : 0};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      p->fft_C = it->second.first;
+      if (!set_tri(p, it->second.second, cus, max_lds)) {
+        pd_set_error("autotune: cached shifted-solve configuration not valid");
+        return PD_EHIP;
+      }
+      return PD_OK;
+    }
+  }
+  const size_t nbar = p->nbar, ell = p->ell;
+  double *zu = nullptr, *zf = nullptr;
+  if (hipMalloc(&zu, nbar * sizeof(double)) != hipSuccess ||
+      hipMalloc(&zf, nbar * ell * sizeof(double)) != hipSuccess) {
+    if (zu) (void)hipFree(zu);
+    pd_set_error("autotune: device allocation failed");
+    return PD_ENOMEM;
+  }
+  pd_status st = PD_OK;
+  if (hipMemset(zu, 0, nbar * sizeof(double)) != hipSuccess ||
+      hipMemset(zf, 0, nbar * ell * sizeof(double)) != hipSuccess)
+    st = PD_EHIP;
+  int bestC = p->fft_C, bestMR = p->tri.MR;
+  if (st == PD_OK) {
+    float best = -1.f;
+    for (int C = 1; C <= 32; C *= 2) {
+      if (!fft_C_ok(p, C, max_lds)) continue;
+      p->fft_C = C;
+      const float ms =
+          time_launches(p, [&] { (void)pd_launch_fft_forward(p, zu, zf, nullptr, p->spec, 0); });
+      if (ms > 0.f && (best < 0.f || ms < best)) {
+        best = ms;
+        bestC = C;
+      }
+    }
+    p->fft_C = bestC;
+    // the spectrum now holds zeros: time the shifted solves of pass B on it
+    best = -1.f;
+    for (int MR : {4, 8, 16}) {
+      if (!set_tri(p, MR, cus, max_lds)) continue;
+      const float ms = time_launches(p, [&] {
+        (void)pd_launch_tridiag(p, 0, p->spec, nullptr, nullptr);
+        (void)pd_launch_reduce_partials(p, nullptr, p->bvec);
+      });
+      if (ms > 0.f && (best < 0.f || ms < best)) {
+        best = ms;
+        bestMR = MR;
+      }
+    }
+    if (!set_tri(p, bestMR, cus, max_lds)) st = PD_EHIP;
+  }
+  (void)hipGetLastError();
+  (void)hipFree(zu);
+  (void)hipFree(zf);
+  if (st != PD_OK) {
+    pd_set_error("autotune: HIP error while timing candidates");
+    return st;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[key] = {bestC, bestMR};
+  return PD_OK;
+}
+
+}  // namespace
+
 extern "C" const char *paradiag_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" void paradiag_default_options(pd_options *opt) {
@@ -168,6 +313,7 @@ extern "C" void paradiag_default_options(pd_options *opt) {
   opt->max_sweeps = 16;
   opt->check_residual = 0;
   opt->stream = nullptr;
+  opt->autotune = 0;
 }
 
 extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double tau,
@@ -270,6 +416,7 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   p->maxit = opt.maxit;
   p->max_sweeps = opt.max_sweeps;
   p->check_residual = opt.check_residual;
+  p->autotune = (opt.autotune != 0 && opt.dims == 1) ? 1 : 0;
   p->stream = reinterpret_cast<hipStream_t>(opt.stream);
   p->mass_identity = (M == nullptr);
   if (hipGetDevice(&p->device) != hipSuccess) {
@@ -417,8 +564,8 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   PD_TRY(dev_alloc(&p->tw64, tw.size()));
   PD_TRY(dev_alloc(&p->tw32, tw32.size()));
   PD_TRY(dev_alloc(&p->dal, dal.size()));
-  PD_TRY(dev_alloc(&p->fac64, fac.size()));
-  PD_TRY(dev_alloc(&p->fac32, fac32.size()));
+  PD_TRY(dev_alloc(&p->fac64, std::max(fac.size(), L.fac)));
+  PD_TRY(dev_alloc(&p->fac32, std::max(fac32.size(), L.fac)));
   PD_TRY(dev_alloc(&p->twd, twd.size()));
   if (p->dims == 2) PD_TRY(dev_alloc(&p->wreal, (size_t)ell * nbar));
   PD_TRY(dev_alloc(reinterpret_cast<unsigned char **>(&p->spec), p->spec_bytes));
@@ -460,7 +607,24 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
     free_plan(p);
     return PD_EHIP;
   }
+  if (p->autotune) {
+    const pd_status ts = autotune(p, cus, max_lds);
+    if (ts != PD_OK) {
+      free_plan(p);
+      return ts;
+    }
+  }
   *out = p;
+  return PD_OK;
+}
+
+extern "C" pd_status paradiag_plan_config(pd_plan p, int *fft_C, int *rows_per_thread) {
+  if (!p) {
+    pd_set_error("plan is NULL");
+    return PD_EINVAL;
+  }
+  if (fft_C) *fft_C = p->dims == 1 ? p->fft_C : p->dst_C;
+  if (rows_per_thread) *rows_per_thread = p->dims == 1 ? p->tri.MR : p->l2d.MR;
   return PD_OK;
 }
 
@@ -493,6 +657,7 @@ extern "C" size_t paradiag_plan_bytes(int n, int ell, const pd_options *opt_in) 
   tmp.prec = opt.precision;
   tmp.maxit = opt.maxit;
   tmp.uniform = true;
+  tmp.autotune = (opt.autotune != 0 && opt.dims == 1) ? 1 : 0;
   int dev = 0, cus = 256, lds = 65536;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);

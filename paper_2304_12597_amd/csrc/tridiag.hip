@@ -868,13 +868,18 @@ pd_status launch_mr(pd_plan p, int mode, const void *in, const double *xv, void 
 // Pick (P, MR, systems per block) for n rows: MR rows per thread, P a power of
 // two with P*MR >= n.
 TriConfig pd_choose_tri(int n, int F2, int prec, size_t max_lds) {
-  TriConfig T;
-  const size_t cb = (prec == PD_FP64) ? 16 : 8;
   int MR = 8;
   if (n > 8192) MR = 16;
   // complex128 above 4096 rows: 16 rows per thread, one system per block
   if (prec == PD_FP64 && n > 4096) MR = 16;
   if (n <= 64) MR = 4;
+  return pd_choose_tri_mr(n, F2, prec, max_lds, MR);
+}
+
+// The configuration for a given MR (4, 8 or 16).
+TriConfig pd_choose_tri_mr(int n, int F2, int prec, size_t max_lds, int MR) {
+  TriConfig T;
+  const size_t cb = (prec == PD_FP64) ? 16 : 8;
   int P = 1;
   while (P * MR < n) P *= 2;
   T.P = P;

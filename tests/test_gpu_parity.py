@@ -257,3 +257,26 @@ def test_fem_full_size_sampled(lib):
     assert info.rel_residual < 1e-8
     assert np.allclose(U[-1, ii[:50]], modal.modal_sample(p, np.full(50, p.ell - 1), ii[:50]),
                        rtol=1e-6, atol=1e-9)
+
+
+@pytest.mark.parametrize("n,ell", [(300, 64), (1500, 128), (5000, 256)])
+def test_autotuned_plan(lib, n, ell):
+    """An autotuned plan picks a valid tile width and rows per thread, solves
+    to the same accuracy as the built-in choice, and a second plan of the
+    same shape reuses the choice."""
+    p = make_problem("fem1", n, ell, 11)
+    s = torch.cuda.current_stream().cuda_stream
+    plan = lib.paradiag_plan_create(p.n, p.ell, p.tau, p.M, p.K, stream=s, autotune=1)
+    plan2 = lib.paradiag_plan_create(p.n, p.ell, p.tau, p.M, p.K, stream=s, autotune=1)
+    try:
+        C, MR = lib.paradiag_plan_config(plan)
+        assert C in (1, 2, 4, 8, 16, 32) and MR in (4, 8, 16)
+        assert lib.paradiag_plan_config(plan2) == (C, MR)
+        U = torch.empty((p.ell, p.nbar), dtype=torch.float64, device=dev())
+        info = lib.paradiag_solve(plan, T(p.u0), T(p.F), U, 1e-10)
+        torch.cuda.synchronize()
+        assert allatonce.rel_err(U.cpu().numpy(), modal.modal_solution(p)) < 1e-9
+        assert info.gmres_iters >= 1
+    finally:
+        lib.paradiag_plan_destroy(plan)
+        lib.paradiag_plan_destroy(plan2)
