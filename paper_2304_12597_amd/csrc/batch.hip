@@ -93,7 +93,7 @@ pd_status build_run(BatchRun &r, const pd_plan *plans, int count, const double *
       FftJob &f = fj[i];
       f.N = p->ell; f.n = p->n; f.nbar = p->nbar; f.dims = 1;
       f.C = p->fft_C; f.stride = p->fft_stride; f.tau = p->tau;
-      f.u0 = u0[i]; f.F = F[i]; f.U = nullptr; f.coef = p->coef64; f.dal = p->dal;
+      f.u0 = u0[i]; f.F = F[i]; f.U = nullptr; f.coef = p->coef64; f.dal = p->alpha == 1.0 ? nullptr : p->dal;
       f.tw = (prec == PD_FP64) ? (const void *)p->tw64 : (const void *)p->tw32;
       f.spec = p->spec; f.out = U[i]; f.red = p->red;
       const int tiles = (p->nbar + 2 * f.C - 1) / (2 * f.C);

@@ -164,35 +164,57 @@ __device__ __forceinline__ void fft_forward_body(int tile, int N, int n, int nba
   const int i0 = tile * S;
   double rn2 = 0.0, gn2 = 0.0;
   // Issue UNR independent loads per thread before storing to LDS, so their
-  // HBM latencies overlap instead of adding up.
+  // HBM latencies overlap instead of adding up: every load reads a clamped,
+  // valid address, and out-of-tile entries are zeroed afterwards.  dal ==
+  // NULL: alpha = 1, no scaling.
   constexpr int UNR = 8;
   const int total = N * S;
+  double h0 = 0.0;   // u0 at the point of a t = 0 entry (threads tid < S)
+  if (MODE == 0) {
+    const int i = i0 + (tid < S ? tid : 0);
+    h0 = u0[i < nbar ? i : nbar - 1];
+  }
   for (int base = tid; base < total; base += UNR * T) {
     double vals[UNR];
+    if constexpr (MODE != 1) {
+      double fv[UNR], sc[UNR];
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const int idx = base + u * T;
-      double val = 0.0;
-      if (idx < total) {
-        const int t = idx / S, pnt = idx - t * S;
-        const int i = i0 + pnt;
-        if (i < nbar) {
-          if (MODE == 0) {
-            val = tau * F[(size_t)t * nbar + i];
-            if (t == 0) val += u0[i];
-          } else if (MODE == 2) {
-            val = F[(size_t)t * nbar + i];   // plain real input
-          } else {
+      for (int u = 0; u < UNR; ++u) {
+        const int idx = base + u * T;
+        const int ic = idx < total ? idx : total - 1;
+        const int t = ic / S, i = i0 + (ic - t * S);
+        fv[u] = F[(size_t)t * nbar + (i < nbar ? i : nbar - 1)];
+        sc[u] = dal ? dal[t] : 1.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int idx = base + u * T;
+        const int ic = idx < total ? idx : total - 1;
+        const int i = i0 + (ic - (ic / S) * S);
+        double val = (MODE == 0) ? tau * fv[u] : fv[u];
+        if (MODE == 0 && idx < S) val += h0;
+        if (dal) val *= sc[u];
+        vals[u] = (idx < total && i < nbar) ? val : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int idx = base + u * T;
+        double val = 0.0;
+        if (idx < total) {
+          const int t = idx / S, pnt = idx - t * S;
+          const int i = i0 + pnt;
+          if (i < nbar) {
             double r, g;
             residual_point(t, i, n, nbar, dims, tau, u0, F, U, coef, r, g);
             rn2 += r * r;
             gn2 += g * g;
             val = r;
+            if (dal) val *= dal[t];
           }
-          val *= dal[t];
         }
+        vals[u] = val;
       }
-      vals[u] = val;
     }
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
@@ -300,15 +322,22 @@ __device__ __forceinline__ void fft_inverse_body(int tile, int N, int nbar, int 
     cpx<R> xa[UNR], xb[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
+      // clamped, valid addresses; out-of-tile values are zeroed after the loads
       const int idx = base + u * T;
-      xa[u] = cpx<R>{R(0), R(0)};
-      xb[u] = cpx<R>{R(0), R(0)};
-      if (idx < total) {
-        const int k = idx / C, c = idx - k * C;
-        const int ia = i0 + 2 * c, ib = ia + 1;
-        if (ia < nbar) xa[u] = in[(size_t)k * nbar + ia];
-        if (ib < nbar) xb[u] = in[(size_t)k * nbar + ib];
-      }
+      const int ic = idx < total ? idx : total - 1;
+      const int k = ic / C, c = ic - k * C;
+      const int ia = i0 + 2 * c, ib = ia + 1;
+      xa[u] = in[(size_t)k * nbar + (ia < nbar ? ia : nbar - 1)];
+      xb[u] = in[(size_t)k * nbar + (ib < nbar ? ib : nbar - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = base + u * T;
+      const int ic = idx < total ? idx : total - 1;
+      const int ia = i0 + 2 * (ic - (ic / C) * C);
+      const cpx<R> zc = {R(0), R(0)};
+      xa[u] = pd_sel(idx < total && ia < nbar, xa[u], zc);
+      xb[u] = pd_sel(idx < total && ia + 1 < nbar, xb[u], zc);
     }
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
@@ -339,7 +368,8 @@ __device__ __forceinline__ void fft_inverse_body(int tile, int N, int nbar, int 
       int i = i0 + pnt;
       i = i < nbar ? i : nbar - 1;
       const cpx<R> z = lds[(pnt >> 1) * stride + pd_fpad(t)];
-      val[u] = (double)((pnt & 1) ? z.im : z.re) * invN * dalinv[t];
+      val[u] = (double)((pnt & 1) ? z.im : z.re) * invN;
+      if (dalinv) val[u] *= dalinv[t];
       if (ACC) val[u] += U[(size_t)t * nbar + i];
     }
 #pragma unroll
@@ -524,10 +554,11 @@ int pd_choose_fft_C(int ell, int nbar, int prec, size_t max_lds) {
 pd_status pd_launch_fft_forward(pd_plan p, const double *u0, const double *F,
                                 const double *U, void *out, int mode) {
   FftLaunch L = fft_config(p);
+  const double *dal = p->alpha == 1.0 ? nullptr : p->dal;   // D_alpha = I for alpha = 1
 #define PD_FWD(R, M, TW, O)                                                                 \
   hipLaunchKernelGGL((fft_forward_kernel<R, M>), dim3(L.blocks), dim3(L.threads), L.lds,    \
                      p->stream, p->ell, p->n, p->nbar, p->dims, L.C, L.stride, p->tau, u0, \
-                     F, U, p->coef64, p->dal, TW, O, p->red)
+                     F, U, p->coef64, dal, TW, O, p->red)
   if (p->prec == PD_FP64) {
     auto tw = reinterpret_cast<const cpx<double> *>(p->tw64);
     auto o = reinterpret_cast<cpx<double> *>(out);
@@ -595,7 +626,7 @@ pd_status pd_launch_dst_x(pd_plan p, int mode, const double *u0, const double *F
 
 pd_status pd_launch_fft_inverse(pd_plan p, const void *in, double *U, int accumulate) {
   FftLaunch L = fft_config(p);
-  const double *dalinv = p->dal + p->ell;
+  const double *dalinv = p->alpha == 1.0 ? nullptr : p->dal + p->ell;
 #define PD_INV(R, A, TW, I)                                                                 \
   hipLaunchKernelGGL((fft_inverse_kernel<R, A>), dim3(L.blocks), dim3(L.threads), L.lds,    \
                      p->stream, p->ell, p->nbar, L.C, L.stride, I, dalinv, TW, U)
@@ -652,7 +683,7 @@ fft_inverse_batch_kernel(const FftJob *__restrict__ jobs, const int2 *__restrict
   const int2 m = map[blockIdx.x];
   const FftJob &j = jobs[m.x];
   fft_inverse_body<R, 0>(m.y, j.N, j.nbar, j.C, j.stride,
-                         reinterpret_cast<const cpx<R> *>(j.spec), j.dal + j.N,
+                         reinterpret_cast<const cpx<R> *>(j.spec), j.dal ? j.dal + j.N : nullptr,
                          reinterpret_cast<const cpx<R> *>(j.tw), j.out);
 }
 }  // namespace
