@@ -214,9 +214,7 @@ pd_status enqueue_solve(const BatchRun &r, int K, double rtol, hipStream_t s) {
   PD_B(pd_launch_fft_forward_batch(r.prec, r.fj, r.fm, r.nf, r.fft_threads, r.fft_lds, s));
   PD_B(pd_launch_tridiag_batch(r.prec, r.MR, 0, r.tj, r.t0, r.n0, r.tri_lds, nullptr, 0, s));
   PD_B(pd_launch_reduce_batch(r.vj, r.rm, r.nr, -1, nullptr, s));
-  PD_B(pd_gmres_batch_dots(r.vj, r.vm, r.nv, 0, 1, nullptr, s));
-  PD_B(pd_gmres_batch_init(r.vj, r.count, r.MX, r.st, s));
-  PD_B(pd_gmres_batch_scale(r.vj, r.vm, r.nv, 0, r.MX, 1, nullptr, s));
+  PD_B(pd_gmres_batch_start(r.vj, r.count, r.MX, r.st, s));
   for (int j = 0; j < K; ++j) {
     PD_B(pd_launch_tridiag_batch(r.prec, r.MR, 2, r.tjJ, r.t0, r.n0, r.tri_lds, nullptr, j, s));
     PD_B(pd_launch_reduce_batch(r.vj, r.rm, r.nr, j, nullptr, s));

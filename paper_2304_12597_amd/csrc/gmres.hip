@@ -336,6 +336,76 @@ int pd_vec_blocks(int n) {
 
 namespace {
 
+// Start of GMRES on one block: beta = ||b||, the small state reset (g =
+// beta e_1, converged flag set when beta is 0 or not finite), V_0 = b / beta.
+// st_out[0..3] = beta, beta, 0, beta; st_out[4] (with_flag) = converged.
+template <int RPT>
+__device__ __forceinline__ void gm_init_body(int n, const double *__restrict__ b,
+                                             double *__restrict__ V, double *__restrict__ gm,
+                                             int MX, double *__restrict__ st_out, bool with_flag) {
+  constexpr int NW = ARN_T / 64;
+  __shared__ double part[NW];
+  __shared__ double bsh;
+  GmLayout L{MX};
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int i = tid; i < L.size(); i += blockDim.x) gm[i] = 0.0;
+  double br[RPT];
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int r = tid + k * ARN_T;
+    br[k] = r < n ? b[r] : 0.0;
+    s += br[k] * br[k];
+  }
+  s = wave_sum(s);
+  if (lane == 0) part[wv] = s;
+  __syncthreads();   // also orders the reset of gm before thread 0 writes it
+  if (tid == 0) {
+    double nn = 0.0;
+    for (int q = 0; q < NW; ++q) nn += part[q];
+    const double beta = sqrt(nn);
+    const double done = (beta == 0.0 || !isfinite(beta)) ? 1.0 : 0.0;
+    gm[L.g(0)] = beta;
+    gm[L.st(0)] = beta;
+    gm[L.st(1)] = beta;
+    gm[L.st(3)] = beta;
+    gm[L.st(GM_DONE)] = done;
+    st_out[0] = beta;
+    st_out[1] = beta;
+    st_out[2] = 0.0;
+    st_out[3] = beta;
+    if (with_flag) st_out[4] = done;
+    bsh = beta;
+  }
+  __syncthreads();
+  const double inv = (bsh > 0.0) ? 1.0 / bsh : 0.0;
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int r = tid + k * ARN_T;
+    if (r < n) V[r] = br[k] * inv;
+  }
+}
+
+template <int RPT>
+__global__ void __launch_bounds__(ARN_T)
+gm_init_kernel(int n, const double *__restrict__ b, double *__restrict__ V,
+               double *__restrict__ gm, int MX, double *__restrict__ host) {
+  gm_init_body<RPT>(n, b, V, gm, MX, host, true);
+}
+
+void launch_gm_init(pd_plan p, const double *b) {
+  const int n = p->nbar;
+  if (n <= 4 * ARN_T)
+    hipLaunchKernelGGL((gm_init_kernel<4>), dim3(1), dim3(ARN_T), 0, p->stream, n, b, p->V,
+                       p->gm, p->maxit, p->host_dev);
+  else if (n <= 8 * ARN_T)
+    hipLaunchKernelGGL((gm_init_kernel<8>), dim3(1), dim3(ARN_T), 0, p->stream, n, b, p->V,
+                       p->gm, p->maxit, p->host_dev);
+  else
+    hipLaunchKernelGGL((gm_init_kernel<16>), dim3(1), dim3(ARN_T), 0, p->stream, n, b, p->V,
+                       p->gm, p->maxit, p->host_dev);
+}
+
 void launch_arnoldi(pd_plan p, int j, double rtol) {
   const int n = p->nbar;
   GmLayout L{p->maxit};
@@ -378,12 +448,8 @@ pd_status gmres_fused(pd_plan p, const double *b, double *x, double rtol, int *i
   const int n = p->nbar, MX = p->maxit;
   const int B = pd_vec_blocks(n);
   GmLayout L{MX};
-  double *red1 = p->red;
   volatile double *st = p->host_pin;
-  hipLaunchKernelGGL(dots_kernel, dim3(B), dim3(VB), 0, p->stream, n, 0, p->V, b, red1);
-  hipLaunchKernelGGL(init_kernel, dim3(1), dim3(256), 0, p->stream, B, red1, p->gm, MX,
-                     p->host_dev);
-  hipLaunchKernelGGL(scale_kernel, dim3(B), dim3(VB), 0, p->stream, n, b, p->V, p->gm, MX);
+  launch_gm_init(p, b);
   PD_HIP_CHECK(hipGetLastError());
   p->gm_skip = p->gm + L.st(GM_DONE);
   int j = 0, chunk = 2;
@@ -447,10 +513,7 @@ size_t pd_gmres_done_index(int maxit) { return (size_t)GmLayout{maxit}.st(GM_DON
 pd_status pd_gmres_enqueue(pd_plan p, const double *b, double *x, double rtol, int count) {
   const int n = p->nbar, MX = p->maxit;
   const int B = pd_vec_blocks(n);
-  hipLaunchKernelGGL(dots_kernel, dim3(B), dim3(VB), 0, p->stream, n, 0, p->V, b, p->red);
-  hipLaunchKernelGGL(init_kernel, dim3(1), dim3(256), 0, p->stream, B, p->red, p->gm, MX,
-                     p->host_dev);
-  hipLaunchKernelGGL(scale_kernel, dim3(B), dim3(VB), 0, p->stream, n, b, p->V, p->gm, MX);
+  launch_gm_init(p, b);
   PD_HIP_CHECK(hipGetLastError());
   pd_status s = enqueue_iters(p, 0, count, rtol);
   if (s != PD_OK) return s;
@@ -723,6 +786,19 @@ batch_arnoldi_kernel(const VecJob *__restrict__ jobs, int j, int MX, double rtol
     arnoldi_step_body<16>(J.n, J.V, J.w, J.gm, MX, j, rtol, st, false);
 }
 
+// one block per problem: the fused start of GMRES (same body as alone)
+__global__ void __launch_bounds__(ARN_T)
+batch_gm_init_kernel(const VecJob *__restrict__ jobs, int MX, double *__restrict__ status) {
+  const VecJob &J = jobs[blockIdx.x];
+  double *st = status + 4 * blockIdx.x;
+  if (J.n <= 4 * ARN_T)
+    gm_init_body<4>(J.n, J.b, J.V, J.gm, MX, st, false);
+  else if (J.n <= 8 * ARN_T)
+    gm_init_body<8>(J.n, J.b, J.V, J.gm, MX, st, false);
+  else
+    gm_init_body<16>(J.n, J.b, J.V, J.gm, MX, st, false);
+}
+
 // per problem: back substitution (block 0 of the problem does it first in a
 // separate launch), then x = V y
 __global__ void batch_backsolve_kernel(const VecJob *__restrict__ jobs, int MX,
@@ -779,6 +855,13 @@ pd_status pd_gmres_batch_arnoldi(const VecJob *jobs, int count, int j, int MX, d
 }
 
 int pd_gmres_fused_max_n() { return ARN_MAXN; }
+
+pd_status pd_gmres_batch_start(const VecJob *jobs, int count, int MX, double *status,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(batch_gm_init_kernel, dim3(count), dim3(ARN_T), 0, s, jobs, MX, status);
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
 
 pd_status pd_gmres_batch_givens(const VecJob *jobs, int count, int j, int MX, double *status,
                                 const int *active, hipStream_t s) {

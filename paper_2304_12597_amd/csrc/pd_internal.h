@@ -297,6 +297,9 @@ pd_status pd_gmres_batch_update(const VecJob *jobs, const int2 *vmap, int nvb, i
 pd_status pd_gmres_batch_arnoldi(const VecJob *jobs, int count, int j, int MX, double rtol,
                                  double *status, const int *active, hipStream_t s);
 int pd_gmres_fused_max_n();
+// the fused start of GMRES per problem (beta, state reset, V_0), as alone
+pd_status pd_gmres_batch_start(const VecJob *jobs, int count, int MX, double *status,
+                               hipStream_t s);
 // speculative capacitance GMRES of the single-problem 1D path
 bool pd_gmres_fused_ok(pd_plan p);
 size_t pd_gmres_done_index(int maxit);   // offset of the converged flag in the state
