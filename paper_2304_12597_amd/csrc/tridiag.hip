@@ -778,6 +778,43 @@ __global__ void reduce_slices_kernel(int n, int G, const double *__restrict__ pa
   stage[(size_t)blockIdx.y * n + i] = s;
 }
 
+// Both stages in one launch: a 1024-thread block owns 64 columns; wave w sums
+// slices w, w + 16, ... (RS rows each, in order) and wave 0 adds the slice
+// sums in order, so the result equals the two-kernel form bit for bit.
+constexpr int RF_COLS = 64, RF_WAVES = 16, RF_MAX_SLICES = 64;
+__global__ void __launch_bounds__(1024)
+reduce_fused_kernel(int n, int G, const double *__restrict__ partials,
+                    const double *__restrict__ base, double *__restrict__ out,
+                    const double *__restrict__ skip) {
+  __shared__ double sl[RF_MAX_SLICES][RF_COLS];
+  if (skip && *skip != 0.0) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = blockIdx.x * RF_COLS + lane;
+  const int ic = i < n ? i : n - 1;
+  const int slices = (G + RS - 1) / RS;
+  for (int sidx = w; sidx < slices; sidx += RF_WAVES) {
+    const int g0 = sidx * RS;
+    const int g1 = g0 + RS < G ? g0 + RS : G;
+    double v[RS];
+#pragma unroll
+    for (int u = 0; u < RS; ++u) {
+      const int g = g0 + u < g1 ? g0 + u : g1 - 1;
+      v[u] = partials[(size_t)g * n + ic];
+    }
+    double t = 0.0;
+#pragma unroll
+    for (int u = 0; u < RS; ++u)
+      if (g0 + u < g1) t += v[u];
+    sl[sidx][lane] = t;
+  }
+  __syncthreads();
+  if (w == 0 && i < n) {
+    double s = 0.0;
+    for (int sidx = 0; sidx < slices; ++sidx) s += sl[sidx][lane];
+    out[i] = (base ? base[i] : 0.0) + s;
+  }
+}
+
 __global__ void reduce_partials_kernel(int n, int G, const double *__restrict__ partials,
                                        const double *__restrict__ base,
                                        double *__restrict__ out, const double *__restrict__ skip) {
@@ -961,7 +998,10 @@ pd_status pd_launch_reduce_partials(pd_plan p, const double *base, double *out) 
   const int nitems = pd_tri_nitems(p->tri, p->F2);
   int G = nitems < p->tri_G ? nitems : p->tri_G;
   if (p->dims == 2) G = p->l2d.nkc;
-  if (G > RS) {
+  if (G > 0 && (G + RS - 1) / RS <= RF_MAX_SLICES) {
+    hipLaunchKernelGGL(reduce_fused_kernel, dim3((n + RF_COLS - 1) / RF_COLS), dim3(1024), 0,
+                       p->stream, n, G, p->partials, base, out, p->gm_skip);
+  } else if (G > RS) {
     const int slices = (G + RS - 1) / RS;
     hipLaunchKernelGGL(reduce_slices_kernel, dim3((n + 255) / 256, slices), dim3(256), 0,
                        p->stream, n, G, p->partials, p->rstage, p->gm_skip);
