@@ -81,32 +81,47 @@ __device__ __forceinline__ void twiddle_powers(cpx<R> *x, cpx<R> w1) {
   }
 }
 
-// One Stockham autosort stage of radix RAD over C columns of length N held
-// in LDS (entry i of column c at c * stride + pd_fpad(i)), in place: all
-// reads, barrier, all writes.  Ns = length of the sub-transforms already
-// done; the twiddles come from the LDS tables (lo, then hi).  Each thread
-// handles up to 8/RAD butterflies (the host launches >= C*N/8 threads).
+// One Stockham autosort stage of radix RAD over C columns of length N = 2^lgN
+// held in LDS (entry i of column c at c * stride + pd_fpad(i)), in place: all
+// reads, barrier, all writes.  Ns = 2^lgNs = length of the sub-transforms
+// already done; the twiddles come from the LDS tables (lo, then hi).  Each
+// thread handles up to 8/RAD butterflies (the host launches >= C*N/8
+// threads).  All sizes are powers of two, so index arithmetic is shifts and
+// masks; where the unpadded stride between a butterfly's RAD entries is a
+// multiple of 8, the padded index is affine in the entry number.
 template <typename R, bool INV, int RAD>
-__device__ __forceinline__ void stockham_stage(cpx<R> *lds, int N, int Ns, int C, int stride,
+__device__ __forceinline__ void stockham_stage(cpx<R> *lds, int lgN, int lgNs, int C, int stride,
                                                const cpx<R> *lo) {
   constexpr int BPT = 8 / RAD;
+  constexpr int LGR = RAD == 8 ? 3 : (RAD == 4 ? 2 : 1);
   const int T = blockDim.x, tid = threadIdx.x;
-  const int per_col = N / RAD;
-  const int nb = C * per_col;
-  const int twstep = N / (Ns * RAD);
+  const int N = 1 << lgN, Ns = 1 << lgNs;
+  const int lgpc = lgN - LGR, per_col = 1 << lgpc;
+  const int nb = C << lgpc;
+  const int lgtw = lgN - lgNs - LGR;   // twiddle step N / (Ns * RAD)
   const cpx<R> *hi = lo + pd_tw_lo(N);
+  const bool rlin = (per_col & 7) == 0;
+  const int rstep = per_col + (per_col >> 3);
+  const bool wlin = (Ns & 7) == 0 || (Ns == 1 && RAD == 8);
+  const int wstep = Ns + (Ns >> 3);
   cpx<R> v[8];
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
-    int b = tid + q * T;
+    const int b = tid + q * T;
     if (b < nb) {
-      int c = b / per_col, j = b - c * per_col;
+      const int c = b >> lgpc, j = b & (per_col - 1);
       const cpx<R> *col = lds + c * stride;
-      int jm = j & (Ns - 1);
+      const int jm = j & (Ns - 1);
+      if (rlin) {
+        const cpx<R> *p = col + pd_fpad(j);
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) v[q * RAD + r] = col[pd_fpad(j + r * per_col)];
+        for (int r = 0; r < RAD; ++r) v[q * RAD + r] = p[r * rstep];
+      } else {
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) v[q * RAD + r] = col[pd_fpad(j + r * per_col)];
+      }
       if (Ns > 1) {
-        const int m = jm * twstep;
+        const int m = jm << lgtw;
         cpx<R> w = cmul(hi[m >> 6], lo[m & 63]);
         if (INV) w.im = -w.im;
         twiddle_powers<R, RAD>(&v[q * RAD], w);
@@ -117,14 +132,20 @@ __device__ __forceinline__ void stockham_stage(cpx<R> *lds, int N, int Ns, int C
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
-    int b = tid + q * T;
+    const int b = tid + q * T;
     if (b < nb) {
-      int c = b / per_col, j = b - c * per_col;
+      const int c = b >> lgpc, j = b & (per_col - 1);
       cpx<R> *col = lds + c * stride;
-      int jm = j & (Ns - 1);
-      int base = (j / Ns) * Ns * RAD + jm;
+      const int jm = j & (Ns - 1);
+      const int base = ((j >> lgNs) << (lgNs + LGR)) + jm;
+      if (wlin) {
+        cpx<R> *p = col + pd_fpad(base);
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) col[pd_fpad(base + r * Ns)] = v[q * RAD + r];
+        for (int r = 0; r < RAD; ++r) p[r * wstep] = v[q * RAD + r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) col[pd_fpad(base + r * Ns)] = v[q * RAD + r];
+      }
     }
   }
   __syncthreads();
@@ -132,15 +153,16 @@ __device__ __forceinline__ void stockham_stage(cpx<R> *lds, int N, int Ns, int C
 
 template <typename R, bool INV>
 __device__ __forceinline__ void fft_lds(cpx<R> *lds, int N, int C, int stride, const cpx<R> *twl) {
-  int Ns = 1;
-  while (Ns * 8 <= N) {
-    stockham_stage<R, INV, 8>(lds, N, Ns, C, stride, twl);
-    Ns *= 8;
+  const int lgN = __builtin_ctz(N);
+  int lgNs = 0;
+  while (lgNs + 3 <= lgN) {
+    stockham_stage<R, INV, 8>(lds, lgN, lgNs, C, stride, twl);
+    lgNs += 3;
   }
-  if (Ns * 4 == N) {
-    stockham_stage<R, INV, 4>(lds, N, Ns, C, stride, twl);
-  } else if (Ns * 2 == N) {
-    stockham_stage<R, INV, 2>(lds, N, Ns, C, stride, twl);
+  if (lgNs + 2 == lgN) {
+    stockham_stage<R, INV, 4>(lds, lgN, lgNs, C, stride, twl);
+  } else if (lgNs + 1 == lgN) {
+    stockham_stage<R, INV, 2>(lds, lgN, lgNs, C, stride, twl);
   }
 }
 
@@ -160,70 +182,64 @@ __device__ __forceinline__ void fft_forward_body(int tile, int N, int n, int nba
   cpx<R> *twl = lds + C * stride;
   tw_to_lds(twl, tw, N);
   const int T = blockDim.x, tid = threadIdx.x;
-  const int S = 2 * C;
+  const int lgS = __builtin_ctz(C) + 1, S = 2 * C;
   const int i0 = tile * S;
+  // T is a multiple of S: every thread owns one point of the tile and the
+  // time rows t0, t0 + dt, ... (entry t*S + pnt of the tile is thread
+  // (t*S + pnt) mod T's)
+  const int pnt = tid & (S - 1);
+  const int t0 = tid >> lgS, dt = T >> lgS;
+  const int i = i0 + pnt;
+  const bool inb = i < nbar;
+  const int ic = inb ? i : nbar - 1;
+  R *lcol = reinterpret_cast<R *>(lds + (pnt >> 1) * stride) + (pnt & 1);
   double rn2 = 0.0, gn2 = 0.0;
   // Issue UNR independent loads per thread before storing to LDS, so their
   // HBM latencies overlap instead of adding up: every load reads a clamped,
   // valid address, and out-of-tile entries are zeroed afterwards.  dal ==
   // NULL: alpha = 1, no scaling.
   constexpr int UNR = 8;
-  const int total = N * S;
-  double h0 = 0.0;   // u0 at the point of a t = 0 entry (threads tid < S)
-  if (MODE == 0) {
-    const int i = i0 + (tid < S ? tid : 0);
-    h0 = u0[i < nbar ? i : nbar - 1];
-  }
-  for (int base = tid; base < total; base += UNR * T) {
+  double h0 = 0.0;   // u0 at this point (used by the t = 0 entry)
+  if (MODE == 0) h0 = u0[ic];
+  for (int tb = t0; tb < N; tb += UNR * dt) {
     double vals[UNR];
     if constexpr (MODE != 1) {
       double fv[UNR], sc[UNR];
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
-        const int idx = base + u * T;
-        const int ic = idx < total ? idx : total - 1;
-        const int t = ic / S, i = i0 + (ic - t * S);
-        fv[u] = F[(size_t)t * nbar + (i < nbar ? i : nbar - 1)];
-        sc[u] = dal ? dal[t] : 1.0;
+        const int t = tb + u * dt;
+        const int tc = t < N ? t : N - 1;
+        fv[u] = F[(size_t)tc * nbar + ic];
+        sc[u] = dal ? dal[tc] : 1.0;
       }
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
-        const int idx = base + u * T;
-        const int ic = idx < total ? idx : total - 1;
-        const int i = i0 + (ic - (ic / S) * S);
+        const int t = tb + u * dt;
         double val = (MODE == 0) ? tau * fv[u] : fv[u];
-        if (MODE == 0 && idx < S) val += h0;
+        if (MODE == 0 && t == 0) val += h0;
         if (dal) val *= sc[u];
-        vals[u] = (idx < total && i < nbar) ? val : 0.0;
+        vals[u] = (t < N && inb) ? val : 0.0;
       }
     } else {
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
-        const int idx = base + u * T;
+        const int t = tb + u * dt;
         double val = 0.0;
-        if (idx < total) {
-          const int t = idx / S, pnt = idx - t * S;
-          const int i = i0 + pnt;
-          if (i < nbar) {
-            double r, g;
-            residual_point(t, i, n, nbar, dims, tau, u0, F, U, coef, r, g);
-            rn2 += r * r;
-            gn2 += g * g;
-            val = r;
-            if (dal) val *= dal[t];
-          }
+        if (t < N && inb) {
+          double r, g;
+          residual_point(t, i, n, nbar, dims, tau, u0, F, U, coef, r, g);
+          rn2 += r * r;
+          gn2 += g * g;
+          val = r;
+          if (dal) val *= dal[t];
         }
         vals[u] = val;
       }
     }
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
-      const int idx = base + u * T;
-      if (idx < total) {
-        const int t = idx / S, pnt = idx - t * S;
-        R *l = reinterpret_cast<R *>(&lds[(pnt >> 1) * stride + pd_fpad(t)]);
-        l[pnt & 1] = (R)vals[u];
-      }
+      const int t = tb + u * dt;
+      if (t < N) lcol[2 * pd_fpad(t)] = (R)vals[u];
     }
   }
   __syncthreads();
@@ -231,35 +247,30 @@ __device__ __forceinline__ void fft_forward_body(int tile, int N, int n, int nba
   const int half = N / 2;
   // split the packed pairs: UNR outputs per thread per round, all LDS reads
   // before the stores (k < N/2 here, the Nyquist row k = N/2 below)
-  const int nout = half * S;
-  for (int base = tid; base < nout; base += UNR * T) {
+  const cpx<R> *ccol = lds + (pnt >> 1) * stride;
+  for (int kb = t0; kb < half; kb += UNR * dt) {
     cpx<R> X[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
-      const int idx = base + u * T;
-      const int ic = idx < nout ? idx : 0;
-      const int k = ic / S, pnt = ic - k * S, c = pnt >> 1;
-      const cpx<R> zk = lds[c * stride + pd_fpad(k)];
-      const cpx<R> zn = lds[c * stride + pd_fpad((N - k) & (N - 1))];
+      const int k = kb + u * dt;
+      const int kc = k < half ? k : 0;
+      const cpx<R> zk = ccol[pd_fpad(kc)];
+      const cpx<R> zn = ccol[pd_fpad((N - kc) & (N - 1))];
       const R xr = (pnt & 1) ? zk.im + zn.im : zk.re + zn.re;
       const R xi = (pnt & 1) ? zn.re - zk.re : zk.im - zn.im;
       X[u] = cpx<R>{R(0.5) * xr, R(0.5) * xi};
     }
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
-      const int idx = base + u * T;
-      if (idx < nout) {
-        const int k = idx / S, pnt = idx - k * S;
-        if (i0 + pnt < nbar) out[(size_t)k * nbar + i0 + pnt] = X[u];
-      }
+      const int k = kb + u * dt;
+      if (k < half && inb) out[(size_t)k * nbar + i] = X[u];
     }
   }
-  for (int pnt = tid; pnt < S; pnt += T) {
-    if (i0 + pnt >= nbar) continue;
-    const cpx<R> z = lds[(pnt >> 1) * stride + pd_fpad(half)];
+  if (tid < S && inb) {
+    const cpx<R> z = ccol[pd_fpad(half)];
     const R xr = (pnt & 1) ? z.im + z.im : z.re + z.re;
     const R xi = (pnt & 1) ? z.re - z.re : z.im - z.im;
-    out[(size_t)half * nbar + i0 + pnt] = cpx<R>{R(0.5) * xr, R(0.5) * xi};
+    out[(size_t)half * nbar + i] = cpx<R>{R(0.5) * xr, R(0.5) * xi};
   }
   if (MODE == 1) {
     // block reduction of the two norms (float64)
@@ -313,72 +324,75 @@ __device__ __forceinline__ void fft_inverse_body(int tile, int N, int nbar, int 
   cpx<R> *twl = lds + C * stride;
   tw_to_lds(twl, tw, N);
   const int T = blockDim.x, tid = threadIdx.x;
-  const int S = 2 * C;
+  const int lgC = __builtin_ctz(C), lgS = lgC + 1, S = 2 * C;
   const int i0 = tile * S;
   const int half = N / 2;
   constexpr int UNR = 4;
-  const int total = (half + 1) * C;
-  for (int base = tid; base < total; base += UNR * T) {
-    cpx<R> xa[UNR], xb[UNR];
+  // input: T is a multiple of C, so every thread owns one point pair c of
+  // the tile and the frequencies k0, k0 + dk, ..., k <= N/2
+  {
+    const int c = tid & (C - 1);
+    const int k0 = tid >> lgC, dk = T >> lgC;
+    const int ia = i0 + 2 * c, ib = ia + 1;
+    const int iac = ia < nbar ? ia : nbar - 1, ibc = ib < nbar ? ib : nbar - 1;
+    cpx<R> *ccol = lds + c * stride;
+    for (int kb = k0; kb <= half; kb += UNR * dk) {
+      cpx<R> xa[UNR], xb[UNR];
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      // clamped, valid addresses; out-of-tile values are zeroed after the loads
-      const int idx = base + u * T;
-      const int ic = idx < total ? idx : total - 1;
-      const int k = ic / C, c = ic - k * C;
-      const int ia = i0 + 2 * c, ib = ia + 1;
-      xa[u] = in[(size_t)k * nbar + (ia < nbar ? ia : nbar - 1)];
-      xb[u] = in[(size_t)k * nbar + (ib < nbar ? ib : nbar - 1)];
-    }
+      for (int u = 0; u < UNR; ++u) {
+        // clamped, valid addresses; out-of-tile values are zeroed after the loads
+        const int k = kb + u * dk;
+        const int kc = k <= half ? k : half;
+        xa[u] = in[(size_t)kc * nbar + iac];
+        xb[u] = in[(size_t)kc * nbar + ibc];
+      }
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const int idx = base + u * T;
-      const int ic = idx < total ? idx : total - 1;
-      const int ia = i0 + 2 * (ic - (ic / C) * C);
-      const cpx<R> zc = {R(0), R(0)};
-      xa[u] = pd_sel(idx < total && ia < nbar, xa[u], zc);
-      xb[u] = pd_sel(idx < total && ia + 1 < nbar, xb[u], zc);
-    }
+      for (int u = 0; u < UNR; ++u) {
+        const int k = kb + u * dk;
+        const cpx<R> zc = {R(0), R(0)};
+        xa[u] = pd_sel(k <= half && ia < nbar, xa[u], zc);
+        xb[u] = pd_sel(k <= half && ib < nbar, xb[u], zc);
+      }
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const int idx = base + u * T;
-      if (idx < total) {
-        const int k = idx / C, c = idx - k * C;
-        cpx<R> a = xa[u], b = xb[u];
-        if (k == 0 || k == half) { a.im = R(0); b.im = R(0); }
-        lds[c * stride + pd_fpad(k)] = cpx<R>{a.re - b.im, a.im + b.re};
-        if (k > 0 && k < half) lds[c * stride + pd_fpad(N - k)] = cpx<R>{a.re + b.im, b.re - a.im};
+      for (int u = 0; u < UNR; ++u) {
+        const int k = kb + u * dk;
+        if (k <= half) {
+          cpx<R> a = xa[u], b = xb[u];
+          if (k == 0 || k == half) { a.im = R(0); b.im = R(0); }
+          ccol[pd_fpad(k)] = cpx<R>{a.re - b.im, a.im + b.re};
+          if (k > 0 && k < half) ccol[pd_fpad(N - k)] = cpx<R>{a.re + b.im, b.re - a.im};
+        }
       }
     }
   }
   __syncthreads();
   fft_lds<R, true>(lds, N, C, stride, twl);
   const double invN = 1.0 / (double)N;
-  // UNR2 outputs per thread per round: the LDS reads and the dalinv (and,
-  // accumulating, U) loads are all issued before the stores
+  // output: every thread owns one point of the tile and the rows t0, t0 +
+  // dt, ...; UNR2 outputs per round, the LDS reads and the dalinv (and,
+  // accumulating, U) loads all issued before the stores
   constexpr int UNR2 = 8;
-  const int nout = N * S;
-  for (int base = tid; base < nout; base += UNR2 * T) {
+  const int pnt = tid & (S - 1);
+  const int t0 = tid >> lgS, dt = T >> lgS;
+  const int i = i0 + pnt;
+  const bool inb = i < nbar;
+  const int ic = inb ? i : nbar - 1;
+  const cpx<R> *ocol = lds + (pnt >> 1) * stride;
+  for (int tb = t0; tb < N; tb += UNR2 * dt) {
     double val[UNR2];
 #pragma unroll
     for (int u = 0; u < UNR2; ++u) {
-      const int idx = base + u * T;
-      const int ic = idx < nout ? idx : 0;
-      const int t = ic / S, pnt = ic - t * S;
-      int i = i0 + pnt;
-      i = i < nbar ? i : nbar - 1;
-      const cpx<R> z = lds[(pnt >> 1) * stride + pd_fpad(t)];
+      const int t = tb + u * dt;
+      const int tc = t < N ? t : 0;
+      const cpx<R> z = ocol[pd_fpad(tc)];
       val[u] = (double)((pnt & 1) ? z.im : z.re) * invN;
-      if (dalinv) val[u] *= dalinv[t];
-      if (ACC) val[u] += U[(size_t)t * nbar + i];
+      if (dalinv) val[u] *= dalinv[tc];
+      if (ACC) val[u] += U[(size_t)tc * nbar + ic];
     }
 #pragma unroll
     for (int u = 0; u < UNR2; ++u) {
-      const int idx = base + u * T;
-      if (idx < nout) {
-        const int t = idx / S, pnt = idx - t * S;
-        if (i0 + pnt < nbar) U[(size_t)t * nbar + i0 + pnt] = val[u];
-      }
+      const int t = tb + u * dt;
+      if (t < N && inb) U[(size_t)t * nbar + i] = val[u];
     }
   }
 }
@@ -551,9 +565,14 @@ int pd_choose_fft_C(int ell, int nbar, int prec, size_t max_lds) {
   return C;
 }
 
+// The transform bodies index with shifts: C must be a power of two <= 32
+// (then the block size, a multiple of 64, is a multiple of 2C).
+static bool fft_C_valid(int C) { return C >= 1 && C <= 32 && (C & (C - 1)) == 0; }
+
 pd_status pd_launch_fft_forward(pd_plan p, const double *u0, const double *F,
                                 const double *U, void *out, int mode) {
   FftLaunch L = fft_config(p);
+  if (!fft_C_valid(L.C)) return PD_EINVAL;
   const double *dal = p->alpha == 1.0 ? nullptr : p->dal;   // D_alpha = I for alpha = 1
 #define PD_FWD(R, M, TW, O)                                                                 \
   hipLaunchKernelGGL((fft_forward_kernel<R, M>), dim3(L.blocks), dim3(L.threads), L.lds,    \
@@ -626,6 +645,7 @@ pd_status pd_launch_dst_x(pd_plan p, int mode, const double *u0, const double *F
 
 pd_status pd_launch_fft_inverse(pd_plan p, const void *in, double *U, int accumulate) {
   FftLaunch L = fft_config(p);
+  if (!fft_C_valid(L.C)) return PD_EINVAL;
   const double *dalinv = p->alpha == 1.0 ? nullptr : p->dal + p->ell;
 #define PD_INV(R, A, TW, I)                                                                 \
   hipLaunchKernelGGL((fft_inverse_kernel<R, A>), dim3(L.blocks), dim3(L.threads), L.lds,    \
