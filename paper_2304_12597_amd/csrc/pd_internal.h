@@ -123,6 +123,11 @@ __device__ __forceinline__ void pd_lds_dma16(const void *gptr, void *lds_base) {
   __builtin_amdgcn_global_load_lds(gptr, lds_base, 16, 0, 0);
 #endif
 }
+__device__ __forceinline__ void pd_lds_dma4(const void *gptr, void *lds_base) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_global_load_lds(gptr, lds_base, 4, 0, 0);
+#endif
+}
 __device__ __forceinline__ void pd_wait_all() {
 #if defined(__HIP_DEVICE_COMPILE__)
   __builtin_amdgcn_s_waitcnt(0);

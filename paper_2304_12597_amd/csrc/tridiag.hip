@@ -489,13 +489,16 @@ __device__ __forceinline__ void tridiag_uniform_body(
 // Pipelined complex128 body for systems of whole waves (P >= 64).  LDS holds
 // the NEXT item's right-hand side and elimination factors, brought in by
 // global_load_lds while the current item is solved from registers, so the
-// HBM loads overlap the elimination.  The right-hand side is staged
-// transposed -- row lt*MR + q of group g at g*P*MR + q*P + lt -- so that every
-// LDS read of a thread's chunk is conflict-free; DMA instruction q of a wave
-// reads rows lt*MR + q of its 64 lanes (a 256-byte stride that the L2 merges
-// into whole lines).  The per-item scalars (lambda_k, gamma_k) are read with
-// scalar loads, which do not wait for the vector-memory counter.  Mode 1
-// stores each thread's rows straight from registers.
+// HBM loads overlap the elimination.  The right-hand side is staged in row
+// order with a rotation inside each thread's chunk -- row lt*MR + q of group
+// g at g*P*MR + lt*MR + ((q + rot(lt)) mod MR), rot(lt) = lt*MR/16 -- so
+// that every LDS read of a thread's chunk is conflict-free, while each DMA
+// instruction (4 bytes per lane) fills 16 consecutive entries from 16
+// consecutive rows: the global reads are contiguous.  The per-item scalars
+// (lambda_k, gamma_k) are read with scalar loads, which do not wait for the
+// vector-memory counter.  Mode 1 transposes 4x4 blocks of rows inside each
+// lane quad, so that each store instruction writes runs of 4 consecutive
+// rows (64 bytes) instead of one row per lane 16*MR bytes apart.
 //
 // Work item slot 0 pairs the two real shifts k = 0 and k = ell/2 (real
 // matrices, real right-hand sides): system k = 0 runs in the real parts and
@@ -507,6 +510,13 @@ __device__ __forceinline__ void tridiag_uniform_body(
 // LDS: [spb*P*MR cpx stage][spb*P Row3 exchange][2*spb*NFP cpx factors]
 template <int MR>
 constexpr int pipe_nfp() { return (6 * (MR - 1) + 63) / 64 * 64; }
+
+// staging entry of row q of thread lt's chunk (see above)
+template <int MR>
+__device__ __forceinline__ int pipe_entry(int lt, int q) {
+  constexpr int LG = MR == 16 ? 0 : (MR == 8 ? 1 : 2);   // rot(lt) = lt >> LG
+  return lt * MR + ((q + (lt >> LG)) & (MR - 1));
+}
 
 template <int MR, int MODE>
 __device__ __forceinline__ void tridiag_pipe_body(
@@ -571,11 +581,22 @@ __device__ __forceinline__ void tridiag_pipe_body(
     const int sl = slot_in < nslots ? slot_in : nslots - 1;
     if constexpr (MODE != 2) {
       if (sl != 0) {
-        const Cx *src = in + (size_t)sl * n;
-#pragma unroll
-        for (int q = 0; q < MR; ++q) {
-          const int r = s0 + q < n ? s0 + q : n - 1;
-          pd_lds_dma16(src + r, stage + q * P + wib * 64);
+        // the wave's 4*MR windows of 16 staging entries, one DMA instruction
+        // each: lane l fills dword l & 3 of entry e0 + l/4, which holds row
+        // lt*MR + q of the rotated layout (rows >= n read row n-1 and are
+        // zeroed when read)
+        constexpr int LG = MR == 16 ? 0 : (MR == 8 ? 1 : 2);
+        const unsigned *src32 = reinterpret_cast<const unsigned *>(in + (size_t)sl * n);
+        const int lane = lt & 63;
+#pragma unroll 8
+        for (int wdw = 0; wdw < 4 * MR; ++wdw) {
+          const int e0 = wib * 64 * MR + wdw * 16;
+          const int e = e0 + (lane >> 2);
+          const int tl = e / MR, j = e & (MR - 1);
+          const int q = (j - (tl >> LG)) & (MR - 1);
+          int r = tl * MR + q;
+          r = r < n ? r : n - 1;
+          pd_lds_dma4(src32 + (size_t)r * 4 + (lane & 3), stage + e0);
         }
       }
     }
@@ -630,9 +651,10 @@ __device__ __forceinline__ void tridiag_pipe_body(
         right = pd_sel(s0 + MR < n, Cx{ra[rr].re, rb[rr].re}, zero);
       } else {
 #pragma unroll
-        for (int q = 0; q < MR; ++q) d[q] = pd_sel(q < len, stage[q * P + lt], zero);
-        left = pd_sel(lt > 0, stage[(MR - 1) * P + (lt > 0 ? lt - 1 : 0)], zero);
-        right = pd_sel(s0 + MR < n && lt + 1 < P, stage[lt + 1 < P ? lt + 1 : lt], zero);
+        for (int q = 0; q < MR; ++q) d[q] = pd_sel(q < len, stage[pipe_entry<MR>(lt, q)], zero);
+        left = pd_sel(lt > 0, stage[pipe_entry<MR>(lt > 0 ? lt - 1 : 0, MR - 1)], zero);
+        right = pd_sel(s0 + MR < n && lt + 1 < P, stage[pipe_entry<MR>(lt + 1 < P ? lt + 1 : lt, 0)],
+                       zero);
       }
       // right-hand side d = M r (- w M x), formed in place; ghost rows are zero
       Cx rl = left;
@@ -672,10 +694,33 @@ __device__ __forceinline__ void tridiag_pipe_body(
               db[q] = Cx{d[q].im, R(0)};
             }
         } else {
-          Cx *dst = out + (size_t)k * n + s0;
+          // 4x4 transpose inside each lane quad (for every group of 4 rows
+          // a): lane c ends with row (quad base + b)*MR + 4a + c in d[4a + b]
+          const int c = lt & 3;
 #pragma unroll
-          for (int q = 0; q < MR; ++q)
-            if (q < len) dst[q] = d[q];
+          for (int a = 0; a < MR / 4; ++a) {
+            Cx *w = &d[4 * a];
+#pragma unroll
+            for (int kx = 2; kx >= 1; kx >>= 1) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                if ((r & kx) == 0) {
+                  const bool hi = (c & kx) != 0;
+                  const Cx send = pd_sel(hi, w[r], w[r ^ kx]);
+                  const Cx got = {__shfl_xor(send.re, kx, 64), __shfl_xor(send.im, kx, 64)};
+                  w[r] = pd_sel(hi, got, w[r]);
+                  w[r ^ kx] = pd_sel(hi, w[r ^ kx], got);
+                }
+              }
+            }
+          }
+          Cx *dst = out + (size_t)k * n;
+          const int qb = lt & ~3;
+#pragma unroll
+          for (int q = 0; q < MR; ++q) {
+            const int row = (qb + (q & 3)) * MR + (q & ~3) + c;
+            if (row < n) dst[row] = d[q];
+          }
         }
       }
     } else {
