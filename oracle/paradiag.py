@@ -21,7 +21,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .allatonce import rhs
+from .allatonce import apply_allatonce, rhs
 
 
 # --------------------------------------------------------------------------
@@ -128,12 +128,17 @@ def gmres(matvec, b, tol=1e-12, maxit=200):
 # --------------------------------------------------------------------------
 
 def paradiag(Msp, Ksp, tau, u0, F, alpha=1.0, capacitance="dense",
-             tol=1e-13, maxit=200):
+             tol=1e-13, maxit=200, early_exit_eps=None):
     """ParaDiag with backward Euler.  Returns a dict with the intermediates
     of the method (pi, gamma, Ghat, L, U1, b, x, W) and the solution U.
 
     capacitance = "dense" forms J_ell explicitly and solves it with LU;
-    "gmres" applies J_ell matrix-free and solves with ``gmres``."""
+    "gmres" applies J_ell matrix-free and solves with ``gmres``.
+
+    early_exit_eps: Algorithm 3's test on the first term -- if the residual
+    of U_1 in the original all-at-once system (with Sigma_1, not C_alpha) is
+    at most eps * ||U_1||_F, U = U_1 and the capacitance solve and the
+    second parfor are skipped (early_exit = True in the result)."""
     ell, nbar = F.shape
     pi, gamma = circulant_eigs(ell, alpha)
     weight = alpha ** (1.0 / ell)
@@ -148,6 +153,12 @@ def paradiag(Msp, Ksp, tau, u0, F, alpha=1.0, capacitance="dense",
         L[i] = cap.solve_shifted(i, Ghat[i])
     # U_1 = L F^{-T} D_alpha^{-1}
     U1 = np.fft.ifft(L, axis=0) / Dalpha[:, None]
+    if early_exit_eps is not None:
+        R = rhs(Msp, tau, u0, F) - apply_allatonce(Msp, Ksp, tau, U1.real)
+        if np.linalg.norm(R) <= early_exit_eps * np.linalg.norm(U1.real):
+            return dict(pi=pi, gamma=gamma, G=G, Ghat=Ghat, L=L, U1=U1, b=None,
+                        x=None, W=None, U=U1.real.copy(), gmres_iters=0,
+                        early_exit=True)
     # b = L F^{-T} e_ell = sum_i gamma_i L e_i
     b = (gamma[:, None] * L).sum(axis=0)
     if capacitance == "dense":
@@ -163,7 +174,7 @@ def paradiag(Msp, Ksp, tau, u0, F, alpha=1.0, capacitance="dense",
     # U = U_1 - alpha^(1/ell) W F^{-T} D_alpha^{-1}
     U = U1 - weight * np.fft.ifft(W, axis=0) / Dalpha[:, None]
     return dict(pi=pi, gamma=gamma, G=G, Ghat=Ghat, L=L, U1=U1, b=b, x=x,
-                W=W, U=U, gmres_iters=its)
+                W=W, U=U, gmres_iters=its, early_exit=False)
 
 
 def smw_dense(Msp, Ksp, tau, u0, F, alpha=1.0) -> np.ndarray:

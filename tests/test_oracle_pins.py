@@ -197,6 +197,57 @@ def test_smw_dense_matches_dense_lu(kind, alpha):
     assert allatonce.rel_err(U4.real, U2) < 1e-11
 
 
+@pytest.mark.parametrize("kind", ["fd1", "fem1"])
+@pytest.mark.parametrize("alpha", [1e-2, 1e-6])
+def test_alpha_first_term_solves_alpha_circulant_system(kind, alpha):
+    """Algorithm 3: U_1 = L F^{-T} D_alpha^{-1} is the exact solution of the
+    all-at-once system with Sigma_1 replaced by C_alpha (dense LU of
+    I (x) (M + tau K) - C_alpha (x) M), and its residual in the original
+    system is -alpha M u_ell in the first time row and zero elsewhere
+    (C_alpha - Sigma_1 = alpha e_1 e_ell^T)."""
+    M, K, Msp, Ksp, tau, u0, F = _random_problem(kind, 7, 8, 21)
+    ell, nbar = F.shape
+    out = paradiag.paradiag(Msp, Ksp, tau, u0, F, alpha=alpha)
+    U1 = out["U1"]
+    Md = Msp.toarray()
+    A = np.kron(np.eye(ell), Md + tau * Ksp.toarray()) - np.kron(
+        paradiag.circulant_c1(ell, alpha), Md)
+    G = allatonce.rhs(Msp, tau, u0, F)
+    U1_lu = np.linalg.solve(A, G.reshape(-1)).reshape(ell, nbar)
+    assert np.max(np.abs(U1.imag)) < 1e-9 * np.max(np.abs(U1_lu))
+    # the scaled DFT has condition number alpha^{-(ell-1)/ell}
+    kappa = alpha ** (-(ell - 1) / ell)
+    assert allatonce.rel_err(U1.real, U1_lu) < 1e-13 * kappa
+    R, _ = allatonce.residual(Msp, Ksp, tau, u0, F, U1_lu)
+    expect = np.zeros_like(R)
+    expect[0] = -alpha * (Msp @ U1_lu[-1])
+    assert np.allclose(R, expect, rtol=0, atol=1e-12 * np.linalg.norm(G))
+
+
+@pytest.mark.parametrize("kind", ["fd1", "fem1"])
+def test_alpha_early_exit_decision(kind):
+    """Algorithm 3's test: with eps just above the first term's residual
+    ratio the method returns U_1 (no capacitance solve); just below it, the
+    full correction runs and U is the exact all-at-once solution."""
+    M, K, Msp, Ksp, tau, u0, F = _random_problem(kind, 7, 8, 22)
+    alpha = 1e-6
+    ref = paradiag.paradiag(Msp, Ksp, tau, u0, F, alpha=alpha)
+    U1 = ref["U1"].real
+    _, rel = allatonce.residual(Msp, Ksp, tau, u0, F, U1)
+    G = allatonce.rhs(Msp, tau, u0, F)
+    ratio = rel * np.linalg.norm(G) / np.linalg.norm(U1)
+    # closed form of the ratio: alpha ||M u_ell|| / ||U_1||
+    assert np.isclose(ratio, alpha * np.linalg.norm(Msp @ U1[-1]) / np.linalg.norm(U1),
+                      rtol=1e-6)
+    hi = paradiag.paradiag(Msp, Ksp, tau, u0, F, alpha=alpha, early_exit_eps=1.01 * ratio)
+    assert hi["early_exit"] and hi["gmres_iters"] == 0
+    assert np.array_equal(hi["U"], U1)
+    lo = paradiag.paradiag(Msp, Ksp, tau, u0, F, alpha=alpha, early_exit_eps=0.99 * ratio)
+    assert not lo["early_exit"]
+    U2 = allatonce.solve_dense(Msp, Ksp, tau, u0, F)
+    assert allatonce.rel_err(lo["U"].real, U2) < 1e-8
+
+
 def test_paradiag_2d_matches_stepping():
     p = wl.heat_2d(7, 8, 0.1, 1.0, np.random.default_rng(9))
     Msp, Ksp = problem_matrices(p)
