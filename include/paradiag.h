@@ -90,6 +90,10 @@ typedef struct {
                        /* and shifted-solve rows per thread at plan creation */
                        /* and keep the fastest (cached per n, ell,          */
                        /* precision); 0 = built-in choice                   */
+  int early_exit;      /* Algorithm 3's test: first form U_1 (the alpha-    */
+                       /* circulant solve, x = 0) and return it when        */
+                       /* ||G - A(U_1)||_F <= tol * ||U_1||_F, skipping the */
+                       /* capacitance solve; 0 = always correct             */
 } pd_options;
 
 typedef struct {
@@ -98,10 +102,11 @@ typedef struct {
   int pint_loops;             /* batches of ell shifted solves (#PinT)     */
   double rel_residual;        /* ||G - A(U)||_F / ||G||_F, or -1           */
   double gmres_rel_residual;  /* last capacitance residual / ||b||         */
+  int early_exit;             /* 1: U = U_1 was returned (early_exit test)  */
 } pd_info;
 
 /* Fill *opt with defaults: dims 1, PD_FP64, alpha 1, maxit 64,
- * max_sweeps 16, check_residual 0, stream NULL, autotune 0. */
+ * max_sweeps 16, check_residual 0, stream NULL, autotune 0, early_exit 0. */
 void paradiag_default_options(pd_options *opt);
 
 /* Create a plan for an n x ell problem with time step tau (Section 1).

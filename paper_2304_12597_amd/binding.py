@@ -36,13 +36,14 @@ class pd_options(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int), ("precision", ctypes.c_int),
                 ("alpha", ctypes.c_double), ("maxit", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int), ("check_residual", ctypes.c_int),
-                ("stream", _vp), ("autotune", ctypes.c_int)]
+                ("stream", _vp), ("autotune", ctypes.c_int),
+                ("early_exit", ctypes.c_int)]
 
 
 class pd_info(ctypes.Structure):
     _fields_ = [("gmres_iters", ctypes.c_int), ("sweeps", ctypes.c_int),
                 ("pint_loops", ctypes.c_int), ("rel_residual", ctypes.c_double),
-                ("gmres_rel_residual", ctypes.c_double)]
+                ("gmres_rel_residual", ctypes.c_double), ("early_exit", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -130,7 +131,7 @@ def paradiag_last_error() -> str:
 def paradiag_plan_create(n, ell, tau, M, K, options=None, **kw):
     """M, K: (lower, diag, upper) arrays or None for M = I.  Keyword
     arguments override fields of pd_options (dims, precision, alpha, maxit,
-    max_sweeps, check_residual, stream, autotune)."""
+    max_sweeps, check_residual, stream, autotune, early_exit)."""
     opt = options if options is not None else paradiag_default_options()
     for k, v in kw.items():
         if k == "stream" and v is not None and not isinstance(v, int):

@@ -190,6 +190,7 @@ struct pd_plan_s {
   int gm_pred = 2;             // GMRES iterations enqueued ahead (the last solve's count)
   int gm_seen = 0;             // a solve has run (gm_pred is learned)
   int autotune = 0;            // buffers sized for every tuning candidate
+  int early_exit = 0;          // Algorithm 3's test on U_1 before the correction
   int tri_G = 0;
   double *bvec = nullptr, *xvec = nullptr, *wvec = nullptr;
   double *V = nullptr;         // [(maxit+1)][nbar] Krylov basis
@@ -257,6 +258,9 @@ pd_status pd_residual_impl(pd_plan p, const double *u0, const double *F,
                            const double *U, double *rel);
 pd_status pd_sum_norms(pd_plan p, int nblk, double *rn2, double *gn2);
 int pd_residual_blocks(pd_plan p);
+// ||G - A(U)||_F^2, ||G||_F^2 and ||U||_F^2 in float64 (synchronises)
+pd_status pd_residual_norms(pd_plan p, const double *u0, const double *F, const double *U,
+                            double *rn2, double *gn2, double *un2);
 int pd_fft_blocks(pd_plan p);
 int pd_vec_blocks(int n);
 size_t pd_gmres_state_doubles(int maxit);

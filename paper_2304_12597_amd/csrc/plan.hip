@@ -147,7 +147,7 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
   size_t fb = 2 * (size_t)pd_fft_blocks(p);
   if (p->autotune) fb = 2 * (size_t)((p->nbar + 1) / 2);   // any tile width down to C = 1
   if (fb > red_n) red_n = fb;
-  size_t rb = 2 * (size_t)pd_residual_blocks(p);
+  size_t rb = 3 * (size_t)pd_residual_blocks(p);
   if (rb > red_n) red_n = rb;
   if (p->dims == 2) {
     size_t db = 2 * (size_t)pd_dst_blocks(p);
@@ -314,6 +314,7 @@ extern "C" void paradiag_default_options(pd_options *opt) {
   opt->check_residual = 0;
   opt->stream = nullptr;
   opt->autotune = 0;
+  opt->early_exit = 0;
 }
 
 extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double tau,
@@ -417,6 +418,7 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   p->max_sweeps = opt.max_sweeps;
   p->check_residual = opt.check_residual;
   p->autotune = (opt.autotune != 0 && opt.dims == 1) ? 1 : 0;
+  p->early_exit = opt.early_exit != 0 ? 1 : 0;
   p->stream = reinterpret_cast<hipStream_t>(opt.stream);
   p->mass_identity = (M == nullptr);
   if (hipGetDevice(&p->device) != hipSuccess) {

@@ -157,10 +157,36 @@ extern "C" pd_status paradiag_solve(pd_plan p, const double *u0, const double *F
     info->pint_loops = 0;
     info->rel_residual = -1.0;
     info->gmres_rel_residual = -1.0;
+    info->early_exit = 0;
   }
   pd_status gst = PD_OK;
   pd_status st = pd_forward(p, u0, F, nullptr, p->spec, 0);
   if (st != PD_OK) return st;
+  if (p->early_exit) {
+    // Algorithm 3: U_1 = P^{-1} Ghat F^{-T} D_alpha^{-1} (pass C with x = 0,
+    // pass D), accepted when its residual in the original all-at-once system
+    // is at most tol * ||U_1||_F
+    PD_HIP_CHECK(hipMemsetAsync(p->xvec, 0, sizeof(double) * (size_t)p->nbar, p->stream));
+    st = pd_launch_tridiag(p, 1, p->spec, p->xvec, p->spec);
+    if (st != PD_OK) return st;
+    st = pd_inverse(p, p->spec, U, 0);
+    if (st != PD_OK) return st;
+    double rn2, gn2, un2;
+    st = pd_residual_norms(p, u0, F, U, &rn2, &gn2, &un2);
+    if (st != PD_OK) return st;
+    if (std::sqrt(rn2) <= tol * std::sqrt(un2)) {
+      if (info) {
+        info->early_exit = 1;
+        info->pint_loops = 1;
+        info->rel_residual = gn2 > 0.0 ? std::sqrt(rn2 / gn2) : std::sqrt(rn2);
+      }
+      return PD_OK;
+    }
+    // rejected: the spectrum (overwritten by pass C) is formed again and the
+    // full method runs
+    st = pd_forward(p, u0, F, nullptr, p->spec, 0);
+    if (st != PD_OK) return st;
+  }
   if (p->prec != PD_MIXED && pd_gmres_fused_ok(p)) return solve_speculative(p, u0, F, U, tol, info);
   st = sweep_tail(p, U, tol, 0, 0, info, &gst);
   if (st != PD_OK) return st;

@@ -225,6 +225,54 @@ def test_end_to_end_alpha(lib, alpha):
     assert allatonce.rel_err(U, U2) < 1e-9
 
 
+def _first_term_ratio(p, alpha):
+    """Oracle: U_1 of Algorithm 3 and ||G - A(U_1)||_F / ||U_1||_F."""
+    Msp, Ksp = problem_matrices(p)
+    out = paradiag.paradiag(Msp, Ksp, p.tau, p.u0, p.F, alpha=alpha)
+    U1 = out["U1"].real
+    R, _ = allatonce.residual(Msp, Ksp, p.tau, p.u0, p.F, U1)
+    return U1, float(np.linalg.norm(R) / np.linalg.norm(U1))
+
+
+# alpha large enough that the exact first-term residual (alpha M u_ell)
+# dominates the rounding residual ||A|| kappa u of the computed U_1
+@pytest.mark.parametrize("kind,n,ell,alpha", [("fd1", 63, 32, 1e-2), ("fem1", 255, 64, 1e-2),
+                                               ("fd1", 1000, 256, 0.1)])
+def test_alpha_early_exit(lib, kind, n, ell, alpha):
+    """Algorithm 3's test on the first term: with tol just above the oracle's
+    residual ratio of U_1 the solve returns U_1 (one parfor, no capacitance
+    solve); just below it, the full method runs and U solves the original
+    system."""
+    p = make_problem(kind, n, ell, 7 + n, nu=0.1)
+    U1, ratio = _first_term_ratio(p, alpha)
+    kappa = alpha ** (-(ell - 1) / ell)   # condition of the scaled DFT
+    U, info = _solve(lib, p, tol=1.05 * ratio, alpha=alpha, early_exit=1)
+    assert info.early_exit == 1 and info.gmres_iters == 0 and info.pint_loops == 1
+    # the float64 bar, widened by the condition of the scaled DFT
+    assert allatonce.rel_err(U, U1) < 1e-10 * max(1.0, kappa / 100), allatonce.rel_err(U, U1)
+    tol = 0.95 * ratio
+    U, info = _solve(lib, p, tol=tol, alpha=alpha, early_exit=1)
+    assert info.early_exit == 0 and info.gmres_iters >= 1
+    # the full method to the requested tolerance (GMRES stops at tol/100 ||b||)
+    Uref = modal.modal_solution(p)
+    assert allatonce.rel_err(U, Uref) < tol, allatonce.rel_err(U, Uref)
+    assert info.rel_residual < tol
+
+
+def test_alpha_early_exit_2d(lib):
+    p = wl.heat_2d(31, 16, 0.1, 1.0, np.random.default_rng(3))
+    alpha = 1e-2
+    U1, ratio = _first_term_ratio(p, alpha)
+    U, info = _solve(lib, p, tol=1.05 * ratio, alpha=alpha, early_exit=1, dims=2)
+    assert info.early_exit == 1 and info.gmres_iters == 0
+    assert allatonce.rel_err(U, U1) < 1e-10
+    tol = 0.95 * ratio
+    U, info = _solve(lib, p, tol=tol, alpha=alpha, early_exit=1, dims=2)
+    assert info.early_exit == 0
+    assert allatonce.rel_err(U, allatonce.step(p)) < tol
+    assert info.rel_residual < tol
+
+
 def test_end_to_end_nonuniform_matrices(lib):
     """General (non-constant-diagonal) SPD M and K use the per-row kernel."""
     n, ell = 77, 16
