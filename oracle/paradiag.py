@@ -137,8 +137,11 @@ def paradiag(Msp, Ksp, tau, u0, F, alpha=1.0, capacitance="dense",
 
     early_exit_eps: Algorithm 3's test on the first term -- if the residual
     of U_1 in the original all-at-once system (with Sigma_1, not C_alpha) is
-    at most eps * ||U_1||_F, U = U_1 and the capacitance solve and the
-    second parfor are skipped (early_exit = True in the result)."""
+    at most eps * ||M U_1||_F, U = U_1 and the capacitance solve and the
+    second parfor are skipped (early_exit = True in the result).  The paper
+    states the test for M = I against ||U_1||_F; with a mass matrix every
+    row of the residual carries a factor M, so it is measured against
+    ||M U_1||_F (the same test when M = I)."""
     ell, nbar = F.shape
     pi, gamma = circulant_eigs(ell, alpha)
     weight = alpha ** (1.0 / ell)
@@ -155,7 +158,8 @@ def paradiag(Msp, Ksp, tau, u0, F, alpha=1.0, capacitance="dense",
     U1 = np.fft.ifft(L, axis=0) / Dalpha[:, None]
     if early_exit_eps is not None:
         R = rhs(Msp, tau, u0, F) - apply_allatonce(Msp, Ksp, tau, U1.real)
-        if np.linalg.norm(R) <= early_exit_eps * np.linalg.norm(U1.real):
+        MU1 = np.asarray((Msp @ U1.real.T).T)
+        if np.linalg.norm(R) <= early_exit_eps * np.linalg.norm(MU1):
             return dict(pi=pi, gamma=gamma, G=G, Ghat=Ghat, L=L, U1=U1, b=None,
                         x=None, W=None, U=U1.real.copy(), gmres_iters=0,
                         early_exit=True)

@@ -227,17 +227,19 @@ def test_alpha_first_term_solves_alpha_circulant_system(kind, alpha):
 @pytest.mark.parametrize("kind", ["fd1", "fem1"])
 def test_alpha_early_exit_decision(kind):
     """Algorithm 3's test: with eps just above the first term's residual
-    ratio the method returns U_1 (no capacitance solve); just below it, the
-    full correction runs and U is the exact all-at-once solution."""
+    ratio ||G - A(U_1)||_F / ||M U_1||_F the method returns U_1 (no
+    capacitance solve); just below it, the full correction runs and U is the
+    exact all-at-once solution."""
     M, K, Msp, Ksp, tau, u0, F = _random_problem(kind, 7, 8, 22)
     alpha = 1e-6
     ref = paradiag.paradiag(Msp, Ksp, tau, u0, F, alpha=alpha)
     U1 = ref["U1"].real
     _, rel = allatonce.residual(Msp, Ksp, tau, u0, F, U1)
     G = allatonce.rhs(Msp, tau, u0, F)
-    ratio = rel * np.linalg.norm(G) / np.linalg.norm(U1)
-    # closed form of the ratio: alpha ||M u_ell|| / ||U_1||
-    assert np.isclose(ratio, alpha * np.linalg.norm(Msp @ U1[-1]) / np.linalg.norm(U1),
+    MU1 = np.asarray((Msp @ U1.T).T)
+    ratio = rel * np.linalg.norm(G) / np.linalg.norm(MU1)
+    # closed form of the ratio: alpha ||M u_ell|| / ||M U_1||
+    assert np.isclose(ratio, alpha * np.linalg.norm(Msp @ U1[-1]) / np.linalg.norm(MU1),
                       rtol=1e-6)
     hi = paradiag.paradiag(Msp, Ksp, tau, u0, F, alpha=alpha, early_exit_eps=1.01 * ratio)
     assert hi["early_exit"] and hi["gmres_iters"] == 0
