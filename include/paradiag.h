@@ -92,8 +92,9 @@ typedef struct {
                        /* precision); 0 = built-in choice                   */
   int early_exit;      /* Algorithm 3's test: first form U_1 (the alpha-    */
                        /* circulant solve, x = 0) and return it when        */
-                       /* ||G - A(U_1)||_F <= tol * ||U_1||_F, skipping the */
-                       /* capacitance solve; 0 = always correct             */
+                       /* ||G - A(U_1)||_F <= tol * ||M U_1||_F (M = I: the */
+                       /* paper's ||U_1||_F), skipping the capacitance      */
+                       /* solve; 0 = always correct                         */
 } pd_options;
 
 typedef struct {

@@ -258,7 +258,7 @@ pd_status pd_residual_impl(pd_plan p, const double *u0, const double *F,
                            const double *U, double *rel);
 pd_status pd_sum_norms(pd_plan p, int nblk, double *rn2, double *gn2);
 int pd_residual_blocks(pd_plan p);
-// ||G - A(U)||_F^2, ||G||_F^2 and ||U||_F^2 in float64 (synchronises)
+// ||G - A(U)||_F^2, ||G||_F^2 and ||M U||_F^2 in float64 (synchronises)
 pd_status pd_residual_norms(pd_plan p, const double *u0, const double *F, const double *U,
                             double *rn2, double *gn2, double *un2);
 int pd_fft_blocks(pd_plan p);

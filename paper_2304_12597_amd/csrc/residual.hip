@@ -25,7 +25,14 @@ residual_kernel(int n, int nbar, int ell, int dims, double tau, const double *__
   while (t < ell) {
     double r, g;
     residual_point(t, i, n, nbar, dims, tau, u0, F, U, coef, r, g);
-    const double u = U[(size_t)t * nbar + i];
+    // (M U)_{t,i}: Algorithm 3's test measures the residual against ||M U||_F
+    const double *Ut = U + (size_t)t * nbar;
+    double u = Ut[i];
+    if (dims == 1) {
+      u = coef[n + i] * Ut[i];
+      if (i > 0) u += coef[i] * Ut[i - 1];
+      if (i < n - 1) u += coef[2 * n + i] * Ut[i + 1];
+    }
     rn += r * r;
     gn += g * g;
     un += u * u;

@@ -165,7 +165,8 @@ extern "C" pd_status paradiag_solve(pd_plan p, const double *u0, const double *F
   if (p->early_exit) {
     // Algorithm 3: U_1 = P^{-1} Ghat F^{-T} D_alpha^{-1} (pass C with x = 0,
     // pass D), accepted when its residual in the original all-at-once system
-    // is at most tol * ||U_1||_F
+    // is at most tol * ||M U_1||_F (the paper's ||U_1||_F when M = I; with a
+    // mass matrix every residual row carries M)
     PD_HIP_CHECK(hipMemsetAsync(p->xvec, 0, sizeof(double) * (size_t)p->nbar, p->stream));
     st = pd_launch_tridiag(p, 1, p->spec, p->xvec, p->spec);
     if (st != PD_OK) return st;

@@ -226,12 +226,13 @@ def test_end_to_end_alpha(lib, alpha):
 
 
 def _first_term_ratio(p, alpha):
-    """Oracle: U_1 of Algorithm 3 and ||G - A(U_1)||_F / ||U_1||_F."""
+    """Oracle: U_1 of Algorithm 3 and ||G - A(U_1)||_F / ||M U_1||_F."""
     Msp, Ksp = problem_matrices(p)
     out = paradiag.paradiag(Msp, Ksp, p.tau, p.u0, p.F, alpha=alpha)
     U1 = out["U1"].real
     R, _ = allatonce.residual(Msp, Ksp, p.tau, p.u0, p.F, U1)
-    return U1, float(np.linalg.norm(R) / np.linalg.norm(U1))
+    MU1 = np.asarray((Msp @ U1.T).T)
+    return U1, float(np.linalg.norm(R) / np.linalg.norm(MU1))
 
 
 # alpha large enough that the exact first-term residual (alpha M u_ell)
