@@ -11,8 +11,12 @@ import numpy as np
 
 
 def sine_matrix(n: int) -> np.ndarray:
-    k = np.arange(1, n + 1)
-    return np.sqrt(2.0 / (n + 1)) * np.sin(np.outer(k, k) * np.pi / (n + 1))
+    """The integer product (k+1)(i+1) is reduced modulo 2(n+1) before it is
+    scaled by pi/(n+1), so every phase is exact to rounding: unreduced, the
+    phases reach ~n^2 pi/(n+1) radians and lose ~1e-12 for n ~ 4096."""
+    k = np.arange(1, n + 1, dtype=np.int64)
+    r = np.outer(k, k) % (2 * (n + 1))
+    return np.sqrt(2.0 / (n + 1)) * np.sin(r * np.pi / (n + 1))
 
 
 def dst1(x: np.ndarray, axis: int = -1) -> np.ndarray:

@@ -427,6 +427,14 @@ def test_pins_catch_planted_mistakes(monkeypatch):
 
 # ------------------------------------------------------------------ DST-I --
 
+def test_sine_matrix_orthogonal_large():
+    """S S = I to float64 rounding at a size where unreduced phases fail."""
+    n = 2047
+    S = dst.sine_matrix(n)
+    assert np.max(np.abs(S @ S - np.eye(n))) < 1e-14
+    assert np.array_equal(S, S.T)
+
+
 def test_sine_matrix_diagonalises_toeplitz():
     n = 13
     S = dst.sine_matrix(n)
