@@ -62,6 +62,15 @@ typedef enum {
 } pd_status;
 
 typedef enum {
+  PD_SHIFTED_PARTITION = 0,  /* tridiagonal partition solves + parallel cyclic   */
+                             /* reduction, capacitance system by GMRES (any M, K) */
+  PD_SHIFTED_SINE = 1        /* 1D, float64, symmetric Toeplitz M and K (uniform */
+                             /* grid, zero Dirichlet ends), n + 1 a power of two */
+                             /* >= 16: every shifted matrix and J_ell diagonal  */
+                             /* in the DST-I basis; capacitance solved exactly   */
+} pd_shifted_solver;
+
+typedef enum {
   PD_FP64 = 0,        /* everything in float64 / complex128                  */
   PD_MIXED = 1,       /* complex64 transforms and shifted solves, float64    */
                       /* capacitance Arnoldi, residual and refinement        */
@@ -95,6 +104,7 @@ typedef struct {
                        /* ||G - A(U_1)||_F <= tol * ||M U_1||_F (M = I: the */
                        /* paper's ||U_1||_F), skipping the capacitance      */
                        /* solve; 0 = always correct                         */
+  int shifted_solver;  /* pd_shifted_solver                                 */
 } pd_options;
 
 typedef struct {
@@ -107,7 +117,8 @@ typedef struct {
 } pd_info;
 
 /* Fill *opt with defaults: dims 1, PD_FP64, alpha 1, maxit 64,
- * max_sweeps 16, check_residual 0, stream NULL, autotune 0, early_exit 0. */
+ * max_sweeps 16, check_residual 0, stream NULL, autotune 0, early_exit 0,
+ * shifted_solver PD_SHIFTED_PARTITION. */
 void paradiag_default_options(pd_options *opt);
 
 /* Create a plan for an n x ell problem with time step tau (Section 1).
@@ -173,6 +184,13 @@ pd_status paradiag_forward_transform(pd_plan plan, const double *u0,
  * of Uhat, b must be non-NULL. */
 pd_status paradiag_shifted_solve(pd_plan plan, const void *Hhat,
                                  const double *x, void *Uhat, double *b);
+
+/* PD_SHIFTED_SINE plans: orthonormal DST-I along space of each of the ell
+ * rows of a [ell][n] float64 array, out[t][k-1] = sqrt(2/(n+1)) sum_j
+ * in[t][j-1] sin(pi j k/(n+1)), j, k = 1..n (the basis that diagonalises M
+ * and K; Section 6.1 uses it along x in 2D).  out may equal in.
+ * Errors: PD_EINVAL, PD_ENOTSUP (plan without the sine basis). */
+pd_status paradiag_sine_transform(pd_plan plan, const double *in, double *out);
 
 /* One capacitance product Jv = v + w sum_k gamma_k P_k^{-1} M v
  * (eq. SMW_linearsystemII; eq. innersystem_alpha), v and Jv float64 [nbar]. */

@@ -19,6 +19,7 @@ PD_OK, PD_EINVAL, PD_ENOMEM, PD_EHIP, PD_ENOTCONV, PD_ESINGULAR, \
 STATUS_NAMES = ["PD_OK", "PD_EINVAL", "PD_ENOMEM", "PD_EHIP", "PD_ENOTCONV",
                 "PD_ESINGULAR", "PD_ENONFINITE", "PD_EBUDGET", "PD_ENOTSUP"]
 PD_FP64, PD_MIXED, PD_FP32 = 0, 1, 2
+PD_SHIFTED_PARTITION, PD_SHIFTED_SINE = 0, 1
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libparadiag.so is not built (run __graft_entry__.build())")
@@ -37,7 +38,7 @@ class pd_options(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("maxit", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int), ("check_residual", ctypes.c_int),
                 ("stream", _vp), ("autotune", ctypes.c_int),
-                ("early_exit", ctypes.c_int)]
+                ("early_exit", ctypes.c_int), ("shifted_solver", ctypes.c_int)]
 
 
 class pd_info(ctypes.Structure):
@@ -73,6 +74,7 @@ _plan_config = _sig("paradiag_plan_config", ctypes.c_int,
 _last_error = _sig("paradiag_last_error", ctypes.c_char_p, [])
 _spectrum_bytes = _sig("paradiag_spectrum_bytes", ctypes.c_size_t, [_vp])
 _forward = _sig("paradiag_forward_transform", ctypes.c_int, [_vp, _vp, _vp, _vp])
+_sine = _sig("paradiag_sine_transform", ctypes.c_int, [_vp, _vp, _vp])
 _shifted = _sig("paradiag_shifted_solve", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp])
 _cap_apply = _sig("paradiag_capacitance_apply", ctypes.c_int, [_vp, _vp, _vp])
 _cap_solve = _sig("paradiag_capacitance_solve", ctypes.c_int,
@@ -131,7 +133,7 @@ def paradiag_last_error() -> str:
 def paradiag_plan_create(n, ell, tau, M, K, options=None, **kw):
     """M, K: (lower, diag, upper) arrays or None for M = I.  Keyword
     arguments override fields of pd_options (dims, precision, alpha, maxit,
-    max_sweeps, check_residual, stream, autotune, early_exit)."""
+    max_sweeps, check_residual, stream, autotune, early_exit, shifted_solver)."""
     opt = options if options is not None else paradiag_default_options()
     for k, v in kw.items():
         if k == "stream" and v is not None and not isinstance(v, int):
@@ -176,6 +178,10 @@ def paradiag_solve_batch(plans, u0s, Fs, Us, tol, allow_notconv=False):
 
 def paradiag_spectrum_bytes(plan) -> int:
     return int(_spectrum_bytes(plan))
+
+
+def paradiag_sine_transform(plan, inp, out):
+    return _check(_sine(plan, _ptr(inp), _ptr(out)), "paradiag_sine_transform")
 
 
 def paradiag_forward_transform(plan, u0, F, Hhat):

@@ -191,6 +191,14 @@ struct pd_plan_s {
   int gm_seen = 0;             // a solve has run (gm_pred is learned)
   int autotune = 0;            // buffers sized for every tuning candidate
   int early_exit = 0;          // Algorithm 3's test on U_1 before the correction
+  // sine-basis shifted solves (symmetric Toeplitz M, K; n + 1 a power of two)
+  int sine = 0;
+  int sine_C = 1;              // rows per block of the DST-I kernel
+  double *sine_q = nullptr;    // [n+1] sin(pi j / (n+1))
+  double *sine_wN = nullptr;   // [(n+1)/2 + 1] exp(-2 pi i m / (n+1))
+  double *sine_twH = nullptr;  // [(n+1)/2] exp(-2 pi i m / ((n+1)/2))
+  double *sine_m = nullptr;    // [n] eigenvalues of M on the sine modes
+  double *sine_k = nullptr;    // [n] eigenvalues of tau K on the sine modes
   int tri_G = 0;
   double *bvec = nullptr, *xvec = nullptr, *wvec = nullptr;
   double *V = nullptr;         // [(maxit+1)][nbar] Krylov basis
@@ -257,6 +265,14 @@ pd_status pd_gmres(pd_plan p, const double *b, double *x, double rtol,
 pd_status pd_residual_impl(pd_plan p, const double *u0, const double *F,
                            const double *U, double *rel);
 pd_status pd_sum_norms(pd_plan p, int nblk, double *rn2, double *gn2);
+// sine-basis path (sine.hip)
+int pd_sine_dst_C(int n, int ell);
+size_t pd_sine_dst_lds(int n, int C);
+size_t pd_sine_modal_lds(pd_plan p, int threads);
+pd_status pd_launch_sine_dst(pd_plan p, int mode, const double *u0, const double *F,
+                             const double *in, double *out);
+pd_status pd_launch_sine_modal(pd_plan p, const double *A, double *B);
+void pd_sine_set_attributes(size_t max_lds);
 int pd_residual_blocks(pd_plan p);
 // ||G - A(U)||_F^2, ||G||_F^2 and ||M U||_F^2 in float64 (synchronises)
 pd_status pd_residual_norms(pd_plan p, const double *u0, const double *F, const double *U,

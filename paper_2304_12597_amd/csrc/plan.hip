@@ -68,7 +68,7 @@ void free_plan(pd_plan p) {
   if (!p) return;
   void *ptrs[] = {p->coef64, p->coef32, p->lam64, p->lam32, p->gB64, p->gJ64, p->tw64,
                   p->tw32, p->dal, p->fac64, p->fac32, p->twd, p->wreal, p->spec, p->partials, p->rstage, p->bvec, p->xvec, p->wvec, p->V,
-                  p->gm, p->red};
+                  p->gm, p->red, p->sine_q, p->sine_wN, p->sine_twH, p->sine_m, p->sine_k};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   if (p->host_pin) (void)hipHostFree(p->host_pin);
@@ -82,12 +82,12 @@ std::mutex g_attr_mu;
 // Launch configurations and device allocation sizes (in elements of their
 // type) of a plan; shared by plan creation and paradiag_plan_bytes.
 struct Layout {
-  size_t coef = 0, lam = 0, tw = 0, dal = 0, fac = 0, twd = 0, wreal = 0;
+  size_t coef = 0, lam = 0, tw = 0, dal = 0, fac = 0, twd = 0, wreal = 0, sine = 0;
   size_t spec_bytes = 0, partials = 0, rstage = 0, vec = 0, V = 0, gm = 0, red = 0;
   size_t total_bytes() const {
     return coef * 12 + lam * 12 + 2 * lam * 8 + tw * 12 + dal * 8 + fac * 12 + twd * 8 +
            wreal * 8 + spec_bytes + partials * 8 + rstage * 8 + 3 * vec * 8 + V * 8 + gm * 8 +
-           red * 8;
+           red * 8 + sine * 8;
   }
 };
 
@@ -134,6 +134,21 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
     L.fac = (size_t)(F2 + 1) * 6 * ((p->autotune ? 16 : p->tri.MR) - 1) * 2;
   }
   if (p->autotune) L.partials = std::max(L.partials, (size_t)cus * n);
+  if (p->sine) {
+    const int N = n + 1, H = N / 2;
+    p->sine_C = pd_sine_dst_C(n, ell);
+    if (pd_sine_dst_lds(n, p->sine_C) > max_lds) {
+      pd_set_error("sine transform tile does not fit in LDS");
+      return PD_ENOTSUP;
+    }
+    int need = p->fft_C * ell / 8;
+    need = need < 64 ? 64 : need;
+    if (pd_sine_modal_lds(p, ((need + 63) / 64) * 64) > max_lds) {
+      pd_set_error("sine-basis time tile does not fit in LDS");
+      return PD_ENOTSUP;
+    }
+    L.sine = (size_t)N + 2 * (size_t)(H + 1) + 2 * (size_t)H + 2 * (size_t)n;
+  }
   L.coef = 6 * (size_t)n;
   L.lam = 2 * (size_t)F2;
   L.tw = 2 * (size_t)ell;
@@ -315,6 +330,7 @@ extern "C" void paradiag_default_options(pd_options *opt) {
   opt->stream = nullptr;
   opt->autotune = 0;
   opt->early_exit = 0;
+  opt->shifted_solver = PD_SHIFTED_PARTITION;
 }
 
 extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double tau,
@@ -389,6 +405,28 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
       }
     }
   }
+  if (opt.shifted_solver != PD_SHIFTED_PARTITION && opt.shifted_solver != PD_SHIFTED_SINE) {
+    pd_set_error("unknown shifted_solver");
+    return PD_EINVAL;
+  }
+  if (opt.shifted_solver == PD_SHIFTED_SINE) {
+    if (opt.dims != 1 || opt.precision != PD_FP64 || !is_pow2(n + 1) || n + 1 < 16) {
+      pd_set_error("sine-basis solves need a 1D float64 plan with n + 1 a power of two >= 16");
+      return PD_ENOTSUP;
+    }
+    // symmetric Toeplitz M and K (constant diagonals, equal off-diagonals)
+    auto toeplitz = [n](const pd_tridiag *T) {
+      const double d0 = T->diag[0], o0 = T->upper[0];
+      for (int i = 0; i < n; ++i)
+        if (T->diag[i] != d0 || (i < n - 1 && (T->upper[i] != o0 || T->lower[i + 1] != o0)))
+          return false;
+      return true;
+    };
+    if (!toeplitz(K) || (M && !toeplitz(M))) {
+      pd_set_error("sine-basis solves need symmetric Toeplitz M and K");
+      return PD_ENOTSUP;
+    }
+  }
   for (int i = 0; i < n; ++i) {
     double vals[6] = {K->diag[i], i > 0 ? K->lower[i] : 0.0, i < n - 1 ? K->upper[i] : 0.0,
                       M ? M->diag[i] : 1.0, (M && i > 0) ? M->lower[i] : 0.0,
@@ -419,6 +457,7 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   p->check_residual = opt.check_residual;
   p->autotune = (opt.autotune != 0 && opt.dims == 1) ? 1 : 0;
   p->early_exit = opt.early_exit != 0 ? 1 : 0;
+  p->sine = opt.shifted_solver == PD_SHIFTED_SINE ? 1 : 0;
   p->stream = reinterpret_cast<hipStream_t>(opt.stream);
   p->mass_identity = (M == nullptr);
   if (hipGetDevice(&p->device) != hipSuccess) {
@@ -441,6 +480,7 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
     pd_line2d_set_attributes(g_max_lds);
     pd_fft_batch_set_attributes(g_max_lds);
     pd_tri_batch_set_attributes(g_max_lds);
+    pd_sine_set_attributes(g_max_lds);
     g_attr_device = p->device;
   }
   const size_t max_lds = g_max_lds;
@@ -545,6 +585,38 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
     pd_uniform_factors(p, p->tri.MR, fac);
   }
   std::vector<float> fac32(fac.begin(), fac.end());
+  std::vector<double> sq, swN, stwH, sm, sk;
+  if (p->sine) {
+    const int N = n + 1, H = N / 2;
+    sq.resize(N);
+    for (int j = 0; j < N; ++j) {
+      double c, s;
+      cis(j, 2 * (long)N, c, s);
+      sq[j] = s;                              // sin(pi j / N)
+    }
+    swN.resize(2 * (size_t)(H + 1));
+    for (int m = 0; m <= H; ++m) {
+      double c, s;
+      cis(m, N, c, s);
+      swN[2 * m] = c;
+      swN[2 * m + 1] = -s;                    // exp(-2 pi i m / N)
+    }
+    stwH.resize(2 * (size_t)H);
+    for (int m = 0; m < H; ++m) {
+      double c, s;
+      cis(m, H, c, s);
+      stwH[2 * m] = c;
+      stwH[2 * m + 1] = -s;
+    }
+    sm.resize(n);
+    sk.resize(n);
+    for (int k = 0; k < n; ++k) {
+      double c, s;
+      cis(k + 1, 2 * (long)N, c, s);          // cos(pi (k+1) / N)
+      sm[k] = p->uni[1] + 2.0 * p->uni[2] * c;
+      sk[k] = p->uni[4] + 2.0 * p->uni[5] * c;
+    }
+  }
   const size_t nbar = p->nbar;
   p->spec_bytes = L.spec_bytes;
   p->bytes = L.total_bytes();
@@ -579,6 +651,13 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   PD_TRY(dev_alloc(&p->V, (size_t)(p->maxit + 1) * nbar));
   PD_TRY(dev_alloc(&p->gm, pd_gmres_state_doubles(p->maxit)));
   PD_TRY(dev_alloc(&p->red, L.red));
+  if (p->sine) {
+    PD_TRY(dev_alloc(&p->sine_q, sq.size()));
+    PD_TRY(dev_alloc(&p->sine_wN, swN.size()));
+    PD_TRY(dev_alloc(&p->sine_twH, stwH.size()));
+    PD_TRY(dev_alloc(&p->sine_m, sm.size()));
+    PD_TRY(dev_alloc(&p->sine_k, sk.size()));
+  }
   // small status block written by kernels straight into pinned host memory
   if (hipHostMalloc(reinterpret_cast<void **>(&p->host_pin), 8 * sizeof(double),
                     hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
@@ -603,6 +682,13 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   PD_TRY(upload(p->fac64, fac, p->stream));
   PD_TRY(upload(p->fac32, fac32, p->stream));
   PD_TRY(upload(p->twd, twd, p->stream));
+  if (p->sine) {
+    PD_TRY(upload(p->sine_q, sq, p->stream));
+    PD_TRY(upload(p->sine_wN, swN, p->stream));
+    PD_TRY(upload(p->sine_twH, stwH, p->stream));
+    PD_TRY(upload(p->sine_m, sm, p->stream));
+    PD_TRY(upload(p->sine_k, sk, p->stream));
+  }
 #undef PD_TRY
   if (hipStreamSynchronize(p->stream) != hipSuccess) {
     pd_set_error("stream synchronisation failed during plan creation");
@@ -660,6 +746,7 @@ extern "C" size_t paradiag_plan_bytes(int n, int ell, const pd_options *opt_in) 
   tmp.maxit = opt.maxit;
   tmp.uniform = true;
   tmp.autotune = (opt.autotune != 0 && opt.dims == 1) ? 1 : 0;
+  tmp.sine = opt.shifted_solver == PD_SHIFTED_SINE ? 1 : 0;
   int dev = 0, cus = 256, lds = 65536;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);

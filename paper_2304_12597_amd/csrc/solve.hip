@@ -130,6 +130,34 @@ pd_status solve_speculative(pd_plan p, const double *u0, const double *F, double
   return gst;
 }
 
+// Sine-basis form: DST-I of every time row of h (into the spectrum buffer,
+// read as [ell][n] float64), the per-mode time transform and solve (into U),
+// DST-I of every row of U in place.  The capacitance system is diagonal in
+// this basis and solved exactly, so no Krylov iteration runs.
+pd_status solve_sine(pd_plan p, const double *u0, const double *F, double *U, pd_info *info) {
+  double *A = reinterpret_cast<double *>(p->spec);
+  pd_status st = pd_launch_sine_dst(p, 0, u0, F, nullptr, A);
+  if (st != PD_OK) return st;
+  st = pd_launch_sine_modal(p, A, U);
+  if (st != PD_OK) return st;
+  st = pd_launch_sine_dst(p, 1, nullptr, nullptr, U, U);
+  if (st != PD_OK) return st;
+  if (info) {
+    info->gmres_iters = 0;
+    info->pint_loops = 1;
+    info->sweeps = 1;
+    info->gmres_rel_residual = 0.0;
+  }
+  if (p->check_residual) {
+    double rel;
+    st = pd_residual_impl(p, u0, F, U, &rel);
+    if (st != PD_OK) return st;
+    if (info) info->rel_residual = rel;
+  }
+  PD_HIP_CHECK(hipStreamSynchronize(p->stream));
+  return PD_OK;
+}
+
 bool check_ptrs(const void *a, const void *b, const void *c) {
   if (!a || !b || !c) {
     pd_set_error("NULL array argument");
@@ -160,6 +188,7 @@ extern "C" pd_status paradiag_solve(pd_plan p, const double *u0, const double *F
     info->early_exit = 0;
   }
   pd_status gst = PD_OK;
+  if (p->sine) return solve_sine(p, u0, F, U, info);
   pd_status st = pd_forward(p, u0, F, nullptr, p->spec, 0);
   if (st != PD_OK) return st;
   if (p->early_exit) {
@@ -330,4 +359,16 @@ extern "C" pd_status paradiag_residual(pd_plan p, const double *u0, const double
   }
   if (!check_ptrs(u0, F, U)) return PD_EINVAL;
   return pd_residual_impl(p, u0, F, U, rel);
+}
+
+extern "C" pd_status paradiag_sine_transform(pd_plan p, const double *in, double *out) {
+  if (!p || !in || !out) {
+    pd_set_error("invalid sine-transform arguments");
+    return PD_EINVAL;
+  }
+  if (!p->sine) {
+    pd_set_error("the plan was not created with PD_SHIFTED_SINE");
+    return PD_ENOTSUP;
+  }
+  return pd_launch_sine_dst(p, 1, nullptr, nullptr, in, out);
 }
