@@ -41,9 +41,10 @@ def parse():
     ap.add_argument("--count", type=int, default=0, help="ensemble / stream size")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--forms", default="fp64,mixed",
+    ap.add_argument("--forms", default="fp64,mixed,sine",
                     help="fp64, mixed, fp32: Algorithm 1 in that precision; alpha: "
-                         "Algorithm 3 (float64) with the early-exit test")
+                         "Algorithm 3 (float64) with the early-exit test; sine: Algorithm 1 "
+                         "in float64 with the shifted solves in the sine basis")
     ap.add_argument("--alpha", type=float, default=1e-2,
                     help="alpha of the 'alpha' form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -87,8 +88,10 @@ def main():
     results_U = {}
     for form in args.forms.split(","):
         prec = {"fp64": pd.PD_FP64, "mixed": pd.PD_MIXED, "fp32": pd.PD_FP32,
-                "alpha": pd.PD_FP64}[form]
+                "alpha": pd.PD_FP64, "sine": pd.PD_FP64}[form]
         extra = dict(alpha=args.alpha, early_exit=1) if form == "alpha" else {}
+        if form == "sine":
+            extra = dict(shifted_solver=pd.PD_SHIFTED_SINE)
         plan = pd.paradiag_plan_create(prob.n, ell, prob.tau, prob.M, prob.K, precision=prec,
                                        stream=stream.cuda_stream, **extra)
         try:
@@ -118,8 +121,11 @@ def main():
             }
             if form == "alpha":
                 forms[form].update(alpha=args.alpha, early_exit=info.early_exit)
+            if form == "sine":
+                forms[form]["dst_rows_ms"] = time_sine_transform(torch, pd, plan, U, stream,
+                                                                 args.kernel_reps)
             results_U[form] = U.cpu().numpy()
-            if form != "alpha":
+            if form not in ("alpha", "sine"):
                 kernels[form] = time_stages(pd, plan, prob, u0, F, U, stream,
                                             args.kernel_reps, prec)
         finally:
@@ -129,17 +135,21 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_leg(prob, results_U, forms, args.cpu_seconds)
 
-    # the headline is Algorithm 1 (float64 or mixed precision); the alpha form
-    # (Algorithm 3, a different accuracy trade-off) is reported beside it
-    alg1 = [f for f in forms if f != "alpha"]
+    # the headline is Algorithm 1 with partition/PCR shifted solves (float64
+    # or mixed precision); the alpha form (Algorithm 3, a different accuracy
+    # trade-off) and the sine-basis form (uniform grids only) are reported
+    # beside it
+    alg1 = [f for f in forms if f not in ("alpha", "sine")] or list(kernels) or list(forms)
     ok = [f for f in alg1 if forms[f].get("rel_err_vs_exact", 0.0) <= 1e-8]
     best = max(ok or alg1, key=lambda f: forms[f]["unknowns_per_s"])
-    k = kernels[best]
-    # the capacitance product runs once per GMRES iteration
-    k["stages"]["capacitance_apply"]["per_solve"] = forms[best]["gmres_iters"] * \
-        max(1, forms[best]["sweeps"])
-    dom = max(k["stages"], key=lambda s: k["stages"][s]["ms"] * k["stages"][s]["per_solve"])
-    roof = roofline(k["stages"][dom], dom, best)
+    roof = None
+    if best in kernels:
+        k = kernels[best]
+        # the capacitance product runs once per GMRES iteration
+        k["stages"]["capacitance_apply"]["per_solve"] = forms[best]["gmres_iters"] * \
+            max(1, forms[best]["sweeps"])
+        dom = max(k["stages"], key=lambda s: k["stages"][s]["ms"] * k["stages"][s]["per_solve"])
+        roof = roofline(k["stages"][dom], dom, best)
     line = {
         "metric": METRIC,
         "value": forms[best]["unknowns_per_s"],
@@ -158,6 +168,21 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
+
+
+def time_sine_transform(torch, pd, plan, U, stream, reps):
+    """Average duration of one DST-I pass over all time rows (HIP events on
+    the plan's stream)."""
+    scratch = torch.empty_like(U)
+    pd.paradiag_sine_transform(plan, U, scratch)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        pd.paradiag_sine_transform(plan, U, scratch)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
 
 
 def roofline(st, name, form):

@@ -31,8 +31,9 @@ using namespace pdfft;
 // MODE 0: rows h_t = tau f_t (+ u0 at t = 0); MODE 1: rows of `in`.
 // out may alias in (every row is read completely before it is written).
 // LDS: [C * stride cpx columns][twiddles of length H][T double scan sums]
+// (at most 128 VGPRs: two 512-thread blocks per CU)
 template <int MODE>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(512, 4)
 dst_rows_kernel(int n, int C, int stride, double tau, const double *__restrict__ u0,
                 const double *__restrict__ F, const double *in,
                 const double *__restrict__ sinq, const cpx<double> *__restrict__ wN,
@@ -63,22 +64,24 @@ dst_rows_kernel(int n, int C, int stride, double tau, const double *__restrict__
     return (i >= 0 && i < n) ? v : 0.0;
   };
   Cx *col = lds + c * stride;
-  {
-    double xa[8], xb[8], xc[8], xd[8];
+  // packed input c_m = y_{2m} + i y_{2m+1}, m = lt + u G: consecutive lanes
+  // read neighbouring elements; real parts, then imaginary parts (16 loads
+  // in flight per phase)
+  double *cold = reinterpret_cast<double *>(col);
+#pragma unroll
+  for (int ph = 0; ph < 2; ++ph) {
+    double xa[8], xb[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int m = 8 * lt + u;
-      xa[u] = xval(2 * m);
-      xb[u] = xval(N - 2 * m);
-      xc[u] = xval(2 * m + 1);
-      xd[u] = xval(N - 2 * m - 1);
+      const int j = 2 * (lt + u * G) + ph;
+      xa[u] = xval(j);
+      xb[u] = xval(N - j);
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int m = 8 * lt + u;
-      const double y0 = sinq[2 * m] * (xa[u] + xb[u]) + 0.5 * (xa[u] - xb[u]);
-      const double y1 = sinq[2 * m + 1] * (xc[u] + xd[u]) + 0.5 * (xc[u] - xd[u]);
-      col[pd_fpad(m)] = Cx{y0, y1};
+      const int m = lt + u * G;
+      const int j = 2 * m + ph;
+      cold[2 * pd_fpad(m) + ph] = sinq[j] * (xa[u] + xb[u]) + 0.5 * (xa[u] - xb[u]);
     }
   }
   __syncthreads();
@@ -105,15 +108,21 @@ dst_rows_kernel(int n, int C, int stride, double tau, const double *__restrict__
     s += Rv[u];
     loc[u] = s;
   }
-  scan[tid] = s;
-  __syncthreads();
-  for (int off = 1; off < G; off <<= 1) {
-    const double v = lt >= off ? scan[tid - off] : 0.0;
-    __syncthreads();
-    scan[tid] += v;
-    __syncthreads();
+  // prefix over the row's threads: within the wave by shuffles (segments of
+  // G lanes when a wave holds several rows), then over the row's waves
+  const int lane = tid & 63, seg = G < 64 ? G : 64;
+  double incl = s;
+  for (int off = 1; off < seg; off <<= 1) {
+    const double v = __shfl_up(incl, off, 64);
+    if ((lane & (seg - 1)) >= off) incl += v;
   }
-  const double excl = scan[tid] - s;
+  if (G > 64) {
+    if (lane == 63) scan[tid >> 6] = incl;
+    __syncthreads();
+    const int w0 = (tid >> 6) & ~((G >> 6) - 1);   // first wave of this row
+    for (int q = w0; q < (tid >> 6); ++q) incl += scan[q];
+  }
+  const double excl = incl - s;
   // results in row order through LDS (every thread has finished its split
   // reads), then contiguous stores
   double *orow = reinterpret_cast<double *>(col);
@@ -142,9 +151,8 @@ dst_rows_kernel(int n, int C, int stride, double tau, const double *__restrict__
 __global__ void __launch_bounds__(512)
 sine_modal_kernel(int N, int n, int C, int stride, const double *__restrict__ A,
                   const double *__restrict__ dal, const cpx<double> *__restrict__ tw,
-                  const double *__restrict__ lam, const double *__restrict__ gB,
-                  const double *__restrict__ gJ, const double *__restrict__ mk,
-                  const double *__restrict__ kk, double w, double *__restrict__ B) {
+                  const double *__restrict__ mk, const double *__restrict__ kk, double w,
+                  double *__restrict__ B) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using Cx = cpx<double>;
   Cx *lds = reinterpret_cast<Cx *>(smem_raw);
@@ -195,14 +203,32 @@ sine_modal_kernel(int N, int n, int C, int stride, const double *__restrict__ A,
     return (pnt & 1) ? Cx{0.5 * (zk.im + zn.im), 0.5 * (zn.re - zk.re)}
                      : Cx{0.5 * (zk.re + zn.re), 0.5 * (zk.im - zn.im)};
   };
-  auto denom = [&](int k) -> Cx { return Cx{lam[2 * k] * m + kap, lam[2 * k + 1] * m}; };
+  // per frequency: omega^k = exp(-2 pi i k/N) from the LDS twiddle tables,
+  // lambda_k = 1 - w omega^k, gamma_k = omega^k / N (times 2 for the
+  // conjugate half, k = 1..N/2-1)
+  const Cx *thi = twl + pd_tw_lo(N);
+  const double invNd = 1.0 / (double)N;
+  auto omega = [&](int k) -> Cx { return cmul(thi[k >> 6], twl[k & 63]); };
+  auto recip = [](double x) {   // 1/x: hardware estimate and two Newton steps
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+  };
+  // 1 / (lambda_k m + kap)
+  auto dinv = [&](Cx om) -> Cx {
+    const Cx d = {(1.0 - w * om.re) * m + kap, -w * om.im * m};
+    const double s2 = recip(d.re * d.re + d.im * d.im);
+    return Cx{d.re * s2, -d.im * s2};
+  };
   auto accumulate = [&](int k, Cx x) {
-    const Cx d = denom(k);
-    const double s2 = 1.0 / (d.re * d.re + d.im * d.im);
-    const Cx inv = {d.re * s2, -d.im * s2};
+    const Cx om = omega(k);
+    const Cx inv = dinv(om);
+    const double g = ((k == 0 || k == half) ? 1.0 : 2.0) * invNd;
     const Cx L = {m * (x.re * inv.re - x.im * inv.im), m * (x.re * inv.im + x.im * inv.re)};
-    bs += gB[2 * k] * L.re - gB[2 * k + 1] * L.im;
-    fs += m * (gJ[2 * k] * inv.re - gJ[2 * k + 1] * inv.im);
+    bs += g * (om.re * L.re - om.im * L.im);
+    fs += w * g * m * (om.re * inv.re - om.im * inv.im);
   };
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
@@ -234,9 +260,7 @@ sine_modal_kernel(int N, int n, int C, int stride, const double *__restrict__ A,
   const double x = bt / (1.0 + ft);
   // U~_k = m (X_k - w x) / d_k, then repack the two real columns
   auto solved = [&](int k, Cx v) -> Cx {
-    const Cx d = denom(k);
-    const double s2 = 1.0 / (d.re * d.re + d.im * d.im);
-    const Cx inv = {d.re * s2, -d.im * s2};
+    const Cx inv = dinv(omega(k));
     const Cx r = {m * (v.re - w * x), m * v.im};
     return Cx{r.re * inv.re - r.im * inv.im, r.re * inv.im + r.im * inv.re};
   };
@@ -329,8 +353,8 @@ pd_status pd_launch_sine_modal(pd_plan p, const double *A, double *B) {
   const double *dal = p->alpha == 1.0 ? nullptr : p->dal;
   hipLaunchKernelGGL(sine_modal_kernel, dim3(blocks), dim3(T), pd_sine_modal_lds(p, T),
                      p->stream, N, p->n, C, p->fft_stride, A, dal,
-                     reinterpret_cast<const cpx<double> *>(p->tw64), p->lam64, p->gB64, p->gJ64,
-                     p->sine_m, p->sine_k, p->w, B);
+                     reinterpret_cast<const cpx<double> *>(p->tw64), p->sine_m, p->sine_k, p->w,
+                     B);
   PD_HIP_CHECK(hipGetLastError());
   return PD_OK;
 }
