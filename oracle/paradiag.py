@@ -123,17 +123,81 @@ def gmres(matvec, b, tol=1e-12, maxit=200):
     return x, m, hist
 
 
+def fom(cap, Msp, Ksp, tau, b, eps=1e-8, maxit=50, q=1):
+    """Algorithm 2: the FOM-like projection of J_ell x = b onto a polynomial
+    Krylov space, with the residual computed (and the small system solved)
+    every q-th iteration.
+
+    The space is K_m(A, b) with A = tau M^{-1} K, which is the paper's
+    K_m(K, b) when M = I (a scalar multiple does not change the space).  With
+    the Arnoldi relation A V_m = V_m T_m + t_{m+1,m} v_{m+1} e_m^T every
+    shifted operator P_i^{-1} M = (lambda_i I + A)^{-1}, lambda_i = 1 - pi_i,
+    satisfies the shift-invariant relation of Section 3 (tau, which the
+    printed relation leaves off the t_{m+1,m} term, is inside A here), so
+      S_i = (lambda_i I_m + T_m)^{-1},  h_i = P_i^{-1} M v_{m+1},
+      (I + w sum_i gamma_i (I - t_{m+1,m} V_m^T h_i e_m^T) S_i) y = beta e_1,
+      ||r|| = |t_{m+1,m}| w || (I - V_m V_m^T) sum_i gamma_i h_i e_m^T S_i y ||
+    (eq. compute_ym and eq. compute_resnorm, with the alpha weight w of
+    Section 4 and gamma_i in the residual as in eq. compute_resnorm).
+    The loop runs at most maxit iterations.  Returns (x, m, residual norms at
+    the checks)."""
+    b = np.asarray(b, dtype=np.float64)
+    beta = float(np.linalg.norm(b))
+    if beta == 0.0:
+        return np.zeros_like(b), 0, [0.0]
+    Mlu = spla.splu(Msp.tocsc())
+    V = [b / beta]
+    T = np.zeros((maxit + 1, maxit))
+    m = 0
+    res = np.inf
+    hist = []
+    y = np.zeros(0)
+    lam = 1.0 - cap.pi
+    while res > eps * beta and m < maxit:
+        m += 1
+        w = tau * Mlu.solve(Ksp @ V[m - 1])
+        for k in range(m):
+            T[k, m - 1] = V[k] @ w
+            w = w - T[k, m - 1] * V[k]
+        T[m, m - 1] = np.linalg.norm(w)
+        V.append(w / T[m, m - 1])
+        if m % q == 0 or m == maxit:
+            Tm = T[:m, :m]
+            t = T[m, m - 1]
+            Vm = np.array(V[:m]).T                     # nbar x m
+            Mv = Msp @ V[m]
+            Z = np.eye(m, dtype=np.complex128)
+            S, H = [], []
+            for i, g in enumerate(cap.gamma):
+                Si = np.linalg.inv(lam[i] * np.eye(m) + Tm)
+                hi = cap.solve_shifted(i, Mv)
+                pi_ = Vm.T @ hi
+                em = np.zeros(m); em[-1] = 1.0
+                Z += cap.weight * g * (np.eye(m) - t * np.outer(pi_, em)) @ Si
+                S.append(Si)
+                H.append(hi)
+            e1 = np.zeros(m); e1[0] = beta
+            y = np.linalg.solve(Z, e1).real
+            z = sum(g * H[i] * (S[i][-1] @ y) for i, g in enumerate(cap.gamma))
+            rho = z - Vm @ (Vm.T @ z)
+            res = abs(t) * cap.weight * float(np.linalg.norm(rho))
+            hist.append(res)
+    x = np.array(V[:m]).T @ y
+    return x, m, hist
+
+
 # --------------------------------------------------------------------------
 # Algorithm 1 / Algorithm 3
 # --------------------------------------------------------------------------
 
 def paradiag(Msp, Ksp, tau, u0, F, alpha=1.0, capacitance="dense",
-             tol=1e-13, maxit=200, early_exit_eps=None):
+             tol=1e-13, maxit=200, early_exit_eps=None, q=1):
     """ParaDiag with backward Euler.  Returns a dict with the intermediates
     of the method (pi, gamma, Ghat, L, U1, b, x, W) and the solution U.
 
     capacitance = "dense" forms J_ell explicitly and solves it with LU;
-    "gmres" applies J_ell matrix-free and solves with ``gmres``.
+    "gmres" applies J_ell matrix-free and solves with ``gmres``; "fom" runs
+    Algorithm 2 (``fom``, residual checks every ``q`` iterations).
 
     early_exit_eps: Algorithm 3's test on the first term -- if the residual
     of U_1 in the original all-at-once system (with Sigma_1, not C_alpha) is
@@ -168,6 +232,8 @@ def paradiag(Msp, Ksp, tau, u0, F, alpha=1.0, capacitance="dense",
     if capacitance == "dense":
         x = np.linalg.solve(cap.dense(), b)
         its = 0
+    elif capacitance == "fom":
+        x, its, _ = fom(cap, Msp, Ksp, tau, b.real, eps=tol, maxit=maxit, q=q)
     else:
         x, its, _ = gmres(cap.matvec, b, tol=tol, maxit=maxit)
     # second parfor: W e_i = P_i^{-1} M x

@@ -9,6 +9,7 @@ import os
 import numpy as np
 import pytest
 import scipy.sparse as sp
+import scipy.sparse.linalg  # noqa: F401  (sp.linalg)
 
 from oracle import allatonce, dst, modal, paradiag
 from oracle.spatial import problem_matrices, spatial_matrices
@@ -386,6 +387,88 @@ def test_one_inner_iteration_suffices_2d():
     out = paradiag.paradiag(Msp, Ksp, p.tau, p.u0, p.F, capacitance="dense")
     _, its, _ = paradiag.gmres(cap.matvec, out["b"], tol=1e-8)
     assert its <= 2
+
+
+@pytest.mark.parametrize("kind", ["fd1", "fem1"])
+@pytest.mark.parametrize("alpha", [1.0, 1e-2])
+def test_fom_residual_formula_is_the_true_residual(kind, alpha):
+    """Algorithm 2's residual norm (eq. compute_resnorm, with gamma_i and the
+    alpha weight) equals ||J x_m - b|| computed directly from sparse LU
+    solves, at every m; the two printed variants it replaces (no gamma_i in
+    the residual line, and the listing's t_{m+1,m} without tau for the
+    Krylov space of K) do not."""
+    M, K, Msp, Ksp, tau, u0, F = _random_problem(kind, 9, 8, 31)
+    cap = paradiag.Capacitance(Msp, Ksp, tau, F.shape[0], alpha)
+    b = paradiag.paradiag(Msp, Ksp, tau, u0, F, alpha=alpha)["b"].real
+    for m_max in (1, 2, 3, 5):
+        x, m, hist = paradiag.fom(cap, Msp, Ksp, tau, b, eps=0.0, maxit=m_max)
+        direct = np.linalg.norm(cap.matvec(x).real - b)
+        assert m == m_max
+        assert np.isclose(hist[-1], direct, rtol=1e-7, atol=1e-14 * np.linalg.norm(b))
+    # the variants: rebuild the last check of m = 2 with each change
+    m = 2
+    Mlu = sp.linalg.splu(Msp.tocsc())
+    V = [b / np.linalg.norm(b)]
+    Tm = np.zeros((m + 1, m))
+    for j in range(m):
+        w = tau * Mlu.solve(Ksp @ V[j])
+        for k in range(j + 1):
+            Tm[k, j] = V[k] @ w
+            w = w - Tm[k, j] * V[k]
+        Tm[j + 1, j] = np.linalg.norm(w)
+        V.append(w / Tm[j + 1, j])
+    x, _, hist = paradiag.fom(cap, Msp, Ksp, tau, b, eps=0.0, maxit=m)
+    direct = np.linalg.norm(cap.matvec(x).real - b)
+    Vm = np.array(V[:m]).T
+    t = Tm[m, m - 1]
+    lam = 1.0 - cap.pi
+    em = np.eye(m)[-1]
+    e1 = np.eye(m)[0] * np.linalg.norm(b)
+    Z = np.eye(m, dtype=complex)
+    S, H = [], []
+    for i, g in enumerate(cap.gamma):
+        Si = np.linalg.inv(lam[i] * np.eye(m) + Tm[:m, :m])
+        hi = cap.solve_shifted(i, Msp @ V[m])
+        Z += cap.weight * g * (np.eye(m) - t * np.outer(Vm.T @ hi, em)) @ Si
+        S.append(Si); H.append(hi)
+    y = np.linalg.solve(Z, e1).real
+    no_gamma = sum(H[i] * (S[i][-1] @ y) for i in range(len(H)))
+    r_no_gamma = abs(t) * cap.weight * np.linalg.norm(no_gamma - Vm @ (Vm.T @ no_gamma))
+    assert not np.isclose(r_no_gamma, direct, rtol=1e-2)
+    with_g = sum(g * H[i] * (S[i][-1] @ y) for i, g in enumerate(cap.gamma))
+    r_no_tau = abs(t / tau) * cap.weight * np.linalg.norm(with_g - Vm @ (Vm.T @ with_g))
+    assert not np.isclose(r_no_tau, direct, rtol=1e-2)
+
+
+@pytest.mark.parametrize("kind", ["fd1", "fem1"])
+def test_fom_reaches_the_exact_solution(kind):
+    """With the whole space (m = nbar) Algorithm 2 returns the exact x, and
+    x = alpha^((ell-1)/ell) u_ell (the last time step of the all-at-once
+    solution); inside Algorithm 1 it gives the dense-LU solution."""
+    M, K, Msp, Ksp, tau, u0, F = _random_problem(kind, 7, 8, 32)
+    alpha = 1e-2
+    out = paradiag.paradiag(Msp, Ksp, tau, u0, F, alpha=alpha, capacitance="fom",
+                            tol=1e-14, maxit=7)
+    U2 = allatonce.solve_dense(Msp, Ksp, tau, u0, F)
+    assert allatonce.rel_err(out["U"].real, U2) < 1e-11
+    ell = F.shape[0]
+    assert np.allclose(out["x"], alpha ** ((ell - 1) / ell) * U2[-1], rtol=1e-10, atol=1e-12)
+
+
+def test_fom_one_iteration_suffices_2d():
+    """Section 6.1 states that one iteration of Algorithm 2 is enough for the
+    2D heat example; on a scaled-down grid the first residual check is below
+    1e-8 ||b||."""
+    n, ell = 15, 32
+    p = wl.heat_2d(n, ell, 1.0, 1.0, np.random.default_rng(1))
+    x = np.arange(1, n + 1) / (n + 1)
+    X, Y = np.meshgrid(x, x)
+    p.u0 = (X * Y * (X - 1) * (1 - Y)).reshape(-1)
+    Msp, Ksp = problem_matrices(p)
+    cap = paradiag.Capacitance(Msp, Ksp, p.tau, ell)
+    b = paradiag.paradiag(Msp, Ksp, p.tau, p.u0, p.F, capacitance="dense")["b"].real
+    _, m, hist = paradiag.fom(cap, Msp, Ksp, p.tau, b, eps=1e-8)
+    assert m == 1 and hist[0] <= 1e-8 * np.linalg.norm(b)
 
 
 # ------------------------------------------------------- planted mistakes --
