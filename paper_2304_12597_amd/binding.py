@@ -20,9 +20,14 @@ STATUS_NAMES = ["PD_OK", "PD_EINVAL", "PD_ENOMEM", "PD_EHIP", "PD_ENOTCONV",
                 "PD_ESINGULAR", "PD_ENONFINITE", "PD_EBUDGET", "PD_ENOTSUP"]
 PD_FP64, PD_MIXED, PD_FP32 = 0, 1, 2
 PD_SHIFTED_PARTITION, PD_SHIFTED_SINE = 0, 1
+PD_KRYLOV_GMRES, PD_KRYLOV_FOM = 0, 1
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libparadiag.so is not built (run __graft_entry__.build())")
+# torch brings its own HIP and HSA runtime libraries (same sonames as the
+# ones the library links); load them first, so that the library binds to
+# that one runtime instead of starting a second one in the process
+import torch  # noqa: E402,F401
 _lib = ctypes.CDLL(LIB_PATH)
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -38,7 +43,8 @@ class pd_options(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("maxit", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int), ("check_residual", ctypes.c_int),
                 ("stream", _vp), ("autotune", ctypes.c_int),
-                ("early_exit", ctypes.c_int), ("shifted_solver", ctypes.c_int)]
+                ("early_exit", ctypes.c_int), ("shifted_solver", ctypes.c_int),
+                ("krylov", ctypes.c_int), ("fom_q", ctypes.c_int)]
 
 
 class pd_info(ctypes.Structure):
@@ -133,7 +139,8 @@ def paradiag_last_error() -> str:
 def paradiag_plan_create(n, ell, tau, M, K, options=None, **kw):
     """M, K: (lower, diag, upper) arrays or None for M = I.  Keyword
     arguments override fields of pd_options (dims, precision, alpha, maxit,
-    max_sweeps, check_residual, stream, autotune, early_exit, shifted_solver)."""
+    max_sweeps, check_residual, stream, autotune, early_exit, shifted_solver, krylov,
+    fom_q)."""
     opt = options if options is not None else paradiag_default_options()
     for k, v in kw.items():
         if k == "stream" and v is not None and not isinstance(v, int):
