@@ -62,6 +62,14 @@ typedef enum {
 } pd_status;
 
 typedef enum {
+  PD_KRYLOV_GMRES = 0,       /* GMRES on J_ell (Arnoldi on J_ell itself)         */
+  PD_KRYLOV_FOM = 1          /* Algorithm 2: Galerkin projection onto            */
+                             /* K_m(tau M^{-1} K, b) (= K_m(K, b) for M = I),   */
+                             /* residual every fom_q steps; 1D float64 plans    */
+                             /* with constant-diagonal M, K; at most 32 steps   */
+} pd_krylov;
+
+typedef enum {
   PD_SHIFTED_PARTITION = 0,  /* tridiagonal partition solves + parallel cyclic   */
                              /* reduction, capacitance system by GMRES (any M, K) */
   PD_SHIFTED_SINE = 1        /* 1D, float64, symmetric Toeplitz M and K (uniform */
@@ -105,6 +113,9 @@ typedef struct {
                        /* paper's ||U_1||_F), skipping the capacitance      */
                        /* solve; 0 = always correct                         */
   int shifted_solver;  /* pd_shifted_solver                                 */
+  int krylov;          /* pd_krylov (ignored by PD_SHIFTED_SINE plans, whose */
+                       /* capacitance system is solved exactly)             */
+  int fom_q;           /* PD_KRYLOV_FOM: residual check every fom_q steps   */
 } pd_options;
 
 typedef struct {
@@ -118,7 +129,7 @@ typedef struct {
 
 /* Fill *opt with defaults: dims 1, PD_FP64, alpha 1, maxit 64,
  * max_sweeps 16, check_residual 0, stream NULL, autotune 0, early_exit 0,
- * shifted_solver PD_SHIFTED_PARTITION. */
+ * shifted_solver PD_SHIFTED_PARTITION, krylov PD_KRYLOV_GMRES, fom_q 1. */
 void paradiag_default_options(pd_options *opt);
 
 /* Create a plan for an n x ell problem with time step tau (Section 1).

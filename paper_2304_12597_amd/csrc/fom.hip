@@ -1,0 +1,483 @@
+// Algorithm 2: the FOM-like projection of the capacitance system
+// J_ell x = b onto a polynomial Krylov space, on the GPU.
+//
+// With the mass matrix the operator is A = tau M^{-1} K, so that every
+// shifted block is P_i^{-1} M = (lambda_i I + A)^{-1} (lambda_i = 1 - pi_i)
+// and K_m(A, b) is the paper's K_m(K, b) when M = I.  From the Arnoldi
+// relation A V_m = V_m T_m + t v_{m+1} e_m^T (t = t_{m+1,m}):
+//   S_i = (lambda_i I_m + T_m)^{-1},  h_i = P_i^{-1} M v_{m+1},
+//   (I + w sum_i gamma_i (I - t V_m^T h_i e_m^T) S_i) y = beta e_1,
+//   ||r|| = |t| w || (I - V_m V_m^T) sum_i gamma_i h_i e_m^T S_i y ||
+// (Section 3, eq. compute_ym and eq. compute_resnorm; w = alpha^(1/ell),
+// Section 4).  The sums over the full spectrum use its conjugate halves
+// (real data: twice the real part for k = 1..ell/2-1).
+//
+// One Krylov step: u = tau K v (stencil) and w = M^{-1} u (one block, the
+// partition solve), then two classical Gram-Schmidt passes.  Every q-th step
+// (and at the cap) the residual check: all h_i at once through the pass-C
+// shifted-solve kernel on a zero spectrum (one parfor: it writes -w h_i),
+// V_m^T h_i, per frequency S_i by Gauss-Jordan, the m x m system for y, the
+// weighted sum z = sum_i c_i h_i and the projected norm.
+#include "pd_internal.h"
+#include "pd_partition.h"
+
+#include <cmath>
+#include <vector>
+
+namespace {
+
+constexpr int FB = 512;    // single-block kernels
+constexpr int FR = 16;     // rows per thread of the single-block kernels (n <= FB*FR)
+
+// Sum over the block, returned to every thread, in a fixed order.
+__device__ double block_sum(double v, double *red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += red[q];
+  return s;
+}
+
+// beta = ||b||, v_1 = b / beta, T = 0, state[0] = beta
+__global__ void __launch_bounds__(FB)
+fom_start_kernel(int n, const double *__restrict__ b, double *__restrict__ V,
+                 double *__restrict__ T, int tsize, double *__restrict__ state) {
+  __shared__ double red[FB / 64];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += FB) s += b[i] * b[i];
+  const double beta = sqrt(block_sum(s, red));
+  for (int i = threadIdx.x; i < n; i += FB) V[i] = beta > 0.0 ? b[i] / beta : 0.0;
+  for (int i = threadIdx.x; i < tsize; i += FB) T[i] = 0.0;
+  if (threadIdx.x == 0) state[0] = beta;
+}
+
+// w = M^{-1} (tau K) v: stencil, then the partition solve with the uniform
+// mass factors (16 rows per thread, P = ceil(n/16) threads).
+__global__ void __launch_bounds__(512)
+fom_apply_kernel(int n, const double *__restrict__ v, const cpx<double> *__restrict__ mfac,
+                 double ml, double mu, double kl, double kd, double ku,
+                 double *__restrict__ w) {
+  constexpr int MR = 16;
+  __shared__ cpx<double> lfac[6 * (MR - 1)];
+  __shared__ Row3<double> xch[512];
+  const int P = blockDim.x, lt = threadIdx.x;
+  for (int i = lt; i < 6 * (MR - 1); i += P) lfac[i] = mfac[i];
+  const int s0 = lt * MR;
+  int len = n - s0;
+  len = len < 0 ? 0 : (len > MR ? MR : len);
+  cpx<double> d[MR];
+#pragma unroll
+  for (int q = 0; q < MR; ++q) {
+    const int i = s0 + q;
+    double u = 0.0;
+    if (q < len) {
+      u = kd * v[i];
+      if (i > 0) u += kl * v[i - 1];
+      if (i < n - 1) u += ku * v[i + 1];
+    }
+    d[q] = cpx<double>{u, 0.0};
+  }
+  __syncthreads();   // lfac visible
+  partition_solve<double, MR>(d, len, lt, P, lfac, xch, cpx<double>{ml, 0.0},
+                              cpx<double>{mu, 0.0});
+#pragma unroll
+  for (int q = 0; q < MR; ++q)
+    if (q < len) w[s0 + q] = d[q].re;
+}
+
+// Two classical Gram-Schmidt passes of w against v_1..v_m (V rows 0..m-1),
+// T[k][m-1] (row-major, FM_ columns), t = ||w||, V row m = w / t.
+template <int FM_>
+__global__ void __launch_bounds__(FB)
+fom_orth_kernel(int n, int m, double *__restrict__ V, const double *__restrict__ wsrc,
+                double *__restrict__ T) {
+  __shared__ double red[FB / 64];
+  __shared__ double part[FM_][FB / 64];
+  __shared__ double dots[FM_];
+  const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63, nw = FB / 64;
+  double wv[FR];
+#pragma unroll
+  for (int r = 0; r < FR; ++r) {
+    const int i = tid + r * FB;
+    wv[r] = i < n ? wsrc[i] : 0.0;
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int k = 0; k < m; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int r = 0; r < FR; ++r) {
+        const int i = tid + r * FB;
+        if (i < n) s += V[(size_t)k * n + i] * wv[r];
+      }
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+      if (lane == 0) part[k][wid] = s;
+    }
+    __syncthreads();
+    if (tid < m) {
+      double s = 0.0;
+      for (int q = 0; q < nw; ++q) s += part[tid][q];
+      dots[tid] = s;
+      T[(size_t)tid * FM_ + (m - 1)] += s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < FR; ++r) {
+      const int i = tid + r * FB;
+      if (i < n)
+        for (int k = 0; k < m; ++k) wv[r] -= dots[k] * V[(size_t)k * n + i];
+    }
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int r = 0; r < FR; ++r) s += wv[r] * wv[r];
+  const double t = sqrt(block_sum(s, red));
+  if (tid == 0) T[(size_t)m * FM_ + (m - 1)] = t;
+#pragma unroll
+  for (int r = 0; r < FR; ++r) {
+    const int i = tid + r * FB;
+    if (i < n) V[(size_t)m * n + i] = t > 0.0 ? wv[r] / t : 0.0;
+  }
+}
+
+// proj[i][k] = s * sum_rows V[k][row] * hs_i[row], one block per frequency
+// (hs holds -w h_i; s = -1/w).
+template <int FM_>
+__global__ void __launch_bounds__(256)
+fom_proj_kernel(int n, int m, const cpx<double> *__restrict__ hs, const double *__restrict__ V,
+                double s, cpx<double> *__restrict__ proj) {
+  __shared__ double pr[FM_][4], pi[FM_][4];
+  const int i = blockIdx.x, tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+  const cpx<double> *h = hs + (size_t)i * n;
+  double ar[FM_], ai[FM_];
+#pragma unroll
+  for (int k = 0; k < FM_; ++k) { ar[k] = 0.0; ai[k] = 0.0; }
+  for (int row = tid; row < n; row += 256) {
+    const cpx<double> hv = h[row];
+#pragma unroll
+    for (int k = 0; k < FM_; ++k)
+      if (k < m) {
+        const double vk = V[(size_t)k * n + row];
+        ar[k] += vk * hv.re;
+        ai[k] += vk * hv.im;
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < FM_; ++k) {
+    if (k < m) {
+      double a = ar[k], b = ai[k];
+      for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+      }
+      if (lane == 0) { pr[k][wid] = a; pi[k][wid] = b; }
+    }
+  }
+  __syncthreads();
+  if (tid < m) {
+    double a = 0.0, b = 0.0;
+    for (int q = 0; q < 4; ++q) { a += pr[tid][q]; b += pi[tid][q]; }
+    proj[(size_t)i * FM_ + tid] = cpx<double>{s * a, s * b};
+  }
+}
+
+// Per frequency i (one thread each): S_i = (lambda_i I + T_m)^{-1} by
+// Gauss-Jordan with partial pivoting in the thread's scratch [m][2m]; the
+// last row of S_i, and Zpart_i = Re(w g_i (S_i - t p_i (e_m^T S_i)))
+// (g_i = weight * gamma_i, the conjugate half folded in).
+template <int FM_>
+__global__ void __launch_bounds__(64)
+fom_small_kernel(int F2, int m, const double *__restrict__ lam, const double *__restrict__ gB,
+                 double w, const double *__restrict__ T, const cpx<double> *__restrict__ proj,
+                 cpx<double> *__restrict__ scratch, double *__restrict__ Zpart,
+                 cpx<double> *__restrict__ lastrow) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= F2) return;
+  using Cx = cpx<double>;
+  const int W = 2 * m;
+  Cx *a = scratch + (size_t)i * FM_ * 2 * FM_;
+  const Cx li = {lam[2 * i], lam[2 * i + 1]};
+  for (int r = 0; r < m; ++r)
+    for (int c = 0; c < W; ++c) {
+      Cx v = {0.0, 0.0};
+      if (c < m) {
+        v.re = T[(size_t)r * FM_ + c];
+        if (r == c) { v.re += li.re; v.im += li.im; }
+      } else if (c - m == r) {
+        v.re = 1.0;
+      }
+      a[r * W + c] = v;
+    }
+  for (int col = 0; col < m; ++col) {
+    int piv = col;
+    double best = -1.0;
+    for (int r = col; r < m; ++r) {
+      const Cx v = a[r * W + col];
+      const double mag = v.re * v.re + v.im * v.im;
+      if (mag > best) { best = mag; piv = r; }
+    }
+    if (piv != col)
+      for (int c = 0; c < W; ++c) {
+        const Cx t = a[col * W + c];
+        a[col * W + c] = a[piv * W + c];
+        a[piv * W + c] = t;
+      }
+    const Cx inv = crecip(a[col * W + col]);
+    for (int c = 0; c < W; ++c) a[col * W + c] = cmul(a[col * W + c], inv);
+    for (int r = 0; r < m; ++r) {
+      if (r == col) continue;
+      const Cx f = a[r * W + col];
+      for (int c = 0; c < W; ++c) a[r * W + c] = csub(a[r * W + c], cmul(f, a[col * W + c]));
+    }
+  }
+  // S_i = right half of a
+  const double t = T[(size_t)m * FM_ + (m - 1)];
+  const Cx g = {w * gB[2 * i], w * gB[2 * i + 1]};
+  for (int c = 0; c < m; ++c) lastrow[(size_t)i * FM_ + c] = a[(m - 1) * W + m + c];
+  for (int r = 0; r < m; ++r) {
+    const Cx pr = proj[(size_t)i * FM_ + r];
+    for (int c = 0; c < m; ++c) {
+      const Cx sv = a[r * W + m + c];
+      const Cx last = a[(m - 1) * W + m + c];
+      const Cx e = csub(sv, cmul(Cx{t * pr.re, t * pr.im}, last));
+      Zpart[(size_t)i * FM_ * FM_ + r * FM_ + c] = g.re * e.re - g.im * e.im;
+    }
+  }
+}
+
+// Z = I + sum_i Zpart_i (fixed order), y = Z^{-1} beta e_1 (partial
+// pivoting), c_i = g_i (e_m^T S_i y).
+template <int FM_>
+__global__ void __launch_bounds__(FB)
+fom_solve_kernel(int F2, int m, const double *__restrict__ Zpart,
+                 const cpx<double> *__restrict__ lastrow, const double *__restrict__ gB,
+                 const double *__restrict__ state, double *__restrict__ y,
+                 cpx<double> *__restrict__ cvec) {
+  __shared__ double Z[FM_][FM_ + 1];
+  __shared__ double ys[FM_];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < m * m; e += FB) {
+    const int r = e / m, c = e - r * m;
+    double s = (r == c) ? 1.0 : 0.0;
+    for (int i = 0; i < F2; ++i) s += Zpart[(size_t)i * FM_ * FM_ + r * FM_ + c];
+    Z[r][c] = s;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int r = 0; r < m; ++r) Z[r][FM_] = (r == 0) ? state[0] : 0.0;
+    for (int col = 0; col < m; ++col) {
+      int piv = col;
+      for (int r = col + 1; r < m; ++r)
+        if (fabs(Z[r][col]) > fabs(Z[piv][col])) piv = r;
+      if (piv != col)
+        for (int c = 0; c <= FM_; ++c) {
+          const double t = Z[col][c];
+          Z[col][c] = Z[piv][c];
+          Z[piv][c] = t;
+        }
+      for (int r = col + 1; r < m; ++r) {
+        const double f = Z[r][col] / Z[col][col];
+        for (int c = col; c < m; ++c) Z[r][c] -= f * Z[col][c];
+        Z[r][FM_] -= f * Z[col][FM_];
+      }
+    }
+    for (int r = m - 1; r >= 0; --r) {
+      double s = Z[r][FM_];
+      for (int c = r + 1; c < m; ++c) s -= Z[r][c] * ys[c];
+      ys[r] = s / Z[r][r];
+    }
+    for (int r = 0; r < m; ++r) y[r] = ys[r];
+  }
+  __syncthreads();
+  for (int i = tid; i < F2; i += FB) {
+    cpx<double> s = {0.0, 0.0};
+    for (int c = 0; c < m; ++c) {
+      const cpx<double> l = lastrow[(size_t)i * FM_ + c];
+      s.re += l.re * ys[c];
+      s.im += l.im * ys[c];
+    }
+    const cpx<double> g = {gB[2 * i], gB[2 * i + 1]};
+    cvec[i] = cmul(g, s);
+  }
+}
+
+// z[row] = s * sum_i Re(c_i hs_i[row])  (hs = -w h, s = -1/w)
+__global__ void __launch_bounds__(256)
+fom_wsum_kernel(int n, int F2, const cpx<double> *__restrict__ hs,
+                const cpx<double> *__restrict__ cvec, double s, double *__restrict__ z) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  double acc = 0.0;
+  for (int i = 0; i < F2; ++i) {
+    const cpx<double> h = hs[(size_t)i * n + row], c = cvec[i];
+    acc += c.re * h.re - c.im * h.im;
+  }
+  z[row] = s * acc;
+}
+
+// rho = (I - V_m V_m^T) z (two passes), state[1] = |t| w ||rho||
+template <int FM_>
+__global__ void __launch_bounds__(FB)
+fom_resid_kernel(int n, int m, const double *__restrict__ V, const double *__restrict__ z,
+                 const double *__restrict__ T, double w, double *__restrict__ state) {
+  __shared__ double red[FB / 64];
+  __shared__ double part[FM_][FB / 64];
+  __shared__ double dots[FM_];
+  const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63, nw = FB / 64;
+  double zv[FR];
+#pragma unroll
+  for (int r = 0; r < FR; ++r) {
+    const int i = tid + r * FB;
+    zv[r] = i < n ? z[i] : 0.0;
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int k = 0; k < m; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int r = 0; r < FR; ++r) {
+        const int i = tid + r * FB;
+        if (i < n) s += V[(size_t)k * n + i] * zv[r];
+      }
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+      if (lane == 0) part[k][wid] = s;
+    }
+    __syncthreads();
+    if (tid < m) {
+      double s = 0.0;
+      for (int q = 0; q < nw; ++q) s += part[tid][q];
+      dots[tid] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < FR; ++r) {
+      const int i = tid + r * FB;
+      if (i < n)
+        for (int k = 0; k < m; ++k) zv[r] -= dots[k] * V[(size_t)k * n + i];
+    }
+    __syncthreads();
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int r = 0; r < FR; ++r) s += zv[r] * zv[r];
+  const double nrm = sqrt(block_sum(s, red));
+  if (tid == 0) state[1] = fabs(T[(size_t)m * FM_ + (m - 1)]) * w * nrm;
+}
+
+// x = V_m y
+__global__ void __launch_bounds__(256)
+fom_combine_kernel(int n, int m, const double *__restrict__ V, const double *__restrict__ y,
+                   double *__restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < m; ++k) s += y[k] * V[(size_t)k * n + i];
+  x[i] = s;
+}
+
+}  // namespace
+
+// Host side --------------------------------------------------------------
+
+size_t pd_fom_doubles(int n, int F2) {
+  const size_t FM = PD_FOM_MAXM;
+  return (FM + 1) * FM                // T
+         + 2 * (size_t)F2 * FM        // proj
+         + 2 * (size_t)F2 * FM * 2 * FM   // Gauss-Jordan scratch
+         + (size_t)F2 * FM * FM       // Zpart
+         + 2 * (size_t)F2 * FM        // last rows of S_i
+         + FM                         // y
+         + 2 * (size_t)F2             // c_i
+         + 4                          // beta, residual
+         + 12 * 15                    // mass factors (16 rows per thread)
+         + (size_t)n;                 // z
+}
+
+bool pd_fom_supported(pd_plan p) {
+  return p->dims == 1 && p->prec == PD_FP64 && p->uniform && p->n <= FB * FR;
+}
+
+size_t pd_fom_mfac_offset(int F2) {
+  const size_t FM = PD_FOM_MAXM;
+  return (FM + 1) * FM + 2 * (size_t)F2 * FM + 2 * (size_t)F2 * FM * 2 * FM +
+         (size_t)F2 * FM * FM + 2 * (size_t)F2 * FM + FM + 2 * (size_t)F2 + 4;
+}
+
+pd_status pd_fom(pd_plan p, const double *b, double *x, double rtol, int *iters,
+                 double *relres, int *checks) {
+  constexpr int FM = PD_FOM_MAXM;
+  const int n = p->nbar, F2 = p->F2;
+  const int maxm = p->maxit < FM ? p->maxit : FM;
+  const int q = p->fom_q < 1 ? 1 : p->fom_q;
+  double *T = p->fom;
+  auto proj = reinterpret_cast<cpx<double> *>(T + (FM + 1) * FM);
+  auto scratch = proj + (size_t)F2 * FM;
+  double *Zpart = reinterpret_cast<double *>(scratch + (size_t)F2 * FM * 2 * FM);
+  auto lastrow = reinterpret_cast<cpx<double> *>(Zpart + (size_t)F2 * FM * FM);
+  double *y = reinterpret_cast<double *>(lastrow + (size_t)F2 * FM);
+  auto cvec = reinterpret_cast<cpx<double> *>(y + FM);
+  double *state = reinterpret_cast<double *>(cvec + F2);
+  auto mfac = reinterpret_cast<const cpx<double> *>(state + 4);
+  double *z = state + 4 + 12 * 15;
+  auto hs = reinterpret_cast<cpx<double> *>(p->fom_h);
+  const double s = -1.0 / p->w;
+  const int P = (n + 15) / 16;
+  hipLaunchKernelGGL(fom_start_kernel, dim3(1), dim3(FB), 0, p->stream, n, b, p->V, T,
+                     (FM + 1) * FM, state);
+  PD_HIP_CHECK(hipGetLastError());
+  double beta = 0.0, res = 0.0;
+  int m = 0;
+  bool checked = false;
+  int nchecks = 0;
+  while (m < maxm) {
+    ++m;
+    hipLaunchKernelGGL(fom_apply_kernel, dim3(1), dim3(P), 0, p->stream, n,
+                       p->V + (size_t)(m - 1) * n, mfac, p->uni[0], p->uni[2], p->uni[3],
+                       p->uni[4], p->uni[5], p->wvec);
+    hipLaunchKernelGGL((fom_orth_kernel<FM>), dim3(1), dim3(FB), 0, p->stream, n, m, p->V,
+                       p->wvec, T);
+    PD_HIP_CHECK(hipGetLastError());
+    if (m % q != 0 && m != maxm) continue;
+    // h_i for all i: pass C on a zero spectrum with x = v_{m+1} gives -w h_i
+    PD_HIP_CHECK(hipMemsetAsync(p->fom_h, 0, p->spec_bytes, p->stream));
+    pd_status st = pd_launch_tridiag(p, 1, p->fom_h, p->V + (size_t)m * n, p->fom_h);
+    if (st != PD_OK) return st;
+    hipLaunchKernelGGL((fom_proj_kernel<FM>), dim3(F2), dim3(256), 0, p->stream, n, m, hs, p->V,
+                       s, proj);
+    hipLaunchKernelGGL((fom_small_kernel<FM>), dim3((F2 + 63) / 64), dim3(64), 0, p->stream, F2, m,
+                       p->lam64, p->gB64, p->w, T, proj, scratch, Zpart, lastrow);
+    hipLaunchKernelGGL((fom_solve_kernel<FM>), dim3(1), dim3(FB), 0, p->stream, F2, m, Zpart,
+                       lastrow, p->gB64, state, y, cvec);
+    hipLaunchKernelGGL(fom_wsum_kernel, dim3((n + 255) / 256), dim3(256), 0, p->stream, n, F2, hs,
+                       cvec, s, z);
+    hipLaunchKernelGGL((fom_resid_kernel<FM>), dim3(1), dim3(FB), 0, p->stream, n, m, p->V, z, T,
+                       p->w, state);
+    PD_HIP_CHECK(hipGetLastError());
+    double hst[2];
+    PD_HIP_CHECK(hipMemcpyAsync(hst, state, 2 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    PD_HIP_CHECK(hipStreamSynchronize(p->stream));
+    beta = hst[0];
+    res = hst[1];
+    checked = true;
+    ++nchecks;
+    if (!std::isfinite(res) || !std::isfinite(beta)) {
+      pd_set_error("Algorithm 2 produced a non-finite residual");
+      return PD_ENONFINITE;
+    }
+    if (res <= rtol * beta) break;
+  }
+  hipLaunchKernelGGL(fom_combine_kernel, dim3((n + 255) / 256), dim3(256), 0, p->stream, n, m, p->V,
+                     y, x);
+  PD_HIP_CHECK(hipGetLastError());
+  if (iters) *iters = m;
+  if (relres) *relres = beta > 0.0 ? res / beta : 0.0;
+  if (checks) *checks = nchecks;
+  return (checked && res <= rtol * beta) ? PD_OK : PD_ENOTCONV;
+}
+
+// mass factors for fom_apply_kernel (host, float64): 16 rows per thread
+void pd_fom_mass_factors(pd_plan p, std::vector<double> &out) {
+  out.assign(12 * 15, 0.0);
+  pd_partition_factors(p->uni[0], 0.0, p->uni[1], 0.0, p->uni[2], 0.0, 16, out.data());
+}

@@ -191,6 +191,10 @@ struct pd_plan_s {
   int gm_seen = 0;             // a solve has run (gm_pred is learned)
   int autotune = 0;            // buffers sized for every tuning candidate
   int early_exit = 0;          // Algorithm 3's test on U_1 before the correction
+  int krylov = 0;              // capacitance solver: 0 GMRES, 1 Algorithm 2
+  int fom_q = 1;               // Algorithm 2: residual check every fom_q steps
+  double *fom = nullptr;       // Algorithm 2 device state (pd_fom_doubles)
+  void *fom_h = nullptr;       // Algorithm 2: -w h_i for all i (spectrum sized)
   // sine-basis shifted solves (symmetric Toeplitz M, K; n + 1 a power of two)
   int sine = 0;
   int sine_C = 1;              // rows per block of the DST-I kernel
@@ -265,6 +269,14 @@ pd_status pd_gmres(pd_plan p, const double *b, double *x, double rtol,
 pd_status pd_residual_impl(pd_plan p, const double *u0, const double *F,
                            const double *U, double *rel);
 pd_status pd_sum_norms(pd_plan p, int nblk, double *rn2, double *gn2);
+// Algorithm 2 (fom.hip)
+constexpr int PD_FOM_MAXM = 32;   // largest Krylov dimension of Algorithm 2
+size_t pd_fom_doubles(int n, int F2);
+size_t pd_fom_mfac_offset(int F2);
+bool pd_fom_supported(pd_plan p);
+pd_status pd_fom(pd_plan p, const double *b, double *x, double rtol, int *iters,
+                 double *relres, int *checks);
+void pd_fom_mass_factors(pd_plan p, std::vector<double> &out);
 // sine-basis path (sine.hip)
 int pd_sine_dst_C(int n, int ell);
 size_t pd_sine_dst_lds(int n, int C);

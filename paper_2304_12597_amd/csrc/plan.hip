@@ -68,7 +68,8 @@ void free_plan(pd_plan p) {
   if (!p) return;
   void *ptrs[] = {p->coef64, p->coef32, p->lam64, p->lam32, p->gB64, p->gJ64, p->tw64,
                   p->tw32, p->dal, p->fac64, p->fac32, p->twd, p->wreal, p->spec, p->partials, p->rstage, p->bvec, p->xvec, p->wvec, p->V,
-                  p->gm, p->red, p->sine_q, p->sine_wN, p->sine_twH, p->sine_m, p->sine_k};
+                  p->gm, p->red, p->sine_q, p->sine_wN, p->sine_twH, p->sine_m, p->sine_k,
+                  p->fom, p->fom_h};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   if (p->host_pin) (void)hipHostFree(p->host_pin);
@@ -82,12 +83,12 @@ std::mutex g_attr_mu;
 // Launch configurations and device allocation sizes (in elements of their
 // type) of a plan; shared by plan creation and paradiag_plan_bytes.
 struct Layout {
-  size_t coef = 0, lam = 0, tw = 0, dal = 0, fac = 0, twd = 0, wreal = 0, sine = 0;
+  size_t coef = 0, lam = 0, tw = 0, dal = 0, fac = 0, twd = 0, wreal = 0, sine = 0, fom = 0;
   size_t spec_bytes = 0, partials = 0, rstage = 0, vec = 0, V = 0, gm = 0, red = 0;
   size_t total_bytes() const {
     return coef * 12 + lam * 12 + 2 * lam * 8 + tw * 12 + dal * 8 + fac * 12 + twd * 8 +
            wreal * 8 + spec_bytes + partials * 8 + rstage * 8 + 3 * vec * 8 + V * 8 + gm * 8 +
-           red * 8 + sine * 8;
+           red * 8 + sine * 8 + fom * 8 + (fom ? spec_bytes : 0);
   }
 };
 
@@ -149,6 +150,7 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
     }
     L.sine = (size_t)N + 2 * (size_t)(H + 1) + 2 * (size_t)H + 2 * (size_t)n;
   }
+  if (p->krylov == PD_KRYLOV_FOM) L.fom = pd_fom_doubles(n, F2);
   L.coef = 6 * (size_t)n;
   L.lam = 2 * (size_t)F2;
   L.tw = 2 * (size_t)ell;
@@ -331,6 +333,8 @@ extern "C" void paradiag_default_options(pd_options *opt) {
   opt->autotune = 0;
   opt->early_exit = 0;
   opt->shifted_solver = PD_SHIFTED_PARTITION;
+  opt->krylov = PD_KRYLOV_GMRES;
+  opt->fom_q = 1;
 }
 
 extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double tau,
@@ -405,6 +409,10 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
       }
     }
   }
+  if ((opt.krylov != PD_KRYLOV_GMRES && opt.krylov != PD_KRYLOV_FOM) || opt.fom_q < 1) {
+    pd_set_error("unknown krylov solver or fom_q < 1");
+    return PD_EINVAL;
+  }
   if (opt.shifted_solver != PD_SHIFTED_PARTITION && opt.shifted_solver != PD_SHIFTED_SINE) {
     pd_set_error("unknown shifted_solver");
     return PD_EINVAL;
@@ -458,6 +466,8 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   p->autotune = (opt.autotune != 0 && opt.dims == 1) ? 1 : 0;
   p->early_exit = opt.early_exit != 0 ? 1 : 0;
   p->sine = opt.shifted_solver == PD_SHIFTED_SINE ? 1 : 0;
+  p->krylov = opt.krylov;
+  p->fom_q = opt.fom_q;
   p->stream = reinterpret_cast<hipStream_t>(opt.stream);
   p->mass_identity = (M == nullptr);
   if (hipGetDevice(&p->device) != hipSuccess) {
@@ -569,6 +579,11 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
       return lst;
     }
   }
+  if (p->krylov == PD_KRYLOV_FOM && !p->sine && !pd_fom_supported(p)) {
+    pd_set_error("Algorithm 2 runs on 1D float64 plans with constant-diagonal M and K, n <= 8192");
+    free_plan(p);
+    return PD_ENOTSUP;
+  }
   std::vector<double> fac;
   std::vector<double> twd;
   if (p->dims == 2) {
@@ -651,6 +666,10 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   PD_TRY(dev_alloc(&p->V, (size_t)(p->maxit + 1) * nbar));
   PD_TRY(dev_alloc(&p->gm, pd_gmres_state_doubles(p->maxit)));
   PD_TRY(dev_alloc(&p->red, L.red));
+  if (p->krylov == PD_KRYLOV_FOM) {
+    PD_TRY(dev_alloc(&p->fom, L.fom));
+    PD_TRY(dev_alloc(reinterpret_cast<unsigned char **>(&p->fom_h), p->spec_bytes));
+  }
   if (p->sine) {
     PD_TRY(dev_alloc(&p->sine_q, sq.size()));
     PD_TRY(dev_alloc(&p->sine_wN, swN.size()));
@@ -682,6 +701,12 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   PD_TRY(upload(p->fac64, fac, p->stream));
   PD_TRY(upload(p->fac32, fac32, p->stream));
   PD_TRY(upload(p->twd, twd, p->stream));
+  if (p->krylov == PD_KRYLOV_FOM) {
+    std::vector<double> mf;
+    pd_fom_mass_factors(p, mf);
+    PD_HIP_CHECK(hipMemcpyAsync(p->fom + pd_fom_mfac_offset(p->F2), mf.data(),
+                                mf.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  }
   if (p->sine) {
     PD_TRY(upload(p->sine_q, sq, p->stream));
     PD_TRY(upload(p->sine_wN, swN, p->stream));
@@ -747,6 +772,7 @@ extern "C" size_t paradiag_plan_bytes(int n, int ell, const pd_options *opt_in) 
   tmp.uniform = true;
   tmp.autotune = (opt.autotune != 0 && opt.dims == 1) ? 1 : 0;
   tmp.sine = opt.shifted_solver == PD_SHIFTED_SINE ? 1 : 0;
+  tmp.krylov = opt.krylov;
   int dev = 0, cus = 256, lds = 65536;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);

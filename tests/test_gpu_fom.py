@@ -1,0 +1,108 @@
+"""GPU parity of Algorithm 2 (PD_KRYLOV_FOM) for the capacitance system:
+whole solves against the oracle's Algorithm 2 (same Krylov dimension, same
+U) and against the exact solution."""
+import numpy as np
+import pytest
+
+from oracle import allatonce, modal, paradiag
+from oracle.spatial import problem_matrices
+from paper_2304_12597_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def T(a):
+    return torch.tensor(np.ascontiguousarray(a), device=dev())
+
+
+def make_problem(kind, n, ell, seed, nu=1.0, T_=1.0):
+    return wl.heat_1d(kind, n, ell, T_, nu, np.random.default_rng(seed), True)
+
+
+def _solve(lib, p, tol=1e-10, **kw):
+    plan = lib.paradiag_plan_create(p.n, p.ell, p.tau, p.M, p.K, krylov=lib.PD_KRYLOV_FOM,
+                                    check_residual=1,
+                                    stream=torch.cuda.current_stream().cuda_stream, **kw)
+    try:
+        U = torch.empty((p.ell, p.nbar), dtype=torch.float64, device=dev())
+        info = lib.paradiag_solve(plan, T(p.u0), T(p.F), U, tol, allow_notconv=True)
+        torch.cuda.synchronize()
+        return U.cpu().numpy(), info
+    finally:
+        lib.paradiag_plan_destroy(plan)
+
+
+# cases where Algorithm 2 converges within its 32 steps (it projects onto a
+# polynomial space of K, so stiff problems need many steps: Section 3)
+@pytest.mark.parametrize("kind,n,ell,T_,alpha", [
+    ("fd1", 15, 8, 1.0, 1.0), ("fd1", 31, 16, 1.0, 1.0), ("fem1", 31, 8, 1.0, 1.0),
+    ("fd1", 127, 16, 4.0, 1.0), ("fem1", 255, 16, 10.0, 1.0), ("fem1", 255, 16, 10.0, 0.1)])
+def test_fom_matches_oracle(lib, kind, n, ell, T_, alpha):
+    """Same Krylov dimension as the oracle's Algorithm 2 at the same
+    tolerance (tol/100 on ||r|| / beta, q = 1; one step either way where a
+    check sits at the threshold), and the same U."""
+    p = make_problem(kind, n, ell, n + ell, T_=T_)
+    tol = 1e-10
+    U, info = _solve(lib, p, tol=tol, alpha=alpha)
+    Msp, Ksp = problem_matrices(p)
+    ref = paradiag.paradiag(Msp, Ksp, p.tau, p.u0, p.F, alpha=alpha, capacitance="fom",
+                            tol=tol * 1e-2, maxit=32)
+    assert ref["gmres_iters"] < 32
+    assert abs(info.gmres_iters - ref["gmres_iters"]) <= 1, (info.as_dict(), ref["gmres_iters"])
+    assert info.pint_loops == info.gmres_iters + 2
+    err = allatonce.rel_err(U, ref["U"].real)
+    assert err < 1e-10, err
+
+
+@pytest.mark.parametrize("kind,n,ell,T_", [("fem1", 255, 16, 10.0), ("fd1", 127, 16, 4.0),
+                                           ("fem1", 4095, 16, 10.0)])
+def test_fom_end_to_end_exact(lib, kind, n, ell, T_):
+    p = make_problem(kind, n, ell, 7 * n + ell, T_=T_)
+    U, info = _solve(lib, p)
+    err = allatonce.rel_err(U, modal.modal_solution(p))
+    assert err < 5e-9, (err, info.as_dict())
+    assert info.rel_residual < 1e-9
+
+
+@pytest.mark.parametrize("q", [2, 3])
+def test_fom_residual_freezing(lib, q):
+    """Residual checks every q steps (Section 3): the Krylov dimension is a
+    multiple of q and #PinT = m/q + 2."""
+    p = make_problem("fd1", 31, 16, 5)
+    U, info = _solve(lib, p, fom_q=q)
+    assert info.gmres_iters % q == 0 and info.gmres_iters < 32
+    assert info.pint_loops == info.gmres_iters // q + 2
+    assert allatonce.rel_err(U, modal.modal_solution(p)) < 5e-9
+
+
+def test_fom_step_cap_is_reported(lib):
+    """A stiff problem that needs more than 32 steps ends at the cap with
+    PD_ENOTCONV (and the last iterate)."""
+    p = make_problem("fem1", 255, 32, 3, nu=0.1)
+    plan = lib.paradiag_plan_create(p.n, p.ell, p.tau, p.M, p.K, krylov=lib.PD_KRYLOV_FOM,
+                                    stream=torch.cuda.current_stream().cuda_stream)
+    try:
+        U = torch.empty((p.ell, p.nbar), dtype=torch.float64, device=dev())
+        with pytest.raises(lib.PDError) as e:
+            lib.paradiag_solve(plan, T(p.u0), T(p.F), U, 1e-10)
+        assert e.value.status == lib.PD_ENOTCONV
+        info = lib.paradiag_solve(plan, T(p.u0), T(p.F), U, 1e-10, allow_notconv=True)
+        assert info.gmres_iters == 32
+    finally:
+        lib.paradiag_plan_destroy(plan)
+
+
+def test_fom_rejects_unsupported(lib):
+    p = make_problem("fd1", 63, 8, 1)
+    with pytest.raises(RuntimeError):     # mixed precision
+        lib.paradiag_plan_create(p.n, p.ell, p.tau, p.M, p.K, krylov=lib.PD_KRYLOV_FOM,
+                                 precision=lib.PD_MIXED)
+    K = (p.K[0], p.K[1].copy(), p.K[2])
+    K[1][3] *= 1.1                         # not constant-diagonal
+    with pytest.raises(RuntimeError):
+        lib.paradiag_plan_create(p.n, p.ell, p.tau, p.M, K, krylov=lib.PD_KRYLOV_FOM)
