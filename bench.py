@@ -35,7 +35,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="fem1d",
-                    choices=["fem1d", "ensemble", "serve", "alpha"])
+                    choices=["fem1d", "ensemble", "serve", "alpha", "fom"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--count", type=int, default=0, help="ensemble / stream size")
@@ -75,6 +75,9 @@ def main():
         return
     if args.workload == "alpha":
         print(json.dumps(bench_alpha(args, torch, pd, wl, dev)))
+        return
+    if args.workload == "fom":
+        print(json.dumps(bench_fom(args, torch, pd, wl, dev)))
         return
     stream = torch.cuda.current_stream(dev)
     prob = wl.cfg_fem_1d()
@@ -430,6 +433,57 @@ def bench_alpha(args, torch, pd, wl, dev):
         for ci, r in enumerate(rows):
             Uh = Us[ci]
             r["rel_err_vs_exact"] = float(np.linalg.norm(Uh[tt, ii] - ref) / np.linalg.norm(ref))
+    return out
+
+
+def bench_fom(args, torch, pd, wl, dev):
+    """The capacitance system by GMRES and by Algorithm 2 (FOM-like
+    projection on K_m(K, b), residual every q steps) on three 1D FEM/FD heat
+    problems: one where J_ell is close to I, one needing many steps, and the
+    stiff headline problem (n = 8191, ell = 2048)."""
+    cases = [("fem1", 4095, 16, 10.0), ("fd1", 127, 16, 4.0), ("fem1", 8191, 2048, 1.0)]
+    stream = torch.cuda.current_stream(dev)
+    tol = 1e-8
+    rows, Us, probs = [], [], []
+    for kind, n, ell, T in cases:
+        p = wl.heat_1d(kind, n, ell, T, 1.0, np.random.default_rng(n + ell), True)
+        u0 = torch.tensor(p.u0, device=dev)
+        F = torch.tensor(p.F, device=dev)
+        U = torch.empty((p.ell, p.nbar), dtype=torch.float64, device=dev)
+        for name, extra in (("gmres", {}), ("fom_q1", dict(krylov=pd.PD_KRYLOV_FOM, fom_q=1)),
+                            ("fom_q4", dict(krylov=pd.PD_KRYLOV_FOM, fom_q=4))):
+            plan = pd.paradiag_plan_create(p.n, p.ell, p.tau, p.M, p.K,
+                                           stream=stream.cuda_stream, **extra)
+            try:
+                for _ in range(args.warmup):
+                    pd.paradiag_solve(plan, u0, F, U, tol, allow_notconv=True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    info = pd.paradiag_solve(plan, u0, F, U, tol, allow_notconv=True)
+                torch.cuda.synchronize()
+                wall = (time.perf_counter() - t0) / args.steps
+                rows.append({"problem": "%s n=%d ell=%d T=%g" % (kind, n, ell, T),
+                             "krylov": name, "ms": 1e3 * wall, "steps": info.gmres_iters,
+                             "pint_loops": info.pint_loops,
+                             "capacitance_rel_residual": info.gmres_rel_residual})
+                Us.append(U.cpu().numpy())
+                probs.append(p)
+            finally:
+                pd.paradiag_plan_destroy(plan)
+    out = {"metric": "capacitance solver comparison (GMRES vs Algorithm 2)",
+           "value": None, "unit": "ms per solve", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": False, "dtype": "f64",
+           "data": "synthetic", "config": {"workload": "1D heat, three problems", "tol": tol},
+           "rows": rows}
+    if not args.no_cpu_baseline:
+        from oracle import modal
+        rng = np.random.default_rng(0)
+        for r, U, p in zip(rows, Us, probs):
+            tt = rng.integers(0, p.ell, 4000)
+            ii = rng.integers(0, p.nbar, 4000)
+            ref = modal.modal_sample(p, tt, ii)
+            r["rel_err_vs_exact"] = float(np.linalg.norm(U[tt, ii] - ref) / np.linalg.norm(ref))
     return out
 
 
