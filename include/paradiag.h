@@ -116,6 +116,12 @@ typedef struct {
   int krylov;          /* pd_krylov (ignored by PD_SHIFTED_SINE plans, whose */
                        /* capacitance system is solved exactly)             */
   int fom_q;           /* PD_KRYLOV_FOM: residual check every fom_q steps   */
+  int bdf_order;       /* s = 1..6: BDF of order s in time (Section 5,      */
+                       /* table of BDF coefficients); 1 = backward Euler.   */
+                       /* s > 1: 1D, PD_FP64, alpha 1, GMRES, partition     */
+                       /* solves, no early_exit, ell >= 2 s; u0 holds the   */
+                       /* s starting values u_{1-s}..u_0 as [s][nbar] and   */
+                       /* capacitance vectors are [s][nbar]                 */
 } pd_options;
 
 typedef struct {
@@ -129,7 +135,8 @@ typedef struct {
 
 /* Fill *opt with defaults: dims 1, PD_FP64, alpha 1, maxit 64,
  * max_sweeps 16, check_residual 0, stream NULL, autotune 0, early_exit 0,
- * shifted_solver PD_SHIFTED_PARTITION, krylov PD_KRYLOV_GMRES, fom_q 1. */
+ * shifted_solver PD_SHIFTED_PARTITION, krylov PD_KRYLOV_GMRES, fom_q 1,
+ * bdf_order 1. */
 void paradiag_default_options(pd_options *opt);
 
 /* Create a plan for an n x ell problem with time step tau (Section 1).
@@ -148,6 +155,10 @@ pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double tau,
  * written to U [ell][nbar] (device float64, must not alias u0 or F).
  * tol: the capacitance GMRES stops at residual <= tol/100 * ||b||; PD_MIXED
  * refines until the float64 relative all-at-once residual is <= tol.
+ * BDF plans (bdf_order s > 1, Section 5): the system is
+ * (M + tau beta K) U - M U Sigma_s^T = G with G_t = M (sum_{j>t} alpha_j
+ * u_{t+1-j} + tau beta f_{t+1}); u0 is [s][nbar] (u_{1-s} first), and the
+ * capacitance GMRES runs on the s x s block system J^(s) x = b^(s).
  * info may be NULL.  Synchronises the plan's stream. */
 pd_status paradiag_solve(pd_plan plan, const double *u0, const double *F,
                          double *U, double tol, pd_info *info);
@@ -181,7 +192,8 @@ size_t paradiag_spectrum_bytes(pd_plan plan);
  * Sections 2 and 4) WITHOUT the mass matrix:
  * Hhat_k = sum_t alpha^(t/ell) h_t exp(-2 pi i t k / ell), k = 0..ell/2,
  * with h_0 = u0 + tau f_1 and h_t = tau f_{t+1}.  (M commutes with the
- * time transform and is applied inside the shifted solves.) */
+ * time transform and is applied inside the shifted solves.)  BDF plans:
+ * h_t = sum_{j=t+1}^{s} alpha_j u_{t+1-j} + tau beta f_{t+1}, u0 [s][nbar]. */
 pd_status paradiag_forward_transform(pd_plan plan, const double *u0,
                                      const double *F, void *Hhat);
 
@@ -192,7 +204,9 @@ pd_status paradiag_forward_transform(pd_plan plan, const double *u0,
  * If b != NULL, b = sum over the full spectrum k = 0..ell-1 of
  * gamma_k P_k^{-1} M Hhat_k (real, float64; x does not enter b), the
  * conjugate half being implied (Section 2, b = L F^{-T} e_ell).  At least one
- * of Uhat, b must be non-NULL. */
+ * of Uhat, b must be non-NULL.  BDF plans: P_k = (1 - pi_k) M + tau beta K
+ * with pi_k the eigenvalues of C_s; only Uhat with x = NULL (PD_ENOTSUP
+ * otherwise). */
 pd_status paradiag_shifted_solve(pd_plan plan, const void *Hhat,
                                  const double *x, void *Uhat, double *b);
 
@@ -204,12 +218,15 @@ pd_status paradiag_shifted_solve(pd_plan plan, const void *Hhat,
 pd_status paradiag_sine_transform(pd_plan plan, const double *in, double *out);
 
 /* One capacitance product Jv = v + w sum_k gamma_k P_k^{-1} M v
- * (eq. SMW_linearsystemII; eq. innersystem_alpha), v and Jv float64 [nbar]. */
+ * (eq. SMW_linearsystemII; eq. innersystem_alpha), v and Jv float64 [nbar].
+ * BDF plans: the block product J^(s) v (eq. linearsystem_s), block k =
+ * v_k + sum_h sum_i gamma_i^(k) theta_i^(h) P_i^{-1} M v_h with
+ * P_i = (1 - pi_i) M + tau beta K, v and Jv float64 [s][nbar]. */
 pd_status paradiag_capacitance_apply(pd_plan plan, const double *v,
                                      double *Jv);
 
-/* GMRES on J_ell x = b from x = 0 until residual <= rtol * ||b|| or the
- * plan's maxit.  iters and relres (may be NULL) receive the iteration count
+/* GMRES on J_ell x = b (BDF plans: J^(s), b and x [s][nbar]) from x = 0
+ * until residual <= rtol * ||b|| or the plan's maxit.  iters and relres (may be NULL) receive the iteration count
  * and final residual / ||b||.  Returns PD_ENOTCONV if rtol was not met.
  * Synchronises the plan's stream. */
 pd_status paradiag_capacitance_solve(pd_plan plan, const double *b,
@@ -224,7 +241,8 @@ pd_status paradiag_inverse_transform(pd_plan plan, const void *Uhat,
                                      double *U);
 
 /* Relative float64 residual ||G - A(U)||_F / ||G||_F of the all-at-once
- * system (Algorithm 3, residual test), written to *rel (host).
+ * system (Algorithm 3, residual test; BDF plans: eq. discrete_probBDF with
+ * u0 [s][nbar]), written to *rel (host).
  * Synchronises the plan's stream. */
 pd_status paradiag_residual(pd_plan plan, const double *u0, const double *F,
                             const double *U, double *rel);

@@ -146,7 +146,7 @@ def paradiag_bdf(Msp, Ksp, tau, s, U0, F, gamma_transposed=True):
                                .astype(np.complex128)) for i in range(ell)])
     U = np.fft.ifft(L - W, axis=0).real
     U1 = np.fft.ifft(L, axis=0).real
-    return dict(U=U, U1=U1, b=b, x=x, pi=pi)
+    return dict(U=U, U1=U1, b=b, x=x, pi=pi, J=J.real)
 
 
 def modal_bdf(p, s):

@@ -44,7 +44,8 @@ class pd_options(ctypes.Structure):
                 ("max_sweeps", ctypes.c_int), ("check_residual", ctypes.c_int),
                 ("stream", _vp), ("autotune", ctypes.c_int),
                 ("early_exit", ctypes.c_int), ("shifted_solver", ctypes.c_int),
-                ("krylov", ctypes.c_int), ("fom_q", ctypes.c_int)]
+                ("krylov", ctypes.c_int), ("fom_q", ctypes.c_int),
+                ("bdf_order", ctypes.c_int)]
 
 
 class pd_info(ctypes.Structure):
@@ -140,7 +141,7 @@ def paradiag_plan_create(n, ell, tau, M, K, options=None, **kw):
     """M, K: (lower, diag, upper) arrays or None for M = I.  Keyword
     arguments override fields of pd_options (dims, precision, alpha, maxit,
     max_sweeps, check_residual, stream, autotune, early_exit, shifted_solver, krylov,
-    fom_q)."""
+    fom_q, bdf_order)."""
     opt = options if options is not None else paradiag_default_options()
     for k, v in kw.items():
         if k == "stream" and v is not None and not isinstance(v, int):

@@ -30,7 +30,7 @@ bool batchable(const pd_plan *plans, int count) {
     const pd_plan p = plans[i];
     if (!p || p->dims != 1 || !p->uniform || p->prec != p0->prec || p->prec == PD_MIXED ||
         p->tri.block != pd_tri_block_threads(p->prec) ||
-        p->maxit != p0->maxit || p->early_exit || p->sine || p->krylov ||
+        p->maxit != p0->maxit || p->early_exit || p->sine || p->krylov || p->bdf_s > 1 ||
         !pd_gmres_fused_ok(p))
       return false;
     for (int j = 0; j < i; ++j)

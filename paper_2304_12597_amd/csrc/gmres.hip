@@ -394,7 +394,7 @@ gm_init_kernel(int n, const double *__restrict__ b, double *__restrict__ V,
 }
 
 void launch_gm_init(pd_plan p, const double *b) {
-  const int n = p->nbar;
+  const int n = p->ncap;
   if (n <= 4 * ARN_T)
     hipLaunchKernelGGL((gm_init_kernel<4>), dim3(1), dim3(ARN_T), 0, p->stream, n, b, p->V,
                        p->gm, p->maxit, p->host_dev);
@@ -407,7 +407,7 @@ void launch_gm_init(pd_plan p, const double *b) {
 }
 
 void launch_arnoldi(pd_plan p, int j, double rtol) {
-  const int n = p->nbar;
+  const int n = p->ncap;
   GmLayout L{p->maxit};
   (void)L;
   if (n <= 4 * ARN_T)
@@ -426,7 +426,7 @@ void launch_arnoldi(pd_plan p, int j, double rtol) {
 // converged flag.
 pd_status enqueue_iters(pd_plan p, int j0, int count, double rtol) {
   GmLayout L{p->maxit};
-  const int n = p->nbar;
+  const int n = p->ncap;
   p->gm_skip = p->gm + L.st(GM_DONE);
   pd_status s = PD_OK;
   for (int j = j0; j < j0 + count && j < p->maxit && s == PD_OK; ++j) {
@@ -445,7 +445,7 @@ pd_status enqueue_iters(pd_plan p, int j0, int count, double rtol) {
 // capacitance product's kernels read the flag through p->gm_skip).
 pd_status gmres_fused(pd_plan p, const double *b, double *x, double rtol, int *iters,
                       double *relres) {
-  const int n = p->nbar, MX = p->maxit;
+  const int n = p->ncap, MX = p->maxit;
   const int B = pd_vec_blocks(n);
   GmLayout L{MX};
   volatile double *st = p->host_pin;
@@ -505,13 +505,13 @@ pd_status gmres_fused(pd_plan p, const double *b, double *x, double rtol, int *i
 
 }  // namespace
 
-bool pd_gmres_fused_ok(pd_plan p) { return p->dims == 1 && p->nbar <= ARN_MAXN; }
+bool pd_gmres_fused_ok(pd_plan p) { return p->dims == 1 && p->ncap <= ARN_MAXN; }
 size_t pd_gmres_done_index(int maxit) { return (size_t)GmLayout{maxit}.st(GM_DONE); }
 
 // Speculative form: init, `count` iterations and x = V y with the iteration
 // count taken from the device status, all enqueued without synchronising.
 pd_status pd_gmres_enqueue(pd_plan p, const double *b, double *x, double rtol, int count) {
-  const int n = p->nbar, MX = p->maxit;
+  const int n = p->ncap, MX = p->maxit;
   const int B = pd_vec_blocks(n);
   launch_gm_init(p, b);
   PD_HIP_CHECK(hipGetLastError());
@@ -535,7 +535,7 @@ void pd_gmres_read(pd_plan p, int *m, double *res, double *beta, bool *done) {
 // Continues a speculative GMRES that had not converged (iterations from m on,
 // one synchronisation per chunk), then x = V y.  Returns the final status.
 pd_status pd_gmres_continue(pd_plan p, double *x, double rtol, int *iters, double *relres) {
-  const int n = p->nbar, MX = p->maxit;
+  const int n = p->ncap, MX = p->maxit;
   const int B = pd_vec_blocks(n);
   volatile double *st = p->host_pin;
   int j = (int)st[2], chunk = 2;
@@ -565,8 +565,8 @@ pd_status pd_gmres_continue(pd_plan p, double *x, double rtol, int *iters, doubl
 
 pd_status pd_gmres(pd_plan p, const double *b, double *x, double rtol, int *iters,
                    double *relres) {
-  if (p->dims == 1 && p->nbar <= ARN_MAXN) return gmres_fused(p, b, x, rtol, iters, relres);
-  const int n = p->nbar, MX = p->maxit;
+  if (p->dims == 1 && p->ncap <= ARN_MAXN) return gmres_fused(p, b, x, rtol, iters, relres);
+  const int n = p->ncap, MX = p->maxit;
   const int B = pd_vec_blocks(n);
   GmLayout L{MX};
   double *red1 = p->red, *red2 = p->red + (size_t)B * (MX + 2);

@@ -205,7 +205,7 @@ struct pd_plan_s {
   double *sine_k = nullptr;    // [n] eigenvalues of tau K on the sine modes
   int tri_G = 0;
   double *bvec = nullptr, *xvec = nullptr, *wvec = nullptr;
-  double *V = nullptr;         // [(maxit+1)][nbar] Krylov basis
+  double *V = nullptr;         // [(maxit+1)][ncap] Krylov basis
   double *gm = nullptr;        // GMRES small state (device)
   double *red = nullptr;       // reduction scratch
   int red_blocks = 0;
@@ -217,7 +217,15 @@ struct pd_plan_s {
   int fft_stride = 0;          // LDS column stride (complex elements)
   int dst_C = 1;               // 2D: row pairs per DST-I block
   double *twd = nullptr;       // 2D: exp(-2 pi i m / (2(n+1))) twiddles
-  double *wreal = nullptr;     // 2D: [ell][nbar] float64 work array (DST-x domain)
+  double *wreal = nullptr;     // 2D: [ell][nbar] float64 work array (DST-x domain);
+                               // BDF: the time-domain input of the transforms
+  // BDF of order s (Section 5); s = 1 is backward Euler and uses none of these
+  int bdf_s = 1;
+  double bdf_beta = 1.0;
+  double bdf_alpha[6] = {1, 0, 0, 0, 0, 0};   // alpha_1..alpha_s
+  int ncap = 0;                // capacitance vector length: s * nbar
+  double *wz = nullptr;        // BDF: [ell][nbar] inverse-transform output
+  int bdf_clean = 0;           // rows s..ell-1 of wreal hold zeros
 };
 
 // error reporting
@@ -277,6 +285,16 @@ bool pd_fom_supported(pd_plan p);
 pd_status pd_fom(pd_plan p, const double *b, double *x, double rtol, int *iters,
                  double *relres, int *checks);
 void pd_fom_mass_factors(pd_plan p, std::vector<double> &out);
+// BDF of order s > 1 (bdf.hip): h of eq. discrete_probBDF into out [ell][nbar];
+// the block capacitance product J^(s) v; the whole solve; the float64
+// residual norms ||G - A(U)||^2 and ||G||^2.
+pd_status pd_bdf_rhs(pd_plan p, const double *u0s, const double *F, double *out);
+pd_status pd_bdf_apply(pd_plan p, const double *v, double *Jv);
+pd_status pd_bdf_solve(pd_plan p, const double *u0s, const double *F, double *U, double tol,
+                       pd_info *info);
+pd_status pd_bdf_residual_norms(pd_plan p, const double *u0s, const double *F,
+                                const double *U, double *rn2, double *gn2);
+int pd_bdf_residual_blocks(pd_plan p);
 // sine-basis path (sine.hip)
 int pd_sine_dst_C(int n, int ell);
 size_t pd_sine_dst_lds(int n, int C);

@@ -44,6 +44,21 @@ void cis(long k, long N, double &c, double &s) {
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// BDF coefficients of order s <= 6 (Section 5, table of BDF coefficients):
+// u_n - sum_j alpha_j u_{n-j} = tau beta f_n, as exact fractions.
+void bdf_coefficients(int s, double *beta, double alpha[6]) {
+  static const int num[6][7] = {{1, 1},
+                                {2, 4, -1},
+                                {6, 18, -9, 2},
+                                {12, 48, -36, 16, -3},
+                                {60, 300, -300, 200, -75, 12},
+                                {60, 360, -450, 400, -225, 72, -10}};
+  static const int den[6] = {1, 3, 11, 25, 137, 147};
+  const int r = (s >= 1 && s <= 6) ? s - 1 : 0;
+  *beta = (double)num[r][0] / den[r];
+  for (int j = 0; j < 6; ++j) alpha[j] = (j <= r) ? (double)num[r][j + 1] / den[r] : 0.0;
+}
+
 template <typename T>
 pd_status dev_alloc(T **ptr, size_t count) {
   *ptr = nullptr;
@@ -69,7 +84,7 @@ void free_plan(pd_plan p) {
   void *ptrs[] = {p->coef64, p->coef32, p->lam64, p->lam32, p->gB64, p->gJ64, p->tw64,
                   p->tw32, p->dal, p->fac64, p->fac32, p->twd, p->wreal, p->spec, p->partials, p->rstage, p->bvec, p->xvec, p->wvec, p->V,
                   p->gm, p->red, p->sine_q, p->sine_wN, p->sine_twH, p->sine_m, p->sine_k,
-                  p->fom, p->fom_h};
+                  p->fom, p->fom_h, p->wz};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   if (p->host_pin) (void)hipHostFree(p->host_pin);
@@ -83,11 +98,12 @@ std::mutex g_attr_mu;
 // Launch configurations and device allocation sizes (in elements of their
 // type) of a plan; shared by plan creation and paradiag_plan_bytes.
 struct Layout {
-  size_t coef = 0, lam = 0, tw = 0, dal = 0, fac = 0, twd = 0, wreal = 0, sine = 0, fom = 0;
+  size_t coef = 0, lam = 0, tw = 0, dal = 0, fac = 0, twd = 0, wreal = 0, wz = 0, sine = 0,
+         fom = 0;
   size_t spec_bytes = 0, partials = 0, rstage = 0, vec = 0, V = 0, gm = 0, red = 0;
   size_t total_bytes() const {
     return coef * 12 + lam * 12 + 2 * lam * 8 + tw * 12 + dal * 8 + fac * 12 + twd * 8 +
-           wreal * 8 + spec_bytes + partials * 8 + rstage * 8 + 3 * vec * 8 + V * 8 + gm * 8 +
+           wreal * 8 + wz * 8 + spec_bytes + partials * 8 + rstage * 8 + 3 * vec * 8 + V * 8 + gm * 8 +
            red * 8 + sine * 8 + fom * 8 + (fom ? spec_bytes : 0);
   }
 };
@@ -151,21 +167,29 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
     L.sine = (size_t)N + 2 * (size_t)(H + 1) + 2 * (size_t)H + 2 * (size_t)n;
   }
   if (p->krylov == PD_KRYLOV_FOM) L.fom = pd_fom_doubles(n, F2);
+  if (p->bdf_s > 1) {
+    L.wreal = (size_t)ell * p->nbar;
+    L.wz = (size_t)ell * p->nbar;
+  }
   L.coef = 6 * (size_t)n;
   L.lam = 2 * (size_t)F2;
   L.tw = 2 * (size_t)ell;
   L.dal = 2 * (size_t)ell;
   L.spec_bytes = (size_t)F2 * p->nbar * cb;
-  L.vec = p->nbar;
-  L.V = (size_t)(p->maxit + 1) * p->nbar;
+  L.vec = p->ncap;
+  L.V = (size_t)(p->maxit + 1) * p->ncap;
   L.gm = pd_gmres_state_doubles(p->maxit);
-  const int B = pd_vec_blocks(p->nbar);
+  const int B = pd_vec_blocks(p->ncap);
   size_t red_n = 2 * (size_t)B * (p->maxit + 2);
   size_t fb = 2 * (size_t)pd_fft_blocks(p);
   if (p->autotune) fb = 2 * (size_t)((p->nbar + 1) / 2);   // any tile width down to C = 1
   if (fb > red_n) red_n = fb;
   size_t rb = 3 * (size_t)pd_residual_blocks(p);
   if (rb > red_n) red_n = rb;
+  if (p->bdf_s > 1) {
+    size_t bb = 2 * (size_t)pd_bdf_residual_blocks(p);
+    if (bb > red_n) red_n = bb;
+  }
   if (p->dims == 2) {
     size_t db = 2 * (size_t)pd_dst_blocks(p);
     if (db > red_n) red_n = db;
@@ -335,6 +359,7 @@ extern "C" void paradiag_default_options(pd_options *opt) {
   opt->shifted_solver = PD_SHIFTED_PARTITION;
   opt->krylov = PD_KRYLOV_GMRES;
   opt->fom_q = 1;
+  opt->bdf_order = 1;
 }
 
 extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double tau,
@@ -417,6 +442,18 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
     pd_set_error("unknown shifted_solver");
     return PD_EINVAL;
   }
+  if (opt.bdf_order < 1 || opt.bdf_order > 6) {
+    pd_set_error("bdf_order must lie in [1, 6]");
+    return PD_EINVAL;
+  }
+  if (opt.bdf_order > 1 &&
+      (opt.dims != 1 || opt.precision != PD_FP64 || opt.alpha != 1.0 ||
+       opt.krylov != PD_KRYLOV_GMRES || opt.shifted_solver != PD_SHIFTED_PARTITION ||
+       opt.early_exit != 0 || ell < 2 * opt.bdf_order)) {
+    pd_set_error("BDF plans of order > 1 need dims 1, PD_FP64, alpha 1, GMRES, partition "
+                 "solves, no early_exit and ell >= 2 * bdf_order");
+    return PD_ENOTSUP;
+  }
   if (opt.shifted_solver == PD_SHIFTED_SINE) {
     if (opt.dims != 1 || opt.precision != PD_FP64 || !is_pow2(n + 1) || n + 1 < 16) {
       pd_set_error("sine-basis solves need a 1D float64 plan with n + 1 a power of two >= 16");
@@ -470,6 +507,9 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   p->fom_q = opt.fom_q;
   p->stream = reinterpret_cast<hipStream_t>(opt.stream);
   p->mass_identity = (M == nullptr);
+  p->bdf_s = opt.bdf_order;
+  bdf_coefficients(p->bdf_s, &p->bdf_beta, p->bdf_alpha);
+  p->ncap = p->bdf_s * p->nbar;
   if (hipGetDevice(&p->device) != hipSuccess) {
     pd_set_error("no HIP device");
     free_plan(p);
@@ -496,15 +536,16 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   const size_t max_lds = g_max_lds;
   attr_lock.unlock();
 
-  // coefficients: ML MD MU (M or I), tau*K
+  // coefficients: ML MD MU (M or I), tau*K (BDF: tau beta K, Section 5)
+  const double tk = tau * p->bdf_beta;
   std::vector<double> coef(6 * (size_t)n, 0.0);
   for (int i = 0; i < n; ++i) {
     coef[i] = (M && i > 0) ? M->lower[i] : 0.0;
     coef[n + i] = M ? M->diag[i] : 1.0;
     coef[2 * n + i] = (M && i < n - 1) ? M->upper[i] : 0.0;
-    coef[3 * n + i] = (i > 0) ? tau * K->lower[i] : 0.0;
-    coef[4 * n + i] = tau * K->diag[i];
-    coef[5 * n + i] = (i < n - 1) ? tau * K->upper[i] : 0.0;
+    coef[3 * n + i] = (i > 0) ? tk * K->lower[i] : 0.0;
+    coef[4 * n + i] = tk * K->diag[i];
+    coef[5 * n + i] = (i < n - 1) ? tk * K->upper[i] : 0.0;
   }
   // alpha = 1: P_0 = tau K must be nonsingular (Section 2, the zero
   // frequency); check with an unpivoted elimination in float64.
@@ -552,6 +593,19 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
     p->gB[2 * k + 1] = weight * gi;
     p->gJ[2 * k] = p->w * weight * gr;
     p->gJ[2 * k + 1] = p->w * weight * gi;
+    if (p->bdf_s > 1) {
+      // pi_k = sum_j alpha_j exp(-2 pi i j k / ell), the eigenvalues of C_s
+      // (Section 5); pi_0 = sum_j alpha_j = 1 exactly (consistency)
+      double sr = 0.0, si = 0.0;
+      for (int j = 1; j <= p->bdf_s; ++j) {
+        double cj, sj;
+        cis((long)j * k, ell, cj, sj);
+        sr += p->bdf_alpha[j - 1] * cj;
+        si -= p->bdf_alpha[j - 1] * sj;
+      }
+      p->lam[2 * k] = (k == 0) ? 0.0 : 1.0 - sr;
+      p->lam[2 * k + 1] = (k == 0 || 2 * k == ell) ? 0.0 : -si;
+    }
   }
   std::vector<float> lam32(p->lam.begin(), p->lam.end());
   std::vector<double> tw(2 * (size_t)ell);
@@ -656,14 +710,15 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   PD_TRY(dev_alloc(&p->fac64, std::max(fac.size(), L.fac)));
   PD_TRY(dev_alloc(&p->fac32, std::max(fac32.size(), L.fac)));
   PD_TRY(dev_alloc(&p->twd, twd.size()));
-  if (p->dims == 2) PD_TRY(dev_alloc(&p->wreal, (size_t)ell * nbar));
+  if (p->dims == 2 || p->bdf_s > 1) PD_TRY(dev_alloc(&p->wreal, (size_t)ell * nbar));
+  if (p->bdf_s > 1) PD_TRY(dev_alloc(&p->wz, L.wz));
   PD_TRY(dev_alloc(reinterpret_cast<unsigned char **>(&p->spec), p->spec_bytes));
   PD_TRY(dev_alloc(&p->partials, L.partials));
   PD_TRY(dev_alloc(&p->rstage, L.rstage));
-  PD_TRY(dev_alloc(&p->bvec, nbar));
-  PD_TRY(dev_alloc(&p->xvec, nbar));
-  PD_TRY(dev_alloc(&p->wvec, nbar));
-  PD_TRY(dev_alloc(&p->V, (size_t)(p->maxit + 1) * nbar));
+  PD_TRY(dev_alloc(&p->bvec, L.vec));
+  PD_TRY(dev_alloc(&p->xvec, L.vec));
+  PD_TRY(dev_alloc(&p->wvec, L.vec));
+  PD_TRY(dev_alloc(&p->V, L.V));
   PD_TRY(dev_alloc(&p->gm, pd_gmres_state_doubles(p->maxit)));
   PD_TRY(dev_alloc(&p->red, L.red));
   if (p->krylov == PD_KRYLOV_FOM) {
@@ -773,6 +828,8 @@ extern "C" size_t paradiag_plan_bytes(int n, int ell, const pd_options *opt_in) 
   tmp.autotune = (opt.autotune != 0 && opt.dims == 1) ? 1 : 0;
   tmp.sine = opt.shifted_solver == PD_SHIFTED_SINE ? 1 : 0;
   tmp.krylov = opt.krylov;
+  tmp.bdf_s = (opt.bdf_order >= 1 && opt.bdf_order <= 6) ? opt.bdf_order : 1;
+  tmp.ncap = tmp.bdf_s * tmp.nbar;
   int dev = 0, cus = 256, lds = 65536;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);

@@ -215,6 +215,7 @@ extern "C" pd_status paradiag_solve(pd_plan p, const double *u0, const double *F
     info->early_exit = 0;
   }
   pd_status gst = PD_OK;
+  if (p->bdf_s > 1) return pd_bdf_solve(p, u0, F, U, tol, info);
   if (p->sine) return solve_sine(p, u0, F, U, info);
   pd_status st = pd_forward(p, u0, F, nullptr, p->spec, 0);
   if (st != PD_OK) return st;
@@ -327,6 +328,11 @@ extern "C" pd_status paradiag_forward_transform(pd_plan p, const double *u0, con
     return PD_EINVAL;
   }
   if (!check_ptrs(u0, F, Hhat)) return PD_EINVAL;
+  if (p->bdf_s > 1) {
+    pd_status st = pd_bdf_rhs(p, u0, F, p->wreal);
+    if (st != PD_OK) return st;
+    return pd_launch_fft_forward(p, nullptr, p->wreal, nullptr, Hhat, 2);
+  }
   return pd_forward(p, u0, F, nullptr, Hhat, 0);
 }
 
@@ -335,6 +341,10 @@ extern "C" pd_status paradiag_shifted_solve(pd_plan p, const void *Hhat, const d
   if (!p || !Hhat || (!Uhat && !b)) {
     pd_set_error("invalid shifted-solve arguments");
     return PD_EINVAL;
+  }
+  if (p->bdf_s > 1 && (b || x)) {
+    pd_set_error("BDF plans: the shifted solves take x = NULL and produce Uhat only");
+    return PD_ENOTSUP;
   }
   pd_status st;
   if (b) {
@@ -386,6 +396,13 @@ extern "C" pd_status paradiag_residual(pd_plan p, const double *u0, const double
     return PD_EINVAL;
   }
   if (!check_ptrs(u0, F, U)) return PD_EINVAL;
+  if (p->bdf_s > 1) {
+    double rn2, gn2;
+    pd_status st = pd_bdf_residual_norms(p, u0, F, U, &rn2, &gn2);
+    if (st != PD_OK) return st;
+    *rel = gn2 > 0.0 ? std::sqrt(rn2 / gn2) : std::sqrt(rn2);
+    return PD_OK;
+  }
   return pd_residual_impl(p, u0, F, U, rel);
 }
 

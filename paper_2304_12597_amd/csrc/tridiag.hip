@@ -1061,6 +1061,7 @@ pd_status pd_launch_reduce_partials(pd_plan p, const double *base, double *out) 
 }
 
 pd_status pd_capacitance_apply_impl(pd_plan p, const double *v, double *Jv) {
+  if (p->bdf_s > 1) return pd_bdf_apply(p, v, Jv);
   pd_status st = pd_launch_tridiag(p, 2, v, nullptr, nullptr);
   if (st != PD_OK) return st;
   return pd_launch_reduce_partials(p, v, Jv);
