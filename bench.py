@@ -35,7 +35,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="fem1d",
-                    choices=["fem1d", "ensemble", "serve", "alpha", "fom"])
+                    choices=["fem1d", "ensemble", "serve", "alpha", "fom", "bdf"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--count", type=int, default=0, help="ensemble / stream size")
@@ -78,6 +78,9 @@ def main():
         return
     if args.workload == "fom":
         print(json.dumps(bench_fom(args, torch, pd, wl, dev)))
+        return
+    if args.workload == "bdf":
+        print(json.dumps(bench_bdf(args, torch, pd, wl, dev)))
         return
     stream = torch.cuda.current_stream(dev)
     prob = wl.cfg_fem_1d()
@@ -484,6 +487,73 @@ def bench_fom(args, torch, pd, wl, dev):
             ii = rng.integers(0, p.nbar, 4000)
             ref = modal.modal_sample(p, tt, ii)
             r["rel_err_vs_exact"] = float(np.linalg.norm(U[tt, ii] - ref) / np.linalg.norm(ref))
+    return out
+
+
+def bench_bdf(args, torch, pd, wl, dev):
+    """BDF of order s = 1..6 (Section 5) on the n = 8191, ell = 2048 P1-FEM
+    workload, every starting value equal to u0: whole solves, the block
+    capacitance product alone, and (cpu_baseline leg) the error against the
+    per-mode BDF recurrence and the oracle's sequential stepping on a
+    bounded number of steps."""
+    stream = torch.cuda.current_stream(dev)
+    p = wl.cfg_fem_1d()
+    tol = 1e-8
+    F = torch.tensor(p.F, device=dev)
+    U = torch.empty((p.ell, p.nbar), dtype=torch.float64, device=dev)
+    rows, Us = [], {}
+    for s in range(1, 7):
+        u0s = torch.tensor(np.tile(p.u0, (s, 1)), device=dev)
+        plan = pd.paradiag_plan_create(p.n, p.ell, p.tau, p.M, p.K, bdf_order=s,
+                                       stream=stream.cuda_stream)
+        try:
+            for _ in range(args.warmup):
+                pd.paradiag_solve(plan, u0s, F, U, tol)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                info = pd.paradiag_solve(plan, u0s, F, U, tol)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / args.steps
+            v = torch.randn(s * p.nbar, dtype=torch.float64, device=dev)
+            Jv = torch.empty_like(v)
+            pd.paradiag_capacitance_apply(plan, v, Jv)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.kernel_reps):
+                pd.paradiag_capacitance_apply(plan, v, Jv)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            rows.append({"s": s, "ms": 1e3 * wall, "gmres_iters": info.gmres_iters,
+                         "pint_loops": info.pint_loops,
+                         "unknowns_per_s": p.nbar * p.ell / wall,
+                         "capacitance_product_ms": e0.elapsed_time(e1) / args.kernel_reps,
+                         "capacitance_rel_residual": info.gmres_rel_residual})
+            Us[s] = U.cpu().numpy()
+        finally:
+            pd.paradiag_plan_destroy(plan)
+    out = {"metric": "BDF-s ParaDiag solves (Section 5)", "value": None,
+           "unit": "ms per solve", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "heat1d-fem n=8191 ell=2048 T=1 nu=1 (16-mode source), "
+                                  "u_{1-s} = ... = u_0 = u0", "tol": tol},
+           "rows": rows}
+    if not args.no_cpu_baseline:
+        from oracle import bdf
+        from oracle.spatial import problem_matrices
+        Msp, Ksp = problem_matrices(p)
+        for r in rows:
+            ref = bdf.modal_bdf(p, r["s"])
+            r["rel_err_vs_exact"] = float(np.linalg.norm(Us[r["s"]] - ref) / np.linalg.norm(ref))
+        steps = 256
+        t0 = time.perf_counter()
+        Ucpu = bdf.step_bdf(Msp, Ksp, p.tau, 2, [p.u0] * 2, p.F[:steps])
+        sec = time.perf_counter() - t0
+        assert np.allclose(Ucpu, Us[2][:steps], rtol=0, atol=1e-9 * np.abs(Ucpu).max())
+        out["cpu_baseline"] = {"value": p.nbar * steps / sec, "unit": "unknowns/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": "BDF2 sequential stepping (sparse LU), first %d of "
+                                         "%d steps" % (steps, p.ell)}
     return out
 
 
