@@ -19,7 +19,11 @@ sum_i gamma_i^(k) P_i^{-1} Ghat_i, and U = (L - W) F^{-T} with
 W e_i = P_i^{-1} M sum_h theta_i^(h) x_h.  The transposes on A_s follow from
 N = F^{-T}[e_{ell-s+1}..e_ell] A_s^T (the printed definition of gamma^(i)
 uses A_s e_i; the transposed form is the one that reproduces the dense
-solution, see the pins).  Arrays are time-major; FFTs run along axis 0."""
+solution, see the pins).  The capacitance system is solved densely or by
+the block Galerkin method of the Proposition (``block_galerkin``), whose
+block matrices are (s sm) x (s sm) with s x s blocks of size sm (the
+printed R^{ms x ms} is read that way).  Arrays are time-major; FFTs run
+along axis 0."""
 from __future__ import annotations
 
 from fractions import Fraction as Fr
@@ -114,13 +118,13 @@ def solve_dense_bdf(Msp, Ksp, tau, s, U0, F):
     return np.linalg.solve(A, rhs_bdf(Msp, tau, s, U0, F).reshape(-1)).reshape(ell, nbar)
 
 
-def paradiag_bdf(Msp, Ksp, tau, s, U0, F, gamma_transposed=True):
-    """ParaDiag for BDF-s following Section 5, with a dense solve of the
-    s*nbar capacitance system (tiny sizes).  Returns U and the pieces."""
-    beta, _ = coefficients(s)
+def _pieces(Msp, Ksp, tau, s, U0, F, gamma_transposed=True):
+    """pi, theta^(h), gamma^(k), the LU of every P_i, L = P^{-1} Ghat and
+    b^(s) (Section 5)."""
+    beta, alpha = coefficients(s)
     ell, nbar = F.shape
     c = np.zeros(ell)
-    c[1:s + 1] = coefficients(s)[1]
+    c[1:s + 1] = alpha
     pi = np.fft.fft(c)                                   # F C_s e_1
     theta = [np.fft.fft(np.eye(ell)[h]) for h in range(s)]   # F e_h
     A = alpha_block(s)
@@ -134,6 +138,17 @@ def paradiag_bdf(Msp, Ksp, tau, s, U0, F, gamma_transposed=True):
     Ghat = np.fft.fft(G, axis=0)
     L = np.array([lus[i].solve(Ghat[i].astype(np.complex128)) for i in range(ell)])
     b = np.concatenate([(gamma[k][:, None] * L).sum(axis=0) for k in range(s)]).real
+    return dict(pi=pi, theta=theta, gamma=gamma, lus=lus, L=L, b=b, beta=beta)
+
+
+def paradiag_bdf(Msp, Ksp, tau, s, U0, F, gamma_transposed=True, capacitance="dense",
+                 eps=1e-12, maxit=40):
+    """ParaDiag for BDF-s following Section 5.  capacitance: "dense" solves
+    the s*nbar capacitance system by dense LU (tiny sizes), "galerkin" by
+    the block Galerkin method of the Proposition (``block_galerkin``)."""
+    ell, nbar = F.shape
+    P = _pieces(Msp, Ksp, tau, s, U0, F, gamma_transposed)
+    pi, theta, gamma, lus, L, b = (P[k] for k in ("pi", "theta", "gamma", "lus", "L", "b"))
     Md = Msp.toarray().astype(np.complex128)
     PM = [lus[i].solve(Md) for i in range(ell)]
     J = np.eye(s * nbar, dtype=np.complex128)
@@ -141,12 +156,87 @@ def paradiag_bdf(Msp, Ksp, tau, s, U0, F, gamma_transposed=True):
         for h in range(s):
             blk = sum(gamma[k][i] * theta[h][i] * PM[i] for i in range(ell))
             J[k * nbar:(k + 1) * nbar, h * nbar:(h + 1) * nbar] += blk
-    x = np.linalg.solve(J, b).real.reshape(s, nbar)
+    extra = {}
+    if capacitance == "galerkin":
+        x, m, hist = block_galerkin(Msp, Ksp, tau, s, P, eps=eps, maxit=maxit)
+        x = x.reshape(s, nbar)
+        extra = dict(steps=m, history=hist)
+    else:
+        x = np.linalg.solve(J, b).real.reshape(s, nbar)
     W = np.array([lus[i].solve((Msp @ sum(theta[h][i] * x[h] for h in range(s)))
                                .astype(np.complex128)) for i in range(ell)])
     U = np.fft.ifft(L - W, axis=0).real
     U1 = np.fft.ifft(L, axis=0).real
-    return dict(U=U, U1=U1, b=b, x=x, pi=pi, J=J.real)
+    return dict(U=U, U1=U1, b=b, x=x, pi=pi, J=J.real, **extra)
+
+
+def block_galerkin(Msp, Ksp, tau, s, pieces, eps=1e-12, maxit=40):
+    """The block Galerkin method of Section 5 (Proposition) for
+    J^(s) x = b^(s): block Arnoldi on A with the starting block
+    B^(s) = [b_1 .. b_s] = V_1 beta (QR), x_k = V_m y_k, y from
+    (I + T_m) y = (e_1 (x) I_s) beta with the (k, h) blocks
+    sum_i gamma_i^(k) theta_i^(h) (S_i - V_m^T H_i t_{m+1,m} E_m^T S_i),
+    S_i = ((1 - pi_i) I + T_m)^{-1}, H_i = P_i^{-1} M V_{m+1}, and the
+    residual norm ||(I - I_s (x) V_m V_m^T) S_m y|| of the Proposition.
+    With a mass matrix the Krylov operator is A = tau beta M^{-1} K
+    (P_i^{-1} M = ((1 - pi_i) I + A)^{-1}; for M = I the paper's tau beta K
+    with tau beta taken into T_m).  Returns (x, m, residual history)."""
+    pi, theta, gamma, lus, b, beta = (pieces[k] for k in
+                                      ("pi", "theta", "gamma", "lus", "b", "beta"))
+    ell = len(pi)
+    nbar = b.size // s
+    Mlu = spla.splu(Msp.tocsc())
+
+    def apply_A(W):
+        return Mlu.solve(tau * beta * np.asarray(Ksp @ W))
+
+    B = b.reshape(s, nbar).T                     # column k = b_k
+    V1, bet = np.linalg.qr(B)
+    Vs = [V1]
+    T = np.zeros((s * (maxit + 1), s * maxit))
+    coef = [[gamma[k] * theta[h] for h in range(s)] for k in range(s)]
+    nb = np.linalg.norm(b)
+    hist = []
+    x = np.zeros(s * nbar)
+    for m in range(1, maxit + 1):
+        W = apply_A(Vs[-1])
+        col = slice((m - 1) * s, m * s)
+        for _ in range(2):                        # block classical Gram-Schmidt, twice
+            for j, Vj in enumerate(Vs):
+                h = Vj.T @ W
+                T[j * s:(j + 1) * s, col] += h
+                W = W - Vj @ h
+        Q, R = np.linalg.qr(W)
+        T[m * s:(m + 1) * s, col] = R
+        Vm = np.hstack(Vs)
+        Tm = T[:s * m, :s * m]
+        sm = s * m
+        H = [lus[i].solve(np.asarray(Msp @ Q).astype(np.complex128)) for i in range(ell)]
+        S = [np.linalg.inv((1.0 - pi[i]) * np.eye(sm) + Tm) for i in range(ell)]
+        ES = [R @ Si[-s:, :] for Si in S]          # t_{m+1,m} E_m^T S_i
+        Tbig = np.eye(s * sm, dtype=np.complex128)
+        Sbig = [[None] * s for _ in range(s)]
+        for k in range(s):
+            for h in range(s):
+                Ssum = sum(coef[k][h][i] * (H[i] @ ES[i]) for i in range(ell))
+                Sbig[k][h] = Ssum                   # nbar x sm
+                Tsum = sum(coef[k][h][i] * S[i] for i in range(ell)) - Vm.T @ Ssum
+                Tbig[k * sm:(k + 1) * sm, h * sm:(h + 1) * sm] += Tsum
+        rhs = np.zeros(s * sm)
+        for k in range(s):
+            rhs[k * sm:k * sm + s] = bet[:, k]
+        y = np.linalg.solve(Tbig, rhs).real
+        res2 = 0.0
+        for k in range(s):
+            z = sum(Sbig[k][h] @ y[h * sm:(h + 1) * sm] for h in range(s)).real
+            r = z - Vm @ (Vm.T @ z)
+            res2 += float(r @ r)
+        hist.append(np.sqrt(res2))
+        x = np.concatenate([Vm @ y[k * sm:(k + 1) * sm] for k in range(s)])
+        if hist[-1] <= eps * nb or sm + s > nbar:
+            return x, m, hist
+        Vs.append(Q)
+    return x, maxit, hist
 
 
 def modal_bdf(p, s):

@@ -1,8 +1,10 @@
 """Pins of the BDF-s oracle (Section 5) against what the mathematics fixes:
 the order conditions of the coefficient table, the circulant-plus-rank-s
 split of Sigma_s, dense LU of the all-at-once matrix, the scalar recurrence
-per sine mode, the convergence order on an ODE with a known solution, and
-backward Euler at s = 1."""
+per sine mode, the convergence order on an ODE with a known solution,
+backward Euler at s = 1, and, for the block Galerkin method of the
+Proposition, its residual formula against the true residual, exactness on
+the full space and Algorithm 2 at s = 1."""
 from fractions import Fraction as Fr
 
 import numpy as np
@@ -174,3 +176,50 @@ def test_pins_catch_planted_mistakes(monkeypatch):
     Dbad = bdf.solve_dense_bdf(Msp, Ksp, tau, 3, U0, F)
     monkeypatch.setattr(bdf, "rhs_bdf", good_rhs)
     assert allatonce.rel_err(bdf.step_bdf(Msp, Ksp, tau, 3, U0, F), Dbad) > 1e-6
+
+
+# --------------------------------------------- block Galerkin (Proposition) --
+
+def _block_case(kind, n, s, seed, ell=16):
+    Msp, Ksp, tau, U0, F = _problem(kind, n, ell, s, seed)
+    P = bdf._pieces(Msp, Ksp, tau, s, U0, F)
+    J = bdf.paradiag_bdf(Msp, Ksp, tau, s, U0, F)["J"]
+    return Msp, Ksp, tau, U0, F, P, J
+
+
+@pytest.mark.parametrize("kind", ["fd1", "fem1"])
+@pytest.mark.parametrize("s", [2, 3])
+def test_block_galerkin_residual_formula(kind, s):
+    """||(I - I_s (x) V_m V_m^T) S_m y|| of the Proposition is the true
+    residual ||J^(s) x_m - b^(s)|| at every m."""
+    Msp, Ksp, tau, U0, F, P, J = _block_case(kind, 12, s, 40 + s)
+    b = P["b"]
+    for m in range(1, 12 // s):
+        x, mm, hist = bdf.block_galerkin(Msp, Ksp, tau, s, P, eps=0.0, maxit=m)
+        assert mm == m
+        true = np.linalg.norm(J @ x - b)
+        assert abs(hist[-1] - true) <= 1e-8 * true + 1e-15 * np.linalg.norm(b), (m, hist[-1], true)
+
+
+@pytest.mark.parametrize("kind", ["fd1", "fem1"])
+@pytest.mark.parametrize("s", [2, 3, 4, 6])
+def test_block_galerkin_full_space_is_exact(kind, s):
+    """Once the block Krylov space is all of R^nbar (m s = nbar) the Galerkin
+    solution is the solution, and U solves the all-at-once system."""
+    Msp, Ksp, tau, U0, F, P, J = _block_case(kind, 12, s, 50 + s)
+    out = bdf.paradiag_bdf(Msp, Ksp, tau, s, U0, F, capacitance="galerkin", eps=1e-14)
+    assert out["steps"] <= 12 // s
+    D = bdf.solve_dense_bdf(Msp, Ksp, tau, s, U0, F)
+    assert allatonce.rel_err(out["U"], D) < 1e-12
+
+
+def test_block_galerkin_s1_is_algorithm2():
+    """At s = 1 the block method is Algorithm 2: the same iterate x_m at
+    every m (alpha = 1, where gamma^(1) is the backward-Euler gamma)."""
+    Msp, Ksp, tau, U0, F, P, J = _block_case("fem1", 12, 1, 3)
+    cap = paradiag.Capacitance(Msp, Ksp, tau, F.shape[0])
+    for m in range(1, 6):
+        xb, _, _ = bdf.block_galerkin(Msp, Ksp, tau, 1, P, eps=0.0, maxit=m)
+        xf, mf, _ = paradiag.fom(cap, Msp, Ksp, tau, P["b"], eps=0.0, maxit=m)
+        assert mf == m
+        assert np.linalg.norm(xb - xf) <= 1e-10 * np.linalg.norm(xf)
