@@ -532,12 +532,40 @@ def bench_bdf(args, torch, pd, wl, dev):
             Us[s] = U.cpu().numpy()
         finally:
             pd.paradiag_plan_destroy(plan)
+    # the block Galerkin method of Section 5 for J^(s) on the same workload
+    # (stiff: its polynomial space needs many steps) and on a problem where
+    # J^(s) is close to I
+    grows = []
+    mild = wl.heat_1d("fem1", 4095, 16, 10.0, 1.0, np.random.default_rng(4111), True)
+    for prob, name in ((p, "n=8191 ell=2048 T=1"), (mild, "n=4095 ell=16 T=10")):
+        Fp = torch.tensor(prob.F, device=dev)
+        Up = torch.empty((prob.ell, prob.nbar), dtype=torch.float64, device=dev)
+        for s, q in ((2, 1), (2, 4), (3, 4)):
+            u0s = torch.tensor(np.tile(prob.u0, (s, 1)), device=dev)
+            plan = pd.paradiag_plan_create(prob.n, prob.ell, prob.tau, prob.M, prob.K,
+                                           bdf_order=s, krylov=pd.PD_KRYLOV_FOM, fom_q=q,
+                                           stream=stream.cuda_stream)
+            try:
+                for _ in range(args.warmup):
+                    pd.paradiag_solve(plan, u0s, Fp, Up, tol, allow_notconv=True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    info = pd.paradiag_solve(plan, u0s, Fp, Up, tol, allow_notconv=True)
+                torch.cuda.synchronize()
+                wall = (time.perf_counter() - t0) / args.steps
+                grows.append({"problem": "fem1 " + name, "s": s, "q": q, "ms": 1e3 * wall,
+                              "block_steps": info.gmres_iters, "pint_loops": info.pint_loops,
+                              "capacitance_rel_residual": info.gmres_rel_residual,
+                              "_U": Up.cpu().numpy(), "_p": prob})
+            finally:
+                pd.paradiag_plan_destroy(plan)
     out = {"metric": "BDF-s ParaDiag solves (Section 5)", "value": None,
            "unit": "ms per solve", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "higher_is_better": False, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "heat1d-fem n=8191 ell=2048 T=1 nu=1 (16-mode source), "
                                   "u_{1-s} = ... = u_0 = u0", "tol": tol},
-           "rows": rows}
+           "rows": rows, "block_galerkin_rows": grows}
     if not args.no_cpu_baseline:
         from oracle import bdf
         from oracle.spatial import problem_matrices
@@ -545,6 +573,9 @@ def bench_bdf(args, torch, pd, wl, dev):
         for r in rows:
             ref = bdf.modal_bdf(p, r["s"])
             r["rel_err_vs_exact"] = float(np.linalg.norm(Us[r["s"]] - ref) / np.linalg.norm(ref))
+        for r in grows:
+            ref = bdf.modal_bdf(r["_p"], r["s"])
+            r["rel_err_vs_exact"] = float(np.linalg.norm(r["_U"] - ref) / np.linalg.norm(ref))
         steps = 256
         t0 = time.perf_counter()
         Ucpu = bdf.step_bdf(Msp, Ksp, p.tau, 2, [p.u0] * 2, p.F[:steps])
@@ -554,6 +585,8 @@ def bench_bdf(args, torch, pd, wl, dev):
                                "cores": 1, "kind": "oracle",
                                "sample": "BDF2 sequential stepping (sparse LU), first %d of "
                                          "%d steps" % (steps, p.ell)}
+    for r in grows:
+        del r["_U"], r["_p"]
     return out
 
 

@@ -114,12 +114,14 @@ typedef struct {
                        /* solve; 0 = always correct                         */
   int shifted_solver;  /* pd_shifted_solver                                 */
   int krylov;          /* pd_krylov (ignored by PD_SHIFTED_SINE plans, whose */
-                       /* capacitance system is solved exactly)             */
+                       /* capacitance system is solved exactly); BDF plans: */
+                       /* PD_KRYLOV_FOM selects the block Galerkin method   */
+                       /* of Section 5 (basis dimension s m <= 32)          */
   int fom_q;           /* PD_KRYLOV_FOM: residual check every fom_q steps   */
   int bdf_order;       /* s = 1..6: BDF of order s in time (Section 5,      */
                        /* table of BDF coefficients); 1 = backward Euler.   */
-                       /* s > 1: 1D, PD_FP64, alpha 1, GMRES, partition     */
-                       /* solves, no early_exit, ell >= 2 s; u0 holds the   */
+                       /* s > 1: 1D, PD_FP64, alpha 1, partition solves,   */
+                       /* no early_exit, ell >= 2 s; u0 holds the           */
                        /* s starting values u_{1-s}..u_0 as [s][nbar] and   */
                        /* capacitance vectors are [s][nbar]                 */
 } pd_options;

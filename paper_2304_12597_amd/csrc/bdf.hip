@@ -21,7 +21,8 @@
 //     the array holding v_h in time row h-1 and zeros elsewhere;
 //   U = U_1 - Y(X(x)) with x the solution of J^(s) x = b^(s).
 // One capacitance product is one parfor of shifted solves between a forward
-// and an inverse transform; #PinT = GMRES iterations + 2 as for s = 1.
+// and an inverse transform; #PinT = GMRES iterations + 2 as for s = 1 (the
+// block Galerkin method of bgal.hip: residual checks + 2).
 #include "pd_internal.h"
 
 #include <algorithm>
@@ -256,7 +257,8 @@ pd_status pd_bdf_residual_norms(pd_plan p, const double *u0s, const double *F,
   return PD_OK;
 }
 
-// The whole BDF solve: h, U_1 = Y(h) into U, b^(s), GMRES on J^(s),
+// The whole BDF solve: h, U_1 = Y(h) into U, b^(s), J^(s) x = b^(s) by
+// GMRES or by the block Galerkin method (krylov = PD_KRYLOV_FOM),
 // U -= Y(X(x)).
 pd_status pd_bdf_solve(pd_plan p, const double *u0s, const double *F, double *U, double tol,
                        pd_info *info) {
@@ -267,9 +269,12 @@ pd_status pd_bdf_solve(pd_plan p, const double *u0s, const double *F, double *U,
   if (st != PD_OK) return st;
   st = extract(p, nullptr, U, p->bvec);
   if (st != PD_OK) return st;
-  int its = 0;
+  int its = 0, checks = 0;
   double rr = 0.0;
-  const pd_status gst = pd_gmres(p, p->bvec, p->xvec, tol * PD_GMRES_TOL_FACTOR, &its, &rr);
+  const pd_status gst =
+      p->krylov == PD_KRYLOV_FOM
+          ? pd_bgal(p, p->bvec, p->xvec, tol * PD_GMRES_TOL_FACTOR, &its, &rr, &checks)
+          : pd_gmres(p, p->bvec, p->xvec, tol * PD_GMRES_TOL_FACTOR, &its, &rr);
   if (gst != PD_OK && gst != PD_ENOTCONV) return gst;
   st = place(p, p->xvec, -1.0);
   if (st != PD_OK) return st;
@@ -277,7 +282,7 @@ pd_status pd_bdf_solve(pd_plan p, const double *u0s, const double *F, double *U,
   if (st != PD_OK) return st;
   if (info) {
     info->gmres_iters = its;
-    info->pint_loops = its + 2;
+    info->pint_loops = (p->krylov == PD_KRYLOV_FOM ? checks : its) + 2;
     info->sweeps = 1;
     info->gmres_rel_residual = rr;
   }

@@ -1,0 +1,557 @@
+// The block Galerkin method for the BDF capacitance system J^(s) x = b^(s)
+// (Section 5, Proposition), on the GPU.
+//
+// Block Arnoldi on A = tau beta M^{-1} K (P_i^{-1} M = (nu_i I + A)^{-1},
+// nu_i = 1 - pi_i; for M = I the paper's tau beta K) from the starting block
+// B = [b_1 .. b_s] = V_1 beta, column by column: the j-th column of the new
+// block is A applied to column j of the current block, orthogonalised
+// against every basis vector so far (two classical Gram-Schmidt passes), so
+// that A V_m = V_m T_m + V_{m+1} t_{m+1,m} E_m^T with t_{m+1,m} upper
+// triangular.  x_k = V_m y_k with y from (I + T) y = (e_1 (x) I_s) beta,
+//   T_{k,h} = sum_i gamma_i^(k) theta_i^(h) E_i,
+//   E_i = S_i - V_m^T H_i t_{m+1,m} E_m^T S_i,
+//   S_i = (nu_i I + T_m)^{-1},  H_i = P_i^{-1} M V_{m+1},
+// and the residual norm of the Proposition,
+//   ||r||^2 = sum_k ||(I - V_m V_m^T) sum_i gamma_i^(k) H_i t_{m+1,m}
+//             E_m^T S_i sum_h theta_i^(h) y_h||^2.
+// The sums over the full spectrum use its conjugate halves (weights 1 at
+// i = 0 and ell/2, 2 elsewhere, real part).  Each check is one parfor of
+// shifted solves with s right-hand sides per frequency (s launches of the
+// pass-C kernel on a zero spectrum, which writes -h).  The basis dimension
+// s m is at most BG_SMAX.
+#include "pd_internal.h"
+
+#include <cmath>
+#include <vector>
+
+namespace {
+
+constexpr int FB = 512;          // single-block kernels
+constexpr int FR = 16;           // rows per thread of the single-block kernels
+constexpr int CAP = 40;          // basis vectors an orthogonalisation handles (>= SMAX + 5)
+constexpr int NCH = 16;          // frequency chunks of the Galerkin-matrix sums
+constexpr int SMX = BG_SMAX;
+constexpr int NMAX = 6 * SMX;    // largest Galerkin system
+using Cx = cpx<double>;
+
+__device__ double block_sum(double v, double *red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += red[q];
+  return s;
+}
+
+// Two classical Gram-Schmidt passes of w against V rows 0..cnt-1:
+// T[k*ldT + col] += dots (k < cnt), T[cnt*ldT + col] = ||w'||, V row cnt =
+// w' / ||w'|| (0 if w' = 0).  cnt < CAP.
+__global__ void __launch_bounds__(FB)
+bg_orth_kernel(int n, int cnt, int col, int ldT, double *__restrict__ V,
+               const double *__restrict__ wsrc, double *__restrict__ T) {
+  __shared__ double red[FB / 64];
+  __shared__ double part[CAP][FB / 64];
+  __shared__ double dots[CAP];
+  const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63, nw = FB / 64;
+  double wv[FR];
+#pragma unroll
+  for (int r = 0; r < FR; ++r) {
+    const int i = tid + r * FB;
+    wv[r] = i < n ? wsrc[i] : 0.0;
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int k = 0; k < cnt; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int r = 0; r < FR; ++r) {
+        const int i = tid + r * FB;
+        if (i < n) s += V[(size_t)k * n + i] * wv[r];
+      }
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+      if (lane == 0) part[k][wid] = s;
+    }
+    __syncthreads();
+    if (tid < cnt) {
+      double s = 0.0;
+      for (int q = 0; q < nw; ++q) s += part[tid][q];
+      dots[tid] = s;
+      T[(size_t)tid * ldT + col] += s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < FR; ++r) {
+      const int i = tid + r * FB;
+      if (i < n)
+        for (int k = 0; k < cnt; ++k) wv[r] -= dots[k] * V[(size_t)k * n + i];
+    }
+    __syncthreads();
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int r = 0; r < FR; ++r) s += wv[r] * wv[r];
+  const double t = sqrt(block_sum(s, red));
+  if (tid == 0) T[(size_t)cnt * ldT + col] = t;
+#pragma unroll
+  for (int r = 0; r < FR; ++r) {
+    const int i = tid + r * FB;
+    if (i < n) V[(size_t)cnt * n + i] = t > 0.0 ? wv[r] / t : 0.0;
+  }
+}
+
+// proj[i][k][j] = (V_k . h_i^(j)) for k < sm, j < s; one block per
+// frequency.  hs_j holds -h^(j) (pass C on a zero spectrum), spectra
+// `sstride` complex elements apart.
+__global__ void __launch_bounds__(256)
+bg_proj_kernel(int n, int sm, int s, const Cx *__restrict__ hs, size_t sstride,
+               const double *__restrict__ V, Cx *__restrict__ proj) {
+  __shared__ double pr[SMX][4], pim[SMX][4];
+  const int i = blockIdx.x, tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+  for (int j = 0; j < s; ++j) {
+    const Cx *h = hs + j * sstride + (size_t)i * n;
+    double ar[SMX], ai[SMX];
+#pragma unroll
+    for (int k = 0; k < SMX; ++k) { ar[k] = 0.0; ai[k] = 0.0; }
+    for (int row = tid; row < n; row += 256) {
+      const Cx hv = h[row];
+#pragma unroll
+      for (int k = 0; k < SMX; ++k)
+        if (k < sm) {
+          const double vk = V[(size_t)k * n + row];
+          ar[k] += vk * hv.re;
+          ai[k] += vk * hv.im;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < SMX; ++k) {
+      if (k < sm) {
+        double a = ar[k], b = ai[k];
+        for (int off = 32; off > 0; off >>= 1) {
+          a += __shfl_xor(a, off, 64);
+          b += __shfl_xor(b, off, 64);
+        }
+        if (lane == 0) { pr[k][wid] = a; pim[k][wid] = b; }
+      }
+    }
+    __syncthreads();
+    if (tid < sm) {
+      double a = 0.0, b = 0.0;
+      for (int q = 0; q < 4; ++q) { a += pr[tid][q]; b += pim[tid][q]; }
+      proj[((size_t)i * SMX + tid) * 6 + j] = Cx{-a, -b};
+    }
+    __syncthreads();
+  }
+}
+
+// One thread per frequency i: S_i = (nu_i I + T_m)^{-1} by Gauss-Jordan with
+// partial pivoting in the thread's scratch [sm][2 sm]; L_i = the last s rows
+// of S_i (E_m^T S_i); E_i = S_i - proj_i t_{m+1,m} L_i.
+__global__ void __launch_bounds__(64)
+bg_small_kernel(int F2, int sm, int s, int m, const double *__restrict__ lam,
+                const double *__restrict__ T, int ldT, const Cx *__restrict__ proj,
+                Cx *__restrict__ scratch, Cx *__restrict__ E, Cx *__restrict__ L) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= F2) return;
+  const int W = 2 * sm;
+  Cx *a = scratch + (size_t)i * SMX * 2 * SMX;
+  const Cx nu = {lam[2 * i], lam[2 * i + 1]};
+  for (int r = 0; r < sm; ++r)
+    for (int c = 0; c < W; ++c) {
+      Cx v = {0.0, 0.0};
+      if (c < sm) {
+        v.re = T[(size_t)r * ldT + c];
+        if (r == c) { v.re += nu.re; v.im += nu.im; }
+      } else if (c - sm == r) {
+        v.re = 1.0;
+      }
+      a[r * W + c] = v;
+    }
+  for (int col = 0; col < sm; ++col) {
+    int piv = col;
+    double best = -1.0;
+    for (int r = col; r < sm; ++r) {
+      const Cx v = a[r * W + col];
+      const double mag = v.re * v.re + v.im * v.im;
+      if (mag > best) { best = mag; piv = r; }
+    }
+    if (piv != col)
+      for (int c = 0; c < W; ++c) {
+        const Cx t = a[col * W + c];
+        a[col * W + c] = a[piv * W + c];
+        a[piv * W + c] = t;
+      }
+    const Cx inv = crecip(a[col * W + col]);
+    for (int c = 0; c < W; ++c) a[col * W + c] = cmul(a[col * W + c], inv);
+    for (int r = 0; r < sm; ++r) {
+      if (r == col) continue;
+      const Cx f = a[r * W + col];
+      for (int c = 0; c < W; ++c) a[r * W + c] = csub(a[r * W + c], cmul(f, a[col * W + c]));
+    }
+  }
+  Cx *Li = L + (size_t)i * 6 * SMX;
+  for (int q = 0; q < s; ++q)
+    for (int c = 0; c < sm; ++c) Li[q * SMX + c] = a[(sm - s + q) * W + sm + c];
+  // t_{m+1,m}: rows sm..sm+s-1, columns (m-1)s..ms-1 of T (upper triangular)
+  const int c0 = (m - 1) * s;
+  Cx *Ei = E + (size_t)i * SMX * SMX;
+  for (int r = 0; r < sm; ++r) {
+    Cx pr[6];
+    for (int q = 0; q < s; ++q) {       // (proj_i t)_{r,q}
+      Cx acc = {0.0, 0.0};
+      for (int j = 0; j <= q; ++j) {
+        const double t = T[(size_t)(sm + j) * ldT + c0 + q];
+        const Cx pv = proj[((size_t)i * SMX + r) * 6 + j];
+        acc.re += pv.re * t;
+        acc.im += pv.im * t;
+      }
+      pr[q] = acc;
+    }
+    for (int c = 0; c < sm; ++c) {
+      Cx e = a[r * W + sm + c];
+      for (int q = 0; q < s; ++q) e = csub(e, cmul(pr[q], Li[q * SMX + c]));
+      Ei[r * SMX + c] = e;
+    }
+  }
+}
+
+// part[ch][(k s + h)][r][c] = sum over chunk ch of frequencies of
+// Re(ctab[k s + h][i] E_i[r][c]).  Grid: (ceil(sm^2/256), NCH).
+__global__ void __launch_bounds__(256)
+bg_assemble_kernel(int F2, int sm, int s, const Cx *__restrict__ ctab,
+                   const Cx *__restrict__ E, double *__restrict__ part) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int ch = blockIdx.y;
+  if (e >= sm * sm) return;
+  const int r = e / sm, c = e - r * sm;
+  const int per = (F2 + NCH - 1) / NCH;
+  const int i0 = ch * per, i1 = (i0 + per < F2) ? i0 + per : F2;
+  double acc[36];
+  for (int q = 0; q < 36; ++q) acc[q] = 0.0;
+  for (int i = i0; i < i1; ++i) {
+    const Cx ev = E[(size_t)i * SMX * SMX + r * SMX + c];
+    for (int q = 0; q < s * s; ++q) {
+      const Cx w = ctab[(size_t)q * F2 + i];
+      acc[q] += w.re * ev.re - w.im * ev.im;
+    }
+  }
+  for (int q = 0; q < s * s; ++q)
+    part[(((size_t)ch * 36 + q) * SMX + r) * SMX + c] = acc[q];
+}
+
+// G = I + sum of the chunk partials, rhs = (e_1 (x) I_s) beta per block,
+// y = G^{-1} rhs by Gaussian elimination with partial pivoting (G in the
+// global scratch, ld N + 1).  One block.
+__global__ void __launch_bounds__(256)
+bg_solve_kernel(int sm, int s, const double *__restrict__ part, const double *__restrict__ beta,
+                double *__restrict__ G, double *__restrict__ y) {
+  __shared__ int piv_s;
+  __shared__ double ys[NMAX];
+  const int N = s * sm, ld = N + 1, tid = threadIdx.x;
+  for (int e = tid; e < N * N; e += 256) {
+    const int row = e / N, col = e - row * N;
+    const int k = row / sm, r = row - k * sm, h = col / sm, c = col - h * sm;
+    double v = (row == col) ? 1.0 : 0.0;
+    for (int ch = 0; ch < NCH; ++ch)
+      v += part[(((size_t)ch * 36 + k * s + h) * SMX + r) * SMX + c];
+    G[(size_t)row * ld + col] = v;
+  }
+  for (int row = tid; row < N; row += 256) {
+    const int k = row / sm, r = row - k * sm;
+    G[(size_t)row * ld + N] = (r < s) ? beta[r * 6 + k] : 0.0;
+  }
+  __syncthreads();
+  for (int col = 0; col < N; ++col) {
+    if (tid == 0) {
+      int p = col;
+      for (int r = col + 1; r < N; ++r)
+        if (fabs(G[(size_t)r * ld + col]) > fabs(G[(size_t)p * ld + col])) p = r;
+      piv_s = p;
+    }
+    __syncthreads();
+    const int p = piv_s;
+    if (p != col)
+      for (int c = col + tid; c <= N; c += 256) {
+        const double t = G[(size_t)col * ld + c];
+        G[(size_t)col * ld + c] = G[(size_t)p * ld + c];
+        G[(size_t)p * ld + c] = t;
+      }
+    __syncthreads();
+    const double dinv = 1.0 / G[(size_t)col * ld + col];
+    for (int r = col + 1 + tid; r < N; r += 256) {
+      const double f = G[(size_t)r * ld + col] * dinv;
+      for (int c = col + 1; c <= N; ++c) G[(size_t)r * ld + c] -= f * G[(size_t)col * ld + c];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    for (int r = N - 1; r >= 0; --r) {
+      double v = G[(size_t)r * ld + N];
+      for (int c = r + 1; c < N; ++c) v -= G[(size_t)r * ld + c] * ys[c];
+      ys[r] = v / G[(size_t)r * ld + r];
+    }
+  }
+  __syncthreads();
+  for (int r = tid; r < N; r += 256) y[r] = ys[r];
+}
+
+// One thread per frequency: u = sum_h theta_i^(h) y_h, v = L_i u,
+// w = t_{m+1,m} v, cw[i][k][j] = gtab[k][i] w_j.
+__global__ void __launch_bounds__(64)
+bg_cw_kernel(int F2, int sm, int s, int m, const Cx *__restrict__ L,
+             const double *__restrict__ T, int ldT, const Cx *__restrict__ thtab,
+             const Cx *__restrict__ gtab, const double *__restrict__ y, Cx *__restrict__ cw) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= F2) return;
+  const Cx *Li = L + (size_t)i * 6 * SMX;
+  Cx v[6];
+  for (int q = 0; q < s; ++q) v[q] = Cx{0.0, 0.0};
+  for (int c = 0; c < sm; ++c) {
+    Cx u = {0.0, 0.0};
+    for (int h = 0; h < s; ++h) {
+      const Cx th = thtab[(size_t)h * F2 + i];
+      const double yv = y[h * sm + c];
+      u.re += th.re * yv;
+      u.im += th.im * yv;
+    }
+    for (int q = 0; q < s; ++q) {
+      const Cx l = Li[q * SMX + c];
+      v[q].re += l.re * u.re - l.im * u.im;
+      v[q].im += l.re * u.im + l.im * u.re;
+    }
+  }
+  const int c0 = (m - 1) * s;
+  Cx w[6];
+  for (int j = 0; j < s; ++j) {
+    Cx acc = {0.0, 0.0};
+    for (int q = j; q < s; ++q) {
+      const double t = T[(size_t)(sm + j) * ldT + c0 + q];
+      acc.re += t * v[q].re;
+      acc.im += t * v[q].im;
+    }
+    w[j] = acc;
+  }
+  for (int k = 0; k < s; ++k) {
+    const Cx g = gtab[(size_t)k * F2 + i];
+    for (int j = 0; j < s; ++j) cw[((size_t)i * 6 + k) * 6 + j] = cmul(g, w[j]);
+  }
+}
+
+// z_k[row] = sum_i sum_j Re(cw[i][k][j] h_i^(j)[row]) (hs_j = -h^(j)).
+__global__ void __launch_bounds__(256)
+bg_wsum_kernel(int n, int F2, int s, const Cx *__restrict__ hs, size_t sstride,
+               const Cx *__restrict__ cw, double *__restrict__ z) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int i = 0; i < F2; ++i)
+    for (int j = 0; j < s; ++j) {
+      const Cx h = hs[j * sstride + (size_t)i * n + row];
+      for (int k = 0; k < s; ++k) {
+        const Cx c = cw[((size_t)i * 6 + k) * 6 + j];
+        acc[k] -= c.re * h.re - c.im * h.im;
+      }
+    }
+  for (int k = 0; k < s; ++k) z[(size_t)k * n + row] = acc[k];
+}
+
+// state[1] = sqrt(sum_k ||(I - V V^T) z_k||^2) (two projection passes).
+__global__ void __launch_bounds__(FB)
+bg_resid_kernel(int n, int sm, int s, const double *__restrict__ V, const double *__restrict__ z,
+                double *__restrict__ state) {
+  __shared__ double red[FB / 64];
+  __shared__ double part[SMX][FB / 64];
+  __shared__ double dots[SMX];
+  const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63, nw = FB / 64;
+  double total = 0.0;
+  for (int k = 0; k < s; ++k) {
+    double zv[FR];
+#pragma unroll
+    for (int r = 0; r < FR; ++r) {
+      const int i = tid + r * FB;
+      zv[r] = i < n ? z[(size_t)k * n + i] : 0.0;
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int c = 0; c < sm; ++c) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int r = 0; r < FR; ++r) {
+          const int i = tid + r * FB;
+          if (i < n) sacc += V[(size_t)c * n + i] * zv[r];
+        }
+        for (int off = 32; off > 0; off >>= 1) sacc += __shfl_xor(sacc, off, 64);
+        if (lane == 0) part[c][wid] = sacc;
+      }
+      __syncthreads();
+      if (tid < sm) {
+        double a = 0.0;
+        for (int q = 0; q < nw; ++q) a += part[tid][q];
+        dots[tid] = a;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < FR; ++r) {
+        const int i = tid + r * FB;
+        if (i < n)
+          for (int c = 0; c < sm; ++c) zv[r] -= dots[c] * V[(size_t)c * n + i];
+      }
+      __syncthreads();
+    }
+    double sq = 0.0;
+#pragma unroll
+    for (int r = 0; r < FR; ++r) sq += zv[r] * zv[r];
+    total += block_sum(sq, red);
+  }
+  if (tid == 0) state[1] = sqrt(total);
+}
+
+// x[k n + row] = sum_c y[k sm + c] V[c][row]
+__global__ void __launch_bounds__(256)
+bg_combine_kernel(int n, int sm, int s, const double *__restrict__ V,
+                  const double *__restrict__ y, double *__restrict__ x) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (row >= n || k >= s) return;
+  double acc = 0.0;
+  for (int c = 0; c < sm; ++c) acc += y[k * sm + c] * V[(size_t)c * n + row];
+  x[(size_t)k * n + row] = acc;
+}
+
+// ||b||^2 of the s starting vectors into state[0] (as a norm)
+__global__ void __launch_bounds__(FB)
+bg_norm_kernel(int len, const double *__restrict__ b, double *__restrict__ state) {
+  __shared__ double red[FB / 64];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < len; i += FB) s += b[i] * b[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) state[0] = sqrt(s);
+}
+
+}  // namespace
+
+// Layout of the block Galerkin state (doubles), F2 frequencies, n rows.
+BgLayout pd_bgal_layout(int n, int F2) {
+  BgLayout L;
+  size_t o = 0;
+  auto take = [&](size_t cnt) {
+    const size_t at = o;
+    o += (cnt + 1) & ~(size_t)1;   // keep complex arrays 16-byte aligned
+    return at;
+  };
+  L.T = take((size_t)BG_TROWS * BG_LDT);
+  L.beta = take(36);
+  L.proj = take(2 * (size_t)F2 * SMX * 6);
+  L.scratch = take(2 * (size_t)F2 * SMX * 2 * SMX);
+  L.E = take(2 * (size_t)F2 * SMX * SMX);
+  L.L = take(2 * (size_t)F2 * 6 * SMX);
+  L.part = take((size_t)NCH * 36 * SMX * SMX);
+  L.G = take((size_t)NMAX * (NMAX + 1));
+  L.y = take(NMAX);
+  L.cw = take(2 * (size_t)F2 * 36);
+  L.z = take(6 * (size_t)n);
+  L.state = take(8);
+  L.mfac = take(12 * 15);
+  L.ctab = take(2 * (size_t)36 * F2);
+  L.gtab = take(2 * (size_t)6 * F2);
+  L.thtab = take(2 * (size_t)6 * F2);
+  L.total = o;
+  return L;
+}
+
+pd_status pd_bgal(pd_plan p, const double *b, double *x, double rtol, int *iters,
+                  double *relres, int *checks) {
+  const int n = p->nbar, F2 = p->F2, s = p->bdf_s;
+  if (s < 1 || s > 6 || n > FB * FR || !p->fom || !p->fom_h) {
+    pd_set_error("block Galerkin: unsupported plan");
+    return PD_ENOTSUP;
+  }
+  const BgLayout Lo = pd_bgal_layout(n, F2);
+  double *base = p->fom;
+  double *T = base + Lo.T;
+  double *beta = base + Lo.beta;
+  Cx *proj = reinterpret_cast<Cx *>(base + Lo.proj);
+  Cx *scratch = reinterpret_cast<Cx *>(base + Lo.scratch);
+  Cx *E = reinterpret_cast<Cx *>(base + Lo.E);
+  Cx *Lr = reinterpret_cast<Cx *>(base + Lo.L);
+  double *part = base + Lo.part;
+  double *G = base + Lo.G;
+  double *y = base + Lo.y;
+  Cx *cw = reinterpret_cast<Cx *>(base + Lo.cw);
+  double *z = base + Lo.z;
+  double *state = base + Lo.state;
+  const Cx *mfac = reinterpret_cast<const Cx *>(base + Lo.mfac);
+  const Cx *ctab = reinterpret_cast<const Cx *>(base + Lo.ctab);
+  const Cx *gtab = reinterpret_cast<const Cx *>(base + Lo.gtab);
+  const Cx *thtab = reinterpret_cast<const Cx *>(base + Lo.thtab);
+  Cx *hs = reinterpret_cast<Cx *>(p->fom_h);
+  const size_t sstride = (size_t)F2 * n;   // complex elements per spectrum
+  int mmax = SMX / s;
+  if (p->maxit < mmax) mmax = p->maxit;
+  const int q = p->fom_q < 1 ? 1 : p->fom_q;
+  double *V = p->V;                        // (maxit + 1) * s * n >= (mmax + 1) * s * n
+
+  PD_HIP_CHECK(hipMemsetAsync(T, 0, sizeof(double) * BG_TROWS * BG_LDT, p->stream));
+  PD_HIP_CHECK(hipMemsetAsync(beta, 0, sizeof(double) * 36, p->stream));
+  hipLaunchKernelGGL(bg_norm_kernel, dim3(1), dim3(FB), 0, p->stream, s * n, b, state);
+  // B = V_1 beta (Gram-Schmidt QR of the s starting columns, beta ld 6)
+  for (int j = 0; j < s; ++j)
+    hipLaunchKernelGGL(bg_orth_kernel, dim3(1), dim3(FB), 0, p->stream, n, j, j, 6, V,
+                       b + (size_t)j * n, beta);
+  PD_HIP_CHECK(hipGetLastError());
+  double bnorm = 0.0, res = 0.0;
+  int m = 0, nchecks = 0;
+  bool checked = false;
+  while (m < mmax) {
+    ++m;
+    const int sm = s * m;
+    for (int j = 0; j < s; ++j) {
+      pd_status st = pd_fom_apply(p, mfac, V + (size_t)((m - 1) * s + j) * n, p->wvec);
+      if (st != PD_OK) return st;
+      hipLaunchKernelGGL(bg_orth_kernel, dim3(1), dim3(FB), 0, p->stream, n, sm + j,
+                         (m - 1) * s + j, BG_LDT, V, p->wvec, T);
+    }
+    PD_HIP_CHECK(hipGetLastError());
+    if (m % q != 0 && m != mmax) continue;
+    // H_i for all i: pass C on a zero spectrum with x = column j of V_{m+1}
+    for (int j = 0; j < s; ++j) {
+      Cx *hj = hs + j * sstride;
+      PD_HIP_CHECK(hipMemsetAsync(hj, 0, sstride * sizeof(Cx), p->stream));
+      pd_status st = pd_launch_tridiag(p, 1, hj, V + (size_t)(sm + j) * n, hj);
+      if (st != PD_OK) return st;
+    }
+    hipLaunchKernelGGL(bg_proj_kernel, dim3(F2), dim3(256), 0, p->stream, n, sm, s, hs, sstride,
+                       V, proj);
+    hipLaunchKernelGGL(bg_small_kernel, dim3((F2 + 63) / 64), dim3(64), 0, p->stream, F2, sm, s,
+                       m, p->lam64, T, BG_LDT, proj, scratch, E, Lr);
+    hipLaunchKernelGGL(bg_assemble_kernel, dim3((sm * sm + 255) / 256, NCH), dim3(256), 0,
+                       p->stream, F2, sm, s, ctab, E, part);
+    hipLaunchKernelGGL(bg_solve_kernel, dim3(1), dim3(256), 0, p->stream, sm, s, part, beta, G,
+                       y);
+    hipLaunchKernelGGL(bg_cw_kernel, dim3((F2 + 63) / 64), dim3(64), 0, p->stream, F2, sm, s, m,
+                       Lr, T, BG_LDT, thtab, gtab, y, cw);
+    hipLaunchKernelGGL(bg_wsum_kernel, dim3((n + 255) / 256), dim3(256), 0, p->stream, n, F2, s,
+                       hs, sstride, cw, z);
+    hipLaunchKernelGGL(bg_resid_kernel, dim3(1), dim3(FB), 0, p->stream, n, sm, s, V, z, state);
+    PD_HIP_CHECK(hipGetLastError());
+    double hst[2];
+    PD_HIP_CHECK(hipMemcpyAsync(hst, state, 2 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    PD_HIP_CHECK(hipStreamSynchronize(p->stream));
+    bnorm = hst[0];
+    res = hst[1];
+    checked = true;
+    ++nchecks;
+    if (!std::isfinite(res) || !std::isfinite(bnorm)) {
+      pd_set_error("block Galerkin produced a non-finite residual");
+      return PD_ENONFINITE;
+    }
+    if (res <= rtol * bnorm) break;
+  }
+  const int sm = s * m;
+  hipLaunchKernelGGL(bg_combine_kernel, dim3((n + 255) / 256, s), dim3(256), 0, p->stream, n, sm,
+                     s, V, y, x);
+  PD_HIP_CHECK(hipGetLastError());
+  if (iters) *iters = m;
+  if (relres) *relres = bnorm > 0.0 ? res / bnorm : 0.0;
+  if (checks) *checks = nchecks;
+  return (checked && res <= rtol * bnorm) ? PD_OK : PD_ENOTCONV;
+}

@@ -476,6 +476,18 @@ pd_status pd_fom(pd_plan p, const double *b, double *x, double rtol, int *iters,
   return (checked && res <= rtol * beta) ? PD_OK : PD_ENOTCONV;
 }
 
+pd_status pd_fom_apply(pd_plan p, const cpx<double> *mfac, const double *v, double *w) {
+  const int n = p->nbar;
+  if (n > FB * FR) {
+    pd_set_error("Algorithm 2 operator: n exceeds the single-block limit");
+    return PD_ENOTSUP;
+  }
+  hipLaunchKernelGGL(fom_apply_kernel, dim3(1), dim3((n + 15) / 16), 0, p->stream, n, v, mfac,
+                     p->uni[0], p->uni[2], p->uni[3], p->uni[4], p->uni[5], w);
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
 // mass factors for fom_apply_kernel (host, float64): 16 rows per thread
 void pd_fom_mass_factors(pd_plan p, std::vector<double> &out) {
   out.assign(12 * 15, 0.0);

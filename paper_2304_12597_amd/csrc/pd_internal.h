@@ -295,6 +295,20 @@ pd_status pd_bdf_solve(pd_plan p, const double *u0s, const double *F, double *U,
 pd_status pd_bdf_residual_norms(pd_plan p, const double *u0s, const double *F,
                                 const double *U, double *rn2, double *gn2);
 int pd_bdf_residual_blocks(pd_plan p);
+// Block Galerkin method for J^(s) (bgal.hip): basis dimension s m <= BG_SMAX;
+// T is BG_TROWS x BG_LDT row-major.  Offsets (doubles) into p->fom.
+constexpr int BG_SMAX = 32;
+constexpr int BG_TROWS = BG_SMAX + 6;
+constexpr int BG_LDT = BG_SMAX;
+struct BgLayout {
+  size_t T, beta, proj, scratch, E, L, part, G, y, cw, z, state, mfac, ctab, gtab, thtab, total;
+};
+BgLayout pd_bgal_layout(int n, int F2);
+pd_status pd_bgal(pd_plan p, const double *b, double *x, double rtol, int *iters,
+                  double *relres, int *checks);
+// w = tau M^{-1} K v with the uniform mass factors mfac (Algorithm 2's operator;
+// BDF plans: tau beta M^{-1} K)
+pd_status pd_fom_apply(pd_plan p, const cpx<double> *mfac, const double *v, double *w);
 // sine-basis path (sine.hip)
 int pd_sine_dst_C(int n, int ell);
 size_t pd_sine_dst_lds(int n, int C);

@@ -100,11 +100,12 @@ std::mutex g_attr_mu;
 struct Layout {
   size_t coef = 0, lam = 0, tw = 0, dal = 0, fac = 0, twd = 0, wreal = 0, wz = 0, sine = 0,
          fom = 0;
+  size_t fom_h_bytes = 0;
   size_t spec_bytes = 0, partials = 0, rstage = 0, vec = 0, V = 0, gm = 0, red = 0;
   size_t total_bytes() const {
     return coef * 12 + lam * 12 + 2 * lam * 8 + tw * 12 + dal * 8 + fac * 12 + twd * 8 +
            wreal * 8 + wz * 8 + spec_bytes + partials * 8 + rstage * 8 + 3 * vec * 8 + V * 8 + gm * 8 +
-           red * 8 + sine * 8 + fom * 8 + (fom ? spec_bytes : 0);
+           red * 8 + sine * 8 + fom * 8 + fom_h_bytes;
   }
 };
 
@@ -166,7 +167,10 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
     }
     L.sine = (size_t)N + 2 * (size_t)(H + 1) + 2 * (size_t)H + 2 * (size_t)n;
   }
-  if (p->krylov == PD_KRYLOV_FOM) L.fom = pd_fom_doubles(n, F2);
+  if (p->krylov == PD_KRYLOV_FOM) {
+    L.fom = p->bdf_s > 1 ? pd_bgal_layout(p->nbar, F2).total : pd_fom_doubles(n, F2);
+    L.fom_h_bytes = (size_t)p->bdf_s * F2 * p->nbar * cb;
+  }
   if (p->bdf_s > 1) {
     L.wreal = (size_t)ell * p->nbar;
     L.wz = (size_t)ell * p->nbar;
@@ -448,9 +452,9 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   }
   if (opt.bdf_order > 1 &&
       (opt.dims != 1 || opt.precision != PD_FP64 || opt.alpha != 1.0 ||
-       opt.krylov != PD_KRYLOV_GMRES || opt.shifted_solver != PD_SHIFTED_PARTITION ||
+       opt.shifted_solver != PD_SHIFTED_PARTITION ||
        opt.early_exit != 0 || ell < 2 * opt.bdf_order)) {
-    pd_set_error("BDF plans of order > 1 need dims 1, PD_FP64, alpha 1, GMRES, partition "
+    pd_set_error("BDF plans of order > 1 need dims 1, PD_FP64, alpha 1, partition "
                  "solves, no early_exit and ell >= 2 * bdf_order");
     return PD_ENOTSUP;
   }
@@ -686,6 +690,51 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
       sk[k] = p->uni[4] + 2.0 * p->uni[5] * c;
     }
   }
+  // block Galerkin (BDF, krylov = FOM): weight_i gamma_i^(k) theta_i^(h),
+  // weight_i gamma_i^(k) and theta_i^(h) for i = 0..ell/2 (Section 5), with
+  // gamma^(k) = F^{-T}[e_{ell-s+1}..e_ell] A_s^T e_k, theta^(h) = F e_h
+  std::vector<double> bg_ct, bg_gt, bg_tt;
+  if (p->krylov == PD_KRYLOV_FOM && p->bdf_s > 1) {
+    const int s = p->bdf_s;
+    bg_ct.assign(2 * (size_t)s * s * F2, 0.0);
+    bg_gt.assign(2 * (size_t)s * F2, 0.0);
+    bg_tt.assign(2 * (size_t)s * F2, 0.0);
+    for (int i = 0; i < F2; ++i) {
+      const double wgt = (i == 0 || 2 * i == ell) ? 1.0 : 2.0;
+      double th[6][2], ga[6][2];
+      for (int h = 0; h < s; ++h) {
+        double c, sn;
+        cis((long)i * h, ell, c, sn);
+        th[h][0] = c;
+        th[h][1] = -sn;                                // exp(-2 pi i i h / ell)
+      }
+      for (int k = 0; k < s; ++k) {
+        double gr = 0.0, gi = 0.0;
+        for (int c = k; c < s; ++c) {
+          const double a = p->bdf_alpha[s - c + k - 1];   // (A_s)_{k,c}
+          double cc, sn;
+          cis((long)i * (ell - s + c), ell, cc, sn);       // exp(+2 pi i i (ell-s+c) / ell)
+          gr += a * cc;
+          gi += a * sn;
+        }
+        ga[k][0] = gr / ell;
+        ga[k][1] = gi / ell;
+      }
+      for (int h = 0; h < s; ++h) {
+        bg_tt[2 * ((size_t)h * F2 + i)] = th[h][0];
+        bg_tt[2 * ((size_t)h * F2 + i) + 1] = th[h][1];
+      }
+      for (int k = 0; k < s; ++k) {
+        bg_gt[2 * ((size_t)k * F2 + i)] = wgt * ga[k][0];
+        bg_gt[2 * ((size_t)k * F2 + i) + 1] = wgt * ga[k][1];
+        for (int h = 0; h < s; ++h) {
+          const size_t q = (size_t)(k * s + h) * F2 + i;
+          bg_ct[2 * q] = wgt * (ga[k][0] * th[h][0] - ga[k][1] * th[h][1]);
+          bg_ct[2 * q + 1] = wgt * (ga[k][0] * th[h][1] + ga[k][1] * th[h][0]);
+        }
+      }
+    }
+  }
   const size_t nbar = p->nbar;
   p->spec_bytes = L.spec_bytes;
   p->bytes = L.total_bytes();
@@ -723,7 +772,7 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   PD_TRY(dev_alloc(&p->red, L.red));
   if (p->krylov == PD_KRYLOV_FOM) {
     PD_TRY(dev_alloc(&p->fom, L.fom));
-    PD_TRY(dev_alloc(reinterpret_cast<unsigned char **>(&p->fom_h), p->spec_bytes));
+    PD_TRY(dev_alloc(reinterpret_cast<unsigned char **>(&p->fom_h), L.fom_h_bytes));
   }
   if (p->sine) {
     PD_TRY(dev_alloc(&p->sine_q, sq.size()));
@@ -759,8 +808,20 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   if (p->krylov == PD_KRYLOV_FOM) {
     std::vector<double> mf;
     pd_fom_mass_factors(p, mf);
-    PD_HIP_CHECK(hipMemcpyAsync(p->fom + pd_fom_mfac_offset(p->F2), mf.data(),
-                                mf.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
+    const size_t mfo = p->bdf_s > 1 ? pd_bgal_layout(p->nbar, p->F2).mfac
+                                    : pd_fom_mfac_offset(p->F2);
+    PD_HIP_CHECK(hipMemcpyAsync(p->fom + mfo, mf.data(), mf.size() * sizeof(double),
+                                hipMemcpyHostToDevice, p->stream));
+    if (p->bdf_s > 1) {
+      const BgLayout bl = pd_bgal_layout(p->nbar, p->F2);
+      PD_HIP_CHECK(hipMemcpyAsync(p->fom + bl.ctab, bg_ct.data(), bg_ct.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, p->stream));
+      PD_HIP_CHECK(hipMemcpyAsync(p->fom + bl.gtab, bg_gt.data(), bg_gt.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, p->stream));
+      PD_HIP_CHECK(hipMemcpyAsync(p->fom + bl.thtab, bg_tt.data(),
+                                  bg_tt.size() * sizeof(double), hipMemcpyHostToDevice,
+                                  p->stream));
+    }
   }
   if (p->sine) {
     PD_TRY(upload(p->sine_q, sq, p->stream));

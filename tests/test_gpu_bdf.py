@@ -1,7 +1,8 @@
 """GPU parity of the BDF-s path (bdf_order = s in 2..6, Section 5): whole
-solves against the oracle's stepping and exact modal recurrence, and the
+solves against the oracle's stepping and exact modal recurrence, the
 stages (h transform, block capacitance product, capacitance solve,
-residual) against the oracle's pieces."""
+residual) against the oracle's pieces, and the block Galerkin method
+(krylov = PD_KRYLOV_FOM) against the oracle's."""
 import numpy as np
 import pytest
 
@@ -192,7 +193,6 @@ def test_bdf_rejects_unsupported(lib):
     p = wl.cfg_small_fd()
     bad = [dict(bdf_order=7), dict(bdf_order=0), dict(bdf_order=2, precision=lib.PD_MIXED),
            dict(bdf_order=2, alpha=0.5), dict(bdf_order=2, early_exit=1),
-           dict(bdf_order=2, krylov=lib.PD_KRYLOV_FOM),
            dict(bdf_order=2, shifted_solver=lib.PD_SHIFTED_SINE)]
     for kw in bad:
         with pytest.raises(RuntimeError):
@@ -202,3 +202,84 @@ def test_bdf_rejects_unsupported(lib):
     q = wl.heat_2d(15, 16, 0.1, 1.0, np.random.default_rng(0))
     with pytest.raises(RuntimeError):
         lib.paradiag_plan_create(q.n, q.ell, q.tau, None, q.K, dims=2, bdf_order=2)
+
+
+# ------------------------------------------------ block Galerkin for J^(s) --
+
+def _bg_problem(kind, n, ell, T_, s):
+    p = wl.heat_1d(kind, n, ell, T_, 1.0, np.random.default_rng(n + ell), True)
+    return p, np.tile(p.u0, (s, 1))
+
+
+def _bg_solve(lib, p, U0, s, tol, **kw):
+    plan = _plan(lib, p.n, p.ell, p.tau, p.M, p.K, s, krylov=lib.PD_KRYLOV_FOM,
+                 check_residual=1, **kw)
+    try:
+        U = torch.empty((p.ell, p.n), dtype=torch.float64, device=dev())
+        info = lib.paradiag_solve(plan, T(U0), T(p.F), U, tol, allow_notconv=True)
+        torch.cuda.synchronize()
+        return U.cpu().numpy(), info
+    finally:
+        lib.paradiag_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("kind,n,ell,T_,s", [
+    ("fd1", 15, 16, 1.0, 3), ("fd1", 31, 16, 1.0, 2), ("fd1", 31, 16, 1.0, 6),
+    ("fem1", 31, 16, 1.0, 3), ("fd1", 127, 16, 4.0, 3), ("fem1", 511, 32, 10.0, 2),
+    ("fem1", 511, 32, 10.0, 3)])
+def test_block_galerkin_matches_oracle(lib, kind, n, ell, T_, s):
+    """Same number of block steps as the oracle's block Galerkin method at
+    the same tolerance (tol/100 on ||r|| / ||b||; one step either way at the
+    threshold), #PinT = checks + 2, and the same U."""
+    p, U0 = _bg_problem(kind, n, ell, T_, s)
+    tol = 1e-10
+    U, info = _bg_solve(lib, p, U0, s, tol)
+    Msp, Ksp = problem_matrices(p)
+    ref = bdf.paradiag_bdf(Msp, Ksp, p.tau, s, list(U0), p.F, capacitance="galerkin",
+                           eps=tol * 1e-2, maxit=32 // s)
+    assert ref["history"][-1] <= tol * 1e-2 * np.linalg.norm(ref["b"])
+    assert abs(info.gmres_iters - ref["steps"]) <= 1, (info.as_dict(), ref["steps"])
+    assert info.pint_loops == info.gmres_iters + 2
+    assert allatonce.rel_err(U, ref["U"]) < 1e-10
+    D = bdf.step_bdf(Msp, Ksp, p.tau, s, list(U0), p.F)
+    assert allatonce.rel_err(U, D) < 1e-10
+    assert info.rel_residual < 1e-9
+
+
+def test_block_galerkin_residual_matches_oracle(lib):
+    """The residual norm after m = 1, 2, 3 block steps (maxit = m) equals
+    the oracle's ||(I - I_s (x) V V^T) S y|| there (residuals well above
+    rounding: after 10 steps it is 1.5e-11 ||b|| and rounding moves it by
+    a few per cent on either side)."""
+    p, U0 = _bg_problem("fem1", 255, 16, 10.0, 3)
+    Msp, Ksp = problem_matrices(p)
+    ref = bdf.paradiag_bdf(Msp, Ksp, p.tau, 3, list(U0), p.F, capacitance="galerkin",
+                           eps=0.0, maxit=3)
+    for m in (1, 2, 3):
+        U, info = _bg_solve(lib, p, U0, 3, 1e-10, maxit=m)
+        assert info.gmres_iters == m
+        rel = ref["history"][m - 1] / np.linalg.norm(ref["b"])
+        assert abs(info.gmres_rel_residual - rel) <= 1e-5 * rel, (m, info.gmres_rel_residual, rel)
+
+
+@pytest.mark.parametrize("q", [2, 3])
+def test_block_galerkin_residual_freezing(lib, q):
+    p, U0 = _bg_problem("fd1", 31, 16, 1.0, 3)
+    U, info = _bg_solve(lib, p, U0, 3, 1e-10, fom_q=q)
+    assert info.gmres_iters % q == 0 or info.gmres_iters == 32 // 3
+    assert info.pint_loops == -(-info.gmres_iters // q) + 2
+    Msp, Ksp = problem_matrices(p)
+    D = bdf.step_bdf(Msp, Ksp, p.tau, 3, list(U0), p.F)
+    assert allatonce.rel_err(U, D) < 1e-10
+
+
+def test_block_galerkin_step_cap_is_reported(lib):
+    p, U0 = _bg_problem("fem1", 255, 16, 10.0, 3)
+    plan = _plan(lib, p.n, p.ell, p.tau, p.M, p.K, 3, krylov=lib.PD_KRYLOV_FOM)
+    try:
+        U = torch.empty((p.ell, p.n), dtype=torch.float64, device=dev())
+        with pytest.raises(lib.PDError) as e:
+            lib.paradiag_solve(plan, T(U0), T(p.F), U, 1e-12)
+        assert e.value.status == lib.PD_ENOTCONV
+    finally:
+        lib.paradiag_plan_destroy(plan)
