@@ -20,9 +20,13 @@
 //     theta^(h) = F e_h, so sum_h theta_i^(h) v_h is the transform of X(v),
 //     the array holding v_h in time row h-1 and zeros elsewhere;
 //   U = U_1 - Y(X(x)) with x the solution of J^(s) x = b^(s).
-// One capacitance product is one parfor of shifted solves between a forward
-// and an inverse transform; #PinT = GMRES iterations + 2 as for s = 1 (the
-// block Galerkin method of bgal.hip: residual checks + 2).
+// X(v) has s nonzero rows, so its transform is an s-term sum per frequency
+// (bdf_spec_kernel), and only s rows of the inverse transform are needed:
+// sum_c (A_s)_{k,c} Z[ell-s+c] = sum_i gamma_i^(k) Zhat_i, one weighted sum
+// over the half spectrum per block (bdf_gather_kernel, weights 2 Re(.) for
+// the conjugate halves).  A capacitance product is then one parfor of
+// shifted solves between two streaming passes; #PinT = GMRES iterations + 2
+// as for s = 1 (the block Galerkin method of bgal.hip: residual checks + 2).
 #include "pd_internal.h"
 
 #include <algorithm>
@@ -56,16 +60,70 @@ bdf_rhs_kernel(int n, int s, double tb, BdfAlpha c, const double *__restrict__ u
   out[idx] = v;
 }
 
-// out[t][i] = sign * v[t][i] for t < s, 0 for s <= t < rows.
-// Grid: (ceil(n/BB), rows).
+// spec[f][i] = sign * sum_{h<s} v_h[i] exp(-2 pi i f h / ell), f = 0..ell/2:
+// the half spectrum of X(v).  tw[m] = exp(-2 pi i m / ell), ell a power of
+// two.  Grid: (ceil(n/BB), F2).
 __global__ void __launch_bounds__(BB)
-bdf_place_kernel(int n, int s, double sign, const double *__restrict__ v,
-                 double *__restrict__ out) {
+bdf_spec_kernel(int n, int ell, int s, double sign, const double *__restrict__ v,
+                const cpx<double> *__restrict__ tw, cpx<double> *__restrict__ spec) {
   const int i = blockIdx.x * BB + threadIdx.x;
-  const int t = blockIdx.y;
+  const int f = blockIdx.y;
   if (i >= n) return;
-  const size_t idx = (size_t)t * n + i;
-  out[idx] = t < s ? sign * v[idx] : 0.0;
+  double re = 0.0, im = 0.0;
+#pragma unroll
+  for (int h = 0; h < 6; ++h)
+    if (h < s) {
+      const cpx<double> w = tw[(f * h) & (ell - 1)];
+      const double x = sign * v[(size_t)h * n + i];
+      re += w.re * x;
+      im += w.im * x;
+    }
+  spec[(size_t)f * n + i] = cpx<double>{re, im};
+}
+
+// part[ch][k][i] = sum over the ch-th chunk of frequencies f of
+// Re(g[k][f] Y[f][i]) (g = weight_f gamma_f^(k)).  Block: 64 columns x 4
+// frequency lanes (a wave reads 64 consecutive entries of one frequency).
+// Grid: (ceil(n/64), PD_BDF_GCH).
+__global__ void __launch_bounds__(256)
+bdf_gather_kernel(int n, int F2, int s, const cpx<double> *__restrict__ g,
+                  const cpx<double> *__restrict__ Y, double *__restrict__ part) {
+  __shared__ double sh[4][6][64];
+  const int col = threadIdx.x & 63, lane = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + col;
+  const int ch = blockIdx.y;
+  const int per = (F2 + PD_BDF_GCH - 1) / PD_BDF_GCH;
+  const int f0 = ch * per, f1 = (f0 + per < F2) ? f0 + per : F2;
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (i < n)
+    for (int f = f0 + lane; f < f1; f += 4) {
+      const cpx<double> y = Y[(size_t)f * n + i];
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        if (k < s) {
+          const cpx<double> w = g[(size_t)k * F2 + f];
+          acc[k] += w.re * y.re - w.im * y.im;
+        }
+    }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) sh[lane][k][col] = acc[k];
+  __syncthreads();
+  if (lane == 0 && i < n)
+    for (int k = 0; k < s; ++k)
+      part[((size_t)ch * s + k) * n + i] = sh[0][k][col] + sh[1][k][col] + sh[2][k][col] +
+                                           sh[3][k][col];
+}
+
+// out[k][i] = v[k][i] + sum_ch part[ch][k][i] (fixed order).  Grid: (ceil(n/BB), s).
+__global__ void __launch_bounds__(BB)
+bdf_finish_kernel(int n, int s, const double *__restrict__ v, const double *__restrict__ part,
+                  double *__restrict__ out) {
+  const int i = blockIdx.x * BB + threadIdx.x;
+  const int k = blockIdx.y;
+  if (i >= n) return;
+  double acc = v[(size_t)k * n + i];
+  for (int ch = 0; ch < PD_BDF_GCH; ++ch) acc += part[((size_t)ch * s + k) * n + i];
+  out[(size_t)k * n + i] = acc;
 }
 
 // out[k][i] = v[k][i] (0 if v is NULL) + sum_{c>=k} (A_s)_{k,c} Z[ell-s+c][i].
@@ -166,7 +224,7 @@ BdfBlock block_of(pd_plan p) {
 }
 
 bool bdf_plan_ok(pd_plan p) {
-  if (p->bdf_s < 2 || p->bdf_s > 6 || p->dims != 1 || !p->wreal || !p->wz ||
+  if (p->bdf_s < 2 || p->bdf_s > 6 || p->dims != 1 || !p->wreal || !p->wz || !p->bdf_g ||
       p->ell < 2 * p->bdf_s) {
     pd_set_error("not a BDF plan of order > 1");
     return false;
@@ -174,15 +232,13 @@ bool bdf_plan_ok(pd_plan p) {
   return true;
 }
 
-// X = sign * [v; 0] into p->wreal; rows >= s are written only when they may
-// hold something else (after the right-hand side used the buffer).
-pd_status place(pd_plan p, const double *v, double sign) {
-  const int n = p->n, s = p->bdf_s;
-  const int rows = p->bdf_clean ? s : p->ell;
-  hipLaunchKernelGGL(bdf_place_kernel, dim3((n + BB - 1) / BB, rows), dim3(BB), 0, p->stream, n,
-                     s, sign, v, p->wreal);
+// p->spec = the half spectrum of X(sign * v)
+pd_status spectrum_of(pd_plan p, const double *v, double sign) {
+  const int n = p->n;
+  hipLaunchKernelGGL(bdf_spec_kernel, dim3((n + BB - 1) / BB, p->F2), dim3(BB), 0, p->stream, n,
+                     p->ell, p->bdf_s, sign, v, reinterpret_cast<const cpx<double> *>(p->tw64),
+                     reinterpret_cast<cpx<double> *>(p->spec));
   PD_HIP_CHECK(hipGetLastError());
-  p->bdf_clean = 1;
   return PD_OK;
 }
 
@@ -216,17 +272,23 @@ pd_status pd_bdf_rhs(pd_plan p, const double *u0s, const double *F, double *out)
   hipLaunchKernelGGL(bdf_rhs_kernel, dim3((n + BB - 1) / BB, p->ell), dim3(BB), 0, p->stream, n,
                      p->bdf_s, p->tau * p->bdf_beta, alpha_of(p), u0s, F, out);
   PD_HIP_CHECK(hipGetLastError());
-  if (out == p->wreal) p->bdf_clean = 0;
   return PD_OK;
 }
 
 pd_status pd_bdf_apply(pd_plan p, const double *v, double *Jv) {
   if (!bdf_plan_ok(p)) return PD_ENOTSUP;
-  pd_status st = place(p, v, 1.0);
+  const int n = p->n, s = p->bdf_s;
+  pd_status st = spectrum_of(p, v, 1.0);
   if (st != PD_OK) return st;
-  st = transform_solve(p, p->wz, 0);
+  st = pd_launch_tridiag(p, 1, p->spec, nullptr, p->spec);
   if (st != PD_OK) return st;
-  return extract(p, v, p->wz, Jv);
+  hipLaunchKernelGGL(bdf_gather_kernel, dim3((n + 63) / 64, PD_BDF_GCH), dim3(256), 0, p->stream,
+                     n, p->F2, s, reinterpret_cast<const cpx<double> *>(p->bdf_g),
+                     reinterpret_cast<const cpx<double> *>(p->spec), p->wz);
+  hipLaunchKernelGGL(bdf_finish_kernel, dim3((n + BB - 1) / BB, s), dim3(BB), 0, p->stream, n, s,
+                     v, p->wz, Jv);
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
 }
 
 pd_status pd_bdf_residual_norms(pd_plan p, const double *u0s, const double *F,
@@ -259,7 +321,7 @@ pd_status pd_bdf_residual_norms(pd_plan p, const double *u0s, const double *F,
 
 // The whole BDF solve: h, U_1 = Y(h) into U, b^(s), J^(s) x = b^(s) by
 // GMRES or by the block Galerkin method (krylov = PD_KRYLOV_FOM),
-// U -= Y(X(x)).
+// U -= Y(X(x)) (the transform of X(x) as an s-term sum).
 pd_status pd_bdf_solve(pd_plan p, const double *u0s, const double *F, double *U, double tol,
                        pd_info *info) {
   if (!bdf_plan_ok(p)) return PD_ENOTSUP;
@@ -276,9 +338,11 @@ pd_status pd_bdf_solve(pd_plan p, const double *u0s, const double *F, double *U,
           ? pd_bgal(p, p->bvec, p->xvec, tol * PD_GMRES_TOL_FACTOR, &its, &rr, &checks)
           : pd_gmres(p, p->bvec, p->xvec, tol * PD_GMRES_TOL_FACTOR, &its, &rr);
   if (gst != PD_OK && gst != PD_ENOTCONV) return gst;
-  st = place(p, p->xvec, -1.0);
+  st = spectrum_of(p, p->xvec, -1.0);
   if (st != PD_OK) return st;
-  st = transform_solve(p, U, 1);
+  st = pd_launch_tridiag(p, 1, p->spec, nullptr, p->spec);
+  if (st != PD_OK) return st;
+  st = pd_launch_fft_inverse(p, p->spec, U, 1);
   if (st != PD_OK) return st;
   if (info) {
     info->gmres_iters = its;

@@ -18,7 +18,7 @@
 // i = 0 and ell/2, 2 elsewhere, real part).  Each check is one parfor of
 // shifted solves with s right-hand sides per frequency (s launches of the
 // pass-C kernel on a zero spectrum, which writes -h).  The basis dimension
-// s m is at most BG_SMAX.
+// s m is at most BG_SMAX and at most n (where the block space is all of R^n).
 #include "pd_internal.h"
 
 #include <cmath>
@@ -487,6 +487,11 @@ pd_status pd_bgal(pd_plan p, const double *b, double *x, double rtol, int *iters
   const size_t sstride = (size_t)F2 * n;   // complex elements per spectrum
   int mmax = SMX / s;
   if (p->maxit < mmax) mmax = p->maxit;
+  if (n / s < mmax) mmax = n / s;          // the basis spans R^n at s m = n
+  if (mmax < 1) {
+    pd_set_error("block Galerkin: n < s");
+    return PD_ENOTSUP;
+  }
   const int q = p->fom_q < 1 ? 1 : p->fom_q;
   double *V = p->V;                        // (maxit + 1) * s * n >= (mmax + 1) * s * n
 

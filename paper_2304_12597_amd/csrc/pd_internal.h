@@ -224,9 +224,10 @@ struct pd_plan_s {
   double bdf_beta = 1.0;
   double bdf_alpha[6] = {1, 0, 0, 0, 0, 0};   // alpha_1..alpha_s
   int ncap = 0;                // capacitance vector length: s * nbar
-  double *wz = nullptr;        // BDF: [ell][nbar] inverse-transform output
-  int bdf_clean = 0;           // rows s..ell-1 of wreal hold zeros
+  double *wz = nullptr;        // BDF: capacitance-product partial sums
+  double *bdf_g = nullptr;     // BDF: [s][F2] complex weight_f gamma_f^(k)
 };
+constexpr int PD_BDF_GCH = 16;   // frequency chunks of the BDF capacitance product
 
 // error reporting
 void pd_set_error(const std::string &msg);

@@ -84,7 +84,7 @@ void free_plan(pd_plan p) {
   void *ptrs[] = {p->coef64, p->coef32, p->lam64, p->lam32, p->gB64, p->gJ64, p->tw64,
                   p->tw32, p->dal, p->fac64, p->fac32, p->twd, p->wreal, p->spec, p->partials, p->rstage, p->bvec, p->xvec, p->wvec, p->V,
                   p->gm, p->red, p->sine_q, p->sine_wN, p->sine_twH, p->sine_m, p->sine_k,
-                  p->fom, p->fom_h, p->wz};
+                  p->fom, p->fom_h, p->wz, p->bdf_g};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   if (p->host_pin) (void)hipHostFree(p->host_pin);
@@ -98,13 +98,13 @@ std::mutex g_attr_mu;
 // Launch configurations and device allocation sizes (in elements of their
 // type) of a plan; shared by plan creation and paradiag_plan_bytes.
 struct Layout {
-  size_t coef = 0, lam = 0, tw = 0, dal = 0, fac = 0, twd = 0, wreal = 0, wz = 0, sine = 0,
-         fom = 0;
+  size_t coef = 0, lam = 0, tw = 0, dal = 0, fac = 0, twd = 0, wreal = 0, wz = 0, bdfg = 0,
+         sine = 0, fom = 0;
   size_t fom_h_bytes = 0;
   size_t spec_bytes = 0, partials = 0, rstage = 0, vec = 0, V = 0, gm = 0, red = 0;
   size_t total_bytes() const {
     return coef * 12 + lam * 12 + 2 * lam * 8 + tw * 12 + dal * 8 + fac * 12 + twd * 8 +
-           wreal * 8 + wz * 8 + spec_bytes + partials * 8 + rstage * 8 + 3 * vec * 8 + V * 8 + gm * 8 +
+           wreal * 8 + wz * 8 + bdfg * 8 + spec_bytes + partials * 8 + rstage * 8 + 3 * vec * 8 + V * 8 + gm * 8 +
            red * 8 + sine * 8 + fom * 8 + fom_h_bytes;
   }
 };
@@ -173,7 +173,8 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
   }
   if (p->bdf_s > 1) {
     L.wreal = (size_t)ell * p->nbar;
-    L.wz = (size_t)ell * p->nbar;
+    L.wz = (size_t)PD_BDF_GCH * p->bdf_s * p->nbar;
+    L.bdfg = 2 * (size_t)p->bdf_s * F2;
   }
   L.coef = 6 * (size_t)n;
   L.lam = 2 * (size_t)F2;
@@ -693,8 +694,9 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   // block Galerkin (BDF, krylov = FOM): weight_i gamma_i^(k) theta_i^(h),
   // weight_i gamma_i^(k) and theta_i^(h) for i = 0..ell/2 (Section 5), with
   // gamma^(k) = F^{-T}[e_{ell-s+1}..e_ell] A_s^T e_k, theta^(h) = F e_h
+  // (the second also weights the BDF capacitance product's frequency sums)
   std::vector<double> bg_ct, bg_gt, bg_tt;
-  if (p->krylov == PD_KRYLOV_FOM && p->bdf_s > 1) {
+  if (p->bdf_s > 1) {
     const int s = p->bdf_s;
     bg_ct.assign(2 * (size_t)s * s * F2, 0.0);
     bg_gt.assign(2 * (size_t)s * F2, 0.0);
@@ -760,7 +762,10 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   PD_TRY(dev_alloc(&p->fac32, std::max(fac32.size(), L.fac)));
   PD_TRY(dev_alloc(&p->twd, twd.size()));
   if (p->dims == 2 || p->bdf_s > 1) PD_TRY(dev_alloc(&p->wreal, (size_t)ell * nbar));
-  if (p->bdf_s > 1) PD_TRY(dev_alloc(&p->wz, L.wz));
+  if (p->bdf_s > 1) {
+    PD_TRY(dev_alloc(&p->wz, L.wz));
+    PD_TRY(dev_alloc(&p->bdf_g, L.bdfg));
+  }
   PD_TRY(dev_alloc(reinterpret_cast<unsigned char **>(&p->spec), p->spec_bytes));
   PD_TRY(dev_alloc(&p->partials, L.partials));
   PD_TRY(dev_alloc(&p->rstage, L.rstage));
@@ -805,6 +810,7 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   PD_TRY(upload(p->fac64, fac, p->stream));
   PD_TRY(upload(p->fac32, fac32, p->stream));
   PD_TRY(upload(p->twd, twd, p->stream));
+  if (p->bdf_s > 1) PD_TRY(upload(p->bdf_g, bg_gt, p->stream));
   if (p->krylov == PD_KRYLOV_FOM) {
     std::vector<double> mf;
     pd_fom_mass_factors(p, mf);

@@ -53,18 +53,23 @@ def _solve(lib, n, ell, tau, M, K, s, U0, F, tol=1e-12, **kw):
         lib.paradiag_plan_destroy(plan)
 
 
-@pytest.mark.parametrize("kind,n,ell,s", [
-    ("fd1", 15, 16, 2), ("fem1", 15, 16, 3), ("fd1", 63, 32, 4), ("fem1", 63, 64, 5),
-    ("fd1", 127, 16, 6), ("fem1", 255, 128, 2), ("fd1", 1000, 64, 3), ("fem1", 2047, 32, 6)])
-def test_bdf_solve_matches_stepping(lib, kind, n, ell, s):
+@pytest.mark.parametrize("kind,n,ell,s,tol", [
+    ("fd1", 15, 16, 2, 1e-10), ("fem1", 15, 16, 3, 1e-10), ("fd1", 63, 32, 4, 1e-10),
+    ("fem1", 63, 64, 5, 1e-10), ("fd1", 127, 16, 6, 1e-10), ("fem1", 255, 128, 2, 1e-10),
+    ("fd1", 1000, 64, 3, 1e-10), ("fem1", 2047, 32, 6, 1e-10), ("fd1", 2, 4, 2, 1e-10),
+    ("fem1", 3, 8, 4, 1e-10), ("fd1", 5, 16, 6, 1e-10), ("fem1", 8191, 16, 3, 1e-9)])
+def test_bdf_solve_matches_stepping(lib, kind, n, ell, s, tol):
     """Ragged and power-of-two n, every order: U against sequential BDF
-    stepping (sparse LU), #PinT = iterations + 2, residual reported."""
+    stepping (sparse LU), #PinT = iterations + 2, residual reported.  Random
+    data excites every mode, so two correct float64 solvers differ by up to
+    about kappa u (kappa = tau beta lambda_max(M^{-1} K) ~ 3e7 for the FEM
+    n = 8191, ell = 16 case: tol 1e-9 there)."""
     M, K, tau, U0, F = _problem(kind, n, ell, s, 100 * s + n)
     U, info = _solve(lib, n, ell, tau, M, K, s, U0, F)
     Msp, Ksp = spatial_matrices(M, K, 1)
     ref = bdf.step_bdf(Msp, Ksp, tau, s, list(U0), F)
     err = allatonce.rel_err(U, ref)
-    assert err < 1e-10, (err, info.as_dict())
+    assert err < tol, (err, info.as_dict())
     assert info.pint_loops == info.gmres_iters + 2
     assert 0 <= info.rel_residual < 1e-10
 
@@ -226,7 +231,7 @@ def _bg_solve(lib, p, U0, s, tol, **kw):
 @pytest.mark.parametrize("kind,n,ell,T_,s", [
     ("fd1", 15, 16, 1.0, 3), ("fd1", 31, 16, 1.0, 2), ("fd1", 31, 16, 1.0, 6),
     ("fem1", 31, 16, 1.0, 3), ("fd1", 127, 16, 4.0, 3), ("fem1", 511, 32, 10.0, 2),
-    ("fem1", 511, 32, 10.0, 3)])
+    ("fem1", 511, 32, 10.0, 3), ("fd1", 9, 16, 1.0, 3), ("fem1", 4, 8, 1.0, 2)])
 def test_block_galerkin_matches_oracle(lib, kind, n, ell, T_, s):
     """Same number of block steps as the oracle's block Galerkin method at
     the same tolerance (tol/100 on ||r|| / ||b||; one step either way at the
