@@ -20,6 +20,7 @@
 // pass-C kernel on a zero spectrum, which writes -h).  The basis dimension
 // s m is at most BG_SMAX and at most n (where the block space is all of R^n).
 #include "pd_internal.h"
+#include "pd_gj.h"
 
 #include <cmath>
 #include <vector>
@@ -144,74 +145,40 @@ bg_proj_kernel(int n, int sm, int s, const Cx *__restrict__ hs, size_t sstride,
   }
 }
 
-// One thread per frequency i: S_i = (nu_i I + T_m)^{-1} by Gauss-Jordan with
-// partial pivoting in the thread's scratch [sm][2 sm]; L_i = the last s rows
-// of S_i (E_m^T S_i); E_i = S_i - proj_i t_{m+1,m} L_i.
+// One wave per frequency i: S_i = (nu_i I + T_m)^{-1} by Gauss-Jordan in LDS
+// (wave_gj_inverse); L_i = the last s rows of S_i (E_m^T S_i);
+// E_i = S_i - proj_i t_{m+1,m} L_i.  Lane c writes column c.
 __global__ void __launch_bounds__(64)
 bg_small_kernel(int F2, int sm, int s, int m, const double *__restrict__ lam,
                 const double *__restrict__ T, int ldT, const Cx *__restrict__ proj,
-                Cx *__restrict__ scratch, Cx *__restrict__ E, Cx *__restrict__ L) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= F2) return;
-  const int W = 2 * sm;
-  Cx *a = scratch + (size_t)i * SMX * 2 * SMX;
-  const Cx nu = {lam[2 * i], lam[2 * i + 1]};
-  for (int r = 0; r < sm; ++r)
-    for (int c = 0; c < W; ++c) {
-      Cx v = {0.0, 0.0};
-      if (c < sm) {
-        v.re = T[(size_t)r * ldT + c];
-        if (r == c) { v.re += nu.re; v.im += nu.im; }
-      } else if (c - sm == r) {
-        v.re = 1.0;
-      }
-      a[r * W + c] = v;
-    }
-  for (int col = 0; col < sm; ++col) {
-    int piv = col;
-    double best = -1.0;
-    for (int r = col; r < sm; ++r) {
-      const Cx v = a[r * W + col];
-      const double mag = v.re * v.re + v.im * v.im;
-      if (mag > best) { best = mag; piv = r; }
-    }
-    if (piv != col)
-      for (int c = 0; c < W; ++c) {
-        const Cx t = a[col * W + c];
-        a[col * W + c] = a[piv * W + c];
-        a[piv * W + c] = t;
-      }
-    const Cx inv = crecip(a[col * W + col]);
-    for (int c = 0; c < W; ++c) a[col * W + c] = cmul(a[col * W + c], inv);
-    for (int r = 0; r < sm; ++r) {
-      if (r == col) continue;
-      const Cx f = a[r * W + col];
-      for (int c = 0; c < W; ++c) a[r * W + c] = csub(a[r * W + c], cmul(f, a[col * W + c]));
-    }
-  }
+                Cx *__restrict__ E, Cx *__restrict__ L) {
+  __shared__ Cx a[SMX][2 * SMX];
+  __shared__ Cx fcol[SMX];
+  const int i = blockIdx.x, c = threadIdx.x;
+  wave_gj_inverse<SMX>(sm, Cx{lam[2 * i], lam[2 * i + 1]}, T, ldT, a, fcol);
+  if (c >= sm) return;
   Cx *Li = L + (size_t)i * 6 * SMX;
-  for (int q = 0; q < s; ++q)
-    for (int c = 0; c < sm; ++c) Li[q * SMX + c] = a[(sm - s + q) * W + sm + c];
+  Cx lc[6];
+  for (int q = 0; q < s; ++q) {
+    lc[q] = a[sm - s + q][sm + c];
+    Li[q * SMX + c] = lc[q];
+  }
   // t_{m+1,m}: rows sm..sm+s-1, columns (m-1)s..ms-1 of T (upper triangular)
   const int c0 = (m - 1) * s;
   Cx *Ei = E + (size_t)i * SMX * SMX;
   for (int r = 0; r < sm; ++r) {
-    Cx pr[6];
-    for (int q = 0; q < s; ++q) {       // (proj_i t)_{r,q}
-      Cx acc = {0.0, 0.0};
+    Cx e = a[r][sm + c];
+    for (int q = 0; q < s; ++q) {       // (proj_i t)_{r,q} L_i[q][c]
+      Cx pq = {0.0, 0.0};
       for (int j = 0; j <= q; ++j) {
         const double t = T[(size_t)(sm + j) * ldT + c0 + q];
         const Cx pv = proj[((size_t)i * SMX + r) * 6 + j];
-        acc.re += pv.re * t;
-        acc.im += pv.im * t;
+        pq.re += pv.re * t;
+        pq.im += pv.im * t;
       }
-      pr[q] = acc;
+      e = csub(e, cmul(pq, lc[q]));
     }
-    for (int c = 0; c < sm; ++c) {
-      Cx e = a[r * W + sm + c];
-      for (int q = 0; q < s; ++q) e = csub(e, cmul(pr[q], Li[q * SMX + c]));
-      Ei[r * SMX + c] = e;
-    }
+    Ei[r * SMX + c] = e;
   }
 }
 
@@ -337,22 +304,47 @@ bg_cw_kernel(int F2, int sm, int s, int m, const Cx *__restrict__ L,
   }
 }
 
-// z_k[row] = sum_i sum_j Re(cw[i][k][j] h_i^(j)[row]) (hs_j = -h^(j)).
+// zpart[ch][k][row] = -sum over the ch-th chunk of frequencies i of
+// sum_j Re(cw[i][k][j] h_i^(j)[row]) (hs_j = -h^(j)).  Block: 64 rows x 4
+// frequency lanes; grid (ceil(n/64), NCH).
 __global__ void __launch_bounds__(256)
 bg_wsum_kernel(int n, int F2, int s, const Cx *__restrict__ hs, size_t sstride,
-               const Cx *__restrict__ cw, double *__restrict__ z) {
-  const int row = blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= n) return;
+               const Cx *__restrict__ cw, double *__restrict__ zpart) {
+  __shared__ double sh[4][6][64];
+  const int col = threadIdx.x & 63, lane = threadIdx.x >> 6;
+  const int row = blockIdx.x * 64 + col, ch = blockIdx.y;
+  const int per = (F2 + NCH - 1) / NCH;
+  const int i0 = ch * per, i1 = (i0 + per < F2) ? i0 + per : F2;
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int i = 0; i < F2; ++i)
-    for (int j = 0; j < s; ++j) {
-      const Cx h = hs[j * sstride + (size_t)i * n + row];
-      for (int k = 0; k < s; ++k) {
-        const Cx c = cw[((size_t)i * 6 + k) * 6 + j];
-        acc[k] -= c.re * h.re - c.im * h.im;
+  if (row < n)
+    for (int i = i0 + lane; i < i1; i += 4)
+      for (int j = 0; j < s; ++j) {
+        const Cx h = hs[j * sstride + (size_t)i * n + row];
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+          if (k < s) {
+            const Cx c = cw[((size_t)i * 6 + k) * 6 + j];
+            acc[k] -= c.re * h.re - c.im * h.im;
+          }
       }
-    }
-  for (int k = 0; k < s; ++k) z[(size_t)k * n + row] = acc[k];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) sh[lane][k][col] = acc[k];
+  __syncthreads();
+  if (lane == 0 && row < n)
+    for (int k = 0; k < s; ++k)
+      zpart[((size_t)ch * 6 + k) * n + row] =
+          sh[0][k][col] + sh[1][k][col] + sh[2][k][col] + sh[3][k][col];
+}
+
+// z[k][row] = sum_ch zpart[ch][k][row] (fixed order).  Grid (ceil(n/256), s).
+__global__ void __launch_bounds__(256)
+bg_wfinish_kernel(int n, const double *__restrict__ zpart, double *__restrict__ z) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (row >= n) return;
+  double acc = 0.0;
+  for (int ch = 0; ch < NCH; ++ch) acc += zpart[((size_t)ch * 6 + k) * n + row];
+  z[(size_t)k * n + row] = acc;
 }
 
 // state[1] = sqrt(sum_k ||(I - V V^T) z_k||^2) (two projection passes).
@@ -441,7 +433,6 @@ BgLayout pd_bgal_layout(int n, int F2) {
   L.T = take((size_t)BG_TROWS * BG_LDT);
   L.beta = take(36);
   L.proj = take(2 * (size_t)F2 * SMX * 6);
-  L.scratch = take(2 * (size_t)F2 * SMX * 2 * SMX);
   L.E = take(2 * (size_t)F2 * SMX * SMX);
   L.L = take(2 * (size_t)F2 * 6 * SMX);
   L.part = take((size_t)NCH * 36 * SMX * SMX);
@@ -449,6 +440,7 @@ BgLayout pd_bgal_layout(int n, int F2) {
   L.y = take(NMAX);
   L.cw = take(2 * (size_t)F2 * 36);
   L.z = take(6 * (size_t)n);
+  L.zpart = take((size_t)NCH * 6 * n);
   L.state = take(8);
   L.mfac = take(12 * 15);
   L.ctab = take(2 * (size_t)36 * F2);
@@ -470,7 +462,6 @@ pd_status pd_bgal(pd_plan p, const double *b, double *x, double rtol, int *iters
   double *T = base + Lo.T;
   double *beta = base + Lo.beta;
   Cx *proj = reinterpret_cast<Cx *>(base + Lo.proj);
-  Cx *scratch = reinterpret_cast<Cx *>(base + Lo.scratch);
   Cx *E = reinterpret_cast<Cx *>(base + Lo.E);
   Cx *Lr = reinterpret_cast<Cx *>(base + Lo.L);
   double *part = base + Lo.part;
@@ -478,6 +469,7 @@ pd_status pd_bgal(pd_plan p, const double *b, double *x, double rtol, int *iters
   double *y = base + Lo.y;
   Cx *cw = reinterpret_cast<Cx *>(base + Lo.cw);
   double *z = base + Lo.z;
+  double *zpart = base + Lo.zpart;
   double *state = base + Lo.state;
   const Cx *mfac = reinterpret_cast<const Cx *>(base + Lo.mfac);
   const Cx *ctab = reinterpret_cast<const Cx *>(base + Lo.ctab);
@@ -526,16 +518,18 @@ pd_status pd_bgal(pd_plan p, const double *b, double *x, double rtol, int *iters
     }
     hipLaunchKernelGGL(bg_proj_kernel, dim3(F2), dim3(256), 0, p->stream, n, sm, s, hs, sstride,
                        V, proj);
-    hipLaunchKernelGGL(bg_small_kernel, dim3((F2 + 63) / 64), dim3(64), 0, p->stream, F2, sm, s,
-                       m, p->lam64, T, BG_LDT, proj, scratch, E, Lr);
+    hipLaunchKernelGGL(bg_small_kernel, dim3(F2), dim3(64), 0, p->stream, F2, sm, s, m, p->lam64,
+                       T, BG_LDT, proj, E, Lr);
     hipLaunchKernelGGL(bg_assemble_kernel, dim3((sm * sm + 255) / 256, NCH), dim3(256), 0,
                        p->stream, F2, sm, s, ctab, E, part);
     hipLaunchKernelGGL(bg_solve_kernel, dim3(1), dim3(256), 0, p->stream, sm, s, part, beta, G,
                        y);
     hipLaunchKernelGGL(bg_cw_kernel, dim3((F2 + 63) / 64), dim3(64), 0, p->stream, F2, sm, s, m,
                        Lr, T, BG_LDT, thtab, gtab, y, cw);
-    hipLaunchKernelGGL(bg_wsum_kernel, dim3((n + 255) / 256), dim3(256), 0, p->stream, n, F2, s,
-                       hs, sstride, cw, z);
+    hipLaunchKernelGGL(bg_wsum_kernel, dim3((n + 63) / 64, NCH), dim3(256), 0, p->stream, n, F2,
+                       s, hs, sstride, cw, zpart);
+    hipLaunchKernelGGL(bg_wfinish_kernel, dim3((n + 255) / 256, s), dim3(256), 0, p->stream, n,
+                       zpart, z);
     hipLaunchKernelGGL(bg_resid_kernel, dim3(1), dim3(FB), 0, p->stream, n, sm, s, V, z, state);
     PD_HIP_CHECK(hipGetLastError());
     double hst[2];

@@ -19,6 +19,7 @@
 // V_m^T h_i, per frequency S_i by Gauss-Jordan, the m x m system for y, the
 // weighted sum z = sum_i c_i h_i and the projected norm.
 #include "pd_internal.h"
+#include "pd_gj.h"
 #include "pd_partition.h"
 
 #include <cmath>
@@ -183,67 +184,30 @@ fom_proj_kernel(int n, int m, const cpx<double> *__restrict__ hs, const double *
   }
 }
 
-// Per frequency i (one thread each): S_i = (lambda_i I + T_m)^{-1} by
-// Gauss-Jordan with partial pivoting in the thread's scratch [m][2m]; the
-// last row of S_i, and Zpart_i = Re(w g_i (S_i - t p_i (e_m^T S_i)))
-// (g_i = weight * gamma_i, the conjugate half folded in).
+// Per frequency i (one wave each): S_i = (lambda_i I + T_m)^{-1} by
+// Gauss-Jordan in LDS (wave_gj_inverse); the last row of S_i, and
+// Zpart_i = Re(w g_i (S_i - t p_i (e_m^T S_i))) (g_i = weight * gamma_i, the
+// conjugate half folded in).  Lane c writes column c.
 template <int FM_>
 __global__ void __launch_bounds__(64)
 fom_small_kernel(int F2, int m, const double *__restrict__ lam, const double *__restrict__ gB,
                  double w, const double *__restrict__ T, const cpx<double> *__restrict__ proj,
-                 cpx<double> *__restrict__ scratch, double *__restrict__ Zpart,
-                 cpx<double> *__restrict__ lastrow) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= F2) return;
+                 double *__restrict__ Zpart, cpx<double> *__restrict__ lastrow) {
   using Cx = cpx<double>;
-  const int W = 2 * m;
-  Cx *a = scratch + (size_t)i * FM_ * 2 * FM_;
-  const Cx li = {lam[2 * i], lam[2 * i + 1]};
-  for (int r = 0; r < m; ++r)
-    for (int c = 0; c < W; ++c) {
-      Cx v = {0.0, 0.0};
-      if (c < m) {
-        v.re = T[(size_t)r * FM_ + c];
-        if (r == c) { v.re += li.re; v.im += li.im; }
-      } else if (c - m == r) {
-        v.re = 1.0;
-      }
-      a[r * W + c] = v;
-    }
-  for (int col = 0; col < m; ++col) {
-    int piv = col;
-    double best = -1.0;
-    for (int r = col; r < m; ++r) {
-      const Cx v = a[r * W + col];
-      const double mag = v.re * v.re + v.im * v.im;
-      if (mag > best) { best = mag; piv = r; }
-    }
-    if (piv != col)
-      for (int c = 0; c < W; ++c) {
-        const Cx t = a[col * W + c];
-        a[col * W + c] = a[piv * W + c];
-        a[piv * W + c] = t;
-      }
-    const Cx inv = crecip(a[col * W + col]);
-    for (int c = 0; c < W; ++c) a[col * W + c] = cmul(a[col * W + c], inv);
-    for (int r = 0; r < m; ++r) {
-      if (r == col) continue;
-      const Cx f = a[r * W + col];
-      for (int c = 0; c < W; ++c) a[r * W + c] = csub(a[r * W + c], cmul(f, a[col * W + c]));
-    }
-  }
+  __shared__ Cx a[FM_][2 * FM_];
+  __shared__ Cx fcol[FM_];
+  const int i = blockIdx.x, c = threadIdx.x;
+  wave_gj_inverse<FM_>(m, Cx{lam[2 * i], lam[2 * i + 1]}, T, FM_, a, fcol);
   // S_i = right half of a
+  if (c >= m) return;
   const double t = T[(size_t)m * FM_ + (m - 1)];
   const Cx g = {w * gB[2 * i], w * gB[2 * i + 1]};
-  for (int c = 0; c < m; ++c) lastrow[(size_t)i * FM_ + c] = a[(m - 1) * W + m + c];
+  const Cx last = a[m - 1][m + c];
+  lastrow[(size_t)i * FM_ + c] = last;
   for (int r = 0; r < m; ++r) {
     const Cx pr = proj[(size_t)i * FM_ + r];
-    for (int c = 0; c < m; ++c) {
-      const Cx sv = a[r * W + m + c];
-      const Cx last = a[(m - 1) * W + m + c];
-      const Cx e = csub(sv, cmul(Cx{t * pr.re, t * pr.im}, last));
-      Zpart[(size_t)i * FM_ * FM_ + r * FM_ + c] = g.re * e.re - g.im * e.im;
-    }
+    const Cx e = csub(a[r][m + c], cmul(Cx{t * pr.re, t * pr.im}, last));
+    Zpart[(size_t)i * FM_ * FM_ + r * FM_ + c] = g.re * e.re - g.im * e.im;
   }
 }
 
@@ -303,17 +267,37 @@ fom_solve_kernel(int F2, int m, const double *__restrict__ Zpart,
   }
 }
 
-// z[row] = s * sum_i Re(c_i hs_i[row])  (hs = -w h, s = -1/w)
+constexpr int WCH = 16;   // frequency chunks of the weighted sum
+
+// zpart[ch][row] = sum over the ch-th chunk of frequencies of Re(c_i hs_i[row]).
+// Block: 64 rows x 4 frequency lanes; grid (ceil(n/64), WCH).
 __global__ void __launch_bounds__(256)
 fom_wsum_kernel(int n, int F2, const cpx<double> *__restrict__ hs,
-                const cpx<double> *__restrict__ cvec, double s, double *__restrict__ z) {
+                const cpx<double> *__restrict__ cvec, double *__restrict__ zpart) {
+  __shared__ double sh[4][64];
+  const int col = threadIdx.x & 63, lane = threadIdx.x >> 6;
+  const int row = blockIdx.x * 64 + col, ch = blockIdx.y;
+  const int per = (F2 + WCH - 1) / WCH;
+  const int i0 = ch * per, i1 = (i0 + per < F2) ? i0 + per : F2;
+  double acc = 0.0;
+  if (row < n)
+    for (int i = i0 + lane; i < i1; i += 4) {
+      const cpx<double> h = hs[(size_t)i * n + row], c = cvec[i];
+      acc += c.re * h.re - c.im * h.im;
+    }
+  sh[lane][col] = acc;
+  __syncthreads();
+  if (lane == 0 && row < n)
+    zpart[(size_t)ch * n + row] = sh[0][col] + sh[1][col] + sh[2][col] + sh[3][col];
+}
+
+// z[row] = s * sum_ch zpart[ch][row] (hs = -w h, s = -1/w)
+__global__ void __launch_bounds__(256)
+fom_wfinish_kernel(int n, const double *__restrict__ zpart, double s, double *__restrict__ z) {
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= n) return;
   double acc = 0.0;
-  for (int i = 0; i < F2; ++i) {
-    const cpx<double> h = hs[(size_t)i * n + row], c = cvec[i];
-    acc += c.re * h.re - c.im * h.im;
-  }
+  for (int ch = 0; ch < WCH; ++ch) acc += zpart[(size_t)ch * n + row];
   z[row] = s * acc;
 }
 
@@ -384,14 +368,14 @@ size_t pd_fom_doubles(int n, int F2) {
   const size_t FM = PD_FOM_MAXM;
   return (FM + 1) * FM                // T
          + 2 * (size_t)F2 * FM        // proj
-         + 2 * (size_t)F2 * FM * 2 * FM   // Gauss-Jordan scratch
          + (size_t)F2 * FM * FM       // Zpart
          + 2 * (size_t)F2 * FM        // last rows of S_i
          + FM                         // y
          + 2 * (size_t)F2             // c_i
          + 4                          // beta, residual
          + 12 * 15                    // mass factors (16 rows per thread)
-         + (size_t)n;                 // z
+         + (size_t)n                  // z
+         + (size_t)WCH * n;           // chunk partials of z
 }
 
 bool pd_fom_supported(pd_plan p) {
@@ -400,8 +384,8 @@ bool pd_fom_supported(pd_plan p) {
 
 size_t pd_fom_mfac_offset(int F2) {
   const size_t FM = PD_FOM_MAXM;
-  return (FM + 1) * FM + 2 * (size_t)F2 * FM + 2 * (size_t)F2 * FM * 2 * FM +
-         (size_t)F2 * FM * FM + 2 * (size_t)F2 * FM + FM + 2 * (size_t)F2 + 4;
+  return (FM + 1) * FM + 2 * (size_t)F2 * FM + (size_t)F2 * FM * FM + 2 * (size_t)F2 * FM + FM +
+         2 * (size_t)F2 + 4;
 }
 
 pd_status pd_fom(pd_plan p, const double *b, double *x, double rtol, int *iters,
@@ -412,14 +396,14 @@ pd_status pd_fom(pd_plan p, const double *b, double *x, double rtol, int *iters,
   const int q = p->fom_q < 1 ? 1 : p->fom_q;
   double *T = p->fom;
   auto proj = reinterpret_cast<cpx<double> *>(T + (FM + 1) * FM);
-  auto scratch = proj + (size_t)F2 * FM;
-  double *Zpart = reinterpret_cast<double *>(scratch + (size_t)F2 * FM * 2 * FM);
+  double *Zpart = reinterpret_cast<double *>(proj + (size_t)F2 * FM);
   auto lastrow = reinterpret_cast<cpx<double> *>(Zpart + (size_t)F2 * FM * FM);
   double *y = reinterpret_cast<double *>(lastrow + (size_t)F2 * FM);
   auto cvec = reinterpret_cast<cpx<double> *>(y + FM);
   double *state = reinterpret_cast<double *>(cvec + F2);
   auto mfac = reinterpret_cast<const cpx<double> *>(state + 4);
   double *z = state + 4 + 12 * 15;
+  double *zpart = z + n;
   auto hs = reinterpret_cast<cpx<double> *>(p->fom_h);
   const double s = -1.0 / p->w;
   const int P = (n + 15) / 16;
@@ -445,12 +429,14 @@ pd_status pd_fom(pd_plan p, const double *b, double *x, double rtol, int *iters,
     if (st != PD_OK) return st;
     hipLaunchKernelGGL((fom_proj_kernel<FM>), dim3(F2), dim3(256), 0, p->stream, n, m, hs, p->V,
                        s, proj);
-    hipLaunchKernelGGL((fom_small_kernel<FM>), dim3((F2 + 63) / 64), dim3(64), 0, p->stream, F2, m,
-                       p->lam64, p->gB64, p->w, T, proj, scratch, Zpart, lastrow);
+    hipLaunchKernelGGL((fom_small_kernel<FM>), dim3(F2), dim3(64), 0, p->stream, F2, m, p->lam64,
+                       p->gB64, p->w, T, proj, Zpart, lastrow);
     hipLaunchKernelGGL((fom_solve_kernel<FM>), dim3(1), dim3(FB), 0, p->stream, F2, m, Zpart,
                        lastrow, p->gB64, state, y, cvec);
-    hipLaunchKernelGGL(fom_wsum_kernel, dim3((n + 255) / 256), dim3(256), 0, p->stream, n, F2, hs,
-                       cvec, s, z);
+    hipLaunchKernelGGL(fom_wsum_kernel, dim3((n + 63) / 64, WCH), dim3(256), 0, p->stream, n, F2,
+                       hs, cvec, zpart);
+    hipLaunchKernelGGL(fom_wfinish_kernel, dim3((n + 255) / 256), dim3(256), 0, p->stream, n, zpart,
+                       s, z);
     hipLaunchKernelGGL((fom_resid_kernel<FM>), dim3(1), dim3(FB), 0, p->stream, n, m, p->V, z, T,
                        p->w, state);
     PD_HIP_CHECK(hipGetLastError());

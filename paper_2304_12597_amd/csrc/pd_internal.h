@@ -302,7 +302,7 @@ constexpr int BG_SMAX = 32;
 constexpr int BG_TROWS = BG_SMAX + 6;
 constexpr int BG_LDT = BG_SMAX;
 struct BgLayout {
-  size_t T, beta, proj, scratch, E, L, part, G, y, cw, z, state, mfac, ctab, gtab, thtab, total;
+  size_t T, beta, proj, E, L, part, G, y, cw, z, zpart, state, mfac, ctab, gtab, thtab, total;
 };
 BgLayout pd_bgal_layout(int n, int F2);
 pd_status pd_bgal(pd_plan p, const double *b, double *x, double rtol, int *iters,
