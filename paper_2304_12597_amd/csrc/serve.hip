@@ -25,6 +25,8 @@ namespace {
 
 struct Key {
   int n, ell, dims, prec, maxit, max_sweeps;
+  // every other option a plan is built with (all but the stream)
+  int check_residual, autotune, early_exit, shifted_solver, krylov, fom_q, bdf_order;
   double tau, alpha;
   std::vector<double> m, k;   // M (empty = identity) and K, row-major triples
   bool operator<(const Key &o) const {
@@ -34,6 +36,12 @@ struct Key {
     if (prec != o.prec) return prec < o.prec;
     if (maxit != o.maxit) return maxit < o.maxit;
     if (max_sweeps != o.max_sweeps) return max_sweeps < o.max_sweeps;
+    const int a[7] = {check_residual, autotune, early_exit, shifted_solver, krylov, fom_q,
+                      bdf_order};
+    const int b[7] = {o.check_residual, o.autotune, o.early_exit, o.shifted_solver, o.krylov,
+                      o.fom_q, o.bdf_order};
+    for (int q = 0; q < 7; ++q)
+      if (a[q] != b[q]) return a[q] < b[q];
     if (tau != o.tau) return tau < o.tau;
     if (alpha != o.alpha) return alpha < o.alpha;
     if (m != o.m) return m < o.m;
@@ -251,6 +259,13 @@ extern "C" pd_status pd_server_submit(pd_server s, const pd_request *req, long *
   job->key.prec = req->opt.precision;
   job->key.maxit = req->opt.maxit;
   job->key.max_sweeps = req->opt.max_sweeps;
+  job->key.check_residual = req->opt.check_residual;
+  job->key.autotune = req->opt.autotune;
+  job->key.early_exit = req->opt.early_exit;
+  job->key.shifted_solver = req->opt.shifted_solver;
+  job->key.krylov = req->opt.krylov;
+  job->key.fom_q = req->opt.fom_q;
+  job->key.bdf_order = req->opt.bdf_order;
   job->key.tau = req->tau;
   job->key.alpha = req->opt.alpha;
   job->key.m = job->mcopy;
@@ -261,7 +276,9 @@ extern "C" pd_status pd_server_submit(pd_server s, const pd_request *req, long *
   job->req.M = req->M ? &job->M : nullptr;
   job->req.K = &job->K;
   const size_t nbar = (req->opt.dims == 2) ? (size_t)n * n : (size_t)n;
-  job->io_bytes = (2 * (size_t)req->ell * nbar + nbar) * sizeof(double);
+  // F and U, plus u0 (BDF: the s starting values)
+  const size_t starts = req->opt.bdf_order > 1 ? (size_t)req->opt.bdf_order : 1;
+  job->io_bytes = (2 * (size_t)req->ell * nbar + starts * nbar) * sizeof(double);
   job->plan_bytes = paradiag_plan_bytes(req->n, req->ell, &req->opt);
   if (job->plan_bytes == 0) {
     pd_set_error("pd_server_submit: unsupported problem");

@@ -107,6 +107,37 @@ def test_server_budget_and_cache(lib):
         assert np.array_equal(U.cpu().numpy(), ref)
 
 
+def test_server_keeps_plans_apart_by_options(lib):
+    """Requests for the same problem with different methods (backward Euler,
+    BDF2, the sine basis, Algorithm 2) each get a plan built with their own
+    options: the plan cache keys on every option."""
+    from oracle import bdf
+    p = wl.heat_1d("fem1", 255, 16, 10.0, 1.0, np.random.default_rng(9), True)
+    variants = [({}, p.u0, modal.modal_solution(p)),
+                ({"bdf_order": 2}, np.tile(p.u0, (2, 1)), bdf.modal_bdf(p, 2)),
+                ({"shifted_solver": lib.PD_SHIFTED_SINE}, p.u0, modal.modal_solution(p)),
+                ({"krylov": lib.PD_KRYLOV_FOM}, p.u0, modal.modal_solution(p)),
+                ({"bdf_order": 3}, np.tile(p.u0, (3, 1)), bdf.modal_bdf(p, 3))]
+    srv = lib.pd_server_create(2, 4 << 30)
+    try:
+        F = T(p.F)
+        bufs = [(T(u0), torch.empty((p.ell, p.nbar), dtype=torch.float64, device=dev()))
+                for _, u0, _ in variants]
+        torch.cuda.synchronize()
+        ts = [lib.pd_server_submit(srv, p.n, p.ell, p.tau, p.M, p.K, u0, F, U, 1e-10, **kw)
+              for (kw, _, _), (u0, U) in zip(variants, bufs)]
+        for t in ts:
+            done, st, info = lib.pd_server_wait(srv, t, -1)
+            assert done and st == 0, (st, info.as_dict())
+        stats = lib.pd_server_stats(srv)
+        assert stats["cache_misses"] == len(variants)
+    finally:
+        lib.pd_server_destroy(srv)
+    for (kw, _, ref), (_, U) in zip(variants, bufs):
+        err = allatonce.rel_err(U.cpu().numpy(), ref)
+        assert err < 1e-9, (kw, err)
+
+
 def test_solve_batch_matches_individual(lib):
     probs = [p for p in mixed_problems(5) if p.dims == 1][:5]
     alone = [solve_alone(lib, p) for p in probs]
