@@ -228,11 +228,35 @@ bg_solve_kernel(int sm, int s, const double *__restrict__ part, const double *__
     G[(size_t)row * ld + N] = (r < s) ? beta[r * 6 + k] : 0.0;
   }
   __syncthreads();
+  __shared__ double wmag[4];
+  __shared__ int widx[4];
   for (int col = 0; col < N; ++col) {
+    // pivot: the first row r >= col with the largest |G[r][col]| (one row
+    // per thread, N <= 256; wave argmax by shuffles, then over the waves)
+    double mag = -1.0;
+    int idx = tid;
+    if (tid >= col && tid < N) mag = fabs(G[(size_t)tid * ld + col]);
+    for (int off = 32; off > 0; off >>= 1) {
+      const double om = __shfl_xor(mag, off, 64);
+      const int oi = __shfl_xor(idx, off, 64);
+      if (om > mag || (om == mag && oi < idx)) {
+        mag = om;
+        idx = oi;
+      }
+    }
+    if ((tid & 63) == 0) {
+      wmag[tid >> 6] = mag;
+      widx[tid >> 6] = idx;
+    }
+    __syncthreads();
     if (tid == 0) {
-      int p = col;
-      for (int r = col + 1; r < N; ++r)
-        if (fabs(G[(size_t)r * ld + col]) > fabs(G[(size_t)p * ld + col])) p = r;
+      int p = widx[0];
+      double best = wmag[0];
+      for (int w = 1; w < 4; ++w)
+        if (wmag[w] > best) {
+          best = wmag[w];
+          p = widx[w];
+        }
       piv_s = p;
     }
     __syncthreads();

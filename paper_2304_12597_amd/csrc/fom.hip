@@ -211,11 +211,29 @@ fom_small_kernel(int F2, int m, const double *__restrict__ lam, const double *__
   }
 }
 
-// Z = I + sum_i Zpart_i (fixed order), y = Z^{-1} beta e_1 (partial
+constexpr int ZCH = 16;   // frequency chunks of the Galerkin-matrix sums
+
+// zp[ch][r][c] = sum over the ch-th chunk of frequencies of Zpart_i[r][c].
+// Grid: (ceil(m^2 / 256), ZCH).
+template <int FM_>
+__global__ void __launch_bounds__(256)
+fom_zsum_kernel(int F2, int m, const double *__restrict__ Zpart, double *__restrict__ zp) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int ch = blockIdx.y;
+  if (e >= m * m) return;
+  const int r = e / m, c = e - r * m;
+  const int per = (F2 + ZCH - 1) / ZCH;
+  const int i0 = ch * per, i1 = (i0 + per < F2) ? i0 + per : F2;
+  double s = 0.0;
+  for (int i = i0; i < i1; ++i) s += Zpart[(size_t)i * FM_ * FM_ + r * FM_ + c];
+  zp[(size_t)ch * FM_ * FM_ + r * FM_ + c] = s;
+}
+
+// Z = I + sum of the chunk sums (fixed order), y = Z^{-1} beta e_1 (partial
 // pivoting), c_i = g_i (e_m^T S_i y).
 template <int FM_>
 __global__ void __launch_bounds__(FB)
-fom_solve_kernel(int F2, int m, const double *__restrict__ Zpart,
+fom_solve_kernel(int F2, int m, const double *__restrict__ zp,
                  const cpx<double> *__restrict__ lastrow, const double *__restrict__ gB,
                  const double *__restrict__ state, double *__restrict__ y,
                  cpx<double> *__restrict__ cvec) {
@@ -225,13 +243,15 @@ fom_solve_kernel(int F2, int m, const double *__restrict__ Zpart,
   for (int e = tid; e < m * m; e += FB) {
     const int r = e / m, c = e - r * m;
     double s = (r == c) ? 1.0 : 0.0;
-    for (int i = 0; i < F2; ++i) s += Zpart[(size_t)i * FM_ * FM_ + r * FM_ + c];
+    for (int ch = 0; ch < ZCH; ++ch) s += zp[(size_t)ch * FM_ * FM_ + r * FM_ + c];
     Z[r][c] = s;
   }
+  for (int r = tid; r < m; r += FB) Z[r][FM_] = (r == 0) ? state[0] : 0.0;
   __syncthreads();
-  if (tid == 0) {
-    for (int r = 0; r < m; ++r) Z[r][FM_] = (r == 0) ? state[0] : 0.0;
-    for (int col = 0; col < m; ++col) {
+  // Gaussian elimination with partial pivoting, the rows below the pivot
+  // updated in parallel
+  for (int col = 0; col < m; ++col) {
+    if (tid == 0) {
       int piv = col;
       for (int r = col + 1; r < m; ++r)
         if (fabs(Z[r][col]) > fabs(Z[piv][col])) piv = r;
@@ -241,12 +261,17 @@ fom_solve_kernel(int F2, int m, const double *__restrict__ Zpart,
           Z[col][c] = Z[piv][c];
           Z[piv][c] = t;
         }
-      for (int r = col + 1; r < m; ++r) {
-        const double f = Z[r][col] / Z[col][col];
-        for (int c = col; c < m; ++c) Z[r][c] -= f * Z[col][c];
-        Z[r][FM_] -= f * Z[col][FM_];
-      }
     }
+    __syncthreads();
+    const int r = col + 1 + tid;
+    if (r < m) {
+      const double f = Z[r][col] / Z[col][col];
+      for (int c = col; c < m; ++c) Z[r][c] -= f * Z[col][c];
+      Z[r][FM_] -= f * Z[col][FM_];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
     for (int r = m - 1; r >= 0; --r) {
       double s = Z[r][FM_];
       for (int c = r + 1; c < m; ++c) s -= Z[r][c] * ys[c];
@@ -375,7 +400,8 @@ size_t pd_fom_doubles(int n, int F2) {
          + 4                          // beta, residual
          + 12 * 15                    // mass factors (16 rows per thread)
          + (size_t)n                  // z
-         + (size_t)WCH * n;           // chunk partials of z
+         + (size_t)WCH * n            // chunk partials of z
+         + (size_t)ZCH * FM * FM;     // chunk sums of the Galerkin matrix
 }
 
 bool pd_fom_supported(pd_plan p) {
@@ -404,6 +430,7 @@ pd_status pd_fom(pd_plan p, const double *b, double *x, double rtol, int *iters,
   auto mfac = reinterpret_cast<const cpx<double> *>(state + 4);
   double *z = state + 4 + 12 * 15;
   double *zpart = z + n;
+  double *zp = zpart + (size_t)WCH * n;
   auto hs = reinterpret_cast<cpx<double> *>(p->fom_h);
   const double s = -1.0 / p->w;
   const int P = (n + 15) / 16;
@@ -431,7 +458,9 @@ pd_status pd_fom(pd_plan p, const double *b, double *x, double rtol, int *iters,
                        s, proj);
     hipLaunchKernelGGL((fom_small_kernel<FM>), dim3(F2), dim3(64), 0, p->stream, F2, m, p->lam64,
                        p->gB64, p->w, T, proj, Zpart, lastrow);
-    hipLaunchKernelGGL((fom_solve_kernel<FM>), dim3(1), dim3(FB), 0, p->stream, F2, m, Zpart,
+    hipLaunchKernelGGL((fom_zsum_kernel<FM>), dim3((m * m + 255) / 256, ZCH), dim3(256), 0,
+                       p->stream, F2, m, Zpart, zp);
+    hipLaunchKernelGGL((fom_solve_kernel<FM>), dim3(1), dim3(FB), 0, p->stream, F2, m, zp,
                        lastrow, p->gB64, state, y, cvec);
     hipLaunchKernelGGL(fom_wsum_kernel, dim3((n + 63) / 64, WCH), dim3(256), 0, p->stream, n, F2,
                        hs, cvec, zpart);
