@@ -21,6 +21,7 @@
 // s m is at most BG_SMAX and at most n (where the block space is all of R^n).
 #include "pd_internal.h"
 #include "pd_gj.h"
+#include "pd_proj.h"
 
 #include <cmath>
 #include <vector>
@@ -101,47 +102,19 @@ bg_orth_kernel(int n, int cnt, int col, int ldT, double *__restrict__ V,
   }
 }
 
-// proj[i][k][j] = (V_k . h_i^(j)) for k < sm, j < s; one block per
-// frequency.  hs_j holds -h^(j) (pass C on a zero spectrum), spectra
-// `sstride` complex elements apart.
+// proj[i][k][j] = (V_k . h_i^(j)) for k < sm, j < s (hs_j holds -h^(j),
+// spectra `sstride` complex elements apart).  Grid: (ceil(F2 / PROJ_PT),
+// ceil(sm / PROJ_PK), s) tiles.
 __global__ void __launch_bounds__(256)
-bg_proj_kernel(int n, int sm, int s, const Cx *__restrict__ hs, size_t sstride,
+bg_proj_kernel(int n, int F2, int sm, const Cx *__restrict__ hs, size_t sstride,
                const double *__restrict__ V, Cx *__restrict__ proj) {
-  __shared__ double pr[SMX][4], pim[SMX][4];
-  const int i = blockIdx.x, tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
-  for (int j = 0; j < s; ++j) {
-    const Cx *h = hs + j * sstride + (size_t)i * n;
-    double ar[SMX], ai[SMX];
-#pragma unroll
-    for (int k = 0; k < SMX; ++k) { ar[k] = 0.0; ai[k] = 0.0; }
-    for (int row = tid; row < n; row += 256) {
-      const Cx hv = h[row];
-#pragma unroll
-      for (int k = 0; k < SMX; ++k)
-        if (k < sm) {
-          const double vk = V[(size_t)k * n + row];
-          ar[k] += vk * hv.re;
-          ai[k] += vk * hv.im;
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < SMX; ++k) {
-      if (k < sm) {
-        double a = ar[k], b = ai[k];
-        for (int off = 32; off > 0; off >>= 1) {
-          a += __shfl_xor(a, off, 64);
-          b += __shfl_xor(b, off, 64);
-        }
-        if (lane == 0) { pr[k][wid] = a; pim[k][wid] = b; }
-      }
-    }
-    __syncthreads();
-    if (tid < sm) {
-      double a = 0.0, b = 0.0;
-      for (int q = 0; q < 4; ++q) { a += pr[tid][q]; b += pim[tid][q]; }
-      proj[((size_t)i * SMX + tid) * 6 + j] = Cx{-a, -b};
-    }
-    __syncthreads();
+  const int i0 = blockIdx.x * PROJ_PT, k0 = blockIdx.y * PROJ_PK, j = blockIdx.z;
+  Cx v;
+  proj_tile(n, F2, sm, V, hs + j * sstride, i0, k0, v);
+  const int t = threadIdx.x;
+  if (t < PROJ_PK * PROJ_PT) {
+    const int k = k0 + t / PROJ_PT, i = i0 + t % PROJ_PT;
+    if (k < sm && i < F2) proj[((size_t)i * SMX + k) * 6 + j] = Cx{-v.re, -v.im};
   }
 }
 
@@ -540,8 +513,9 @@ pd_status pd_bgal(pd_plan p, const double *b, double *x, double rtol, int *iters
       pd_status st = pd_launch_tridiag(p, 1, hj, V + (size_t)(sm + j) * n, hj);
       if (st != PD_OK) return st;
     }
-    hipLaunchKernelGGL(bg_proj_kernel, dim3(F2), dim3(256), 0, p->stream, n, sm, s, hs, sstride,
-                       V, proj);
+    hipLaunchKernelGGL(bg_proj_kernel,
+                       dim3((F2 + PROJ_PT - 1) / PROJ_PT, (sm + PROJ_PK - 1) / PROJ_PK, s),
+                       dim3(256), 0, p->stream, n, F2, sm, hs, sstride, V, proj);
     hipLaunchKernelGGL(bg_small_kernel, dim3(F2), dim3(64), 0, p->stream, F2, sm, s, m, p->lam64,
                        T, BG_LDT, proj, E, Lr);
     hipLaunchKernelGGL(bg_assemble_kernel, dim3((sm * sm + 255) / 256, NCH), dim3(256), 0,

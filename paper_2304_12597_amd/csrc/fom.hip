@@ -21,6 +21,7 @@
 #include "pd_internal.h"
 #include "pd_gj.h"
 #include "pd_partition.h"
+#include "pd_proj.h"
 
 #include <cmath>
 #include <vector>
@@ -143,44 +144,19 @@ fom_orth_kernel(int n, int m, double *__restrict__ V, const double *__restrict__
   }
 }
 
-// proj[i][k] = s * sum_rows V[k][row] * hs_i[row], one block per frequency
-// (hs holds -w h_i; s = -1/w).
+// proj[i][k] = s * sum_rows V[k][row] * hs_i[row] (hs holds -w h_i;
+// s = -1/w).  Grid: (ceil(F2 / PROJ_PT), ceil(m / PROJ_PK)) tiles.
 template <int FM_>
 __global__ void __launch_bounds__(256)
-fom_proj_kernel(int n, int m, const cpx<double> *__restrict__ hs, const double *__restrict__ V,
-                double s, cpx<double> *__restrict__ proj) {
-  __shared__ double pr[FM_][4], pi[FM_][4];
-  const int i = blockIdx.x, tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
-  const cpx<double> *h = hs + (size_t)i * n;
-  double ar[FM_], ai[FM_];
-#pragma unroll
-  for (int k = 0; k < FM_; ++k) { ar[k] = 0.0; ai[k] = 0.0; }
-  for (int row = tid; row < n; row += 256) {
-    const cpx<double> hv = h[row];
-#pragma unroll
-    for (int k = 0; k < FM_; ++k)
-      if (k < m) {
-        const double vk = V[(size_t)k * n + row];
-        ar[k] += vk * hv.re;
-        ai[k] += vk * hv.im;
-      }
-  }
-#pragma unroll
-  for (int k = 0; k < FM_; ++k) {
-    if (k < m) {
-      double a = ar[k], b = ai[k];
-      for (int off = 32; off > 0; off >>= 1) {
-        a += __shfl_xor(a, off, 64);
-        b += __shfl_xor(b, off, 64);
-      }
-      if (lane == 0) { pr[k][wid] = a; pi[k][wid] = b; }
-    }
-  }
-  __syncthreads();
-  if (tid < m) {
-    double a = 0.0, b = 0.0;
-    for (int q = 0; q < 4; ++q) { a += pr[tid][q]; b += pi[tid][q]; }
-    proj[(size_t)i * FM_ + tid] = cpx<double>{s * a, s * b};
+fom_proj_kernel(int n, int F2, int m, const cpx<double> *__restrict__ hs,
+                const double *__restrict__ V, double s, cpx<double> *__restrict__ proj) {
+  const int i0 = blockIdx.x * PROJ_PT, k0 = blockIdx.y * PROJ_PK;
+  cpx<double> v;
+  proj_tile(n, F2, m, V, hs, i0, k0, v);
+  const int t = threadIdx.x;
+  if (t < PROJ_PK * PROJ_PT) {
+    const int k = k0 + t / PROJ_PT, i = i0 + t % PROJ_PT;
+    if (k < m && i < F2) proj[(size_t)i * FM_ + k] = cpx<double>{s * v.re, s * v.im};
   }
 }
 
@@ -454,8 +430,9 @@ pd_status pd_fom(pd_plan p, const double *b, double *x, double rtol, int *iters,
     PD_HIP_CHECK(hipMemsetAsync(p->fom_h, 0, p->spec_bytes, p->stream));
     pd_status st = pd_launch_tridiag(p, 1, p->fom_h, p->V + (size_t)m * n, p->fom_h);
     if (st != PD_OK) return st;
-    hipLaunchKernelGGL((fom_proj_kernel<FM>), dim3(F2), dim3(256), 0, p->stream, n, m, hs, p->V,
-                       s, proj);
+    hipLaunchKernelGGL((fom_proj_kernel<FM>),
+                       dim3((F2 + PROJ_PT - 1) / PROJ_PT, (m + PROJ_PK - 1) / PROJ_PK), dim3(256),
+                       0, p->stream, n, F2, m, hs, p->V, s, proj);
     hipLaunchKernelGGL((fom_small_kernel<FM>), dim3(F2), dim3(64), 0, p->stream, F2, m, p->lam64,
                        p->gB64, p->w, T, proj, Zpart, lastrow);
     hipLaunchKernelGGL((fom_zsum_kernel<FM>), dim3((m * m + 255) / 256, ZCH), dim3(256), 0,
