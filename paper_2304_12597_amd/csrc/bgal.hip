@@ -487,6 +487,23 @@ pd_status pd_bgal(pd_plan p, const double *b, double *x, double rtol, int *iters
   PD_HIP_CHECK(hipMemsetAsync(T, 0, sizeof(double) * BG_TROWS * BG_LDT, p->stream));
   PD_HIP_CHECK(hipMemsetAsync(beta, 0, sizeof(double) * 36, p->stream));
   hipLaunchKernelGGL(bg_norm_kernel, dim3(1), dim3(FB), 0, p->stream, s * n, b, state);
+  {
+    // b = 0 (zero data): x = 0, no Krylov space to build
+    double b0 = 0.0;
+    PD_HIP_CHECK(hipMemcpyAsync(&b0, state, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    PD_HIP_CHECK(hipStreamSynchronize(p->stream));
+    if (!std::isfinite(b0)) {
+      pd_set_error("capacitance right-hand side is not finite");
+      return PD_ENONFINITE;
+    }
+    if (b0 == 0.0) {
+      PD_HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * (size_t)s * n, p->stream));
+      if (iters) *iters = 0;
+      if (relres) *relres = 0.0;
+      if (checks) *checks = 0;
+      return PD_OK;
+    }
+  }
   // B = V_1 beta (Gram-Schmidt QR of the s starting columns, beta ld 6)
   for (int j = 0; j < s; ++j)
     hipLaunchKernelGGL(bg_orth_kernel, dim3(1), dim3(FB), 0, p->stream, n, j, j, 6, V,

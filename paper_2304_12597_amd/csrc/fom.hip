@@ -413,6 +413,23 @@ pd_status pd_fom(pd_plan p, const double *b, double *x, double rtol, int *iters,
   hipLaunchKernelGGL(fom_start_kernel, dim3(1), dim3(FB), 0, p->stream, n, b, p->V, T,
                      (FM + 1) * FM, state);
   PD_HIP_CHECK(hipGetLastError());
+  {
+    // b = 0 (zero data): x = 0, no Krylov space to build
+    double b0 = 0.0;
+    PD_HIP_CHECK(hipMemcpyAsync(&b0, state, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    PD_HIP_CHECK(hipStreamSynchronize(p->stream));
+    if (!std::isfinite(b0)) {
+      pd_set_error("capacitance right-hand side is not finite");
+      return PD_ENONFINITE;
+    }
+    if (b0 == 0.0) {
+      PD_HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * n, p->stream));
+      if (iters) *iters = 0;
+      if (relres) *relres = 0.0;
+      if (checks) *checks = 0;
+      return PD_OK;
+    }
+  }
   double beta = 0.0, res = 0.0;
   int m = 0;
   bool checked = false;

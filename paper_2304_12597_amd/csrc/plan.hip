@@ -459,6 +459,10 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
                  "solves, no early_exit and ell >= 2 * bdf_order");
     return PD_ENOTSUP;
   }
+  if (opt.bdf_order > 1 && opt.krylov == PD_KRYLOV_FOM && n < opt.bdf_order) {
+    pd_set_error("the block Galerkin method needs n >= bdf_order");
+    return PD_ENOTSUP;
+  }
   if (opt.shifted_solver == PD_SHIFTED_SINE) {
     if (opt.dims != 1 || opt.precision != PD_FP64 || !is_pow2(n + 1) || n + 1 < 16) {
       pd_set_error("sine-basis solves need a 1D float64 plan with n + 1 a power of two >= 16");

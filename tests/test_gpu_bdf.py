@@ -288,3 +288,21 @@ def test_block_galerkin_step_cap_is_reported(lib):
         assert e.value.status == lib.PD_ENOTCONV
     finally:
         lib.paradiag_plan_destroy(plan)
+
+
+def test_block_galerkin_zero_data_and_small_n(lib):
+    """Zero data gives x = 0 and U = 0 without building a block space; a
+    block Galerkin plan needs n >= s."""
+    n, ell, s = 31, 16, 3
+    M, K = wl.fem_mass(n), wl.fem_stiffness(n, 1.0)
+    plan = _plan(lib, n, ell, 1.0 / ell, M, K, s, krylov=lib.PD_KRYLOV_FOM)
+    try:
+        U = torch.full((ell, n), 7.0, dtype=torch.float64, device=dev())
+        info = lib.paradiag_solve(plan, T(np.zeros((s, n))), T(np.zeros((ell, n))), U, 1e-10)
+        torch.cuda.synchronize()
+        assert info.gmres_iters == 0
+        assert not U.cpu().numpy().any()
+    finally:
+        lib.paradiag_plan_destroy(plan)
+    with pytest.raises(RuntimeError):
+        _plan(lib, 3, 16, 1.0 / 16, None, wl.fd_laplacian(3, 1.0), 4, krylov=lib.PD_KRYLOV_FOM)

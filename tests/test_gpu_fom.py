@@ -106,3 +106,19 @@ def test_fom_rejects_unsupported(lib):
     K[1][3] *= 1.1                         # not constant-diagonal
     with pytest.raises(RuntimeError):
         lib.paradiag_plan_create(p.n, p.ell, p.tau, p.M, K, krylov=lib.PD_KRYLOV_FOM)
+
+
+def test_fom_zero_data(lib):
+    """u0 = 0 and F = 0: b = 0, the method returns x = 0 at once and U = 0
+    (no Krylov space is built from a zero vector)."""
+    p = make_problem("fem1", 63, 16, 2)
+    plan = lib.paradiag_plan_create(p.n, p.ell, p.tau, p.M, p.K, krylov=lib.PD_KRYLOV_FOM,
+                                    stream=torch.cuda.current_stream().cuda_stream)
+    try:
+        U = torch.full((p.ell, p.nbar), 7.0, dtype=torch.float64, device=dev())
+        info = lib.paradiag_solve(plan, T(np.zeros(p.n)), T(np.zeros((p.ell, p.n))), U, 1e-10)
+        torch.cuda.synchronize()
+        assert info.gmres_iters == 0
+        assert not U.cpu().numpy().any()
+    finally:
+        lib.paradiag_plan_destroy(plan)
