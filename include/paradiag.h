@@ -120,8 +120,9 @@ typedef struct {
   int fom_q;           /* PD_KRYLOV_FOM: residual check every fom_q steps   */
   int bdf_order;       /* s = 1..6: BDF of order s in time (Section 5,      */
                        /* table of BDF coefficients); 1 = backward Euler.   */
-                       /* s > 1: 1D, PD_FP64, alpha 1, partition solves,   */
-                       /* no early_exit, ell >= 2 s; u0 holds the           */
+                       /* s > 1: PD_FP64, alpha 1, partition solves (1D or */
+                       /* 2D; block Galerkin: 1D), no early_exit, ell >= 2s; */
+                       /* u0 holds the                                      */
                        /* s starting values u_{1-s}..u_0 as [s][nbar] and   */
                        /* capacitance vectors are [s][nbar]                 */
 } pd_options;

@@ -240,12 +240,34 @@ def block_galerkin(Msp, Ksp, tau, s, pieces, eps=1e-12, maxit=40):
 
 
 def modal_bdf(p, s):
-    """Exact discrete BDF-s solution of a 1D ``workloads.HeatProblem`` whose
-    s initial values all equal u0 (scalar recurrence per sine mode)."""
+    """Exact discrete BDF-s solution of a ``workloads.HeatProblem`` whose
+    s starting values all equal u0 (scalar recurrence per sine mode; 2D:
+    per pair of modes with the eigenvalues of T added, f = 0)."""
     beta, alpha = coefficients(s)
     n, ell, tau, h = p.n, p.ell, p.tau, p.h
     x = np.arange(1, n + 1) * h
 
+    def series(m_k, kap, c0, a, b):
+        hist = [c0] * s
+        out = np.empty(ell)
+        for j in range(1, ell + 1):
+            acc = tau * beta * (a * np.cos(b * j * tau) if a != 0.0 else 0.0)
+            for q in range(1, s + 1):
+                acc += alpha[q - 1] * hist[-q]
+            c = acc / (1.0 + tau * beta * kap / m_k)
+            hist.append(c)
+            out[j - 1] = c
+        return out
+
+    if p.dims == 2:
+        if p.src_a.size:
+            raise ValueError("2D modal oracle supports f = 0 only")
+        U = np.zeros((ell, n, n))
+        for (k, m), c0 in p.u0_modes.items():
+            kap = _toeplitz_symbol(p.K, k, h) + _toeplitz_symbol(p.K, m, h)
+            U += series(1.0, kap, c0, 0.0, 0.0)[:, None, None] * \
+                np.outer(np.sin(m * np.pi * x), np.sin(k * np.pi * x))[None]
+        return U.reshape(ell, n * n)
     coeffs = {}
     for k, c in p.u0_modes.items():
         coeffs[k] = [c, 0.0, 0.0]
@@ -257,14 +279,5 @@ def modal_bdf(p, s):
     for k, (c0, a, b) in sorted(coeffs.items()):
         m_k = 1.0 if p.M is None else _toeplitz_symbol(p.M, k, h)
         kap = _toeplitz_symbol(p.K, k, h)
-        hist = [c0] * s
-        series = np.empty(ell)
-        for j in range(1, ell + 1):
-            acc = tau * beta * (a * np.cos(b * j * tau) if a != 0.0 else 0.0)
-            for q in range(1, s + 1):
-                acc += alpha[q - 1] * hist[-q]
-            c = acc / (1.0 + tau * beta * kap / m_k)
-            hist.append(c)
-            series[j - 1] = c
-        U += np.outer(series, np.sin(k * np.pi * x))
+        U += np.outer(series(m_k, kap, c0, a, b), np.sin(k * np.pi * x))
     return U

@@ -114,14 +114,15 @@ bdf_gather_kernel(int n, int F2, int s, const cpx<double> *__restrict__ g,
                                            sh[3][k][col];
 }
 
-// out[k][i] = v[k][i] + sum_ch part[ch][k][i] (fixed order).  Grid: (ceil(n/BB), s).
+// out[k][i] = v[k][i] (0 if v is NULL) + sum_ch part[ch][k][i] (fixed order).
+// Grid: (ceil(n/BB), s).
 __global__ void __launch_bounds__(BB)
 bdf_finish_kernel(int n, int s, const double *__restrict__ v, const double *__restrict__ part,
                   double *__restrict__ out) {
   const int i = blockIdx.x * BB + threadIdx.x;
   const int k = blockIdx.y;
   if (i >= n) return;
-  double acc = v[(size_t)k * n + i];
+  double acc = v ? v[(size_t)k * n + i] : 0.0;
   for (int ch = 0; ch < PD_BDF_GCH; ++ch) acc += part[((size_t)ch * s + k) * n + i];
   out[(size_t)k * n + i] = acc;
 }
@@ -208,6 +209,63 @@ bdf_residual_kernel(int n, int ell, int s, double tb, BdfAlpha c, const double *
   }
 }
 
+// 2D (M = I, K = I (x) T + T (x) I, coef holding tau beta T): partial sums of
+// ||G - A(U)||^2 and ||G||^2 at the points i = y n + x of every time row t,
+//   G_t = sum_{j>t} alpha_j u_{t+1-j} + tau beta f_t,
+//   A(U)_t = u_t + tau beta K u_t - sum_{j<=t} alpha_j u_{t-j}.
+// Grid: (ceil(nbar/BB), RES_ROWS); red as for the 1D kernel.
+__global__ void __launch_bounds__(BB)
+bdf_residual2d_kernel(int n, int ell, int s, double tb, BdfAlpha c,
+                      const double *__restrict__ u0s, const double *__restrict__ F,
+                      const double *__restrict__ U, const double *__restrict__ coef,
+                      double *__restrict__ red) {
+  __shared__ double sr[BB / 64], sg[BB / 64];
+  const int nbar = n * n;
+  const int i = blockIdx.x * BB + threadIdx.x;
+  double rn = 0.0, gn = 0.0;
+  if (i < nbar) {
+    const int y = i / n, x = i - y * n;
+    const double *KL = coef + 3 * n, *KD = coef + 4 * n, *KU = coef + 5 * n;
+    for (int t = blockIdx.y; t < ell; t += gridDim.y) {
+      const double *Ut = U + (size_t)t * nbar;
+      double g = tb * F[(size_t)t * nbar + i];
+      double w = -Ut[i];
+      for (int j = 1; j <= s; ++j) {
+        if (j > t) g += c.a[j - 1] * u0s[(size_t)(s + t - j) * nbar + i];
+        else w += c.a[j - 1] * U[(size_t)(t - j) * nbar + i];
+      }
+      double ku = (KD[x] + KD[y]) * Ut[i];
+      if (x > 0) ku += KL[x] * Ut[i - 1];
+      if (x < n - 1) ku += KU[x] * Ut[i + 1];
+      if (y > 0) ku += KL[y] * Ut[i - n];
+      if (y < n - 1) ku += KU[y] * Ut[i + n];
+      const double r = w + g - ku;
+      rn += r * r;
+      gn += g * g;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    rn += __shfl_down(rn, off, 64);
+    gn += __shfl_down(gn, off, 64);
+  }
+  const int wid = threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (lane == 0) {
+    sr[wid] = rn;
+    sg[wid] = gn;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < BB / 64; ++w) {
+      a += sr[w];
+      b += sg[w];
+    }
+    const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    red[2 * blk] = a;
+    red[2 * blk + 1] = b;
+  }
+}
+
 BdfAlpha alpha_of(pd_plan p) {
   BdfAlpha c;
   for (int j = 0; j < 6; ++j) c.a[j] = p->bdf_alpha[j];
@@ -224,17 +282,23 @@ BdfBlock block_of(pd_plan p) {
 }
 
 bool bdf_plan_ok(pd_plan p) {
-  if (p->bdf_s < 2 || p->bdf_s > 6 || p->dims != 1 || !p->wreal || !p->wz || !p->bdf_g ||
-      p->ell < 2 * p->bdf_s) {
+  if (p->bdf_s < 2 || p->bdf_s > 6 || !p->wreal || !p->wz || !p->bdf_g ||
+      p->ell < 2 * p->bdf_s || (p->dims == 2 && (!p->bdf_h || !p->bdf_t))) {
     pd_set_error("not a BDF plan of order > 1");
     return false;
   }
   return true;
 }
 
-// p->spec = the half spectrum of X(sign * v)
+// p->spec = the half spectrum of X(sign * v); 2D plans first take the s
+// rows of v to the DST-x domain of the shifted solves.
 pd_status spectrum_of(pd_plan p, const double *v, double sign) {
-  const int n = p->n;
+  const int n = p->nbar;
+  if (p->dims == 2) {
+    pd_status st = pd_launch_dst_x_rows(p, v, p->bdf_t, p->bdf_s, 0);
+    if (st != PD_OK) return st;
+    v = p->bdf_t;
+  }
   hipLaunchKernelGGL(bdf_spec_kernel, dim3((n + BB - 1) / BB, p->F2), dim3(BB), 0, p->stream, n,
                      p->ell, p->bdf_s, sign, v, reinterpret_cast<const cpx<double> *>(p->tw64),
                      reinterpret_cast<cpx<double> *>(p->spec));
@@ -242,18 +306,19 @@ pd_status spectrum_of(pd_plan p, const double *v, double sign) {
   return PD_OK;
 }
 
-// out (= or +=) IFFT(P^{-1} M FFT(p->wreal)): forward transform, shifted
-// solves with x = 0 in place, inverse transform.
+// out (= or +=) the inverse transform of P^{-1} M FFT(p->wreal): forward
+// transform, shifted solves with x = 0 in place, inverse transform (2D: p->wreal
+// is in the DST-x domain and the result is taken back to space).
 pd_status transform_solve(pd_plan p, double *out, int accumulate) {
   pd_status st = pd_launch_fft_forward(p, nullptr, p->wreal, nullptr, p->spec, 2);
   if (st != PD_OK) return st;
   st = pd_launch_tridiag(p, 1, p->spec, nullptr, p->spec);
   if (st != PD_OK) return st;
-  return pd_launch_fft_inverse(p, p->spec, out, accumulate);
+  return pd_inverse(p, p->spec, out, accumulate);
 }
 
 pd_status extract(pd_plan p, const double *v, const double *Z, double *out) {
-  const int n = p->n, s = p->bdf_s;
+  const int n = p->nbar, s = p->bdf_s;
   hipLaunchKernelGGL(bdf_extract_kernel, dim3((n + BB - 1) / BB, s), dim3(BB), 0, p->stream, n,
                      p->ell, s, block_of(p), v, Z, out);
   PD_HIP_CHECK(hipGetLastError());
@@ -263,12 +328,12 @@ pd_status extract(pd_plan p, const double *v, const double *Z, double *out) {
 }  // namespace
 
 int pd_bdf_residual_blocks(pd_plan p) {
-  return ((p->n + BB - 1) / BB) * std::min(p->ell, RES_ROWS);
+  return ((p->nbar + BB - 1) / BB) * std::min(p->ell, RES_ROWS);
 }
 
 pd_status pd_bdf_rhs(pd_plan p, const double *u0s, const double *F, double *out) {
   if (!bdf_plan_ok(p)) return PD_ENOTSUP;
-  const int n = p->n;
+  const int n = p->nbar;
   hipLaunchKernelGGL(bdf_rhs_kernel, dim3((n + BB - 1) / BB, p->ell), dim3(BB), 0, p->stream, n,
                      p->bdf_s, p->tau * p->bdf_beta, alpha_of(p), u0s, F, out);
   PD_HIP_CHECK(hipGetLastError());
@@ -277,7 +342,7 @@ pd_status pd_bdf_rhs(pd_plan p, const double *u0s, const double *F, double *out)
 
 pd_status pd_bdf_apply(pd_plan p, const double *v, double *Jv) {
   if (!bdf_plan_ok(p)) return PD_ENOTSUP;
-  const int n = p->n, s = p->bdf_s;
+  const int n = p->nbar, s = p->bdf_s;
   pd_status st = spectrum_of(p, v, 1.0);
   if (st != PD_OK) return st;
   st = pd_launch_tridiag(p, 1, p->spec, nullptr, p->spec);
@@ -285,10 +350,20 @@ pd_status pd_bdf_apply(pd_plan p, const double *v, double *Jv) {
   hipLaunchKernelGGL(bdf_gather_kernel, dim3((n + 63) / 64, PD_BDF_GCH), dim3(256), 0, p->stream,
                      n, p->F2, s, reinterpret_cast<const cpx<double> *>(p->bdf_g),
                      reinterpret_cast<const cpx<double> *>(p->spec), p->wz);
-  hipLaunchKernelGGL(bdf_finish_kernel, dim3((n + BB - 1) / BB, s), dim3(BB), 0, p->stream, n, s,
-                     v, p->wz, Jv);
+  if (p->dims == 1) {
+    hipLaunchKernelGGL(bdf_finish_kernel, dim3((n + BB - 1) / BB, s), dim3(BB), 0, p->stream, n,
+                       s, v, p->wz, Jv);
+    PD_HIP_CHECK(hipGetLastError());
+    return PD_OK;
+  }
+  // 2D: the s rows come out in the DST-x domain: Jv = v + DST-x(rows)
+  hipLaunchKernelGGL(bdf_finish_kernel, dim3((n + BB - 1) / BB, s), dim3(BB), 0, p->stream, n,
+                     s, nullptr, p->wz, p->bdf_t);
   PD_HIP_CHECK(hipGetLastError());
-  return PD_OK;
+  if (Jv != v)
+    PD_HIP_CHECK(hipMemcpyAsync(Jv, v, sizeof(double) * (size_t)s * n, hipMemcpyDeviceToDevice,
+                                p->stream));
+  return pd_launch_dst_x_rows(p, p->bdf_t, Jv, s, 1);
 }
 
 pd_status pd_bdf_residual_norms(pd_plan p, const double *u0s, const double *F,
@@ -297,9 +372,14 @@ pd_status pd_bdf_residual_norms(pd_plan p, const double *u0s, const double *F,
   const int n = p->n;
   const int gy = std::min(p->ell, RES_ROWS);
   const int nb = pd_bdf_residual_blocks(p);
-  hipLaunchKernelGGL(bdf_residual_kernel, dim3((n + BB - 1) / BB, gy), dim3(BB), 0, p->stream,
-                     n, p->ell, p->bdf_s, p->tau * p->bdf_beta, alpha_of(p), u0s, F, U,
-                     p->coef64, p->red);
+  if (p->dims == 1)
+    hipLaunchKernelGGL(bdf_residual_kernel, dim3((n + BB - 1) / BB, gy), dim3(BB), 0, p->stream,
+                       n, p->ell, p->bdf_s, p->tau * p->bdf_beta, alpha_of(p), u0s, F, U,
+                       p->coef64, p->red);
+  else
+    hipLaunchKernelGGL(bdf_residual2d_kernel, dim3((p->nbar + BB - 1) / BB, gy), dim3(BB), 0,
+                       p->stream, n, p->ell, p->bdf_s, p->tau * p->bdf_beta, alpha_of(p), u0s, F,
+                       U, p->coef64, p->red);
   PD_HIP_CHECK(hipGetLastError());
   std::vector<double> h(2 * (size_t)nb);
   PD_HIP_CHECK(hipMemcpyAsync(h.data(), p->red, h.size() * sizeof(double),
@@ -325,8 +405,13 @@ pd_status pd_bdf_residual_norms(pd_plan p, const double *u0s, const double *F,
 pd_status pd_bdf_solve(pd_plan p, const double *u0s, const double *F, double *U, double tol,
                        pd_info *info) {
   if (!bdf_plan_ok(p)) return PD_ENOTSUP;
-  pd_status st = pd_bdf_rhs(p, u0s, F, p->wreal);
+  // h into the transform input (2D: into bdf_h, then to the DST-x domain)
+  pd_status st = pd_bdf_rhs(p, u0s, F, p->dims == 2 ? p->bdf_h : p->wreal);
   if (st != PD_OK) return st;
+  if (p->dims == 2) {
+    st = pd_launch_dst_x_rows(p, p->bdf_h, p->wreal, p->ell, 0);
+    if (st != PD_OK) return st;
+  }
   st = transform_solve(p, U, 0);
   if (st != PD_OK) return st;
   st = extract(p, nullptr, U, p->bvec);
@@ -342,7 +427,7 @@ pd_status pd_bdf_solve(pd_plan p, const double *u0s, const double *F, double *U,
   if (st != PD_OK) return st;
   st = pd_launch_tridiag(p, 1, p->spec, nullptr, p->spec);
   if (st != PD_OK) return st;
-  st = pd_launch_fft_inverse(p, p->spec, U, 1);
+  st = pd_inverse(p, p->spec, U, 1);
   if (st != PD_OK) return st;
   if (info) {
     info->gmres_iters = its;

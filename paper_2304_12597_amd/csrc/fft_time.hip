@@ -494,6 +494,25 @@ pd_status pd_launch_dst_x(pd_plan p, int mode, const double *u0, const double *F
   return PD_OK;
 }
 
+// Orthonormal DST-I along x of `trows` time rows of `in` into `out` (or
+// added to it): the mode-2 transform on a [trows][nbar] array.
+pd_status pd_launch_dst_x_rows(pd_plan p, const double *in, double *out, int trows,
+                               int accumulate) {
+  DstLaunch L = dst_config(p);
+  L.blocks = (trows * p->n + 2 * L.C - 1) / (2 * L.C);
+  auto tw = reinterpret_cast<const cpx<double> *>(p->twd);
+  if (accumulate)
+    hipLaunchKernelGGL((dst_x_kernel<2, 1>), dim3(L.blocks), dim3(L.threads), L.lds, p->stream,
+                       p->n, trows, L.C, L.stride, p->tau, nullptr, nullptr, nullptr, in,
+                       p->coef64, tw, out, p->red);
+  else
+    hipLaunchKernelGGL((dst_x_kernel<2, 0>), dim3(L.blocks), dim3(L.threads), L.lds, p->stream,
+                       p->n, trows, L.C, L.stride, p->tau, nullptr, nullptr, nullptr, in,
+                       p->coef64, tw, out, p->red);
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
 pd_status pd_launch_fft_inverse(pd_plan p, const void *in, double *U, int accumulate) {
   FftLaunch L = fft_config(p);
   if (!fft_C_valid(L.C)) return PD_EINVAL;

@@ -226,6 +226,8 @@ struct pd_plan_s {
   int ncap = 0;                // capacitance vector length: s * nbar
   double *wz = nullptr;        // BDF: capacitance-product partial sums
   double *bdf_g = nullptr;     // BDF: [s][F2] complex weight_f gamma_f^(k)
+  double *bdf_h = nullptr;     // BDF 2D: [ell][nbar] h before the DST along x
+  double *bdf_t = nullptr;     // BDF 2D: [s][nbar] rows in the DST-x domain
 };
 constexpr int PD_BDF_GCH = 16;   // frequency chunks of the BDF capacitance product
 
@@ -267,6 +269,9 @@ void pd_line2d_set_attributes(size_t max_lds);
 pd_status pd_forward(pd_plan p, const double *u0, const double *F, const double *U, void *spec,
                      int residual);
 pd_status pd_inverse(pd_plan p, const void *spec, double *U, int accumulate);
+// 2D: orthonormal DST-I along x of trows time rows (in -> out, or added)
+pd_status pd_launch_dst_x_rows(pd_plan p, const double *in, double *out, int trows,
+                               int accumulate);
 int pd_forward_norm_blocks(pd_plan p);
 int pd_dst_blocks(pd_plan p);
 // sum partials: out = base + sum_g partials[g]   (base may be NULL)

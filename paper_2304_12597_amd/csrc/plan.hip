@@ -84,7 +84,7 @@ void free_plan(pd_plan p) {
   void *ptrs[] = {p->coef64, p->coef32, p->lam64, p->lam32, p->gB64, p->gJ64, p->tw64,
                   p->tw32, p->dal, p->fac64, p->fac32, p->twd, p->wreal, p->spec, p->partials, p->rstage, p->bvec, p->xvec, p->wvec, p->V,
                   p->gm, p->red, p->sine_q, p->sine_wN, p->sine_twH, p->sine_m, p->sine_k,
-                  p->fom, p->fom_h, p->wz, p->bdf_g};
+                  p->fom, p->fom_h, p->wz, p->bdf_g, p->bdf_h, p->bdf_t};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   if (p->host_pin) (void)hipHostFree(p->host_pin);
@@ -99,12 +99,12 @@ std::mutex g_attr_mu;
 // type) of a plan; shared by plan creation and paradiag_plan_bytes.
 struct Layout {
   size_t coef = 0, lam = 0, tw = 0, dal = 0, fac = 0, twd = 0, wreal = 0, wz = 0, bdfg = 0,
-         sine = 0, fom = 0;
+         bdfh = 0, bdft = 0, sine = 0, fom = 0;
   size_t fom_h_bytes = 0;
   size_t spec_bytes = 0, partials = 0, rstage = 0, vec = 0, V = 0, gm = 0, red = 0;
   size_t total_bytes() const {
     return coef * 12 + lam * 12 + 2 * lam * 8 + tw * 12 + dal * 8 + fac * 12 + twd * 8 +
-           wreal * 8 + wz * 8 + bdfg * 8 + spec_bytes + partials * 8 + rstage * 8 + 3 * vec * 8 + V * 8 + gm * 8 +
+           wreal * 8 + wz * 8 + bdfg * 8 + bdfh * 8 + bdft * 8 + spec_bytes + partials * 8 + rstage * 8 + 3 * vec * 8 + V * 8 + gm * 8 +
            red * 8 + sine * 8 + fom * 8 + fom_h_bytes;
   }
 };
@@ -175,6 +175,10 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
     L.wreal = (size_t)ell * p->nbar;
     L.wz = (size_t)PD_BDF_GCH * p->bdf_s * p->nbar;
     L.bdfg = 2 * (size_t)p->bdf_s * F2;
+    if (p->dims == 2) {
+      L.bdfh = (size_t)ell * p->nbar;
+      L.bdft = (size_t)p->bdf_s * p->nbar;
+    }
   }
   L.coef = 6 * (size_t)n;
   L.lam = 2 * (size_t)F2;
@@ -452,11 +456,11 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
     return PD_EINVAL;
   }
   if (opt.bdf_order > 1 &&
-      (opt.dims != 1 || opt.precision != PD_FP64 || opt.alpha != 1.0 ||
+      (opt.precision != PD_FP64 || opt.alpha != 1.0 ||
        opt.shifted_solver != PD_SHIFTED_PARTITION ||
        opt.early_exit != 0 || ell < 2 * opt.bdf_order)) {
-    pd_set_error("BDF plans of order > 1 need dims 1, PD_FP64, alpha 1, partition "
-                 "solves, no early_exit and ell >= 2 * bdf_order");
+    pd_set_error("BDF plans of order > 1 need PD_FP64, alpha 1, partition solves, no "
+                 "early_exit and ell >= 2 * bdf_order");
     return PD_ENOTSUP;
   }
   if (opt.bdf_order > 1 && opt.krylov == PD_KRYLOV_FOM && n < opt.bdf_order) {
@@ -769,6 +773,10 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   if (p->bdf_s > 1) {
     PD_TRY(dev_alloc(&p->wz, L.wz));
     PD_TRY(dev_alloc(&p->bdf_g, L.bdfg));
+    if (p->dims == 2) {
+      PD_TRY(dev_alloc(&p->bdf_h, L.bdfh));
+      PD_TRY(dev_alloc(&p->bdf_t, L.bdft));
+    }
   }
   PD_TRY(dev_alloc(reinterpret_cast<unsigned char **>(&p->spec), p->spec_bytes));
   PD_TRY(dev_alloc(&p->partials, L.partials));

@@ -329,8 +329,12 @@ extern "C" pd_status paradiag_forward_transform(pd_plan p, const double *u0, con
   }
   if (!check_ptrs(u0, F, Hhat)) return PD_EINVAL;
   if (p->bdf_s > 1) {
-    pd_status st = pd_bdf_rhs(p, u0, F, p->wreal);
+    pd_status st = pd_bdf_rhs(p, u0, F, p->dims == 2 ? p->bdf_h : p->wreal);
     if (st != PD_OK) return st;
+    if (p->dims == 2) {
+      st = pd_launch_dst_x_rows(p, p->bdf_h, p->wreal, p->ell, 0);
+      if (st != PD_OK) return st;
+    }
     return pd_launch_fft_forward(p, nullptr, p->wreal, nullptr, Hhat, 2);
   }
   return pd_forward(p, u0, F, nullptr, Hhat, 0);

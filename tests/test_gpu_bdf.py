@@ -204,9 +204,6 @@ def test_bdf_rejects_unsupported(lib):
             lib.paradiag_plan_create(p.n, p.ell, p.tau, p.M, p.K, **kw)
     with pytest.raises(RuntimeError):            # ell < 2 s
         lib.paradiag_plan_create(p.n, 8, p.tau, p.M, p.K, bdf_order=5)
-    q = wl.heat_2d(15, 16, 0.1, 1.0, np.random.default_rng(0))
-    with pytest.raises(RuntimeError):
-        lib.paradiag_plan_create(q.n, q.ell, q.tau, None, q.K, dims=2, bdf_order=2)
 
 
 # ------------------------------------------------ block Galerkin for J^(s) --
@@ -306,3 +303,65 @@ def test_block_galerkin_zero_data_and_small_n(lib):
         lib.paradiag_plan_destroy(plan)
     with pytest.raises(RuntimeError):
         _plan(lib, 3, 16, 1.0 / 16, None, wl.fd_laplacian(3, 1.0), 4, krylov=lib.PD_KRYLOV_FOM)
+
+
+# ------------------------------------------------------------------- 2D --
+
+@pytest.mark.parametrize("n,ell,s", [(15, 16, 2), (31, 32, 3), (15, 16, 6), (63, 16, 4)])
+def test_bdf_2d_matches_stepping(lib, n, ell, s):
+    """2D FD heat (M = I, K = I (x) T + T (x) I; the DST-x domain of the
+    shifted solves): random starting values and source, U against BDF
+    stepping with the 2D sparse matrices, and the reported residual."""
+    rng = np.random.default_rng(17 * n + s)
+    p = wl.heat_2d(n, ell, 0.1, 1.0, rng)
+    U0 = rng.standard_normal((s, p.nbar))
+    F = rng.standard_normal((ell, p.nbar))
+    plan = lib.paradiag_plan_create(p.n, p.ell, p.tau, None, p.K, dims=2, bdf_order=s,
+                                    check_residual=1, stream=_stream())
+    try:
+        U = torch.empty((ell, p.nbar), dtype=torch.float64, device=dev())
+        info = lib.paradiag_solve(plan, T(U0), T(F), U, 1e-12)
+        r = lib.paradiag_residual(plan, T(U0), T(F), U)
+        torch.cuda.synchronize()
+        got = U.cpu().numpy()
+    finally:
+        lib.paradiag_plan_destroy(plan)
+    Msp, Ksp = problem_matrices(p)
+    ref = bdf.step_bdf(Msp, Ksp, p.tau, s, list(U0), F)
+    err = allatonce.rel_err(got, ref)
+    assert err < 1e-10, (err, info.as_dict())
+    assert info.pint_loops == info.gmres_iters + 2
+    G = bdf.rhs_bdf(Msp, p.tau, s, list(U0), F)
+    res = np.linalg.norm(G - bdf.apply_bdf(Msp, Ksp, p.tau, s, got)) / np.linalg.norm(G)
+    assert abs(r - res) <= 1e-6 * res + 1e-15 and r < 1e-10
+    assert abs(info.rel_residual - r) <= 1e-12
+
+
+def test_bdf_2d_capacitance_apply(lib):
+    """The 2D block product against the oracle's dense J^(s)."""
+    n, ell, s = 7, 16, 2
+    rng = np.random.default_rng(3)
+    p = wl.heat_2d(n, ell, 0.1, 1.0, rng)
+    U0 = rng.standard_normal((s, p.nbar))
+    F = rng.standard_normal((ell, p.nbar))
+    Msp, Ksp = problem_matrices(p)
+    ref = bdf.paradiag_bdf(Msp, Ksp, p.tau, s, list(U0), F)
+    plan = lib.paradiag_plan_create(p.n, p.ell, p.tau, None, p.K, dims=2, bdf_order=s,
+                                    stream=_stream())
+    try:
+        v = rng.standard_normal(s * p.nbar)
+        Jv = torch.empty(s * p.nbar, dtype=torch.float64, device=dev())
+        lib.paradiag_capacitance_apply(plan, T(v), Jv)
+        torch.cuda.synchronize()
+        got = Jv.cpu().numpy()
+    finally:
+        lib.paradiag_plan_destroy(plan)
+    want = ref["J"] @ v
+    assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
+
+
+def test_bdf_2d_block_galerkin_rejected(lib):
+    p = wl.heat_2d(15, 16, 0.1, 1.0, np.random.default_rng(0))
+    with pytest.raises(RuntimeError):
+        lib.paradiag_plan_create(p.n, p.ell, p.tau, None, p.K, dims=2, bdf_order=2,
+                                 krylov=lib.PD_KRYLOV_FOM)

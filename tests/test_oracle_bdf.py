@@ -223,3 +223,13 @@ def test_block_galerkin_s1_is_algorithm2():
         xf, mf, _ = paradiag.fom(cap, Msp, Ksp, tau, P["b"], eps=0.0, maxit=m)
         assert mf == m
         assert np.linalg.norm(xb - xf) <= 1e-10 * np.linalg.norm(xf)
+
+
+@pytest.mark.parametrize("s", [2, 5])
+def test_modal_recurrence_2d_matches_stepping(s):
+    """2D (K = I (x) T + T (x) I, f = 0): each pair of sine modes follows the
+    scalar BDF recurrence with the sum of the two eigenvalues of T."""
+    p = wl.heat_2d(15, 16, 0.1, 1.0, np.random.default_rng(s))
+    Msp, Ksp = problem_matrices(p)
+    S = bdf.step_bdf(Msp, Ksp, p.tau, s, [p.u0] * s, p.F)
+    assert allatonce.rel_err(bdf.modal_bdf(p, s), S) < 1e-12
