@@ -560,12 +560,41 @@ def bench_bdf(args, torch, pd, wl, dev):
                               "_U": Up.cpu().numpy(), "_p": prob})
             finally:
                 pd.paradiag_plan_destroy(plan)
+    # 2D: the 511 x 511 FD workload (ell = 256, T = 0.1), GMRES
+    rows2d = []
+    p2 = wl.cfg_fd_2d()
+    F2d = torch.tensor(p2.F, device=dev)
+    U2d = torch.empty((p2.ell, p2.nbar), dtype=torch.float64, device=dev)
+    for s in (1, 2, 3):
+        u0s = torch.tensor(np.tile(p2.u0, (s, 1)), device=dev)
+        plan = pd.paradiag_plan_create(p2.n, p2.ell, p2.tau, None, p2.K, dims=2, bdf_order=s,
+                                       stream=stream.cuda_stream)
+        try:
+            for _ in range(args.warmup):
+                pd.paradiag_solve(plan, u0s, F2d, U2d, tol)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                info = pd.paradiag_solve(plan, u0s, F2d, U2d, tol)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / args.steps
+            rng = np.random.default_rng(s)
+            tt = rng.integers(0, p2.ell, 4000)
+            ii = rng.integers(0, p2.nbar, 4000)
+            samp = U2d[torch.tensor(tt, device=dev), torch.tensor(ii, device=dev)].cpu().numpy()
+            rows2d.append({"s": s, "ms": 1e3 * wall, "gmres_iters": info.gmres_iters,
+                           "pint_loops": info.pint_loops,
+                           "unknowns_per_s": p2.nbar * p2.ell / wall,
+                           "_sample": (tt, ii, samp)})
+        finally:
+            pd.paradiag_plan_destroy(plan)
     out = {"metric": "BDF-s ParaDiag solves (Section 5)", "value": None,
            "unit": "ms per solve", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "higher_is_better": False, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "heat1d-fem n=8191 ell=2048 T=1 nu=1 (16-mode source), "
                                   "u_{1-s} = ... = u_0 = u0", "tol": tol},
-           "rows": rows, "block_galerkin_rows": grows}
+           "rows": rows, "block_galerkin_rows": grows, "rows_2d": rows2d,
+           "config_2d": "heat2d-fd 511x511 ell=256 T=0.1 nu=1, u_{1-s} = ... = u_0 = u0"}
     if not args.no_cpu_baseline:
         from oracle import bdf
         from oracle.spatial import problem_matrices
@@ -576,6 +605,11 @@ def bench_bdf(args, torch, pd, wl, dev):
         for r in grows:
             ref = bdf.modal_bdf(r["_p"], r["s"])
             r["rel_err_vs_exact"] = float(np.linalg.norm(r["_U"] - ref) / np.linalg.norm(ref))
+        for r in rows2d:
+            tt, ii, samp = r["_sample"]
+            ref = bdf.modal_bdf(p2, r["s"], (tt, ii))
+            r["rel_err_vs_exact_sampled"] = float(np.linalg.norm(samp - ref) /
+                                                  np.linalg.norm(ref))
         steps = 256
         t0 = time.perf_counter()
         Ucpu = bdf.step_bdf(Msp, Ksp, p.tau, 2, [p.u0] * 2, p.F[:steps])
@@ -587,6 +621,8 @@ def bench_bdf(args, torch, pd, wl, dev):
                                          "%d steps" % (steps, p.ell)}
     for r in grows:
         del r["_U"], r["_p"]
+    for r in rows2d:
+        del r["_sample"]
     return out
 
 

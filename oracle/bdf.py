@@ -239,10 +239,11 @@ def block_galerkin(Msp, Ksp, tau, s, pieces, eps=1e-12, maxit=40):
     return x, maxit, hist
 
 
-def modal_bdf(p, s):
+def modal_bdf(p, s, sample=None):
     """Exact discrete BDF-s solution of a ``workloads.HeatProblem`` whose
     s starting values all equal u0 (scalar recurrence per sine mode; 2D:
-    per pair of modes with the eigenvalues of T added, f = 0)."""
+    per pair of modes with the eigenvalues of T added, f = 0).  2D with
+    sample = (t indices, point indices): only those values."""
     beta, alpha = coefficients(s)
     n, ell, tau, h = p.n, p.ell, p.tau, p.h
     x = np.arange(1, n + 1) * h
@@ -262,6 +263,15 @@ def modal_bdf(p, s):
     if p.dims == 2:
         if p.src_a.size:
             raise ValueError("2D modal oracle supports f = 0 only")
+        if sample is not None:                     # values at (t, i) pairs only
+            tt, ii = (np.asarray(a) for a in sample)
+            yy, xx = ii // n, ii % n
+            out = np.zeros(tt.size)
+            for (k, m), c0 in p.u0_modes.items():
+                kap = _toeplitz_symbol(p.K, k, h) + _toeplitz_symbol(p.K, m, h)
+                ser = series(1.0, kap, c0, 0.0, 0.0)
+                out += ser[tt] * np.sin(m * np.pi * x[yy]) * np.sin(k * np.pi * x[xx])
+            return out
         U = np.zeros((ell, n, n))
         for (k, m), c0 in p.u0_modes.items():
             kap = _toeplitz_symbol(p.K, k, h) + _toeplitz_symbol(p.K, m, h)

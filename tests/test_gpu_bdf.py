@@ -365,3 +365,25 @@ def test_bdf_2d_block_galerkin_rejected(lib):
     with pytest.raises(RuntimeError):
         lib.paradiag_plan_create(p.n, p.ell, p.tau, None, p.K, dims=2, bdf_order=2,
                                  krylov=lib.PD_KRYLOV_FOM)
+
+
+@pytest.mark.parametrize("s", [2, 3])
+def test_bdf_2d_full_size_sampled(lib, s):
+    """511 x 511 grid, ell = 256, T = 0.1 (the 2D FD workload), every
+    starting value u0: sampled outputs against the per-mode BDF recurrence."""
+    p = wl.cfg_fd_2d()
+    plan = lib.paradiag_plan_create(p.n, p.ell, p.tau, None, p.K, dims=2, bdf_order=s,
+                                    stream=_stream())
+    try:
+        U = torch.empty((p.ell, p.nbar), dtype=torch.float64, device=dev())
+        info = lib.paradiag_solve(plan, T(np.tile(p.u0, (s, 1))), T(p.F), U, 1e-10)
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(s)
+        tt = rng.integers(0, p.ell, 4000)
+        ii = rng.integers(0, p.nbar, 4000)
+        got = U[torch.tensor(tt, device=dev()), torch.tensor(ii, device=dev())].cpu().numpy()
+    finally:
+        lib.paradiag_plan_destroy(plan)
+    ref = bdf.modal_bdf(p, s, (tt, ii))
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert err < 1e-9, (err, info.as_dict())
