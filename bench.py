@@ -474,6 +474,34 @@ def bench_fom(args, torch, pd, wl, dev):
                 probs.append(p)
             finally:
                 pd.paradiag_plan_destroy(plan)
+    # the 2D example of Section 6.1 (f = 0, u0 = xy(x-1)(1-y), T = 1) on a
+    # 511 x 511 grid, ell = 256, inner tolerance 1e-8 as in the paper (tol
+    # 1e-6: the capacitance stopping rule is tol/100)
+    n2, ell2 = 511, 256
+    p2 = wl.heat_2d(n2, ell2, 1.0, 1.0, np.random.default_rng(1))
+    xg = np.arange(1, n2 + 1) / (n2 + 1)
+    X, Y = np.meshgrid(xg, xg)
+    u02 = torch.tensor((X * Y * (X - 1) * (1 - Y)).reshape(-1), device=dev)
+    F2d = torch.zeros((ell2, n2 * n2), dtype=torch.float64, device=dev)
+    U2d = torch.empty((ell2, n2 * n2), dtype=torch.float64, device=dev)
+    for name, extra in (("gmres", {}), ("fom_q1", dict(krylov=pd.PD_KRYLOV_FOM, fom_q=1))):
+        plan = pd.paradiag_plan_create(n2, ell2, p2.tau, None, p2.K, dims=2,
+                                       stream=stream.cuda_stream, **extra)
+        try:
+            for _ in range(args.warmup):
+                pd.paradiag_solve(plan, u02, F2d, U2d, 1e-6, allow_notconv=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                info = pd.paradiag_solve(plan, u02, F2d, U2d, 1e-6, allow_notconv=True)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / args.steps
+            rows.append({"problem": "2D Section 6.1: 511^2 ell=256 T=1 u0=xy(x-1)(1-y) tol=1e-6",
+                         "krylov": name, "ms": 1e3 * wall, "steps": info.gmres_iters,
+                         "pint_loops": info.pint_loops,
+                         "capacitance_rel_residual": info.gmres_rel_residual})
+        finally:
+            pd.paradiag_plan_destroy(plan)
     out = {"metric": "capacitance solver comparison (GMRES vs Algorithm 2)",
            "value": None, "unit": "ms per solve", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "higher_is_better": False, "dtype": "f64",

@@ -450,7 +450,7 @@ BgLayout pd_bgal_layout(int n, int F2) {
 pd_status pd_bgal(pd_plan p, const double *b, double *x, double rtol, int *iters,
                   double *relres, int *checks) {
   const int n = p->nbar, F2 = p->F2, s = p->bdf_s;
-  if (s < 1 || s > 6 || n > FB * FR || !p->fom || !p->fom_h) {
+  if (s < 1 || s > 6 || p->dims != 1 || n > FB * FR || !p->fom || !p->fom_h) {
     pd_set_error("block Galerkin: unsupported plan");
     return PD_ENOTSUP;
   }

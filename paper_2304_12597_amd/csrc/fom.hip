@@ -350,6 +350,104 @@ fom_resid_kernel(int n, int m, const double *__restrict__ V, const double *__res
   if (tid == 0) state[1] = fabs(T[(size_t)m * FM_ + (m - 1)]) * w * nrm;
 }
 
+// Multi-block vector kernels (2D plans, n up to 1023^2): classical
+// Gram-Schmidt and norms with per-block partial sums reduced by every block
+// in a fixed order.
+constexpr int MB = 256;
+constexpr int MB_MAX_BLOCKS = 256;
+constexpr int MCAP = PD_FOM_MAXM + 1;
+
+int fom_vec_blocks(int n) {
+  const int b = (n + MB - 1) / MB;
+  return b < MB_MAX_BLOCKS ? b : MB_MAX_BLOCKS;
+}
+
+// part[b * (cnt + 1) + k] = block b's share of V_k . w (k < cnt) and of
+// w . w (k = cnt).
+__global__ void __launch_bounds__(MB)
+fom_mdots_kernel(int n, int cnt, const double *__restrict__ V, const double *__restrict__ w,
+                 double *__restrict__ part) {
+  __shared__ double red[MB / 64];
+  for (int k = 0; k <= cnt; ++k) {
+    double acc = 0.0;
+    for (int row = blockIdx.x * MB + threadIdx.x; row < n; row += gridDim.x * MB) {
+      const double wr = w[row];
+      acc += (k < cnt ? V[(size_t)k * n + row] : wr) * wr;
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) part[(size_t)blockIdx.x * (cnt + 1) + k] = acc;
+  }
+}
+
+// d_k = sum_b part[b][k]; w -= sum_k d_k V_k on the block's rows; block 0
+// adds d_k to T[k * ldT + col] (T may be NULL).
+__global__ void __launch_bounds__(MB)
+fom_mupdate_kernel(int n, int cnt, int nblk, const double *__restrict__ part,
+                   const double *__restrict__ V, double *__restrict__ w, double *__restrict__ T,
+                   int ldT, int col) {
+  __shared__ double d[MCAP];
+  for (int k = threadIdx.x; k < cnt; k += MB) {
+    double acc = 0.0;
+    for (int b = 0; b < nblk; ++b) acc += part[(size_t)b * (cnt + 1) + k];
+    d[k] = acc;
+    if (T && blockIdx.x == 0) T[(size_t)k * ldT + col] += acc;
+  }
+  __syncthreads();
+  for (int row = blockIdx.x * MB + threadIdx.x; row < n; row += gridDim.x * MB) {
+    double v = w[row];
+    for (int k = 0; k < cnt; ++k) v -= d[k] * V[(size_t)k * n + row];
+    w[row] = v;
+  }
+}
+
+// t = sqrt(sum_b part[b][cnt]); V row cnt = w / t (0 if t = 0); block 0
+// writes t to T[cnt * ldT + col] (T != NULL) and to *tout (tout != NULL).
+__global__ void __launch_bounds__(MB)
+fom_mscale_kernel(int n, int cnt, int nblk, const double *__restrict__ part,
+                  const double *__restrict__ w, double *__restrict__ V, double *__restrict__ T,
+                  int ldT, int col, double *__restrict__ tout) {
+  __shared__ double tsh;
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    for (int b = 0; b < nblk; ++b) acc += part[(size_t)b * (cnt + 1) + cnt];
+    tsh = sqrt(acc);
+    if (blockIdx.x == 0) {
+      if (T) T[(size_t)cnt * ldT + col] = tsh;
+      if (tout) *tout = tsh;
+    }
+  }
+  __syncthreads();
+  const double t = tsh;
+  for (int row = blockIdx.x * MB + threadIdx.x; row < n; row += gridDim.x * MB)
+    V[(size_t)cnt * n + row] = t > 0.0 ? w[row] / t : 0.0;
+}
+
+// state[1] = |t_{m+1,m}| w sqrt(sum_b part[b][0]) (the projected norm of z)
+__global__ void fom_mres_kernel(int nblk, const double *__restrict__ part,
+                                const double *__restrict__ T, int ldT, int m, double w,
+                                double *__restrict__ state) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double acc = 0.0;
+  for (int b = 0; b < nblk; ++b) acc += part[b];
+  state[1] = fabs(T[(size_t)m * ldT + (m - 1)]) * w * sqrt(acc);
+}
+
+// 2D plans, in the DST-x domain of the line solves (index y * n + j, x-mode
+// j + 1): w = tau K v with tau K = diag(theta_j) along x plus tau T along y,
+// theta_j = tkd + 2 tku cos(pi (j + 1) / (n + 1)) (twd[j + 1].re).
+__global__ void __launch_bounds__(256)
+fom_apply2d_kernel(int n, const double *__restrict__ v, const cpx<double> *__restrict__ twd,
+                   double tkl, double tkd, double tku, double *__restrict__ w) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= n * n) return;
+  const int y = idx / n, j = idx - y * n;
+  const double th = tkd + 2.0 * tku * twd[j + 1].re;
+  double val = (th + tkd) * v[idx];
+  if (y > 0) val += tkl * v[idx - n];
+  if (y < n - 1) val += tku * v[idx + n];
+  w[idx] = val;
+}
+
 // x = V_m y
 __global__ void __launch_bounds__(256)
 fom_combine_kernel(int n, int m, const double *__restrict__ V, const double *__restrict__ y,
@@ -377,11 +475,13 @@ size_t pd_fom_doubles(int n, int F2) {
          + 12 * 15                    // mass factors (16 rows per thread)
          + (size_t)n                  // z
          + (size_t)WCH * n            // chunk partials of z
-         + (size_t)ZCH * FM * FM;     // chunk sums of the Galerkin matrix
+         + (size_t)ZCH * FM * FM      // chunk sums of the Galerkin matrix
+         + (size_t)MB_MAX_BLOCKS * MCAP;   // multi-block partial sums
 }
 
 bool pd_fom_supported(pd_plan p) {
-  return p->dims == 1 && p->prec == PD_FP64 && p->uniform && p->n <= FB * FR;
+  if (p->prec != PD_FP64 || !p->uniform) return false;
+  return p->dims == 2 || p->n <= FB * FR;
 }
 
 size_t pd_fom_mfac_offset(int F2) {
@@ -407,11 +507,33 @@ pd_status pd_fom(pd_plan p, const double *b, double *x, double rtol, int *iters,
   double *z = state + 4 + 12 * 15;
   double *zpart = z + n;
   double *zp = zpart + (size_t)WCH * n;
+  double *mpart = zp + (size_t)ZCH * FM * FM;
+  // 2D plans: multi-block vector kernels (n = n1^2) and the stencil in the
+  // DST-x domain; 1D: single-block kernels with the mass-matrix solve
+  const bool mb = p->dims == 2;
+  const int NB = fom_vec_blocks(n);
+  // two classical Gram-Schmidt passes of w against V rows 0..cnt-1 (T column
+  // col, or no T), then (T != NULL) V row cnt = w / ||w||
+  auto morth = [&](double *w, int cnt, double *Tc, int col) {
+    for (int pass = 0; pass < 2; ++pass) {
+      hipLaunchKernelGGL(fom_mdots_kernel, dim3(NB), dim3(MB), 0, p->stream, n, cnt, p->V, w,
+                         mpart);
+      hipLaunchKernelGGL(fom_mupdate_kernel, dim3(NB), dim3(MB), 0, p->stream, n, cnt, NB, mpart,
+                         p->V, w, Tc, FM, col);
+    }
+  };
   auto hs = reinterpret_cast<cpx<double> *>(p->fom_h);
   const double s = -1.0 / p->w;
   const int P = (n + 15) / 16;
-  hipLaunchKernelGGL(fom_start_kernel, dim3(1), dim3(FB), 0, p->stream, n, b, p->V, T,
-                     (FM + 1) * FM, state);
+  if (mb) {
+    PD_HIP_CHECK(hipMemsetAsync(T, 0, sizeof(double) * (FM + 1) * FM, p->stream));
+    hipLaunchKernelGGL(fom_mdots_kernel, dim3(NB), dim3(MB), 0, p->stream, n, 0, p->V, b, mpart);
+    hipLaunchKernelGGL(fom_mscale_kernel, dim3(NB), dim3(MB), 0, p->stream, n, 0, NB, mpart, b,
+                       p->V, nullptr, FM, 0, state);
+  } else {
+    hipLaunchKernelGGL(fom_start_kernel, dim3(1), dim3(FB), 0, p->stream, n, b, p->V, T,
+                       (FM + 1) * FM, state);
+  }
   PD_HIP_CHECK(hipGetLastError());
   {
     // b = 0 (zero data): x = 0, no Krylov space to build
@@ -436,11 +558,23 @@ pd_status pd_fom(pd_plan p, const double *b, double *x, double rtol, int *iters,
   int nchecks = 0;
   while (m < maxm) {
     ++m;
-    hipLaunchKernelGGL(fom_apply_kernel, dim3(1), dim3(P), 0, p->stream, n,
-                       p->V + (size_t)(m - 1) * n, mfac, p->uni[0], p->uni[2], p->uni[3],
-                       p->uni[4], p->uni[5], p->wvec);
-    hipLaunchKernelGGL((fom_orth_kernel<FM>), dim3(1), dim3(FB), 0, p->stream, n, m, p->V,
-                       p->wvec, T);
+    if (mb) {
+      hipLaunchKernelGGL(fom_apply2d_kernel, dim3((n + 255) / 256), dim3(256), 0, p->stream,
+                         p->n, p->V + (size_t)(m - 1) * n,
+                         reinterpret_cast<const cpx<double> *>(p->twd), p->uni[3], p->uni[4],
+                         p->uni[5], p->wvec);
+      morth(p->wvec, m, T, m - 1);
+      hipLaunchKernelGGL(fom_mdots_kernel, dim3(NB), dim3(MB), 0, p->stream, n, 0, p->V,
+                         p->wvec, mpart);
+      hipLaunchKernelGGL(fom_mscale_kernel, dim3(NB), dim3(MB), 0, p->stream, n, m, NB, mpart,
+                         p->wvec, p->V, T, FM, m - 1, nullptr);
+    } else {
+      hipLaunchKernelGGL(fom_apply_kernel, dim3(1), dim3(P), 0, p->stream, n,
+                         p->V + (size_t)(m - 1) * n, mfac, p->uni[0], p->uni[2], p->uni[3],
+                         p->uni[4], p->uni[5], p->wvec);
+      hipLaunchKernelGGL((fom_orth_kernel<FM>), dim3(1), dim3(FB), 0, p->stream, n, m, p->V,
+                         p->wvec, T);
+    }
     PD_HIP_CHECK(hipGetLastError());
     if (m % q != 0 && m != maxm) continue;
     // h_i for all i: pass C on a zero spectrum with x = v_{m+1} gives -w h_i
@@ -460,8 +594,16 @@ pd_status pd_fom(pd_plan p, const double *b, double *x, double rtol, int *iters,
                        hs, cvec, zpart);
     hipLaunchKernelGGL(fom_wfinish_kernel, dim3((n + 255) / 256), dim3(256), 0, p->stream, n, zpart,
                        s, z);
-    hipLaunchKernelGGL((fom_resid_kernel<FM>), dim3(1), dim3(FB), 0, p->stream, n, m, p->V, z, T,
-                       p->w, state);
+    if (mb) {
+      morth(z, m, nullptr, 0);
+      hipLaunchKernelGGL(fom_mdots_kernel, dim3(NB), dim3(MB), 0, p->stream, n, 0, p->V, z,
+                         mpart);
+      hipLaunchKernelGGL(fom_mres_kernel, dim3(1), dim3(64), 0, p->stream, NB, mpart, T, FM, m,
+                         p->w, state);
+    } else {
+      hipLaunchKernelGGL((fom_resid_kernel<FM>), dim3(1), dim3(FB), 0, p->stream, n, m, p->V, z,
+                         T, p->w, state);
+    }
     PD_HIP_CHECK(hipGetLastError());
     double hst[2];
     PD_HIP_CHECK(hipMemcpyAsync(hst, state, 2 * sizeof(double), hipMemcpyDeviceToHost, p->stream));

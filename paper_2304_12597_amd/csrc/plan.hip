@@ -168,7 +168,7 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
     L.sine = (size_t)N + 2 * (size_t)(H + 1) + 2 * (size_t)H + 2 * (size_t)n;
   }
   if (p->krylov == PD_KRYLOV_FOM) {
-    L.fom = p->bdf_s > 1 ? pd_bgal_layout(p->nbar, F2).total : pd_fom_doubles(n, F2);
+    L.fom = p->bdf_s > 1 ? pd_bgal_layout(p->nbar, F2).total : pd_fom_doubles(p->nbar, F2);
     L.fom_h_bytes = (size_t)p->bdf_s * F2 * p->nbar * cb;
   }
   if (p->bdf_s > 1) {
@@ -463,8 +463,8 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
                  "early_exit and ell >= 2 * bdf_order");
     return PD_ENOTSUP;
   }
-  if (opt.bdf_order > 1 && opt.krylov == PD_KRYLOV_FOM && n < opt.bdf_order) {
-    pd_set_error("the block Galerkin method needs n >= bdf_order");
+  if (opt.bdf_order > 1 && opt.krylov == PD_KRYLOV_FOM && (n < opt.bdf_order || opt.dims != 1)) {
+    pd_set_error("the block Galerkin method runs on 1D plans with n >= bdf_order");
     return PD_ENOTSUP;
   }
   if (opt.shifted_solver == PD_SHIFTED_SINE) {
@@ -647,7 +647,8 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
     }
   }
   if (p->krylov == PD_KRYLOV_FOM && !p->sine && !pd_fom_supported(p)) {
-    pd_set_error("Algorithm 2 runs on 1D float64 plans with constant-diagonal M and K, n <= 8192");
+    pd_set_error("Algorithm 2 runs on float64 plans with constant-diagonal M and K (1D: n <= "
+                 "8192; the block Galerkin method: 1D)");
     free_plan(p);
     return PD_ENOTSUP;
   }
