@@ -418,11 +418,24 @@ pd_status pd_bdf_solve(pd_plan p, const double *u0s, const double *F, double *U,
   if (st != PD_OK) return st;
   int its = 0, checks = 0;
   double rr = 0.0;
-  const pd_status gst =
-      p->krylov == PD_KRYLOV_FOM
-          ? pd_bgal(p, p->bvec, p->xvec, tol * PD_GMRES_TOL_FACTOR, &its, &rr, &checks)
-          : pd_gmres(p, p->bvec, p->xvec, tol * PD_GMRES_TOL_FACTOR, &its, &rr);
-  if (gst != PD_OK && gst != PD_ENOTCONV) return gst;
+  pd_status gst;
+  if (p->krylov == PD_KRYLOV_FOM && p->dims == 2) {
+    // the block Galerkin method works in the DST-x domain of the line solves:
+    // b^(s) there (its s rows), x back to space
+    const size_t sn = (size_t)p->bdf_s * p->nbar;
+    double *bd = p->wz, *xd = p->wz + sn;
+    st = pd_launch_dst_x_rows(p, p->bvec, bd, p->bdf_s, 0);
+    if (st != PD_OK) return st;
+    gst = pd_bgal(p, bd, xd, tol * PD_GMRES_TOL_FACTOR, &its, &rr, &checks);
+    if (gst != PD_OK && gst != PD_ENOTCONV) return gst;
+    st = pd_launch_dst_x_rows(p, xd, p->xvec, p->bdf_s, 0);
+    if (st != PD_OK) return st;
+  } else {
+    gst = p->krylov == PD_KRYLOV_FOM
+              ? pd_bgal(p, p->bvec, p->xvec, tol * PD_GMRES_TOL_FACTOR, &its, &rr, &checks)
+              : pd_gmres(p, p->bvec, p->xvec, tol * PD_GMRES_TOL_FACTOR, &its, &rr);
+    if (gst != PD_OK && gst != PD_ENOTCONV) return gst;
+  }
   st = spectrum_of(p, p->xvec, -1.0);
   if (st != PD_OK) return st;
   st = pd_launch_tridiag(p, 1, p->spec, nullptr, p->spec);

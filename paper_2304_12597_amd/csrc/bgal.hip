@@ -406,6 +406,11 @@ bg_combine_kernel(int n, int sm, int s, const double *__restrict__ V,
   x[(size_t)k * n + row] = acc;
 }
 
+// out[0] = sqrt(in[0])
+__global__ void bg_sqrt_kernel(const double *__restrict__ in, double *__restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = sqrt(in[0]);
+}
+
 // ||b||^2 of the s starting vectors into state[0] (as a norm)
 __global__ void __launch_bounds__(FB)
 bg_norm_kernel(int len, const double *__restrict__ b, double *__restrict__ state) {
@@ -439,6 +444,7 @@ BgLayout pd_bgal_layout(int n, int F2) {
   L.z = take(6 * (size_t)n);
   L.zpart = take((size_t)NCH * 6 * n);
   L.state = take(8);
+  L.mpart = take((size_t)256 * 40);
   L.mfac = take(12 * 15);
   L.ctab = take(2 * (size_t)36 * F2);
   L.gtab = take(2 * (size_t)6 * F2);
@@ -450,7 +456,10 @@ BgLayout pd_bgal_layout(int n, int F2) {
 pd_status pd_bgal(pd_plan p, const double *b, double *x, double rtol, int *iters,
                   double *relres, int *checks) {
   const int n = p->nbar, F2 = p->F2, s = p->bdf_s;
-  if (s < 1 || s > 6 || p->dims != 1 || n > FB * FR || !p->fom || !p->fom_h) {
+  // 1D: single-block vector kernels (n <= FB * FR); 2D: multi-block ones,
+  // the vectors in the DST-x domain of the line solves
+  const bool mb = p->dims == 2;
+  if (s < 1 || s > 6 || (!mb && n > FB * FR) || !p->fom || !p->fom_h) {
     pd_set_error("block Galerkin: unsupported plan");
     return PD_ENOTSUP;
   }
@@ -468,6 +477,7 @@ pd_status pd_bgal(pd_plan p, const double *b, double *x, double rtol, int *iters
   double *z = base + Lo.z;
   double *zpart = base + Lo.zpart;
   double *state = base + Lo.state;
+  double *mpart = base + Lo.mpart;
   const Cx *mfac = reinterpret_cast<const Cx *>(base + Lo.mfac);
   const Cx *ctab = reinterpret_cast<const Cx *>(base + Lo.ctab);
   const Cx *gtab = reinterpret_cast<const Cx *>(base + Lo.gtab);
@@ -486,7 +496,13 @@ pd_status pd_bgal(pd_plan p, const double *b, double *x, double rtol, int *iters
 
   PD_HIP_CHECK(hipMemsetAsync(T, 0, sizeof(double) * BG_TROWS * BG_LDT, p->stream));
   PD_HIP_CHECK(hipMemsetAsync(beta, 0, sizeof(double) * 36, p->stream));
-  hipLaunchKernelGGL(bg_norm_kernel, dim3(1), dim3(FB), 0, p->stream, s * n, b, state);
+  if (mb) {
+    pd_status st = pd_mvec_norm2(p, s * n, b, state + 2, 0, mpart);
+    if (st != PD_OK) return st;
+    hipLaunchKernelGGL(bg_sqrt_kernel, dim3(1), dim3(64), 0, p->stream, state + 2, state);
+  } else {
+    hipLaunchKernelGGL(bg_norm_kernel, dim3(1), dim3(FB), 0, p->stream, s * n, b, state);
+  }
   {
     // b = 0 (zero data): x = 0, no Krylov space to build
     double b0 = 0.0;
@@ -504,10 +520,19 @@ pd_status pd_bgal(pd_plan p, const double *b, double *x, double rtol, int *iters
       return PD_OK;
     }
   }
-  // B = V_1 beta (Gram-Schmidt QR of the s starting columns, beta ld 6)
-  for (int j = 0; j < s; ++j)
-    hipLaunchKernelGGL(bg_orth_kernel, dim3(1), dim3(FB), 0, p->stream, n, j, j, 6, V,
-                       b + (size_t)j * n, beta);
+  // B = V_1 beta (Gram-Schmidt QR of the s starting columns, beta ld 6;
+  // the multi-block form orthogonalises b in place)
+  for (int j = 0; j < s; ++j) {
+    if (mb) {
+      double *bj = const_cast<double *>(b) + (size_t)j * n;
+      pd_status st = pd_mvec_orth(p, n, V, bj, j, beta, 6, j, mpart);
+      if (st == PD_OK) st = pd_mvec_normalize(p, n, V, bj, j, beta, 6, j, nullptr, mpart);
+      if (st != PD_OK) return st;
+    } else {
+      hipLaunchKernelGGL(bg_orth_kernel, dim3(1), dim3(FB), 0, p->stream, n, j, j, 6, V,
+                         b + (size_t)j * n, beta);
+    }
+  }
   PD_HIP_CHECK(hipGetLastError());
   double bnorm = 0.0, res = 0.0;
   int m = 0, nchecks = 0;
@@ -516,10 +541,20 @@ pd_status pd_bgal(pd_plan p, const double *b, double *x, double rtol, int *iters
     ++m;
     const int sm = s * m;
     for (int j = 0; j < s; ++j) {
-      pd_status st = pd_fom_apply(p, mfac, V + (size_t)((m - 1) * s + j) * n, p->wvec);
-      if (st != PD_OK) return st;
-      hipLaunchKernelGGL(bg_orth_kernel, dim3(1), dim3(FB), 0, p->stream, n, sm + j,
-                         (m - 1) * s + j, BG_LDT, V, p->wvec, T);
+      const double *vj = V + (size_t)((m - 1) * s + j) * n;
+      const int col = (m - 1) * s + j;
+      if (mb) {
+        pd_status st = pd_apply2d(p, vj, p->wvec);
+        if (st == PD_OK) st = pd_mvec_orth(p, n, V, p->wvec, sm + j, T, BG_LDT, col, mpart);
+        if (st == PD_OK)
+          st = pd_mvec_normalize(p, n, V, p->wvec, sm + j, T, BG_LDT, col, nullptr, mpart);
+        if (st != PD_OK) return st;
+      } else {
+        pd_status st = pd_fom_apply(p, mfac, vj, p->wvec);
+        if (st != PD_OK) return st;
+        hipLaunchKernelGGL(bg_orth_kernel, dim3(1), dim3(FB), 0, p->stream, n, sm + j, col,
+                           BG_LDT, V, p->wvec, T);
+      }
     }
     PD_HIP_CHECK(hipGetLastError());
     if (m % q != 0 && m != mmax) continue;
@@ -545,7 +580,17 @@ pd_status pd_bgal(pd_plan p, const double *b, double *x, double rtol, int *iters
                        s, hs, sstride, cw, zpart);
     hipLaunchKernelGGL(bg_wfinish_kernel, dim3((n + 255) / 256, s), dim3(256), 0, p->stream, n,
                        zpart, z);
-    hipLaunchKernelGGL(bg_resid_kernel, dim3(1), dim3(FB), 0, p->stream, n, sm, s, V, z, state);
+    if (mb) {
+      for (int k = 0; k < s; ++k) {
+        pd_status st = pd_mvec_orth(p, n, V, z + (size_t)k * n, sm, nullptr, 0, 0, mpart);
+        if (st == PD_OK) st = pd_mvec_norm2(p, n, z + (size_t)k * n, state + 2, k > 0, mpart);
+        if (st != PD_OK) return st;
+      }
+      hipLaunchKernelGGL(bg_sqrt_kernel, dim3(1), dim3(64), 0, p->stream, state + 2, state + 1);
+    } else {
+      hipLaunchKernelGGL(bg_resid_kernel, dim3(1), dim3(FB), 0, p->stream, n, sm, s, V, z,
+                         state);
+    }
     PD_HIP_CHECK(hipGetLastError());
     double hst[2];
     PD_HIP_CHECK(hipMemcpyAsync(hst, state, 2 * sizeof(double), hipMemcpyDeviceToHost, p->stream));

@@ -355,7 +355,7 @@ fom_resid_kernel(int n, int m, const double *__restrict__ V, const double *__res
 // in a fixed order.
 constexpr int MB = 256;
 constexpr int MB_MAX_BLOCKS = 256;
-constexpr int MCAP = PD_FOM_MAXM + 1;
+constexpr int MCAP = 40;   // basis vectors a multi-block orthogonalisation handles
 
 int fom_vec_blocks(int n) {
   const int b = (n + MB - 1) / MB;
@@ -400,7 +400,8 @@ fom_mupdate_kernel(int n, int cnt, int nblk, const double *__restrict__ part,
   }
 }
 
-// t = sqrt(sum_b part[b][cnt]); V row cnt = w / t (0 if t = 0); block 0
+// t = sqrt(sum_b part[b]) with part from a w . w pass (fom_mdots_kernel with
+// cnt = 0, one value per block); V row cnt = w / t (0 if t = 0); block 0
 // writes t to T[cnt * ldT + col] (T != NULL) and to *tout (tout != NULL).
 __global__ void __launch_bounds__(MB)
 fom_mscale_kernel(int n, int cnt, int nblk, const double *__restrict__ part,
@@ -409,7 +410,7 @@ fom_mscale_kernel(int n, int cnt, int nblk, const double *__restrict__ part,
   __shared__ double tsh;
   if (threadIdx.x == 0) {
     double acc = 0.0;
-    for (int b = 0; b < nblk; ++b) acc += part[(size_t)b * (cnt + 1) + cnt];
+    for (int b = 0; b < nblk; ++b) acc += part[b];
     tsh = sqrt(acc);
     if (blockIdx.x == 0) {
       if (T) T[(size_t)cnt * ldT + col] = tsh;
@@ -420,6 +421,15 @@ fom_mscale_kernel(int n, int cnt, int nblk, const double *__restrict__ part,
   const double t = tsh;
   for (int row = blockIdx.x * MB + threadIdx.x; row < n; row += gridDim.x * MB)
     V[(size_t)cnt * n + row] = t > 0.0 ? w[row] / t : 0.0;
+}
+
+// out[0] = (acc ? out[0] : 0) + sum_b part[b][0]
+__global__ void fom_maccum_kernel(int nblk, const double *__restrict__ part, int acc,
+                                  double *__restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = acc ? out[0] : 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[b];
+  out[0] = s;
 }
 
 // state[1] = |t_{m+1,m}| w sqrt(sum_b part[b][0]) (the projected norm of z)
@@ -643,4 +653,58 @@ pd_status pd_fom_apply(pd_plan p, const cpx<double> *mfac, const double *v, doub
 void pd_fom_mass_factors(pd_plan p, std::vector<double> &out) {
   out.assign(12 * 15, 0.0);
   pd_partition_factors(p->uni[0], 0.0, p->uni[1], 0.0, p->uni[2], 0.0, 16, out.data());
+}
+
+// ---- multi-block vector helpers shared with the block Galerkin method ----
+
+int pd_mvec_blocks(int n) { return fom_vec_blocks(n); }
+
+// Two classical Gram-Schmidt passes of w against V rows 0..cnt-1 (cnt < 40),
+// the coefficients added to T[k * ldT + col] (T may be NULL).  part holds
+// pd_mvec_blocks(n) * 40 doubles.
+pd_status pd_mvec_orth(pd_plan p, int n, const double *V, double *w, int cnt, double *T, int ldT,
+                       int col, double *part) {
+  if (cnt >= MCAP) {
+    pd_set_error("multi-block orthogonalisation: too many basis vectors");
+    return PD_EINVAL;
+  }
+  const int NB = fom_vec_blocks(n);
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(fom_mdots_kernel, dim3(NB), dim3(MB), 0, p->stream, n, cnt, V, w, part);
+    hipLaunchKernelGGL(fom_mupdate_kernel, dim3(NB), dim3(MB), 0, p->stream, n, cnt, NB, part, V,
+                       w, T, ldT, col);
+  }
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
+// V row cnt = w / ||w||; ||w|| written to T[cnt * ldT + col] (T != NULL) and
+// *tout (tout != NULL).
+pd_status pd_mvec_normalize(pd_plan p, int n, double *V, const double *w, int cnt, double *T,
+                            int ldT, int col, double *tout, double *part) {
+  const int NB = fom_vec_blocks(n);
+  hipLaunchKernelGGL(fom_mdots_kernel, dim3(NB), dim3(MB), 0, p->stream, n, 0, V, w, part);
+  hipLaunchKernelGGL(fom_mscale_kernel, dim3(NB), dim3(MB), 0, p->stream, n, cnt, NB, part, w, V,
+                     T, ldT, col, tout);
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
+// out[0] = (acc ? out[0] : 0) + w . w
+pd_status pd_mvec_norm2(pd_plan p, int n, const double *w, double *out, int acc, double *part) {
+  const int NB = fom_vec_blocks(n);
+  hipLaunchKernelGGL(fom_mdots_kernel, dim3(NB), dim3(MB), 0, p->stream, n, 0, w, w, part);
+  hipLaunchKernelGGL(fom_maccum_kernel, dim3(1), dim3(64), 0, p->stream, NB, part, acc, out);
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
+// 2D plans: w = tau K v in the DST-x domain of the line solves
+pd_status pd_apply2d(pd_plan p, const double *v, double *w) {
+  const int n = p->nbar;
+  hipLaunchKernelGGL(fom_apply2d_kernel, dim3((n + 255) / 256), dim3(256), 0, p->stream, p->n, v,
+                     reinterpret_cast<const cpx<double> *>(p->twd), p->uni[3], p->uni[4],
+                     p->uni[5], w);
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
 }

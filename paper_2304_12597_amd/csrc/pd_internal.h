@@ -307,7 +307,8 @@ constexpr int BG_SMAX = 32;
 constexpr int BG_TROWS = BG_SMAX + 6;
 constexpr int BG_LDT = BG_SMAX;
 struct BgLayout {
-  size_t T, beta, proj, E, L, part, G, y, cw, z, zpart, state, mfac, ctab, gtab, thtab, total;
+  size_t T, beta, proj, E, L, part, G, y, cw, z, zpart, state, mpart, mfac, ctab, gtab, thtab,
+      total;
 };
 BgLayout pd_bgal_layout(int n, int F2);
 pd_status pd_bgal(pd_plan p, const double *b, double *x, double rtol, int *iters,
@@ -315,6 +316,15 @@ pd_status pd_bgal(pd_plan p, const double *b, double *x, double rtol, int *iters
 // w = tau M^{-1} K v with the uniform mass factors mfac (Algorithm 2's operator;
 // BDF plans: tau beta M^{-1} K)
 pd_status pd_fom_apply(pd_plan p, const cpx<double> *mfac, const double *v, double *w);
+// multi-block vector helpers (fom.hip): Gram-Schmidt against up to 39 basis
+// vectors, normalisation, squared norms; the 2D operator in the DST-x domain
+int pd_mvec_blocks(int n);
+pd_status pd_mvec_orth(pd_plan p, int n, const double *V, double *w, int cnt, double *T, int ldT,
+                       int col, double *part);
+pd_status pd_mvec_normalize(pd_plan p, int n, double *V, const double *w, int cnt, double *T,
+                            int ldT, int col, double *tout, double *part);
+pd_status pd_mvec_norm2(pd_plan p, int n, const double *w, double *out, int acc, double *part);
+pd_status pd_apply2d(pd_plan p, const double *v, double *w);
 // sine-basis path (sine.hip)
 int pd_sine_dst_C(int n, int ell);
 size_t pd_sine_dst_lds(int n, int C);

@@ -463,8 +463,8 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
                  "early_exit and ell >= 2 * bdf_order");
     return PD_ENOTSUP;
   }
-  if (opt.bdf_order > 1 && opt.krylov == PD_KRYLOV_FOM && (n < opt.bdf_order || opt.dims != 1)) {
-    pd_set_error("the block Galerkin method runs on 1D plans with n >= bdf_order");
+  if (opt.bdf_order > 1 && opt.krylov == PD_KRYLOV_FOM && n < opt.bdf_order) {
+    pd_set_error("the block Galerkin method needs n >= bdf_order");
     return PD_ENOTSUP;
   }
   if (opt.shifted_solver == PD_SHIFTED_SINE) {

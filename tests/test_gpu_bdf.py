@@ -360,11 +360,30 @@ def test_bdf_2d_capacitance_apply(lib):
     assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
 
 
-def test_bdf_2d_block_galerkin_rejected(lib):
-    p = wl.heat_2d(15, 16, 0.1, 1.0, np.random.default_rng(0))
-    with pytest.raises(RuntimeError):
-        lib.paradiag_plan_create(p.n, p.ell, p.tau, None, p.K, dims=2, bdf_order=2,
-                                 krylov=lib.PD_KRYLOV_FOM)
+@pytest.mark.parametrize("n,ell,T_,s", [(15, 16, 1.0, 2), (15, 16, 1.0, 3), (31, 16, 1.0, 2)])
+def test_bdf_2d_block_galerkin_matches_oracle(lib, n, ell, T_, s):
+    """The block Galerkin method on 2D plans (in the DST-x domain, multi-block
+    Gram-Schmidt): the oracle's step count and U."""
+    p = wl.heat_2d(n, ell, T_, 1.0, np.random.default_rng(n + ell))
+    U0 = np.tile(p.u0, (s, 1))
+    tol = 1e-10
+    plan = lib.paradiag_plan_create(p.n, p.ell, p.tau, None, p.K, dims=2, bdf_order=s,
+                                    krylov=lib.PD_KRYLOV_FOM, check_residual=1,
+                                    stream=_stream())
+    try:
+        U = torch.empty((ell, p.nbar), dtype=torch.float64, device=dev())
+        info = lib.paradiag_solve(plan, T(U0), T(p.F), U, tol)
+        torch.cuda.synchronize()
+        got = U.cpu().numpy()
+    finally:
+        lib.paradiag_plan_destroy(plan)
+    Msp, Ksp = problem_matrices(p)
+    ref = bdf.paradiag_bdf(Msp, Ksp, p.tau, s, list(U0), p.F, capacitance="galerkin",
+                           eps=tol * 1e-2, maxit=32 // s)
+    assert abs(info.gmres_iters - ref["steps"]) <= 1, (info.as_dict(), ref["steps"])
+    assert info.pint_loops == info.gmres_iters + 2
+    assert allatonce.rel_err(got, ref["U"]) < 1e-10
+    assert info.rel_residual < 1e-10
 
 
 @pytest.mark.parametrize("s", [2, 3])

@@ -98,10 +98,6 @@ def test_fom_step_cap_is_reported(lib):
 
 
 def test_fom_rejects_unsupported(lib):
-    q = wl.heat_2d(15, 16, 0.1, 1.0, np.random.default_rng(0))
-    with pytest.raises(RuntimeError):     # block Galerkin (BDF with FOM) is 1D only
-        lib.paradiag_plan_create(q.n, q.ell, q.tau, None, q.K, dims=2, bdf_order=2,
-                                 krylov=lib.PD_KRYLOV_FOM)
     p = make_problem("fd1", 63, 8, 1)
     with pytest.raises(RuntimeError):     # mixed precision
         lib.paradiag_plan_create(p.n, p.ell, p.tau, p.M, p.K, krylov=lib.PD_KRYLOV_FOM,
