@@ -74,7 +74,7 @@ def test_forward_transform(lib, prec, n, ell, alpha):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("n,ell", [(2, 2), (37, 8), (63, 32), (101, 256), (33, 2048),
-                                   (1000, 64)])
+                                   (9, 4096), (1000, 64)])
 def test_inverse_transform(lib, prec, n, ell):
     code, cdt, rdt, tol = PRECS[prec]
     p = make_problem("fd1", n, ell, 3)
@@ -306,6 +306,28 @@ def test_fem_full_size_sampled(lib):
     assert info.rel_residual < 1e-8
     assert np.allclose(U[-1, ii[:50]], modal.modal_sample(p, np.full(50, p.ell - 1), ii[:50]),
                        rtol=1e-6, atol=1e-9)
+
+
+@pytest.mark.parametrize("kind,n,ell,prec", [
+    ("fem1", 8192, 4096, 0),     # the float64 limits on n and ell together
+    ("fd1", 16384, 256, 1),      # mixed precision at its limit on n
+])
+def test_maximum_sizes_sampled(lib, kind, n, ell, prec):
+    """Plans at the largest sizes the library accepts solve to 1e-8 against
+    the exact modal solution, on sampled outputs (the full U is 2^25 values)."""
+    p = make_problem(kind, n, ell, 17)
+    U, info = _solve(lib, p, prec=prec, tol=1e-8)
+    rng = np.random.default_rng(1)
+    tt = rng.integers(0, p.ell, 3000)
+    ii = rng.integers(0, p.n, 3000)
+    tt[:4] = [0, 0, p.ell - 1, p.ell - 1]      # the first and last rows and points
+    ii[:4] = [0, p.n - 1, 0, p.n - 1]
+    ref = modal.modal_sample(p, tt, ii)
+    err = np.linalg.norm(U[tt, ii] - ref) / np.linalg.norm(ref)
+    print("%s n=%d ell=%d prec=%d err=%.3e res=%.3e gmres=%d sweeps=%d" % (
+        kind, n, ell, prec, err, info.rel_residual, info.gmres_iters, info.sweeps))
+    assert err < 1e-8, (err, info.as_dict())
+    assert info.rel_residual < 1e-8
 
 
 @pytest.mark.parametrize("n,ell", [(300, 64), (1500, 128), (5000, 256)])
