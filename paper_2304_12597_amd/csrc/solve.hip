@@ -161,7 +161,8 @@ pd_status solve_sine(pd_plan p, const double *u0, const double *F, double *U, pd
 // Algorithm 1 with Algorithm 2 for the capacitance system: pass B, the
 // projection method (its residual check every fom_q steps is one parfor),
 // pass C, pass D.  #PinT = checks + 2 (Section 3).
-pd_status solve_fom(pd_plan p, double *U, double tol, pd_info *info) {
+pd_status solve_fom(pd_plan p, const double *u0, const double *F, double *U, double tol,
+                    pd_info *info) {
   pd_status st = pd_launch_tridiag(p, 0, p->spec, nullptr, nullptr);
   if (st != PD_OK) return st;
   st = pd_launch_reduce_partials(p, nullptr, p->bvec);
@@ -180,6 +181,12 @@ pd_status solve_fom(pd_plan p, double *U, double tol, pd_info *info) {
     info->pint_loops = checks + 2;
     info->sweeps = 1;
     info->gmres_rel_residual = rr;
+  }
+  if (p->check_residual) {
+    double rel;
+    st = pd_residual_impl(p, u0, F, U, &rel);
+    if (st != PD_OK) return st;
+    if (info) info->rel_residual = rel;
   }
   if (fst == PD_ENOTCONV) pd_set_error("Algorithm 2 did not reach the tolerance");
   return fst;
@@ -245,7 +252,7 @@ extern "C" pd_status paradiag_solve(pd_plan p, const double *u0, const double *F
     st = pd_forward(p, u0, F, nullptr, p->spec, 0);
     if (st != PD_OK) return st;
   }
-  if (p->krylov == PD_KRYLOV_FOM) return solve_fom(p, U, tol, info);
+  if (p->krylov == PD_KRYLOV_FOM) return solve_fom(p, u0, F, U, tol, info);
   if (p->prec != PD_MIXED && pd_gmres_fused_ok(p)) return solve_speculative(p, u0, F, U, tol, info);
   st = sweep_tail(p, U, tol, 0, 0, info, &gst);
   if (st != PD_OK) return st;
