@@ -115,8 +115,9 @@ SOLVE_CASES = [("fd1", 7, 8), ("fem1", 63, 32), ("fem1", 100, 16), ("fd1", 257, 
 @pytest.mark.parametrize("alpha", [1.0, 0.05])
 def test_shifted_solves_and_b(lib, prec, kind, n, ell, alpha):
     code, cdt, rdt, tol = PRECS[prec]
-    if prec == "fp32" and n > 300:
-        pytest.skip("complex64 elimination error grows with the condition number of P_k")
+    # complex64 forward error grows with the condition number of P_k (about
+    # (n+1)^2); above n = 300 the solves are checked by their backward error
+    backward_only = prec == "fp32" and n > 300
     p = make_problem(kind, n, ell, n * 7 + ell, nu=0.3)
     out, Hhat = _oracle_pieces(p, alpha)
     F2 = ell // 2 + 1
@@ -134,6 +135,24 @@ def test_shifted_solves_and_b(lib, prec, kind, n, ell, alpha):
         bg = b.cpu().numpy()
     finally:
         lib.paradiag_plan_destroy(plan)
+    if backward_only:
+        # P_k Y_k = M (Hhat_k - w x) for every k, up to a normwise backward
+        # error of a few float32 units (the complex64 rounding of the oracle's
+        # own Y gives 2e-8 here; dropping w x gives 3e-6, a conjugated Y, two
+        # frequencies swapped or one row off by 1e-3 give 1.6e-5 to 2.5e-5)
+        Msp, Ksp = problem_matrices(p)
+        Mcsr = Msp.tocsr()
+        for k in range(F2):
+            Pk = ((1.0 - out["pi"][k]) * Msp + p.tau * Ksp).tocsr()
+            rhs = Mcsr @ (Hhat[k] - w * out["x"].real)
+            Yk = Yg[k].astype(np.complex128)
+            r = Pk @ Yk - rhs
+            nP = float(abs(Pk).sum(axis=1).max())
+            be = np.linalg.norm(r) / (nP * np.linalg.norm(Yk) + np.linalg.norm(rhs))
+            print("k=%d backward error %.2e" % (k, be))
+            assert be < 2e-7, (k, be)
+        assert np.isfinite(bg).all()
+        return
     # Y_k = L_k - w W_k (second parfor), b = sum_k gamma_k L_k (first parfor)
     Yref = (out["L"] - w * out["W"])[:F2]
     tolY = 1e-10 if prec == "fp64" else 2e-3
