@@ -156,8 +156,10 @@ pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double tau,
 /* Algorithm 1 end to end: U = solution of the all-at-once system for
  * initial value u0 [nbar] and nodal source F [ell][nbar] (device float64),
  * written to U [ell][nbar] (device float64, must not alias u0 or F).
- * tol: the capacitance GMRES stops at residual <= tol/100 * ||b||; PD_MIXED
- * refines until the float64 relative all-at-once residual is <= tol.
+ * tol: the capacitance GMRES stops at residual <= tol/100 * ||b|| (with
+ * float32 shifted solves, PD_MIXED and PD_FP32, at no less than 1e-7 * ||b||,
+ * the resolution of float32 capacitance products); PD_MIXED refines until
+ * the float64 relative all-at-once residual is <= tol.
  * BDF plans (bdf_order s > 1, Section 5): the system is
  * (M + tau beta K) U - M U Sigma_s^T = G with G_t = M (sum_{j>t} alpha_j
  * u_{t+1-j} + tau beta f_{t+1}); u0 is [s][nbar] (u_{1-s} first), and the

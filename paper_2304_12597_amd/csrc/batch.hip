@@ -287,7 +287,7 @@ pd_status pd_solve_batch_impl(const pd_plan *plans, int count, const double *con
                               pd_info *infos) {
   const pd_plan p0 = plans[0];
   const int MX = p0->maxit;
-  const double rtol = tol * PD_GMRES_TOL_FACTOR;
+  const double rtol = pd_gmres_tol(p0->prec, tol);
   bool learned = true;
   int K = 1;
   for (int i = 0; i < count; ++i) {

@@ -63,6 +63,16 @@ __device__ __forceinline__ cpx<R> cmul_mi(cpx<R> a) {
 // amplify it on ill-conditioned problems (small diffusion, long horizons).
 constexpr double PD_GMRES_TOL_FACTOR = 1e-2;
 
+// GMRES target for a solve to tol in precision prec.  With float32 shifted
+// solves the capacitance products carry float32 rounding, so a GMRES residual
+// below about 1e-7 of ||b|| is not resolved by them: iterations past it only
+// refine the Krylov estimate (the mixed form's float64 refinement corrects
+// what remains), so the target is floored there.
+inline double pd_gmres_tol(int prec, double tol) {
+  const double t = tol * PD_GMRES_TOL_FACTOR;
+  return (prec != PD_FP64 && t < 1e-7) ? 1e-7 : t;
+}
+
 // LDS column layout of the time and DST transforms: entry i of a column sits
 // at pd_fpad(i) = i + i/8, which spreads the power-of-two strides of the
 // Stockham stages over all LDS banks; columns are pd_fft_col_stride(N)

@@ -47,7 +47,7 @@ pd_status sweep_tail(pd_plan p, double *U, double tol, int has_mass, int accumul
   if (st != PD_OK) return st;
   int its = 0;
   double rr = 0.0;
-  *gm_status = pd_gmres(p, p->bvec, p->xvec, tol * PD_GMRES_TOL_FACTOR, &its, &rr);
+  *gm_status = pd_gmres(p, p->bvec, p->xvec, pd_gmres_tol(p->prec, tol), &its, &rr);
   if (*gm_status != PD_OK && *gm_status != PD_ENOTCONV) return *gm_status;
   st = pd_launch_tridiag(p, 1 | mflag, p->spec, p->xvec, p->spec);
   if (st != PD_OK) return st;
@@ -70,7 +70,7 @@ pd_status sweep_tail(pd_plan p, double *U, double tol, int has_mass, int accumul
 // D are redone.
 pd_status solve_speculative(pd_plan p, const double *u0, const double *F, double *U, double tol,
                             pd_info *info) {
-  const double rtol = tol * PD_GMRES_TOL_FACTOR;
+  const double rtol = pd_gmres_tol(p->prec, tol);
   pd_status st = pd_launch_tridiag(p, 0, p->spec, nullptr, nullptr);
   if (st != PD_OK) return st;
   st = pd_launch_reduce_partials(p, nullptr, p->bvec);
