@@ -56,8 +56,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported "
-              "(the multi-GPU sharding is design-only)" % args.gpus, file=sys.stderr)
+        print("bench.py: the library runs on exactly one GPU; --gpus %d is not supported "
+              "(multi-GPU sharding is a design only)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2304_12597_amd import binding as pd

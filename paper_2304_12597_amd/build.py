@@ -21,7 +21,7 @@ FLAGS = ["-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC",
 
 
 def source_hash() -> str:
-    """sha256 over the native sources and this build script: a recorded
+    """sha256 over the native sources and build.py itself: a recorded
     hardware-counter reading is valid only for the kernels it was taken on."""
     import hashlib
     h = hashlib.sha256()
