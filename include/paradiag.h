@@ -147,7 +147,9 @@ void paradiag_default_options(pd_options *opt);
  * coefficients and twiddle tables in float64 on the host, allocates the
  * device workspace and uploads the constants.
  * Sizes: ell a power of two, 2 <= ell <= 4096.  1D: 2 <= n <= 8192 for
- * PD_FP64, n <= 16384 otherwise.  2D: 2 <= n <= 1024.
+ * PD_FP64, n <= 16384 otherwise.  2D: 2 <= n <= 1024 (the DST-I along x is
+ * one FFT of length 2(n+1) per pair of rows when n + 1 is a power of two,
+ * else the chirp-z form with FFTs of length L >= 2n - 1).
  * M == NULL means M = I.  Errors: PD_EINVAL, PD_ENOTSUP, PD_ENOMEM, PD_EHIP. */
 pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double tau,
                                const pd_tridiag *M, const pd_tridiag *K,

@@ -448,39 +448,203 @@ pd_status pd_launch_fft_forward(pd_plan p, const double *u0, const double *F,
 }
 
 namespace {
+
+// Orthonormal DST-I along x for n + 1 not a power of two (chirp-z form).
+// With j = x + 1, k = m + 1 and N1 = n + 1, jk = (j^2 + k^2 - (k - j)^2) / 2
+// turns the sine sum into a convolution:
+//   S[m] = sqrt(2/N1) Im(c_k sum_j (v_j c_j) conj(c_{k-j})),
+//   c_j = exp(i pi j^2 / (2 N1)),
+// a linear convolution of two length-n sequences, computed as a circular
+// one of length L >= 2n - 1: FFT in LDS, times bhat (the transform of the
+// wrapped conj(c_d), |d| < n, with 1/L folded in), inverse FFT.  One row
+// per LDS column; MODE and ACC as for dst_x_kernel.
+template <int MODE, int ACC>
+__global__ void __launch_bounds__(1024)
+dst_x_chirp_kernel(int n, int ell, int Lc, int C, int stride, double tau,
+                   const double *__restrict__ u0, const double *__restrict__ F,
+                   const double *__restrict__ U, const double *__restrict__ in,
+                   const double *__restrict__ coef, const cpx<double> *__restrict__ tw,
+                   const cpx<double> *__restrict__ chirp, const cpx<double> *__restrict__ bhat,
+                   double *__restrict__ out, double *__restrict__ red) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  using Cx = cpx<double>;
+  Cx *lds = reinterpret_cast<Cx *>(smem_raw);
+  const int T = blockDim.x, tid = threadIdx.x;
+  const int nbar = n * n;
+  const int rows = ell * n;
+  const int r0 = blockIdx.x * C;
+  const int lgL = __builtin_ctz(Lc);
+  Cx *twl = lds + C * stride;
+  tw_to_lds(twl, tw, Lc);
+  double rn2 = 0.0, gn2 = 0.0;
+  // entries n .. L-1 of every column are zero
+  const int padn = Lc - n;
+  for (int idx = tid; idx < C * padn; idx += T) {
+    const int c = idx / padn, q = n + (idx - c * padn);
+    lds[c * stride + pd_fpad(q)] = Cx{0.0, 0.0};
+  }
+  constexpr int UNR = 8;
+  const int total = C * n;
+  for (int base = tid; base < total; base += UNR * T) {
+    double vals[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = base + u * T;
+      double v = 0.0;
+      if (idx < total) {
+        const int lr = idx / n, x = idx - lr * n;
+        const int row = r0 + lr;
+        if (row < rows) {
+          const int t = row / n, y = row - t * n;
+          const int i = y * n + x;
+          if (MODE == 0) {
+            v = tau * F[(size_t)t * nbar + i];
+            if (t == 0) v += u0[i];
+          } else if (MODE == 1) {
+            double r, g;
+            residual_point(t, i, n, nbar, 2, tau, u0, F, U, coef, r, g);
+            rn2 += r * r;
+            gn2 += g * g;
+            v = r;
+          } else {
+            v = in[(size_t)t * nbar + i];
+          }
+        }
+      }
+      vals[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = base + u * T;
+      if (idx < total) {
+        const int lr = idx / n, x = idx - lr * n;
+        const Cx cj = chirp[x + 1];
+        lds[lr * stride + pd_fpad(x)] = Cx{vals[u] * cj.re, vals[u] * cj.im};
+      }
+    }
+  }
+  __syncthreads();
+  fft_lds<double, false>(lds, Lc, C, stride, twl);
+  for (int idx = tid; idx < (C << lgL); idx += T) {
+    const int c = idx >> lgL, q = idx & (Lc - 1);
+    Cx *e = &lds[c * stride + pd_fpad(q)];
+    *e = cmul(*e, bhat[q]);
+  }
+  __syncthreads();
+  fft_lds<double, true>(lds, Lc, C, stride, twl);
+  const double scale = sqrt(2.0 / (double)(n + 1));
+  for (int base = tid; base < total; base += UNR * T) {
+    double s[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = base + u * T;
+      const int ic = idx < total ? idx : 0;
+      const int lr = ic / n, m = ic - lr * n;
+      const Cx z = lds[lr * stride + pd_fpad(m)];
+      const Cx ck = chirp[m + 1];
+      s[u] = (ck.re * z.im + ck.im * z.re) * scale;
+      if (ACC) {
+        int row = r0 + lr;
+        row = row < rows ? row : rows - 1;
+        const int t = row / n, y = row - t * n;
+        s[u] += out[(size_t)t * nbar + (size_t)y * n + m];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = base + u * T;
+      if (idx < total) {
+        const int lr = idx / n, m = idx - lr * n;
+        const int row = r0 + lr;
+        if (row < rows) {
+          const int t = row / n, y = row - t * n;
+          out[(size_t)t * nbar + (size_t)y * n + m] = s[u];
+        }
+      }
+    }
+  }
+  if (MODE == 1) {
+    __shared__ double sr[32], sg[32];
+    for (int off = 32; off > 0; off >>= 1) {
+      rn2 += __shfl_down(rn2, off, 64);
+      gn2 += __shfl_down(gn2, off, 64);
+    }
+    int wid = tid / 64, lane = tid % 64;
+    __syncthreads();
+    if (lane == 0) { sr[wid] = rn2; sg[wid] = gn2; }
+    __syncthreads();
+    if (tid == 0) {
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < (T + 63) / 64; ++w) { a += sr[w]; b += sg[w]; }
+      red[2 * blockIdx.x] = a;
+      red[2 * blockIdx.x + 1] = b;
+    }
+  }
+}
+}  // namespace
+
+namespace {
 struct DstLaunch {
   int C, stride, threads, blocks;
   size_t lds;
 };
-DstLaunch dst_config(pd_plan p) {
+// rows per block: 2C (pairs of rows per FFT column), C for the chirp-z form
+DstLaunch dst_config(pd_plan p, int trows) {
   DstLaunch L;
-  const int N = 2 * (p->n + 1);
+  const int N = p->dst_L ? p->dst_L : 2 * (p->n + 1);
   L.C = p->dst_C;
   L.stride = pd_fft_col_stride(N);
   L.lds = ((size_t)L.C * L.stride + pd_tw_entries(N)) * 16;
   int need = L.C * N / 8;
   if (need < 64) need = 64;
   L.threads = ((need + 63) / 64) * 64;
-  const int rows = p->ell * p->n;
-  L.blocks = (rows + 2 * L.C - 1) / (2 * L.C);
+  const int rows = trows * p->n;
+  const int per = p->dst_L ? L.C : 2 * L.C;
+  L.blocks = (rows + per - 1) / per;
   return L;
 }
 }  // namespace
 
+// FFT length of the chirp-z DST-I of length n: 0 when n + 1 is a power of
+// two (one FFT of length 2(n+1) per pair of rows), else the least power of
+// two >= 2n - 1.
+int pd_dst_chirp_length(int n) {
+  if (((n + 1) & n) == 0) return 0;
+  int L = 4;
+  while (L < 2 * n - 1) L *= 2;
+  return L;
+}
+
 int pd_choose_dst_C(int n) {
-  const int N = 2 * (n + 1);
+  const int Lc = pd_dst_chirp_length(n);
+  const int N = Lc ? Lc : 2 * (n + 1);
   int C = 1;
   const size_t col = (size_t)pd_fft_col_stride(N) * 16, twb = pd_tw_entries(N) * 16;
   while (C < 16 && 2 * C * col + twb <= 65536 && 2 * C * N / 8 <= 1024) C *= 2;
   return C;
 }
 
-int pd_dst_blocks(pd_plan p) { return dst_config(p).blocks; }
+int pd_dst_blocks(pd_plan p) { return dst_config(p, p->ell).blocks; }
 
 pd_status pd_launch_dst_x(pd_plan p, int mode, const double *u0, const double *F,
                           const double *U, const double *in, double *out, int accumulate) {
-  DstLaunch L = dst_config(p);
+  DstLaunch L = dst_config(p, p->ell);
   auto tw = reinterpret_cast<const cpx<double> *>(p->twd);
+  if (p->dst_L) {
+    auto ch = reinterpret_cast<const cpx<double> *>(p->twd + p->twd_chirp);
+    auto bh = reinterpret_cast<const cpx<double> *>(p->twd + p->twd_bhat);
+#define PD_DSTC(M, A)                                                                        \
+  hipLaunchKernelGGL((dst_x_chirp_kernel<M, A>), dim3(L.blocks), dim3(L.threads), L.lds,     \
+                     p->stream, p->n, p->ell, p->dst_L, L.C, L.stride, p->tau, u0, F, U, in,  \
+                     p->coef64, tw, ch, bh, out, p->red)
+    if (mode == 0) PD_DSTC(0, 0);
+    else if (mode == 1) PD_DSTC(1, 0);
+    else if (accumulate) PD_DSTC(2, 1);
+    else PD_DSTC(2, 0);
+#undef PD_DSTC
+    PD_HIP_CHECK(hipGetLastError());
+    return PD_OK;
+  }
 #define PD_DST(M, A)                                                                        \
   hipLaunchKernelGGL((dst_x_kernel<M, A>), dim3(L.blocks), dim3(L.threads), L.lds, p->stream, \
                      p->n, p->ell, L.C, L.stride, p->tau, u0, F, U, in, p->coef64, tw, out,   \
@@ -498,9 +662,22 @@ pd_status pd_launch_dst_x(pd_plan p, int mode, const double *u0, const double *F
 // added to it): the mode-2 transform on a [trows][nbar] array.
 pd_status pd_launch_dst_x_rows(pd_plan p, const double *in, double *out, int trows,
                                int accumulate) {
-  DstLaunch L = dst_config(p);
-  L.blocks = (trows * p->n + 2 * L.C - 1) / (2 * L.C);
+  DstLaunch L = dst_config(p, trows);
   auto tw = reinterpret_cast<const cpx<double> *>(p->twd);
+  if (p->dst_L) {
+    auto ch = reinterpret_cast<const cpx<double> *>(p->twd + p->twd_chirp);
+    auto bh = reinterpret_cast<const cpx<double> *>(p->twd + p->twd_bhat);
+    if (accumulate)
+      hipLaunchKernelGGL((dst_x_chirp_kernel<2, 1>), dim3(L.blocks), dim3(L.threads), L.lds,
+                         p->stream, p->n, trows, p->dst_L, L.C, L.stride, p->tau, nullptr,
+                         nullptr, nullptr, in, p->coef64, tw, ch, bh, out, p->red);
+    else
+      hipLaunchKernelGGL((dst_x_chirp_kernel<2, 0>), dim3(L.blocks), dim3(L.threads), L.lds,
+                         p->stream, p->n, trows, p->dst_L, L.C, L.stride, p->tau, nullptr,
+                         nullptr, nullptr, in, p->coef64, tw, ch, bh, out, p->red);
+    PD_HIP_CHECK(hipGetLastError());
+    return PD_OK;
+  }
   if (accumulate)
     hipLaunchKernelGGL((dst_x_kernel<2, 1>), dim3(L.blocks), dim3(L.threads), L.lds, p->stream,
                        p->n, trows, L.C, L.stride, p->tau, nullptr, nullptr, nullptr, in,
@@ -551,6 +728,10 @@ void pd_fft_set_attributes(size_t max_lds) {
   pd_set_max_lds(reinterpret_cast<const void *>(&dst_x_kernel<1, 0>), v);
   pd_set_max_lds(reinterpret_cast<const void *>(&dst_x_kernel<2, 0>), v);
   pd_set_max_lds(reinterpret_cast<const void *>(&dst_x_kernel<2, 1>), v);
+  pd_set_max_lds(reinterpret_cast<const void *>(&dst_x_chirp_kernel<0, 0>), v);
+  pd_set_max_lds(reinterpret_cast<const void *>(&dst_x_chirp_kernel<1, 0>), v);
+  pd_set_max_lds(reinterpret_cast<const void *>(&dst_x_chirp_kernel<2, 0>), v);
+  pd_set_max_lds(reinterpret_cast<const void *>(&dst_x_chirp_kernel<2, 1>), v);
   pd_set_max_lds(reinterpret_cast<const void *>(&fft_inverse_kernel<double, 0>), v);
   pd_set_max_lds(reinterpret_cast<const void *>(&fft_inverse_kernel<double, 1>), v);
   pd_set_max_lds(reinterpret_cast<const void *>(&fft_inverse_kernel<float, 0>), v);

@@ -444,14 +444,14 @@ __global__ void fom_mres_kernel(int nblk, const double *__restrict__ part,
 
 // 2D plans, in the DST-x domain of the line solves (index y * n + j, x-mode
 // j + 1): w = tau K v with tau K = diag(theta_j) along x plus tau T along y,
-// theta_j = tkd + 2 tku cos(pi (j + 1) / (n + 1)) (twd[j + 1].re).
+// theta_j = tkd + 2 tku cos(pi (j + 1) / (n + 1)) (cosx[j], from the plan).
 __global__ void __launch_bounds__(256)
-fom_apply2d_kernel(int n, const double *__restrict__ v, const cpx<double> *__restrict__ twd,
+fom_apply2d_kernel(int n, const double *__restrict__ v, const double *__restrict__ cosx,
                    double tkl, double tkd, double tku, double *__restrict__ w) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= n * n) return;
   const int y = idx / n, j = idx - y * n;
-  const double th = tkd + 2.0 * tku * twd[j + 1].re;
+  const double th = tkd + 2.0 * tku * cosx[j];
   double val = (th + tkd) * v[idx];
   if (y > 0) val += tkl * v[idx - n];
   if (y < n - 1) val += tku * v[idx + n];
@@ -571,7 +571,7 @@ pd_status pd_fom(pd_plan p, const double *b, double *x, double rtol, int *iters,
     if (mb) {
       hipLaunchKernelGGL(fom_apply2d_kernel, dim3((n + 255) / 256), dim3(256), 0, p->stream,
                          p->n, p->V + (size_t)(m - 1) * n,
-                         reinterpret_cast<const cpx<double> *>(p->twd), p->uni[3], p->uni[4],
+                         p->twd + p->twd_cos, p->uni[3], p->uni[4],
                          p->uni[5], p->wvec);
       morth(p->wvec, m, T, m - 1);
       hipLaunchKernelGGL(fom_mdots_kernel, dim3(NB), dim3(MB), 0, p->stream, n, 0, p->V,
@@ -703,7 +703,7 @@ pd_status pd_mvec_norm2(pd_plan p, int n, const double *w, double *out, int acc,
 pd_status pd_apply2d(pd_plan p, const double *v, double *w) {
   const int n = p->nbar;
   hipLaunchKernelGGL(fom_apply2d_kernel, dim3((n + 255) / 256), dim3(256), 0, p->stream, p->n, v,
-                     reinterpret_cast<const cpx<double> *>(p->twd), p->uni[3], p->uni[4],
+                     p->twd + p->twd_cos, p->uni[3], p->uni[4],
                      p->uni[5], w);
   PD_HIP_CHECK(hipGetLastError());
   return PD_OK;

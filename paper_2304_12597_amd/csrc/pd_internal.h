@@ -227,6 +227,9 @@ struct pd_plan_s {
   int fft_stride = 0;          // LDS column stride (complex elements)
   int dst_C = 1;               // 2D: row pairs per DST-I block
   double *twd = nullptr;       // 2D: exp(-2 pi i m / (2(n+1))) twiddles
+  int dst_L = 0;               // 2D: 0 if n + 1 is a power of two, else the
+                               // chirp-z DST's FFT length L >= 2n - 1
+  size_t twd_chirp = 0, twd_bhat = 0, twd_cos = 0;   // offsets (doubles) in twd
   double *wreal = nullptr;     // 2D: [ell][nbar] float64 work array (DST-x domain);
                                // BDF: the time-domain input of the transforms
   // BDF of order s (Section 5); s = 1 is backward Euler and uses none of these
@@ -271,6 +274,7 @@ pd_status pd_launch_tridiag(pd_plan p, int mode, const void *in,
 pd_status pd_launch_dst_x(pd_plan p, int mode, const double *u0, const double *F,
                           const double *U, const double *in, double *out, int accumulate);
 int pd_choose_dst_C(int n);
+int pd_dst_chirp_length(int n);
 Line2DConfig pd_choose_line2d(int n, int F2, int prec, int cus);
 void pd_line2d_factors(const pd_plan p, std::vector<double> &fac);
 pd_status pd_launch_line2d(pd_plan p, int mode, const void *in, const double *xv, void *out);

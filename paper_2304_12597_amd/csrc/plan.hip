@@ -42,6 +42,43 @@ void cis(long k, long N, double &c, double &s) {
   }
 }
 
+// Tables of the chirp-z DST-I of length n (N1 = n + 1), FFT length L:
+// chirp[j] = exp(i pi j^2 / (2 N1)) for j = 0..n (j^2 reduced mod 4 N1), and
+// bhat = (1/L) DFT_L of the wrapped conjugate chirp b[d mod L] = conj(c_|d|),
+// |d| <= n - 1 (zero elsewhere), summed in long double.  Interleaved re, im.
+void chirp_tables(int n, int L, double *chirp, double *bhat) {
+  const long M = 4L * (n + 1);
+  for (int j = 0; j <= n; ++j) {
+    double c, s;
+    cis(((long)j * j) % M, M, c, s);
+    chirp[2 * j] = c;
+    chirp[2 * j + 1] = s;
+  }
+  std::vector<double> wr(L), wi(L), br(L, 0.0), bi(L, 0.0);
+  for (int m = 0; m < L; ++m) {
+    double c, s;
+    cis(m, L, c, s);
+    wr[m] = c;    // exp(-2 pi i m / L)
+    wi[m] = -s;
+  }
+  for (int d = -(n - 1); d <= n - 1; ++d) {
+    const int q = d >= 0 ? d : d + L, a = d >= 0 ? d : -d;
+    br[q] = chirp[2 * a];
+    bi[q] = -chirp[2 * a + 1];
+  }
+  for (int k = 0; k < L; ++k) {
+    long double sr = 0.0L, si = 0.0L;
+    for (int d = -(n - 1); d <= n - 1; ++d) {
+      const int q = d >= 0 ? d : d + L;
+      const int m = (int)(((long)k * q) & (L - 1));
+      sr += (long double)br[q] * wr[m] - (long double)bi[q] * wi[m];
+      si += (long double)br[q] * wi[m] + (long double)bi[q] * wr[m];
+    }
+    bhat[2 * k] = (double)(sr / L);
+    bhat[2 * k + 1] = (double)(si / L);
+  }
+}
+
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 // BDF coefficients of order s <= 6 (Section 5, table of BDF coefficients):
@@ -136,14 +173,20 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
       pd_set_error("2D line tile does not fit in LDS");
       return PD_ENOTSUP;
     }
+    p->dst_L = pd_dst_chirp_length(n);   // 0: n + 1 a power of two
+    const int ND = p->dst_L ? p->dst_L : 2 * (n + 1);
     p->dst_C = pd_choose_dst_C(n);
-    if (((size_t)p->dst_C * pd_fft_col_stride(2 * (n + 1)) + pd_tw_entries(2 * (n + 1))) * 16 >
-        max_lds) {
+    if (((size_t)p->dst_C * pd_fft_col_stride(ND) + pd_tw_entries(ND)) * 16 > max_lds) {
       pd_set_error("DST tile does not fit in LDS");
       return PD_ENOTSUP;
     }
     L.fac = (size_t)F2 * n * 6 * (p->l2d.MR - 1) * 2;
-    L.twd = 4 * (size_t)(n + 1);
+    // twiddles of the DST's FFT length; for the chirp-z form the chirp c_j
+    // (j = 0..n) and the transformed wrapped chirp; then cos(pi (j+1)/(n+1))
+    p->twd_chirp = 2 * (size_t)ND;
+    p->twd_bhat = p->twd_chirp + (p->dst_L ? 2 * (size_t)(n + 1) : 0);
+    p->twd_cos = p->twd_bhat + (p->dst_L ? 2 * (size_t)p->dst_L : 0);
+    L.twd = p->twd_cos + (size_t)n;
     L.wreal = (size_t)ell * p->nbar;
     if ((size_t)p->l2d.nkc * p->nbar > L.partials) L.partials = (size_t)p->l2d.nkc * p->nbar;
     L.rstage = std::max(L.rstage, (size_t)((p->l2d.nkc + 15) / 16) * p->nbar);
@@ -431,8 +474,8 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
       pd_set_error("2D plans take M = I (pass NULL)");
       return PD_EINVAL;
     }
-    if (n > 1023 || !is_pow2(n + 1)) {
-      pd_set_error("2D plans need n + 1 a power of two, n <= 1023");
+    if (n > 1024) {
+      pd_set_error("2D plans need n <= 1024");
       return PD_ENOTSUP;
     }
     const double d0 = K->diag[0], o0 = K->upper[0];
@@ -656,13 +699,19 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   std::vector<double> twd;
   if (p->dims == 2) {
     pd_line2d_factors(p, fac);
-    const int N = 2 * (n + 1);
-    twd.resize(2 * (size_t)N);
+    const int N = p->dst_L ? p->dst_L : 2 * (n + 1);
+    twd.assign(p->twd_cos + (size_t)n, 0.0);
     for (int m = 0; m < N; ++m) {
       double c, s;
       cis(m, N, c, s);
       twd[2 * m] = c;
       twd[2 * m + 1] = -s;
+    }
+    if (p->dst_L) chirp_tables(n, p->dst_L, &twd[p->twd_chirp], &twd[p->twd_bhat]);
+    for (int j = 0; j < n; ++j) {
+      double c, s;
+      cis(j + 1, 2 * (n + 1), c, s);
+      twd[p->twd_cos + j] = c;
     }
   } else if (p->uniform) {
     pd_uniform_factors(p, p->tri.MR, fac);

@@ -34,7 +34,10 @@ def dst_x(A, n):
     return dst.dst1(A.reshape(A.shape[:-1] + (n, n)), axis=-1).reshape(A.shape)
 
 
-@pytest.mark.parametrize("n,ell", [(3, 4), (7, 8), (31, 32), (63, 16), (127, 8)])
+# n + 1 a power of two (one FFT of length 2(n+1) per pair of rows) and other
+# n (the chirp-z form: FFTs of length L >= 2n - 1)
+@pytest.mark.parametrize("n,ell", [(3, 4), (7, 8), (31, 32), (63, 16), (127, 8),
+                                   (2, 4), (4, 4), (6, 8), (20, 8), (100, 4), (256, 2)])
 @pytest.mark.parametrize("prec", [0, 2])
 def test_2d_forward_transform(lib, n, ell, prec):
     p = wl.heat_2d(n, ell, 0.1, 1.0, np.random.default_rng(n))
@@ -90,7 +93,10 @@ def _solve(lib, p, prec=0, tol=1e-10, **kw):
 @pytest.mark.parametrize("n,ell,nu,T_,bound", [(3, 2, 1.0, 0.1, 1e-10), (7, 8, 1.0, 0.1, 1e-10),
                                                (31, 64, 0.01, 1.0, 1e-10),
                                                (127, 16, 1.0, 0.1, 1e-10),
-                                               (63, 256, 0.001, 0.1, 1e-9)])
+                                               (63, 256, 0.001, 0.1, 1e-9),
+                                               (2, 4, 1.0, 0.1, 1e-10), (6, 8, 1.0, 0.1, 1e-10),
+                                               (20, 16, 0.1, 1.0, 1e-10),
+                                               (100, 16, 1.0, 0.1, 1e-10)])
 def test_2d_end_to_end_fp64(lib, n, ell, nu, T_, bound):
     """nu*T = 1e-4 makes J_ell ill-conditioned (Theorem 1 bound
     1 + 1/(tau lambda_min) ~ 1e5): the solve uses a tighter tolerance and the

@@ -160,13 +160,14 @@ def test_fom_2d_matches_oracle(lib, n, ell, T_):
     assert 0 <= info.rel_residual < 1e-10
 
 
-def test_fom_2d_full_size_one_iteration(lib):
-    """The 2D example of Section 6.1 on a 511 x 511 grid: T = 1, ell = 256,
-    f = 0, u0 = xy(x - 1)(1 - y).  One step of Algorithm 2 brings the
-    capacitance residual below 1e-8 ||b|| (tol = 1e-6; the capacitance
-    stopping rule is tol/100), and U agrees with the GMRES solve at tol 1e-10
-    on sampled outputs."""
-    n, ell = 511, 256
+# 511: n + 1 a power of two; 256, 512 and 1024 are the grids of Table 1
+# (nbar = 65536, 262144, 1048576), run with the chirp-z DST along x
+@pytest.mark.parametrize("n,ell", [(511, 256), (256, 256), (512, 512), (1024, 256)])
+def test_fom_2d_full_size_one_iteration(lib, n, ell):
+    """The 2D example of Section 6.1: T = 1, f = 0, u0 = xy(x - 1)(1 - y).
+    One step of Algorithm 2 brings the capacitance residual below 1e-8 ||b||
+    (tol = 1e-6; the capacitance stopping rule is tol/100), and U agrees with
+    the GMRES solve at tol 1e-10 on sampled outputs."""
     p = wl.heat_2d(n, ell, 1.0, 1.0, np.random.default_rng(1))
     x = np.arange(1, n + 1) / (n + 1)
     X, Y = np.meshgrid(x, x)
