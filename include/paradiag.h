@@ -74,8 +74,9 @@ typedef enum {
                              /* reduction, capacitance system by GMRES (any M, K) */
   PD_SHIFTED_SINE = 1        /* 1D, float64, symmetric Toeplitz M and K (uniform */
                              /* grid, zero Dirichlet ends), n + 1 a power of two */
-                             /* >= 16: every shifted matrix and J_ell diagonal  */
-                             /* in the DST-I basis; capacitance solved exactly   */
+                             /* >= 16 or n <= 4095 (chirp-z DST): every shifted  */
+                             /* matrix and J_ell diagonal in the DST-I basis;    */
+                             /* capacitance solved exactly                       */
 } pd_shifted_solver;
 
 typedef enum {

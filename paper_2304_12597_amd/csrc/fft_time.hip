@@ -457,8 +457,10 @@ namespace {
 // a linear convolution of two length-n sequences, computed as a circular
 // one of length L >= 2n - 1: FFT in LDS, times bhat (the transform of the
 // wrapped conj(c_d), |d| < n, with 1/L folded in), inverse FFT.  One row
-// per LDS column; MODE and ACC as for dst_x_kernel.
-template <int MODE, int ACC>
+// per LDS column; MODE and ACC as for dst_x_kernel.  D1: the rows are the
+// ell time rows of a 1D array [ell][n] (MODE 0 or 2) instead of the grid rows
+// (t, y) of [ell][n*n].
+template <int MODE, int ACC, bool D1 = false>
 __global__ void __launch_bounds__(1024)
 dst_x_chirp_kernel(int n, int ell, int Lc, int C, int stride, double tau,
                    const double *__restrict__ u0, const double *__restrict__ F,
@@ -468,10 +470,11 @@ dst_x_chirp_kernel(int n, int ell, int Lc, int C, int stride, double tau,
                    double *__restrict__ out, double *__restrict__ red) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using Cx = cpx<double>;
+  static_assert(!(D1 && MODE == 1), "1D rows: MODE 0 or 2");
   Cx *lds = reinterpret_cast<Cx *>(smem_raw);
   const int T = blockDim.x, tid = threadIdx.x;
-  const int nbar = n * n;
-  const int rows = ell * n;
+  const int nbar = D1 ? n : n * n;
+  const int rows = D1 ? ell : ell * n;
   const int r0 = blockIdx.x * C;
   const int lgL = __builtin_ctz(Lc);
   Cx *twl = lds + C * stride;
@@ -495,7 +498,7 @@ dst_x_chirp_kernel(int n, int ell, int Lc, int C, int stride, double tau,
         const int lr = idx / n, x = idx - lr * n;
         const int row = r0 + lr;
         if (row < rows) {
-          const int t = row / n, y = row - t * n;
+          const int t = D1 ? row : row / n, y = D1 ? 0 : row - t * n;
           const int i = y * n + x;
           if (MODE == 0) {
             v = tau * F[(size_t)t * nbar + i];
@@ -546,7 +549,7 @@ dst_x_chirp_kernel(int n, int ell, int Lc, int C, int stride, double tau,
       if (ACC) {
         int row = r0 + lr;
         row = row < rows ? row : rows - 1;
-        const int t = row / n, y = row - t * n;
+        const int t = D1 ? row : row / n, y = D1 ? 0 : row - t * n;
         s[u] += out[(size_t)t * nbar + (size_t)y * n + m];
       }
     }
@@ -557,7 +560,7 @@ dst_x_chirp_kernel(int n, int ell, int Lc, int C, int stride, double tau,
         const int lr = idx / n, m = idx - lr * n;
         const int row = r0 + lr;
         if (row < rows) {
-          const int t = row / n, y = row - t * n;
+          const int t = D1 ? row : row / n, y = D1 ? 0 : row - t * n;
           out[(size_t)t * nbar + (size_t)y * n + m] = s[u];
         }
       }
@@ -690,6 +693,35 @@ pd_status pd_launch_dst_x_rows(pd_plan p, const double *in, double *out, int tro
   return PD_OK;
 }
 
+// Orthonormal DST-I of the ell time rows of a 1D array [ell][n] in chirp-z
+// form (sine-basis plans with n + 1 not a power of two).  mode 0: rows
+// h_t = tau f_t (+ u0 at t = 0); mode 1: rows of `in`.  out may equal in
+// (a block reads its rows completely before it writes them).
+pd_status pd_launch_dst_rows1d(pd_plan p, int mode, const double *u0, const double *F,
+                               const double *in, double *out) {
+  if (!p->dst_L) return PD_EINVAL;
+  const int N = p->dst_L, C = p->dst_C;
+  const int stride = pd_fft_col_stride(N);
+  const size_t lds = ((size_t)C * stride + pd_tw_entries(N)) * 16;
+  int need = C * N / 8;
+  if (need < 64) need = 64;
+  const int threads = ((need + 63) / 64) * 64;
+  const int blocks = (p->ell + C - 1) / C;
+  auto tw = reinterpret_cast<const cpx<double> *>(p->twd);
+  auto ch = reinterpret_cast<const cpx<double> *>(p->twd + p->twd_chirp);
+  auto bh = reinterpret_cast<const cpx<double> *>(p->twd + p->twd_bhat);
+  if (mode == 0)
+    hipLaunchKernelGGL((dst_x_chirp_kernel<0, 0, true>), dim3(blocks), dim3(threads), lds,
+                       p->stream, p->n, p->ell, N, C, stride, p->tau, u0, F, nullptr, nullptr,
+                       p->coef64, tw, ch, bh, out, p->red);
+  else
+    hipLaunchKernelGGL((dst_x_chirp_kernel<2, 0, true>), dim3(blocks), dim3(threads), lds,
+                       p->stream, p->n, p->ell, N, C, stride, p->tau, nullptr, nullptr, nullptr,
+                       in, p->coef64, tw, ch, bh, out, p->red);
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+
 pd_status pd_launch_fft_inverse(pd_plan p, const void *in, double *U, int accumulate) {
   FftLaunch L = fft_config(p);
   if (!fft_C_valid(L.C)) return PD_EINVAL;
@@ -732,6 +764,8 @@ void pd_fft_set_attributes(size_t max_lds) {
   pd_set_max_lds(reinterpret_cast<const void *>(&dst_x_chirp_kernel<1, 0>), v);
   pd_set_max_lds(reinterpret_cast<const void *>(&dst_x_chirp_kernel<2, 0>), v);
   pd_set_max_lds(reinterpret_cast<const void *>(&dst_x_chirp_kernel<2, 1>), v);
+  pd_set_max_lds(reinterpret_cast<const void *>(&dst_x_chirp_kernel<0, 0, true>), v);
+  pd_set_max_lds(reinterpret_cast<const void *>(&dst_x_chirp_kernel<2, 0, true>), v);
   pd_set_max_lds(reinterpret_cast<const void *>(&fft_inverse_kernel<double, 0>), v);
   pd_set_max_lds(reinterpret_cast<const void *>(&fft_inverse_kernel<double, 1>), v);
   pd_set_max_lds(reinterpret_cast<const void *>(&fft_inverse_kernel<float, 0>), v);

@@ -275,6 +275,8 @@ pd_status pd_launch_dst_x(pd_plan p, int mode, const double *u0, const double *F
                           const double *U, const double *in, double *out, int accumulate);
 int pd_choose_dst_C(int n);
 int pd_dst_chirp_length(int n);
+pd_status pd_launch_dst_rows1d(pd_plan p, int mode, const double *u0, const double *F,
+                               const double *in, double *out);
 Line2DConfig pd_choose_line2d(int n, int F2, int prec, int cus);
 void pd_line2d_factors(const pd_plan p, std::vector<double> &fac);
 pd_status pd_launch_line2d(pd_plan p, int mode, const void *in, const double *xv, void *out);

@@ -209,6 +209,21 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
       return PD_ENOTSUP;
     }
     L.sine = (size_t)N + 2 * (size_t)(H + 1) + 2 * (size_t)H + 2 * (size_t)n;
+    // n + 1 not a power of two: the DST of the time rows in chirp-z form, with
+    // the 2D plans' table layout (twiddles of L, chirp, transformed chirp)
+    p->dst_L = pd_dst_chirp_length(n);
+    if (p->dst_L) {
+      p->dst_C = pd_choose_dst_C(n);
+      if (((size_t)p->dst_C * pd_fft_col_stride(p->dst_L) + pd_tw_entries(p->dst_L)) * 16 >
+          max_lds) {
+        pd_set_error("sine transform tile does not fit in LDS");
+        return PD_ENOTSUP;
+      }
+      p->twd_chirp = 2 * (size_t)p->dst_L;
+      p->twd_bhat = p->twd_chirp + 2 * (size_t)(n + 1);
+      p->twd_cos = p->twd_bhat + 2 * (size_t)p->dst_L;
+      L.twd = p->twd_cos;
+    }
   }
   if (p->krylov == PD_KRYLOV_FOM) {
     L.fom = p->bdf_s > 1 ? pd_bgal_layout(p->nbar, F2).total : pd_fom_doubles(p->nbar, F2);
@@ -511,8 +526,9 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
     return PD_ENOTSUP;
   }
   if (opt.shifted_solver == PD_SHIFTED_SINE) {
-    if (opt.dims != 1 || opt.precision != PD_FP64 || !is_pow2(n + 1) || n + 1 < 16) {
-      pd_set_error("sine-basis solves need a 1D float64 plan with n + 1 a power of two >= 16");
+    if (opt.dims != 1 || opt.precision != PD_FP64 || (is_pow2(n + 1) ? n + 1 < 16 : n > 4095)) {
+      pd_set_error("sine-basis solves need a 1D float64 plan with n + 1 a power of two >= 16 "
+                   "or n <= 4095");
       return PD_ENOTSUP;
     }
     // symmetric Toeplitz M and K (constant diagonals, equal off-diagonals)
@@ -718,6 +734,16 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   }
   std::vector<float> fac32(fac.begin(), fac.end());
   std::vector<double> sq, swN, stwH, sm, sk;
+  if (p->sine && p->dst_L) {
+    twd.assign(p->twd_cos, 0.0);
+    for (int m = 0; m < p->dst_L; ++m) {
+      double c, s;
+      cis(m, p->dst_L, c, s);
+      twd[2 * m] = c;
+      twd[2 * m + 1] = -s;
+    }
+    chirp_tables(n, p->dst_L, &twd[p->twd_chirp], &twd[p->twd_bhat]);
+  }
   if (p->sine) {
     const int N = n + 1, H = N / 2;
     sq.resize(N);

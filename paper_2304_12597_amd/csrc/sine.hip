@@ -326,6 +326,7 @@ size_t pd_sine_modal_lds(pd_plan p, int threads) {
 
 pd_status pd_launch_sine_dst(pd_plan p, int mode, const double *u0, const double *F,
                              const double *in, double *out) {
+  if (p->dst_L) return pd_launch_dst_rows1d(p, mode, u0, F, in, out);   // any n
   const int n = p->n, H = (n + 1) / 2, C = p->sine_C;
   const int T = C * H / 8;
   if (T < 1 || T > 512 || p->ell % C != 0) return PD_EINVAL;

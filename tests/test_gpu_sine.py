@@ -30,8 +30,10 @@ def make_problem(kind, n, ell, seed, nu=1.0, T_=1.0):
     return wl.heat_1d(kind, n, ell, T_, nu, np.random.default_rng(seed), True)
 
 
+# n + 1 a power of two, and other n (chirp-z form, n <= 4095)
 @pytest.mark.parametrize("n,ell", [(15, 2), (31, 4), (63, 8), (255, 64), (1023, 16),
-                                   (4095, 4), (8191, 2)])
+                                   (4095, 4), (8191, 2), (2, 2), (20, 4), (100, 4), (1000, 8),
+                                   (4000, 2)])
 def test_sine_transform(lib, n, ell):
     p = make_problem("fd1", n, ell, n)
     plan = sine_plan(lib, p)
@@ -65,7 +67,8 @@ def _solve(lib, p, tol=1e-10, **kw):
 @pytest.mark.parametrize("kind,n,ell,nu", [
     ("fd1", 15, 2, 1.0), ("fd1", 31, 8, 1.0), ("fem1", 63, 32, 0.1), ("fd1", 255, 256, 1e-3),
     ("fem1", 1023, 128, 1.0), ("fd1", 2047, 1024, 0.01), ("fem1", 4095, 64, 1e-3),
-    ("fd1", 127, 4096, 1.0)])
+    ("fd1", 127, 4096, 1.0), ("fd1", 100, 16, 1.0), ("fem1", 1000, 64, 0.1),
+    ("fd1", 3000, 32, 1e-2)])
 def test_sine_solve_matches_exact(lib, kind, n, ell, nu):
     """The sine-basis solve reaches the exact all-at-once solution to float64
     rounding (no elimination floor), with no Krylov iterations."""
@@ -116,7 +119,7 @@ def test_sine_fem_full_size_sampled(lib):
 
 
 def test_sine_plan_rejects_unsupported(lib):
-    p = make_problem("fd1", 100, 8, 1)          # n + 1 not a power of two
+    p = make_problem("fd1", 5000, 8, 1)         # n + 1 not a power of two and n > 4095
     with pytest.raises(RuntimeError):
         sine_plan(lib, p)
     p = make_problem("fd1", 63, 8, 1)
