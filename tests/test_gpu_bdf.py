@@ -307,7 +307,9 @@ def test_block_galerkin_zero_data_and_small_n(lib):
 
 # ------------------------------------------------------------------- 2D --
 
-@pytest.mark.parametrize("n,ell,s", [(15, 16, 2), (31, 32, 3), (15, 16, 6), (63, 16, 4)])
+# n = 10 and 20: the chirp-z DST along x (n + 1 not a power of two)
+@pytest.mark.parametrize("n,ell,s", [(15, 16, 2), (31, 32, 3), (15, 16, 6), (63, 16, 4),
+                                     (10, 16, 2), (20, 16, 3)])
 def test_bdf_2d_matches_stepping(lib, n, ell, s):
     """2D FD heat (M = I, K = I (x) T + T (x) I; the DST-x domain of the
     shifted solves): random starting values and source, U against BDF
@@ -337,9 +339,11 @@ def test_bdf_2d_matches_stepping(lib, n, ell, s):
     assert abs(info.rel_residual - r) <= 1e-12
 
 
-def test_bdf_2d_capacitance_apply(lib):
-    """The 2D block product against the oracle's dense J^(s)."""
-    n, ell, s = 7, 16, 2
+@pytest.mark.parametrize("n", [7, 6])
+def test_bdf_2d_capacitance_apply(lib, n):
+    """The 2D block product against the oracle's dense J^(s) (n = 6: the
+    chirp-z DST along x)."""
+    ell, s = 16, 2
     rng = np.random.default_rng(3)
     p = wl.heat_2d(n, ell, 0.1, 1.0, rng)
     U0 = rng.standard_normal((s, p.nbar))
@@ -360,7 +364,8 @@ def test_bdf_2d_capacitance_apply(lib):
     assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
 
 
-@pytest.mark.parametrize("n,ell,T_,s", [(15, 16, 1.0, 2), (15, 16, 1.0, 3), (31, 16, 1.0, 2)])
+@pytest.mark.parametrize("n,ell,T_,s", [(15, 16, 1.0, 2), (15, 16, 1.0, 3), (31, 16, 1.0, 2),
+                                        (20, 16, 1.0, 2)])
 def test_bdf_2d_block_galerkin_matches_oracle(lib, n, ell, T_, s):
     """The block Galerkin method on 2D plans (in the DST-x domain, multi-block
     Gram-Schmidt): the oracle's step count and U."""

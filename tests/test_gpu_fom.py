@@ -127,7 +127,7 @@ def test_fom_zero_data(lib):
 # ------------------------------------------------------------------- 2D --
 
 @pytest.mark.parametrize("n,ell,T_", [(15, 16, 0.1), (15, 16, 1.0), (31, 16, 1.0),
-                                     (31, 32, 1.0), (63, 16, 1.0)])
+                                     (31, 32, 1.0), (63, 16, 1.0), (20, 16, 1.0), (50, 16, 1.0)])
 def test_fom_2d_matches_oracle(lib, n, ell, T_):
     """2D plans (the DST-x domain of the line solves, multi-block vector
     kernels): the same Krylov dimension as the oracle's Algorithm 2 and the
