@@ -33,7 +33,7 @@ def make_problem(kind, n, ell, seed, nu=1.0, T_=1.0):
 # n + 1 a power of two, and other n (chirp-z form, n <= 4095)
 @pytest.mark.parametrize("n,ell", [(15, 2), (31, 4), (63, 8), (255, 64), (1023, 16),
                                    (4095, 4), (8191, 2), (2, 2), (20, 4), (100, 4), (1000, 8),
-                                   (4000, 2)])
+                                   (4000, 2), (4094, 2)])
 def test_sine_transform(lib, n, ell):
     p = make_problem("fd1", n, ell, n)
     plan = sine_plan(lib, p)
