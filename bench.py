@@ -474,10 +474,24 @@ def bench_fom(args, torch, pd, wl, dev):
                 probs.append(p)
             finally:
                 pd.paradiag_plan_destroy(plan)
-    # the 2D example of Section 6.1 (f = 0, u0 = xy(x-1)(1-y), T = 1) on a
-    # 511 x 511 grid, ell = 256, inner tolerance 1e-8 as in the paper (tol
-    # 1e-6: the capacitance stopping rule is tol/100)
-    n2, ell2 = 511, 256
+    # the 2D example of Section 6.1 (f = 0, u0 = xy(x-1)(1-y), T = 1), inner
+    # tolerance 1e-8 as in the paper (tol 1e-6: the capacitance stopping rule
+    # is tol/100), on a 511 x 511 grid and on the grids of Table 1 as printed
+    # (256^2, 512^2, 1024^2: the chirp-z DST along x)
+    cases61 = [(511, 256), (256, 256), (256, 1024), (512, 512), (1024, 256)]
+    for n2, ell2 in cases61:
+        rows.extend(section61_rows(pd, torch, wl, stream, dev, args, n2, ell2))
+    out = {"metric": "capacitance solver comparison (GMRES vs Algorithm 2)",
+           "value": None, "unit": "ms per solve", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": False, "dtype": "f64",
+           "data": "synthetic", "config": {"workload": "1D heat, three problems", "tol": tol},
+           "rows": rows}
+    return finish_fom(out, args, probs, Us)
+
+
+def section61_rows(pd, torch, wl, stream, dev, args, n2, ell2):
+    """GMRES and Algorithm 2 (q = 1) on the Section 6.1 example, n2^2 grid."""
+    rows = []
     p2 = wl.heat_2d(n2, ell2, 1.0, 1.0, np.random.default_rng(1))
     xg = np.arange(1, n2 + 1) / (n2 + 1)
     X, Y = np.meshgrid(xg, xg)
@@ -496,21 +510,24 @@ def bench_fom(args, torch, pd, wl, dev):
                 info = pd.paradiag_solve(plan, u02, F2d, U2d, 1e-6, allow_notconv=True)
             torch.cuda.synchronize()
             wall = (time.perf_counter() - t0) / args.steps
-            rows.append({"problem": "2D Section 6.1: 511^2 ell=256 T=1 u0=xy(x-1)(1-y) tol=1e-6",
+            rows.append({"problem": "2D Section 6.1: %d^2 ell=%d T=1 u0=xy(x-1)(1-y) tol=1e-6"
+                                    % (n2, ell2),
                          "krylov": name, "ms": 1e3 * wall, "steps": info.gmres_iters,
                          "pint_loops": info.pint_loops,
-                         "capacitance_rel_residual": info.gmres_rel_residual})
+                         "capacitance_rel_residual": info.gmres_rel_residual,
+                         "unknowns_per_s": n2 * n2 * ell2 / wall})
         finally:
             pd.paradiag_plan_destroy(plan)
-    out = {"metric": "capacitance solver comparison (GMRES vs Algorithm 2)",
-           "value": None, "unit": "ms per solve", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "higher_is_better": False, "dtype": "f64",
-           "data": "synthetic", "config": {"workload": "1D heat, three problems", "tol": tol},
-           "rows": rows}
+    del F2d, U2d
+    return rows
+
+
+def finish_fom(out, args, probs, Us):
+    """Sampled error of the 1D rows against the exact modal solution."""
     if not args.no_cpu_baseline:
         from oracle import modal
         rng = np.random.default_rng(0)
-        for r, U, p in zip(rows, Us, probs):
+        for r, U, p in zip(out["rows"], Us, probs):
             tt = rng.integers(0, p.ell, 4000)
             ii = rng.integers(0, p.nbar, 4000)
             ref = modal.modal_sample(p, tt, ii)
