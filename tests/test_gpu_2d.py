@@ -118,8 +118,11 @@ def test_2d_with_source_matches_stepping(lib):
     assert allatonce.rel_err(U, allatonce.step(p)) < 1e-11
 
 
-def test_2d_mixed(lib):
-    p = wl.heat_2d(63, 32, 0.1, 1.0, np.random.default_rng(2))
+# n = 100: the refinement's fused residual and accumulating inverse run on
+# the chirp-z DST along x
+@pytest.mark.parametrize("n", [63, 100])
+def test_2d_mixed(lib, n):
+    p = wl.heat_2d(n, 32, 0.1, 1.0, np.random.default_rng(2))
     U, info = _solve(lib, p, prec=1, tol=1e-10)
     err = allatonce.rel_err(U, modal.modal_solution(p))
     assert err < 1e-8, (err, info.as_dict())
