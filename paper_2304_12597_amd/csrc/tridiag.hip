@@ -31,8 +31,12 @@ namespace {
 // dst[idx] = cvt(src[idx - 1]) for idx = lt, lt + P, ... < count, zero where
 // idx - 1 lies outside [0, n) or when !on.  Each thread issues U loads (at
 // clamped, always valid addresses) before its first store, so their
-// latencies overlap instead of adding up.
-template <int U, typename T, typename S, typename Cvt>
+// latencies overlap instead of adding up.  PAD: entry idx is stored at
+// pad16(idx), one spare slot per 16, so that threads reading 16 consecutive
+// entries each (lane stride 17) spread over the LDS banks.
+__device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
+
+template <int U, bool PAD = false, typename T, typename S, typename Cvt>
 __device__ __forceinline__ void stage_halo(T *dst, const S *__restrict__ src, int count, int n,
                                            int lt, int P, bool on, T zero, Cvt cvt) {
   for (int b = lt; b < count; b += U * P) {
@@ -46,21 +50,26 @@ __device__ __forceinline__ void stage_halo(T *dst, const S *__restrict__ src, in
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (b + u * P < count) dst[b + u * P] = v[u];
+      if (b + u * P < count) dst[PAD ? pad16(b + u * P) : b + u * P] = v[u];
   }
 }
 
 // mx[q] = -w (M x)_{s0+q} in float64, rounded once to R (zero past row n-1).
-// x is staged with a zero halo through sx (count >= n + 2 doubles of this
-// thread group's LDS); M's rows come from coef64 = [ML | MD | MU | ...].
+// x is staged with a zero halo through sx (count >= n + 2 entries; float64
+// plans store them at pad16(), pad16(count - 1) + 1 doubles, which their
+// complex128 staging area holds; float32 plans' complex64 area holds only
+// count doubles, so they store them unpadded).  M's rows come from
+// coef64 = [ML | MD | MU | ...].
 // Contains a block barrier.
 template <typename R, int MR, bool UNI>
 __device__ __forceinline__ void minus_w_mx(R (&mx)[MR], double *sx, int count,
                                            const double *__restrict__ coef64,
                                            const double *__restrict__ xv, double w, int n,
                                            int s0, int lt, int P) {
-  stage_halo<8>(sx, xv != nullptr ? xv : coef64, count, n, lt, P, xv != nullptr, 0.0,
-                [](double v) { return v; });
+  constexpr bool PAD = sizeof(R) == sizeof(double);
+  auto at = [](int i) { return PAD ? pad16(i) : i; };
+  stage_halo<8, PAD>(sx, xv != nullptr ? xv : coef64, count, n, lt, P, xv != nullptr, 0.0,
+                     [](double v) { return v; });
   __syncthreads();
   const double ml0 = coef64[n - 1 > 0 ? n - 1 : 0], md0 = coef64[n], mu0 = coef64[2 * n];
 #pragma unroll
@@ -70,9 +79,9 @@ __device__ __forceinline__ void minus_w_mx(R (&mx)[MR], double *sx, int count,
     const double md = UNI ? md0 : coef64[n + ic];
     const double ml = UNI ? ml0 : coef64[ic];
     const double mu = UNI ? mu0 : coef64[2 * n + ic];
-    double v = md * sx[ic + 1];
-    v += ((ic > 0) ? ml : 0.0) * sx[ic];
-    v += ((ic < n - 1) ? mu : 0.0) * sx[ic + 2];
+    double v = md * sx[at(ic + 1)];
+    v += ((ic > 0) ? ml : 0.0) * sx[at(ic)];
+    v += ((ic < n - 1) ? mu : 0.0) * sx[at(ic + 2)];
     mx[q] = (i < n) ? (R)(-w * v) : R(0);
   }
 }
@@ -565,12 +574,13 @@ __device__ __forceinline__ void tridiag_pipe_body(
   if constexpr (MODE == 2) {
     // M v is the same for all frequencies: form it once, in registers
     double *sv = reinterpret_cast<double *>(stage);
-    stage_halo<8>(sv, vin, rows + 2, n, lt, P, true, 0.0, [](double v) { return v; });
+    stage_halo<8, true>(sv, vin, rows + 2, n, lt, P, true, 0.0, [](double v) { return v; });
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < MR; ++q) {
       const int i = s0 + q < n ? s0 + q : n - 1;
-      dv[q] = (q < len) ? cf.md * sv[i + 1] + cf.ml * sv[i] + cf.mu * sv[i + 2] : R(0);
+      dv[q] = (q < len) ? cf.md * sv[pad16(i + 1)] + cf.ml * sv[pad16(i)] + cf.mu * sv[pad16(i + 2)]
+                        : R(0);
     }
   }
   __syncthreads();   // the staging area is free for the DMA
