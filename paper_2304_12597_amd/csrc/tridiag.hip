@@ -773,14 +773,18 @@ __device__ __forceinline__ void tridiag_pipe_body(
 
   if constexpr (MODE != 1) {
     __syncthreads();
-    double *sd = reinterpret_cast<double *>(smem_raw) + (size_t)g * rows;
+    // padded (pad16) so that the per-thread writes of 16 consecutive rows
+    // spread over the banks; spb * gstride doubles fit in the complex128
+    // staging area (2 * spb * rows doubles)
+    const int gstride = pad16(rows - 1) + 1;
+    double *sd = reinterpret_cast<double *>(smem_raw) + (size_t)g * gstride;
 #pragma unroll
-    for (int q = 0; q < MR; ++q) sd[s0 + q] = acc[q];
+    for (int q = 0; q < MR; ++q) sd[pad16(s0 + q)] = acc[q];
     __syncthreads();
     const double *base = reinterpret_cast<double *>(smem_raw);
     for (int i = tid; i < n; i += blockDim.x) {
       double s = 0.0;
-      for (int gg = 0; gg < spb; ++gg) s += base[(size_t)gg * rows + i];
+      for (int gg = 0; gg < spb; ++gg) s += base[(size_t)gg * gstride + pad16(i)];
       partials[(size_t)blk * n + i] = s;
     }
   }
