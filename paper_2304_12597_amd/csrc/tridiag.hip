@@ -317,14 +317,20 @@ tridiag_kernel(int n, int F2, int P, int spb, int nitems, Coef<R> cf,
   if constexpr (MODE != 1) {
     // sum the systems of this block and write one partial row per block
     __syncthreads();
-    double *sd = reinterpret_cast<double *>(smem_raw) + (size_t)g * rows;
+    // float64: padded (pad16) so that the per-thread writes of 16
+    // consecutive rows spread over the banks (spb * gstride doubles fit in
+    // the complex128 staging area); float32's complex64 area has no room
+    constexpr bool PADE = sizeof(R) == sizeof(double);
+    const int gstride = PADE ? pad16(rows - 1) + 1 : rows;
+    auto at = [](int i) { return PADE ? pad16(i) : i; };
+    double *sd = reinterpret_cast<double *>(smem_raw) + (size_t)g * gstride;
 #pragma unroll
-    for (int q = 0; q < MR; ++q) sd[s0 + q] = acc[q];
+    for (int q = 0; q < MR; ++q) sd[at(s0 + q)] = acc[q];
     __syncthreads();
     const double *base = reinterpret_cast<double *>(smem_raw);
     for (int i = tid; i < n; i += blockDim.x) {
       double s = 0.0;
-      for (int gg = 0; gg < spb; ++gg) s += base[(size_t)gg * rows + i];
+      for (int gg = 0; gg < spb; ++gg) s += base[(size_t)gg * gstride + at(i)];
       partials[(size_t)blockIdx.x * n + i] = s;
     }
   }
@@ -482,14 +488,20 @@ __device__ __forceinline__ void tridiag_uniform_body(
 
   if constexpr (MODE != 1) {
     __syncthreads();
-    double *sd = reinterpret_cast<double *>(smem_raw) + (size_t)g * rows;
+    // float64: padded (pad16) so that the per-thread writes of 16
+    // consecutive rows spread over the banks (spb * gstride doubles fit in
+    // the complex128 staging area); float32's complex64 area has no room
+    constexpr bool PADE = sizeof(R) == sizeof(double);
+    const int gstride = PADE ? pad16(rows - 1) + 1 : rows;
+    auto at = [](int i) { return PADE ? pad16(i) : i; };
+    double *sd = reinterpret_cast<double *>(smem_raw) + (size_t)g * gstride;
 #pragma unroll
-    for (int q = 0; q < MR; ++q) sd[s0 + q] = acc[q];
+    for (int q = 0; q < MR; ++q) sd[at(s0 + q)] = acc[q];
     __syncthreads();
     const double *base = reinterpret_cast<double *>(smem_raw);
     for (int i = tid; i < n; i += blockDim.x) {
       double s = 0.0;
-      for (int gg = 0; gg < spb; ++gg) s += base[(size_t)gg * rows + i];
+      for (int gg = 0; gg < spb; ++gg) s += base[(size_t)gg * gstride + at(i)];
       partials[(size_t)blk * n + i] = s;
     }
   }
