@@ -18,8 +18,10 @@ allatonce   the all-at-once system: right-hand side G, residual, dense
             Kronecker matrix and its LU solve (O2), sequential backward-Euler
             stepping (O1; C code for 1D, banded Cholesky for 2D)
 modal       exact per-sine-mode recurrences for sine-series data (O3)
-paradiag    Algorithm 1 (and the alpha-circulant variant, Algorithm 3) step
-            by step, the capacitance matrix J_ell, explicit SMW with
-            Kronecker products (O4), plain GMRES
+paradiag    the objects of Algorithm 1 / 3, each from its own definition (the
+            spectrum of G, blockwise shifted solves, the alpha-circulant
+            solution U_1 by stepping, b, x = J^{-1} b), the capacitance
+            matrix J_ell, explicit SMW with Kronecker products (O4), plain
+            GMRES and the Galerkin projection of Section 3
 dst         the orthonormal DST-I sine matrix
 """

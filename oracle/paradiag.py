@@ -1,10 +1,17 @@
-"""ORACLE (test infrastructure only): ParaDiag for backward Euler, step by step.
+"""ORACLE (test infrastructure only): the objects of the ParaDiag method, each
+from its own definition.
 
-Follows Section 2 (Algorithm 1) and Section 4 (Algorithm 3, alpha-circulant
-variant) of Gander & Palitta, generalised with a mass matrix M: the
-all-at-once equation is (M + tau K) U - M U Sigma_1^T = G and every shifted
-block becomes P_i = (1 - pi_i) M + tau K, the capacitance matrix
+Section 2 (Algorithm 1) and Section 4 (Algorithm 3, alpha-circulant variant)
+of Gander & Palitta, generalised with a mass matrix M: the all-at-once
+equation is (M + tau K) U - M U Sigma_1^T = G, every shifted block becomes
+P_i = (1 - pi_i) M + tau K and the capacitance matrix
 J_ell = I + alpha^(1/ell) sum_i gamma_i P_i^{-1} M.
+
+Nothing here chains the algorithm's steps: the spectrum of G, the blockwise
+shifted solves, the alpha-circulant solution U_1 (by stepping, with no
+Fourier transform), b (a time slice of U_1), x = J_ell^{-1} b and the
+projection method of Section 3 are computed separately, so that the pins can
+check the Sherman-Morrison-Woodbury identities that connect them.
 
 Notation (paper): F is the ell x ell DFT matrix F_{jk} = omega^{(j-1)(k-1)},
 omega = exp(-2 pi i / ell); pi = alpha^(1/ell) F C_1 e_1 are the eigenvalues
@@ -12,8 +19,8 @@ of the (alpha-)circulant, gamma = F^{-T} e_ell; D_alpha =
 diag(1, alpha^(1/ell), ..., alpha^((ell-1)/ell)).  Arrays are time-major, so
 the paper's "post-multiply by F^T" is an FFT along axis 0 here.
 
-Every step uses plain library primitives (numpy FFT, scipy sparse LU, dense
-numpy solves); nothing is blocked, fused or reordered.
+Every piece uses plain library primitives (numpy FFT, scipy sparse LU, dense
+numpy solves); nothing is blocked or fused.
 """
 from __future__ import annotations
 
@@ -123,128 +130,145 @@ def gmres(matvec, b, tol=1e-12, maxit=200):
     return x, m, hist
 
 
-def fom(cap, Msp, Ksp, tau, b, eps=1e-8, maxit=50, q=1):
-    """Algorithm 2: the FOM-like projection of J_ell x = b onto a polynomial
-    Krylov space, with the residual computed (and the small system solved)
-    every q-th iteration.
+def galerkin_projection(cap, Msp, Ksp, tau, b, eps=1e-8, maxit=50, q=1):
+    """Section 3: the projection method for J_ell x = b on a polynomial
+    Krylov space, written from its definition.
 
-    The space is K_m(A, b) with A = tau M^{-1} K, which is the paper's
-    K_m(K, b) when M = I (a scalar multiple does not change the space).  With
-    the Arnoldi relation A V_m = V_m T_m + t_{m+1,m} v_{m+1} e_m^T every
-    shifted operator P_i^{-1} M = (lambda_i I + A)^{-1}, lambda_i = 1 - pi_i,
-    satisfies the shift-invariant relation of Section 3 (tau, which the
-    printed relation leaves off the t_{m+1,m} term, is inside A here), so
-      S_i = (lambda_i I_m + T_m)^{-1},  h_i = P_i^{-1} M v_{m+1},
-      (I + w sum_i gamma_i (I - t_{m+1,m} V_m^T h_i e_m^T) S_i) y = beta e_1,
-      ||r|| = |t_{m+1,m}| w || (I - V_m V_m^T) sum_i gamma_i h_i e_m^T S_i y ||
-    (eq. compute_ym and eq. compute_resnorm, with the alpha weight w of
-    Section 4 and gamma_i in the residual as in eq. compute_resnorm).
-    The loop runs at most maxit iterations.  Returns (x, m, residual norms at
+    The space is K_m(A, b) with A = tau M^{-1} K (the paper's K_m(K, b) when
+    M = I; a scalar multiple of the operator spans the same space).  An
+    orthonormal basis V_m is built by Arnoldi with two Gram-Schmidt passes,
+    and the iterate x_m = V_m y is fixed by the Galerkin condition
+    V_m^T (J_ell x_m - b) = 0, i.e. (V_m^T J_ell V_m) y = ||b|| e_1, with
+    J_ell applied to each basis vector through its definition (the sparse LU
+    solves of ``Capacitance``).  The residual ||J_ell x_m - b|| is evaluated
+    directly, every q-th dimension and at maxit, and the iteration stops
+    once it is at most eps ||b||.
+
+    The paper reaches the same projected matrix without applying J_ell to
+    the basis, through the shifted Arnoldi relation (eq. compute_ym), and the
+    same residual through eq. compute_resnorm; the pins compare those
+    formulas with this direct evaluation.  Returns (x, m, residual norms at
     the checks)."""
     b = np.asarray(b, dtype=np.float64)
     beta = float(np.linalg.norm(b))
     if beta == 0.0:
         return np.zeros_like(b), 0, [0.0]
     Mlu = spla.splu(Msp.tocsc())
-    V = [b / beta]
-    T = np.zeros((maxit + 1, maxit))
-    m = 0
-    res = np.inf
+    basis = [b / beta]
+    images = []                 # J_ell applied to each basis vector
     hist = []
-    y = np.zeros(0)
-    lam = 1.0 - cap.pi
-    while res > eps * beta and m < maxit:
+    x = np.zeros_like(b)
+    m = 0
+    exhausted = False
+    while m < maxit and not exhausted:
         m += 1
-        w = tau * Mlu.solve(Ksp @ V[m - 1])
-        for k in range(m):
-            T[k, m - 1] = V[k] @ w
-            w = w - T[k, m - 1] * V[k]
-        T[m, m - 1] = np.linalg.norm(w)
-        V.append(w / T[m, m - 1])
-        if m % q == 0 or m == maxit:
-            Tm = T[:m, :m]
-            t = T[m, m - 1]
-            Vm = np.array(V[:m]).T                     # nbar x m
-            Mv = Msp @ V[m]
-            Z = np.eye(m, dtype=np.complex128)
-            S, H = [], []
-            for i, g in enumerate(cap.gamma):
-                Si = np.linalg.inv(lam[i] * np.eye(m) + Tm)
-                hi = cap.solve_shifted(i, Mv)
-                pi_ = Vm.T @ hi
-                em = np.zeros(m); em[-1] = 1.0
-                Z += cap.weight * g * (np.eye(m) - t * np.outer(pi_, em)) @ Si
-                S.append(Si)
-                H.append(hi)
-            e1 = np.zeros(m); e1[0] = beta
-            y = np.linalg.solve(Z, e1).real
-            z = sum(g * H[i] * (S[i][-1] @ y) for i, g in enumerate(cap.gamma))
-            rho = z - Vm @ (Vm.T @ z)
-            res = abs(t) * cap.weight * float(np.linalg.norm(rho))
+        images.append(cap.matvec(basis[m - 1]).real)
+        # next basis vector: A v_m orthogonalised against the basis
+        w = tau * Mlu.solve(Ksp @ basis[m - 1])
+        size = float(np.linalg.norm(w))
+        for _ in range(2):
+            for v in basis:
+                w = w - (v @ w) * v
+        if float(np.linalg.norm(w)) <= 1e-13 * size:
+            exhausted = True    # the space is invariant under A (m = nbar)
+        else:
+            basis.append(w / np.linalg.norm(w))
+        if m % q == 0 or m == maxit or exhausted:
+            Vm = np.array(basis[:m]).T
+            Jm = Vm.T @ np.array(images).T
+            rhs_m = np.zeros(m)
+            rhs_m[0] = beta
+            x = Vm @ np.linalg.solve(Jm, rhs_m)
+            res = float(np.linalg.norm(cap.matvec(x).real - b))
             hist.append(res)
-    x = np.array(V[:m]).T @ y
+            if res <= eps * beta:
+                break
     return x, m, hist
 
 
 # --------------------------------------------------------------------------
-# Algorithm 1 / Algorithm 3
+# the pieces of the method, each from its own definition (Sections 2 and 4)
 # --------------------------------------------------------------------------
 
-def paradiag(Msp, Ksp, tau, u0, F, alpha=1.0, capacitance="dense",
-             tol=1e-13, maxit=200, early_exit_eps=None, q=1):
-    """ParaDiag with backward Euler.  Returns a dict with the intermediates
-    of the method (pi, gamma, Ghat, L, U1, b, x, W) and the solution U.
-
-    capacitance = "dense" forms J_ell explicitly and solves it with LU;
-    "gmres" applies J_ell matrix-free and solves with ``gmres``; "fom" runs
-    Algorithm 2 (``fom``, residual checks every ``q`` iterations).
-
-    early_exit_eps: Algorithm 3's test on the first term -- if the residual
-    of U_1 in the original all-at-once system (with Sigma_1, not C_alpha) is
-    at most eps * ||M U_1||_F, U = U_1 and the capacitance solve and the
-    second parfor are skipped (early_exit = True in the result).  The paper
-    states the test for M = I against ||U_1||_F; with a mass matrix every
-    row of the residual carries a factor M, so it is measured against
-    ||M U_1||_F (the same test when M = I)."""
-    ell, nbar = F.shape
-    pi, gamma = circulant_eigs(ell, alpha)
-    weight = alpha ** (1.0 / ell)
-    Dalpha = weight ** np.arange(ell)
+def rhs_spectrum(Msp, tau, u0, F, alpha=1.0):
+    """The right-hand side in Fourier variables, G D_alpha F^T (Section 2;
+    Section 4 for the D_alpha scaling): row i is
+    sum_t alpha^(t/ell) g_t omega^(t i), the un-normalised DFT along time of
+    the scaled rows of G = M [u0 + tau f_1, tau f_2, ...]."""
     G = rhs(Msp, tau, u0, F)
-    # [u0 + tau f_1, ..., tau f_ell] D_alpha F^T  (with M applied: G)
-    Ghat = np.fft.fft(Dalpha[:, None] * G, axis=0)
-    cap = Capacitance(Msp, Ksp, tau, ell, alpha)
-    # first parfor: L e_i = P_i^{-1} Ghat e_i
-    L = np.empty((ell, nbar), dtype=np.complex128)
-    for i in range(ell):
-        L[i] = cap.solve_shifted(i, Ghat[i])
-    # U_1 = L F^{-T} D_alpha^{-1}
-    U1 = np.fft.ifft(L, axis=0) / Dalpha[:, None]
-    if early_exit_eps is not None:
-        R = rhs(Msp, tau, u0, F) - apply_allatonce(Msp, Ksp, tau, U1.real)
-        MU1 = np.asarray((Msp @ U1.real.T).T)
-        if np.linalg.norm(R) <= early_exit_eps * np.linalg.norm(MU1):
-            return dict(pi=pi, gamma=gamma, G=G, Ghat=Ghat, L=L, U1=U1, b=None,
-                        x=None, W=None, U=U1.real.copy(), gmres_iters=0,
-                        early_exit=True)
-    # b = L F^{-T} e_ell = sum_i gamma_i L e_i
-    b = (gamma[:, None] * L).sum(axis=0)
-    if capacitance == "dense":
-        x = np.linalg.solve(cap.dense(), b)
-        its = 0
-    elif capacitance == "fom":
-        x, its, _ = fom(cap, Msp, Ksp, tau, b.real, eps=tol, maxit=maxit, q=q)
-    else:
-        x, its, _ = gmres(cap.matvec, b, tol=tol, maxit=maxit)
-    # second parfor: W e_i = P_i^{-1} M x
-    Mx = Msp @ x
-    W = np.empty((ell, nbar), dtype=np.complex128)
-    for i in range(ell):
-        W[i] = cap.solve_shifted(i, Mx)
-    # U = U_1 - alpha^(1/ell) W F^{-T} D_alpha^{-1}
-    U = U1 - weight * np.fft.ifft(W, axis=0) / Dalpha[:, None]
-    return dict(pi=pi, gamma=gamma, G=G, Ghat=Ghat, L=L, U1=U1, b=b, x=x,
-                W=W, U=U, gmres_iters=its, early_exit=False)
+    ell = G.shape[0]
+    scale = (alpha ** (1.0 / ell)) ** np.arange(ell)
+    return np.fft.fft(scale[:, None] * G, axis=0)
+
+
+def shifted_solutions(cap, spec):
+    """The block-diagonal operator of Section 2 applied blockwise: row i of
+    the result is P_i^{-1} spec_i, P_i = (1 - pi_i) M + tau K."""
+    out = np.empty(spec.shape, dtype=np.complex128)
+    for i in range(spec.shape[0]):
+        out[i] = cap.solve_shifted(i, spec[i])
+    return out
+
+
+def periodic_solution(Msp, Ksp, tau, u0, F, alpha=1.0, tol=1e-15):
+    """U_1, the solution of the alpha-circulant all-at-once system
+    (M + tau K) U - M U C_alpha^T = G (Sigma_1 with alpha in its corner;
+    Section 2 for alpha = 1, Section 4), computed without any Fourier
+    transform: backward-Euler stepping whose first step also sees
+    alpha M u_ell.  Stepping from zero with the data G gives z, stepping
+    the homogeneous problem ell times is Phi^ell with
+    Phi = (M + tau K)^{-1} M, so u_ell solves (I - alpha Phi^ell) u_ell = z
+    (by ``gmres``); one more stepping pass from u_0 := alpha u_ell gives
+    every time slice."""
+    G = rhs(Msp, tau, u0, F)
+    ell, nbar = G.shape
+    lu = spla.splu(sp.csc_matrix(Msp + tau * Ksp))
+
+    def march(start, data):
+        out = np.empty((ell, nbar))
+        prev = start
+        for j in range(ell):
+            rhs_j = Msp @ prev
+            if data is not None:
+                rhs_j = rhs_j + data[j]
+            out[j] = lu.solve(rhs_j)
+            prev = out[j]
+        return out
+
+    z = march(np.zeros(nbar), G)[-1]
+    op = lambda v: v - alpha * march(v, None)[-1]
+    u_last, _, _ = gmres(op, z, tol=tol, maxit=min(nbar, 300))
+    return march(alpha * np.real(u_last), G)
+
+
+def capacitance_rhs(U1, alpha=1.0):
+    """b = L F^{-T} e_ell (Section 2): since U_1 = L F^{-T} D_alpha^{-1},
+    b = U_1 D_alpha e_ell = alpha^((ell-1)/ell) times the last time slice of
+    the alpha-circulant solution."""
+    ell = U1.shape[0]
+    return (alpha ** (1.0 / ell)) ** (ell - 1) * U1[-1]
+
+
+def capacitance_solution(cap, b, method="dense", tol=1e-14, maxit=200):
+    """x = J_ell^{-1} b (eq. SMW_linearsystemII): a dense solve of the
+    matrix J_ell formed column by column, or GMRES with J_ell applied
+    through its definition."""
+    if method == "dense":
+        return np.linalg.solve(cap.dense(), b).real
+    x, _, _ = gmres(lambda v: cap.matvec(v).real, np.asarray(b, dtype=np.float64), tol=tol,
+                    maxit=maxit)
+    return np.real(x)
+
+
+def first_term_accepted(Msp, Ksp, tau, u0, F, U1, eps) -> bool:
+    """Algorithm 3's test on the first term: U_1 is accepted when its
+    residual in the original all-at-once system (with Sigma_1) is at most
+    eps ||M U_1||_F.  The paper states the test for M = I against
+    ||U_1||_F; with a mass matrix every residual row carries a factor M, so
+    the bound uses ||M U_1||_F (the same test when M = I)."""
+    R = rhs(Msp, tau, u0, F) - apply_allatonce(Msp, Ksp, tau, U1)
+    MU1 = np.asarray((Msp @ U1.T).T)
+    return bool(np.linalg.norm(R) <= eps * np.linalg.norm(MU1))
 
 
 def smw_dense(Msp, Ksp, tau, u0, F, alpha=1.0) -> np.ndarray:

@@ -37,6 +37,17 @@ def _solve(lib, p, tol=1e-10, **kw):
         lib.paradiag_plan_destroy(plan)
 
 
+def _oracle_projection_steps(p, alpha, eps, maxit=32):
+    """Krylov dimension at which the oracle's Galerkin projection (Section 3,
+    imposed directly with J applied to the basis) first meets eps ||b||."""
+    Msp, Ksp = problem_matrices(p)
+    cap = paradiag.Capacitance(Msp, Ksp, p.tau, p.ell, alpha)
+    b = paradiag.capacitance_rhs(
+        paradiag.periodic_solution(Msp, Ksp, p.tau, p.u0, p.F, alpha), alpha)
+    _, m, _ = paradiag.galerkin_projection(cap, Msp, Ksp, p.tau, b, eps=eps, maxit=maxit)
+    return m
+
+
 # cases where Algorithm 2 converges within its 32 steps (it projects onto a
 # polynomial space of K, so stiff problems need many steps: Section 3)
 @pytest.mark.parametrize("kind,n,ell,T_,alpha", [
@@ -49,13 +60,11 @@ def test_fom_matches_oracle(lib, kind, n, ell, T_, alpha):
     p = make_problem(kind, n, ell, n + ell, T_=T_)
     tol = 1e-10
     U, info = _solve(lib, p, tol=tol, alpha=alpha)
-    Msp, Ksp = problem_matrices(p)
-    ref = paradiag.paradiag(Msp, Ksp, p.tau, p.u0, p.F, alpha=alpha, capacitance="fom",
-                            tol=tol * 1e-2, maxit=32)
-    assert ref["gmres_iters"] < 32
-    assert abs(info.gmres_iters - ref["gmres_iters"]) <= 1, (info.as_dict(), ref["gmres_iters"])
+    m_ref = _oracle_projection_steps(p, alpha, tol * 1e-2)
+    assert m_ref < 32
+    assert abs(info.gmres_iters - m_ref) <= 1, (info.as_dict(), m_ref)
     assert info.pint_loops == info.gmres_iters + 2
-    err = allatonce.rel_err(U, ref["U"].real)
+    err = allatonce.rel_err(U, modal.modal_solution(p))
     assert err < 1e-10, err
 
 
@@ -144,18 +153,14 @@ def test_fom_2d_matches_oracle(lib, n, ell, T_):
         got = U.cpu().numpy()
     finally:
         lib.paradiag_plan_destroy(plan)
-    Msp, Ksp = problem_matrices(p)
-    ref = paradiag.paradiag(Msp, Ksp, p.tau, p.u0, p.F, capacitance="fom", tol=tol * 1e-2,
-                            maxit=32)
+    m_ref = _oracle_projection_steps(p, 1.0, tol * 1e-2)
     # where the residual falls slowly near the threshold (the 25-step case),
-    # the GPU's two classical Gram-Schmidt passes and the oracle's single
-    # modified pass cross it a few steps apart
-    slack = 1 if ref["gmres_iters"] <= 10 else 3
-    assert abs(info.gmres_iters - ref["gmres_iters"]) <= slack, (info.as_dict(),
-                                                                 ref["gmres_iters"])
+    # rounding in the two sides' Gram-Schmidt passes moves the crossing by a
+    # few steps
+    slack = 1 if m_ref <= 10 else 3
+    assert abs(info.gmres_iters - m_ref) <= slack, (info.as_dict(), m_ref)
     assert info.gmres_rel_residual <= tol * 1e-2
     assert info.pint_loops == info.gmres_iters + 2
-    assert allatonce.rel_err(got, ref["U"].real) < 1e-10
     assert allatonce.rel_err(got, modal.modal_solution(p)) < 1e-10
     assert 0 <= info.rel_residual < 1e-10
 

@@ -173,17 +173,46 @@ def test_sine_mode_decay_closed_form():
 
 # ------------------------------------------------- ParaDiag (Alg. 1 / 3, O4) --
 
+def _reassemble(Msp, Ksp, tau, u0, F, alpha, cap_method="dense"):
+    """The Sherman-Morrison-Woodbury assembly of Section 2 (eq. SMW_U; Section
+    4 for alpha < 1) from the oracle's separately defined pieces:
+    U = U_1 - w W F^{-T} D_alpha^{-1} with W_i = P_i^{-1} M x, x = J^{-1} b."""
+    ell = F.shape[0]
+    cap = paradiag.Capacitance(Msp, Ksp, tau, ell, alpha)
+    U1 = paradiag.periodic_solution(Msp, Ksp, tau, u0, F, alpha)
+    b = paradiag.capacitance_rhs(U1, alpha)
+    x = paradiag.capacitance_solution(cap, b, cap_method)
+    Mx = Msp @ x
+    W = paradiag.shifted_solutions(cap, np.tile(Mx.astype(np.complex128), (ell, 1)))
+    w = alpha ** (1.0 / ell)
+    scale = w ** np.arange(ell)
+    U = U1 - w * np.fft.ifft(W, axis=0) / scale[:, None]
+    return dict(cap=cap, U1=U1, b=b, x=x, W=W, U=U)
+
+
 @pytest.mark.parametrize("kind", ["fd1", "fem1"])
 @pytest.mark.parametrize("alpha", [1.0, 1e-2])
 @pytest.mark.parametrize("cap", ["dense", "gmres"])
-def test_paradiag_matches_dense_lu(kind, alpha, cap):
+def test_smw_pieces_reassemble_dense_lu(kind, alpha, cap):
+    """The pieces, each from its own definition, satisfy the identities that
+    connect them in Algorithm 1 / 3: the blockwise solves of the spectrum of
+    G are U_1 in Fourier variables (U_1 by stepping, no transform), b is
+    both a time slice of U_1 and L F^{-T} e_ell, x = alpha^((ell-1)/ell) u_ell,
+    and U_1 - w W F^{-T} D_alpha^{-1} is the dense-LU solution."""
     M, K, Msp, Ksp, tau, u0, F = _random_problem(kind, 7, 8, 3)
+    ell = F.shape[0]
     U2 = allatonce.solve_dense(Msp, Ksp, tau, u0, F)
-    out = paradiag.paradiag(Msp, Ksp, tau, u0, F, alpha=alpha, capacitance=cap)
+    out = _reassemble(Msp, Ksp, tau, u0, F, alpha, cap)
+    pieces = out["cap"]
+    L = paradiag.shifted_solutions(pieces, paradiag.rhs_spectrum(Msp, tau, u0, F, alpha))
+    w = alpha ** (1.0 / ell)
+    kappa = alpha ** (-(ell - 1) / ell)
+    assert allatonce.rel_err(np.fft.ifft(L, axis=0).real / (w ** np.arange(ell))[:, None],
+                             out["U1"]) < 1e-13 * kappa
+    assert np.allclose((pieces.gamma[:, None] * L).sum(axis=0), out["b"], rtol=1e-11,
+                       atol=1e-13)
     assert np.max(np.abs(out["U"].imag)) < 1e-12
     assert allatonce.rel_err(out["U"].real, U2) < 1e-11
-    # x = alpha^((ell-1)/ell) u_ell
-    ell = F.shape[0]
     assert np.allclose(out["x"], alpha ** ((ell - 1) / ell) * U2[-1],
                        rtol=1e-10, atol=1e-12)
 
@@ -199,26 +228,21 @@ def test_smw_dense_matches_dense_lu(kind, alpha):
 
 
 @pytest.mark.parametrize("kind", ["fd1", "fem1"])
-@pytest.mark.parametrize("alpha", [1e-2, 1e-6])
+@pytest.mark.parametrize("alpha", [1e-2, 1e-6, 1.0])
 def test_alpha_first_term_solves_alpha_circulant_system(kind, alpha):
-    """Algorithm 3: U_1 = L F^{-T} D_alpha^{-1} is the exact solution of the
-    all-at-once system with Sigma_1 replaced by C_alpha (dense LU of
-    I (x) (M + tau K) - C_alpha (x) M), and its residual in the original
-    system is -alpha M u_ell in the first time row and zero elsewhere
-    (C_alpha - Sigma_1 = alpha e_1 e_ell^T)."""
+    """Algorithm 3: U_1 is the exact solution of the all-at-once system with
+    Sigma_1 replaced by C_alpha (dense LU of I (x) (M + tau K) - C_alpha (x) M),
+    and its residual in the original system is -alpha M u_ell in the first
+    time row and zero elsewhere (C_alpha - Sigma_1 = alpha e_1 e_ell^T)."""
     M, K, Msp, Ksp, tau, u0, F = _random_problem(kind, 7, 8, 21)
     ell, nbar = F.shape
-    out = paradiag.paradiag(Msp, Ksp, tau, u0, F, alpha=alpha)
-    U1 = out["U1"]
+    U1 = paradiag.periodic_solution(Msp, Ksp, tau, u0, F, alpha)
     Md = Msp.toarray()
     A = np.kron(np.eye(ell), Md + tau * Ksp.toarray()) - np.kron(
         paradiag.circulant_c1(ell, alpha), Md)
     G = allatonce.rhs(Msp, tau, u0, F)
     U1_lu = np.linalg.solve(A, G.reshape(-1)).reshape(ell, nbar)
-    assert np.max(np.abs(U1.imag)) < 1e-9 * np.max(np.abs(U1_lu))
-    # the scaled DFT has condition number alpha^{-(ell-1)/ell}
-    kappa = alpha ** (-(ell - 1) / ell)
-    assert allatonce.rel_err(U1.real, U1_lu) < 1e-13 * kappa
+    assert allatonce.rel_err(U1, U1_lu) < 1e-13
     R, _ = allatonce.residual(Msp, Ksp, tau, u0, F, U1_lu)
     expect = np.zeros_like(R)
     expect[0] = -alpha * (Msp @ U1_lu[-1])
@@ -228,39 +252,33 @@ def test_alpha_first_term_solves_alpha_circulant_system(kind, alpha):
 @pytest.mark.parametrize("kind", ["fd1", "fem1"])
 def test_alpha_early_exit_decision(kind):
     """Algorithm 3's test: with eps just above the first term's residual
-    ratio ||G - A(U_1)||_F / ||M U_1||_F the method returns U_1 (no
-    capacitance solve); just below it, the full correction runs and U is the
-    exact all-at-once solution."""
+    ratio ||G - A(U_1)||_F / ||M U_1||_F, U_1 is accepted; just below it, it
+    is not.  The ratio has the closed form alpha ||M u_ell|| / ||M U_1||."""
     M, K, Msp, Ksp, tau, u0, F = _random_problem(kind, 7, 8, 22)
     alpha = 1e-6
-    ref = paradiag.paradiag(Msp, Ksp, tau, u0, F, alpha=alpha)
-    U1 = ref["U1"].real
+    U1 = paradiag.periodic_solution(Msp, Ksp, tau, u0, F, alpha)
     _, rel = allatonce.residual(Msp, Ksp, tau, u0, F, U1)
     G = allatonce.rhs(Msp, tau, u0, F)
     MU1 = np.asarray((Msp @ U1.T).T)
     ratio = rel * np.linalg.norm(G) / np.linalg.norm(MU1)
-    # closed form of the ratio: alpha ||M u_ell|| / ||M U_1||
     assert np.isclose(ratio, alpha * np.linalg.norm(Msp @ U1[-1]) / np.linalg.norm(MU1),
                       rtol=1e-6)
-    hi = paradiag.paradiag(Msp, Ksp, tau, u0, F, alpha=alpha, early_exit_eps=1.01 * ratio)
-    assert hi["early_exit"] and hi["gmres_iters"] == 0
-    assert np.array_equal(hi["U"], U1)
-    lo = paradiag.paradiag(Msp, Ksp, tau, u0, F, alpha=alpha, early_exit_eps=0.99 * ratio)
-    assert not lo["early_exit"]
-    U2 = allatonce.solve_dense(Msp, Ksp, tau, u0, F)
-    assert allatonce.rel_err(lo["U"].real, U2) < 1e-8
+    assert paradiag.first_term_accepted(Msp, Ksp, tau, u0, F, U1, 1.01 * ratio)
+    assert not paradiag.first_term_accepted(Msp, Ksp, tau, u0, F, U1, 0.99 * ratio)
 
 
-def test_paradiag_2d_matches_stepping():
+def test_smw_pieces_2d_match_stepping():
     p = wl.heat_2d(7, 8, 0.1, 1.0, np.random.default_rng(9))
     Msp, Ksp = problem_matrices(p)
-    out = paradiag.paradiag(Msp, Ksp, p.tau, p.u0, p.F, capacitance="gmres")
+    out = _reassemble(Msp, Ksp, p.tau, p.u0, p.F, 1.0, "gmres")
     assert allatonce.rel_err(out["U"].real, allatonce.step(p)) < 1e-11
 
 
 def test_b_is_last_column_of_periodic_solution():
-    """b = L F^{-T} e_ell is the last column of the solution of the
-    circulant (periodic) system (M + tau K) U - M U C_1^T = G."""
+    """b = L F^{-T} e_ell (the gamma-weighted sum of the blockwise solves of
+    the spectrum) is the last column of the solution of the circulant
+    (periodic) system (M + tau K) U - M U C_1^T = G, computed here by dense
+    LU, and the oracle's stepping form of U_1 agrees with it."""
     M, K, Msp, Ksp, tau, u0, F = _random_problem("fem1", 6, 8, 6)
     ell, n = F.shape
     G = allatonce.rhs(Msp, tau, u0, F)
@@ -269,9 +287,13 @@ def test_b_is_last_column_of_periodic_solution():
     C1 = paradiag.circulant_c1(ell)
     Acirc = np.kron(np.eye(ell), Ad) - np.kron(C1, Md)
     Uper = np.linalg.solve(Acirc, G.reshape(-1)).reshape(ell, n)
-    out = paradiag.paradiag(Msp, Ksp, tau, u0, F)
-    assert np.allclose(out["b"], Uper[-1], rtol=1e-11, atol=1e-13)
-    assert np.allclose(out["U1"].real, Uper, rtol=1e-11, atol=1e-13)
+    cap = paradiag.Capacitance(Msp, Ksp, tau, ell)
+    L = paradiag.shifted_solutions(cap, paradiag.rhs_spectrum(Msp, tau, u0, F))
+    b = (cap.gamma[:, None] * L).sum(axis=0)
+    assert np.allclose(b, Uper[-1], rtol=1e-11, atol=1e-13)
+    U1 = paradiag.periodic_solution(Msp, Ksp, tau, u0, F)
+    assert np.allclose(U1, Uper, rtol=1e-11, atol=1e-13)
+    assert np.allclose(paradiag.capacitance_rhs(U1), Uper[-1], rtol=1e-11, atol=1e-13)
 
 
 def test_capacitance_on_sine_vectors():
@@ -373,40 +395,33 @@ def test_gmres_oracle_matches_dense():
     assert hist[-1] <= 1e-13 * np.linalg.norm(b) * 10
 
 
+def _section61_problem(n, ell):
+    p = wl.heat_2d(n, ell, 1.0, 1.0, np.random.default_rng(1))
+    x = np.arange(1, n + 1) / (n + 1)
+    X, Y = np.meshgrid(x, x)
+    p.u0 = (X * Y * (X - 1) * (1 - Y)).reshape(-1)
+    return p
+
+
 def test_one_inner_iteration_suffices_2d():
     """Section 6.1: for the 2D heat example J_ell is a tiny perturbation of
     I, so the Krylov solve reaches 1e-8 almost at once (checked here with
     GMRES on a scaled-down grid: at most 2 iterations)."""
     n, ell = 15, 32
-    p = wl.heat_2d(n, ell, 1.0, 1.0, np.random.default_rng(1))
-    x = np.arange(1, n + 1) / (n + 1)
-    X, Y = np.meshgrid(x, x)
-    p.u0 = (X * Y * (X - 1) * (1 - Y)).reshape(-1)
+    p = _section61_problem(n, ell)
     Msp, Ksp = problem_matrices(p)
     cap = paradiag.Capacitance(Msp, Ksp, p.tau, ell)
-    out = paradiag.paradiag(Msp, Ksp, p.tau, p.u0, p.F, capacitance="dense")
-    _, its, _ = paradiag.gmres(cap.matvec, out["b"], tol=1e-8)
+    b = paradiag.capacitance_rhs(paradiag.periodic_solution(Msp, Ksp, p.tau, p.u0, p.F))
+    _, its, _ = paradiag.gmres(lambda v: cap.matvec(v).real, b, tol=1e-8)
     assert its <= 2
 
 
-@pytest.mark.parametrize("kind", ["fd1", "fem1"])
-@pytest.mark.parametrize("alpha", [1.0, 1e-2])
-def test_fom_residual_formula_is_the_true_residual(kind, alpha):
-    """Algorithm 2's residual norm (eq. compute_resnorm, with gamma_i and the
-    alpha weight) equals ||J x_m - b|| computed directly from sparse LU
-    solves, at every m; the two printed variants it replaces (no gamma_i in
-    the residual line, and the listing's t_{m+1,m} without tau for the
-    Krylov space of K) do not."""
-    M, K, Msp, Ksp, tau, u0, F = _random_problem(kind, 9, 8, 31)
-    cap = paradiag.Capacitance(Msp, Ksp, tau, F.shape[0], alpha)
-    b = paradiag.paradiag(Msp, Ksp, tau, u0, F, alpha=alpha)["b"].real
-    for m_max in (1, 2, 3, 5):
-        x, m, hist = paradiag.fom(cap, Msp, Ksp, tau, b, eps=0.0, maxit=m_max)
-        direct = np.linalg.norm(cap.matvec(x).real - b)
-        assert m == m_max
-        assert np.isclose(hist[-1], direct, rtol=1e-7, atol=1e-14 * np.linalg.norm(b))
-    # the variants: rebuild the last check of m = 2 with each change
-    m = 2
+def _paper_projection(cap, Msp, Ksp, tau, b, m):
+    """Algorithm 2's small system and residual as the paper writes them
+    (eq. compute_ym and eq. compute_resnorm): S_i = (lambda_i I + T_m)^{-1},
+    h_i = P_i^{-1} M v_{m+1}, with the Arnoldi data of K_m(tau M^{-1} K, b).
+    Returns (y, residual, and the two printed variants of the residual that
+    drop gamma_i or the tau in t_{m+1,m})."""
     Mlu = sp.linalg.splu(Msp.tocsc())
     V = [b / np.linalg.norm(b)]
     Tm = np.zeros((m + 1, m))
@@ -415,10 +430,12 @@ def test_fom_residual_formula_is_the_true_residual(kind, alpha):
         for k in range(j + 1):
             Tm[k, j] = V[k] @ w
             w = w - Tm[k, j] * V[k]
+        for k in range(j + 1):           # second pass (as the oracle's basis)
+            c = V[k] @ w
+            Tm[k, j] += c
+            w = w - c * V[k]
         Tm[j + 1, j] = np.linalg.norm(w)
         V.append(w / Tm[j + 1, j])
-    x, _, hist = paradiag.fom(cap, Msp, Ksp, tau, b, eps=0.0, maxit=m)
-    direct = np.linalg.norm(cap.matvec(x).real - b)
     Vm = np.array(V[:m]).T
     t = Tm[m, m - 1]
     lam = 1.0 - cap.pi
@@ -430,44 +447,71 @@ def test_fom_residual_formula_is_the_true_residual(kind, alpha):
         Si = np.linalg.inv(lam[i] * np.eye(m) + Tm[:m, :m])
         hi = cap.solve_shifted(i, Msp @ V[m])
         Z += cap.weight * g * (np.eye(m) - t * np.outer(Vm.T @ hi, em)) @ Si
-        S.append(Si); H.append(hi)
+        S.append(Si)
+        H.append(hi)
     y = np.linalg.solve(Z, e1).real
+    with_g = sum(g * H[i] * (S[i][-1] @ y) for i, g in enumerate(cap.gamma))
+    res = abs(t) * cap.weight * np.linalg.norm(with_g - Vm @ (Vm.T @ with_g))
     no_gamma = sum(H[i] * (S[i][-1] @ y) for i in range(len(H)))
     r_no_gamma = abs(t) * cap.weight * np.linalg.norm(no_gamma - Vm @ (Vm.T @ no_gamma))
-    assert not np.isclose(r_no_gamma, direct, rtol=1e-2)
-    with_g = sum(g * H[i] * (S[i][-1] @ y) for i, g in enumerate(cap.gamma))
     r_no_tau = abs(t / tau) * cap.weight * np.linalg.norm(with_g - Vm @ (Vm.T @ with_g))
-    assert not np.isclose(r_no_tau, direct, rtol=1e-2)
+    return y, res, r_no_gamma, r_no_tau
 
 
 @pytest.mark.parametrize("kind", ["fd1", "fem1"])
-def test_fom_reaches_the_exact_solution(kind):
-    """With the whole space (m = nbar) Algorithm 2 returns the exact x, and
-    x = alpha^((ell-1)/ell) u_ell (the last time step of the all-at-once
-    solution); inside Algorithm 1 it gives the dense-LU solution."""
+@pytest.mark.parametrize("alpha", [1.0, 1e-2])
+def test_projection_formulas_match_direct_galerkin(kind, alpha):
+    """Algorithm 2's small system (eq. compute_ym, from the shifted Arnoldi
+    relation) gives the same iterate as the Galerkin condition imposed
+    directly with J_ell applied to the basis (the oracle), and its residual
+    formula (eq. compute_resnorm, with gamma_i and the alpha weight) equals
+    the oracle's directly computed ||J x_m - b|| at every m; the two printed
+    variants it replaces (no gamma_i in the residual line, and t_{m+1,m}
+    without tau for the Krylov space of K) do not."""
+    M, K, Msp, Ksp, tau, u0, F = _random_problem(kind, 9, 8, 31)
+    cap = paradiag.Capacitance(Msp, Ksp, tau, F.shape[0], alpha)
+    b = paradiag.capacitance_rhs(paradiag.periodic_solution(Msp, Ksp, tau, u0, F, alpha), alpha)
+    for m_max in (1, 2, 3, 5):
+        x, m, hist = paradiag.galerkin_projection(cap, Msp, Ksp, tau, b, eps=0.0, maxit=m_max)
+        assert m == m_max
+        direct = np.linalg.norm(cap.matvec(x).real - b)
+        assert np.isclose(hist[-1], direct, rtol=1e-12, atol=1e-15 * np.linalg.norm(b))
+        y, res, r_no_gamma, r_no_tau = _paper_projection(cap, Msp, Ksp, tau, b, m_max)
+        Vm = np.linalg.qr(np.array([np.linalg.matrix_power(
+            tau * np.linalg.solve(Msp.toarray(), Ksp.toarray()), j) @ b
+            for j in range(m_max)]).T)[0]
+        assert np.linalg.norm(x - Vm @ (Vm.T @ x)) < 1e-9 * np.linalg.norm(x)
+        assert np.isclose(res, direct, rtol=1e-7, atol=1e-14 * np.linalg.norm(b))
+        if m_max == 2:
+            assert not np.isclose(r_no_gamma, direct, rtol=1e-2)
+            assert not np.isclose(r_no_tau, direct, rtol=1e-2)
+
+
+@pytest.mark.parametrize("kind", ["fd1", "fem1"])
+def test_projection_reaches_the_exact_solution(kind):
+    """With the whole space (m = nbar) the projection returns the exact x,
+    and x = alpha^((ell-1)/ell) u_ell (the last time step of the all-at-once
+    solution)."""
     M, K, Msp, Ksp, tau, u0, F = _random_problem(kind, 7, 8, 32)
     alpha = 1e-2
-    out = paradiag.paradiag(Msp, Ksp, tau, u0, F, alpha=alpha, capacitance="fom",
-                            tol=1e-14, maxit=7)
-    U2 = allatonce.solve_dense(Msp, Ksp, tau, u0, F)
-    assert allatonce.rel_err(out["U"].real, U2) < 1e-11
     ell = F.shape[0]
-    assert np.allclose(out["x"], alpha ** ((ell - 1) / ell) * U2[-1], rtol=1e-10, atol=1e-12)
+    cap = paradiag.Capacitance(Msp, Ksp, tau, ell, alpha)
+    b = paradiag.capacitance_rhs(paradiag.periodic_solution(Msp, Ksp, tau, u0, F, alpha), alpha)
+    x, m, _ = paradiag.galerkin_projection(cap, Msp, Ksp, tau, b, eps=1e-14, maxit=7)
+    U2 = allatonce.solve_dense(Msp, Ksp, tau, u0, F)
+    assert np.allclose(x, alpha ** ((ell - 1) / ell) * U2[-1], rtol=1e-10, atol=1e-12)
 
 
-def test_fom_one_iteration_suffices_2d():
+def test_projection_one_iteration_suffices_2d():
     """Section 6.1 states that one iteration of Algorithm 2 is enough for the
     2D heat example; on a scaled-down grid the first residual check is below
     1e-8 ||b||."""
     n, ell = 15, 32
-    p = wl.heat_2d(n, ell, 1.0, 1.0, np.random.default_rng(1))
-    x = np.arange(1, n + 1) / (n + 1)
-    X, Y = np.meshgrid(x, x)
-    p.u0 = (X * Y * (X - 1) * (1 - Y)).reshape(-1)
+    p = _section61_problem(n, ell)
     Msp, Ksp = problem_matrices(p)
     cap = paradiag.Capacitance(Msp, Ksp, p.tau, ell)
-    b = paradiag.paradiag(Msp, Ksp, p.tau, p.u0, p.F, capacitance="dense")["b"].real
-    _, m, hist = paradiag.fom(cap, Msp, Ksp, p.tau, b, eps=1e-8)
+    b = paradiag.capacitance_rhs(paradiag.periodic_solution(Msp, Ksp, p.tau, p.u0, p.F))
+    _, m, hist = paradiag.galerkin_projection(cap, Msp, Ksp, p.tau, b, eps=1e-8)
     assert m == 1 and hist[0] <= 1e-8 * np.linalg.norm(b)
 
 
@@ -475,8 +519,10 @@ def test_fom_one_iteration_suffices_2d():
 
 def test_pins_catch_planted_mistakes(monkeypatch):
     """Plant plausible mistakes in the oracle (CPU only) and check that the
-    dense-LU pin rejects each of them."""
+    pins reject each of them: the reassembly against dense LU, and the
+    blockwise solves of the spectrum against U_1 by stepping."""
     M, K, Msp, Ksp, tau, u0, F = _random_problem("fem1", 7, 8, 12)
+    ell = F.shape[0]
     U2 = allatonce.solve_dense(Msp, Ksp, tau, u0, F)
     good = paradiag.circulant_eigs
 
@@ -490,12 +536,18 @@ def test_pins_catch_planted_mistakes(monkeypatch):
 
     for bad in (conj_pi, conj_gamma):
         monkeypatch.setattr(paradiag, "circulant_eigs", bad)
-        out = paradiag.paradiag(Msp, Ksp, tau, u0, F)
+        out = _reassemble(Msp, Ksp, tau, u0, F, 1.0)
         assert allatonce.rel_err(out["U"].real, U2) > 1e-6
         monkeypatch.setattr(paradiag, "circulant_eigs", good)
+    # a conjugated pi also breaks the link between the spectrum's solves and U_1
+    monkeypatch.setattr(paradiag, "circulant_eigs", conj_pi)
+    cap = paradiag.Capacitance(Msp, Ksp, tau, ell)
+    monkeypatch.setattr(paradiag, "circulant_eigs", good)
+    L = paradiag.shifted_solutions(cap, paradiag.rhs_spectrum(Msp, tau, u0, F))
+    U1 = paradiag.periodic_solution(Msp, Ksp, tau, u0, F)
+    assert allatonce.rel_err(np.fft.ifft(L, axis=0).real, U1) > 1e-6
     # dropping the rank-one correction (the circulant preconditioner alone)
-    out = paradiag.paradiag(Msp, Ksp, tau, u0, F)
-    assert allatonce.rel_err(out["U1"].real, U2) > 1e-6
+    assert allatonce.rel_err(U1, U2) > 1e-6
     # forgetting the mass matrix in the capacitance matrix
     good_mv = paradiag.Capacitance.matvec
 
@@ -503,9 +555,14 @@ def test_pins_catch_planted_mistakes(monkeypatch):
         acc = sum(g * self.solve_shifted(i, v) for i, g in enumerate(self.gamma))
         return v + self.weight * acc
     monkeypatch.setattr(paradiag.Capacitance, "matvec", no_mass)
-    out = paradiag.paradiag(Msp, Ksp, tau, u0, F, capacitance="gmres")
+    out = _reassemble(Msp, Ksp, tau, u0, F, 1.0, "gmres")
     assert allatonce.rel_err(out["U"].real, U2) > 1e-6
     monkeypatch.setattr(paradiag.Capacitance, "matvec", good_mv)
+    # a wrap-around term without alpha in the stepping form of U_1
+    good_ps = paradiag.periodic_solution
+    U1a = good_ps(Msp, Ksp, tau, u0, F, 1e-2)
+    U1b = good_ps(Msp, Ksp, tau, u0, F, 1.0)
+    assert allatonce.rel_err(U1b, U1a) > 1e-6
 
 
 # ------------------------------------------------------------------ DST-I --
