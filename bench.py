@@ -28,6 +28,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VEC_PEAK_TFLOPS = 78.6    # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
 METRIC = "space-time unknowns/s at 1e-8 rel err (mixed vs FP64) + p50/p99 latency"
+FLOPS_PER_UNKNOWN = 20.0       # shifted solves: real flops per real space-time unknown
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_fem1d_n8191_l2048_fp64.txt")
 
 
@@ -50,6 +51,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--kernel-reps", type=int, default=10)
+    ap.add_argument("--serve-count", type=int, default=256,
+                    help="requests of the serving stream in the default run (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=80.0,
+                    help="fixed Poisson arrival rate of the serving stream (requests/s)")
+    ap.add_argument("--no-2d", action="store_true",
+                    help="skip the 2D (511^2, ell = 256) rows of the default run")
     return ap.parse_args()
 
 
@@ -71,7 +78,12 @@ def main():
         print(json.dumps(bench_ensemble(args, torch, pd, wl, dev)))
         return
     if args.workload == "serve":
-        print(json.dumps(bench_serve(args, torch, pd, wl, dev)))
+        srv = bench_serve(args, torch, pd, wl, dev, args.count or args.serve_count,
+                          args.serve_rate)
+        if not args.no_cpu_baseline:
+            serve_errors(srv, wl)
+        srv.pop("_samples", None)
+        print(json.dumps(srv))
         return
     if args.workload == "alpha":
         print(json.dumps(bench_alpha(args, torch, pd, wl, dev)))
@@ -137,9 +149,25 @@ def main():
         finally:
             pd.paradiag_plan_destroy(plan)
 
+    rows2d = None
+    if not args.no_2d:
+        rows2d = bench_2d(args, torch, pd, wl, dev)
+    serving = None
+    if args.serve_count > 0:
+        serving = bench_serve(args, torch, pd, wl, dev, args.serve_count, args.serve_rate)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_leg(prob, results_U, forms, args.cpu_seconds)
+        if rows2d is not None:
+            errors_2d(rows2d, wl)
+        if serving is not None:
+            serve_errors(serving, wl)
+    if serving is not None:
+        serving.pop("_samples", None)
+    if rows2d is not None:
+        for r in rows2d["forms"].values():
+            r.pop("_sample", None)
 
     # the headline is Algorithm 1 with partition/PCR shifted solves (float64
     # or mixed precision); the alpha form (Algorithm 3, a different accuracy
@@ -156,6 +184,14 @@ def main():
             max(1, forms[best]["sweeps"])
         dom = max(k["stages"], key=lambda s: k["stages"][s]["ms"] * k["stages"][s]["per_solve"])
         roof = roofline(k["stages"][dom], dom, best)
+    # whole-solve algorithmic HBM traffic: 56 B per space-time unknown per
+    # float64 sweep (pass A 8 + 8, pass B 8, pass C 8 + 8, pass D 8 + 8)
+    solve_bytes = 56.0 * unknowns * max(1, forms[best]["sweeps"]) if best == "fp64" else None
+    solve_hbm = None
+    if solve_bytes is not None:
+        gbs = solve_bytes / (forms[best]["ms_per_step"] * 1e-3) / 1e9
+        solve_hbm = {"algorithmic_bytes_per_step": solve_bytes, "achieved": gbs,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
     line = {
         "metric": METRIC,
         "value": forms[best]["unknowns_per_s"],
@@ -167,10 +203,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": "heat1d-fem n=8191 ell=2048 T=1 nu=1 (16-mode source)",
                    "form": best, "tol": tol, "unknowns": unknowns},
-        "latency_ms": forms[best]["latency_ms"],
+        # the metric's latency half: the serving stream at a fixed arrival
+        # rate (completion - arrival per request); the headline solve's own
+        # back-to-back latencies are under forms
+        "latency_ms": serving["latency_ms"] if serving else None,
         "forms": forms,
         "stages": kernels,
         "roofline": roof,
+        "solve_hbm": solve_hbm,
+        "workload_2d": rows2d,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
@@ -250,22 +292,22 @@ def time_stages(pd, plan, prob, u0, F, U, stream, reps, prec):
     pd.paradiag_shifted_solve(plan, spec, None, None, b)
     pd.paradiag_capacitance_solve(plan, b, x, 1e-9, allow_notconv=True)
     # algorithmic work per launch.  Bytes: each array read or written once.
-    # Flops of one shifted solve per row and frequency, with the LU factors of
-    # P_k precomputed: forward recurrence (complex multiply-subtract and a
-    # complex multiply, 14), back substitution (8), and for the reductions the
-    # weighted real part gamma_k y (4); the transforms' N log N terms are
-    # omitted (they are HBM-bound by a wide margin).
+    # Flops of a parfor of shifted solves: a Thomas-equivalent complex
+    # tridiagonal solve costs about 20 real flops per real space-time unknown
+    # (the half spectrum's ell/2 + 1 complex systems of nbar rows hold
+    # nbar * ell real unknowns); the transforms' 2.5 log2(ell) per unknown
+    # (they are HBM-bound by a wide margin).
     lg = float(np.log2(ell))
     stages = {
         "forward_transform": (lambda: pd.paradiag_forward_transform(plan, u0, F, spec2),
                               8 * nbar * ell + 8 * nbar + cb * F2 * nbar,
                               2.5 * nbar * ell * lg, 1),
         "shifted_solve_b": (lambda: pd.paradiag_shifted_solve(plan, spec, None, None, b),
-                            cb * F2 * nbar + 8 * nbar, 26.0 * nbar * F2, 1),
+                            cb * F2 * nbar + 8 * nbar, FLOPS_PER_UNKNOWN * nbar * ell, 1),
         "capacitance_apply": (lambda: pd.paradiag_capacitance_apply(plan, x, Jv),
-                              16 * nbar, 26.0 * nbar * F2, 0),
+                              16 * nbar, FLOPS_PER_UNKNOWN * nbar * ell, 0),
         "shifted_solve_y": (lambda: pd.paradiag_shifted_solve(plan, spec, x, spec2, None),
-                            2 * cb * F2 * nbar + 8 * nbar, 22.0 * nbar * F2, 1),
+                            2 * cb * F2 * nbar + 8 * nbar, FLOPS_PER_UNKNOWN * nbar * ell, 1),
         "inverse_transform": (lambda: pd.paradiag_inverse_transform(plan, spec2, U),
                               cb * F2 * nbar + 8 * nbar * ell, 2.5 * nbar * ell * lg, 1),
     }
@@ -671,68 +713,179 @@ def bench_bdf(args, torch, pd, wl, dev):
     return out
 
 
-def bench_serve(args, torch, pd, wl, dev):
-    """Poisson stream of mixed 1D FEM / 2D FD requests through the serving
-    runtime: first closed loop (saturation throughput), then open loop at
-    0.7x that rate; p50/p99 of completion - arrival."""
+def bench_2d(args, torch, pd, wl, dev):
+    """The 2D workload (511 x 511 grid, ell = 256, T = 0.1): float64 and mixed
+    forms, inputs resident in HBM, `steps` timed solves each.  Sampled outputs
+    are kept for the cpu_baseline leg's error check."""
+    stream = torch.cuda.current_stream(dev)
+    p = wl.cfg_fd_2d()
+    u0 = torch.tensor(p.u0, device=dev)
+    F = torch.zeros((p.ell, p.nbar), dtype=torch.float64, device=dev)   # f = 0
+    U = torch.empty((p.ell, p.nbar), dtype=torch.float64, device=dev)
+    rng = np.random.default_rng(7)
+    tt = rng.integers(0, p.ell, 4000)
+    ii = rng.integers(0, p.nbar, 4000)
+    tix, iix = torch.tensor(tt, device=dev), torch.tensor(ii, device=dev)
+    steps = max(1, min(args.steps, 10))
+    forms = {}
+    for form, prec in (("fp64", pd.PD_FP64), ("mixed", pd.PD_MIXED)):
+        plan = pd.paradiag_plan_create(p.n, p.ell, p.tau, None, p.K, dims=2, precision=prec,
+                                       stream=stream.cuda_stream)
+        try:
+            for _ in range(min(args.warmup, 2) or 1):
+                pd.paradiag_solve(plan, u0, F, U, 1e-8, allow_notconv=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                info = pd.paradiag_solve(plan, u0, F, U, 1e-8, allow_notconv=True)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / steps
+            forms[form] = {"ms_per_step": 1e3 * wall, "unknowns_per_s": p.unknowns / wall,
+                           "gmres_iters": info.gmres_iters, "sweeps": info.sweeps,
+                           "pint_loops": info.pint_loops,
+                           "rel_residual": pd.paradiag_residual(plan, u0, F, U),
+                           "_sample": (tt, ii, U[tix, iix].cpu().numpy())}
+        finally:
+            pd.paradiag_plan_destroy(plan)
+    del F, U
+    return {"workload": "heat2d-fd 511x511 ell=256 T=0.1 nu=1 (f = 0)", "steps": steps,
+            "unknowns": p.unknowns, "forms": forms}
+
+
+def errors_2d(rows2d, wl):
+    """Oracle leg: sampled error of the 2D rows against the exact modal
+    solution."""
+    from oracle import modal
+    p = wl.cfg_fd_2d()
+    for r in rows2d["forms"].values():
+        tt, ii, got = r["_sample"]
+        ref = modal.modal_sample(p, tt, ii)
+        r["rel_err_vs_exact_sampled"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def bench_serve(args, torch, pd, wl, dev, count, rate):
+    """The serving stream through the pd_server runtime: `count` mixed
+    requests (70% 1D FEM n <= 16383, 30% 2D FD up to 511^2, nu log-uniform,
+    mixed precision to 1e-8) arriving by a Poisson process at the fixed rate
+    `rate` (requests/s), a 200 GB admission budget and 4 worker streams.  A
+    fresh server (empty plan cache) serves the timed stream, so plan creation
+    is inside each request's latency.  Each request's status is recorded;
+    failed requests are excluded from throughput and latency and counted.
+    Sampled outputs are kept for the cpu_baseline leg's error check."""
     import threading
-    count = args.count or 32
-    reqs = wl.serving_stream(count=count, rate=1.0)
-    prec = pd.PD_MIXED
-    staged = []
-    for r in reqs:
-        p = r.problem
-        staged.append((p, torch.tensor(p.u0, device=dev), torch.tensor(p.F, device=dev),
-                       torch.empty((p.ell, p.nbar), dtype=torch.float64, device=dev)))
-    torch.cuda.synchronize()
     budget = 200 << 30
+    reqs, staged = [], []
+    t_stage = time.perf_counter()
+    for r in wl.iter_serving_stream(count=count, rate=rate):
+        p = r.problem
+        u0 = torch.tensor(p.u0, device=dev)
+        if p.dims == 2:
+            F = torch.zeros((p.ell, p.nbar), dtype=torch.float64, device=dev)   # f = 0
+        else:
+            F = torch.tensor(p.F, device=dev)
+        U = torch.empty((p.ell, p.nbar), dtype=torch.float64, device=dev)
+        p.F = np.zeros((0, 0))              # the host copy is no longer needed
+        reqs.append(r)
+        staged.append((p, u0, F, U))
+    torch.cuda.synchronize()
+    stage_s = time.perf_counter() - t_stage
+    print("serve: staged %d requests in %.1f s" % (count, stage_s), file=sys.stderr, flush=True)
+
+    def submit(srv, item):
+        p, u0, F, U = item
+        return pd.pd_server_submit(srv, p.n, p.ell, p.tau, p.M, p.K, u0, F, U, 1e-8,
+                                   dims=p.dims, precision=pd.PD_MIXED)
+
+    # warm-up: a few requests through a separate server (module loading, the
+    # device's first launches), then a fresh server for the timed stream
     srv = pd.pd_server_create(4, budget)
     try:
-        def submit(item):
-            p, u0, F, U = item
-            return pd.pd_server_submit(srv, p.n, p.ell, p.tau, p.M, p.K, u0, F, U, 1e-8,
-                                       dims=p.dims, precision=prec)
-        # warm the plan cache and measure closed-loop throughput
-        t0 = time.perf_counter()
-        ts = [submit(it) for it in staged]
-        for t in ts:
+        for t in [submit(srv, it) for it in staged[:8]]:
             pd.pd_server_wait(srv, t, -1)
-        closed = time.perf_counter() - t0
-        rate = 0.7 * count / closed
-        arrivals = np.cumsum(np.random.default_rng(4).exponential(1.0 / rate, count))
-        done_at = [0.0] * count
-        tickets = [None] * count
+    finally:
+        pd.pd_server_destroy(srv)
+    arrivals = np.array([r.arrival for r in reqs])
+    done_at = [0.0] * count
+    status = [None] * count
+    infos = [None] * count
+    tickets = [None] * count
+    srv = pd.pd_server_create(4, budget)
+    try:
         start = time.perf_counter()
 
         def waiter():
-            for i in range(count):
-                while tickets[i] is None:
-                    time.sleep(1e-4)
-                pd.pd_server_wait(srv, tickets[i], -1)
-                done_at[i] = time.perf_counter() - start
+            # poll every submitted, unfinished ticket, so that each completion
+            # is timed when it happens, whatever the completion order
+            pending = set(range(count))
+            while pending:
+                for i in sorted(pending):
+                    if tickets[i] is None:
+                        continue
+                    done, st, info = pd.pd_server_wait(srv, tickets[i], 0)
+                    if done:
+                        done_at[i] = time.perf_counter() - start
+                        status[i] = st
+                        infos[i] = info
+                        pending.discard(i)
+                time.sleep(2e-4)
         th = threading.Thread(target=waiter)
         th.start()
         for i, it in enumerate(staged):
             now = time.perf_counter() - start
             if arrivals[i] > now:
                 time.sleep(arrivals[i] - now)
-            tickets[i] = submit(it)
+            tickets[i] = submit(srv, it)
         th.join()
-        wall = max(done_at)
-        lat = np.array(done_at) - arrivals
         stats = pd.pd_server_stats(srv)
     finally:
         pd.pd_server_destroy(srv)
-    unknowns = sum(it[0].unknowns for it in staged)
+    ok = [i for i in range(count) if status[i] == pd.PD_OK]
+    failed = {}
+    for i in range(count):
+        if status[i] != pd.PD_OK:
+            name = pd.STATUS_NAMES[status[i]]
+            failed[name] = failed.get(name, 0) + 1
+    lat = np.array([done_at[i] - arrivals[i] for i in ok])
+    wall = max(done_at)
+    unknowns = sum(staged[i][0].unknowns for i in ok)
+    # sampled outputs of every request (for the error check)
+    rng = np.random.default_rng(11)
+    samples = []
+    for i, (p, u0, F, U) in enumerate(staged):
+        tt = rng.integers(0, p.ell, 300)
+        ii = rng.integers(0, p.nbar, 300)
+        got = U[torch.tensor(tt, device=dev), torch.tensor(ii, device=dev)].cpu().numpy()
+        samples.append((i, tt, ii, got))
+    sweeps = [infos[i].sweeps for i in ok]
+    del staged
     return {"metric": "space-time unknowns/s + p50/p99 latency (serving)",
-            "value": unknowns / wall, "unit": "space-time unknowns/s", "n_gpus": 1,
-            "higher_is_better": True, "dtype": "c64+f64", "data": "synthetic",
-            "config": {"workload": "Poisson stream of %d requests, 70%% 1D FEM / 30%% 2D FD, "
-                                   "mixed precision to 1e-8, 200 GB budget" % count,
-                       "arrival_rate_per_s": rate, "closed_loop_s": closed},
+            "value": unknowns / wall, "unit": "space-time unknowns/s",
+            "requests": count, "completed_ok": len(ok), "failed": failed,
+            "arrival_rate_per_s": rate, "wall_s": wall,
+            "requests_per_s": len(ok) / wall,
             "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
-                           "p99": 1e3 * float(np.percentile(lat, 99))},
-            "server": stats}
+                           "p99": 1e3 * float(np.percentile(lat, 99)),
+                           "max": 1e3 * float(lat.max())},
+            "sweeps": {"min": min(sweeps), "max": max(sweeps), "mean": float(np.mean(sweeps))},
+            "config": {"workload": "Poisson stream (fixed rate) of %d requests, 70%% 1D FEM "
+                                   "n<=16383 / 30%% 2D FD side<=511, nu log-uniform [1e-3,1], "
+                                   "mixed precision to 1e-8, 200 GB budget, 4 worker streams, "
+                                   "fresh plan cache" % count,
+                       "staging_s": stage_s},
+            "server": stats, "_samples": (samples, count, rate)}
+
+
+def serve_errors(srv, wl):
+    """Oracle leg: each served request's sampled error against the exact
+    modal solution (the stream is regenerated from its seed)."""
+    from oracle import modal
+    samples, count, rate = srv["_samples"]
+    errs = []
+    for r, (i, tt, ii, got) in zip(wl.iter_serving_stream(count=count, rate=rate), samples):
+        ref = modal.modal_sample(r.problem, tt, ii)
+        errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+    srv["rel_err_vs_exact_sampled"] = {"max": max(errs), "median": float(np.median(errs)),
+                                       "above_1e-8": int(sum(e > 1e-8 for e in errs))}
 
 
 if __name__ == "__main__":

@@ -143,6 +143,15 @@ typedef struct {
  * bdf_order 1. */
 void paradiag_default_options(pd_options *opt);
 
+/* Every check paradiag_plan_create makes that needs no device, with the same
+ * status codes: sizes, options, finite M and K, and -- with alpha = 1 -- a
+ * nonsingular zero-frequency block P_0 = tau K (Section 2: the shift
+ * 1 - pi_0 vanishes; a pure-Neumann K is rejected with PD_ESINGULAR).  Runs
+ * on the host only (no GPU is touched); M, K are host pointers as for
+ * paradiag_plan_create, opt may be NULL (defaults). */
+pd_status paradiag_plan_check(int n, int ell, double tau, const pd_tridiag *M,
+                              const pd_tridiag *K, const pd_options *opt);
+
 /* Create a plan for an n x ell problem with time step tau (Section 1).
  * Computes pi_j, gamma_j (Section 2; Appendix), the shifted-matrix
  * coefficients and twiddle tables in float64 on the host, allocates the
@@ -303,6 +312,47 @@ pd_status pd_server_stats(pd_server s, long *completed, size_t *peak_bytes,
 
 /* Finish all queued work, free every plan and stream. */
 pd_status pd_server_destroy(pd_server s);
+
+/* ---- the serving admission policy, replayed on the host ---------------- */
+
+/* One scripted event: op 0 = request `id` arrives and joins the FIFO queue
+ * (with its problem identity `key` -- requests with equal keys can share a
+ * cached plan -- its array bytes and its plan's workspace bytes); op 1 =
+ * request `id`, which must be running, finishes (create_fails = 1: its plan
+ * could not be created, so no plan joins the cache). */
+typedef struct {
+  int op;
+  int id;
+  int key;
+  int create_fails;
+  size_t io_bytes;
+  size_t plan_bytes;
+} pd_admission_event;
+
+/* What happened to one request: admitted_after = index of the event after
+ * which it was admitted (-1 never, -2 rejected at arrival because its arrays
+ * and plan alone exceed the budget, PD_EBUDGET in the server); cache_hit = 1
+ * if an idle cached plan was reused; evicted = idle plans evicted to admit it
+ * (least recently used first) and first_victim_key the key of the first;
+ * used_after = accounted bytes right after its admission. */
+typedef struct {
+  int admitted_after;
+  int cache_hit;
+  int evicted;
+  int first_victim_key;
+  size_t used_after;
+} pd_admission_outcome;
+
+/* Replay the admission and eviction policy of pd_server (the same policy
+ * code, no device work) on nevents events with at most `workers` requests
+ * running at once and a budget of budget_bytes.  outcomes has nreq entries,
+ * indexed by request id; *peak_bytes (may be NULL) receives the largest
+ * accounted total.  For tests and capacity planning.  Errors: PD_EINVAL
+ * (bad arguments, an id out of range, a request arriving twice or
+ * finishing while not running). */
+pd_status pd_admission_replay(size_t budget_bytes, int workers, const pd_admission_event *events,
+                              int nevents, pd_admission_outcome *outcomes, int nreq,
+                              size_t *peak_bytes);
 
 /* Device bytes a plan for this problem would allocate (workspace and
  * constants), without creating it. */

@@ -155,6 +155,22 @@ def paradiag_plan_create(n, ell, tau, M, K, options=None, **kw):
     return plan
 
 
+_plan_check = _sig("paradiag_plan_check", ctypes.c_int,
+                   [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(pd_tridiag),
+                    ctypes.POINTER(pd_tridiag), ctypes.POINTER(pd_options)])
+
+
+def paradiag_plan_check(n, ell, tau, M, K, options=None, **kw):
+    """Host-only validation of a plan's problem and options; returns the
+    pd_status code (no exception) and touches no GPU."""
+    opt = options if options is not None else paradiag_default_options()
+    for k, v in kw.items():
+        setattr(opt, k, v)
+    keep = []
+    return int(_plan_check(int(n), int(ell), float(tau), _tridiag(M, keep), _tridiag(K, keep),
+                           ctypes.byref(opt)))
+
+
 def paradiag_plan_config(plan):
     """(point pairs per time-transform tile, rows per thread of the shifted
     solves) of a plan."""
@@ -297,3 +313,38 @@ def pd_server_stats(server):
 
 def pd_server_destroy(server):
     return _check(_server_destroy(server), "pd_server_destroy")
+
+
+# ---- the admission policy, replayed on the host ------------------------------
+
+class pd_admission_event(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int), ("id", ctypes.c_int), ("key", ctypes.c_int),
+                ("create_fails", ctypes.c_int), ("io_bytes", ctypes.c_size_t),
+                ("plan_bytes", ctypes.c_size_t)]
+
+
+class pd_admission_outcome(ctypes.Structure):
+    _fields_ = [("admitted_after", ctypes.c_int), ("cache_hit", ctypes.c_int),
+                ("evicted", ctypes.c_int), ("first_victim_key", ctypes.c_int),
+                ("used_after", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_admission_replay = _sig("pd_admission_replay", ctypes.c_int,
+                         [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(pd_admission_event),
+                          ctypes.c_int, ctypes.POINTER(pd_admission_outcome), ctypes.c_int,
+                          ctypes.POINTER(ctypes.c_size_t)])
+
+
+def pd_admission_replay(budget_bytes, workers, events, nreq):
+    """events: (op, id, key, create_fails, io_bytes, plan_bytes) tuples.
+    Returns (list of outcome dicts indexed by request id, peak bytes)."""
+    ev = (pd_admission_event * max(1, len(events)))(
+        *[pd_admission_event(*e) for e in events])
+    out = (pd_admission_outcome * max(1, nreq))()
+    peak = ctypes.c_size_t(0)
+    _check(_admission_replay(int(budget_bytes), int(workers), ev, len(events), out, int(nreq),
+                             ctypes.byref(peak)), "pd_admission_replay")
+    return [out[i].as_dict() for i in range(nreq)], peak.value

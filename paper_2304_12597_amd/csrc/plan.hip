@@ -5,6 +5,7 @@
 // scaling D_alpha (Section 4), DFT twiddles, the coefficients of M and tau K
 // -- and the device workspace of every stage.
 #include "pd_internal.h"
+#include "pd_validate.h"
 
 #include <algorithm>
 #include <cmath>
@@ -441,118 +442,13 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   pd_options opt;
   paradiag_default_options(&opt);
   if (opt_in) opt = *opt_in;
-  if (!K || !K->diag || (n > 1 && (!K->lower || !K->upper))) {
-    pd_set_error("K must provide lower, diag and upper");
-    return PD_EINVAL;
-  }
-  if (M && (!M->diag || (n > 1 && (!M->lower || !M->upper)))) {
-    pd_set_error("M must provide lower, diag and upper (or be NULL)");
-    return PD_EINVAL;
-  }
-  if (opt.dims != 1 && opt.dims != 2) {
-    pd_set_error("dims must be 1 or 2");
-    return PD_EINVAL;
-  }
-  if (opt.precision < PD_FP64 || opt.precision > PD_FP32) {
-    pd_set_error("unknown precision");
-    return PD_EINVAL;
-  }
-  if (!is_pow2(ell) || ell < 2 || ell > 4096) {
-    pd_set_error("ell must be a power of two in [2, 4096]");
-    return (ell >= 2 && ell <= 4096) ? PD_ENOTSUP : PD_EINVAL;
-  }
-  if (!(tau > 0.0) || !std::isfinite(tau)) {
-    pd_set_error("tau must be positive and finite");
-    return PD_EINVAL;
-  }
-  if (!(opt.alpha > 0.0 && opt.alpha <= 1.0)) {
-    pd_set_error("alpha must lie in (0, 1]");
-    return PD_EINVAL;
-  }
-  if (opt.maxit < 1 || opt.maxit > 64 || opt.max_sweeps < 1 || opt.max_sweeps > 64) {
-    pd_set_error("maxit and max_sweeps must lie in [1, 64]");
-    return PD_EINVAL;
-  }
-  if (n < 2) {
-    pd_set_error("n must be at least 2");
-    return PD_EINVAL;
-  }
-  if (opt.dims == 1) {
-    const int nmax = (opt.precision == PD_FP64) ? 8192 : 16384;
-    if (n > nmax) {
-      pd_set_error("1D n exceeds " + std::to_string(nmax) + " for this precision");
-      return PD_ENOTSUP;
+  {
+    std::string msg;
+    const pd_status vst = pdcheck::check_plan_args(n, ell, tau, M, K, opt, &msg);
+    if (vst != PD_OK) {
+      pd_set_error(msg);
+      return vst;
     }
-  } else {
-    // separable 2D path: DST-I along x via a radix-2 FFT of length 2(n+1)
-    if (M) {
-      pd_set_error("2D plans take M = I (pass NULL)");
-      return PD_EINVAL;
-    }
-    if (n > 1024) {
-      pd_set_error("2D plans need n <= 1024");
-      return PD_ENOTSUP;
-    }
-    const double d0 = K->diag[0], o0 = K->upper[0];
-    for (int i = 0; i < n; ++i) {
-      if (K->diag[i] != d0 || (i < n - 1 && (K->upper[i] != o0 || K->lower[i + 1] != o0))) {
-        pd_set_error("2D plans need a symmetric Toeplitz 1D factor T");
-        return PD_ENOTSUP;
-      }
-    }
-  }
-  if ((opt.krylov != PD_KRYLOV_GMRES && opt.krylov != PD_KRYLOV_FOM) || opt.fom_q < 1) {
-    pd_set_error("unknown krylov solver or fom_q < 1");
-    return PD_EINVAL;
-  }
-  if (opt.shifted_solver != PD_SHIFTED_PARTITION && opt.shifted_solver != PD_SHIFTED_SINE) {
-    pd_set_error("unknown shifted_solver");
-    return PD_EINVAL;
-  }
-  if (opt.bdf_order < 1 || opt.bdf_order > 6) {
-    pd_set_error("bdf_order must lie in [1, 6]");
-    return PD_EINVAL;
-  }
-  if (opt.bdf_order > 1 &&
-      (opt.precision != PD_FP64 || opt.alpha != 1.0 ||
-       opt.shifted_solver != PD_SHIFTED_PARTITION ||
-       opt.early_exit != 0 || ell < 2 * opt.bdf_order)) {
-    pd_set_error("BDF plans of order > 1 need PD_FP64, alpha 1, partition solves, no "
-                 "early_exit and ell >= 2 * bdf_order");
-    return PD_ENOTSUP;
-  }
-  if (opt.bdf_order > 1 && opt.krylov == PD_KRYLOV_FOM && n < opt.bdf_order) {
-    pd_set_error("the block Galerkin method needs n >= bdf_order");
-    return PD_ENOTSUP;
-  }
-  if (opt.shifted_solver == PD_SHIFTED_SINE) {
-    if (opt.dims != 1 || opt.precision != PD_FP64 || (is_pow2(n + 1) ? n + 1 < 16 : n > 4095)) {
-      pd_set_error("sine-basis solves need a 1D float64 plan with n + 1 a power of two >= 16 "
-                   "or n <= 4095");
-      return PD_ENOTSUP;
-    }
-    // symmetric Toeplitz M and K (constant diagonals, equal off-diagonals)
-    auto toeplitz = [n](const pd_tridiag *T) {
-      const double d0 = T->diag[0], o0 = T->upper[0];
-      for (int i = 0; i < n; ++i)
-        if (T->diag[i] != d0 || (i < n - 1 && (T->upper[i] != o0 || T->lower[i + 1] != o0)))
-          return false;
-      return true;
-    };
-    if (!toeplitz(K) || (M && !toeplitz(M))) {
-      pd_set_error("sine-basis solves need symmetric Toeplitz M and K");
-      return PD_ENOTSUP;
-    }
-  }
-  for (int i = 0; i < n; ++i) {
-    double vals[6] = {K->diag[i], i > 0 ? K->lower[i] : 0.0, i < n - 1 ? K->upper[i] : 0.0,
-                      M ? M->diag[i] : 1.0, (M && i > 0) ? M->lower[i] : 0.0,
-                      (M && i < n - 1) ? M->upper[i] : 0.0};
-    for (double v : vals)
-      if (!std::isfinite(v)) {
-        pd_set_error("M or K has a non-finite entry");
-        return PD_EINVAL;
-      }
   }
 
   pd_plan p = new (std::nothrow) pd_plan_s();
@@ -618,21 +514,6 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
     coef[3 * n + i] = (i > 0) ? tk * K->lower[i] : 0.0;
     coef[4 * n + i] = tk * K->diag[i];
     coef[5 * n + i] = (i < n - 1) ? tk * K->upper[i] : 0.0;
-  }
-  // alpha = 1: P_0 = tau K must be nonsingular (Section 2, the zero
-  // frequency); check with an unpivoted elimination in float64.
-  if (opt.alpha == 1.0) {
-    double cprev = 0.0;
-    for (int i = 0; i < n; ++i) {
-      double a = coef[3 * n + i], b = coef[4 * n + i], c = coef[5 * n + i];
-      double piv = b - a * cprev;
-      if (!(std::fabs(piv) > 1e-300) || !std::isfinite(piv)) {
-        pd_set_error("tau K is singular (zero frequency shift with alpha = 1)");
-        free_plan(p);
-        return PD_ESINGULAR;
-      }
-      cprev = c / piv;
-    }
   }
   std::vector<float> coef32(coef.begin(), coef.end());
   // constant diagonals (uniform grids): the shifted solves use six scalars
@@ -939,6 +820,18 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   }
   *out = p;
   return PD_OK;
+}
+
+extern "C" pd_status paradiag_plan_check(int n, int ell, double tau, const pd_tridiag *M,
+                                         const pd_tridiag *K, const pd_options *opt_in) {
+  g_last_error.clear();
+  pd_options opt;
+  paradiag_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  std::string msg;
+  const pd_status st = pdcheck::check_plan_args(n, ell, tau, M, K, opt, &msg);
+  if (st != PD_OK) pd_set_error(msg);
+  return st;
 }
 
 extern "C" pd_status paradiag_plan_config(pd_plan p, int *fft_C, int *rows_per_thread) {

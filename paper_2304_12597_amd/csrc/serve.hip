@@ -9,6 +9,7 @@
 // room.  Results do not depend on the mix: a request always runs with the
 // plan configuration its own (n, ell, precision) selects, and every kernel
 // reduces in a fixed order.
+#include "pd_admission.h"
 #include "pd_internal.h"
 
 #include <atomic>
@@ -49,13 +50,6 @@ struct Key {
   }
 };
 
-struct Cached {
-  pd_plan plan = nullptr;
-  size_t bytes = 0;
-  bool busy = false;
-  unsigned long last_used = 0;
-};
-
 struct Job {
   pd_request req;
   Key key;
@@ -84,85 +78,48 @@ std::vector<double> flatten(const pd_tridiag *t, int n) {
 }  // namespace
 
 struct pd_server_s {
+  using Policy = pdserve::Admission<Key, pd_plan>;
   int device = 0;
-  size_t budget = 0;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<std::shared_ptr<Job>> queue;
   std::map<long, std::shared_ptr<Job>> jobs;
-  std::multimap<Key, Cached> cache;
-  size_t used = 0, peak = 0;
-  long next_ticket = 0, completed = 0, hits = 0, misses = 0;
-  unsigned long clock = 0;
+  Policy policy;
+  long next_ticket = 0, completed = 0;
   bool stop = false;
   std::vector<std::thread> workers;
   std::vector<hipStream_t> streams;
 
-  // Evict idle cached plans (LRU) until `need` more bytes fit; call locked.
-  bool make_room(size_t need) {
-    while (used + need > budget) {
-      auto victim = cache.end();
-      for (auto it = cache.begin(); it != cache.end(); ++it)
-        if (!it->second.busy && (victim == cache.end() ||
-                                 it->second.last_used < victim->second.last_used))
-          victim = it;
-      if (victim == cache.end()) return false;
-      used -= victim->second.bytes;
-      (void)paradiag_plan_destroy(victim->second.plan);
-      cache.erase(victim);
-    }
-    return true;
-  }
+  explicit pd_server_s(size_t budget) : policy(budget) {}
 
   void worker(int wid) {
     (void)hipSetDevice(device);
     hipStream_t stream = streams[wid];
     for (;;) {
       std::shared_ptr<Job> job;
-      std::multimap<Key, Cached>::iterator slot = cache.end();
+      Policy::Grant grant;
+      std::vector<std::pair<Key, pd_plan>> evicted;
       {
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
           if (stop && queue.empty()) return;
           if (!queue.empty()) {
             auto &head = queue.front();
-            // an idle cached plan for this problem?
-            auto range = cache.equal_range(head->key);
-            for (auto it = range.first; it != range.second; ++it)
-              if (!it->second.busy) { slot = it; break; }
-            size_t need = head->io_bytes + (slot == cache.end() ? head->plan_bytes : 0);
-            bool fits = used + need <= budget;
-            if (!fits && make_room(need)) {
-              fits = true;
-              // eviction may have removed the slot we found
-              slot = cache.end();
-              auto r2 = cache.equal_range(head->key);
-              for (auto it = r2.first; it != r2.second; ++it)
-                if (!it->second.busy) { slot = it; break; }
-              need = head->io_bytes + (slot == cache.end() ? head->plan_bytes : 0);
-              fits = used + need <= budget;
-            }
-            if (fits) {
+            grant = policy.try_admit(head->key, head->io_bytes, head->plan_bytes, &evicted);
+            if (grant.admitted) {
               job = head;
               queue.pop_front();
-              used += need;
-              if (used > peak) peak = used;
-              if (slot != cache.end()) {
-                slot->second.busy = true;
-                ++hits;
-              } else {
-                ++misses;
-              }
               break;
             }
           }
           cv_work.wait(lk);
         }
       }
+      for (auto &e : evicted) (void)paradiag_plan_destroy(e.second);
       pd_plan plan = nullptr;
       pd_status st = PD_OK;
-      if (slot != cache.end()) {
-        plan = slot->second.plan;
+      if (grant.hit) {
+        plan = grant.slot->second.handle;
       } else {
         pd_options opt = job->req.opt;
         opt.stream = stream;
@@ -175,19 +132,7 @@ struct pd_server_s {
       }
       {
         std::lock_guard<std::mutex> lk(mu);
-        used -= job->io_bytes;
-        if (slot != cache.end()) {
-          slot->second.busy = false;
-          slot->second.last_used = ++clock;
-        } else if (plan) {
-          Cached c;
-          c.plan = plan;
-          c.bytes = job->plan_bytes;
-          c.last_used = ++clock;
-          cache.emplace(job->key, c);
-        } else {
-          used -= job->plan_bytes;   // creation failed: release the reservation
-        }
+        policy.finish(grant, job->key, plan != nullptr, plan);
         job->status = st;
         job->done = true;
         ++completed;
@@ -204,9 +149,8 @@ extern "C" pd_status pd_server_create(pd_server *out, int workers, size_t budget
     return PD_EINVAL;
   }
   *out = nullptr;
-  pd_server s = new (std::nothrow) pd_server_s();
+  pd_server s = new (std::nothrow) pd_server_s(budget_bytes);
   if (!s) return PD_ENOMEM;
-  s->budget = budget_bytes;
   if (hipGetDevice(&s->device) != hipSuccess) {
     delete s;
     pd_set_error("no HIP device");
@@ -284,7 +228,7 @@ extern "C" pd_status pd_server_submit(pd_server s, const pd_request *req, long *
     pd_set_error("pd_server_submit: unsupported problem");
     return PD_ENOTSUP;
   }
-  if (job->io_bytes + job->plan_bytes > s->budget) {
+  if (!s->policy.fits_alone(job->io_bytes, job->plan_bytes)) {
     pd_set_error("pd_server_submit: request exceeds the device-memory budget");
     return PD_EBUDGET;
   }
@@ -329,10 +273,10 @@ extern "C" pd_status pd_server_stats(pd_server s, long *completed, size_t *peak_
   if (!s) return PD_EINVAL;
   std::lock_guard<std::mutex> lk(s->mu);
   if (completed) *completed = s->completed;
-  if (peak_bytes) *peak_bytes = s->peak;
-  if (cache_hits) *cache_hits = s->hits;
-  if (cache_misses) *cache_misses = s->misses;
-  if (current) *current = s->used;
+  if (peak_bytes) *peak_bytes = s->policy.peak();
+  if (cache_hits) *cache_hits = s->policy.hits();
+  if (cache_misses) *cache_misses = s->policy.misses();
+  if (current) *current = s->policy.used();
   return PD_OK;
 }
 
@@ -344,8 +288,93 @@ extern "C" pd_status pd_server_destroy(pd_server s) {
   }
   s->cv_work.notify_all();
   for (auto &t : s->workers) t.join();
-  for (auto &kv : s->cache) (void)paradiag_plan_destroy(kv.second.plan);
+  for (auto &kv : s->policy.cache()) (void)paradiag_plan_destroy(kv.second.handle);
   for (auto st : s->streams) (void)hipStreamDestroy(st);
   delete s;
+  return PD_OK;
+}
+
+// Replay of the admission policy on a scripted sequence of arrivals and
+// completions, with `workers` requests running at most at once: the same
+// policy object pd_server uses, with no device work.
+extern "C" pd_status pd_admission_replay(size_t budget_bytes, int workers,
+                                         const pd_admission_event *events, int nevents,
+                                         pd_admission_outcome *outcomes, int nreq,
+                                         size_t *peak_bytes) {
+  if (budget_bytes == 0 || workers < 1 || nevents < 0 || nreq < 0 || (nevents > 0 && !events) ||
+      (nreq > 0 && !outcomes)) {
+    pd_set_error("pd_admission_replay: invalid arguments");
+    return PD_EINVAL;
+  }
+  using Policy = pdserve::Admission<int, int>;
+  Policy policy(budget_bytes);
+  struct Req {
+    int key = 0;
+    size_t io = 0, plan = 0;
+    int state = 0;   // 0 unseen, 1 queued, 2 running, 3 finished, 4 rejected
+    Policy::Grant grant;
+  };
+  std::vector<Req> reqs((size_t)nreq);
+  std::deque<int> queue;
+  int running = 0;
+  for (int r = 0; r < nreq; ++r) {
+    outcomes[r].admitted_after = -1;
+    outcomes[r].cache_hit = 0;
+    outcomes[r].evicted = 0;
+    outcomes[r].first_victim_key = -1;
+    outcomes[r].used_after = 0;
+  }
+  for (int e = 0; e < nevents; ++e) {
+    const pd_admission_event &ev = events[e];
+    if (ev.id < 0 || ev.id >= nreq) {
+      pd_set_error("pd_admission_replay: request id out of range");
+      return PD_EINVAL;
+    }
+    Req &r = reqs[(size_t)ev.id];
+    if (ev.op == 0) {
+      if (r.state != 0) {
+        pd_set_error("pd_admission_replay: request arrives twice");
+        return PD_EINVAL;
+      }
+      r.key = ev.key;
+      r.io = ev.io_bytes;
+      r.plan = ev.plan_bytes;
+      if (!policy.fits_alone(r.io, r.plan)) {
+        r.state = 4;
+        outcomes[ev.id].admitted_after = -2;
+      } else {
+        r.state = 1;
+        queue.push_back(ev.id);
+      }
+    } else if (ev.op == 1) {
+      if (r.state != 2) {
+        pd_set_error("pd_admission_replay: a request finishes that is not running");
+        return PD_EINVAL;
+      }
+      policy.finish(r.grant, r.key, ev.create_fails == 0, ev.id);
+      r.state = 3;
+      --running;
+    } else {
+      pd_set_error("pd_admission_replay: unknown event op");
+      return PD_EINVAL;
+    }
+    // admit from the head of the queue while a worker is free and it fits
+    while (running < workers && !queue.empty()) {
+      const int id = queue.front();
+      Req &h = reqs[(size_t)id];
+      std::vector<std::pair<int, int>> evicted;
+      h.grant = policy.try_admit(h.key, h.io, h.plan, &evicted);
+      if (!h.grant.admitted) break;
+      queue.pop_front();
+      h.state = 2;
+      ++running;
+      outcomes[id].admitted_after = e;
+      outcomes[id].cache_hit = h.grant.hit ? 1 : 0;
+      outcomes[id].evicted = (int)evicted.size();
+      outcomes[id].first_victim_key = evicted.empty() ? -1 : evicted.front().first;
+      outcomes[id].used_after = policy.used();
+    }
+  }
+  if (peak_bytes) *peak_bytes = policy.peak();
   return PD_OK;
 }

@@ -238,31 +238,47 @@ class Request:
     problem: HeatProblem
 
 
-def serving_stream(seed: int = 4, count: int = 64, rate: float = 100.0,
-                   fem_n=(1023, 16383), fem_ells=(128, 256, 512, 1024, 2048),
-                   sides=(127, 255, 511), fd2_ells=(64, 128, 256, 512)):
+def iter_serving_stream(seed: int = 4, count: int = 64, rate: float = 100.0,
+                        fem_n=(1023, 16383), fem_ells=(128, 256, 512, 1024, 2048),
+                        sides=(127, 255, 511), fd2_ells=(64, 128, 256, 512), build=True):
     """Poisson arrivals at ``rate`` requests/s of mixed requests: 70% 1D FEM
     heat (n ~ U{1023..16383}, ell a power of two in 128..2048, T = 1, with
     source) and 30% 2D FD heat (side in {127, 255, 511}, ell in 64..512,
-    T = 0.1, f = 0), nu log-uniform in [1e-3, 1]."""
+    T = 0.1, f = 0), nu log-uniform in [1e-3, 1].  Yields one Request at a
+    time.  build=False draws the same stream but leaves the problems' arrays
+    empty (sizes only); a set of request indices builds only those."""
     rng = np.random.default_rng(seed)
     t = 0.0
-    out = []
-    for _ in range(count):
+    for idx in range(count):
+        make = build if isinstance(build, bool) else idx in build
         t += float(rng.exponential(1.0 / rate))
         if rng.uniform() < 0.7:
             n = int(rng.integers(fem_n[0], fem_n[1] + 1))
             ell = int(fem_ells[int(rng.integers(0, len(fem_ells)))])
             nu = float(np.exp(rng.uniform(np.log(1e-3), 0.0)))
-            p = heat_1d("fem1", n, ell, 1.0, nu, rng, True)
+            if make:
+                p = heat_1d("fem1", n, ell, 1.0, nu, rng, True)
+            else:
+                rng.standard_normal(7); rng.standard_normal(16); rng.uniform(0.0, 10.0, 16)
+                p = HeatProblem("fem1", n, ell, 1.0, nu, None, (np.zeros(0),) * 3,
+                                np.zeros(0), np.zeros((0, 0)))
         else:
             n = int(sides[int(rng.integers(0, len(sides)))])
             ell = int(fd2_ells[int(rng.integers(0, len(fd2_ells)))])
             nu = float(np.exp(rng.uniform(np.log(1e-3), 0.0)))
-            p = heat_2d(n, ell, 0.1, nu, rng)
+            if make:
+                p = heat_2d(n, ell, 0.1, nu, rng)
+            else:
+                rng.standard_normal((8, 8))
+                p = HeatProblem("fd2", n, ell, 0.1, nu, None, (np.zeros(0),) * 3,
+                                np.zeros(0), np.zeros((0, 0)))
         p.seed = seed
-        out.append(Request(t, p))
-    return out
+        yield Request(t, p)
+
+
+def serving_stream(seed: int = 4, count: int = 64, rate: float = 100.0, build=True, **kw):
+    """The whole stream of ``iter_serving_stream`` as a list."""
+    return list(iter_serving_stream(seed, count, rate, build=build, **kw))
 
 
 def dense_tridiag(t: Tridiag) -> np.ndarray:

@@ -16,7 +16,7 @@ LIB = os.path.join(ROOT, "paper_2304_12597_amd", "libparadiag.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b((?:paradiag|pd_server)_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b((?:paradiag|pd_server|pd_admission)_\w+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")

@@ -128,18 +128,30 @@ def test_2d_mixed(lib, n):
     assert err < 1e-8, (err, info.as_dict())
 
 
-def test_2d_full_size_sampled(lib):
-    """511 x 511 grid, ell = 256, T = 0.1: sampled outputs vs the exact
-    modal solution."""
+@pytest.mark.parametrize("prec", [0, 1])
+def test_2d_full_size_sampled(lib, prec):
+    """511 x 511 grid, ell = 256, T = 0.1 (66.9M space-time unknowns):
+    sampled outputs vs the exact modal solution, float64 (1e-10) and the
+    mixed form (complex64 DST/transforms/line solves, float64 refinement:
+    1e-8, PD_OK, residual at most tol)."""
     p = wl.cfg_fd_2d()
-    U, info = _solve(lib, p, tol=1e-10)
+    tol = 1e-10 if prec == 0 else 1e-8
+    U, info = _solve(lib, p, prec=prec, tol=tol)
     rng = np.random.default_rng(0)
     tt = rng.integers(0, p.ell, 3000)
     ii = rng.integers(0, p.nbar, 3000)
+    tt[:2] = [0, p.ell - 1]
+    ii[:2] = [0, p.nbar - 1]
     ref = modal.modal_sample(p, tt, ii)
     err = np.linalg.norm(U[tt, ii] - ref) / np.linalg.norm(ref)
-    assert err < 1e-10, (err, info.as_dict())
-    assert 0 <= info.rel_residual < 1e-11
+    print("2D 511^2 ell=256 prec=%d err=%.3e res=%.3e gmres=%d sweeps=%d" % (
+        prec, err, info.rel_residual, info.gmres_iters, info.sweeps))
+    if prec == 0:
+        assert err < 1e-10, (err, info.as_dict())
+        assert 0 <= info.rel_residual < 1e-11
+    else:
+        assert err < 1e-8, (err, info.as_dict())
+        assert 0 <= info.rel_residual <= tol
 
 
 # Algorithm 2 runs at T = 1: at T = 0.1 its polynomial Krylov space of the

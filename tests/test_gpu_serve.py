@@ -7,6 +7,8 @@ import pytest
 from oracle import allatonce, modal
 from paper_2304_12597_amd import workloads as wl
 
+from bounds import fp64_error_bound, tau_mu_range
+
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
@@ -74,7 +76,11 @@ def test_server_results_same_alone_and_in_mix(lib, prec):
         Ug = U.cpu().numpy()
         assert np.array_equal(Ug, Ua)          # identical alone and in the mix
         err = allatonce.rel_err(Ug, modal.modal_solution(p))
-        assert err < 1e-8, (p.kind, p.n, p.ell, err)
+        # float64: the bar of the problem's conditioning at tol = 1e-10 (the
+        # 2D draws with nu T = 1e-4 have cond(J) ~ 1e3 and reach about 1e-9);
+        # mixed precision: the 1e-8 bar of the refinement
+        bound = fp64_error_bound(p, 1e-10) if prec == 0 else 1e-8
+        assert err < bound, (p.kind, p.n, p.ell, p.nu, err, bound)
 
 
 def test_server_budget_and_cache(lib):
@@ -152,9 +158,13 @@ def test_solve_batch_matches_individual(lib):
     finally:
         for pl in plans:
             lib.paradiag_plan_destroy(pl)
-    for U, Ua, info in zip(Us, alone, infos):
-        assert np.array_equal(U.cpu().numpy(), Ua)
+    for p, U, Ua, info in zip(probs, Us, alone, infos):
+        Ug = U.cpu().numpy()
+        assert np.array_equal(Ug, Ua)
         assert info.gmres_iters >= 1
+        # and against the exact discrete solution (the oracle's modal form)
+        err = allatonce.rel_err(Ug, modal.modal_solution(p))
+        assert err < fp64_error_bound(p, 1e-10), (p.kind, p.n, p.ell, p.nu, err)
 
 
 def test_solve_batch_graph_replays(lib):
@@ -191,3 +201,45 @@ def test_solve_batch_graph_replays(lib):
             assert np.array_equal(Ua, Ub), call
     for Ua, Ub in zip(results[0], alone):
         assert np.array_equal(Ua, Ub)
+    for p, Ua in zip(probs, results[0]):
+        err = allatonce.rel_err(Ua, modal.modal_solution(p))
+        assert err < fp64_error_bound(p, 1e-10), (p.kind, p.n, p.ell, p.nu, err)
+
+
+def test_server_stiffest_stream_requests(lib):
+    """The three stiffest requests of the 256-request serving stream (1D FEM,
+    tau mu_max 6e6 to 1.5e7, n > 12000) in the mixed form through the
+    server, together: each finishes with PD_OK, its float64 residual at
+    most tol, its sampled error against the exact modal solution at most
+    1e-8, and the same result as when solved alone."""
+    sizes = wl.serving_stream(count=256, rate=1.0, build=False)
+    pick = sorted(range(256), key=lambda i: -tau_mu_range(sizes[i].problem)[1])[:3]
+    reqs = wl.serving_stream(count=256, rate=1.0, build=set(pick))
+    probs = [reqs[i].problem for i in pick]
+    assert min(tau_mu_range(p)[1] for p in probs) > 5e6
+    alone = [solve_alone(lib, p, prec=1, tol=1e-8) for p in probs]
+    srv = lib.pd_server_create(3, 16 << 30)
+    try:
+        bufs = [(T(p.u0), T(p.F), torch.empty((p.ell, p.nbar), dtype=torch.float64,
+                                              device=dev())) for p in probs]
+        torch.cuda.synchronize()
+        ts = [lib.pd_server_submit(srv, p.n, p.ell, p.tau, p.M, p.K, u0, F, U, 1e-8,
+                                   precision=lib.PD_MIXED) for p, (u0, F, U) in zip(probs, bufs)]
+        infos = []
+        for t in ts:
+            done, st, info = lib.pd_server_wait(srv, t, -1)
+            assert done and st == lib.PD_OK, (st, info.as_dict())
+            infos.append(info)
+    finally:
+        lib.pd_server_destroy(srv)
+    rng = np.random.default_rng(6)
+    for p, (_, _, U), Ua, info in zip(probs, bufs, alone, infos):
+        Ug = U.cpu().numpy()
+        assert np.array_equal(Ug, Ua)
+        tt = rng.integers(0, p.ell, 3000)
+        ii = rng.integers(0, p.nbar, 3000)
+        ref = modal.modal_sample(p, tt, ii)
+        err = float(np.linalg.norm(Ug[tt, ii] - ref) / np.linalg.norm(ref))
+        print("n=%d ell=%d nu=%.3f tau*mu_max=%.2e err=%.3e res=%.3e sweeps=%d" % (
+            p.n, p.ell, p.nu, tau_mu_range(p)[1], err, info.rel_residual, info.sweeps))
+        assert err < 1e-8 and 0 <= info.rel_residual <= 1e-8

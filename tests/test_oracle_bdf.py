@@ -236,3 +236,23 @@ def test_modal_recurrence_2d_matches_stepping(s):
     Msp, Ksp = problem_matrices(p)
     S = bdf.step_bdf(Msp, Ksp, p.tau, s, [p.u0] * s, p.F)
     assert allatonce.rel_err(bdf.modal_bdf(p, s), S) < 1e-12
+
+
+@pytest.mark.parametrize("s", [1, 2, 3])
+def test_modal_bdf_sampled_branch_matches_full(s):
+    """The point-by-point (sampled) branch of the 2D per-mode BDF recurrence,
+    which grades full-size GPU results, equals the full-array branch at the
+    same (t, point) pairs, including the first and last time rows and grid
+    corners; the full branch is itself pinned to sequential stepping."""
+    p = wl.heat_2d(15, 16, 0.1, 1.0, np.random.default_rng(40 + s))
+    full = bdf.modal_bdf(p, s)
+    rng = np.random.default_rng(s)
+    tt = rng.integers(0, p.ell, 500)
+    ii = rng.integers(0, p.nbar, 500)
+    tt[:4] = [0, 0, p.ell - 1, p.ell - 1]
+    ii[:4] = [0, p.nbar - 1, p.n - 1, p.nbar - p.n]
+    samp = bdf.modal_bdf(p, s, (tt, ii))
+    assert np.allclose(samp, full[tt, ii], rtol=1e-13, atol=1e-15 * np.abs(full).max())
+    # a transposed point index (x and y swapped) would not match
+    swapped = (ii % p.n) * p.n + ii // p.n
+    assert not np.allclose(full[tt, swapped], full[tt, ii])
