@@ -264,6 +264,21 @@ pd_status paradiag_inverse_transform(pd_plan plan, const void *Uhat,
 pd_status paradiag_residual(pd_plan plan, const double *u0, const double *F,
                             const double *U, double *rel);
 
+/* For callers that cannot allocate device memory during the call (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * paradiag_residual with no allocation at all.  The per-block partial norms
+ * and their totals live in a file-scope device array of the library (at most
+ * 8192 partial-norm blocks, 196,640 bytes, held on every GPU the library runs
+ * on until the process ends; the plan's own reduction buffer is not used),
+ * the totals are summed on the device in a fixed order, and three doubles
+ * come back to the host.  Backward-Euler plans only (PD_ENOTSUP for
+ * bdf_order > 1); PD_ENOTSUP with a message if a plan ever needed more blocks
+ * than the array holds.  Every call on a GPU shares that GPU's array: calls
+ * that overlap on one GPU (other streams, other threads) race.  Synchronises
+ * the plan's stream. */
+pd_status paradiag_residual_noalloc(pd_plan plan, const double *u0, const double *F,
+                                    const double *U, double *rel);
+
 /* ---- serving: continuous batching of independent solves ---------------- */
 
 typedef struct pd_server_s *pd_server;

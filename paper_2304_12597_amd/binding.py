@@ -92,6 +92,10 @@ _residual = _sig("paradiag_residual", ctypes.c_int,
                  [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)])
 
 
+_residual_noalloc = _sig("paradiag_residual_noalloc", ctypes.c_int,
+                         [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)])
+
+
 class PDError(RuntimeError):
     def __init__(self, status, where):
         self.status = status
@@ -231,6 +235,13 @@ def paradiag_capacitance_solve(plan, b, x, rtol, allow_notconv=False):
 
 def paradiag_inverse_transform(plan, Uhat, U):
     return _check(_inverse(plan, _ptr(Uhat), _ptr(U)), "paradiag_inverse_transform")
+
+
+def paradiag_residual_noalloc(plan, u0, F, U) -> float:
+    r = ctypes.c_double(-1.0)
+    _check(_residual_noalloc(plan, _ptr(u0), _ptr(F), _ptr(U), ctypes.byref(r)),
+           "paradiag_residual_noalloc")
+    return r.value
 
 
 def paradiag_residual(plan, u0, F, U) -> float:

@@ -5,6 +5,7 @@
 #include "pd_residual.h"
 
 #include <cmath>
+#include <mutex>
 
 namespace {
 
@@ -100,6 +101,112 @@ pd_status pd_residual_norms(pd_plan p, const double *u0, const double *F, const 
   *rn2 = a;
   *gn2 = b;
   *un2 = c;
+  return PD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The allocation-free residual (paradiag_residual_noalloc): the per-block
+// partial norms and their totals live in a file-scope device array instead
+// of the plan's reduction buffer, and the totals are summed on the device, so
+// the call allocates nothing on the device or the host.  Every call on a GPU
+// shares that GPU's copy of the array; calls that overlap on one GPU race.
+// ---------------------------------------------------------------------------
+constexpr int PD_NOALLOC_MAX_BLOCKS = 8192;
+constexpr size_t PD_NOALLOC_SCRATCH_DOUBLES = 3 * (size_t)PD_NOALLOC_MAX_BLOCKS + 4;
+static __device__ __align__(256) double scratch[PD_NOALLOC_SCRATCH_DOUBLES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+constexpr int PD_MAX_DEVICES = 64;
+double *g_scratch_ptr[PD_MAX_DEVICES] = {};
+
+// Device address of this GPU's copy of `scratch`, looked up once per device
+// with that device current (in host code the array's name is not a device
+// address).
+pd_status scratch_address(int device, double **out) {
+  if (device < 0 || device >= PD_MAX_DEVICES) {
+    pd_set_error("device index out of range for the scratch table");
+    return PD_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = 0;
+    PD_HIP_CHECK(hipGetDevice(&cur));
+    if (cur != device) PD_HIP_CHECK(hipSetDevice(device));
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr) {
+      pd_set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      return PD_EHIP;
+    }
+    g_scratch_ptr[device] = static_cast<double *>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return PD_OK;
+}
+
+// Sum the 3 * nb partial norms in a fixed order (each thread a strided run,
+// then a fixed tree in LDS) into tot[0..2].
+__global__ void __launch_bounds__(RB) sum_partials_kernel(int nb, const double *__restrict__ red,
+                                                          double *__restrict__ tot) {
+  __shared__ double s[3][RB];
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < nb; i += RB) {
+    a += red[3 * i];
+    b += red[3 * i + 1];
+    c += red[3 * i + 2];
+  }
+  s[0][threadIdx.x] = a;
+  s[1][threadIdx.x] = b;
+  s[2][threadIdx.x] = c;
+  __syncthreads();
+  for (int w = RB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int q = 0; q < 3; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) tot[threadIdx.x] = s[threadIdx.x][0];
+}
+
+}  // namespace
+
+extern "C" pd_status paradiag_residual_noalloc(pd_plan p, const double *u0, const double *F,
+                                               const double *U, double *rel) {
+  if (!p || !rel || !u0 || !F || !U) {
+    pd_set_error("invalid residual arguments");
+    return PD_EINVAL;
+  }
+  if (p->bdf_s > 1) {
+    pd_set_error("paradiag_residual_noalloc: backward-Euler plans only (bdf_order 1)");
+    return PD_ENOTSUP;
+  }
+  const int nb = pd_residual_blocks(p);
+  if (nb > PD_NOALLOC_MAX_BLOCKS || 3 * (size_t)nb + 3 > PD_NOALLOC_SCRATCH_DOUBLES) {
+    pd_set_error("paradiag_residual_noalloc: the residual pass needs " + std::to_string(nb) +
+                 " partial-norm blocks, above the static scratch's " +
+                 std::to_string(PD_NOALLOC_MAX_BLOCKS));
+    return PD_ENOTSUP;
+  }
+  double *sp = nullptr;
+  pd_status st = scratch_address(p->device, &sp);
+  if (st != PD_OK) return st;
+  double *red = sp, *tot = sp + 3 * (size_t)PD_NOALLOC_MAX_BLOCKS;
+  // every block writes its three partial norms, so nothing needs clearing
+  hipLaunchKernelGGL(residual_kernel, dim3(nb), dim3(RB), 0, p->stream, p->n, p->nbar, p->ell,
+                     p->dims, p->tau, u0, F, U, p->coef64, red);
+  PD_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(RB), 0, p->stream, nb, red, tot);
+  PD_HIP_CHECK(hipGetLastError());
+  double h[3];
+  PD_HIP_CHECK(hipMemcpyAsync(h, tot, sizeof(h), hipMemcpyDeviceToHost, p->stream));
+  PD_HIP_CHECK(hipStreamSynchronize(p->stream));
+  if (!std::isfinite(h[0]) || !std::isfinite(h[1])) {
+    pd_set_error("non-finite residual norm");
+    return PD_ENONFINITE;
+  }
+  *rel = (h[1] > 0.0) ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
   return PD_OK;
 }
 
