@@ -51,13 +51,21 @@ struct BatchRun {
   hipGraphExec_t exec = nullptr;
   hipStream_t cap = nullptr;       // capture stream (the plan stream may be the legacy one)
   const FftJob *fj = nullptr;
-  const TriJob *tj = nullptr, *tjJ = nullptr;
+  const TriJob *tj = nullptr, *tjJ = nullptr, *tk0 = nullptr;
+  const int2 *k0m = nullptr;
+  int nk0 = 0;
   const VecJob *vj = nullptr;
   const int2 *fm = nullptr, *t0 = nullptr, *t1 = nullptr, *vm = nullptr, *rm = nullptr;
+  // J products: the per-frequency path (t0J, rmJ) for some problems, the
+  // chunked capacitance product (cj, c1m..c3m) for the others
+  const int2 *t0J = nullptr, *rmJ = nullptr;
+  const CpJob *cj = nullptr;
+  const int2 *c1m = nullptr, *c2m = nullptr, *c3m = nullptr;
   int *act = nullptr;
   double *st = nullptr;
   int nf = 0, n0 = 0, n1 = 0, nv = 0, nr = 0, fft_threads = 64;
-  size_t fft_lds = 0, tri_lds = 0;
+  int n0J = 0, nrJ = 0, nc1 = 0, nc2 = 0, nc3 = 0, cthreads2 = 64;
+  size_t fft_lds = 0, tri_lds = 0, clds1 = 0, clds2 = 0;
   ~BatchRun() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (cap) (void)hipStreamDestroy(cap);
@@ -84,7 +92,11 @@ pd_status build_run(BatchRun &r, const pd_plan *plans, int count, const double *
     std::vector<FftJob> fj(count);
     std::vector<TriJob> tj(count);
     std::vector<VecJob> vj(count);
-    std::vector<int2> fftmap, tri0map, tri1map, vmap, redmap;
+    std::vector<int2> fftmap, tri0map, tri1map, vmap, redmap, tri0mapJ, redmapJ;
+    std::vector<CpJob> cj(count);
+    std::vector<int2> c1map, c2map, c3map, k0map;
+    int cthreads2 = 64;
+    size_t clds1 = 0, clds2 = 0;
     int fft_threads = 64, MR = -1;
     size_t fft_lds = 0, tri_lds = 0;
     for (int i = 0; i < count; ++i) {
@@ -130,6 +142,22 @@ pd_status build_run(BatchRun &r, const pd_plan *plans, int count, const double *
       v.bout = p->bvec; v.b = p->bvec; v.done = p->gm + pd_gmres_done_index(MX);
       for (int b = 0; b < v.B; ++b) vmap.push_back(make_int2(i, b));
       for (int b = 0; b < (p->nbar + 255) / 256; ++b) redmap.push_back(make_int2(i, b));
+      if (p->cp_on) {
+        // J products of this problem by the chunked capacitance product (jobs
+        // indexed by problem, like the activity flags)
+        const CpJob J = pd_cp_job(p, p->V, p->wvec, p->gm + pd_gmres_done_index(MX));
+        cj[i] = J;
+        for (int b = 0; b < pd_cp_blocks(J, 1); ++b) c1map.push_back(make_int2(i, b));
+        for (int b = 0; b < pd_cp_blocks(J, 2); ++b) c2map.push_back(make_int2(i, b));
+        for (int b = 0; b < pd_cp_blocks(J, 3); ++b) c3map.push_back(make_int2(i, b));
+        if (p->cpl.k0sep) k0map.push_back(make_int2(i, 0));
+        cthreads2 = std::max(cthreads2, pd_cp_threads2(J));
+        clds1 = std::max(clds1, pd_cp_lds(J, 1));
+        clds2 = std::max(clds2, pd_cp_lds(J, 2));
+      } else {
+        for (int b = 0; b < t.nblk; ++b) tri0mapJ.push_back(make_int2(i, b));
+        for (int b = 0; b < (p->nbar + 255) / 256; ++b) redmapJ.push_back(make_int2(i, b));
+      }
     }
     // J-product jobs: same systems, mode 2, weights gamma_J, v = V_j
     std::vector<TriJob> tjJ = tj;
@@ -139,18 +167,35 @@ pd_status build_run(BatchRun &r, const pd_plan *plans, int count, const double *
       tjJ[i].in = nullptr;
       tjJ[i].skip = plans[i]->gm + pd_gmres_done_index(MX);
     }
+    // the k = 0 term of chunked-product problems that take it through the
+    // shifted-solve body: one block, the first item, weights at k = 0 only
+    std::vector<TriJob> tjK0 = tjJ;
+    for (int i = 0; i < count; ++i)
+      if (plans[i]->cp_on && plans[i]->cpl.k0sep) {
+        tjK0[i].gw = plans[i]->cp_tab + plans[i]->cpl.gJ0;
+        tjK0[i].nitems = 1;
+        tjK0[i].nblk = 1;
+      }
 
     auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
     size_t off = 0;
     const size_t o_fj = off; off = align(off + fj.size() * sizeof(FftJob));
     const size_t o_tj = off; off = align(off + tj.size() * sizeof(TriJob));
     const size_t o_tjJ = off; off = align(off + tjJ.size() * sizeof(TriJob));
+    const size_t o_tk0 = off; off = align(off + tjK0.size() * sizeof(TriJob));
+    const size_t o_k0 = off; off = align(off + k0map.size() * sizeof(int2));
     const size_t o_vj = off; off = align(off + vj.size() * sizeof(VecJob));
     const size_t o_fm = off; off = align(off + fftmap.size() * sizeof(int2));
     const size_t o_t0 = off; off = align(off + tri0map.size() * sizeof(int2));
     const size_t o_t1 = off; off = align(off + tri1map.size() * sizeof(int2));
     const size_t o_vm = off; off = align(off + vmap.size() * sizeof(int2));
     const size_t o_rm = off; off = align(off + redmap.size() * sizeof(int2));
+    const size_t o_t0J = off; off = align(off + tri0mapJ.size() * sizeof(int2));
+    const size_t o_rmJ = off; off = align(off + redmapJ.size() * sizeof(int2));
+    const size_t o_cj = off; off = align(off + cj.size() * sizeof(CpJob));
+    const size_t o_c1 = off; off = align(off + c1map.size() * sizeof(int2));
+    const size_t o_c2 = off; off = align(off + c2map.size() * sizeof(int2));
+    const size_t o_c3 = off; off = align(off + c3map.size() * sizeof(int2));
     const size_t o_act = off; off = align(off + count * sizeof(int));
     const size_t o_st = off; off = align(off + 4 * (size_t)count * sizeof(double));
     if (hipMalloc(&r.dev, off) != hipSuccess) {
@@ -171,23 +216,48 @@ pd_status build_run(BatchRun &r, const pd_plan *plans, int count, const double *
     put(o_fj, fj.data(), fj.size() * sizeof(FftJob));
     put(o_tj, tj.data(), tj.size() * sizeof(TriJob));
     put(o_tjJ, tjJ.data(), tjJ.size() * sizeof(TriJob));
+    put(o_tk0, tjK0.data(), tjK0.size() * sizeof(TriJob));
+    put(o_k0, k0map.data(), k0map.size() * sizeof(int2));
     put(o_vj, vj.data(), vj.size() * sizeof(VecJob));
     put(o_fm, fftmap.data(), fftmap.size() * sizeof(int2));
     put(o_t0, tri0map.data(), tri0map.size() * sizeof(int2));
     put(o_t1, tri1map.data(), tri1map.size() * sizeof(int2));
     put(o_vm, vmap.data(), vmap.size() * sizeof(int2));
     put(o_rm, redmap.data(), redmap.size() * sizeof(int2));
+    put(o_t0J, tri0mapJ.data(), tri0mapJ.size() * sizeof(int2));
+    put(o_rmJ, redmapJ.data(), redmapJ.size() * sizeof(int2));
+    put(o_cj, cj.data(), cj.size() * sizeof(CpJob));
+    put(o_c1, c1map.data(), c1map.size() * sizeof(int2));
+    put(o_c2, c2map.data(), c2map.size() * sizeof(int2));
+    put(o_c3, c3map.data(), c3map.size() * sizeof(int2));
     PD_HIP_CHECK(hipMemcpy(r.dev, host.data(), o_act, hipMemcpyHostToDevice));
     char *base = reinterpret_cast<char *>(r.dev);
     r.fj = reinterpret_cast<const FftJob *>(base + o_fj);
     r.tj = reinterpret_cast<const TriJob *>(base + o_tj);
     r.tjJ = reinterpret_cast<const TriJob *>(base + o_tjJ);
+    r.tk0 = reinterpret_cast<const TriJob *>(base + o_tk0);
+    r.k0m = reinterpret_cast<const int2 *>(base + o_k0);
+    r.nk0 = (int)k0map.size();
     r.vj = reinterpret_cast<const VecJob *>(base + o_vj);
     r.fm = reinterpret_cast<const int2 *>(base + o_fm);
     r.t0 = reinterpret_cast<const int2 *>(base + o_t0);
     r.t1 = reinterpret_cast<const int2 *>(base + o_t1);
     r.vm = reinterpret_cast<const int2 *>(base + o_vm);
     r.rm = reinterpret_cast<const int2 *>(base + o_rm);
+    r.t0J = reinterpret_cast<const int2 *>(base + o_t0J);
+    r.rmJ = reinterpret_cast<const int2 *>(base + o_rmJ);
+    r.cj = reinterpret_cast<const CpJob *>(base + o_cj);
+    r.c1m = reinterpret_cast<const int2 *>(base + o_c1);
+    r.c2m = reinterpret_cast<const int2 *>(base + o_c2);
+    r.c3m = reinterpret_cast<const int2 *>(base + o_c3);
+    r.n0J = (int)tri0mapJ.size();
+    r.nrJ = (int)redmapJ.size();
+    r.nc1 = (int)c1map.size();
+    r.nc2 = (int)c2map.size();
+    r.nc3 = (int)c3map.size();
+    r.cthreads2 = cthreads2;
+    r.clds1 = clds1;
+    r.clds2 = clds2;
     r.act = reinterpret_cast<int *>(base + o_act);
     r.st = reinterpret_cast<double *>(base + o_st);
     r.nf = (int)fftmap.size();
@@ -209,6 +279,17 @@ pd_status build_run(BatchRun &r, const pd_plan *plans, int count, const double *
     if (st_ != PD_OK) return st_; \
   } while (0)
 
+// w = J V_j for every problem still iterating: the per-frequency product
+// and its reduction, and the chunked capacitance product.
+pd_status j_products(const BatchRun &r, int j, const int *act, hipStream_t s) {
+  PD_B(pd_launch_tridiag_batch(r.prec, r.MR, 2, r.tjJ, r.t0J, r.n0J, r.tri_lds, act, j, s));
+  PD_B(pd_launch_reduce_batch(r.vj, r.rmJ, r.nrJ, j, act, s));
+  PD_B(pd_launch_tridiag_batch(r.prec, r.MR, 2, r.tk0, r.k0m, r.nk0, r.tri_lds, act, j, s));
+  PD_B(pd_cp_launch_batch(r.cj, r.c1m, r.nc1, r.c2m, r.nc2, r.cthreads2, r.c3m, r.nc3, r.clds1,
+                          r.clds2, act, j, s));
+  return PD_OK;
+}
+
 // The launch sequence of one batched solve with K GMRES iterations (no
 // synchronisation, no host data: capturable).
 pd_status enqueue_solve(const BatchRun &r, int K, double rtol, hipStream_t s) {
@@ -217,8 +298,7 @@ pd_status enqueue_solve(const BatchRun &r, int K, double rtol, hipStream_t s) {
   PD_B(pd_launch_reduce_batch(r.vj, r.rm, r.nr, -1, nullptr, s));
   PD_B(pd_gmres_batch_start(r.vj, r.count, r.MX, r.st, s));
   for (int j = 0; j < K; ++j) {
-    PD_B(pd_launch_tridiag_batch(r.prec, r.MR, 2, r.tjJ, r.t0, r.n0, r.tri_lds, nullptr, j, s));
-    PD_B(pd_launch_reduce_batch(r.vj, r.rm, r.nr, j, nullptr, s));
+    PD_B(j_products(r, j, nullptr, s));
     PD_B(pd_gmres_batch_arnoldi(r.vj, r.count, j, r.MX, rtol, r.st, nullptr, s));
   }
   PD_B(pd_gmres_batch_finish(r.vj, r.vm, r.nv, r.count, r.MX, nullptr, s));
@@ -248,8 +328,7 @@ pd_status finish_unconverged(const BatchRun &r, int K, double rtol) {
   if (nact == 0) return PD_OK;
   for (int j = K; j < r.MX && nact > 0; ++j) {
     PD_HIP_CHECK(hipMemcpyAsync(r.act, act.data(), r.count * sizeof(int), hipMemcpyHostToDevice, s));
-    PD_B(pd_launch_tridiag_batch(r.prec, r.MR, 2, r.tjJ, r.t0, r.n0, r.tri_lds, r.act, j, s));
-    PD_B(pd_launch_reduce_batch(r.vj, r.rm, r.nr, j, r.act, s));
+    PD_B(j_products(r, j, r.act, s));
     PD_B(pd_gmres_batch_arnoldi(r.vj, r.count, j, r.MX, rtol, r.st, r.act, s));
     PD_HIP_CHECK(hipMemcpyAsync(r.pin, r.st, 4 * (size_t)r.count * sizeof(double),
                                 hipMemcpyDeviceToHost, s));

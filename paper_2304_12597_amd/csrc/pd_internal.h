@@ -161,6 +161,41 @@ struct Line2DConfig {
   size_t lds = 0;
 };
 
+// The chunked capacitance product (capprod.hip): chunking and the offsets
+// (doubles) of its tables and workspace in one device buffer.
+struct CpLayout {
+  int m = 0, nc = 0, L = 0, N0 = 0, NL = 0;
+  int Q = 0;        // matrix-core steps over a chunk window (4 Q >= N0 + 2)
+  int NT = 0, NTc = 0, NH = 0;   // column tiles of 16 chunks, their chunks, blocks over them
+  int VL = 0;       // doubles of v staged in LDS
+  int G1 = 0;       // frequency groups of 4 (tables)
+  int G1run = 0;    // blocks of the first launch (G1, or G1 - 1 with the real pair)
+  int pair = 0;     // frequencies 0 and F2 - 1 share slot 0 of the first block
+  int k0sep = 0;    // frequency 0 goes through the shifted-solve kernel (see pd_cp_tables)
+  int MT = 0;       // row tiles of 16
+  int Sk = 0, KPS = 0, KPT = 0;  // frequency splits, frequencies per split, rows
+  int HLS = 0, NV = 0;   // last-chunk window; vector rows (last chunk's rows, chunks' last rows)
+  int local = 0;    // the chunk-local term is nonzero (some rho_i != 0)
+  size_t T1 = 0, hL = 0, red = 0, gk = 0, T3 = 0, c1 = 0, T4 = 0, L1h = 0, gJ0 = 0;
+  size_t tables = 0, U = 0, tiles = 0, vrow = 0, total = 0;
+};
+
+// One problem's capacitance-product launches (device-readable; the batched
+// launches read an array of them).
+struct CpJob {
+  int n = 0, F2 = 0, pair = 0, m = 0, nc = 0, L = 0, Q = 0, NTc = 0, VL = 0, MT = 0;
+  int Sk = 0, KPS = 0, KPT = 0, NH = 0, HLS = 0, S = 0;
+  double md = 0, ml = 0;
+  const double *v = nullptr;    // input (batched: the GMRES basis, v = V + jv n)
+  double *out = nullptr;        // J v
+  const double *T1 = nullptr, *T3 = nullptr, *T4 = nullptr, *L1h = nullptr;
+  const cpx<double> *hL = nullptr, *red = nullptr, *c1 = nullptr, *gk = nullptr;
+  cpx<double> *U = nullptr;
+  double *tiles = nullptr, *vrow = nullptr;
+  const double *skip = nullptr; // stop flag (nonzero: no product)
+  const double *extra = nullptr; // the k = 0 term added by the last launch, or null
+};
+
 struct pd_plan_s {
   int n = 0, ell = 0, dims = 1, nbar = 0, F2 = 0;
   double tau = 0, alpha = 1, w = 1;   // w = alpha^(1/ell)
@@ -241,6 +276,11 @@ struct pd_plan_s {
   double *bdf_g = nullptr;     // BDF: [s][F2] complex weight_f gamma_f^(k)
   double *bdf_h = nullptr;     // BDF 2D: [ell][nbar] h before the DST along x
   double *bdf_t = nullptr;     // BDF 2D: [s][nbar] rows in the DST-x domain
+  // chunked capacitance product (1D, symmetric Toeplitz M and tau K): tables
+  // and workspace in one buffer laid out by cpl
+  int cp_on = 0;
+  CpLayout cpl;
+  double *cp_tab = nullptr;
 };
 constexpr int PD_BDF_GCH = 16;   // frequency chunks of the BDF capacitance product
 
@@ -294,6 +334,26 @@ int pd_dst_blocks(pd_plan p);
 pd_status pd_launch_reduce_partials(pd_plan p, const double *base,
                                     double *out);
 pd_status pd_capacitance_apply_impl(pd_plan p, const double *v, double *Jv);
+// the chunked capacitance product (capprod.hip)
+void pd_cp_chunking(int n, int *m, int *nc, int *L);
+bool pd_cp_eligible(int n, int dims, int bdf_s, bool uniform, const double *uni);
+CpLayout pd_cp_layout(int n, int F2);
+void pd_cp_tables(pd_plan p, std::vector<double> &tab);
+bool pd_cp_fits(int n, int F2, size_t max_lds);
+void pd_cp_set_attributes(size_t max_lds);
+pd_status pd_cp_apply(pd_plan p, const double *v, double *Jv);
+// The job of plan p (input v, output Jv, stop flag skip) and, for batches,
+// its launches' block counts (launch 1, 2, 3), block size of launch 2 and
+// dynamic LDS bytes of launches 1 and 2.
+CpJob pd_cp_job(pd_plan p, const double *v, double *Jv, const double *skip);
+// k = 0 J-product term by one block of the shifted-solve kernel (partials row 0)
+pd_status pd_launch_j_first_item(pd_plan p, const double *v, const double *gw);
+int pd_cp_blocks(const CpJob &J, int launch);
+int pd_cp_threads2(const CpJob &J);
+size_t pd_cp_lds(const CpJob &J, int launch);
+pd_status pd_cp_launch_batch(const CpJob *jobs, const int2 *map1, int nb1, const int2 *map2,
+                             int nb2, int threads2, const int2 *map3, int nb3, size_t lds1,
+                             size_t lds2, const int *active, int jv, hipStream_t s);
 pd_status pd_gmres(pd_plan p, const double *b, double *x, double rtol,
                    int *iters, double *relres);
 pd_status pd_residual_impl(pd_plan p, const double *u0, const double *F,

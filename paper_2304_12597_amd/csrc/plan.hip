@@ -122,7 +122,7 @@ void free_plan(pd_plan p) {
   void *ptrs[] = {p->coef64, p->coef32, p->lam64, p->lam32, p->gB64, p->gJ64, p->tw64,
                   p->tw32, p->dal, p->fac64, p->fac32, p->twd, p->wreal, p->spec, p->partials, p->rstage, p->bvec, p->xvec, p->wvec, p->V,
                   p->gm, p->red, p->sine_q, p->sine_wN, p->sine_twH, p->sine_m, p->sine_k,
-                  p->fom, p->fom_h, p->wz, p->bdf_g, p->bdf_h, p->bdf_t};
+                  p->fom, p->fom_h, p->wz, p->bdf_g, p->bdf_h, p->bdf_t, p->cp_tab};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   if (p->host_pin) (void)hipHostFree(p->host_pin);
@@ -139,11 +139,12 @@ struct Layout {
   size_t coef = 0, lam = 0, tw = 0, dal = 0, fac = 0, twd = 0, wreal = 0, wz = 0, bdfg = 0,
          bdfh = 0, bdft = 0, sine = 0, fom = 0;
   size_t fom_h_bytes = 0;
+  size_t cp = 0;   // chunked capacitance product: tables + workspace (doubles)
   size_t spec_bytes = 0, partials = 0, rstage = 0, vec = 0, V = 0, gm = 0, red = 0;
   size_t total_bytes() const {
     return coef * 12 + lam * 12 + 2 * lam * 8 + tw * 12 + dal * 8 + fac * 12 + twd * 8 +
            wreal * 8 + wz * 8 + bdfg * 8 + bdfh * 8 + bdft * 8 + spec_bytes + partials * 8 + rstage * 8 + 3 * vec * 8 + V * 8 + gm * 8 +
-           red * 8 + sine * 8 + fom * 8 + fom_h_bytes;
+           red * 8 + sine * 8 + fom * 8 + fom_h_bytes + cp * 8;
   }
 };
 
@@ -238,6 +239,14 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
       L.bdfh = (size_t)ell * p->nbar;
       L.bdft = (size_t)p->bdf_s * p->nbar;
     }
+  }
+  // float64 plans only: the reduced-precision forms keep their J-product in
+  // the passes' own precision
+  if (p->prec == PD_FP64 && pd_cp_eligible(n, p->dims, p->bdf_s, p->uniform, p->uni) &&
+      pd_cp_fits(n, F2, max_lds)) {
+    p->cp_on = 1;
+    p->cpl = pd_cp_layout(n, F2);
+    L.cp = p->cpl.total;
   }
   L.coef = 6 * (size_t)n;
   L.lam = 2 * (size_t)F2;
@@ -499,6 +508,7 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
     pd_fft_batch_set_attributes(g_max_lds);
     pd_tri_batch_set_attributes(g_max_lds);
     pd_sine_set_attributes(g_max_lds);
+    pd_cp_set_attributes(g_max_lds);
     g_attr_device = p->device;
   }
   const size_t max_lds = g_max_lds;
@@ -702,6 +712,8 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
       }
     }
   }
+  std::vector<double> cptab;
+  if (p->cp_on) pd_cp_tables(p, cptab);
   const size_t nbar = p->nbar;
   p->spec_bytes = L.spec_bytes;
   p->bytes = L.total_bytes();
@@ -744,6 +756,7 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   PD_TRY(dev_alloc(&p->V, L.V));
   PD_TRY(dev_alloc(&p->gm, pd_gmres_state_doubles(p->maxit)));
   PD_TRY(dev_alloc(&p->red, L.red));
+  if (p->cp_on) PD_TRY(dev_alloc(&p->cp_tab, L.cp));
   if (p->krylov == PD_KRYLOV_FOM) {
     PD_TRY(dev_alloc(&p->fom, L.fom));
     PD_TRY(dev_alloc(reinterpret_cast<unsigned char **>(&p->fom_h), L.fom_h_bytes));
@@ -779,6 +792,7 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
   PD_TRY(upload(p->fac64, fac, p->stream));
   PD_TRY(upload(p->fac32, fac32, p->stream));
   PD_TRY(upload(p->twd, twd, p->stream));
+  if (p->cp_on) PD_TRY(upload(p->cp_tab, cptab, p->stream));
   if (p->bdf_s > 1) PD_TRY(upload(p->bdf_g, bg_gt, p->stream));
   if (p->krylov == PD_KRYLOV_FOM) {
     std::vector<double> mf;

@@ -909,8 +909,16 @@ void launch_pipe(pd_plan p, int G, int nitems, const Coef<R> &cf, const R *lam,
   }
 }
 
+// Launch overrides for the J-product of frequency 0 alone (one block, the
+// first item, the given weights): 0 / nullptr keep the plan's own.
+struct TriOverride {
+  int G = 0, nitems = 0;
+  const double *gw = nullptr;
+};
+
 template <typename R, int MR, bool UNI>
-pd_status launch_mr(pd_plan p, int mode, const void *in, const double *xv, void *out) {
+pd_status launch_mr(pd_plan p, int mode, const void *in, const double *xv, void *out,
+                    const TriOverride &ov = TriOverride{}) {
   const TriConfig &T = p->tri;
   const int n = p->n;
   Coef<R> cf;
@@ -925,13 +933,14 @@ pd_status launch_mr(pd_plan p, int mode, const void *in, const double *xv, void 
                                   : reinterpret_cast<const R *>(p->lam32);
   const cpx<R> *fac = (sizeof(R) == 8) ? reinterpret_cast<const cpx<R> *>(p->fac64)
                                        : reinterpret_cast<const cpx<R> *>(p->fac32);
-  const int nitems = pd_tri_nitems(T, p->F2);
+  const int nitems = ov.nitems > 0 ? ov.nitems : pd_tri_nitems(T, p->F2);
   const cpx<R> *cin = reinterpret_cast<const cpx<R> *>(in);
   cpx<R> *cout = reinterpret_cast<cpx<R> *>(out);
   const int has_mass = (mode & 0x100) ? 1 : 0;
   mode &= 0xff;
-  const int G = (mode == 1) ? nitems : (nitems < p->tri_G ? nitems : p->tri_G);
-  const double *gw = (mode == 2) ? p->gJ64 : p->gB64;
+  const int Gn = (mode == 1) ? nitems : (nitems < p->tri_G ? nitems : p->tri_G);
+  const int G = ov.G > 0 ? ov.G : Gn;
+  const double *gw = ov.gw ? ov.gw : ((mode == 2) ? p->gJ64 : p->gB64);
   const double *vin = (mode == 2) ? reinterpret_cast<const double *>(in) : nullptr;
   if (mode == 2) {
     cin = nullptr;
@@ -939,7 +948,7 @@ pd_status launch_mr(pd_plan p, int mode, const void *in, const double *xv, void 
   const double *x = (mode == 1) ? xv : nullptr;
   cpx<R> *o = (mode == 1) ? cout : nullptr;
   double *part = (mode == 1) ? nullptr : p->partials;
-  const int Gp = nitems < p->tri_G ? nitems : p->tri_G;   // pipelined body: every mode
+  const int Gp = ov.G > 0 ? ov.G : (nitems < p->tri_G ? nitems : p->tri_G);   // pipelined body: every mode
   if (UNI && T.pipe && MR == 16 && T.spb != 1) {
     // the 16-row body pairs the real shifts in block 0's prologue: one
     // system per block
@@ -1022,16 +1031,17 @@ TriConfig pd_choose_tri_mr(int n, int F2, int prec, size_t max_lds, int MR) {
 }
 
 template <bool UNI>
-pd_status dispatch(pd_plan p, int mode, const void *in, const double *xv, void *out) {
+pd_status dispatch(pd_plan p, int mode, const void *in, const double *xv, void *out,
+                   const TriOverride &ov = TriOverride{}) {
   const int MR = p->tri.MR;
   if (p->prec == PD_FP64) {
-    if (MR == 4) return launch_mr<double, 4, UNI>(p, mode, in, xv, out);
-    if (MR == 8) return launch_mr<double, 8, UNI>(p, mode, in, xv, out);
-    if (MR == 16) return launch_mr<double, 16, UNI>(p, mode, in, xv, out);
+    if (MR == 4) return launch_mr<double, 4, UNI>(p, mode, in, xv, out, ov);
+    if (MR == 8) return launch_mr<double, 8, UNI>(p, mode, in, xv, out, ov);
+    if (MR == 16) return launch_mr<double, 16, UNI>(p, mode, in, xv, out, ov);
   } else {
-    if (MR == 4) return launch_mr<float, 4, UNI>(p, mode, in, xv, out);
-    if (MR == 8) return launch_mr<float, 8, UNI>(p, mode, in, xv, out);
-    if (MR == 16) return launch_mr<float, 16, UNI>(p, mode, in, xv, out);
+    if (MR == 4) return launch_mr<float, 4, UNI>(p, mode, in, xv, out, ov);
+    if (MR == 8) return launch_mr<float, 8, UNI>(p, mode, in, xv, out, ov);
+    if (MR == 16) return launch_mr<float, 16, UNI>(p, mode, in, xv, out, ov);
   }
   pd_set_error("unsupported tridiagonal configuration");
   return PD_ENOTSUP;
@@ -1041,6 +1051,19 @@ pd_status pd_launch_tridiag(pd_plan p, int mode, const void *in, const double *x
   if (p->dims == 2) return pd_launch_line2d(p, mode, in, xv, out);
   return p->uniform ? dispatch<true>(p, mode, in, xv, out)
                     : dispatch<false>(p, mode, in, xv, out);
+}
+
+// gw-weighted J-product terms of the first item's frequencies (slot 0 first)
+// by one block of the plan's own shifted-solve kernel, into partials[0 .. n):
+// with weights nonzero at k = 0 only, the k = 0 term computed exactly as the
+// passes compute their k = 0 solves.
+pd_status pd_launch_j_first_item(pd_plan p, const double *v, const double *gw) {
+  TriOverride ov;
+  ov.G = 1;
+  ov.nitems = 1;
+  ov.gw = gw;
+  return p->uniform ? dispatch<true>(p, 2, v, nullptr, nullptr, ov)
+                    : dispatch<false>(p, 2, v, nullptr, nullptr, ov);
 }
 
 // Elimination factors of the uniform path (float64), 6 complex values per
@@ -1088,6 +1111,7 @@ pd_status pd_launch_reduce_partials(pd_plan p, const double *base, double *out) 
 
 pd_status pd_capacitance_apply_impl(pd_plan p, const double *v, double *Jv) {
   if (p->bdf_s > 1) return pd_bdf_apply(p, v, Jv);
+  if (p->cp_on) return pd_cp_apply(p, v, Jv);
   pd_status st = pd_launch_tridiag(p, 2, v, nullptr, nullptr);
   if (st != PD_OK) return st;
   return pd_launch_reduce_partials(p, v, Jv);

@@ -173,3 +173,219 @@ def test_unclamped_neighbour_read_is_caught():
     assert (s0 > n).any()
     bad_right = s0 + MR
     assert bad_right.max() >= n
+
+
+# ------------------------------------------- chunked capacitance product --
+
+def cp_chunking(n):
+    """pd_cp_chunking: nc <= 64 chunks of m rows (m odd, >= 3), the last one
+    2..m+1 rows."""
+    m = max(3, (n + 63) // 64)
+    if m % 2 == 0:
+        m += 1
+    nc = (n + m - 1) // m
+    L = n - (nc - 1) * m
+    if L == 1 and nc > 1:
+        nc -= 1
+        L = m + 1
+    return m, nc, L
+
+
+CP_SPLITS, CP_KW, CP_VW, CP_UW, CP_PF, CP1_WAVES = 16, 4, 2, 66, 36, 5
+
+
+def cp_layout(n, F2, ell=None):
+    """pd_cp_layout and the pairing choice of pd_cp_tables (csrc/capprod.hip):
+    launch shapes and table sizes."""
+    m, nc, L = cp_chunking(n)
+    c = dict(m=m, nc=nc, L=L, N0=m - 1, NL=L - 1)
+    c["Q"] = (c["N0"] + 2 + 3) // 4
+    c["NT"] = (nc + 15) // 16
+    c["NTc"] = 16 * c["NT"]
+    c["NH"] = c["NT"] // 2 if c["NT"] % 2 == 0 else c["NT"]
+    c["VL"] = (max(n + 3, (c["NTc"] - 1) * m + 4 * c["Q"] + 2) + 1) & ~1
+    c["G1"] = (F2 + 3) // 4
+    ell = 2 * (F2 - 1) if ell is None else ell
+    c["pair"] = ell % 2 == 0 and F2 >= 5 and (F2 - 1) % 4 == 0
+    c["G1run"] = (F2 - 1) // 4 if c["pair"] else c["G1"]
+    c["MT"] = (c["N0"] + 15) // 16
+    c["Sk"] = CP_SPLITS - 1
+    c["KPS"] = (F2 + c["Sk"] - 1) // c["Sk"]
+    c["KPT"] = max(4 * c["G1"], c["Sk"] * c["KPS"])
+    c["HLS"] = c["NL"] + 2
+    c["NV"] = c["NL"] + nc
+    c["sizes"] = dict(T1=c["G1"] * c["Q"] * 64, hL=4 * c["G1"] * c["HLS"], red=8 * F2,
+                      gk=c["KPT"], T3=c["MT"] * c["KPT"] * 64, c1=c["KPT"] * c["NL"],
+                      T4=c["MT"] * c["Q"] * 64, L1h=c["NL"] * (c["NL"] + 2),
+                      U=c["KPT"] * CP_UW, tiles=CP_SPLITS * c["MT"] * 16 * c["NTc"],
+                      vrow=CP_SPLITS * c["NV"])
+    return c
+
+
+def cp_sidx(t, gq, Q):
+    """cp_sidx: window index of matrix-core step t for lane group gq."""
+    B16 = Q >> 4
+    t = np.asarray(t)
+    R = Q - (B16 << 4)
+    full = ((t >> 4) << 6) + (gq << 4) + (t & 15)
+    part = (B16 << 6) + R * gq + (t - (B16 << 4))
+    return np.where(t < (B16 << 4), full, part)
+
+
+def check_cp(n, F2, max_lds=160 * 1024):
+    """cp_freq_kernel / cp_out_kernel / cp_sum_kernel (csrc/capprod.hip):
+    every LDS, table, workspace and output index is in range, the window and
+    frequency contractions cover what they must, and the sum launch writes
+    every output row exactly once.  False when the plan would not use them."""
+    c = cp_layout(n, F2)
+    m, nc, L, N0, NL = c["m"], c["nc"], c["L"], c["N0"], c["NL"]
+    Q, NT, NTc, NH, VL = c["Q"], c["NT"], c["NTc"], c["NH"], c["VL"]
+    MT, Sk, KPS, KPT, NV = c["MT"], c["Sk"], c["KPS"], c["KPT"], c["NV"]
+    sz = c["sizes"]
+    assert m % 2 == 1 and 1 <= nc <= 64 and 2 <= L <= m + 1 and (nc - 1) * m + L == n
+    assert 4 * Q >= N0 + 2 and NTc >= nc and NTc <= 64 and 16 * MT >= N0
+    lds1 = (VL + CP1_WAVES * 64 * 4) * 8
+    lds2 = VL * 8 + (CP_KW - 1) * 2 * 64 * 32
+    if lds1 > max_lds or lds2 > max_lds:
+        return False            # pd_cp_fits: the plan takes the per-frequency path
+    lane = np.arange(64)
+    gq, cl = lane >> 4, lane & 15
+    # the window mapping is a bijection onto [0, 4Q)
+    s_all = np.concatenate([cp_sidx(np.arange(Q), g, Q) for g in range(4)])
+    assert np.array_equal(np.sort(s_all), np.arange(4 * Q))
+    # v staging, both alignments: vs[o + i] = v[i], pairs at vs[2 + 2p],
+    # zeros in [0, o) and [o + n, VL); every entry written once
+    for sh in (0, 1):
+        o = 2 - sh
+        npairs = (n - sh) // 2
+        w = np.zeros(VL, dtype=np.int64)
+        p = np.arange(npairs)
+        assert (sh + 2 * p + 1).max(initial=0) < n
+        np.add.at(w, 2 + 2 * p, 1)
+        np.add.at(w, 3 + 2 * p, 1)
+        if sh:
+            w[o] += 1
+        if (n - sh) & 1:
+            w[o + n - 1] += 1
+        w[:o] += 1
+        w[o + n:] += 1
+        assert (w == 1).all() and o + n <= VL
+        # windows (o - 1 + c m + s, s < 4Q) and the reduced system's rows
+        col = np.arange(NTc)
+        assert (o - 1 + col.max() * m + 4 * Q - 1) < VL
+        assert (o - 1 + (nc - 1) * m + NL + 1) < VL
+        lc = np.minimum(lane, nc - 1)
+        i = np.where(lc == nc - 1, n - 1, lc * m + N0)
+        assert (o + i - 1).min() >= 0 and (o + i + 1).max() < VL and (i[:nc] < n).all()
+    # ---- launch 1 (G1run blocks x 5 waves) ----
+    pair, G1run = c["pair"], c["G1run"]
+    Fs = F2 - 1 if pair else F2
+    kseen = np.zeros(F2, dtype=np.int64)
+    for blk in range(G1run):
+        for wave in range(CP1_WAVES):
+            if wave < 4:
+                kw = 4 * blk + wave if 4 * blk + wave < Fs else -1
+            else:
+                kw = F2 - 1 if (pair and blk == 0) else -1
+            if kw >= 0:
+                kseen[kw] += 1
+            kq = kw if kw >= 0 else 4 * blk
+            assert 0 <= kq < F2 and kq * 8 + 7 < sz["red"]
+            assert (kq * c["HLS"] + NL + 1) < sz["hL"]
+            if kw >= 0:
+                assert kw * CP_UW + CP_UW - 1 < sz["U"]
+        assert (blk * Q + Q - 1) * 64 + 63 < sz["T1"]
+        # Ex: [CP1_WAVES][64][4] after vs
+        assert ((CP1_WAVES - 1) * 64 + 63) * 4 + 3 < CP1_WAVES * 64 * 4
+    assert (kseen == 1).all()                  # every frequency once
+    if pair:
+        assert 4 * G1run + 1 == F2 and G1run <= c["G1"]
+    # ---- launch 2 (MT x S x NH blocks) ----
+    for local in (0, 1):
+        S = Sk + local
+        TPB = NT // NH
+        nmw = TPB * CP_KW
+        assert nmw + CP_VW <= 2 * CP_KW + CP_VW and TPB * NH == NT and TPB <= 2
+        assert Sk * KPS >= F2 and KPT >= Sk * KPS and KPT >= 4 * c["G1"]
+        grid = MT * S * NH
+        blocks = {(b % NH, (b // NH) % MT, b // (NH * MT)) for b in range(grid)}
+        assert len(blocks) == grid
+        qs = (KPS + CP_KW - 1) // CP_KW
+        for sp in sorted({0, Sk - 1}):
+            covered = []
+            for kh in range(CP_KW):
+                kb = min(kh * qs, KPS)
+                ke = min(kb + qs, KPS)
+                ka = sp * KPS + kb
+                cnt = ke - kb
+                covered += list(range(ka, ka + cnt))
+                if cnt == 0:
+                    continue
+                assert ka + cnt <= (sp + 1) * KPS <= KPT
+                assert ((MT - 1) * KPT + ka + cnt - 1) * 64 + 63 < sz["T3"]
+                for nh in range(NH):
+                    for tl in range(TPB):
+                        col = (nh * TPB + tl) * 16 + cl
+                        pb = ((ka + cnt - 1) * CP_UW + col + (gq >> 1)) * 2 + (gq & 1)
+                        assert pb.max() < 2 * sz["U"] and col.max() + 1 < CP_UW
+            # the quarters cover the split's frequencies once
+            assert covered == list(range(sp * KPS, sp * KPS + KPS))
+            # vector rows: each rho < NV once per split over its MT NH blocks
+            NB = MT * NH
+            seen = np.zeros(NV, dtype=np.int64)
+            for b in range(NB):
+                j0 = 0
+                while b + j0 * NB < NV:
+                    for vw in range(CP_VW):
+                        rho = b + (j0 + 4 * vw + (lane >> 4)) * NB
+                        ok = (rho < NV) & ((lane & 15) == 0)
+                        np.add.at(seen, rho[ok], 1)
+                    j0 += 4 * CP_VW
+            assert (seen == 1).all()
+            kg = np.arange(16)
+            nit = (KPS - kg + 15) >> 4          # groups with nit = 0 load nothing
+            kmax = (sp * KPS + kg + 16 * (nit - 1))[nit > 0]
+            assert kmax.max() < KPT
+            assert ((kmax.max() * NL + NL - 1) < sz["c1"]) and kmax.max() * CP_UW + nc < sz["U"]
+            assert kmax.max() < sz["gk"]
+            ks = np.sort(np.concatenate([sp * KPS + g + 16 * np.arange(nit[g]) for g in kg]))
+            assert np.array_equal(ks, np.arange(sp * KPS, sp * KPS + KPS))
+        if local:
+            assert ((MT - 1) * Q + Q - 1) * 64 + 63 < sz["T4"]
+            assert (NL - 1) * (NL + 2) + NL + 1 < sz["L1h"] or NL == 0
+        assert ((CP_KW - 2) * TPB + TPB - 1) * 64 + 63 < (CP_KW - 1) * 2 * 64
+        # ---- launch 3: every output row exactly once ----
+        hits = np.zeros(n, dtype=np.int64)
+        nt = MT * 16 * NTc
+        it = np.arange(nt)
+        mt_, e = it // (16 * NTc), it % (16 * NTc)
+        r_, c_ = e // NTc, e % NTc
+        s_ = 16 * mt_ + r_
+        ok = (c_ < nc - 1) & (s_ < N0)
+        np.add.at(hits, (c_ * m + s_)[ok], 1)
+        assert ((S - 1) * nt + it.max()) < sz["tiles"]
+        rho = np.arange(NV)
+        i = np.where(rho < NL, (nc - 1) * m + rho,
+                     np.where(rho - NL == nc - 1, n - 1, (rho - NL) * m + N0))
+        assert i.min() >= 0 and i.max() < n
+        np.add.at(hits, i, 1)
+        assert ((S - 1) * NV + NV - 1) < sz["vrow"]
+        assert (hits == 1).all()
+    return True
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6, 7, 63, 64, 65, 127, 128, 129, 130, 255, 1000,
+                               4095, 4097, 8191, 8192, 12759, 16383, 16384, 18000, 20000])
+def test_chunked_capacitance_indices(n):
+    for ell in (2, 16, 2048):
+        check_cp(n, ell // 2 + 1)
+
+
+def test_chunked_capacitance_headline_fits():
+    # the 1D FEM workload of the headline (n = 8191, ell = 2048) runs on it
+    assert check_cp(8191, 1025)
+
+
+def test_chunked_capacitance_ensemble_shapes():
+    for n in sorted({n for n, _ in ensemble_shapes()}):
+        check_cp(n, 33)
