@@ -36,7 +36,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="fem1d",
-                    choices=["fem1d", "ensemble", "serve", "alpha", "fom", "bdf"])
+                    choices=["fem1d", "ensemble", "serve", "alpha", "fom", "bdf", "fd2d"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--count", type=int, default=0, help="ensemble / stream size")
@@ -93,6 +93,14 @@ def main():
         return
     if args.workload == "bdf":
         print(json.dumps(bench_bdf(args, torch, pd, wl, dev)))
+        return
+    if args.workload == "fd2d":
+        # the 2D rows alone (the forms of --forms among fp64 and mixed), e.g.
+        # for a kernel trace of one form
+        rows = bench_2d(args, torch, pd, wl, dev, forms_sel=args.forms.split(","))
+        for r in rows["forms"].values():
+            r.pop("_sample", None)
+        print(json.dumps(rows))
         return
     stream = torch.cuda.current_stream(dev)
     prob = wl.cfg_fem_1d()
@@ -713,7 +721,7 @@ def bench_bdf(args, torch, pd, wl, dev):
     return out
 
 
-def bench_2d(args, torch, pd, wl, dev):
+def bench_2d(args, torch, pd, wl, dev, forms_sel=("fp64", "mixed")):
     """The 2D workload (511 x 511 grid, ell = 256, T = 0.1): float64 and mixed
     forms, inputs resident in HBM, `steps` timed solves each.  Sampled outputs
     are kept for the cpu_baseline leg's error check."""
@@ -729,6 +737,8 @@ def bench_2d(args, torch, pd, wl, dev):
     steps = max(1, min(args.steps, 10))
     forms = {}
     for form, prec in (("fp64", pd.PD_FP64), ("mixed", pd.PD_MIXED)):
+        if form not in forms_sel:
+            continue
         plan = pd.paradiag_plan_create(p.n, p.ell, p.tau, None, p.K, dims=2, precision=prec,
                                        stream=stream.cuda_stream)
         try:

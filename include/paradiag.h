@@ -180,11 +180,17 @@ pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double tau,
 pd_status paradiag_solve(pd_plan plan, const double *u0, const double *F,
                          double *U, double tol, pd_info *info);
 
-/* Solve `count` independent problems, each with its own plan, in one
- * submission: every stage is launched once for all problems of a
- * (precision, dims) group.  Arrays as in paradiag_solve, one per problem;
- * plans must not repeat.  infos may be NULL.  Synchronises the stream of
- * plans[0], which all work is enqueued on. */
+/* Solve `count` independent problems, each with its own plan.  Plans that
+ * batch together -- 1D, uniform grid, float64 or float32 (not PD_MIXED),
+ * backward Euler with the GMRES capacitance solver, the same precision and
+ * maxit, no repeats -- form groups, and every stage of a group is one launch
+ * for all of its problems (lockstep GMRES, each problem stopping on its own
+ * convergence flag; a group's results equal the problems' results solved
+ * alone, bit for bit).  Every other problem (2D, PD_MIXED, non-uniform
+ * grids, BDF, the sine basis, Algorithm 2) and any group of one is solved
+ * with paradiag_solve, one after another.  Arrays as in paradiag_solve, one
+ * per problem.  infos may be NULL.  Synchronises each group's first plan's
+ * stream. */
 pd_status paradiag_solve_batch(const pd_plan *plans, int count,
                                const double *const *u0,
                                const double *const *F, double *const *U,

@@ -9,6 +9,8 @@
 // transform and the correction added in the inverse transform's epilogue.
 #include "pd_internal.h"
 
+#include <algorithm>
+
 #include <cmath>
 
 // Forward stage for 1D or 2D plans.  residual = 0: transform h from (u0, F);
@@ -318,9 +320,59 @@ extern "C" pd_status paradiag_solve_batch(const pd_plan *plans, int count, const
     return PD_EINVAL;
   }
   if (pd_batchable(plans, count)) return pd_solve_batch_impl(plans, count, u0, F, U, tol, infos);
-  // other groups (2D, mixed precision, non-uniform grids): one after another
-  pd_status worst = PD_OK;
+  // Split into groups that batch together (1D, uniform, same precision and
+  // iteration limit; see pd_batchable), each solved in one submission; the
+  // rest (2D, mixed precision, non-uniform grids, BDF, the sine basis,
+  // Algorithm 2, repeated plans) one after another.
+  std::vector<int> rest;
+  std::vector<std::vector<int>> groups;
   for (int i = 0; i < count; ++i) {
+    bool placed = false;
+    if (pd_batchable(&plans[i], 1)) {
+      for (auto &g : groups) {
+        std::vector<pd_plan> trial;
+        trial.push_back(plans[g[0]]);
+        trial.push_back(plans[i]);
+        bool dup = false;
+        for (int j : g) dup = dup || plans[j] == plans[i];
+        if (!dup && pd_batchable(trial.data(), 2)) {
+          g.push_back(i);
+          placed = true;
+          break;
+        }
+      }
+      if (!placed) {
+        groups.push_back({i});
+        placed = true;
+      }
+    }
+    if (!placed) rest.push_back(i);
+  }
+  pd_status worst = PD_OK;
+  for (const auto &g : groups) {
+    if (g.size() == 1) {
+      rest.push_back(g[0]);
+      continue;
+    }
+    std::vector<pd_plan> gp;
+    std::vector<const double *> gu, gf;
+    std::vector<double *> gU;
+    std::vector<pd_info> gi(g.size());
+    for (int i : g) {
+      gp.push_back(plans[i]);
+      gu.push_back(u0[i]);
+      gf.push_back(F[i]);
+      gU.push_back(U[i]);
+    }
+    const pd_status st = pd_solve_batch_impl(gp.data(), (int)g.size(), gu.data(), gf.data(),
+                                             gU.data(), tol, infos ? gi.data() : nullptr);
+    if (st != PD_OK && st != PD_ENOTCONV) return st;
+    if (st == PD_ENOTCONV) worst = PD_ENOTCONV;
+    if (infos)
+      for (size_t t = 0; t < g.size(); ++t) infos[g[t]] = gi[t];
+  }
+  std::sort(rest.begin(), rest.end());
+  for (int i : rest) {
     pd_status st = paradiag_solve(plans[i], u0[i], F[i], U[i], tol, infos ? &infos[i] : nullptr);
     if (st != PD_OK && st != PD_ENOTCONV) return st;
     if (st == PD_ENOTCONV) worst = PD_ENOTCONV;

@@ -167,6 +167,33 @@ def test_solve_batch_matches_individual(lib):
         assert err < fp64_error_bound(p, 1e-10), (p.kind, p.n, p.ell, p.nu, err)
 
 
+def test_solve_batch_groups_a_mixed_list(lib):
+    """A list mixing batchable 1D float64 problems, 2D problems and a mixed-
+    precision plan: the 1D float64 problems go through one batched
+    submission, the rest one by one; every result equals the problem solved
+    alone bit for bit, and every info is filled."""
+    probs = mixed_problems(11)
+    precs = [0] * len(probs)
+    precs[0] = 1                          # one mixed-precision plan in the list
+    alone = [solve_alone(lib, p, prec) for p, prec in zip(probs, precs)]
+    s = torch.cuda.current_stream().cuda_stream
+    plans = [lib.paradiag_plan_create(p.n, p.ell, p.tau, p.M, p.K, dims=p.dims, precision=prec,
+                                      stream=s) for p, prec in zip(probs, precs)]
+    try:
+        u0s = [T(p.u0) for p in probs]
+        Fs = [T(p.F) for p in probs]
+        Us = [torch.empty((p.ell, p.nbar), dtype=torch.float64, device=dev()) for p in probs]
+        infos = lib.paradiag_solve_batch(plans, u0s, Fs, Us, 1e-10)
+        torch.cuda.synchronize()
+    finally:
+        for pl in plans:
+            lib.paradiag_plan_destroy(pl)
+    assert sum(1 for p, pr in zip(probs, precs) if p.dims == 1 and pr == 0) >= 3
+    for p, U, Ua, info in zip(probs, Us, alone, infos):
+        assert np.array_equal(U.cpu().numpy(), Ua), (p.kind, p.n, p.ell, p.dims)
+        assert info.gmres_iters >= 1 and info.sweeps >= 1
+
+
 def test_solve_batch_graph_replays(lib):
     """The first batched call runs eagerly and records each plan's GMRES
     iteration count; the second captures the whole solve as a HIP graph and
