@@ -143,6 +143,23 @@ __device__ __forceinline__ void pd_wait_all() {
   __builtin_amdgcn_s_waitcnt(0);
 #endif
 }
+// Block barrier for data exchanged through LDS by ds_read / ds_write only.
+// __syncthreads() is a release/acquire fence as well, so it waits for every
+// outstanding vector-memory operation of the wave -- including a
+// global_load_lds prefetch into a different LDS area, which then no longer
+// overlaps anything.  This barrier waits only for the wave's LDS accesses
+// (lgkmcnt(0); vmcnt and expcnt left at their maxima in the gfx9 encoding)
+// and keeps the compiler from moving memory accesses across it.  LDS that a
+// prefetch writes must still be read only after pd_wait_all() and a full
+// barrier.
+__device__ __forceinline__ void pd_lds_barrier() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+#endif
+}
 
 // ---------------------------------------------------------------------------
 // plan

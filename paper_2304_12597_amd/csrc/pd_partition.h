@@ -20,7 +20,10 @@
 //
 // Every thread of the block must call this together (it contains block
 // barriers); on entry the block may still be reading its staging area, which
-// xch is allowed to alias.
+// xch is allowed to alias.  LB: the barriers only order LDS accesses
+// (pd_lds_barrier), so that a global_load_lds prefetch issued before the call
+// keeps streaming in; for callers whose xch does not alias LDS that such a
+// prefetch writes.
 #pragma once
 #include "pd_internal.h"
 
@@ -55,10 +58,16 @@ struct DualOps {
   static __device__ __forceinline__ cpx<R> one() { return cpx<R>{R(1), R(1)}; }
 };
 
-template <typename R, int MR, typename A = CplxOps<R>>
+template <typename R, int MR, typename A = CplxOps<R>, bool LB = false>
 __device__ __forceinline__ void partition_solve(cpx<R> (&d)[MR], int len, int lt, int P,
                                                 const cpx<R> *lfac, Row3<R> *xch,
                                                 cpx<R> ca, cpx<R> cc) {
+  auto barrier = [] {
+    if constexpr (LB)
+      pd_lds_barrier();
+    else
+      __syncthreads();
+  };
   const cpx<R> zero = {R(0), R(0)};
   const int L2 = len < 2 ? 2 : len;   // a lone row gets a zero pad row
   cpx<R> ud = zero;
@@ -86,9 +95,9 @@ __device__ __forceinline__ void partition_solve(cpx<R> (&d)[MR], int len, int lt
   }
   if (len == 0) { ua = zero; uc = zero; ud = zero; }
 
-  __syncthreads();   // staging area -> exchange area
+  barrier();   // staging area -> exchange area
   xch[lt] = Row3<R>{ua, uc, ud};
-  __syncthreads();
+  barrier();
   Row3<R> nx = xch[lt + 1 < P ? lt + 1 : lt];
   const bool hasnx = lt + 1 < P;
   nx.a = pd_sel(hasnx, nx.a, zero);
@@ -105,9 +114,9 @@ __device__ __forceinline__ void partition_solve(cpx<R> (&d)[MR], int len, int lt
     de = A::mul(de, rb);
   }
   for (int st = 1; st < P; st <<= 1) {
-    __syncthreads();
+    barrier();
     xch[lt] = Row3<R>{al, ga, de};
-    __syncthreads();
+    barrier();
     Row3<R> lo = xch[lt >= st ? lt - st : lt];
     Row3<R> hi = xch[lt + st < P ? lt + st : lt];
     const bool haslo = lt >= st, hashi = lt + st < P;
@@ -123,9 +132,9 @@ __device__ __forceinline__ void partition_solve(cpx<R> (&d)[MR], int len, int lt
     de = A::mul(nd, rb);
   }
   const cpx<R> xe = pd_sel(len >= 2, de, zero);
-  __syncthreads();
+  barrier();
   xch[lt].d = xe;
-  __syncthreads();
+  barrier();
   const cpx<R> xprev = pd_sel(lt > 0, xch[lt > 0 ? lt - 1 : 0].d, zero);
   const cpx<R> xs = csub(csub(ud, A::mul(ua, xprev)), A::mul(uc, xe));
   cpx<R> ynext = xe;

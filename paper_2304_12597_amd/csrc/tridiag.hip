@@ -514,8 +514,10 @@ __device__ __forceinline__ void tridiag_uniform_body(
 // order with a rotation inside each thread's chunk -- row lt*MR + q of group
 // g at g*P*MR + lt*MR + ((q + rot(lt)) mod MR), rot(lt) = lt*MR/16 -- so
 // that every LDS read of a thread's chunk is conflict-free, while each DMA
-// instruction (4 bytes per lane) fills 16 consecutive entries from 16
-// consecutive rows: the global reads are contiguous.  The per-item scalars
+// instruction (16 bytes per lane) fills 64 consecutive entries from the 64
+// rows they hold: the global reads stay within one 1 KiB span.  The
+// reduction's barriers order LDS accesses only (pd_lds_barrier): a full
+// barrier would wait for the whole prefetch.  The per-item scalars
 // (lambda_k, gamma_k) are read with scalar loads, which do not wait for the
 // vector-memory counter.  Mode 1 transposes 4x4 blocks of rows inside each
 // lane quad, so that each store instruction writes runs of 4 consecutive
@@ -525,8 +527,7 @@ __device__ __forceinline__ void tridiag_uniform_body(
 // matrices, real right-hand sides): system k = 0 runs in the real parts and
 // k = ell/2 in the imaginary parts with componentwise arithmetic (DualOps,
 // factor row F2), so F2 - 1 items cover the half spectrum; slot s >= 1 is
-// k = s.  Slot 0 reads its right-hand side directly instead of through the
-// staging area.
+// k = s.  Slot 0 stages the two real parts with 4-byte DMA instructions.
 //
 // LDS: [spb*P*MR cpx stage][spb*P Row3 exchange][2*spb*NFP cpx factors]
 template <int MR>
@@ -597,19 +598,36 @@ __device__ __forceinline__ void tridiag_pipe_body(
   }
   __syncthreads();   // the staging area is free for the DMA
 
-  // DMA of a slot's right-hand side (not for slot 0, read directly) and of
-  // its factors into factor buffer b
+  // DMA of a slot's right-hand side and of its factors into factor buffer b.
+  // Slot 0 (the real shifts k = 0 and k = ell/2) takes the real parts of
+  // rows k = 0 (dwords 0, 1 of each entry) and k = ell/2 (dwords 2, 3).
   auto issue = [&](int slot_in, int b) {
     const int sl = slot_in < nslots ? slot_in : nslots - 1;
     if constexpr (MODE != 2) {
+      // staging entry e holds row tl*MR + q of the rotated layout, tl = e/MR
+      // (rows >= n read row n-1 and are zeroed when read)
+      constexpr int LG = MR == 16 ? 0 : (MR == 8 ? 1 : 2);
+      const int lane = lt & 63;
       if (sl != 0) {
-        // the wave's 4*MR windows of 16 staging entries, one DMA instruction
-        // each: lane l fills dword l & 3 of entry e0 + l/4, which holds row
-        // lt*MR + q of the rotated layout (rows >= n read row n-1 and are
-        // zeroed when read)
-        constexpr int LG = MR == 16 ? 0 : (MR == 8 ? 1 : 2);
-        const unsigned *src32 = reinterpret_cast<const unsigned *>(in + (size_t)sl * n);
-        const int lane = lt & 63;
+        // the wave's MR windows of 64 entries, one 16-byte DMA each
+        const Cx *src = in + (size_t)sl * n;
+#pragma unroll
+        for (int wdw = 0; wdw < MR; ++wdw) {
+          const int e0 = wib * 64 * MR + wdw * 64;
+          const int e = e0 + lane;
+          const int tl = e / MR, j = e & (MR - 1);
+          const int q = (j - (tl >> LG)) & (MR - 1);
+          int r = tl * MR + q;
+          r = r < n ? r : n - 1;
+          pd_lds_dma16(src + r, stage + e0);
+        }
+      } else {
+        // the wave's 4*MR windows of 16 entries, one 4-byte DMA each: lane
+        // l fills dword l & 3 of entry e0 + l/4, dwords 0, 1 from the real
+        // part of row k = 0 and dwords 2, 3 from that of row k = ell/2
+        const unsigned *srcA = reinterpret_cast<const unsigned *>(in);
+        const unsigned *srcB = reinterpret_cast<const unsigned *>(in + (size_t)(F2 - 1) * n);
+        const unsigned *lsrc = ((lane & 2) ? srcB : srcA) + (lane & 1);
 #pragma unroll 8
         for (int wdw = 0; wdw < 4 * MR; ++wdw) {
           const int e0 = wib * 64 * MR + wdw * 16;
@@ -618,7 +636,7 @@ __device__ __forceinline__ void tridiag_pipe_body(
           const int q = (j - (tl >> LG)) & (MR - 1);
           int r = tl * MR + q;
           r = r < n ? r : n - 1;
-          pd_lds_dma4(src32 + (size_t)r * 4 + (lane & 3), stage + e0);
+          pd_lds_dma4(lsrc + (size_t)r * 4, stage + e0);
         }
       }
     }
@@ -657,27 +675,13 @@ __device__ __forceinline__ void tridiag_pipe_body(
 #pragma unroll
       for (int q = 0; q < MR; ++q) d[q] = Cx{dv[q], DUAL ? dv[q] : R(0)};
     } else {
+      // staged right-hand side (slot 0: real parts of rows k = 0 and k = ell/2)
       Cx left, right;
-      if constexpr (DUAL) {
-        // real parts of rows k = 0 and k = ell/2, read directly
-        const Cx *ra = in, *rb = in + (size_t)(F2 - 1) * n;
 #pragma unroll
-        for (int q = 0; q < MR; ++q) {
-          const int r = s0 + q < n ? s0 + q : n - 1;
-          d[q] = pd_sel(q < len, Cx{ra[r].re, rb[r].re}, zero);
-        }
-        // neighbour rows, clamped to [0, n) (threads past the end have s0 > n)
-        const int rl = (lt > 0 && s0 - 1 < n) ? s0 - 1 : 0;
-        const int rr = s0 + MR < n ? s0 + MR : n - 1;
-        left = pd_sel(lt > 0, Cx{ra[rl].re, rb[rl].re}, zero);
-        right = pd_sel(s0 + MR < n, Cx{ra[rr].re, rb[rr].re}, zero);
-      } else {
-#pragma unroll
-        for (int q = 0; q < MR; ++q) d[q] = pd_sel(q < len, stage[pipe_entry<MR>(lt, q)], zero);
-        left = pd_sel(lt > 0, stage[pipe_entry<MR>(lt > 0 ? lt - 1 : 0, MR - 1)], zero);
-        right = pd_sel(s0 + MR < n && lt + 1 < P, stage[pipe_entry<MR>(lt + 1 < P ? lt + 1 : lt, 0)],
-                       zero);
-      }
+      for (int q = 0; q < MR; ++q) d[q] = pd_sel(q < len, stage[pipe_entry<MR>(lt, q)], zero);
+      left = pd_sel(lt > 0, stage[pipe_entry<MR>(lt > 0 ? lt - 1 : 0, MR - 1)], zero);
+      right = pd_sel(s0 + MR < n && lt + 1 < P, stage[pipe_entry<MR>(lt + 1 < P ? lt + 1 : lt, 0)],
+                     zero);
       // right-hand side d = M r (- w M x), formed in place; ghost rows are zero
       Cx rl = left;
 #pragma unroll
@@ -700,22 +704,16 @@ __device__ __forceinline__ void tridiag_pipe_body(
     sync();
     // waves of whole chunks take a copy without the ragged-chunk guards (at
     // 16 rows per thread the second copy would not fit in registers)
+    // LDS-only barriers: the next item's prefetch keeps streaming in through
+    // the reduction (xch does not alias the staging area)
     if (!DUAL && MR <= 8 && __all(len == MR))
-      partition_solve<R, MR, OPS>(d, MR, lt, P, lfac, xch, ca, cc);
+      partition_solve<R, MR, OPS, true>(d, MR, lt, P, lfac, xch, ca, cc);
     else
-      partition_solve<R, MR, OPS>(d, len, lt, P, lfac, xch, ca, cc);
+      partition_solve<R, MR, OPS, true>(d, len, lt, P, lfac, xch, ca, cc);
 
     if constexpr (MODE == 1) {
       if (active) {
-        if constexpr (DUAL) {
-          Cx *da = out + s0, *db = out + (size_t)(F2 - 1) * n + s0;
-#pragma unroll
-          for (int q = 0; q < MR; ++q)
-            if (q < len) {
-              da[q] = Cx{d[q].re, R(0)};
-              db[q] = Cx{d[q].im, R(0)};
-            }
-        } else {
+        {
           // 4x4 transpose inside each lane quad (for every group of 4 rows
           // a): lane c ends with row (quad base + b)*MR + 4a + c in d[4a + b]
           const int c = lt & 3;
@@ -736,12 +734,25 @@ __device__ __forceinline__ void tridiag_pipe_body(
               }
             }
           }
-          Cx *dst = out + (size_t)k * n;
           const int qb = lt & ~3;
+          if constexpr (DUAL) {
+            // slot 0: the real parts go to rows k = 0 and k = ell/2
+            Cx *da = out, *db = out + (size_t)(F2 - 1) * n;
 #pragma unroll
-          for (int q = 0; q < MR; ++q) {
-            const int row = (qb + (q & 3)) * MR + (q & ~3) + c;
-            if (row < n) dst[row] = d[q];
+            for (int q = 0; q < MR; ++q) {
+              const int row = (qb + (q & 3)) * MR + (q & ~3) + c;
+              if (row < n) {
+                da[row] = Cx{d[q].re, R(0)};
+                db[row] = Cx{d[q].im, R(0)};
+              }
+            }
+          } else {
+            Cx *dst = out + (size_t)k * n;
+#pragma unroll
+            for (int q = 0; q < MR; ++q) {
+              const int row = (qb + (q & 3)) * MR + (q & ~3) + c;
+              if (row < n) dst[row] = d[q];
+            }
           }
         }
       }
@@ -757,13 +768,15 @@ __device__ __forceinline__ void tridiag_pipe_body(
 
   int item = blk, buf = 0;
   if (PAIR_FIRST && blk == 0) {
-    // slot 0 first: its factors into buffer 1 while the next item's data
-    // (buffer 0) streams in behind it
+    // slot 0 first (its right-hand side staged, its factors into buffer 1);
+    // the next item's data (buffer 0) streams in behind its solve
     issue(0, 1);
-    if (nblk < nitems) issue(nblk, 0);
     pd_wait_all();
     __syncthreads();
-    work(DualOps<R>{}, 0, facb + ((size_t)1 * spb + g) * NFP, [] {});
+    work(DualOps<R>{}, 0, facb + ((size_t)1 * spb + g) * NFP, [&] {
+      __syncthreads();   // every thread has read the staging area
+      if (nblk < nitems) issue(nblk, 0);
+    });
     item = nblk;
   } else if (blk < nitems) {
     issue(item * spb + g, 0);

@@ -9,9 +9,9 @@ paired real shifts k = 0 and k = ell/2 (one work item) read the neighbour
 rows s0 - 1 and s0 + MR of a thread's chunk without clamping, and threads
 whose chunk starts past the end of the system (s0 > n, present whenever
 P * MR exceeds n by more than one chunk) read before or after the array.
-The kernel now clamps both; these tests keep that and every other access of
-the tridiag_pipe_body / tridiag_uniform_body expressions (csrc/tridiag.hip)
-in range.  The expressions below restate the kernel's, statement by
+That pair is now staged through LDS like every other slot; these tests keep
+every access of the tridiag_pipe_body / tridiag_uniform_body expressions
+(csrc/tridiag.hip) in range.  The expressions below restate the kernel's, statement by
 statement."""
 import numpy as np
 import pytest
@@ -19,6 +19,7 @@ import pytest
 from paper_2304_12597_amd import workloads as wl
 
 CUS = 256
+MAX_LDS = 160 * 1024
 
 
 def choose_tri(n, prec):
@@ -60,7 +61,22 @@ def check_pipe(n, F2):
     lane = lt & 63
     wib = lt >> 6
     LG = lg_of(MR)
-    # issue(): one DMA window of 16 staging entries per instruction
+    # issue(), complex slots: one 16-byte DMA window of 64 entries per instruction
+    seen = np.zeros(rows, dtype=np.int64)
+    for wdw in range(MR):
+        e0 = wib * 64 * MR + wdw * 64
+        e = e0 + lane
+        tl = e // MR
+        j = e & (MR - 1)
+        q = (j - (tl >> LG)) & (MR - 1)
+        r = np.minimum(tl * MR + q, n - 1)
+        assert r.min() >= 0 and r.max() < n
+        assert e0.min() >= 0 and (e0 + 63).max() < rows           # LDS window
+        assert np.all(e0 == (e0 // 64) * 64) and np.all(e0 == e - lane)   # 64 entries per wave
+        assert np.all(pipe_entry(tl, q, MR) == e)
+        seen += np.bincount(e, minlength=rows)
+    assert np.all(seen == 1)                        # every staging entry filled once
+    # issue(), paired real shifts: one 4-byte DMA window of 16 entries per instruction
     for wdw in range(4 * MR):
         e0 = wib * 64 * MR + wdw * 16
         e = e0 + (lane >> 2)
@@ -72,14 +88,14 @@ def check_pipe(n, F2):
         assert e0.min() >= 0 and (e0 + 15).max() < rows           # LDS window
         # the staged entry e holds row tl*MR + q: the rotation is a bijection
         assert np.all(pipe_entry(tl, q, MR) == e)
-    # work(), paired real shifts: rows of the thread's chunk and neighbours
-    for q in range(MR):
-        r = np.minimum(s0 + q, n - 1)
-        assert r.min() >= 0 and r.max() < n
-    rl = np.where((lt > 0) & (s0 - 1 < n), s0 - 1, 0)
-    rr = np.where(s0 + MR < n, s0 + MR, n - 1)
-    assert rl.min() >= 0 and rl.max() < n and rr.min() >= 0 and rr.max() < n
-    # work(), complex shifts: staging entries of the chunk and neighbours
+        # paired real shifts (slot 0): lanes with bit 1 read the real part of
+        # frequency ell/2, the others that of frequency 0; dword lane & 1 of the row
+        src_row = np.where(lane & 2, F2 - 1, 0)
+        dw = r * 4 + (lane & 1)
+        assert src_row.max() < F2 and dw.max() < 4 * n and np.all((dw & 3) < 2)
+        # the four lanes of an entry fill dwords 0, 1 (k = 0) and 2, 3 (k = ell/2)
+        assert np.all(np.where(lane & 2, 2, 0) + (lane & 1) == (lane & 3))
+    # work(): staging entries of the chunk and neighbours (every slot)
     for q in range(MR):
         assert pipe_entry(lt, q, MR).max() < rows
     assert pipe_entry(np.maximum(lt - 1, 0), MR - 1, MR).max() < rows
@@ -101,6 +117,11 @@ def check_pipe(n, F2):
     nitems = F2 - 1
     G = min(nitems, CUS)
     assert G <= min(nitems, CUS)
+    # LDS: stage | P Row3 exchange entries per group | two factor buffers,
+    # within the 160 KiB of a CU
+    nfp = (6 * (MR - 1) + 63) // 64 * 64
+    lds = spb * (rows + 3 * P + 2 * nfp) * 16
+    assert lds <= MAX_LDS, (n, lds)
 
 
 def check_uniform(n, prec):
