@@ -46,29 +46,29 @@ __device__ __forceinline__ void fft_forward_body(int tile, int N, int n, int nba
   R *lcol = reinterpret_cast<R *>(lds + (pnt >> 1) * stride) + (pnt & 1);
   double rn2 = 0.0, gn2 = 0.0;
   // Issue UNR independent loads per thread before storing to LDS, so their
-  // HBM latencies overlap instead of adding up: every load reads a clamped,
-  // valid address, and out-of-tile entries are zeroed afterwards.  dal ==
-  // NULL: alpha = 1, no scaling.
-  constexpr int UNR = 8;
+  // HBM latencies overlap instead of adding up (16: a whole 2048-step column
+  // pair of 512 threads in one round; the residual form, with more loads per
+  // entry, 8): every load reads a clamped, valid address, and out-of-tile
+  // entries are zeroed afterwards.  dal == NULL: alpha = 1, no scaling.
+  constexpr int UNR = MODE == 1 ? 8 : 16;
   double h0 = 0.0;   // u0 at this point (used by the t = 0 entry)
   if (MODE == 0) h0 = u0[ic];
   for (int tb = t0; tb < N; tb += UNR * dt) {
     double vals[UNR];
     if constexpr (MODE != 1) {
-      double fv[UNR], sc[UNR];
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
         const int t = tb + u * dt;
         const int tc = t < N ? t : N - 1;
-        fv[u] = F[(size_t)tc * nbar + ic];
-        sc[u] = dal ? dal[tc] : 1.0;
+        vals[u] = F[(size_t)tc * nbar + ic];
       }
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
         const int t = tb + u * dt;
-        double val = (MODE == 0) ? tau * fv[u] : fv[u];
+        const int tc = t < N ? t : N - 1;
+        double val = (MODE == 0) ? tau * vals[u] : vals[u];
         if (MODE == 0 && t == 0) val += h0;
-        if (dal) val *= sc[u];
+        if (dal) val *= dal[tc];
         vals[u] = (t < N && inb) ? val : 0.0;
       }
     } else {
@@ -96,13 +96,14 @@ __device__ __forceinline__ void fft_forward_body(int tile, int N, int n, int nba
   __syncthreads();
   fft_lds<R, false>(lds, N, C, stride, twl);
   const int half = N / 2;
-  // split the packed pairs: UNR outputs per thread per round, all LDS reads
+  // split the packed pairs: UNS outputs per thread per round, all LDS reads
   // before the stores (k < N/2 here, the Nyquist row k = N/2 below)
   const cpx<R> *ccol = lds + (pnt >> 1) * stride;
-  for (int kb = t0; kb < half; kb += UNR * dt) {
-    cpx<R> X[UNR];
+  constexpr int UNS = 8;
+  for (int kb = t0; kb < half; kb += UNS * dt) {
+    cpx<R> X[UNS];
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
+    for (int u = 0; u < UNS; ++u) {
       const int k = kb + u * dt;
       const int kc = k < half ? k : 0;
       const cpx<R> zk = ccol[pd_fpad(kc)];
@@ -112,7 +113,7 @@ __device__ __forceinline__ void fft_forward_body(int tile, int N, int n, int nba
       X[u] = cpx<R>{R(0.5) * xr, R(0.5) * xi};
     }
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
+    for (int u = 0; u < UNS; ++u) {
       const int k = kb + u * dt;
       if (k < half && inb) out[(size_t)k * nbar + i] = X[u];
     }
@@ -178,7 +179,7 @@ __device__ __forceinline__ void fft_inverse_body(int tile, int N, int nbar, int 
   const int lgC = __builtin_ctz(C), lgS = lgC + 1, S = 2 * C;
   const int i0 = tile * S;
   const int half = N / 2;
-  constexpr int UNR = 4;
+  constexpr int UNR = 8;
   // input: T is a multiple of C, so every thread owns one point pair c of
   // the tile and the frequencies k0, k0 + dk, ..., k <= N/2
   {

@@ -171,27 +171,37 @@ __global__ void init_kernel(int nblk, const double *__restrict__ red, double *__
   }
 }
 
-// back substitution R y = g on the m x m triangle (single thread); m < 0:
-// the iteration count recorded in the status
-__global__ void backsolve_kernel(double *__restrict__ gm, int MX, int m) {
+// Back substitution R y = g on the m x m triangle, then x = V y, in one
+// launch (m < 0: the iteration count recorded in the status): every block
+// reads the (at most 64 x 64) triangle and g into LDS with one parallel round
+// trip, solves it on one thread (block 0 also stores y), and forms its rows
+// of x.
+__global__ void solve_combine_kernel(int n, int m, const double *__restrict__ V,
+                                     double *__restrict__ gm, int MX, double *__restrict__ x) {
+  __shared__ double Rt[64][65];
+  __shared__ double gv[64], yv[64];
   GmLayout L{MX};
-  if (threadIdx.x != 0) return;
   if (m < 0) m = (int)gm[L.st(2)];
-  for (int i = m - 1; i >= 0; --i) {
-    double s = gm[L.g(i)];
-    for (int k = i + 1; k < m; ++k) s -= gm[L.H(i, k)] * gm[L.y(k)];
-    double d = gm[L.H(i, i)];
-    gm[L.y(i)] = (d != 0.0) ? s / d : 0.0;
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+    const int i = e / m, k = e - i * m;
+    if (k >= i) Rt[i][k] = gm[L.H(i, k)];
   }
-}
-
-__global__ void combine_kernel(int n, int m, const double *__restrict__ V,
-                               const double *__restrict__ gm, int MX, double *__restrict__ x) {
-  GmLayout L{MX};
-  if (m < 0) m = (int)gm[L.st(2)];
+  for (int i = threadIdx.x; i < m; i += blockDim.x) gv[i] = gm[L.g(i)];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = m - 1; i >= 0; --i) {
+      double s = gv[i];
+      for (int k = i + 1; k < m; ++k) s -= Rt[i][k] * yv[k];
+      const double d = Rt[i][i];
+      yv[i] = (d != 0.0) ? s / d : 0.0;
+    }
+    if (blockIdx.x == 0)
+      for (int i = 0; i < m; ++i) gm[L.y(i)] = yv[i];
+  }
+  __syncthreads();
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
     double s = 0.0;
-    for (int i = 0; i < m; ++i) s += gm[L.y(i)] * V[(size_t)i * n + r];
+    for (int i = 0; i < m; ++i) s += yv[i] * V[(size_t)i * n + r];
     x[r] = s;
   }
 }
@@ -225,35 +235,82 @@ __device__ __forceinline__ void arnoldi_step_body(int n, double *__restrict__ V,
   constexpr int NW = ARN_T / 64;
   __shared__ double part[NW][65];
   __shared__ double h[64];
+  __shared__ double hcol[66];           // column j of H, accumulated here
+  __shared__ double csl[64], snl[64];   // the earlier Givens rotations
   __shared__ double hsh;
   GmLayout L{MX};
   if (gm[L.st(GM_DONE)] != 0.0) return;   // the whole block leaves together
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nv = j + 1;
+  // the small state thread 0 needs, read up front in parallel (one global
+  // round trip instead of a chain of them); column j of H starts at zero
+  if (tid < j) {
+    csl[tid] = gm[L.cs(tid)];
+    snl[tid] = gm[L.sn(tid)];
+  }
+  if (tid < j + 2) hcol[tid] = 0.0;
+  double gj = 0.0, beta = 0.0;
+  if (tid == 0) {
+    gj = gm[L.g(j)];
+    beta = gm[L.st(3)];
+  }
   double wr[RPT];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     const int r = tid + k * ARN_T;
     wr[k] = r < n ? w[r] : 0.0;
   }
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int i = 0; i < nv; ++i) {
-      const double *vi = V + (size_t)i * n;
-      double s = 0.0;
+  // the first iterations keep V_0 .. V_j in registers (up to NC vectors,
+  // as the register budget allows): each is then read once instead of four
+  // times (two passes, each a dot and an update), and a single block's
+  // bandwidth is what bounds this step
+  constexpr int NC = RPT <= 4 ? 4 : (RPT <= 8 ? 2 : 1);
+  const bool cached = RPT <= 8 && nv <= NC;
+  double vr[NC][RPT];
+  if (cached) {
 #pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int r = tid + k * ARN_T;
-        if (r < n) s += vi[r] * wr[k];
+    for (int i = 0; i < NC; ++i)
+      if (i < nv) {
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+          const int r = tid + k * ARN_T;
+          vr[i][k] = r < n ? V[(size_t)i * n + r] : 0.0;
+        }
       }
-      s = wave_sum(s);
-      if (lane == 0) part[wv][i] = s;
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    if (cached) {
+#pragma unroll
+      for (int i = 0; i < NC; ++i)
+        if (i < nv) {
+          double s = 0.0;
+#pragma unroll
+          for (int k = 0; k < RPT; ++k) {
+            const int r = tid + k * ARN_T;
+            if (r < n) s += vr[i][k] * wr[k];
+          }
+          s = wave_sum(s);
+          if (lane == 0) part[wv][i] = s;
+        }
+    } else {
+      for (int i = 0; i < nv; ++i) {
+        const double *vi = V + (size_t)i * n;
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+          const int r = tid + k * ARN_T;
+          if (r < n) s += vi[r] * wr[k];
+        }
+        s = wave_sum(s);
+        if (lane == 0) part[wv][i] = s;
+      }
     }
     __syncthreads();
     if (tid < nv) {
       double s = 0.0;
       for (int q = 0; q < NW; ++q) s += part[q][tid];
       h[tid] = s;
-      gm[L.H(tid, j)] += s;
+      hcol[tid] += s;
     }
     __syncthreads();
 #pragma unroll
@@ -261,7 +318,13 @@ __device__ __forceinline__ void arnoldi_step_body(int n, double *__restrict__ V,
       const int r = tid + k * ARN_T;
       if (r < n) {
         double t = wr[k];
-        for (int i = 0; i < nv; ++i) t -= h[i] * V[(size_t)i * n + r];
+        if (cached) {
+#pragma unroll
+          for (int i = 0; i < NC; ++i)
+            if (i < nv) t -= h[i] * vr[i][k];
+        } else {
+          for (int i = 0; i < nv; ++i) t -= h[i] * V[(size_t)i * n + r];
+        }
         wr[k] = t;
       }
     }
@@ -277,24 +340,23 @@ __device__ __forceinline__ void arnoldi_step_body(int n, double *__restrict__ V,
     double nn = 0.0;
     for (int q = 0; q < NW; ++q) nn += part[q][0];
     const double hn = sqrt(nn);
-    gm[L.H(j + 1, j)] = hn;
+    hcol[j + 1] = hn;
     for (int i = 0; i < j; ++i) {
-      const double c = gm[L.cs(i)], sn = gm[L.sn(i)];
-      const double a = gm[L.H(i, j)], b = gm[L.H(i + 1, j)];
-      gm[L.H(i, j)] = c * a + sn * b;
-      gm[L.H(i + 1, j)] = -sn * a + c * b;
+      const double c = csl[i], sn = snl[i];
+      const double a = hcol[i], b = hcol[i + 1];
+      hcol[i] = c * a + sn * b;
+      hcol[i + 1] = -sn * a + c * b;
     }
-    const double a = gm[L.H(j, j)], b = gm[L.H(j + 1, j)];
+    const double a = hcol[j], b = hcol[j + 1];
     const double rr = hypot(a, b);
     const double c = (rr == 0.0) ? 1.0 : a / rr, sn = (rr == 0.0) ? 0.0 : b / rr;
     gm[L.cs(j)] = c;
     gm[L.sn(j)] = sn;
-    gm[L.H(j, j)] = rr;
-    gm[L.H(j + 1, j)] = 0.0;
-    const double gj = gm[L.g(j)];
+    hcol[j] = rr;
+    hcol[j + 1] = 0.0;
     gm[L.g(j)] = c * gj;
     gm[L.g(j + 1)] = -sn * gj;
-    const double res = fabs(-sn * gj), beta = gm[L.st(3)];
+    const double res = fabs(-sn * gj);
     const double done = (res <= rtol * beta || hn == 0.0 || !isfinite(res)) ? 1.0 : 0.0;
     gm[L.st(0)] = res;
     gm[L.st(1)] = hn;
@@ -308,6 +370,7 @@ __device__ __forceinline__ void arnoldi_step_body(int n, double *__restrict__ V,
     hsh = hn;
   }
   __syncthreads();
+  if (tid < j + 2) gm[L.H(tid, j)] = hcol[tid];
   const double inv = (hsh > 0.0) ? 1.0 / hsh : 0.0;
   double *vn = V + (size_t)(j + 1) * n;
 #pragma unroll
@@ -495,8 +558,8 @@ pd_status gmres_fused(pd_plan p, const double *b, double *x, double rtol, int *i
     if (relres) *relres = 0.0;
     return PD_OK;
   }
-  hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, p->stream, p->gm, MX, m);
-  hipLaunchKernelGGL(combine_kernel, dim3(B), dim3(VB), 0, p->stream, n, m, p->V, p->gm, MX, x);
+  hipLaunchKernelGGL(solve_combine_kernel, dim3(B), dim3(VB), 0, p->stream, n, m, p->V, p->gm, MX,
+                     x);
   PD_HIP_CHECK(hipGetLastError());
   if (iters) *iters = m;
   if (relres) *relres = res / beta;
@@ -517,8 +580,8 @@ pd_status pd_gmres_enqueue(pd_plan p, const double *b, double *x, double rtol, i
   PD_HIP_CHECK(hipGetLastError());
   pd_status s = enqueue_iters(p, 0, count, rtol);
   if (s != PD_OK) return s;
-  hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, p->stream, p->gm, MX, -1);
-  hipLaunchKernelGGL(combine_kernel, dim3(B), dim3(VB), 0, p->stream, n, -1, p->V, p->gm, MX, x);
+  hipLaunchKernelGGL(solve_combine_kernel, dim3(B), dim3(VB), 0, p->stream, n, -1, p->V, p->gm, MX,
+                     x);
   PD_HIP_CHECK(hipGetLastError());
   return PD_OK;
 }
@@ -555,8 +618,8 @@ pd_status pd_gmres_continue(pd_plan p, double *x, double rtol, int *iters, doubl
     pd_set_error("capacitance GMRES produced a non-finite residual");
     return PD_ENONFINITE;
   }
-  hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, p->stream, p->gm, MX, m);
-  hipLaunchKernelGGL(combine_kernel, dim3(B), dim3(VB), 0, p->stream, n, m, p->V, p->gm, MX, x);
+  hipLaunchKernelGGL(solve_combine_kernel, dim3(B), dim3(VB), 0, p->stream, n, m, p->V, p->gm, MX,
+                     x);
   PD_HIP_CHECK(hipGetLastError());
   if (iters) *iters = m;
   if (relres) *relres = beta > 0.0 ? res / beta : 0.0;
@@ -617,8 +680,8 @@ pd_status pd_gmres(pd_plan p, const double *b, double *x, double rtol, int *iter
     }
     if (res <= rtol * beta || ((volatile double *)st_host)[1] == 0.0) break;
   }
-  hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, p->stream, p->gm, MX, m);
-  hipLaunchKernelGGL(combine_kernel, dim3(B), dim3(VB), 0, p->stream, n, m, p->V, p->gm, MX, x);
+  hipLaunchKernelGGL(solve_combine_kernel, dim3(B), dim3(VB), 0, p->stream, n, m, p->V, p->gm, MX,
+                     x);
   PD_HIP_CHECK(hipGetLastError());
   if (iters) *iters = m;
   if (relres) *relres = res / beta;
