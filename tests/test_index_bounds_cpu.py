@@ -196,6 +196,66 @@ def test_unclamped_neighbour_read_is_caught():
     assert bad_right.max() >= n
 
 
+def pipe_schedule(nitems, nblk, spb, MR):
+    """The item loop of tridiag_pipe_body, restated: per block, the sequence
+    of DMA issues (slot, factor buffer) and solves (slot, factor buffer, ops).
+    At 16 rows per thread block 0 runs the paired slot 0 before its regular
+    items (factor buffer 1); otherwise slot 0 is an ordinary item of the
+    loop."""
+    pair_first = MR == 16
+    out = []
+    for blk in range(nblk):
+        ev = []
+        item, buf = blk, 0
+        if pair_first and blk == 0:
+            ev.append(("issue", 0, 1))
+            ev.append(("solve", 0, 1, "dual"))
+            if nblk < nitems:
+                ev.append(("issue", nblk, 0))
+            item = nblk
+        elif blk < nitems:
+            ev.append(("issue", item * spb, 0))
+        while item < nitems:
+            slot = item * spb
+            ops = "dual" if (not pair_first and slot == 0) else "cplx"
+            ev.append(("solve", slot, buf, ops))
+            if item + nblk < nitems:
+                ev.append(("issue", (item + nblk) * spb, buf ^ 1))
+            item += nblk
+            buf ^= 1
+        out.append(ev)
+    return out
+
+
+@pytest.mark.parametrize("MR", [8, 16])
+@pytest.mark.parametrize("nitems,nblk", [(1024, 256), (1023, 256), (256, 256), (5, 5),
+                                         (64, 37), (1, 1), (2, 2), (3, 2)])
+def test_pipe_item_schedule(MR, nitems, nblk):
+    """Every slot is solved once, with the factor buffer its DMA filled, the
+    paired slot 0 with the componentwise (dual) arithmetic; an item's
+    successor streams into the other factor buffer, and the right-hand-side
+    staging area is refilled only after the item that read it."""
+    spb = 1
+    solved = []
+    for ev in pipe_schedule(nitems, nblk, spb, MR):
+        pending = None            # (slot, buffer) of the DMA in flight
+        in_use = None             # factor buffer of the item being solved
+        for e in ev:
+            if e[0] == "issue":
+                assert pending is None      # one staging area: consumed first
+                assert e[2] != in_use       # factors of the solve in progress kept
+                pending = (e[1], e[2])
+            else:
+                _, slot, buf, ops = e
+                assert pending == (slot, buf)
+                assert (ops == "dual") == (slot == 0)
+                pending = None
+                in_use = buf
+                solved.append(slot)
+        assert pending is None
+    assert sorted(solved) == list(range(nitems * spb))
+
+
 # ------------------------------------------- chunked capacitance product --
 
 def cp_chunking(n):
