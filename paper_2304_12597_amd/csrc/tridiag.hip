@@ -86,6 +86,34 @@ __device__ __forceinline__ void minus_w_mx(R (&mx)[MR], double *sx, int count,
   }
 }
 
+// The same -w (M x)_{s0+q} with constant diagonals, loaded straight from x
+// (no staging, no barrier), so that it can run while a DMA into the staging
+// area is in flight.  Rounds exactly as minus_w_mx<R, MR, true>: the same
+// expressions on the same values (x outside [0, n) enters as zero).
+template <typename R, int MR>
+__device__ __forceinline__ void minus_w_mx_direct(R (&mx)[MR], const double *__restrict__ coef64,
+                                                  const double *__restrict__ xv, double w, int n,
+                                                  int s0) {
+  const double ml0 = coef64[n - 1 > 0 ? n - 1 : 0], md0 = coef64[n], mu0 = coef64[2 * n];
+  double xs[MR + 2];   // x_{s0-1} .. x_{s0+MR}
+#pragma unroll
+  for (int j = 0; j < MR + 2; ++j) {
+    const int i = s0 - 1 + j;
+    const int ic = i < 0 ? 0 : (i < n ? i : n - 1);
+    const double t = xv != nullptr ? xv[ic] : 0.0;
+    xs[j] = pd_sel(i >= 0 && i < n, t, 0.0);
+  }
+#pragma unroll
+  for (int q = 0; q < MR; ++q) {
+    const int i = s0 + q;
+    const int ic = i < n ? i : n - 1;   // rows past n give zero
+    double v = md0 * xs[q + 1];
+    v += ((ic > 0) ? ml0 : 0.0) * xs[q];
+    v += ((ic < n - 1) ? mu0 : 0.0) * xs[q + 2];
+    mx[q] = (i < n) ? (R)(-w * v) : R(0);
+  }
+}
+
 template <typename R>
 struct Coef {
   const R *ML, *MD, *MU, *KL, *KD, *KU;   // per-row coefficients
@@ -579,11 +607,6 @@ __device__ __forceinline__ void tridiag_pipe_body(
 #pragma unroll
     for (int q = 0; q < MR; ++q) acc[q] = 0.0;
   }
-  if constexpr (MODE == 1) {
-    // -w M x, the same for every frequency
-    minus_w_mx<R, MR, true>(mx, reinterpret_cast<double *>(stage), rows + 2, coef64, xv,
-                            wscale, n, s0, lt, P);
-  }
   if constexpr (MODE == 2) {
     // M v is the same for all frequencies: form it once, in registers
     double *sv = reinterpret_cast<double *>(stage);
@@ -767,10 +790,17 @@ __device__ __forceinline__ void tridiag_pipe_body(
   };
 
   int item = blk, buf = 0;
+  if (PAIR_FIRST && blk == 0)
+    issue(0, 1);
+  else if (blk < nitems)
+    issue(item * spb + g, 0);
+  if constexpr (MODE == 1) {
+    // -w M x, the same for every frequency, while the first item streams in
+    minus_w_mx_direct<R, MR>(mx, coef64, xv, wscale, n, s0);
+  }
   if (PAIR_FIRST && blk == 0) {
     // slot 0 first (its right-hand side staged, its factors into buffer 1);
     // the next item's data (buffer 0) streams in behind its solve
-    issue(0, 1);
     pd_wait_all();
     __syncthreads();
     work(DualOps<R>{}, 0, facb + ((size_t)1 * spb + g) * NFP, [&] {
@@ -778,8 +808,6 @@ __device__ __forceinline__ void tridiag_pipe_body(
       if (nblk < nitems) issue(nblk, 0);
     });
     item = nblk;
-  } else if (blk < nitems) {
-    issue(item * spb + g, 0);
   }
   for (; item < nitems; item += nblk, buf ^= 1) {
     const int slot = __builtin_amdgcn_readfirstlane(item * spb + g);

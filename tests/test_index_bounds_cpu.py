@@ -109,7 +109,12 @@ def check_pipe(n, F2):
         assert row.min() >= 0
         hits += np.bincount(row[row < n], minlength=n)
     assert np.all(hits == 1)                        # every row written exactly once
-    # one-time staging of x / M v with a zero halo (pad16 layout, count = rows + 2)
+    # mode 1: -w M x from direct loads of x_{s0-1} .. x_{s0+MR}, clamped
+    for j in range(MR + 2):
+        i = s0 - 1 + j
+        ic = np.where(i < 0, 0, np.where(i < n, i, n - 1))
+        assert ic.min() >= 0 and ic.max() < n
+    # mode 2: one-time staging of M v with a zero halo (pad16 layout, count = rows + 2)
     count = rows + 2
     pad16 = lambda i: i + (i >> 4)
     assert pad16(count - 1) < 2 * rows              # fits the complex128 area
