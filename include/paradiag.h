@@ -171,7 +171,9 @@ pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double tau,
  * tol: the capacitance GMRES stops at residual <= tol/100 * ||b|| (with
  * float32 shifted solves, PD_MIXED and PD_FP32, at no less than 1e-7 * ||b||,
  * the resolution of float32 capacitance products); PD_MIXED refines until
- * the float64 relative all-at-once residual is <= tol.
+ * the float64 relative all-at-once residual is <= tol, or until a sweep
+ * fails to lower it: then that sweep's correction is taken back and the best
+ * iterate is returned with PD_ENOTCONV (info->rel_residual is its residual).
  * BDF plans (bdf_order s > 1, Section 5): the system is
  * (M + tau beta K) U - M U Sigma_s^T = G with G_t = M (sum_{j>t} alpha_j
  * u_{t+1-j} + tau beta f_{t+1}); u0 is [s][nbar] (u_{1-s} first), and the

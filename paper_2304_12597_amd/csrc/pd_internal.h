@@ -243,6 +243,9 @@ struct pd_plan_s {
 
   // workspace
   void *spec = nullptr;        // [F2][nbar] complex (c128 or c64)
+  void *spec2 = nullptr;       // PD_MIXED: a second spectrum, so that the last
+                               // correction's stays while the next residual is
+                               // transformed (rollback on a stalled sweep)
   size_t spec_bytes = 0;
   size_t bytes = 0;            // device bytes this plan allocated
   double *partials = nullptr;  // [tri_G][nbar]

@@ -120,7 +120,7 @@ pd_status upload(T *dst, const std::vector<T> &src, hipStream_t s) {
 void free_plan(pd_plan p) {
   if (!p) return;
   void *ptrs[] = {p->coef64, p->coef32, p->lam64, p->lam32, p->gB64, p->gJ64, p->tw64,
-                  p->tw32, p->dal, p->fac64, p->fac32, p->twd, p->wreal, p->spec, p->partials, p->rstage, p->bvec, p->xvec, p->wvec, p->V,
+                  p->tw32, p->dal, p->fac64, p->fac32, p->twd, p->wreal, p->spec, p->spec2, p->partials, p->rstage, p->bvec, p->xvec, p->wvec, p->V,
                   p->gm, p->red, p->sine_q, p->sine_wN, p->sine_twH, p->sine_m, p->sine_k,
                   p->fom, p->fom_h, p->wz, p->bdf_g, p->bdf_h, p->bdf_t, p->cp_tab};
   for (void *q : ptrs)
@@ -141,9 +141,10 @@ struct Layout {
   size_t fom_h_bytes = 0;
   size_t cp = 0;   // chunked capacitance product: tables + workspace (doubles)
   size_t spec_bytes = 0, partials = 0, rstage = 0, vec = 0, V = 0, gm = 0, red = 0;
+  size_t spec2_bytes = 0;   // PD_MIXED: the last correction's spectrum (stall rollback)
   size_t total_bytes() const {
     return coef * 12 + lam * 12 + 2 * lam * 8 + tw * 12 + dal * 8 + fac * 12 + twd * 8 +
-           wreal * 8 + wz * 8 + bdfg * 8 + bdfh * 8 + bdft * 8 + spec_bytes + partials * 8 + rstage * 8 + 3 * vec * 8 + V * 8 + gm * 8 +
+           wreal * 8 + wz * 8 + bdfg * 8 + bdfh * 8 + bdft * 8 + spec_bytes + spec2_bytes + partials * 8 + rstage * 8 + 3 * vec * 8 + V * 8 + gm * 8 +
            red * 8 + sine * 8 + fom * 8 + fom_h_bytes + cp * 8;
   }
 };
@@ -253,6 +254,7 @@ pd_status compute_layout(pd_plan p, int cus, size_t max_lds, Layout &L) {
   L.tw = 2 * (size_t)ell;
   L.dal = 2 * (size_t)ell;
   L.spec_bytes = (size_t)F2 * p->nbar * cb;
+  if (p->prec == PD_MIXED) L.spec2_bytes = L.spec_bytes;
   L.vec = p->ncap;
   L.V = (size_t)(p->maxit + 1) * p->ncap;
   L.gm = pd_gmres_state_doubles(p->maxit);
@@ -748,6 +750,8 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
     }
   }
   PD_TRY(dev_alloc(reinterpret_cast<unsigned char **>(&p->spec), p->spec_bytes));
+  if (L.spec2_bytes)
+    PD_TRY(dev_alloc(reinterpret_cast<unsigned char **>(&p->spec2), L.spec2_bytes));
   PD_TRY(dev_alloc(&p->partials, L.partials));
   PD_TRY(dev_alloc(&p->rstage, L.rstage));
   PD_TRY(dev_alloc(&p->bvec, L.vec));

@@ -13,6 +13,25 @@
 
 #include <cmath>
 
+namespace {
+__global__ void negate_kernel(float *__restrict__ x, size_t count) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * blockDim.x)
+    x[i] = -x[i];
+}
+
+// spec = -spec for a PD_MIXED plan's complex64 spectrum (spec_bytes long)
+pd_status pd_negate_spectrum(pd_plan p, void *spec) {
+  const size_t count = p->spec_bytes / sizeof(float);
+  const size_t want = (count + 255) / 256;
+  const int blocks = (int)(want < 4096 ? (want > 0 ? want : 1) : 4096);
+  hipLaunchKernelGGL(negate_kernel, dim3(blocks), dim3(256), 0, p->stream,
+                     reinterpret_cast<float *>(spec), count);
+  PD_HIP_CHECK(hipGetLastError());
+  return PD_OK;
+}
+}  // namespace
+
 // Forward stage for 1D or 2D plans.  residual = 0: transform h from (u0, F);
 // residual = 1: transform the float64 residual of (u0, F, U), with the
 // partial norms left in p->red.  2D plans first apply the orthonormal DST-I
@@ -260,10 +279,15 @@ extern "C" pd_status paradiag_solve(pd_plan p, const double *u0, const double *F
   if (st != PD_OK) return st;
   pd_status final_status = gst;
   if (p->prec == PD_MIXED) {
-    double rel = -1.0;
-    bool converged = false;
+    double rel = -1.0, prev = -1.0;
+    bool converged = false, stalled = false;
+    int swaps = 0;
     for (int s = 1; s < p->max_sweeps; ++s) {
-      // residual of the current iterate, fused with the next forward transform
+      // residual of the current iterate, fused with the next forward
+      // transform, into the other spectrum buffer: the last correction's
+      // spectrum stays in p->spec2
+      std::swap(p->spec, p->spec2);
+      ++swaps;
       st = pd_forward(p, u0, F, U, p->spec, 1);
       if (st != PD_OK) return st;
       double rn2, gn2;
@@ -278,10 +302,25 @@ extern "C" pd_status paradiag_solve(pd_plan p, const double *u0, const double *F
         converged = true;
         break;
       }
+      if (prev >= 0.0 && rel >= prev) {
+        // stalled: the last correction did not lower the residual.  Take it
+        // back (U -= its inverse transform, from the negated spectrum) so
+        // that the best iterate is returned, and stop.
+        st = pd_negate_spectrum(p, p->spec2);
+        if (st != PD_OK) return st;
+        st = pd_inverse(p, p->spec2, U, 1);
+        if (st != PD_OK) return st;
+        rel = prev;
+        stalled = true;
+        break;
+      }
+      prev = rel;
       st = sweep_tail(p, U, tol, 1, 1, info, &gst);
       if (st != PD_OK) return st;
       rel = -1.0;
     }
+    if (swaps & 1) std::swap(p->spec, p->spec2);
+    if (stalled) pd_set_error("refinement stalled: the residual stopped falling");
     if (rel < 0.0) {
       st = pd_residual_impl(p, u0, F, U, &rel);
       if (st != PD_OK) return st;
@@ -289,6 +328,10 @@ extern "C" pd_status paradiag_solve(pd_plan p, const double *u0, const double *F
     }
     if (info) info->rel_residual = rel;
     final_status = converged ? PD_OK : PD_ENOTCONV;
+    if (final_status == PD_ENOTCONV && stalled) {
+      PD_HIP_CHECK(hipStreamSynchronize(p->stream));
+      return final_status;
+    }
   } else {
     if (p->check_residual) {
       double rel;

@@ -122,3 +122,66 @@ def test_capacitance_not_converged_returns_last_iterate(lib, prec):
         assert allatonce.rel_err(Ux1, Uref) > 1e-6      # x_1 is not the solution
     else:
         assert allatonce.rel_err(Ug, Uref) < allatonce.rel_err(U1, Uref)
+
+
+def _mixed_run(lib, p, max_sweeps, tol, dims=1):
+    plan = lib.paradiag_plan_create(p.n, p.ell, p.tau, p.M, p.K, precision=1, dims=dims,
+                                    max_sweeps=max_sweeps, stream=stream())
+    try:
+        U = torch.empty((p.ell, p.nbar), dtype=torch.float64, device=dev())
+        status, msg = lib.PD_OK, ""
+        try:
+            info = lib.paradiag_solve(plan, T(p.u0), T(p.F), U, tol)
+        except lib.PDError as e:
+            assert e.status == lib.PD_ENOTCONV, e
+            status, msg = e.status, lib.paradiag_last_error()
+            info = lib.paradiag_solve(plan, T(p.u0), T(p.F), U, tol, allow_notconv=True)
+        torch.cuda.synchronize()
+        return U.cpu().numpy(), info, status, msg
+    finally:
+        lib.paradiag_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("case", ["fem1-stiff", "fd1-floor", "fd2-floor"])
+def test_mixed_refinement_stall_returns_best_iterate(lib, case):
+    """PD_MIXED refinement stops when a sweep no longer lowers the float64
+    all-at-once residual: it takes that sweep's correction back and returns
+    PD_ENOTCONV with the best iterate, before max_sweeps.  The returned U's
+    residual (oracle, CPU) is the smallest over the iterates, which runs
+    capped at k = 1, 2, ... sweeps reproduce, and info.rel_residual is it.
+    Cases: a stiff FEM problem (tau mu_max ~ 2e8, where float32 elimination
+    barely contracts) at a reachable-looking tolerance, and tolerances below
+    the float64 residual floor in 1D and 2D."""
+    from oracle.spatial import problem_matrices
+    rng = np.random.default_rng(11)
+    if case == "fem1-stiff":
+        p, dims, tol = wl.heat_1d("fem1", 16383, 16, 1.0, 1.0, rng, True), 1, 1e-10
+    elif case == "fd1-floor":
+        p, dims, tol = wl.heat_1d("fd1", 1023, 64, 1.0, 1.0, rng, True), 1, 1e-17
+    else:
+        p, dims, tol = wl.heat_2d(31, 16, 0.1, 1.0, rng), 2, 1e-17
+    print("stall case", case, p.n, p.ell, flush=True)
+    max_sweeps = 16
+    U, info, status, msg = _mixed_run(lib, p, max_sweeps, tol, dims)
+    assert np.isfinite(U).all()
+    Msp, Ksp = problem_matrices(p)
+    res = lambda V: allatonce.residual(Msp, Ksp, p.tau, p.u0, p.F, V)[1]
+    r = res(U)
+    # rounding floor of a computed relative residual: a few units of float64
+    # roundoff times || |A| |U| + |G| || / ||G|| (|A| the entrywise absolute
+    # all-at-once operator); on the stiff problem it is above 1e-9
+    G = allatonce.rhs(Msp, p.tau, p.u0, p.F)
+    aU = np.abs(U)
+    AU = np.asarray((abs(Msp + p.tau * Ksp) @ aU.T).T)
+    AU[1:] += np.asarray((abs(Msp) @ aU[:-1].T).T)
+    floor = 8 * 2.0 ** -53 * np.linalg.norm(AU + np.abs(G)) / np.linalg.norm(G)
+    if status == lib.PD_OK:                  # converged after all
+        assert info.rel_residual <= tol and r <= 10 * tol
+        return
+    assert "stalled" in msg, msg
+    assert 2 <= info.sweeps < max_sweeps, info.as_dict()
+    # the iterates after k = 1 .. sweeps - 1 sweeps (the last sweep was taken back)
+    rk = [res(_mixed_run(lib, p, k, tol, dims)[0]) for k in range(1, info.sweeps)]
+    best = min(rk)
+    assert r <= 1.5 * best + floor, (r, rk, floor)
+    assert abs(info.rel_residual - r) <= 0.5 * r + floor, (info.rel_residual, r, floor)
