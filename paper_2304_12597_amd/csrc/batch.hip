@@ -44,7 +44,13 @@ bool batchable(const pd_plan *plans, int count) {
 struct BatchRun {
   std::vector<const void *> key;   // plans, u0, F, U
   double tol = 0.0;
-  int K = 0, count = 0, MR = 0, prec = 0, MX = 0;
+  int K = 0, count = 0, prec = 0, MX = 0;
+  // shifted-solve launches, one per rows-per-thread bucket (MR 4, 8, 16):
+  // each bucket's entries are contiguous in the t0, t1, t0J and k0m maps
+  struct TriBucket {
+    int MR = 0, o0 = 0, n0 = 0, o1 = 0, n1 = 0, o0J = 0, n0J = 0, ok0 = 0, nk0 = 0;
+    size_t lds = 0;
+  } tb[3];
   hipStream_t s = nullptr;
   void *dev = nullptr;
   double *pin = nullptr;           // statuses [4 * count]: residual, h, iterations, beta
@@ -65,7 +71,7 @@ struct BatchRun {
   double *st = nullptr;
   int nf = 0, n0 = 0, n1 = 0, nv = 0, nr = 0, fft_threads = 64;
   int n0J = 0, nrJ = 0, nc1 = 0, nc2 = 0, nc3 = 0, cthreads2 = 64;
-  size_t fft_lds = 0, tri_lds = 0, clds1 = 0, clds2 = 0;
+  size_t fft_lds = 0, clds1 = 0, clds2 = 0;
   ~BatchRun() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (cap) (void)hipStreamDestroy(cap);
@@ -97,12 +103,15 @@ pd_status build_run(BatchRun &r, const pd_plan *plans, int count, const double *
     std::vector<int2> c1map, c2map, c3map, k0map;
     int cthreads2 = 64;
     size_t clds1 = 0, clds2 = 0;
-    int fft_threads = 64, MR = -1;
-    size_t fft_lds = 0, tri_lds = 0;
+    int fft_threads = 64;
+    size_t fft_lds = 0;
+    // per rows-per-thread bucket: the shifted-solve block maps and LDS size
+    std::vector<int2> t0b[3], t1b[3], t0Jb[3], k0b[3];
+    size_t ldsb[3] = {0, 0, 0};
     for (int i = 0; i < count; ++i) {
       const pd_plan p = plans[i];
-      if (MR < 0) MR = p->tri.MR;
-      if (p->tri.MR != MR) return PD_ENOTSUP;
+      const int bi = p->tri.MR == 4 ? 0 : (p->tri.MR == 8 ? 1 : 2);
+      if (p->tri.MR != 4 && p->tri.MR != 8 && p->tri.MR != 16) return PD_ENOTSUP;
       FftJob &f = fj[i];
       f.N = p->ell; f.n = p->n; f.nbar = p->nbar; f.dims = 1;
       f.C = p->fft_C; f.stride = p->fft_stride; f.tau = p->tau;
@@ -131,9 +140,9 @@ pd_status build_run(BatchRun &r, const pd_plan *plans, int count, const double *
       t.fac = (prec == PD_FP64) ? (const void *)p->fac64 : (const void *)p->fac32;
       t.gw = p->gB64; t.in = p->spec; t.vin = nullptr; t.xv = p->xvec; t.wscale = p->w;
       t.out = p->spec; t.partials = p->partials; t.skip = nullptr;
-      for (int b = 0; b < t.nblk; ++b) tri0map.push_back(make_int2(i, b));
-      for (int b = 0; b < t.nblk; ++b) tri1map.push_back(make_int2(i, b));
-      tri_lds = std::max(tri_lds, p->tri.lds);   // batchable: the same packing as p->tri
+      for (int b = 0; b < t.nblk; ++b) t0b[bi].push_back(make_int2(i, b));
+      for (int b = 0; b < t.nblk; ++b) t1b[bi].push_back(make_int2(i, b));
+      ldsb[bi] = std::max(ldsb[bi], p->tri.lds);   // batchable: the same packing as p->tri
 
       VecJob &v = vj[i];
       v.n = p->nbar; v.B = pd_vec_blocks(p->nbar); v.G = t.nblk;
@@ -150,14 +159,31 @@ pd_status build_run(BatchRun &r, const pd_plan *plans, int count, const double *
         for (int b = 0; b < pd_cp_blocks(J, 1); ++b) c1map.push_back(make_int2(i, b));
         for (int b = 0; b < pd_cp_blocks(J, 2); ++b) c2map.push_back(make_int2(i, b));
         for (int b = 0; b < pd_cp_blocks(J, 3); ++b) c3map.push_back(make_int2(i, b));
-        if (p->cpl.k0sep) k0map.push_back(make_int2(i, 0));
+        if (p->cpl.k0sep) k0b[bi].push_back(make_int2(i, 0));
         cthreads2 = std::max(cthreads2, pd_cp_threads2(J));
         clds1 = std::max(clds1, pd_cp_lds(J, 1));
         clds2 = std::max(clds2, pd_cp_lds(J, 2));
       } else {
-        for (int b = 0; b < t.nblk; ++b) tri0mapJ.push_back(make_int2(i, b));
+        for (int b = 0; b < t.nblk; ++b) t0Jb[bi].push_back(make_int2(i, b));
         for (int b = 0; b < (p->nbar + 255) / 256; ++b) redmapJ.push_back(make_int2(i, b));
       }
+    }
+    for (int bi = 0; bi < 3; ++bi) {
+      auto &B = r.tb[bi];
+      B.MR = 4 << bi;
+      B.lds = ldsb[bi];
+      B.o0 = (int)tri0map.size();
+      B.n0 = (int)t0b[bi].size();
+      tri0map.insert(tri0map.end(), t0b[bi].begin(), t0b[bi].end());
+      B.o1 = (int)tri1map.size();
+      B.n1 = (int)t1b[bi].size();
+      tri1map.insert(tri1map.end(), t1b[bi].begin(), t1b[bi].end());
+      B.o0J = (int)tri0mapJ.size();
+      B.n0J = (int)t0Jb[bi].size();
+      tri0mapJ.insert(tri0mapJ.end(), t0Jb[bi].begin(), t0Jb[bi].end());
+      B.ok0 = (int)k0map.size();
+      B.nk0 = (int)k0b[bi].size();
+      k0map.insert(k0map.end(), k0b[bi].begin(), k0b[bi].end());
     }
     // J-product jobs: same systems, mode 2, weights gamma_J, v = V_j
     std::vector<TriJob> tjJ = tj;
@@ -267,8 +293,6 @@ pd_status build_run(BatchRun &r, const pd_plan *plans, int count, const double *
     r.nr = (int)redmap.size();
     r.fft_threads = fft_threads;
     r.fft_lds = fft_lds;
-    r.tri_lds = tri_lds;
-    r.MR = MR;
   }
   return PD_OK;
 }
@@ -279,12 +303,25 @@ pd_status build_run(BatchRun &r, const pd_plan *plans, int count, const double *
     if (st_ != PD_OK) return st_; \
   } while (0)
 
+// One shifted-solve launch per rows-per-thread bucket present in the batch
+// (map, off, cnt: which of the bucket's block maps).
+pd_status tri_batch(const BatchRun &r, int mode, const TriJob *jobs, const int2 *map,
+                    int BatchRun::TriBucket::*off, int BatchRun::TriBucket::*cnt, const int *act,
+                    int j, hipStream_t s) {
+  for (const auto &B : r.tb)
+    if (B.*cnt > 0)
+      PD_B(pd_launch_tridiag_batch(r.prec, B.MR, mode, jobs, map + B.*off, B.*cnt, B.lds, act, j,
+                                   s));
+  return PD_OK;
+}
+using TB = BatchRun::TriBucket;
+
 // w = J V_j for every problem still iterating: the per-frequency product
 // and its reduction, and the chunked capacitance product.
 pd_status j_products(const BatchRun &r, int j, const int *act, hipStream_t s) {
-  PD_B(pd_launch_tridiag_batch(r.prec, r.MR, 2, r.tjJ, r.t0J, r.n0J, r.tri_lds, act, j, s));
+  PD_B(tri_batch(r, 2, r.tjJ, r.t0J, &TB::o0J, &TB::n0J, act, j, s));
   PD_B(pd_launch_reduce_batch(r.vj, r.rmJ, r.nrJ, j, act, s));
-  PD_B(pd_launch_tridiag_batch(r.prec, r.MR, 2, r.tk0, r.k0m, r.nk0, r.tri_lds, act, j, s));
+  PD_B(tri_batch(r, 2, r.tk0, r.k0m, &TB::ok0, &TB::nk0, act, j, s));
   PD_B(pd_cp_launch_batch(r.cj, r.c1m, r.nc1, r.c2m, r.nc2, r.cthreads2, r.c3m, r.nc3, r.clds1,
                           r.clds2, act, j, s));
   return PD_OK;
@@ -294,7 +331,7 @@ pd_status j_products(const BatchRun &r, int j, const int *act, hipStream_t s) {
 // synchronisation, no host data: capturable).
 pd_status enqueue_solve(const BatchRun &r, int K, double rtol, hipStream_t s) {
   PD_B(pd_launch_fft_forward_batch(r.prec, r.fj, r.fm, r.nf, r.fft_threads, r.fft_lds, s));
-  PD_B(pd_launch_tridiag_batch(r.prec, r.MR, 0, r.tj, r.t0, r.n0, r.tri_lds, nullptr, 0, s));
+  PD_B(tri_batch(r, 0, r.tj, r.t0, &TB::o0, &TB::n0, nullptr, 0, s));
   PD_B(pd_launch_reduce_batch(r.vj, r.rm, r.nr, -1, nullptr, s));
   PD_B(pd_gmres_batch_start(r.vj, r.count, r.MX, r.st, s));
   for (int j = 0; j < K; ++j) {
@@ -302,7 +339,7 @@ pd_status enqueue_solve(const BatchRun &r, int K, double rtol, hipStream_t s) {
     PD_B(pd_gmres_batch_arnoldi(r.vj, r.count, j, r.MX, rtol, r.st, nullptr, s));
   }
   PD_B(pd_gmres_batch_finish(r.vj, r.vm, r.nv, r.count, r.MX, nullptr, s));
-  PD_B(pd_launch_tridiag_batch(r.prec, r.MR, 1, r.tj, r.t1, r.n1, r.tri_lds, nullptr, 0, s));
+  PD_B(tri_batch(r, 1, r.tj, r.t1, &TB::o1, &TB::n1, nullptr, 0, s));
   PD_B(pd_launch_fft_inverse_batch(r.prec, r.fj, r.fm, r.nf, r.fft_threads, r.fft_lds, s));
   PD_HIP_CHECK(hipMemcpyAsync(r.pin, r.st, 4 * (size_t)r.count * sizeof(double),
                               hipMemcpyDeviceToHost, s));
@@ -344,7 +381,7 @@ pd_status finish_unconverged(const BatchRun &r, int K, double rtol) {
   }
   PD_B(pd_launch_fft_forward_batch(r.prec, r.fj, r.fm, r.nf, r.fft_threads, r.fft_lds, s));
   PD_B(pd_gmres_batch_finish(r.vj, r.vm, r.nv, r.count, r.MX, nullptr, s));
-  PD_B(pd_launch_tridiag_batch(r.prec, r.MR, 1, r.tj, r.t1, r.n1, r.tri_lds, nullptr, 0, s));
+  PD_B(tri_batch(r, 1, r.tj, r.t1, &TB::o1, &TB::n1, nullptr, 0, s));
   PD_B(pd_launch_fft_inverse_batch(r.prec, r.fj, r.fm, r.nf, r.fft_threads, r.fft_lds, s));
   PD_HIP_CHECK(hipStreamSynchronize(s));
   return PD_OK;

@@ -1268,6 +1268,7 @@ pd_status pd_launch_tridiag_batch(int prec, int MR, int mode, const TriJob *jobs
   if (prec == PD_FP64) {
     if (MR == 4) PD_TB_MODES(double, 4);
     else if (MR == 8) PD_TB_MODES(double, 8);
+    else if (MR == 16) PD_TB_MODES(double, 16);
     else { pd_set_error("batched solve: unsupported MR"); return PD_ENOTSUP; }
   } else {
     if (MR == 4) PD_TB_MODES(float, 4);
@@ -1299,6 +1300,9 @@ void pd_tri_batch_set_attributes(size_t max_lds) {
       reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 8, 0, 512>),
       reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 8, 1, 512>),
       reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 8, 2, 512>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 16, 0, 512>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 16, 1, 512>),
+      reinterpret_cast<const void *>(&tridiag_batch_kernel<double, 16, 2, 512>),
       reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 4, 0, 1024>),
       reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 4, 1, 1024>),
       reinterpret_cast<const void *>(&tridiag_batch_kernel<float, 4, 2, 1024>),
