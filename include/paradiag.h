@@ -135,6 +135,17 @@ typedef struct {
   double rel_residual;        /* ||G - A(U)||_F / ||G||_F, or -1           */
   double gmres_rel_residual;  /* last capacitance residual / ||b||         */
   int early_exit;             /* 1: U = U_1 was returned (early_exit test)  */
+  double est_rel_error;       /* bound on ||M^1/2 (U* - U)||_F / ||M^1/2 U||_F
+                                 from the computed residual R (U* the exact
+                                 solution): sqrt(ell (ell+1) / 2)
+                                 sqrt(lmax(M) / lmin(M)) ||R||_F / ||M U||_F,
+                                 valid when M is symmetric positive definite
+                                 and K symmetric positive semi-definite (both
+                                 checked by Gershgorin's theorem at plan
+                                 creation; backward Euler only).  Filled
+                                 whenever the solve computes the float64
+                                 residual (check_residual, or PD_MIXED's last
+                                 check); otherwise -1. */
 } pd_info;
 
 /* Fill *opt with defaults: dims 1, PD_FP64, alpha 1, maxit 64,

@@ -51,7 +51,8 @@ class pd_options(ctypes.Structure):
 class pd_info(ctypes.Structure):
     _fields_ = [("gmres_iters", ctypes.c_int), ("sweeps", ctypes.c_int),
                 ("pint_loops", ctypes.c_int), ("rel_residual", ctypes.c_double),
-                ("gmres_rel_residual", ctypes.c_double), ("early_exit", ctypes.c_int)]
+                ("gmres_rel_residual", ctypes.c_double), ("early_exit", ctypes.c_int),
+                ("est_rel_error", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

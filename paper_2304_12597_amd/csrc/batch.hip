@@ -492,11 +492,14 @@ pd_status pd_solve_batch_impl(const pd_plan *plans, int count, const double *con
       infos[i].pint_loops = m + 2;
       infos[i].gmres_rel_residual = beta > 0.0 ? res / beta : 0.0;
       infos[i].rel_residual = -1.0;
+      infos[i].est_rel_error = -1.0;
+      infos[i].early_exit = 0;
       if (plans[i]->check_residual) {
-        double rel;
-        pd_status rs = pd_residual_impl(plans[i], u0[i], F[i], U[i], &rel);
+        double rel, est;
+        pd_status rs = pd_residual_impl(plans[i], u0[i], F[i], U[i], &rel, &est);
         if (rs != PD_OK) return rs;
         infos[i].rel_residual = rel;
+        infos[i].est_rel_error = est;
       }
     }
   }

@@ -221,6 +221,9 @@ struct pd_plan_s {
   hipStream_t stream = nullptr;
   int device = 0;
   bool mass_identity = true;
+  // sqrt(ell (ell + 1) / 2) sqrt(lmax(M) / lmin(M)) when M is SPD and K SPSD
+  // (Gershgorin), else -1: turns ||R||_F / ||M U||_F into an error bound
+  double err_factor = -1.0;
   bool uniform = false;        // M and tau K have constant diagonals
   double uni[6] = {0, 0, 0, 0, 0, 0};  // ml md mu tkl tkd tku when uniform
 
@@ -376,8 +379,10 @@ pd_status pd_cp_launch_batch(const CpJob *jobs, const int2 *map1, int nb1, const
                              size_t lds2, const int *active, int jv, hipStream_t s);
 pd_status pd_gmres(pd_plan p, const double *b, double *x, double rtol,
                    int *iters, double *relres);
+// rel = ||G - A(U)||_F / ||G||_F; est (if non-null): the plan's error bound
+// from the same residual (pd_info.est_rel_error), or -1
 pd_status pd_residual_impl(pd_plan p, const double *u0, const double *F,
-                           const double *U, double *rel);
+                           const double *U, double *rel, double *est = nullptr);
 pd_status pd_sum_norms(pd_plan p, int nblk, double *rn2, double *gn2);
 // Algorithm 2 (fom.hip)
 constexpr int PD_FOM_MAXM = 32;   // largest Krylov dimension of Algorithm 2

@@ -528,6 +528,30 @@ extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double t
     coef[5 * n + i] = (i < n - 1) ? tk * K->upper[i] : 0.0;
   }
   std::vector<float> coef32(coef.begin(), coef.end());
+  // Error bound factor.  With M symmetric positive definite and K symmetric
+  // positive semi-definite, the scaled step (I + tau M^-1/2 K M^-1/2)^-1 has
+  // norm at most 1, so the error E of any U solves a block-bidiagonal system
+  // whose solution obeys ||M^1/2 E_j|| <= sum_{i<=j} ||M^-1/2 R_i||, hence
+  // ||M^1/2 E||_F <= sqrt(ell (ell + 1) / 2) ||M^-1/2 R||_F; relative to
+  // ||M^1/2 U||_F >= ||M U||_F / sqrt(lmax(M)) that is the factor below
+  // times ||R||_F / ||M U||_F.  Symmetry is checked exactly and the
+  // eigenvalue bounds by Gershgorin's theorem (backward Euler only; in 2D
+  // with M = I, where K's Kronecker sum inherits the 1D bound).
+  if (p->bdf_s == 1 && (p->dims == 1 || M == nullptr)) {
+    bool sym = true;
+    double mlo = HUGE_VAL, mhi = 0.0, klo = HUGE_VAL, kmax = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double ml = coef[i], md = coef[n + i], mu = coef[2 * n + i];
+      const double kl = coef[3 * n + i], kd = coef[4 * n + i], ku = coef[5 * n + i];
+      if (i + 1 < n) sym = sym && coef[2 * n + i] == coef[i + 1] && coef[5 * n + i] == coef[3 * n + i + 1];
+      mlo = std::min(mlo, md - std::fabs(ml) - std::fabs(mu));
+      mhi = std::max(mhi, md + std::fabs(ml) + std::fabs(mu));
+      klo = std::min(klo, kd - std::fabs(kl) - std::fabs(ku));
+      kmax = std::max(kmax, std::fabs(kd));
+    }
+    if (sym && mlo > 0.0 && klo >= -1e-12 * kmax)
+      p->err_factor = std::sqrt(0.5 * (double)ell * (double)(ell + 1)) * std::sqrt(mhi / mlo);
+  }
   // constant diagonals (uniform grids): the shifted solves use six scalars
   {
     bool uni = true;

@@ -211,10 +211,11 @@ extern "C" pd_status paradiag_residual_noalloc(pd_plan p, const double *u0, cons
 }
 
 pd_status pd_residual_impl(pd_plan p, const double *u0, const double *F, const double *U,
-                           double *rel) {
+                           double *rel, double *est) {
   double a, b, c;
   pd_status st = pd_residual_norms(p, u0, F, U, &a, &b, &c);
   if (st != PD_OK) return st;
   *rel = (b > 0.0) ? std::sqrt(a / b) : std::sqrt(a);
+  if (est) *est = (p->err_factor > 0.0 && c > 0.0) ? p->err_factor * std::sqrt(a / c) : -1.0;
   return PD_OK;
 }

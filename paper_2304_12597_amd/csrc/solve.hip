@@ -142,10 +142,13 @@ pd_status solve_speculative(pd_plan p, const double *u0, const double *F, double
     info->gmres_rel_residual = beta > 0.0 ? res / beta : 0.0;
   }
   if (p->check_residual) {
-    double rel;
-    st = pd_residual_impl(p, u0, F, U, &rel);
+    double rel, est;
+    st = pd_residual_impl(p, u0, F, U, &rel, &est);
     if (st != PD_OK) return st;
-    if (info) info->rel_residual = rel;
+    if (info) {
+      info->rel_residual = rel;
+      info->est_rel_error = est;
+    }
   }
   if (gst == PD_ENOTCONV) pd_set_error("tolerance not reached");
   return gst;
@@ -170,10 +173,13 @@ pd_status solve_sine(pd_plan p, const double *u0, const double *F, double *U, pd
     info->gmres_rel_residual = 0.0;
   }
   if (p->check_residual) {
-    double rel;
-    st = pd_residual_impl(p, u0, F, U, &rel);
+    double rel, est;
+    st = pd_residual_impl(p, u0, F, U, &rel, &est);
     if (st != PD_OK) return st;
-    if (info) info->rel_residual = rel;
+    if (info) {
+      info->rel_residual = rel;
+      info->est_rel_error = est;
+    }
   }
   PD_HIP_CHECK(hipStreamSynchronize(p->stream));
   return PD_OK;
@@ -204,10 +210,13 @@ pd_status solve_fom(pd_plan p, const double *u0, const double *F, double *U, dou
     info->gmres_rel_residual = rr;
   }
   if (p->check_residual) {
-    double rel;
-    st = pd_residual_impl(p, u0, F, U, &rel);
+    double rel, est;
+    st = pd_residual_impl(p, u0, F, U, &rel, &est);
     if (st != PD_OK) return st;
-    if (info) info->rel_residual = rel;
+    if (info) {
+      info->rel_residual = rel;
+      info->est_rel_error = est;
+    }
   }
   if (fst == PD_ENOTCONV) pd_set_error("Algorithm 2 did not reach the tolerance");
   return fst;
@@ -241,6 +250,7 @@ extern "C" pd_status paradiag_solve(pd_plan p, const double *u0, const double *F
     info->rel_residual = -1.0;
     info->gmres_rel_residual = -1.0;
     info->early_exit = 0;
+    info->est_rel_error = -1.0;
   }
   pd_status gst = PD_OK;
   if (p->bdf_s > 1) return pd_bdf_solve(p, u0, F, U, tol, info);
@@ -321,10 +331,18 @@ extern "C" pd_status paradiag_solve(pd_plan p, const double *u0, const double *F
     }
     if (swaps & 1) std::swap(p->spec, p->spec2);
     if (stalled) pd_set_error("refinement stalled: the residual stopped falling");
-    if (rel < 0.0) {
-      st = pd_residual_impl(p, u0, F, U, &rel);
+    const bool checked = rel >= 0.0;   // the loop's last check is of this U
+    if (!checked || p->check_residual) {
+      // the standalone residual: the stopping test after the last sweep, or
+      // the accuracy report (with the error bound) when it was asked for
+      double r2, est;
+      st = pd_residual_impl(p, u0, F, U, &r2, &est);
       if (st != PD_OK) return st;
-      converged = rel <= tol;
+      if (!checked) {
+        rel = r2;
+        converged = rel <= tol;
+      }
+      if (info) info->est_rel_error = est;
     }
     if (info) info->rel_residual = rel;
     final_status = converged ? PD_OK : PD_ENOTCONV;
@@ -334,10 +352,13 @@ extern "C" pd_status paradiag_solve(pd_plan p, const double *u0, const double *F
     }
   } else {
     if (p->check_residual) {
-      double rel;
-      st = pd_residual_impl(p, u0, F, U, &rel);
+      double rel, est;
+      st = pd_residual_impl(p, u0, F, U, &rel, &est);
       if (st != PD_OK) return st;
-      if (info) info->rel_residual = rel;
+      if (info) {
+        info->rel_residual = rel;
+        info->est_rel_error = est;
+      }
     }
     PD_HIP_CHECK(hipStreamSynchronize(p->stream));
   }

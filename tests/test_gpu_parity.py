@@ -444,3 +444,51 @@ def test_autotuned_plan(lib, n, ell):
     finally:
         lib.paradiag_plan_destroy(plan)
         lib.paradiag_plan_destroy(plan2)
+
+
+def _mnorm_rel_err(p, U, Uex):
+    """||M^1/2 (Uex - U)||_F / ||M^1/2 U||_F (x^T M x summed over time rows)."""
+    Msp, _ = problem_matrices(p)
+    E = Uex - U
+    num = float(np.sum(E * np.asarray((Msp @ E.T).T)))
+    den = float(np.sum(U * np.asarray((Msp @ U.T).T)))
+    return np.sqrt(num / den)
+
+
+@pytest.mark.parametrize("case,prec", [("fd1", 0), ("fem1", 0), ("fem1-ill", 0), ("fd2", 0),
+                                       ("fem1", 1), ("fd2", 1)])
+def test_error_bound_holds(lib, case, prec):
+    """info.est_rel_error bounds the M-norm error against the exact discrete
+    solution (oracle's modal form): each backward-Euler step is an M-norm
+    contraction for SPD M and SPSD K, so sqrt(ell (ell+1) / 2)
+    sqrt(kappa(M)) ||R|| / ||M U|| bounds it (kappa by Gershgorin)."""
+    rng = np.random.default_rng(31)
+    dims = 1
+    if case == "fd1":
+        p = wl.heat_1d("fd1", 63, 32, 1.0, 1.0, rng, True)
+    elif case == "fem1":
+        p = wl.heat_1d("fem1", 255, 64, 1.0, 1.0, rng, True)
+    elif case == "fem1-ill":
+        p = wl.heat_1d("fem1", 1023, 256, 1.0, 1e-3, rng, True)
+    else:
+        p, dims = wl.heat_2d(31, 16, 0.1, 1.0, rng), 2
+    U, info = _solve(lib, p, prec=prec, tol=1e-10, dims=dims)
+    err = _mnorm_rel_err(p, U, modal.modal_solution(p))
+    assert info.rel_residual >= 0 and info.est_rel_error > 0, info.as_dict()
+    assert err <= info.est_rel_error, (err, info.as_dict())
+    assert info.est_rel_error < 1e-5, info.as_dict()      # and it is informative
+
+
+def test_error_bound_absent_when_not_applicable(lib):
+    """A non-symmetric K (a convection term) or a BDF plan: no bound (-1)."""
+    import dataclasses
+    p = wl.heat_1d("fd1", 63, 32, 1.0, 1.0, np.random.default_rng(32), True)
+    U, info = _solve(lib, p, tol=1e-10)
+    assert info.est_rel_error > 0
+    lower, diag, upper = (np.array(a, dtype=np.float64) for a in p.K)
+    q = dataclasses.replace(p, K=(lower, diag, 0.9 * upper))     # K no longer symmetric
+    U, info = _solve(lib, q, tol=1e-10)
+    assert info.rel_residual >= 0 and info.est_rel_error == -1.0, info.as_dict()
+    b = dataclasses.replace(p, u0=np.tile(p.u0, (2, 1)))         # BDF2: s = 2 starting values
+    U, info = _solve(lib, b, tol=1e-10, bdf_order=2)
+    assert info.est_rel_error == -1.0, info.as_dict()
