@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/paradiag.h"
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 // ---------------------------------------------------------------------------
 // complex helpers (interleaved re/im, real type R = double or float)
@@ -306,6 +307,16 @@ struct pd_plan_s {
   double *cp_tab = nullptr;
 };
 constexpr int PD_BDF_GCH = 16;   // frequency chunks of the BDF capacitance product
+
+// A named host range for profilers (roctx; shown by rocprofv3 --marker-trace):
+// the stages of a solve as the host enqueues them.  A push and a pop per
+// range, nothing else, when no profiler is attached.
+struct PdRange {
+  explicit PdRange(const char *name) { roctxRangePushA(name); }
+  ~PdRange() { roctxRangePop(); }
+  PdRange(const PdRange &) = delete;
+  PdRange &operator=(const PdRange &) = delete;
+};
 
 // error reporting
 void pd_set_error(const std::string &msg);

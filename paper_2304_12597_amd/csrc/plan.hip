@@ -444,6 +444,7 @@ extern "C" void paradiag_default_options(pd_options *opt) {
 extern "C" pd_status paradiag_plan_create(pd_plan *out, int n, int ell, double tau,
                                           const pd_tridiag *M, const pd_tridiag *K,
                                           const pd_options *opt_in) {
+  PdRange whole("paradiag_plan_create");
   g_last_error.clear();
   if (!out) {
     pd_set_error("out is NULL");

@@ -92,18 +92,34 @@ pd_status sweep_tail(pd_plan p, double *U, double tol, int has_mass, int accumul
 pd_status solve_speculative(pd_plan p, const double *u0, const double *F, double *U, double tol,
                             pd_info *info) {
   const double rtol = pd_gmres_tol(p->prec, tol);
-  pd_status st = pd_launch_tridiag(p, 0, p->spec, nullptr, nullptr);
-  if (st != PD_OK) return st;
-  st = pd_launch_reduce_partials(p, nullptr, p->bvec);
-  if (st != PD_OK) return st;
+  pd_status st;
+  {
+    PdRange r("paradiag: pass B (shifted solves, b)");
+    st = pd_launch_tridiag(p, 0, p->spec, nullptr, nullptr);
+    if (st != PD_OK) return st;
+    st = pd_launch_reduce_partials(p, nullptr, p->bvec);
+    if (st != PD_OK) return st;
+  }
   const int pred = p->gm_pred < 1 ? 1 : (p->gm_pred > p->maxit ? p->maxit : p->gm_pred);
-  st = pd_gmres_enqueue(p, p->bvec, p->xvec, rtol, pred);
-  if (st != PD_OK) return st;
-  st = pd_launch_tridiag(p, 1, p->spec, p->xvec, p->spec);
-  if (st != PD_OK) return st;
-  st = pd_inverse(p, p->spec, U, 0);
-  if (st != PD_OK) return st;
-  PD_HIP_CHECK(hipStreamSynchronize(p->stream));
+  {
+    PdRange r("paradiag: capacitance GMRES (enqueued ahead)");
+    st = pd_gmres_enqueue(p, p->bvec, p->xvec, rtol, pred);
+    if (st != PD_OK) return st;
+  }
+  {
+    PdRange r("paradiag: pass C (shifted solves)");
+    st = pd_launch_tridiag(p, 1, p->spec, p->xvec, p->spec);
+    if (st != PD_OK) return st;
+  }
+  {
+    PdRange r("paradiag: pass D (inverse transform)");
+    st = pd_inverse(p, p->spec, U, 0);
+    if (st != PD_OK) return st;
+  }
+  {
+    PdRange r("paradiag: wait for the solve");
+    PD_HIP_CHECK(hipStreamSynchronize(p->stream));
+  }
   int m;
   double res, beta;
   bool done;
@@ -252,11 +268,16 @@ extern "C" pd_status paradiag_solve(pd_plan p, const double *u0, const double *F
     info->early_exit = 0;
     info->est_rel_error = -1.0;
   }
+  PdRange whole("paradiag_solve");
   pd_status gst = PD_OK;
   if (p->bdf_s > 1) return pd_bdf_solve(p, u0, F, U, tol, info);
   if (p->sine) return solve_sine(p, u0, F, U, info);
-  pd_status st = pd_forward(p, u0, F, nullptr, p->spec, 0);
-  if (st != PD_OK) return st;
+  pd_status st;
+  {
+    PdRange r("paradiag: pass A (forward transform)");
+    st = pd_forward(p, u0, F, nullptr, p->spec, 0);
+    if (st != PD_OK) return st;
+  }
   if (p->early_exit) {
     // Algorithm 3: U_1 = P^{-1} Ghat F^{-T} D_alpha^{-1} (pass C with x = 0,
     // pass D), accepted when its residual in the original all-at-once system
@@ -293,6 +314,7 @@ extern "C" pd_status paradiag_solve(pd_plan p, const double *u0, const double *F
     bool converged = false, stalled = false;
     int swaps = 0;
     for (int s = 1; s < p->max_sweeps; ++s) {
+      PdRange r("paradiag: refinement sweep");
       // residual of the current iterate, fused with the next forward
       // transform, into the other spectrum buffer: the last correction's
       // spectrum stays in p->spec2
@@ -374,6 +396,7 @@ extern "C" pd_status paradiag_solve_batch(const pd_plan *plans, int count, const
     return PD_EINVAL;
   }
   if (count == 0) return PD_OK;
+  PdRange whole("paradiag_solve_batch");
   for (int i = 0; i < count; ++i)
     if (!plans[i] || !u0[i] || !F[i] || !U[i]) {
       pd_set_error("invalid batch arguments");

@@ -42,6 +42,18 @@ def test_library_exports_every_declared_symbol(built):
     assert not missing, missing
 
 
+def test_library_marks_its_stages_for_profilers(built):
+    """The solve's host stages are roctx ranges (rocprofv3 --marker-trace):
+    the library imports the push/pop pair and names its ranges."""
+    out = subprocess.run(["nm", "-D", "--undefined-only", built], capture_output=True,
+                         text=True, check=True).stdout
+    assert "roctxRangePushA" in out and "roctxRangePop" in out
+    blob = open(built, "rb").read()
+    for name in (b"paradiag_solve", b"paradiag: pass B (shifted solves, b)",
+                 b"paradiag: capacitance GMRES (enqueued ahead)", b"paradiag: refinement sweep"):
+        assert name in blob, name
+
+
 def test_binding_has_every_declared_name(built):
     from paper_2304_12597_amd import binding
     for f in declared_functions():
