@@ -40,6 +40,11 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--count", type=int, default=0, help="ensemble / stream size")
+    ap.add_argument("--ensemble-precision", default="fp64", choices=["fp64", "mixed", "fp32"],
+                    help="ensemble: precision of every plan (mixed plans do not batch: the "
+                         "batched call solves them one after another)")
+    ap.add_argument("--ensemble-autotune", action="store_true",
+                    help="ensemble: plans time their tile widths at creation")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--forms", default="fp64,mixed,sine",
@@ -381,12 +386,14 @@ def bench_ensemble(args, torch, pd, wl, dev):
     count = args.count or 512
     probs = wl.ensemble(count=count)
     stream = torch.cuda.current_stream(dev)
+    prec = {"fp64": pd.PD_FP64, "mixed": pd.PD_MIXED, "fp32": pd.PD_FP32}[args.ensemble_precision]
     plans, u0s, Fs, Us = [], [], [], []
     try:
         for idx, p in enumerate(probs):
             if idx % 64 == 0:
                 print("ensemble: creating plan %d/%d" % (idx, count), file=sys.stderr, flush=True)
-            plans.append(pd.paradiag_plan_create(p.n, p.ell, p.tau, p.M, p.K,
+            plans.append(pd.paradiag_plan_create(p.n, p.ell, p.tau, p.M, p.K, precision=prec,
+                                                 autotune=int(args.ensemble_autotune),
                                                  stream=stream.cuda_stream))
             u0s.append(torch.tensor(p.u0, device=dev))
             Fs.append(torch.tensor(p.F, device=dev))
@@ -413,10 +420,14 @@ def bench_ensemble(args, torch, pd, wl, dev):
         out = {"metric": "space-time unknowns/s (batched ensemble)",
                "value": unknowns / wall, "unit": "space-time unknowns/s", "n_gpus": 1,
                "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall,
-               "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+               "higher_is_better": True,
+               "dtype": {"fp64": "f64", "mixed": "c64+f64", "fp32": "f32"}[args.ensemble_precision],
+               "data": "synthetic",
                "config": {"workload": "ensemble of %d 1D FD heat problems, n in [255,4095], "
                                       "ell in {64..1024}, nu log-uniform [1e-3,1]" % count,
-                          "unknowns": unknowns},
+                          "unknowns": unknowns, "precision": args.ensemble_precision,
+                          "autotune": bool(args.ensemble_autotune)},
+               "sweeps": {"min": min(i.sweeps for i in infos), "max": max(i.sweeps for i in infos)},
                "gmres_iters": {"min": min(its), "max": max(its), "mean": float(np.mean(its))},
                "one_by_one": {"ms": 1e3 * seq, "unknowns_per_s": unknowns / seq}}
         if not args.no_cpu_baseline:
