@@ -288,18 +288,33 @@ dst_x_kernel(int n, int ell, int C, int stride, double tau, const double *__rest
     lds[c * stride + pd_fpad(n + 1)] = cpx<double>{0.0, 0.0};
   }
   constexpr int UNR = 8;
-  const int total = 2 * C * n;
+  // Elements are walked over rows padded to n + 1 (a power of two here), so
+  // (row in block, x) come from shifts; the padding column is skipped.  The
+  // block's first row gives (t0, y0) once; later rows step y with a carry.
+  const int lgNP = __builtin_ctz(n + 1);
+  const int total = (2 * C) << lgNP;
+  const int t0 = r0 / n, y0 = r0 - t0 * n;
+  auto row_ty = [&](int lr, int &t, int &y) {
+    y = y0 + lr;
+    t = t0;
+    if (y >= n) {
+      const int q = y / n;   // one step unless n < 2C
+      t += q;
+      y -= q * n;
+    }
+  };
   for (int base = tid; base < total; base += UNR * T) {
     double vals[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const int idx = base + u * T;
       double v = 0.0;
-      if (idx < total) {
-        const int lr = idx / n, x = idx - lr * n;
+      const int lr = idx >> lgNP, x = idx & n;
+      if (idx < total && x < n) {
         const int row = r0 + lr;
         if (row < rows) {
-          const int t = row / n, y = row - t * n;
+          int t, y;
+          row_ty(lr, t, y);
           const int i = y * n + x;
           if (MODE == 0) {
             v = tau * F[(size_t)t * nbar + i];
@@ -320,8 +335,8 @@ dst_x_kernel(int n, int ell, int C, int stride, double tau, const double *__rest
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const int idx = base + u * T;
-      if (idx < total) {
-        const int lr = idx / n, x = idx - lr * n;
+      const int lr = idx >> lgNP, x = idx & n;
+      if (idx < total && x < n) {
         double *p1 = reinterpret_cast<double *>(&lds[(lr >> 1) * stride + pd_fpad(x + 1)]);
         double *p2 = reinterpret_cast<double *>(&lds[(lr >> 1) * stride + pd_fpad(N - 1 - x)]);
         p1[lr & 1] = vals[u];
@@ -339,24 +354,24 @@ dst_x_kernel(int n, int ell, int C, int stride, double tau, const double *__rest
     for (int u = 0; u < UNR; ++u) {
       const int idx = base + u * T;
       const int ic = idx < total ? idx : 0;
-      const int lr = ic / n, m = ic - lr * n;
+      const int lr = ic >> lgNP, m0 = ic & n, m = m0 < n ? m0 : n - 1;
       const cpx<double> z = lds[(lr >> 1) * stride + pd_fpad(m + 1)];
       s[u] = ((lr & 1) ? z.re : -z.im) * scale;
       if (ACC) {
-        int row = r0 + lr;
-        row = row < rows ? row : rows - 1;
-        const int t = row / n, y = row - t * n;
+        int t, y;
+        row_ty(r0 + lr < rows ? lr : rows - 1 - r0, t, y);
         s[u] += out[(size_t)t * nbar + (size_t)y * n + m];
       }
     }
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const int idx = base + u * T;
-      if (idx < total) {
-        const int lr = idx / n, m = idx - lr * n;
+      const int lr = idx >> lgNP, m = idx & n;
+      if (idx < total && m < n) {
         const int row = r0 + lr;
         if (row < rows) {
-          const int t = row / n, y = row - t * n;
+          int t, y;
+          row_ty(lr, t, y);
           out[(size_t)t * nbar + (size_t)y * n + m] = s[u];
         }
       }

@@ -17,7 +17,7 @@
 namespace {
 
 template <typename R, int MR, int MODE>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(512, 4)
 line2d_kernel(int n, int F2, int P, int S, int mgroups, int kchunk,
               const cpx<R> *__restrict__ fac, R toff, const double *__restrict__ gw,
               const cpx<R> *__restrict__ in, const double *__restrict__ vin,
@@ -58,6 +58,10 @@ line2d_kernel(int n, int F2, int P, int S, int mgroups, int kchunk,
   }
   const cpx<R> zero = {R(0), R(0)};
   const cpx<R> cc = {toff, R(0)};
+  // tile entry idx = y S + gg (S a power of two): shifts, no division
+  const int lgS = __builtin_ctz(S);
+  const int tile = n * S;
+  constexpr int U = 8;   // loads in flight per thread
 
   double acc[(MODE == 1) ? 1 : MR];
   R xr[(MODE == 2) ? 1 : MR];   // mode 1: -w x on this line; mode 2: v on this line
@@ -78,13 +82,25 @@ line2d_kernel(int n, int F2, int P, int S, int mgroups, int kchunk,
       lfac_all[idx] = fac[((size_t)k * n + mm) * NF + j];
     }
     if constexpr (MODE != 2) {
+      // U loads in flight per thread (at clamped, valid addresses), then the
+      // LDS stores; columns past n stage zeros
       const cpx<R> *src = in + (size_t)k * nbar;
-      for (int idx = tid; idx < n * S; idx += blockDim.x) {
-        const int y = idx / S, gg = idx - y * S;
-        const int mm = m0 + gg;
-        cpx<R> v = zero;
-        if (mm < n) v = src[(size_t)y * n + mm];
-        reinterpret_cast<cpx<R> *>(smem_raw)[(size_t)gg * sstride + y + 1] = v;
+      for (int b = tid; b < tile; b += U * (int)blockDim.x) {
+        cpx<R> v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int idx = b + u * (int)blockDim.x;
+          const int ic = idx < tile ? idx : tile - 1;
+          const int y = ic >> lgS, mm = m0 + (ic & (S - 1));
+          const cpx<R> t = src[(size_t)y * n + (mm < n ? mm : n - 1)];
+          v[u] = pd_sel(mm < n, t, zero);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int idx = b + u * (int)blockDim.x;
+          if (idx < tile)
+            reinterpret_cast<cpx<R> *>(smem_raw)[(size_t)(idx & (S - 1)) * sstride + (idx >> lgS) + 1] = v[u];
+        }
       }
     }
     __syncthreads();
@@ -110,8 +126,8 @@ line2d_kernel(int n, int F2, int P, int S, int mgroups, int kchunk,
         if (q < len) stage[s0 + q + 1] = d[q];
       __syncthreads();
       cpx<R> *dst = out + (size_t)k * nbar;
-      for (int idx = tid; idx < n * S; idx += blockDim.x) {
-        const int y = idx / S, gg = idx - y * S;
+      for (int idx = tid; idx < tile; idx += blockDim.x) {
+        const int y = idx >> lgS, gg = idx & (S - 1);
         const int mm = m0 + gg;
         if (mm < n)
           dst[(size_t)y * n + mm] =
@@ -133,8 +149,8 @@ line2d_kernel(int n, int F2, int P, int S, int mgroups, int kchunk,
     __syncthreads();
     const int kc = blockIdx.x / mgroups;
     double *dst = partials + (size_t)kc * nbar;
-    for (int idx = tid; idx < n * S; idx += blockDim.x) {
-      const int y = idx / S, gg = idx - y * S;
+    for (int idx = tid; idx < tile; idx += blockDim.x) {
+      const int y = idx >> lgS, gg = idx & (S - 1);
       const int mm = m0 + gg;
       if (mm < n) dst[(size_t)y * n + mm] = sd[(size_t)gg * rows + y];
     }
