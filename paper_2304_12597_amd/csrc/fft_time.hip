@@ -270,7 +270,7 @@ template <int MODE, int ACC>
 __global__ void __launch_bounds__(1024)
 dst_x_kernel(int n, int ell, int C, int stride, double tau, const double *__restrict__ u0,
              const double *__restrict__ F, const double *__restrict__ U,
-             const double *__restrict__ in, const double *__restrict__ coef,
+             const double *__restrict__ in, const double *__restrict__ coef, Stencil2 sk,
              const cpx<double> *__restrict__ tw, double *__restrict__ out,
              double *__restrict__ red) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -321,7 +321,7 @@ dst_x_kernel(int n, int ell, int C, int stride, double tau, const double *__rest
             if (t == 0) v += u0[i];
           } else if (MODE == 1) {
             double r, g;
-            residual_point(t, i, n, nbar, 2, tau, u0, F, U, coef, r, g);
+            residual_point_2d(t, x, y, n, nbar, tau, u0, F, U, coef, sk, r, g);
             rn2 += r * r;
             gn2 += g * g;
             v = r;
@@ -481,7 +481,8 @@ __global__ void __launch_bounds__(1024)
 dst_x_chirp_kernel(int n, int ell, int Lc, int C, int stride, double tau,
                    const double *__restrict__ u0, const double *__restrict__ F,
                    const double *__restrict__ U, const double *__restrict__ in,
-                   const double *__restrict__ coef, const cpx<double> *__restrict__ tw,
+                   const double *__restrict__ coef, Stencil2 sk,
+                   const cpx<double> *__restrict__ tw,
                    const cpx<double> *__restrict__ chirp, const cpx<double> *__restrict__ bhat,
                    double *__restrict__ out, double *__restrict__ red) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -521,7 +522,7 @@ dst_x_chirp_kernel(int n, int ell, int Lc, int C, int stride, double tau,
             if (t == 0) v += u0[i];
           } else if (MODE == 1) {
             double r, g;
-            residual_point(t, i, n, nbar, 2, tau, u0, F, U, coef, r, g);
+            residual_point_2d(t, x, y, n, nbar, tau, u0, F, U, coef, sk, r, g);
             rn2 += r * r;
             gn2 += g * g;
             v = r;
@@ -645,6 +646,16 @@ int pd_choose_dst_C(int n) {
 
 int pd_dst_blocks(pd_plan p) { return dst_config(p, p->ell).blocks; }
 
+// tau T's constant diagonals for the residual stencil on uniform grids
+static Stencil2 pd_stencil2(pd_plan p) {
+  Stencil2 s;
+  s.uni = p->uniform ? 1 : 0;
+  s.kl = p->uni[3];
+  s.kd = p->uni[4];
+  s.ku = p->uni[5];
+  return s;
+}
+
 pd_status pd_launch_dst_x(pd_plan p, int mode, const double *u0, const double *F,
                           const double *U, const double *in, double *out, int accumulate) {
   DstLaunch L = dst_config(p, p->ell);
@@ -655,7 +666,7 @@ pd_status pd_launch_dst_x(pd_plan p, int mode, const double *u0, const double *F
 #define PD_DSTC(M, A)                                                                        \
   hipLaunchKernelGGL((dst_x_chirp_kernel<M, A>), dim3(L.blocks), dim3(L.threads), L.lds,     \
                      p->stream, p->n, p->ell, p->dst_L, L.C, L.stride, p->tau, u0, F, U, in,  \
-                     p->coef64, tw, ch, bh, out, p->red)
+                     p->coef64, pd_stencil2(p), tw, ch, bh, out, p->red)
     if (mode == 0) PD_DSTC(0, 0);
     else if (mode == 1) PD_DSTC(1, 0);
     else if (accumulate) PD_DSTC(2, 1);
@@ -666,8 +677,8 @@ pd_status pd_launch_dst_x(pd_plan p, int mode, const double *u0, const double *F
   }
 #define PD_DST(M, A)                                                                        \
   hipLaunchKernelGGL((dst_x_kernel<M, A>), dim3(L.blocks), dim3(L.threads), L.lds, p->stream, \
-                     p->n, p->ell, L.C, L.stride, p->tau, u0, F, U, in, p->coef64, tw, out,   \
-                     p->red)
+                     p->n, p->ell, L.C, L.stride, p->tau, u0, F, U, in, p->coef64,            \
+                     pd_stencil2(p), tw, out, p->red)
   if (mode == 0) PD_DST(0, 0);
   else if (mode == 1) PD_DST(1, 0);
   else if (accumulate) PD_DST(2, 1);
@@ -689,22 +700,22 @@ pd_status pd_launch_dst_x_rows(pd_plan p, const double *in, double *out, int tro
     if (accumulate)
       hipLaunchKernelGGL((dst_x_chirp_kernel<2, 1>), dim3(L.blocks), dim3(L.threads), L.lds,
                          p->stream, p->n, trows, p->dst_L, L.C, L.stride, p->tau, nullptr,
-                         nullptr, nullptr, in, p->coef64, tw, ch, bh, out, p->red);
+                         nullptr, nullptr, in, p->coef64, pd_stencil2(p), tw, ch, bh, out, p->red);
     else
       hipLaunchKernelGGL((dst_x_chirp_kernel<2, 0>), dim3(L.blocks), dim3(L.threads), L.lds,
                          p->stream, p->n, trows, p->dst_L, L.C, L.stride, p->tau, nullptr,
-                         nullptr, nullptr, in, p->coef64, tw, ch, bh, out, p->red);
+                         nullptr, nullptr, in, p->coef64, pd_stencil2(p), tw, ch, bh, out, p->red);
     PD_HIP_CHECK(hipGetLastError());
     return PD_OK;
   }
   if (accumulate)
     hipLaunchKernelGGL((dst_x_kernel<2, 1>), dim3(L.blocks), dim3(L.threads), L.lds, p->stream,
                        p->n, trows, L.C, L.stride, p->tau, nullptr, nullptr, nullptr, in,
-                       p->coef64, tw, out, p->red);
+                       p->coef64, pd_stencil2(p), tw, out, p->red);
   else
     hipLaunchKernelGGL((dst_x_kernel<2, 0>), dim3(L.blocks), dim3(L.threads), L.lds, p->stream,
                        p->n, trows, L.C, L.stride, p->tau, nullptr, nullptr, nullptr, in,
-                       p->coef64, tw, out, p->red);
+                       p->coef64, pd_stencil2(p), tw, out, p->red);
   PD_HIP_CHECK(hipGetLastError());
   return PD_OK;
 }
@@ -729,11 +740,11 @@ pd_status pd_launch_dst_rows1d(pd_plan p, int mode, const double *u0, const doub
   if (mode == 0)
     hipLaunchKernelGGL((dst_x_chirp_kernel<0, 0, true>), dim3(blocks), dim3(threads), lds,
                        p->stream, p->n, p->ell, N, C, stride, p->tau, u0, F, nullptr, nullptr,
-                       p->coef64, tw, ch, bh, out, p->red);
+                       p->coef64, pd_stencil2(p), tw, ch, bh, out, p->red);
   else
     hipLaunchKernelGGL((dst_x_chirp_kernel<2, 0, true>), dim3(blocks), dim3(threads), lds,
                        p->stream, p->n, p->ell, N, C, stride, p->tau, nullptr, nullptr, nullptr,
-                       in, p->coef64, tw, ch, bh, out, p->red);
+                       in, p->coef64, pd_stencil2(p), tw, ch, bh, out, p->red);
   PD_HIP_CHECK(hipGetLastError());
   return PD_OK;
 }

@@ -3,6 +3,49 @@
 #pragma once
 #include "pd_internal.h"
 
+// tau T's diagonals for the 2D stencil: constant on uniform grids (uni),
+// then no coefficient loads per point
+struct Stencil2 {
+  int uni;
+  double kl, kd, ku;
+};
+
+// The 2D residual at point (x, y) of time row t (i = y n + x) for callers
+// that walk x and y: the same expressions as residual_point's 2D branch, with
+// tau T's diagonals from the scalars when uniform (the boundary entries they
+// would differ in are never used).
+static __device__ __forceinline__ void residual_point_2d(int t, int x, int y, int n, int nbar,
+                                                  double tau, const double *__restrict__ u0,
+                                                  const double *__restrict__ F,
+                                                  const double *__restrict__ U,
+                                                  const double *__restrict__ coef,
+                                                  const Stencil2 &sk, double &r_out,
+                                                  double &g_out) {
+  const int i = y * n + x;
+  const double *Ft = F + (size_t)t * nbar;
+  const double *Ut = U + (size_t)t * nbar;
+  double h = tau * Ft[i];
+  if (t == 0) h += u0[i];
+  double z = h - Ut[i];
+  if (t > 0) z += U[(size_t)(t - 1) * nbar + i];
+  double kdx, kdy, klx, kux, kly, kuy;
+  if (sk.uni) {
+    kdx = kdy = sk.kd;
+    klx = kly = sk.kl;
+    kux = kuy = sk.ku;
+  } else {
+    const double *KL = coef + 3 * n, *KD = coef + 4 * n, *KU = coef + 5 * n;
+    kdx = KD[x]; kdy = KD[y]; klx = KL[x]; kux = KU[x]; kly = KL[y]; kuy = KU[y];
+  }
+  double ku = (kdx + kdy) * Ut[i];
+  if (x > 0) ku += klx * Ut[i - 1];
+  if (x < n - 1) ku += kux * Ut[i + 1];
+  if (y > 0) ku += kly * Ut[i - n];
+  if (y < n - 1) ku += kuy * Ut[i + n];
+  r_out = z - ku;
+  g_out = h;
+}
+
 // float64 all-at-once residual R_t = G_t - ((M + tau K) u_t - M u_{t-1}) at
 // one space-time point, with G_t = M h_t, h_t = tau f_t (+ u0 at t = 0).
 // coef rows: ML MD MU tKL tKD tKU (tK = tau K; 2D: the 1D factor tau T).
