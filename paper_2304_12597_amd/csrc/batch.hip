@@ -138,6 +138,7 @@ pd_status build_run(BatchRun &r, const pd_plan *plans, int count, const double *
       t.coef64 = p->coef64;
       t.lam = (prec == PD_FP64) ? (const void *)p->lam64 : (const void *)p->lam32;
       t.fac = (prec == PD_FP64) ? (const void *)p->fac64 : (const void *)p->fac32;
+      t.scan = (prec == PD_FP64 && pd_use_scan(p)) ? 1 : 0;
       t.gw = p->gB64; t.in = p->spec; t.vin = nullptr; t.xv = p->xvec; t.wscale = p->w;
       t.out = p->spec; t.partials = p->partials; t.skip = nullptr;
       for (int b = 0; b < t.nblk; ++b) t0b[bi].push_back(make_int2(i, b));

@@ -115,6 +115,7 @@ struct TriJob {
   void *out;
   double *partials;
   const double *skip;   // nonzero: the problem's GMRES has converged (J jobs)
+  int scan;             // the recurrence-form solve (pd_scan.h), P >= 64 float64 only
 };
 
 struct VecJob {     // one problem's vectors for the batched GMRES kernels
@@ -458,6 +459,15 @@ int pd_choose_fft_C(int ell, int nbar, int prec, size_t max_lds);
 inline int pd_tri_nitems(const TriConfig &T, int F2) {
   const int slots = T.pipe ? F2 - 1 : F2;
   return (slots + T.spb - 1) / T.spb;
+}
+
+// The pipelined body solves symmetric Toeplitz systems (uniform 1D grids,
+// M and tau K symmetric) by the recurrence form of pd_scan.h instead of the
+// partition method; the plan's factor table then holds its constants.
+inline bool pd_use_scan(const pd_plan p) {
+  const double *u = p->uni;
+  return p->dims == 1 && p->uniform && p->tri.pipe && p->tri.MR >= 8 && p->tri.P <= 512 &&
+         p->tri.P % 64 == 0 && u[0] == u[2] && u[3] == u[5];
 }
 
 // Threads per shifted-solve block: 512 for complex128 (a 256-register budget

@@ -41,6 +41,10 @@ struct CplxOps {
   }
   static __device__ __forceinline__ cpx<R> recip(cpx<R> a) { return crecip(a); }
   static __device__ __forceinline__ cpx<R> one() { return cpx<R>{R(1), R(0)}; }
+  // s + b*c, one expression per component (fused multiply-adds)
+  static __device__ __forceinline__ cpx<R> fma(cpx<R> s, cpx<R> b, cpx<R> c) {
+    return cpx<R>{s.re + b.re * c.re - b.im * c.im, s.im + b.re * c.im + b.im * c.re};
+  }
 };
 // ... or of two independent real systems held in the real and imaginary
 // parts (the real shifts k = 0 and k = ell/2 share one work item)
@@ -56,6 +60,9 @@ struct DualOps {
     return cpx<R>{R(1) / a.re, R(1) / a.im};
   }
   static __device__ __forceinline__ cpx<R> one() { return cpx<R>{R(1), R(1)}; }
+  static __device__ __forceinline__ cpx<R> fma(cpx<R> s, cpx<R> b, cpx<R> c) {
+    return cpx<R>{s.re + b.re * c.re, s.im + b.im * c.im};
+  }
 };
 
 template <typename R, int MR, typename A = CplxOps<R>, bool LB = false>

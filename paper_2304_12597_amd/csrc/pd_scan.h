@@ -1,0 +1,260 @@
+// Shifted solves of symmetric Toeplitz tridiagonal systems by two first-order
+// recurrences (the pass B / pass C solves of the uniform-grid path).
+//
+// For one frequency the system has constant sub-diagonal a, diagonal b and
+// super-diagonal c.  Let kappa be the root of larger modulus of
+// kappa^2 - b kappa + a c = 0, r1 = -a/kappa, r2 = -c/kappa, rho = r1 r2 and
+// Z the down-shift.  Then kappa (1 + rho) = b and
+//
+//     P = kappa (I - r1 Z)(I - r2 Z^T) + kappa rho e_0 e_0^T,
+//
+// since the product of the two bidiagonal factors reproduces every row of P
+// except the first, where it lacks rho x_0.  With
+// S(y) = (I - r2 Z^T)^{-1} (I - r1 Z)^{-1} y -- a forward recurrence
+// v_i = y_i + r1 v_{i-1} (v_{-1} = 0) and a backward one
+// z_i = v_i + r2 z_{i+1} (z_n = 0) -- and w = S(e_0), the Sherman-Morrison
+// formula for the corner term gives
+//
+//     x = (z - beta z_0 w) / kappa,   beta = rho / (1 + rho w_0).
+//
+// For P symmetric (a = c) r1 = r2 = r with |r| <= 1, so both recurrences
+// are stable.  The corner term needs no second vector: z_0 = sum_i r^i v_i
+// is a weighted sum of the forward values, so beta z_0 is known before the
+// backward recurrence runs, and subtracting beta z_0 r^i from v_i (the
+// forward recurrence of e_0 is r^i) makes the backward recurrence return
+// kappa x directly.
+//
+// A group of P threads solves one system of n <= P*MR rows: thread lt owns
+// rows [lt*MR, lt*MR + len), s0 = lt*MR.  The forward recurrence runs over
+// the thread's rows from a zero start (u_q); the chunk carries are combined
+// by a scan across the group that composes the chunk maps x -> R x + e
+// (R = r^MR): wave shuffles in log2(64) steps, then the waves' totals through
+// LDS.  With ex = v at row s0-1, the chunk's rows are v_q = u_q + r^(q+1) ex,
+// so its share of z_0 is r^s0 (sum_q r^q u_q + ex sum_{q<len} r^(2q+1)), and
+// the corrected rows are u_q + r^q (r ex - beta z_0 r^s0): one pass over the
+// rows after z_0 is summed.  The backward recurrence runs the same way.  No
+// division and three block barriers per solve, against the log2(P)
+// dependent reduction steps of a partition method.  Powers of r inside a
+// chunk are formed by repeated multiplication, and the chunk start
+// r^s0 = R^lt comes out of the forward scan (lane l ends with R^(l+1)).
+//
+// Per-frequency table (complex entries, built on the host by
+// pd_scan_table, read with scalar loads):
+//   0 r1,  1 r2,  2 R1 = r1^MR,  3 R2 = r2^MR,  4 1/kappa,  5 beta,
+//   6 sum_{q<MR} r^(2q+1).
+#pragma once
+#include <complex>
+#include "pd_partition.h"
+
+constexpr int PD_SCAN_ENTRIES = 7;
+
+
+// OPS as for partition_solve: CplxOps (one complex system) or DualOps (two
+// real systems in the real and imaginary parts).  xw: 3*(P/64) complex LDS
+// entries for the group.  LB: LDS-only barriers.  SCALE: return x; otherwise
+// kappa x (the caller folds 1/kappa into its weights).  The group's P threads
+// are whole waves (P a multiple of 64, P <= 512).  Every thread of the block
+// calls this together; rows past the end of the system (q >= len) hold zero
+// on entry and are left undefined.
+template <typename R, int MR, typename A, bool LB, bool SCALE>
+__device__ __forceinline__ void scan_solve(cpx<R> (&d)[MR], int len, int lt, int P,
+                                           const cpx<R> *__restrict__ tb, cpx<R> *xw) {
+  auto barrier = [] {
+    if constexpr (LB)
+      pd_lds_barrier();
+    else
+      __syncthreads();
+  };
+  auto fma = [](cpx<R> s, cpx<R> b, cpx<R> c) { return A::fma(s, b, c); };
+  auto shup = [](cpx<R> v, int s) {
+    return cpx<R>{__shfl_up(v.re, s, 64), __shfl_up(v.im, s, 64)};
+  };
+  auto shdn = [](cpx<R> v, int s) {
+    return cpx<R>{__shfl_down(v.re, s, 64), __shfl_down(v.im, s, 64)};
+  };
+  auto bcast = [](cpx<R> v, int l) { return cpx<R>{__shfl(v.re, l, 64), __shfl(v.im, l, 64)}; };
+  const cpx<R> zero = {R(0), R(0)};
+  int lane = lt & 63;
+  // lane passes through an empty asm: the shuffle indices derived from it
+  // are formed here, not hoisted out of the caller's loop over work items
+  // (where they would hold registers through the whole loop)
+  asm volatile("" : "+v"(lane));
+  const int wv = lt >> 6, NW = P >> 6;
+  const cpx<R> r1 = tb[0], r2 = tb[1];
+  // a wave with a ragged or empty chunk takes the masked loops
+  const bool ragged = __any(len < MR);
+
+  // forward recurrence inside the chunk, from zero: u_q
+  cpx<R> acc = zero;
+#pragma unroll
+  for (int q = 0; q < MR; ++q) {
+    acc = fma(d[q], r1, acc);
+    d[q] = acc;
+  }
+  // scan of the chunk maps x -> R1 x + e_t across the wave (left to right):
+  // lane l ends with R1^(l+1) and v at its chunk's last row from the wave's
+  // start
+  cpx<R> c = acc, m = tb[2];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const int s = 1 << j;
+    const cpx<R> oc = shup(c, s), om = shup(m, s);
+    const bool in = lane >= s;
+    c = pd_sel(in, fma(c, m, oc), c);
+    m = pd_sel(in, A::mul(m, om), m);
+  }
+  cpx<R> ex = pd_sel(lane > 0, shup(c, 1), zero);
+  const cpx<R> pl = pd_sel(lane > 0, shup(m, 1), A::one());   // R1^lane
+  const cpx<R> R64 = bcast(m, 63);                               // R1^64
+  if (lane == 63) xw[wv] = c;
+  // sum_{q<len} r^q u_q by Horner, and sum_{q<len} r^(2q+1)
+  cpx<R> h = zero, K = tb[6];
+  if (!ragged) {
+#pragma unroll
+    for (int q = MR - 1; q >= 0; --q) h = fma(d[q], r1, h);
+  } else {
+    const cpx<R> rr = A::mul(r1, r2);
+    cpx<R> p = r1;
+    K = zero;
+#pragma unroll
+    for (int q = 0; q < MR; ++q) {
+      K = pd_sel(q < len, cadd(K, p), K);
+      p = A::mul(p, rr);
+    }
+#pragma unroll
+    for (int q = MR - 1; q >= 0; --q) h = pd_sel(q < len, fma(d[q], r1, h), h);
+  }
+  // R1^lt = r^s0: the power r^i at the chunk's start
+  cpx<R> a0 = pl;
+  for (int w = 0; w < wv; ++w) a0 = A::mul(a0, R64);
+  barrier();
+  // carry into this wave: the waves before it, in order
+  {
+    cpx<R> C = zero;
+    for (int w = 0; w < wv; ++w) C = fma(xw[w], R64, C);
+    ex = fma(ex, pl, C);   // v at the row before this chunk
+  }
+  // this chunk's share of z_0 = sum_i r^i v_i, summed over the group
+  cpx<R> dot = A::mul(a0, fma(h, ex, K));
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1)
+    dot = cadd(dot, cpx<R>{__shfl_xor(dot.re, s, 64), __shfl_xor(dot.im, s, 64)});
+  if (lane == 0) xw[NW + wv] = dot;
+  barrier();
+  cpx<R> z0 = zero;
+  for (int w = 0; w < NW; ++w) z0 = cadd(z0, xw[NW + w]);
+  // rows of v - beta z_0 r^i = u_q + r^q (r ex - beta z_0 r^s0)
+  {
+    const cpx<R> E = csub(A::mul(r1, ex), A::mul(A::mul(tb[5], z0), a0));
+    cpx<R> pw = A::one();
+    if (!ragged) {
+#pragma unroll
+      for (int q = 0; q < MR; ++q) {
+        d[q] = fma(d[q], pw, E);
+        pw = A::mul(pw, r1);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < MR; ++q) {
+        d[q] = pd_sel(q < len, fma(d[q], pw, E), zero);
+        pw = A::mul(pw, r1);
+      }
+    }
+  }
+  // backward recurrence inside the chunk, from zero
+  acc = zero;
+#pragma unroll
+  for (int q = MR - 1; q >= 0; --q) {
+    acc = fma(d[q], r2, acc);
+    d[q] = acc;
+  }
+  // the same scan from the right: lane l ends with R2^(64-l) and the
+  // value at its chunk's first row from the wave's end
+  cpx<R> cz = acc;
+  m = tb[3];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const int s = 1 << j;
+    const cpx<R> oz = shdn(cz, s), om = shdn(m, s);
+    const bool in = lane + s < 64;
+    cz = pd_sel(in, fma(cz, m, oz), cz);
+    m = pd_sel(in, A::mul(m, om), m);
+  }
+  cpx<R> exz = pd_sel(lane < 63, shdn(cz, 1), zero);
+  const cpx<R> pr = pd_sel(lane < 63, shdn(m, 1), A::one());   // R2^(63-lane)
+  const cpx<R> S64 = bcast(m, 0);                                // R2^64
+  if (lane == 0) xw[2 * NW + wv] = cz;
+  barrier();
+  {
+    cpx<R> CZ = zero;
+    for (int w = NW - 1; w > wv; --w) CZ = fma(xw[2 * NW + w], S64, CZ);
+    exz = fma(exz, pr, CZ);   // the value at the row after this chunk
+  }
+  cpx<R> p2 = r2;   // r^(MR-q)
+  if constexpr (SCALE) {
+    const cpx<R> ik = tb[4];
+    exz = A::mul(ik, exz);
+#pragma unroll
+    for (int q = MR - 1; q >= 0; --q) {
+      d[q] = fma(A::mul(ik, d[q]), p2, exz);
+      p2 = A::mul(p2, r2);
+    }
+  } else {
+#pragma unroll
+    for (int q = MR - 1; q >= 0; --q) {
+      d[q] = fma(d[q], p2, exz);
+      p2 = A::mul(p2, r2);
+    }
+  }
+}
+
+// The table above for one frequency (host).  a, b, c: the constant sub-,
+// main and super-diagonal; real: the system is real (lambda real), so the
+// discriminant is clamped at zero and every entry is real.  Computed in long
+// double and rounded once.
+inline void pd_scan_table(std::complex<double> a, std::complex<double> b, std::complex<double> c,
+                          bool real, int n, int MR, std::complex<double> *dst) {
+  using C = std::complex<long double>;
+  const C A(a.real(), a.imag()), B(b.real(), b.imag()), Cc(c.real(), c.imag());
+  C kap;
+  if (real) {
+    long double disc = B.real() * B.real() - 4.0L * A.real() * Cc.real();
+    if (disc < 0.0L) disc = 0.0L;
+    const long double s = std::sqrt(disc);
+    kap = C(B.real() >= 0.0L ? (B.real() + s) / 2.0L : (B.real() - s) / 2.0L, 0.0L);
+  } else {
+    const C s = std::sqrt(B * B - 4.0L * A * Cc);
+    const C k1 = (B + s) / 2.0L, k2 = (B - s) / 2.0L;
+    kap = std::abs(k1) >= std::abs(k2) ? k1 : k2;
+  }
+  const C r1 = -A / kap, r2 = -Cc / kap, rho = r1 * r2;
+  auto put = [&](int i, C v) { dst[i] = std::complex<double>((double)v.real(), (double)v.imag()); };
+  C R1 = 1.0L, R2 = 1.0L;
+  for (int q = 0; q < MR; ++q) {
+    R1 *= r1;
+    R2 *= r2;
+  }
+  put(0, r1);
+  put(1, r2);
+  put(2, R1);
+  put(3, R2);
+  // w_0 = sum_{m < n} rho^m by doubling: (S, rho^m) for the bits of n
+  C S = 0.0L, pm = 1.0L, Sb = 1.0L, pb = rho;
+  for (int m = n; m; m >>= 1) {
+    if (m & 1) {
+      S += pm * Sb;
+      pm *= pb;
+    }
+    Sb += pb * Sb;
+    pb *= pb;
+  }
+  const C ik = 1.0L / kap, beta = rho / (1.0L + rho * S);
+  put(4, ik);
+  put(5, beta);
+  C K = 0.0L, p = r1;
+  for (int q = 0; q < MR; ++q) {
+    K += p;
+    p *= rho;
+  }
+  put(6, K);
+}

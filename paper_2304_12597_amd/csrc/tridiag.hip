@@ -22,6 +22,7 @@
 // the conjugate half implied) into per-block float64 partial sums; 1 writes
 // y_k; 2 accumulates the capacitance product sum_k w gamma_k P_k^{-1} M v.
 #include "pd_partition.h"
+#include "pd_scan.h"
 
 #include <algorithm>
 #include <type_traits>
@@ -568,7 +569,7 @@ __device__ __forceinline__ int pipe_entry(int lt, int q) {
   return lt * MR + ((q + (lt >> LG)) & (MR - 1));
 }
 
-template <int MR, int MODE>
+template <int MR, int MODE, bool SCAN>
 __device__ __forceinline__ void tridiag_pipe_body(
     int blk, int nblk, int n, int F2, int P, int spb, int nitems, const Coef<double> &cf,
     const double *__restrict__ coef64, const double *__restrict__ lam,
@@ -663,11 +664,14 @@ __device__ __forceinline__ void tridiag_pipe_body(
         }
       }
     }
-    const Cx *fsrc = fac + (size_t)(sl == 0 ? F2 : sl) * NF;
-    Cx *fdst = facb + ((size_t)b * spb + g) * NFP;
-    for (int c0 = wib * 64; c0 < NFP; c0 += P) {
-      const int idx = c0 + (lt & 63);
-      pd_lds_dma16(fsrc + (idx < NF ? idx : NF - 1), fdst + c0);
+    if constexpr (!SCAN) {
+      // (the recurrence form reads its constants with scalar loads instead)
+      const Cx *fsrc = fac + (size_t)(sl == 0 ? F2 : sl) * NF;
+      Cx *fdst = facb + ((size_t)b * spb + g) * NFP;
+      for (int c0 = wib * 64; c0 < NFP; c0 += P) {
+        const int idx = c0 + (lt & 63);
+        pd_lds_dma16(fsrc + (idx < NF ? idx : NF - 1), fdst + c0);
+      }
     }
   };
 
@@ -687,6 +691,19 @@ __device__ __forceinline__ void tridiag_pipe_body(
       gr = gw[2 * k];
       gi = gw[2 * k + 1];
       grB = gw[2 * kB];
+      if constexpr (SCAN) {
+        // the recurrence form returns kappa_k y_k: fold 1/kappa_k into the
+        // weights
+        const Cx ik = fac[(size_t)(DUAL ? F2 : k) * NF + 4];
+        if (DUAL) {
+          gr *= ik.re;
+          grB *= ik.im;
+        } else {
+          const double t = gr * ik.re - gi * ik.im;
+          gi = gr * ik.im + gi * ik.re;
+          gr = t;
+        }
+      }
     }
     // sub- and super-diagonals: complex, or (k = 0, k = ell/2) componentwise
     const Cx ca = DUAL ? Cx{lr * cf.ml + cf.kl, lrB * cf.ml + cf.kl}
@@ -729,7 +746,10 @@ __device__ __forceinline__ void tridiag_pipe_body(
     // 16 rows per thread the second copy would not fit in registers)
     // LDS-only barriers: the next item's prefetch keeps streaming in through
     // the reduction (xch does not alias the staging area)
-    if (!DUAL && MR <= 8 && __all(len == MR))
+    if constexpr (SCAN)
+      scan_solve<R, MR, OPS, true, MODE == 1>(d, len, lt, P, fac + (size_t)(DUAL ? F2 : k) * NF,
+                                   reinterpret_cast<Cx *>(xch));
+    else if (!DUAL && MR <= 8 && __all(len == MR))
       partition_solve<R, MR, OPS, true>(d, MR, lt, P, lfac, xch, ca, cc);
     else
       partition_solve<R, MR, OPS, true>(d, len, lt, P, lfac, xch, ca, cc);
@@ -844,7 +864,7 @@ __device__ __forceinline__ void tridiag_pipe_body(
 }
 
 // skip: if non-null and nonzero (a converged GMRES), the launch does nothing
-template <int MR, int MODE>
+template <int MR, int MODE, bool SCAN>
 __global__ void __launch_bounds__(512)
 tridiag_pipe_kernel(int n, int F2, int P, int spb, int nitems, Coef<double> cf,
                     const double *__restrict__ coef64, const double *__restrict__ lam,
@@ -854,7 +874,7 @@ tridiag_pipe_kernel(int n, int F2, int P, int spb, int nitems, Coef<double> cf,
                     cpx<double> *__restrict__ out, double *__restrict__ partials,
                     const double *__restrict__ skip) {
   if (skip && *skip != 0.0) return;
-  tridiag_pipe_body<MR, MODE>(blockIdx.x, gridDim.x, n, F2, P, spb, nitems, cf, coef64, lam, fac,
+  tridiag_pipe_body<MR, MODE, SCAN>(blockIdx.x, gridDim.x, n, F2, P, spb, nitems, cf, coef64, lam, fac,
                               gw, in, vin, xv, wscale, rhs_has_mass, out, partials);
 }
 
@@ -944,9 +964,17 @@ void launch_pipe(pd_plan p, int G, int nitems, const Coef<R> &cf, const R *lam,
   if constexpr (sizeof(R) == 8) {
     const TriConfig &T = p->tri;
     if (MR == 16 && T.spb != 1) return;   // excluded by the caller's check
-    hipLaunchKernelGGL((tridiag_pipe_kernel<MR, M>), dim3(G), dim3(T.block), T.lds, p->stream,
-                       p->n, p->F2, T.P, T.spb, nitems, cf, p->coef64, lam, fac, gw, cin, vin, x,
-                       p->w, has_mass, o, part, p->gm_skip);
+    if constexpr (MR >= 8) {
+      if (pd_use_scan(p)) {
+        hipLaunchKernelGGL((tridiag_pipe_kernel<MR, M, true>), dim3(G), dim3(T.block), T.lds,
+                           p->stream, p->n, p->F2, T.P, T.spb, nitems, cf, p->coef64, lam, fac,
+                           gw, cin, vin, x, p->w, has_mass, o, part, p->gm_skip);
+        return;
+      }
+    }
+    hipLaunchKernelGGL((tridiag_pipe_kernel<MR, M, false>), dim3(G), dim3(T.block), T.lds,
+                       p->stream, p->n, p->F2, T.P, T.spb, nitems, cf, p->coef64, lam, fac, gw,
+                       cin, vin, x, p->w, has_mass, o, part, p->gm_skip);
   }
 }
 
@@ -1115,6 +1143,22 @@ void pd_uniform_factors(const pd_plan p, int MR, std::vector<double> &fac) {
   const size_t NF = 6 * (size_t)(MR - 1);
   fac.assign((size_t)(F2 + 1) * NF * 2, 0.0);
   const double *u = p->uni;
+  if (pd_use_scan(p) && MR == p->tri.MR) {
+    // recurrence-form constants (pd_scan.h) at the same row stride
+    for (int k = 0; k < F2; ++k) {
+      const double lr = p->lam[2 * k], li = p->lam[2 * k + 1];
+      pd_scan_table({lr * u[0] + u[3], li * u[0]}, {lr * u[1] + u[4], li * u[1]},
+                    {lr * u[2] + u[5], li * u[2]}, li == 0.0, p->n, MR,
+                    reinterpret_cast<std::complex<double> *>(&fac[(size_t)k * NF * 2]));
+    }
+    double *dual = &fac[(size_t)F2 * NF * 2];
+    const double *f0 = &fac[0], *fl = &fac[(size_t)(F2 - 1) * NF * 2];
+    for (size_t j = 0; j < NF; ++j) {
+      dual[2 * j] = f0[2 * j];
+      dual[2 * j + 1] = fl[2 * j];
+    }
+    return;
+  }
   for (int k = 0; k < F2; ++k) {
     const double lr = p->lam[2 * k], li = p->lam[2 * k + 1];
     pd_partition_factors(lr * u[0] + u[3], li * u[0], lr * u[1] + u[4], li * u[1],
@@ -1173,9 +1217,14 @@ void set_attr_mr(int v) {
   for (const void *f : fns)
     pd_set_max_lds(f, v);
   if constexpr (sizeof(R) == 8) {
-    pd_set_max_lds(reinterpret_cast<const void *>(&tridiag_pipe_kernel<MR, 0>), v);
-    pd_set_max_lds(reinterpret_cast<const void *>(&tridiag_pipe_kernel<MR, 1>), v);
-    pd_set_max_lds(reinterpret_cast<const void *>(&tridiag_pipe_kernel<MR, 2>), v);
+    pd_set_max_lds(reinterpret_cast<const void *>(&tridiag_pipe_kernel<MR, 0, false>), v);
+    pd_set_max_lds(reinterpret_cast<const void *>(&tridiag_pipe_kernel<MR, 1, false>), v);
+    pd_set_max_lds(reinterpret_cast<const void *>(&tridiag_pipe_kernel<MR, 2, false>), v);
+    if constexpr (MR >= 8) {
+      pd_set_max_lds(reinterpret_cast<const void *>(&tridiag_pipe_kernel<MR, 0, true>), v);
+      pd_set_max_lds(reinterpret_cast<const void *>(&tridiag_pipe_kernel<MR, 1, true>), v);
+      pd_set_max_lds(reinterpret_cast<const void *>(&tridiag_pipe_kernel<MR, 2, true>), v);
+    }
   }
 }
 }  // namespace
@@ -1205,13 +1254,18 @@ tridiag_batch_kernel(const TriJob *__restrict__ jobs, const int2 *__restrict__ m
   cf.kl = (R)j.kl; cf.kd = (R)j.kd; cf.ku = (R)j.ku;
   if constexpr (sizeof(R) == 8) {
     if (j.P >= 64) {   // the single-problem path's pipelined body (TriConfig::pipe)
-      tridiag_pipe_body<MR, MODE>(m.y, j.nblk, j.n, j.F2, j.P, j.spb, j.nitems, cf, j.coef64,
-                                  reinterpret_cast<const double *>(j.lam),
-                                  reinterpret_cast<const cpx<double> *>(j.fac), j.gw,
-                                  reinterpret_cast<const cpx<double> *>(j.in),
-                                  j.vin ? j.vin + (size_t)jv * j.n : nullptr, j.xv, j.wscale,
-                                  j.has_mass, reinterpret_cast<cpx<double> *>(j.out),
-                                  j.partials);
+      auto body = [&](auto scan) {
+        tridiag_pipe_body<MR, MODE, decltype(scan)::value>(
+            m.y, j.nblk, j.n, j.F2, j.P, j.spb, j.nitems, cf, j.coef64,
+            reinterpret_cast<const double *>(j.lam), reinterpret_cast<const cpx<double> *>(j.fac),
+            j.gw, reinterpret_cast<const cpx<double> *>(j.in),
+            j.vin ? j.vin + (size_t)jv * j.n : nullptr, j.xv, j.wscale, j.has_mass,
+            reinterpret_cast<cpx<double> *>(j.out), j.partials);
+      };
+      if (j.scan)
+        body(std::true_type{});
+      else
+        body(std::false_type{});
       return;
     }
   }

@@ -249,9 +249,10 @@ def test_end_to_end_fp64(lib, kind, n, ell, nu):
     print("%s n=%d ell=%d nu=%g tau*mu_max=%.2e err=%.3e bound=%.1e res=%.3e gmres=%d" % (
         kind, n, ell, nu, stiff, err, bound, info.rel_residual, info.gmres_iters))
     assert err < bound, (err, bound, info.as_dict())
-    # the float64 residual of an elimination solve sits at u times the
-    # problem's stiffness (1.8e-10 at tau mu_max = 7.9e5, 1e-9 at 8.4e6)
-    assert 0 <= info.rel_residual < 1e-9
+    # the float64 residual of a direct shifted solve sits at about u times
+    # the problem's stiffness (1.8e-10 at tau mu_max = 7.9e5, 1.0e-9 at
+    # 8.4e6): bounded by 4u tau mu_max, and 1e-10 for the mild cases
+    assert 0 <= info.rel_residual < max(1e-10, 2.0 ** -51 * stiff)
 
 
 @pytest.mark.parametrize("alpha", [0.5, 1e-2])
