@@ -34,19 +34,20 @@
 // the corrected rows are u_q + r^q (r ex - beta z_0 r^s0): one pass over the
 // rows after z_0 is summed.  The backward recurrence runs the same way.  No
 // division and three block barriers per solve, against the log2(P)
-// dependent reduction steps of a partition method.  Powers of r inside a
-// chunk are formed by repeated multiplication, and the chunk start
+// dependent reduction steps of a partition method.  The chunk start
 // r^s0 = R^lt comes out of the forward scan (lane l ends with R^(l+1)).
 //
 // Per-frequency table (complex entries, built on the host by
 // pd_scan_table, read with scalar loads):
 //   0 r1,  1 r2,  2 R1 = r1^MR,  3 R2 = r2^MR,  4 1/kappa,  5 beta,
-//   6 sum_{q<MR} r^(2q+1).
+//   6 sum_{q<MR} r^(2q+1),  7 + q: r^q for q = 0..MR (the symmetric r).
+// The powers of r inside a chunk come from the table as scalar operands.
 #pragma once
 #include <complex>
 #include "pd_partition.h"
 
-constexpr int PD_SCAN_ENTRIES = 7;
+template <int MR>
+constexpr int pd_scan_entries() { return 8 + MR; }
 
 
 // OPS as for partition_solve: CplxOps (one complex system) or DualOps (two
@@ -146,19 +147,12 @@ __device__ __forceinline__ void scan_solve(cpx<R> (&d)[MR], int len, int lt, int
   // rows of v - beta z_0 r^i = u_q + r^q (r ex - beta z_0 r^s0)
   {
     const cpx<R> E = csub(A::mul(r1, ex), A::mul(A::mul(tb[5], z0), a0));
-    cpx<R> pw = A::one();
     if (!ragged) {
 #pragma unroll
-      for (int q = 0; q < MR; ++q) {
-        d[q] = fma(d[q], pw, E);
-        pw = A::mul(pw, r1);
-      }
+      for (int q = 0; q < MR; ++q) d[q] = fma(d[q], tb[7 + q], E);
     } else {
 #pragma unroll
-      for (int q = 0; q < MR; ++q) {
-        d[q] = pd_sel(q < len, fma(d[q], pw, E), zero);
-        pw = A::mul(pw, r1);
-      }
+      for (int q = 0; q < MR; ++q) d[q] = pd_sel(q < len, fma(d[q], tb[7 + q], E), zero);
     }
   }
   // backward recurrence inside the chunk, from zero
@@ -190,21 +184,14 @@ __device__ __forceinline__ void scan_solve(cpx<R> (&d)[MR], int len, int lt, int
     for (int w = NW - 1; w > wv; --w) CZ = fma(xw[2 * NW + w], S64, CZ);
     exz = fma(exz, pr, CZ);   // the value at the row after this chunk
   }
-  cpx<R> p2 = r2;   // r^(MR-q)
+  // rows: the local value plus r^(MR-q) times the value after the chunk
   if constexpr (SCALE) {
     const cpx<R> ik = tb[4];
-    exz = A::mul(ik, exz);
 #pragma unroll
-    for (int q = MR - 1; q >= 0; --q) {
-      d[q] = fma(A::mul(ik, d[q]), p2, exz);
-      p2 = A::mul(p2, r2);
-    }
+    for (int q = MR - 1; q >= 0; --q) d[q] = A::mul(ik, fma(d[q], tb[7 + MR - q], exz));
   } else {
 #pragma unroll
-    for (int q = MR - 1; q >= 0; --q) {
-      d[q] = fma(d[q], p2, exz);
-      p2 = A::mul(p2, r2);
-    }
+    for (int q = MR - 1; q >= 0; --q) d[q] = fma(d[q], tb[7 + MR - q], exz);
   }
 }
 
@@ -257,4 +244,9 @@ inline void pd_scan_table(std::complex<double> a, std::complex<double> b, std::c
     p *= rho;
   }
   put(6, K);
+  C pq = 1.0L;
+  for (int q = 0; q <= MR; ++q) {
+    put(7 + q, pq);
+    pq *= r1;
+  }
 }
