@@ -13,10 +13,11 @@
 // P threads with the chunked solver of pd_partition.h, from elimination
 // factors precomputed per (k, m).
 #include "pd_partition.h"
+#include "pd_scan.h"
 
 namespace {
 
-template <typename R, int MR, int MODE>
+template <typename R, int MR, int MODE, bool SCAN>
 __global__ void __launch_bounds__(512, 4)
 line2d_kernel(int n, int F2, int P, int S, int mgroups, int kchunk,
               const cpx<R> *__restrict__ fac, R toff, const double *__restrict__ gw,
@@ -76,10 +77,12 @@ line2d_kernel(int n, int F2, int P, int S, int mgroups, int kchunk,
 
   for (int k = kbeg; k < kend; ++k) {
     __syncthreads();
-    for (int idx = tid; idx < S * NF; idx += blockDim.x) {
-      const int gg = idx / NF, j = idx - gg * NF;
+    // (the recurrence form's table: its pd_scan_entries entries of each row)
+    constexpr int NC = SCAN ? pd_scan_entries<MR>() : NF;
+    for (int idx = tid; idx < S * NC; idx += blockDim.x) {
+      const int gg = idx / NC, j = idx - gg * NC;
       const int mm = m0 + gg < n ? m0 + gg : n - 1;
-      lfac_all[idx] = fac[((size_t)k * n + mm) * NF + j];
+      lfac_all[gg * NF + j] = fac[((size_t)k * n + mm) * NF + j];
     }
     if constexpr (MODE != 2) {
       // U loads in flight per thread (at clamped, valid addresses), then the
@@ -118,7 +121,10 @@ line2d_kernel(int n, int F2, int P, int S, int mgroups, int kchunk,
       }
       d[q] = v;
     }
-    partition_solve<R, MR>(d, len, lt, P, lfac, xch, cc, cc);
+    if constexpr (SCAN)
+      scan_solve_group<R, MR, CplxOps<R>, MODE == 1>(d, len, lt, P, lfac);
+    else
+      partition_solve<R, MR>(d, len, lt, P, lfac, xch, cc, cc);
     if constexpr (MODE == 1) {
       __syncthreads();
 #pragma unroll
@@ -134,7 +140,14 @@ line2d_kernel(int n, int F2, int P, int S, int mgroups, int kchunk,
               reinterpret_cast<cpx<R> *>(smem_raw)[(size_t)gg * sstride + y + 1];
       }
     } else {
-      const double gr = gw[2 * k], gi = gw[2 * k + 1];
+      double gr = gw[2 * k], gi = gw[2 * k + 1];
+      if constexpr (SCAN) {
+        // the recurrence form returns kappa y: fold 1/kappa into the weight
+        const cpx<R> ik = lfac[4];
+        const double t = gr * (double)ik.re - gi * (double)ik.im;
+        gi = gr * (double)ik.im + gi * (double)ik.re;
+        gr = t;
+      }
 #pragma unroll
       for (int q = 0; q < MR; ++q)
         if (q < len) acc[q] += gr * (double)d[q].re - gi * (double)d[q].im;
@@ -157,31 +170,39 @@ line2d_kernel(int n, int F2, int P, int S, int mgroups, int kchunk,
   }
 }
 
-template <typename R, int MR>
-pd_status launch2d(pd_plan p, int mode, const void *in, const double *xv, void *out) {
+template <typename R, int MR, bool SCAN>
+pd_status launch2d_form(pd_plan p, int mode, const void *in, const double *xv, void *out) {
   const Line2DConfig &L = p->l2d;
   const cpx<R> *fac = (sizeof(R) == 8) ? reinterpret_cast<const cpx<R> *>(p->fac64)
                                        : reinterpret_cast<const cpx<R> *>(p->fac32);
   const R toff = (R)p->uni[3];
   mode &= 0xff;
   if (mode == 1) {
-    hipLaunchKernelGGL((line2d_kernel<R, MR, 1>), dim3(p->F2 * L.mgroups), dim3(L.block),
+    hipLaunchKernelGGL((line2d_kernel<R, MR, 1, SCAN>), dim3(p->F2 * L.mgroups), dim3(L.block),
                        L.lds, p->stream, p->n, p->F2, L.P, L.S, L.mgroups, L.kchunk, fac, toff,
                        p->gB64, reinterpret_cast<const cpx<R> *>(in), nullptr, xv, p->w,
                        reinterpret_cast<cpx<R> *>(out), nullptr);
   } else if (mode == 0) {
-    hipLaunchKernelGGL((line2d_kernel<R, MR, 0>), dim3(L.nkc * L.mgroups), dim3(L.block),
+    hipLaunchKernelGGL((line2d_kernel<R, MR, 0, SCAN>), dim3(L.nkc * L.mgroups), dim3(L.block),
                        L.lds, p->stream, p->n, p->F2, L.P, L.S, L.mgroups, L.kchunk, fac, toff,
                        p->gB64, reinterpret_cast<const cpx<R> *>(in), nullptr, nullptr, p->w,
                        nullptr, p->partials);
   } else {
-    hipLaunchKernelGGL((line2d_kernel<R, MR, 2>), dim3(L.nkc * L.mgroups), dim3(L.block),
+    hipLaunchKernelGGL((line2d_kernel<R, MR, 2, SCAN>), dim3(L.nkc * L.mgroups), dim3(L.block),
                        L.lds, p->stream, p->n, p->F2, L.P, L.S, L.mgroups, L.kchunk, fac, toff,
                        p->gJ64, nullptr, reinterpret_cast<const double *>(in), nullptr, p->w,
                        nullptr, p->partials);
   }
   PD_HIP_CHECK(hipGetLastError());
   return PD_OK;
+}
+
+template <typename R, int MR>
+pd_status launch2d(pd_plan p, int mode, const void *in, const double *xv, void *out) {
+  if constexpr (sizeof(R) == 8) {
+    if (pd_line2d_scan(p)) return launch2d_form<R, MR, true>(p, mode, in, xv, out);
+  }
+  return launch2d_form<R, MR, false>(p, mode, in, xv, out);
 }
 
 }  // namespace
@@ -220,9 +241,17 @@ void pd_line2d_factors(const pd_plan p, std::vector<double> &fac) {
   const size_t NF = 6 * (size_t)(MR - 1);
   fac.assign((size_t)F2 * n * NF * 2, 0.0);
   const double tl = p->uni[3], td = p->uni[4];
+  const bool scan = pd_line2d_scan(p);
   for (int k = 0; k < F2; ++k) {
     for (int m = 0; m < n; ++m) {
       const double theta = td + 2.0 * tl * std::cos((m + 1) * M_PI / (n + 1));
+      if (scan) {
+        // recurrence-form constants (pd_scan.h) at the same row stride
+        pd_scan_table({tl, 0.0}, {p->lam[2 * k] + theta + td, p->lam[2 * k + 1]}, {tl, 0.0},
+                      p->lam[2 * k + 1] == 0.0, n, MR,
+                      reinterpret_cast<std::complex<double> *>(&fac[((size_t)k * n + m) * NF * 2]));
+        continue;
+      }
       pd_partition_factors(tl, 0.0, p->lam[2 * k] + theta + td, p->lam[2 * k + 1], tl, 0.0, MR,
                            &fac[((size_t)k * n + m) * NF * 2]);
     }
@@ -245,18 +274,24 @@ pd_status pd_launch_line2d(pd_plan p, int mode, const void *in, const double *xv
 void pd_line2d_set_attributes(size_t max_lds) {
   const int v = (int)max_lds;
   const void *fns[] = {
-      reinterpret_cast<const void *>(&line2d_kernel<double, 4, 0>),
-      reinterpret_cast<const void *>(&line2d_kernel<double, 4, 1>),
-      reinterpret_cast<const void *>(&line2d_kernel<double, 4, 2>),
-      reinterpret_cast<const void *>(&line2d_kernel<double, 8, 0>),
-      reinterpret_cast<const void *>(&line2d_kernel<double, 8, 1>),
-      reinterpret_cast<const void *>(&line2d_kernel<double, 8, 2>),
-      reinterpret_cast<const void *>(&line2d_kernel<float, 4, 0>),
-      reinterpret_cast<const void *>(&line2d_kernel<float, 4, 1>),
-      reinterpret_cast<const void *>(&line2d_kernel<float, 4, 2>),
-      reinterpret_cast<const void *>(&line2d_kernel<float, 8, 0>),
-      reinterpret_cast<const void *>(&line2d_kernel<float, 8, 1>),
-      reinterpret_cast<const void *>(&line2d_kernel<float, 8, 2>)};
+      reinterpret_cast<const void *>(&line2d_kernel<double, 4, 0, false>),
+      reinterpret_cast<const void *>(&line2d_kernel<double, 4, 0, true>),
+      reinterpret_cast<const void *>(&line2d_kernel<double, 4, 1, false>),
+      reinterpret_cast<const void *>(&line2d_kernel<double, 4, 1, true>),
+      reinterpret_cast<const void *>(&line2d_kernel<double, 4, 2, false>),
+      reinterpret_cast<const void *>(&line2d_kernel<double, 4, 2, true>),
+      reinterpret_cast<const void *>(&line2d_kernel<double, 8, 0, false>),
+      reinterpret_cast<const void *>(&line2d_kernel<double, 8, 0, true>),
+      reinterpret_cast<const void *>(&line2d_kernel<double, 8, 1, false>),
+      reinterpret_cast<const void *>(&line2d_kernel<double, 8, 1, true>),
+      reinterpret_cast<const void *>(&line2d_kernel<double, 8, 2, false>),
+      reinterpret_cast<const void *>(&line2d_kernel<double, 8, 2, true>),
+      reinterpret_cast<const void *>(&line2d_kernel<float, 4, 0, false>),
+      reinterpret_cast<const void *>(&line2d_kernel<float, 4, 1, false>),
+      reinterpret_cast<const void *>(&line2d_kernel<float, 4, 2, false>),
+      reinterpret_cast<const void *>(&line2d_kernel<float, 8, 0, false>),
+      reinterpret_cast<const void *>(&line2d_kernel<float, 8, 1, false>),
+      reinterpret_cast<const void *>(&line2d_kernel<float, 8, 2, false>)};
   for (const void *f : fns)
     pd_set_max_lds(f, v);
 }

@@ -470,6 +470,12 @@ inline bool pd_use_scan(const pd_plan p) {
          p->tri.P % 64 == 0 && u[0] == u[2] && u[3] == u[5];
 }
 
+// The 2D line solves of float64 plans with groups of at most one wave use
+// the recurrence form as well (symmetric Toeplitz lines, pd_scan.h).
+inline bool pd_line2d_scan(const pd_plan p) {
+  return p->dims == 2 && p->prec == PD_FP64 && p->l2d.P <= 64 && p->l2d.MR >= 4;
+}
+
 // Threads per shifted-solve block: 512 for complex128 (a 256-register budget
 // per thread keeps the partition solve out of scratch), 1024 otherwise.
 inline int pd_tri_block_threads(int prec) { return prec == PD_FP64 ? 512 : 1024; }

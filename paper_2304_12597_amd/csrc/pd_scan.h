@@ -195,6 +195,93 @@ __device__ __forceinline__ void scan_solve(cpx<R> (&d)[MR], int len, int lt, int
   }
 }
 
+// The same solve for groups of P <= 64 threads inside one wave (several
+// systems per wave when P < 64): the scans and the sum for z_0 stay inside
+// the group's lanes (shuffles of width P), so no LDS and no barrier.  tb may
+// differ between groups (an LDS or global pointer per group).
+template <typename R, int MR, typename A, bool SCALE>
+__device__ __forceinline__ void scan_solve_group(cpx<R> (&d)[MR], int len, int lt, int P,
+                                                 const cpx<R> *tb) {
+  auto fma = [](cpx<R> s, cpx<R> b, cpx<R> c) { return A::fma(s, b, c); };
+  auto shup = [P](cpx<R> v, int s) {
+    return cpx<R>{__shfl_up(v.re, s, P), __shfl_up(v.im, s, P)};
+  };
+  auto shdn = [P](cpx<R> v, int s) {
+    return cpx<R>{__shfl_down(v.re, s, P), __shfl_down(v.im, s, P)};
+  };
+  const cpx<R> zero = {R(0), R(0)};
+  const cpx<R> r1 = tb[0], r2 = tb[1];
+  const bool ragged = __any(len < MR);
+
+  cpx<R> acc = zero;
+#pragma unroll
+  for (int q = 0; q < MR; ++q) {
+    acc = fma(d[q], r1, acc);
+    d[q] = acc;
+  }
+  cpx<R> c = acc, m = tb[2];
+  for (int s = 1; s < P; s <<= 1) {
+    const cpx<R> oc = shup(c, s), om = shup(m, s);
+    const bool in = lt >= s;
+    c = pd_sel(in, fma(c, m, oc), c);
+    m = pd_sel(in, A::mul(m, om), m);
+  }
+  const cpx<R> ex = pd_sel(lt > 0, shup(c, 1), zero);       // v at the row before the chunk
+  const cpx<R> a0 = pd_sel(lt > 0, shup(m, 1), A::one());   // R1^lt = r^s0
+  cpx<R> h = zero, K = tb[6];
+  if (!ragged) {
+#pragma unroll
+    for (int q = MR - 1; q >= 0; --q) h = fma(d[q], r1, h);
+  } else {
+    const cpx<R> rr = A::mul(r1, r2);
+    cpx<R> p = r1;
+    K = zero;
+#pragma unroll
+    for (int q = 0; q < MR; ++q) {
+      K = pd_sel(q < len, cadd(K, p), K);
+      p = A::mul(p, rr);
+    }
+#pragma unroll
+    for (int q = MR - 1; q >= 0; --q) h = pd_sel(q < len, fma(d[q], r1, h), h);
+  }
+  cpx<R> z0 = A::mul(a0, fma(h, ex, K));
+  for (int s = P >> 1; s >= 1; s >>= 1)
+    z0 = cadd(z0, cpx<R>{__shfl_xor(z0.re, s, P), __shfl_xor(z0.im, s, P)});
+  {
+    const cpx<R> E = csub(A::mul(r1, ex), A::mul(A::mul(tb[5], z0), a0));
+    if (!ragged) {
+#pragma unroll
+      for (int q = 0; q < MR; ++q) d[q] = fma(d[q], tb[7 + q], E);
+    } else {
+#pragma unroll
+      for (int q = 0; q < MR; ++q) d[q] = pd_sel(q < len, fma(d[q], tb[7 + q], E), zero);
+    }
+  }
+  acc = zero;
+#pragma unroll
+  for (int q = MR - 1; q >= 0; --q) {
+    acc = fma(d[q], r2, acc);
+    d[q] = acc;
+  }
+  cpx<R> cz = acc;
+  m = tb[3];
+  for (int s = 1; s < P; s <<= 1) {
+    const cpx<R> oz = shdn(cz, s), om = shdn(m, s);
+    const bool in = lt + s < P;
+    cz = pd_sel(in, fma(cz, m, oz), cz);
+    m = pd_sel(in, A::mul(m, om), m);
+  }
+  const cpx<R> exz = pd_sel(lt + 1 < P, shdn(cz, 1), zero);   // the row after the chunk
+  if constexpr (SCALE) {
+    const cpx<R> ik = tb[4];
+#pragma unroll
+    for (int q = MR - 1; q >= 0; --q) d[q] = A::mul(ik, fma(d[q], tb[7 + MR - q], exz));
+  } else {
+#pragma unroll
+    for (int q = MR - 1; q >= 0; --q) d[q] = fma(d[q], tb[7 + MR - q], exz);
+  }
+}
+
 // The table above for one frequency (host).  a, b, c: the constant sub-,
 // main and super-diagonal; real: the system is real (lambda real), so the
 // discriminant is clamped at zero and every entry is real.  Computed in long
