@@ -49,6 +49,56 @@
 template <int MR>
 constexpr int pd_scan_entries() { return 8 + MR; }
 
+// Lane moves by DPP (data-parallel primitives: a VALU operand modifier, no
+// LDS round trip).  CTRL: row_shr:s = 0x110 + s, row_shl:s = 0x100 + s,
+// wave_shr:1 = 0x138, wave_shl:1 = 0x130, row_bcast:15 = 0x142,
+// row_bcast:31 = 0x143.  Lanes whose source is outside the pattern, or whose
+// row is off in ROWMASK, take `old`.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double pd_dpp(double v, double old) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const long long vb = __builtin_bit_cast(long long, v), ob = __builtin_bit_cast(long long, old);
+  const int lo = __builtin_amdgcn_update_dpp((int)ob, (int)vb, CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(ob >> 32), (int)(vb >> 32), CTRL, ROWMASK, 0xF,
+                                             false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+#else
+  return v;
+#endif
+}
+template <int CTRL, int ROWMASK, typename R>
+__device__ __forceinline__ cpx<R> pd_dpp(cpx<R> v, cpx<R> old) {
+  return cpx<R>{pd_dpp<CTRL, ROWMASK>(v.re, old.re), pd_dpp<CTRL, ROWMASK>(v.im, old.im)};
+}
+template <typename R>
+__device__ __forceinline__ cpx<R> pd_readlane(cpx<R> v, int l) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  auto rl = [l](double x) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+  };
+  return cpx<R>{rl(v.re), rl(v.im)};
+#else
+  return v;
+#endif
+}
+
+// One step of the inclusive scan of chunk maps (m, c) across a wave: lanes
+// combine with the partial map of the lanes before them (identity: m = 1,
+// c = 0, which `old` supplies where the pattern has no source).
+template <int CTRL, int ROWMASK, typename A, typename R>
+__device__ __forceinline__ void pd_scan_step(cpx<R> &c, cpx<R> &m) {
+  const cpx<R> oc = pd_dpp<CTRL, ROWMASK>(c, cpx<R>{R(0), R(0)});
+  const cpx<R> om = pd_dpp<CTRL, ROWMASK>(m, A::one());
+  c = A::fma(c, m, oc);
+  m = A::mul(m, om);
+}
+
+struct PdNoPrefetch {
+  __device__ void operator()(int) const {}
+};
+
 
 // OPS as for partition_solve: CplxOps (one complex system) or DualOps (two
 // real systems in the real and imaginary parts).  xw: 3*(P/64) complex LDS
@@ -57,9 +107,10 @@ constexpr int pd_scan_entries() { return 8 + MR; }
 // are whole waves (P a multiple of 64, P <= 512).  Every thread of the block
 // calls this together; rows past the end of the system (q >= len) hold zero
 // on entry and are left undefined.
-template <typename R, int MR, typename A, bool LB, bool SCALE>
+template <typename R, int MR, typename A, bool LB, bool SCALE, typename Pre = PdNoPrefetch>
 __device__ __forceinline__ void scan_solve(cpx<R> (&d)[MR], int len, int lt, int P,
-                                           const cpx<R> *__restrict__ tb, cpx<R> *xw) {
+                                           const cpx<R> *__restrict__ tb, cpx<R> *xw,
+                                           Pre pre = Pre{}) {
   auto barrier = [] {
     if constexpr (LB)
       pd_lds_barrier();
@@ -67,13 +118,6 @@ __device__ __forceinline__ void scan_solve(cpx<R> (&d)[MR], int len, int lt, int
       __syncthreads();
   };
   auto fma = [](cpx<R> s, cpx<R> b, cpx<R> c) { return A::fma(s, b, c); };
-  auto shup = [](cpx<R> v, int s) {
-    return cpx<R>{__shfl_up(v.re, s, 64), __shfl_up(v.im, s, 64)};
-  };
-  auto shdn = [](cpx<R> v, int s) {
-    return cpx<R>{__shfl_down(v.re, s, 64), __shfl_down(v.im, s, 64)};
-  };
-  auto bcast = [](cpx<R> v, int l) { return cpx<R>{__shfl(v.re, l, 64), __shfl(v.im, l, 64)}; };
   const cpx<R> zero = {R(0), R(0)};
   int lane = lt & 63;
   // lane passes through an empty asm: the shuffle indices derived from it
@@ -95,18 +139,17 @@ __device__ __forceinline__ void scan_solve(cpx<R> (&d)[MR], int len, int lt, int
   // scan of the chunk maps x -> R1 x + e_t across the wave (left to right):
   // lane l ends with R1^(l+1) and v at its chunk's last row from the wave's
   // start
+  pre(0);   // the caller's next prefetch, a part at a time between the phases
   cpx<R> c = acc, m = tb[2];
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    const int s = 1 << j;
-    const cpx<R> oc = shup(c, s), om = shup(m, s);
-    const bool in = lane >= s;
-    c = pd_sel(in, fma(c, m, oc), c);
-    m = pd_sel(in, A::mul(m, om), m);
-  }
-  cpx<R> ex = pd_sel(lane > 0, shup(c, 1), zero);
-  const cpx<R> pl = pd_sel(lane > 0, shup(m, 1), A::one());   // R1^lane
-  const cpx<R> R64 = bcast(m, 63);                               // R1^64
+  pd_scan_step<0x111, 0xF, A>(c, m);   // row_shr:1, 2, 4, 8
+  pd_scan_step<0x112, 0xF, A>(c, m);
+  pd_scan_step<0x114, 0xF, A>(c, m);
+  pd_scan_step<0x118, 0xF, A>(c, m);
+  pd_scan_step<0x142, 0xA, A>(c, m);   // row_bcast:15 into rows 1 and 3
+  pd_scan_step<0x143, 0xC, A>(c, m);   // row_bcast:31 into rows 2 and 3
+  cpx<R> ex = pd_dpp<0x138, 0xF>(c, zero);                // wave_shr:1
+  const cpx<R> pl = pd_dpp<0x138, 0xF>(m, A::one());     // R1^lane
+  const cpx<R> R64 = pd_readlane(m, 63);                  // R1^64
   if (lane == 63) xw[wv] = c;
   // sum_{q<len} r^q u_q by Horner, and sum_{q<len} r^(2q+1)
   cpx<R> h = zero, K = tb[6];
@@ -129,6 +172,7 @@ __device__ __forceinline__ void scan_solve(cpx<R> (&d)[MR], int len, int lt, int
   cpx<R> a0 = pl;
   for (int w = 0; w < wv; ++w) a0 = A::mul(a0, R64);
   barrier();
+  pre(1);
   // carry into this wave: the waves before it, in order
   {
     cpx<R> C = zero;
@@ -137,11 +181,16 @@ __device__ __forceinline__ void scan_solve(cpx<R> (&d)[MR], int len, int lt, int
   }
   // this chunk's share of z_0 = sum_i r^i v_i, summed over the group
   cpx<R> dot = A::mul(a0, fma(h, ex, K));
-#pragma unroll
-  for (int s = 32; s >= 1; s >>= 1)
-    dot = cadd(dot, cpx<R>{__shfl_xor(dot.re, s, 64), __shfl_xor(dot.im, s, 64)});
-  if (lane == 0) xw[NW + wv] = dot;
+  // wave sum: row sums by row_shr, then the row totals into lane 63
+  dot = cadd(dot, pd_dpp<0x111, 0xF>(dot, zero));
+  dot = cadd(dot, pd_dpp<0x112, 0xF>(dot, zero));
+  dot = cadd(dot, pd_dpp<0x114, 0xF>(dot, zero));
+  dot = cadd(dot, pd_dpp<0x118, 0xF>(dot, zero));
+  dot = cadd(dot, pd_dpp<0x142, 0xA>(dot, zero));
+  dot = cadd(dot, pd_dpp<0x143, 0xC>(dot, zero));
+  if (lane == 63) xw[NW + wv] = dot;
   barrier();
+  pre(2);
   cpx<R> z0 = zero;
   for (int w = 0; w < NW; ++w) z0 = cadd(z0, xw[NW + w]);
   // rows of v - beta z_0 r^i = u_q + r^q (r ex - beta z_0 r^s0)
@@ -164,19 +213,30 @@ __device__ __forceinline__ void scan_solve(cpx<R> (&d)[MR], int len, int lt, int
   }
   // the same scan from the right: lane l ends with R2^(64-l) and the
   // value at its chunk's first row from the wave's end
+  pre(3);
   cpx<R> cz = acc;
   m = tb[3];
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    const int s = 1 << j;
-    const cpx<R> oz = shdn(cz, s), om = shdn(m, s);
-    const bool in = lane + s < 64;
+  pd_scan_step<0x101, 0xF, A>(cz, m);   // row_shl:1, 2, 4, 8
+  pd_scan_step<0x102, 0xF, A>(cz, m);
+  pd_scan_step<0x104, 0xF, A>(cz, m);
+  pd_scan_step<0x108, 0xF, A>(cz, m);
+  // across rows (lane shuffles): rows 0 and 2 take the next row's first
+  // lane, then rows 0 and 1 take lane 32
+  {
+    auto from = [](cpx<R> v, int l) { return cpx<R>{__shfl(v.re, l, 64), __shfl(v.im, l, 64)}; };
+    const int srcA = (lane | 15) + 1;
+    const cpx<R> oz = from(cz, srcA & 63), om = from(m, srcA & 63);
+    const bool in = ((lane >> 4) & 1) == 0;
     cz = pd_sel(in, fma(cz, m, oz), cz);
     m = pd_sel(in, A::mul(m, om), m);
+    const cpx<R> oz2 = from(cz, 32), om2 = from(m, 32);
+    const bool in2 = lane < 32;
+    cz = pd_sel(in2, fma(cz, m, oz2), cz);
+    m = pd_sel(in2, A::mul(m, om2), m);
   }
-  cpx<R> exz = pd_sel(lane < 63, shdn(cz, 1), zero);
-  const cpx<R> pr = pd_sel(lane < 63, shdn(m, 1), A::one());   // R2^(63-lane)
-  const cpx<R> S64 = bcast(m, 0);                                // R2^64
+  cpx<R> exz = pd_dpp<0x130, 0xF>(cz, zero);               // wave_shl:1
+  const cpx<R> pr = pd_dpp<0x130, 0xF>(m, A::one());      // R2^(63-lane)
+  const cpx<R> S64 = pd_readlane(m, 0);                    // R2^64
   if (lane == 0) xw[2 * NW + wv] = cz;
   barrier();
   {

@@ -625,8 +625,11 @@ __device__ __forceinline__ void tridiag_pipe_body(
   // DMA of a slot's right-hand side and of its factors into factor buffer b.
   // Slot 0 (the real shifts k = 0 and k = ell/2) takes the real parts of
   // rows k = 0 (dwords 0, 1 of each entry) and k = ell/2 (dwords 2, 3).
-  auto issue = [&](int slot_in, int b) {
+  // part in [0, 4): only the windows of that quarter of the slot's rows
+  // (the recurrence form spreads a prefetch over its phases); -1: all
+  auto issue = [&](int slot_in, int b, int part = -1) {
     const int sl = slot_in < nslots ? slot_in : nslots - 1;
+    const int w0 = part < 0 ? 0 : part * (MR / 4), w1 = part < 0 ? MR : (part + 1) * (MR / 4);
     if constexpr (MODE != 2) {
       // staging entry e holds row tl*MR + q of the rotated layout, tl = e/MR
       // (rows >= n read row n-1 and are zeroed when read)
@@ -637,6 +640,7 @@ __device__ __forceinline__ void tridiag_pipe_body(
         const Cx *src = in + (size_t)sl * n;
 #pragma unroll
         for (int wdw = 0; wdw < MR; ++wdw) {
+          if (wdw < w0 || wdw >= w1) continue;
           const int e0 = wib * 64 * MR + wdw * 64;
           const int e = e0 + lane;
           const int tl = e / MR, j = e & (MR - 1);
@@ -679,7 +683,7 @@ __device__ __forceinline__ void tridiag_pipe_body(
   // or DualOps (slot 0: k = 0 in the real parts, k = ell/2 in the imaginary
   // parts).  The caller has made the item's data visible in LDS; `sync`
   // runs between the last read of the staging area and the solve.
-  auto work = [&](auto ops, int slot, const Cx *lfac, auto sync) {
+  auto work = [&](auto ops, int slot, const Cx *lfac, auto sync, auto pre) {
     using OPS = decltype(ops);
     constexpr bool DUAL = std::is_same<OPS, DualOps<R>>::value;
     const bool active = slot < nslots;
@@ -748,7 +752,7 @@ __device__ __forceinline__ void tridiag_pipe_body(
     // the reduction (xch does not alias the staging area)
     if constexpr (SCAN)
       scan_solve<R, MR, OPS, true, MODE == 1>(d, len, lt, P, fac + (size_t)(DUAL ? F2 : k) * NF,
-                                   reinterpret_cast<Cx *>(xch));
+                                               reinterpret_cast<Cx *>(xch), pre);
     else if (!DUAL && MR <= 8 && __all(len == MR))
       partition_solve<R, MR, OPS, true>(d, MR, lt, P, lfac, xch, ca, cc);
     else
@@ -823,9 +827,14 @@ __device__ __forceinline__ void tridiag_pipe_body(
     // the next item's data (buffer 0) streams in behind its solve
     pd_wait_all();
     __syncthreads();
+    // the recurrence form issues the next item's DMA in quarters between its
+    // phases (a wave's vector-memory instructions issue in order, so one
+    // burst of them would hold up its arithmetic)
     work(DualOps<R>{}, 0, facb + ((size_t)1 * spb + g) * NFP, [&] {
       __syncthreads();   // every thread has read the staging area
-      if (nblk < nitems) issue(nblk, 0);
+      if (!SCAN && nblk < nitems) issue(nblk, 0);
+    }, [&](int part) {
+      if (nblk < nitems) issue(nblk, 0, part);
     });
     item = nblk;
   }
@@ -836,12 +845,15 @@ __device__ __forceinline__ void tridiag_pipe_body(
     const Cx *lfac = facb + ((size_t)buf * spb + g) * NFP;
     auto sync = [&] {
       __syncthreads();   // every thread has read the staging area
-      if (item + nblk < nitems) issue((item + nblk) * spb + g, buf ^ 1);
+      if (!SCAN && item + nblk < nitems) issue((item + nblk) * spb + g, buf ^ 1);
+    };
+    auto pre = [&](int part) {
+      if (item + nblk < nitems) issue((item + nblk) * spb + g, buf ^ 1, part);
     };
     if (!PAIR_FIRST && slot == 0)
-      work(DualOps<R>{}, slot, lfac, sync);
+      work(DualOps<R>{}, slot, lfac, sync, pre);
     else
-      work(CplxOps<R>{}, slot, lfac, sync);
+      work(CplxOps<R>{}, slot, lfac, sync, pre);
   }
 
   if constexpr (MODE != 1) {

@@ -33,6 +33,26 @@ def table(a, b, n, MR, real):
     return kap, r, beta, K
 
 
+def _pattern(lane, shift, rowmask):
+    """Source lane (in the same wave) and validity of a DPP move: row shift
+    right (shift > 0) or left (< 0) within rows of 16 lanes, or the row
+    broadcasts of lane 15 / lane 31 ("b15", "b31") into the rows of rowmask."""
+    base = lane - lane % 64
+    w = lane % 64
+    row, i = w // 16, w % 16
+    if shift == "b15":
+        ok = (row > 0) & (((rowmask >> row) & 1) == 1)
+        return base + np.maximum(row * 16 - 1, 0), ok
+    if shift == "b31":
+        ok = ((rowmask >> row) & 1) == 1
+        return base + 31, ok
+    if shift > 0:
+        ok = i >= shift
+        return base + np.where(ok, w - shift, w), ok
+    ok = i - shift < 16
+    return base + np.where(ok, w - shift, w), ok
+
+
 def scan_solve(y, a, b, P, MR, real=False):
     n = y.size
     kap, r, beta, K_full = table(a, b, n, MR, real)
@@ -51,14 +71,22 @@ def scan_solve(y, a, b, P, MR, real=False):
     for q in range(MR):
         acc = d[:, q] + r * acc
         d[:, q] = acc
-    # scan of the chunk maps across each wave (Hillis-Steele on (m, c))
+    # scan of the chunk maps across each wave: for whole waves by rows of 16
+    # lanes, then the rows' last lanes (the kernel's DPP row shifts and row
+    # broadcasts); for smaller groups by Hillis-Steele steps of width P
     c, m = acc.copy(), np.full(P, R)
-    s = 1
-    while s < W:
-        oc, om = np.roll(c, s), np.roll(m, s)
-        inn = (lane % W) >= s
-        c, m = np.where(inn, c + m * oc, c), np.where(inn, m * om, m)
-        s *= 2
+    if W == 64:
+        for shift, rows in ((1, 15), (2, 15), (4, 15), (8, 15), ("b15", 10), ("b31", 12)):
+            src, ok = _pattern(lt, shift, rows)
+            oc, om = np.where(ok, c[src], 0), np.where(ok, m[src], 1)
+            c, m = c + m * oc, m * om
+    else:
+        s = 1
+        while s < W:
+            oc, om = np.roll(c, s), np.roll(m, s)
+            inn = (lane % W) >= s
+            c, m = np.where(inn, c + m * oc, c), np.where(inn, m * om, m)
+            s *= 2
     ex = np.where(lane % W > 0, np.roll(c, 1), 0)
     pl = np.where(lane % W > 0, np.roll(m, 1), 1)           # R^lane
     R64 = R ** W
@@ -87,12 +115,27 @@ def scan_solve(y, a, b, P, MR, real=False):
         acc = d[:, q] + r * acc
         d[:, q] = acc
     cz, m = acc.copy(), np.full(P, R)
-    s = 1
-    while s < W:
-        oz, om = np.roll(cz, -s), np.roll(m, -s)
-        inn = (lane % W) + s < W
-        cz, m = np.where(inn, cz + m * oz, cz), np.where(inn, m * om, m)
-        s *= 2
+    if W == 64:
+        # rows of 16 from the right, then rows 0 and 2 take the next row's
+        # first lane, then rows 0 and 1 take lane 32
+        for shift in (-1, -2, -4, -8):
+            src, ok = _pattern(lt, shift, 15)
+            oz, om = np.where(ok, cz[src], 0), np.where(ok, m[src], 1)
+            cz, m = cz + m * oz, m * om
+        base = (lt // 64) * 64
+        src = base + (((lane | 15) + 1) & 63)
+        inn = ((lane >> 4) & 1) == 0
+        cz, m = np.where(inn, cz + m * cz[src], cz), np.where(inn, m * m[src], m)
+        src = base + 32
+        inn = lane < 32
+        cz, m = np.where(inn, cz + m * cz[src], cz), np.where(inn, m * m[src], m)
+    else:
+        s = 1
+        while s < W:
+            oz, om = np.roll(cz, -s), np.roll(m, -s)
+            inn = (lane % W) + s < W
+            cz, m = np.where(inn, cz + m * oz, cz), np.where(inn, m * om, m)
+            s *= 2
     exz = np.where(lane % W < W - 1, np.roll(cz, -1), 0)
     pr = np.where(lane % W < W - 1, np.roll(m, -1), 1)       # R^(W-1-lane)
     tot = cz.reshape(NW, -1)[:, 0]
