@@ -668,14 +668,17 @@ __device__ __forceinline__ void tridiag_pipe_body(
         }
       }
     }
+    const Cx *fsrc = fac + (size_t)(sl == 0 ? F2 : sl) * NF;
+    Cx *fdst = facb + ((size_t)b * spb + g) * NFP;
     if constexpr (!SCAN) {
-      // (the recurrence form reads its constants with scalar loads instead)
-      const Cx *fsrc = fac + (size_t)(sl == 0 ? F2 : sl) * NF;
-      Cx *fdst = facb + ((size_t)b * spb + g) * NFP;
       for (int c0 = wib * 64; c0 < NFP; c0 += P) {
         const int idx = c0 + (lt & 63);
         pd_lds_dma16(fsrc + (idx < NF ? idx : NF - 1), fdst + c0);
       }
+    } else if (part <= 0 && wib == 0) {
+      // the recurrence form's constants: one 64-entry window
+      const int idx = lt & 63;
+      pd_lds_dma16(fsrc + (idx < NF ? idx : NF - 1), fdst);
     }
   };
 
@@ -698,7 +701,7 @@ __device__ __forceinline__ void tridiag_pipe_body(
       if constexpr (SCAN) {
         // the recurrence form returns kappa_k y_k: fold 1/kappa_k into the
         // weights
-        const Cx ik = fac[(size_t)(DUAL ? F2 : k) * NF + 4];
+        const Cx ik = lfac[4];
         if (DUAL) {
           gr *= ik.re;
           grB *= ik.im;
@@ -751,8 +754,8 @@ __device__ __forceinline__ void tridiag_pipe_body(
     // LDS-only barriers: the next item's prefetch keeps streaming in through
     // the reduction (xch does not alias the staging area)
     if constexpr (SCAN)
-      scan_solve<R, MR, OPS, true, MODE == 1>(d, len, lt, P, fac + (size_t)(DUAL ? F2 : k) * NF,
-                                               reinterpret_cast<Cx *>(xch), pre);
+      scan_solve<R, MR, OPS, true, MODE == 1>(d, len, lt, P, lfac, reinterpret_cast<Cx *>(xch),
+                                               pre);
     else if (!DUAL && MR <= 8 && __all(len == MR))
       partition_solve<R, MR, OPS, true>(d, MR, lt, P, lfac, xch, ca, cc);
     else
