@@ -127,6 +127,18 @@ def check_pipe(n, F2):
     nfp = (6 * (MR - 1) + 63) // 64 * 64
     lds = spb * (rows + 3 * P + 2 * nfp) * 16
     assert lds <= MAX_LDS, (n, lds)
+    # recurrence form (pd_scan.h): the issue split into four parts covers
+    # each window once; the constants' one 64-entry DMA window (wave 0)
+    # reads entries min(idx, NF - 1) of row F2 or k < F2 of the (F2 + 1) x NF
+    # table and fills entries 0..63 of a factor buffer of nfp >= 64 entries;
+    # the solve reads entries 0..8 + MR of it; the exchange area xw holds
+    # 3 * (P / 64) complex128 entries inside the group's P Row3 entries
+    NF = 6 * (MR - 1)
+    parts = [w for part in range(4) for w in range(part * (MR // 4), (part + 1) * (MR // 4))]
+    assert sorted(parts) == list(range(MR))
+    idx = np.minimum(np.arange(64), NF - 1)
+    assert idx.max() < NF and nfp >= 64 and 8 + MR < NF
+    assert 3 * (P // 64) * 16 <= P * 48
 
 
 def check_uniform(n, prec):
