@@ -40,14 +40,15 @@
 // Per-frequency table (complex entries, built on the host by
 // pd_scan_table, read with scalar loads):
 //   0 r1,  1 r2,  2 R1 = r1^MR,  3 R2 = r2^MR,  4 1/kappa,  5 beta,
-//   6 sum_{q<MR} r^(2q+1),  7 + q: r^q for q = 0..MR (the symmetric r).
+//   6 sum_{q<MR} r^(2q+1),  7 + q: r^q for q = 0..MR (the symmetric r),
+//   8 + MR: sum_{q < n mod MR} r^(2q+1) (the one ragged chunk's share).
 // The powers of r inside a chunk come from the table as scalar operands.
 #pragma once
 #include <complex>
 #include "pd_partition.h"
 
 template <int MR>
-constexpr int pd_scan_entries() { return 8 + MR; }
+constexpr int pd_scan_entries() { return 9 + MR; }
 
 // Lane moves by DPP (data-parallel primitives: a VALU operand modifier, no
 // LDS round trip).  CTRL: row_shr:s = 0x110 + s, row_shl:s = 0x100 + s,
@@ -157,20 +158,19 @@ __device__ __forceinline__ void scan_solve(cpx<R> (&d)[MR], int len, int lt, int
 #pragma unroll
     for (int q = MR - 1; q >= 0; --q) h = fma(d[q], r1, h);
   } else {
-    const cpx<R> rr = A::mul(r1, r2);
-    cpx<R> p = r1;
-    K = zero;
-#pragma unroll
-    for (int q = 0; q < MR; ++q) {
-      K = pd_sel(q < len, cadd(K, p), K);
-      p = A::mul(p, rr);
-    }
+    // full chunks, the one ragged chunk (len = n mod MR), empty chunks
+    K = pd_sel(len == MR, tb[6], pd_sel(len > 0, tb[8 + MR], zero));
 #pragma unroll
     for (int q = MR - 1; q >= 0; --q) h = pd_sel(q < len, fma(d[q], r1, h), h);
   }
   // R1^lt = r^s0: the power r^i at the chunk's start
   cpx<R> a0 = pl;
-  for (int w = 0; w < wv; ++w) a0 = A::mul(a0, R64);
+  if (wv & 1) a0 = A::mul(a0, R64);
+  if (wv & 6) {
+    const cpx<R> R128 = A::mul(R64, R64);
+    if (wv & 2) a0 = A::mul(a0, R128);
+    if (wv & 4) a0 = A::mul(a0, A::mul(R128, R128));
+  }
   barrier();
   pre(1);
   // carry into this wave: the waves before it, in order
@@ -293,14 +293,8 @@ __device__ __forceinline__ void scan_solve_group(cpx<R> (&d)[MR], int len, int l
 #pragma unroll
     for (int q = MR - 1; q >= 0; --q) h = fma(d[q], r1, h);
   } else {
-    const cpx<R> rr = A::mul(r1, r2);
-    cpx<R> p = r1;
-    K = zero;
-#pragma unroll
-    for (int q = 0; q < MR; ++q) {
-      K = pd_sel(q < len, cadd(K, p), K);
-      p = A::mul(p, rr);
-    }
+    // full chunks, the one ragged chunk (len = n mod MR), empty chunks
+    K = pd_sel(len == MR, tb[6], pd_sel(len > 0, tb[8 + MR], zero));
 #pragma unroll
     for (int q = MR - 1; q >= 0; --q) h = pd_sel(q < len, fma(d[q], r1, h), h);
   }
@@ -396,4 +390,10 @@ inline void pd_scan_table(std::complex<double> a, std::complex<double> b, std::c
     put(7 + q, pq);
     pq *= r1;
   }
+  C Kr = 0.0L, pr = r1;
+  for (int q = 0; q < n % MR; ++q) {
+    Kr += pr;
+    pr *= rho;
+  }
+  put(8 + MR, Kr);
 }
