@@ -10,8 +10,9 @@
 // owns S consecutive m for one frequency (mode 1) or for a range of
 // frequencies (modes 0 and 2, which sum over k); its tile [y][m0..m0+S) is
 // staged through LDS with coalesced row segments, and each line is solved by
-// P threads with the chunked solver of pd_partition.h, from elimination
-// factors precomputed per (k, m).
+// P threads from constants precomputed per (k, m): float64 lines of at most
+// one wave by the recurrence form of pd_scan.h (the lines are symmetric
+// Toeplitz), the others by the chunked solver of pd_partition.h.
 #include "pd_partition.h"
 #include "pd_scan.h"
 

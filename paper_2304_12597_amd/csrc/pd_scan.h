@@ -1,5 +1,7 @@
 // Shifted solves of symmetric Toeplitz tridiagonal systems by two first-order
-// recurrences (the pass B / pass C solves of the uniform-grid path).
+// recurrences: the parfor of shifted solves of Algorithm 1 (Section 2,
+// P_k = lambda_k M + tau K) on uniform grids, passes B and C, and the 2D
+// line solves after the DST along x (Section 6.1).
 //
 // For one frequency the system has constant sub-diagonal a, diagonal b and
 // super-diagonal c.  Let kappa be the root of larger modulus of
@@ -28,8 +30,9 @@
 // rows [lt*MR, lt*MR + len), s0 = lt*MR.  The forward recurrence runs over
 // the thread's rows from a zero start (u_q); the chunk carries are combined
 // by a scan across the group that composes the chunk maps x -> R x + e
-// (R = r^MR): wave shuffles in log2(64) steps, then the waves' totals through
-// LDS.  With ex = v at row s0-1, the chunk's rows are v_q = u_q + r^(q+1) ex,
+// (R = r^MR): DPP row shifts and row broadcasts inside a wave (lane shuffles
+// of width P for groups smaller than a wave), then the waves' totals
+// through LDS.  With ex = v at row s0-1, the chunk's rows are v_q = u_q + r^(q+1) ex,
 // so its share of z_0 is r^s0 (sum_q r^q u_q + ex sum_{q<len} r^(2q+1)), and
 // the corrected rows are u_q + r^q (r ex - beta z_0 r^s0): one pass over the
 // rows after z_0 is summed.  The backward recurrence runs the same way.  No
@@ -38,11 +41,11 @@
 // r^s0 = R^lt comes out of the forward scan (lane l ends with R^(l+1)).
 //
 // Per-frequency table (complex entries, built on the host by
-// pd_scan_table, read with scalar loads):
+// pd_scan_table; the kernels stage each system's row into LDS):
 //   0 r1,  1 r2,  2 R1 = r1^MR,  3 R2 = r2^MR,  4 1/kappa,  5 beta,
 //   6 sum_{q<MR} r^(2q+1),  7 + q: r^q for q = 0..MR (the symmetric r),
 //   8 + MR: sum_{q < n mod MR} r^(2q+1) (the one ragged chunk's share).
-// The powers of r inside a chunk come from the table as scalar operands.
+// The powers of r inside a chunk come from the table, not from products.
 #pragma once
 #include <complex>
 #include "pd_partition.h"

@@ -17,6 +17,10 @@
 //      (PCR) in LDS;
 //   3. each thread back-substitutes its interior rows.
 //
+// Complex128 systems with symmetric constant diagonals (uniform grids) and
+// whole waves per system use the recurrence form of pd_scan.h instead of
+// steps 1-3 (pd_use_scan); everything else about the kernels is shared.
+//
 // The right-hand side is staged through LDS so that global loads and stores
 // are coalesced.  Modes: 0 accumulates b = sum_k gamma_k y_k (full spectrum,
 // the conjugate half implied) into per-block float64 partial sums; 1 writes
